@@ -1,0 +1,436 @@
+"""FP64 CPU oracle of the Microcosmos filament-fluid timestep.
+
+TEST INFRASTRUCTURE ONLY.  This module exists so that tests, the smoke check
+and the benchmark's CPU baseline can check the HIP path against a plain,
+slow, obviously correct implementation.  The product path never imports it.
+
+Everything is plain PyTorch on the CPU in float64, written in the paper's
+order and notation; every step that is elementwise over nodes, edges or cells
+is written as one vectorised expression over the index set it ranges over.
+Reverse mode (the gradient of a rollout with respect to the rest angles and
+the initial positions) is PyTorch's autograd of exactly this forward code.
+
+Readings where the paper is silent (stated once here, cited per function):
+  * sub-step order within one step: actuation, elastic force, deposit,
+    Gaussian filter, repulsion, force spread, fluid update, gather+integrate;
+  * PBD couples to the fluid as an explicit immersed-boundary force: the
+    projected positions y are the elastic target and F_el = k_el (y - x);
+  * edge angles are re-synchronised to atan2 of the edge vectors at the start
+    of every step; K PBD iterations; two-colour Gauss-Seidel ordering;
+  * bend constraint angle difference wrapped into (-pi, pi];
+  * particle/grid transfer with Peskin's 4-point kernel, cell centres at
+    integer coordinates, periodic grid;
+  * Gaussian filter sigma = 1 cell, radius 4, sampled taps normalised, circular
+    (identical to the FFT convolution with the same kernel);
+  * repulsion = -k_rep * interpolate(central difference of the filtered field);
+  * D2Q9 two-relaxation-time collision with Guo forcing, magic parameter 1/4;
+  * explicit Euler integration of nodes with the interpolated fluid velocity.
+
+Pins: see tests/test_oracle_pins.py (closed forms, invariants, brute force,
+library routines, physics).  Nothing here is "parity unpinned" except the
+numeric constants of the reading (stiffnesses, k_el, k_rep, sigma), which the
+paper does not give.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+DT = torch.float64
+TWO_PI = 2.0 * math.pi
+
+
+@dataclass
+class Params:
+    """Physical and numerical constants of one world (lattice units)."""
+
+    nx: int
+    ny: int
+    tau: float = 1.0             # BGK-equivalent relaxation time, nu = (tau - 1/2)/3
+    trt_magic: float = 0.25      # TRT magic parameter Lambda
+    k_bend: float = 0.5          # bending stiffness (Eq. 1)
+    k_stretch: float = 1.0       # stretch stiffness (Eq. 3)
+    k_shear: float = 0.5         # shear blend (Eq. 3)
+    pbd_iters: int = 4           # PBD iterations per step
+    k_elastic: float = 0.05      # F_el = k_elastic (y - x)
+    k_repulse: float = 0.1       # steric repulsion strength
+    sigma: float = 1.0           # Gaussian filter width (cells)
+    radius: int = 4              # Gaussian filter truncation radius (cells)
+    u_max: float = 0.3           # Mach guard on |u|
+
+
+# ---------------------------------------------------------------------------
+# Filament topology (Methods, Filaments: chains with nearest-neighbour edges)
+# ---------------------------------------------------------------------------
+
+class Topology:
+    """Index sets of a set of chains given by CSR offsets.
+
+    Edge e joins nodes (e, e+1) of one filament; joint i is an interior node
+    between edges i-1 and i.  Sets are split by the parity of the local index
+    (edge: e - o_f; joint: i - o_f - 1) for two-colour Gauss-Seidel sweeps.
+    """
+
+    def __init__(self, fil_offset):
+        off = np.asarray(fil_offset, dtype=np.int64)
+        self.fil_offset = off
+        self.n_filaments = len(off) - 1
+        self.n = int(off[-1])
+        edges, elocal, joints, jlocal, jfil, jcount = [], [], [], [], [], []
+        fil_of_node = np.zeros(self.n, dtype=np.int64)
+        for f in range(self.n_filaments):
+            a, b = int(off[f]), int(off[f + 1])
+            fil_of_node[a:b] = f
+            for e in range(a, b - 1):
+                edges.append(e)
+                elocal.append(e - a)
+            for i in range(a + 1, b - 1):
+                joints.append(i)
+                jlocal.append(i - a - 1)
+                jfil.append(f)
+                jcount.append(b - a - 2)
+        t = lambda v: torch.tensor(v, dtype=torch.int64)
+        self.edges = t(edges)
+        self.joints = t(joints)
+        self.joint_local = t(jlocal)
+        self.joint_fil = t(jfil)
+        self.joint_count = t(jcount)        # n_f - 2 for the joint's filament
+        self.fil_of_node = torch.from_numpy(fil_of_node)
+        el = np.array(elocal, dtype=np.int64)
+        jl = np.array(jlocal, dtype=np.int64)
+        ed = np.array(edges, dtype=np.int64)
+        jo = np.array(joints, dtype=np.int64)
+        self.edge_sets = [t(ed[el % 2 == 0]), t(ed[el % 2 == 1])]
+        self.joint_sets = [t(jo[jl % 2 == 0]), t(jo[jl % 2 == 1])]
+
+
+# ---------------------------------------------------------------------------
+# S0. Actuation: time-dependent rest angle (Experiments, Hand-designed
+# locomotion: sinusoidal wave along the body; reading: one travelling
+# wavelength per body)
+# ---------------------------------------------------------------------------
+
+def actuation(rest_angle, topo: Topology, amp, period, phase, t):
+    """theta_hat_i = theta_rest_i + A_f sin(2 pi t / T_f + psi_f - 2 pi k / (n_f - 2))."""
+    theta_hat = rest_angle.clone()
+    if topo.joints.numel() == 0:
+        return theta_hat
+    f = topo.joint_fil
+    arg = (TWO_PI * float(t) / period[f] + phase[f]
+           - TWO_PI * topo.joint_local.to(DT) / topo.joint_count.to(DT))
+    return theta_hat.index_add(0, topo.joints, amp[f] * torch.sin(arg))
+
+
+# ---------------------------------------------------------------------------
+# S1. Elastic force: PBD Cosserat projection (Methods, Bending Pass Eq. 1,
+# Position Pass Eqs. 2-4)
+# ---------------------------------------------------------------------------
+
+def wrap_angle(d):
+    """Map an angle difference into (-pi, pi]."""
+    return d - TWO_PI * torch.ceil((d - math.pi) / TWO_PI)
+
+
+def edge_angles(y, topo: Topology):
+    """theta_e = atan2 of edge vector y_{e+1} - y_e, for every edge (others 0)."""
+    theta = torch.zeros(topo.n, dtype=DT)
+    if topo.edges.numel() == 0:
+        return theta
+    e = topo.edges
+    v = y[:, e + 1] - y[:, e]
+    return theta.index_put((e,), torch.atan2(v[1], v[0]))
+
+
+def bend_pass(theta, joints, theta_hat, k_bend):
+    """Eq. 1 for a set of joints that share no edge: C = wrap(th_2 - th_1) - th_hat,
+    th_1 += k C / 2, th_2 -= k C / 2, with th_1 the edge before the joint."""
+    if joints.numel() == 0:
+        return theta
+    c = wrap_angle(theta[joints] - theta[joints - 1]) - theta_hat[joints]
+    return theta.index_add(0, joints - 1, 0.5 * k_bend * c).index_add(0, joints, -0.5 * k_bend * c)
+
+
+def position_pass(y, theta, edges, rest_length, k_stretch, k_shear):
+    """Eqs. 2-4 for a set of edges that share no node."""
+    if edges.numel() == 0:
+        return y
+    v = y[:, edges + 1] - y[:, edges]
+    ell = torch.sqrt(v[0] * v[0] + v[1] * v[1])
+    L = rest_length[edges]
+    c_stretch = (ell - L) * v / ell                                          # Eq. 2
+    d = torch.stack([torch.cos(theta[edges]), torch.sin(theta[edges])])
+    dx = 0.5 * k_stretch * (c_stretch + k_shear * (v - L * d - c_stretch))   # Eq. 3
+    return y.index_add(1, edges, dx).index_add(1, edges + 1, -dx)           # Eq. 4
+
+
+def pbd_project(x, topo: Topology, theta_hat, rest_length, p: Params, iters=None):
+    """K iterations of (bend even, bend odd, position even, position odd) from y = x.
+
+    Returns the projected positions y and the edge angles theta."""
+    iters = p.pbd_iters if iters is None else iters
+    y = x
+    theta = edge_angles(y, topo)
+    for _ in range(iters):
+        for js in topo.joint_sets:
+            theta = bend_pass(theta, js, theta_hat, p.k_bend)
+        for es in topo.edge_sets:
+            y = position_pass(y, theta, es, rest_length, p.k_stretch, p.k_shear)
+    return y, theta
+
+
+def elastic_force(x, topo: Topology, theta_hat, rest_length, p: Params):
+    """F_el,i = k_el (y_i - x_i) with y the PBD projection of x."""
+    y, _ = pbd_project(x, topo, theta_hat, rest_length, p)
+    return p.k_elastic * (y - x)
+
+
+# ---------------------------------------------------------------------------
+# Particle <-> grid transfer (Methods, Fluid-filament interaction: immersed
+# boundary with a smoothing kernel over a small neighbourhood; reading:
+# Peskin's 4-point function)
+# ---------------------------------------------------------------------------
+
+def peskin_phi(r):
+    """Peskin's 4-point regularised delta function (one dimension).
+
+    phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4r^2)) / 8       for |r| <= 1
+           = (5 - 2|r| - sqrt(-7 + 12|r| - 4r^2)) / 8     for 1 <= |r| <= 2
+           = 0                                              otherwise
+    Each branch is evaluated on |r| clamped to its own interval so that no
+    square root ever sees a negative argument (keeps reverse mode finite).
+    """
+    a = torch.abs(r)
+    ai = torch.clamp(a, max=1.0)
+    ao = torch.clamp(a, min=1.0, max=2.0)
+    inner = (3.0 - 2.0 * ai + torch.sqrt(1.0 + 4.0 * ai - 4.0 * ai * ai)) / 8.0
+    outer = (5.0 - 2.0 * ao - torch.sqrt(-7.0 + 12.0 * ao - 4.0 * ao * ao)) / 8.0
+    return torch.where(a <= 1.0, inner, torch.where(a < 2.0, outer, torch.zeros_like(a)))
+
+
+def support(xc, n):
+    """Cells floor(x)-1 .. floor(x)+2 (mod n) and their 1D weights phi(c - x): [N, 4] each."""
+    base = torch.floor(xc.detach())
+    m = torch.arange(-1, 3, dtype=DT)
+    cells = base[:, None] + m[None, :]
+    w = peskin_phi(cells - xc[:, None])
+    idx = torch.remainder(cells.to(torch.int64), n)
+    return idx, w
+
+
+def transfer_stencil(x, p: Params):
+    """Flat cell indices [N, 16] and weights W(c - x_i) = phi(dx) phi(dy) [N, 16]."""
+    ix, wx = support(x[0], p.nx)
+    iy, wy = support(x[1], p.ny)
+    flat = (iy[:, :, None] * p.nx + ix[:, None, :]).reshape(-1, 16)
+    w = (wy[:, :, None] * wx[:, None, :]).reshape(-1, 16)
+    return flat, w
+
+
+def spread(x, vals, p: Params):
+    """Grid field G_c = sum_i W(c - x_i) v_i for vals [C, N] -> [C, ny, nx]."""
+    flat, w = transfer_stencil(x, p)
+    C = vals.shape[0]
+    out = []
+    for k in range(C):
+        g = torch.zeros(p.ny * p.nx, dtype=DT)
+        g = g.index_add(0, flat.reshape(-1), (w * vals[k][:, None]).reshape(-1))
+        out.append(g.reshape(p.ny, p.nx))
+    return torch.stack(out)
+
+
+def interpolate(x, field, p: Params):
+    """Node values v_i = sum_c W(c - x_i) G_c for field [C, ny, nx] -> [C, N]."""
+    flat, w = transfer_stencil(x, p)
+    return torch.stack([(field[k].reshape(-1)[flat] * w).sum(dim=1) for k in range(field.shape[0])])
+
+
+# ---------------------------------------------------------------------------
+# S2-S4. Steric repulsion field (Methods, Fields: deposit, Gaussian filter,
+# gradient of the density gives repulsion)
+# ---------------------------------------------------------------------------
+
+def deposit(x, p: Params):
+    """s_c = sum_i W(c - x_i)."""
+    ones = torch.ones((1, x.shape[1]), dtype=DT)
+    return spread(x, ones, p)[0]
+
+
+def gaussian_taps(sigma, radius):
+    k = torch.arange(-radius, radius + 1, dtype=DT)
+    g = torch.exp(-k * k / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def gaussian_filter(s, p: Params):
+    """Circular separable convolution: first along x, then along y."""
+    g = gaussian_taps(p.sigma, p.radius)
+    R = p.radius
+    tx = sum(g[k + R] * torch.roll(s, shifts=k, dims=1) for k in range(-R, R + 1))
+    return sum(g[k + R] * torch.roll(tx, shifts=k, dims=0) for k in range(-R, R + 1))
+
+
+def central_difference(st):
+    """(D s)_c = ((s[x+1] - s[x-1]) / 2, (s[y+1] - s[y-1]) / 2), periodic; [2, ny, nx]."""
+    gx = 0.5 * (torch.roll(st, shifts=-1, dims=1) - torch.roll(st, shifts=1, dims=1))
+    gy = 0.5 * (torch.roll(st, shifts=-1, dims=0) - torch.roll(st, shifts=1, dims=0))
+    return torch.stack([gx, gy])
+
+
+def repulsion(x, st, p: Params):
+    """F_rep,i = -k_rep sum_c W(c - x_i) (D s~)_c."""
+    return -p.k_repulse * interpolate(x, central_difference(st), p)
+
+
+# ---------------------------------------------------------------------------
+# S6. Fluid: D2Q9 lattice Boltzmann, TRT collision with Guo forcing, periodic
+# streaming (Methods, Fields; Fluid-filament interaction)
+# ---------------------------------------------------------------------------
+
+# D2Q9 velocities, weights and opposite directions (Qian, d'Humieres, Lallemand)
+C_Q = torch.tensor([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]],
+                   dtype=DT)
+W_Q = torch.tensor([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=DT)
+OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+
+
+def lbm_collide(f, F, p: Params):
+    """TRT collision with Guo forcing at every cell.
+
+    f: [9, ny, nx] pre-collision populations; F: [2, ny, nx] body force.
+    Returns (post-collision populations, u) with u = (sum_q f_q c_q + F/2) / rho.
+    """
+    cx = C_Q[:, 0].reshape(9, 1, 1)
+    cy = C_Q[:, 1].reshape(9, 1, 1)
+    w = W_Q.reshape(9, 1, 1)
+    rho = f.sum(dim=0)
+    ux = ((f * cx).sum(dim=0) + 0.5 * F[0]) / rho
+    uy = ((f * cy).sum(dim=0) + 0.5 * F[1]) / rho
+    cu = cx * ux + cy * uy
+    usq = ux * ux + uy * uy
+    feq = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq)
+    S = w * ((3.0 * (cx - ux) + 9.0 * cu * cx) * F[0] + (3.0 * (cy - uy) + 9.0 * cu * cy) * F[1])
+    om_p = 1.0 / p.tau
+    om_m = 1.0 / (p.trt_magic / (p.tau - 0.5) + 0.5)
+    opp = OPP
+    sym = lambda a: 0.5 * (a + a[opp])
+    anti = lambda a: 0.5 * (a - a[opp])
+    fstar = (f - om_p * (sym(f) - sym(feq)) - om_m * (anti(f) - anti(feq))
+             + (1.0 - 0.5 * om_p) * sym(S) + (1.0 - 0.5 * om_m) * anti(S))
+    return fstar, torch.stack([ux, uy])
+
+
+def lbm_stream(fstar):
+    """f_q(c + c_q) <- f*_q(c), periodic."""
+    return torch.stack([torch.roll(fstar[q], shifts=(int(C_Q[q, 1]), int(C_Q[q, 0])), dims=(0, 1))
+                        for q in range(9)])
+
+
+def rest_populations(p: Params):
+    """Fluid at rest: f_q = w_q (rho = 1, u = 0)."""
+    return W_Q.reshape(9, 1, 1).expand(9, p.ny, p.nx).clone()
+
+
+# ---------------------------------------------------------------------------
+# One step and rollouts
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Inputs:
+    """Fixed per-world arrays (float64 / int64 tensors)."""
+
+    topo: Topology
+    rest_angle: torch.Tensor
+    rest_length: torch.Tensor
+    amp: torch.Tensor
+    period: torch.Tensor
+    phase: torch.Tensor
+
+
+def inputs_from_world(w) -> Inputs:
+    """Widen a workloads.World to float64 tensors (exact)."""
+    return Inputs(
+        topo=Topology(w.fil_offset),
+        rest_angle=torch.from_numpy(w.rest_angle.astype(np.float64)),
+        rest_length=torch.from_numpy(w.rest_length.astype(np.float64)),
+        amp=torch.from_numpy(w.act_amp.astype(np.float64)),
+        period=torch.from_numpy(w.act_period.astype(np.float64)),
+        phase=torch.from_numpy(w.act_phase.astype(np.float64)),
+    )
+
+
+def positions_from_world(w):
+    return torch.from_numpy(w.cell.astype(np.float64) + w.frac.astype(np.float64))
+
+
+def step(x, f, t, inp: Inputs, p: Params, rest_angle=None, trace=None):
+    """Advance (x, f) by one step at time index t; returns (x', f', u_t).
+
+    ``rest_angle`` overrides inp.rest_angle (for differentiation).  If ``trace``
+    is a dict, intermediate fields are stored in it.
+    """
+    ra = inp.rest_angle if rest_angle is None else rest_angle
+    theta_hat = actuation(ra, inp.topo, inp.amp, inp.period, inp.phase, t)      # S0
+    f_el = elastic_force(x, inp.topo, theta_hat, inp.rest_length, p)           # S1
+    s = deposit(x, p)                                                           # S2
+    st = gaussian_filter(s, p)                                                  # S3
+    f_rep = repulsion(x, st, p)                                                 # S4
+    force = f_el + f_rep
+    Fg = spread(x, force, p)                                                    # S5
+    fstar, u = lbm_collide(f, Fg, p)                                            # S6
+    f_new = lbm_stream(fstar)
+    x_new = x + interpolate(x, u, p)                                            # S7
+    if trace is not None:
+        trace.update(theta_hat=theta_hat, f_el=f_el, s=s, st=st, f_rep=f_rep, force=force,
+                     Fg=Fg, u=u, fstar=fstar)
+    return x_new, f_new, u
+
+
+def rollout(x, f, t0, n, inp: Inputs, p: Params, rest_angle=None, every=None):
+    """n steps from time t0.  ``every(k, x, f, u)`` is called after step k (0-based)."""
+    for k in range(n):
+        x, f, u = step(x, f, t0 + k, inp, p, rest_angle=rest_angle)
+        if every is not None:
+            every(k, x, f, u)
+    return x, f
+
+
+def fold_loss(x, target):
+    """Mean over nodes of the squared distance to the target: (1/N) sum_i |x_i - y*_i|^2."""
+    return ((x - target) ** 2).sum() / x.shape[1]
+
+
+def rollout_gradient(x0, f0, t0, n, inp: Inputs, p: Params, grad_xT, segment=20):
+    """d(<grad_xT, x_T>)/d(rest_angle) and d/d(x0) by reverse mode over segments.
+
+    The forward is replayed from the stored segment-start states (x, f); the
+    adjoint of each segment is PyTorch's autograd of the forward code above.
+    """
+    starts = []
+    x, f = x0.detach(), f0.detach()
+    k = 0
+    while k < n:
+        starts.append((k, x, f))
+        m = min(segment, n - k)
+        with torch.no_grad():
+            x, f = rollout(x, f, t0 + k, m, inp, p)
+        k += m
+    gx = grad_xT.detach().clone()
+    gf = torch.zeros_like(f0)
+    g_ra = torch.zeros_like(inp.rest_angle)
+    for (k, xs, fs) in reversed(starts):
+        m = min(segment, n - k)
+        xs = xs.clone().requires_grad_(True)
+        fs = fs.clone().requires_grad_(True)
+        ra = inp.rest_angle.clone().requires_grad_(True)
+        xe, fe = rollout(xs, fs, t0 + k, m, inp, p, rest_angle=ra)
+        outs = [xe, fe]
+        gouts = [gx, gf]
+        gxs, gfs, gra = torch.autograd.grad(outs, [xs, fs, ra], gouts, allow_unused=True)
+        gx = gxs.detach()
+        gf = gfs.detach() if gfs is not None else torch.zeros_like(f0)
+        if gra is not None:
+            g_ra = g_ra + gra.detach()
+    return g_ra, gx

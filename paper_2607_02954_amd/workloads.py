@@ -1,0 +1,235 @@
+"""Seeded synthetic inputs for the filament-fluid timestep.
+
+This module is the one piece shared by the GPU path and the FP64 oracle.  It
+only draws random numbers and lays out the initial state (straight chains,
+rest shapes, actuation parameters, loss targets); it contains none of the
+method's arithmetic (no forces, no transfer kernel, no fluid update).
+
+Workloads follow the paper's setting (Methods, "Filaments": chains of nodes
+with per-edge rest length and per-joint rest angle; "Fields": a periodic 2D
+grid) with sizes of the scaling, folding and population experiments
+(Experiments, "Scalability", "Filament Folding").  Every array is produced by
+numpy's PCG64 generator from an integer seed.
+
+Positions are handed out as an integer cell plus a float32 fraction in
+[0, 1); the exact real position is ``cell + float64(frac)``, so both sides
+start from bit-identical coordinates.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class World:
+    """Initial state of one world (host numpy arrays)."""
+
+    nx: int
+    ny: int
+    fil_offset: np.ndarray          # int32 [F+1], CSR offsets into the node arrays
+    cell: np.ndarray                # int32 [2, N] integer cell of every node (x row, y row)
+    frac: np.ndarray                # float32 [2, N] fractional part, in [0, 1)
+    rest_angle: np.ndarray          # float32 [N], joint at interior node i (edges i-1, i)
+    rest_length: np.ndarray         # float32 [N], edge (i, i+1); last node of a filament unused
+    act_amp: np.ndarray             # float32 [F] actuation amplitude (rad)
+    act_period: np.ndarray          # float32 [F] actuation period (steps)
+    act_phase: np.ndarray           # float32 [F] actuation phase offset (rad)
+    target: Optional[np.ndarray] = None   # float64 [2, N] loss target (folding workload)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.fil_offset[-1])
+
+    @property
+    def n_filaments(self) -> int:
+        return int(self.fil_offset.shape[0] - 1)
+
+    def positions64(self) -> np.ndarray:
+        """Exact node positions as float64 [2, N]."""
+        return self.cell.astype(np.float64) + self.frac.astype(np.float64)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def split_position(x: np.ndarray):
+    """Split float64 positions into (int32 cell, float32 frac) with frac in [0, 1)."""
+    cell = np.floor(x).astype(np.int64)
+    frac = (x - cell).astype(np.float32)
+    roll = frac >= np.float32(1.0)
+    cell = np.where(roll, cell + 1, cell)
+    frac = np.where(roll, np.float32(0.0), frac).astype(np.float32)
+    return cell.astype(np.int32), frac
+
+
+def straight_chain(n: int, centre, angle: float, bond: float = 1.0) -> np.ndarray:
+    """Nodes of a straight chain of ``n`` nodes, spacing ``bond``, float64 [2, n]."""
+    s = (np.arange(n, dtype=np.float64) - 0.5 * (n - 1)) * bond
+    return np.stack([centre[0] + s * math.cos(angle), centre[1] + s * math.sin(angle)])
+
+
+def _assemble(nx, ny, chains, rest_angle, rest_length, amp, period, phase, target=None, meta=None):
+    lengths = [c.shape[1] for c in chains]
+    off = np.zeros(len(chains) + 1, dtype=np.int32)
+    off[1:] = np.cumsum(lengths)
+    x = np.concatenate(chains, axis=1) if chains else np.zeros((2, 0))
+    cell, frac = split_position(x)
+    return World(
+        nx=int(nx), ny=int(ny), fil_offset=off, cell=cell, frac=frac,
+        rest_angle=np.asarray(rest_angle, dtype=np.float32),
+        rest_length=np.asarray(rest_length, dtype=np.float32),
+        act_amp=np.asarray(amp, dtype=np.float32),
+        act_period=np.asarray(period, dtype=np.float32),
+        act_phase=np.asarray(phase, dtype=np.float32),
+        target=target, meta=dict(meta or {}))
+
+
+def random_world(seed: int, nx: int, ny: int, lengths: List[int], *, angle_sd: float = 0.3,
+                 amp: float = 0.0, period_range=(20.0, 100.0), bond: float = 1.0) -> World:
+    """Chains of the given lengths, centres uniform in the box, orientations uniform.
+
+    Rest angles ~ N(0, angle_sd^2) at interior joints; rest lengths = ``bond``.
+    Actuation amplitude ``amp`` (0 disables it), period ~ U(period_range) steps,
+    phase ~ U(0, 2 pi).
+    """
+    g = _rng(seed)
+    F = len(lengths)
+    centres = g.uniform(0.0, 1.0, size=(F, 2)) * np.array([nx, ny], dtype=np.float64)
+    orient = g.uniform(0.0, 2.0 * math.pi, size=F)
+    chains = [straight_chain(n, centres[f], orient[f], bond) for f, n in enumerate(lengths)]
+    N = int(sum(lengths))
+    rest_angle = np.zeros(N, dtype=np.float64)
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    draws = g.normal(0.0, angle_sd, size=N)
+    for f in range(F):
+        a, b = off[f], off[f + 1]
+        if b - a >= 3:
+            rest_angle[a + 1:b - 1] = draws[a + 1:b - 1]
+    rest_length = np.full(N, bond, dtype=np.float64)
+    period = g.uniform(period_range[0], period_range[1], size=F)
+    phase = g.uniform(0.0, 2.0 * math.pi, size=F)
+    amps = np.full(F, amp, dtype=np.float64)
+    return _assemble(nx, ny, chains, rest_angle, rest_length, amps, period, phase,
+                     meta=dict(seed=seed, orient=orient, centres=centres))
+
+
+# ---------------------------------------------------------------------------
+# The five workloads (sizes of the paper's experiments; synthetic stand-ins).
+# ---------------------------------------------------------------------------
+
+def parity_single(seed: int = 0, nx: int = 64, ny: int = 64, n: int = 32) -> World:
+    """One straight chain of ``n`` nodes along +x centred in an nx x ny box.
+
+    Rest angles ~ N(0, 0.3^2), bond 1 cell, no actuation, fluid at rest.
+    """
+    g = _rng(seed)
+    chain = straight_chain(n, (nx / 2.0, ny / 2.0), 0.0)
+    ra = np.zeros(n)
+    if n >= 3:
+        ra[1:n - 1] = g.normal(0.0, 0.3, size=n - 2)
+    return _assemble(nx, ny, [chain], ra, np.ones(n), [0.0], [50.0], [0.0],
+                     meta=dict(seed=seed, name="single"))
+
+
+def uniform_population(seed: int = 0, n_fil: int = 1024, length: int = 64, nx: int = 512,
+                       ny: int = 512, amp: float = 0.5) -> World:
+    """``n_fil`` chains of ``length`` nodes with sinusoidal active bending (amp rad,
+    period U(20, 100) steps)."""
+    w = random_world(seed, nx, ny, [length] * n_fil, amp=amp)
+    w.meta["name"] = "uniform"
+    return w
+
+
+def scaling_lengths(seed: int, total: int, lo: int = 16, hi: int = 256) -> List[int]:
+    """Lengths ~ U{lo..hi} drawn until fewer than hi + lo nodes remain; the remainder
+    becomes one or two chains of length >= lo, so the lengths sum to ``total``."""
+    g = _rng(seed + 7919)
+    out: List[int] = []
+    rem = total
+    while rem >= hi + lo:
+        n = int(g.integers(lo, hi + 1))
+        out.append(n)
+        rem -= n
+    if rem > 0:
+        if rem <= hi:
+            out.append(rem)
+        else:
+            out.extend([rem // 2, rem - rem // 2])
+    assert sum(out) == total and min(out) >= lo
+    return out
+
+
+def scaling_population(seed: int = 0, total: int = 1_048_576, nx: int = 2048, ny: int = 2048,
+                       amp: float = 0.5) -> World:
+    """The million-particle scaling workload: lengths U{16..256}, 2048^2 grid."""
+    lengths = scaling_lengths(seed, total)
+    w = random_world(seed, nx, ny, lengths, amp=amp)
+    w.meta["name"] = "scaling"
+    return w
+
+
+def folding_population(seed: int = 0, n_fil: int = 64, length: int = 48, nx: int = 256,
+                       ny: int = 256) -> World:
+    """Differentiation workload: no actuation, plus a seeded smooth target fold per chain.
+
+    Target: a chain with unit bonds whose turning angles are
+    k_j = sum_{m=1..3} a_m sin(pi m (j+1)/(n-1) + b_m), a ~ N(0, 0.3^2),
+    b ~ U(0, 2 pi), placed at the chain's initial centroid and orientation.
+    """
+    w = random_world(seed, nx, ny, [length] * n_fil, amp=0.0)
+    g = _rng(seed + 104729)
+    tgt = []
+    for f in range(n_fil):
+        a = g.normal(0.0, 0.3, size=3)
+        b = g.uniform(0.0, 2.0 * math.pi, size=3)
+        j = np.arange(length - 2, dtype=np.float64)
+        kappa = sum(a[m] * np.sin(math.pi * (m + 1) * (j + 1) / (length - 1) + b[m]) for m in range(3))
+        heading = w.meta["orient"][f] + np.concatenate([[0.0], np.cumsum(kappa)])
+        pts = np.zeros((2, length))
+        pts[0, 1:] = np.cumsum(np.cos(heading))
+        pts[1, 1:] = np.cumsum(np.sin(heading))
+        pts -= pts.mean(axis=1, keepdims=True)
+        pts += w.meta["centres"][f][:, None]
+        tgt.append(pts)
+    w.target = np.concatenate(tgt, axis=1)
+    w.meta["name"] = "folding"
+    return w
+
+
+@dataclass
+class Job:
+    """One rollout job of the served workload."""
+
+    job_id: int
+    arrival: float        # seconds after trace start
+    steps: int
+    world: World
+
+
+def served_jobs(seed: int = 0, n_jobs: int = 256, rate: float = 50.0, max_fil: int = 512,
+                len_range=(8, 128), side_range=(128, 512), side_step: int = 32,
+                steps_range=(200, 2000), make_world: bool = True) -> List[Job]:
+    """Jobs with filament counts log-uniform on [1, max_fil], lengths U{8..128},
+    grid side U{128, 160, ..., 512}, steps U{200..2000}, Poisson arrivals at ``rate``/s."""
+    g = _rng(seed + 31337)
+    sides = np.arange(side_range[0], side_range[1] + 1, side_step)
+    jobs = []
+    t = 0.0
+    for j in range(n_jobs):
+        t += float(g.exponential(1.0 / rate))
+        n_fil = int(round(math.exp(g.uniform(0.0, math.log(max_fil)))))
+        n_fil = max(1, n_fil)
+        lengths = [int(v) for v in g.integers(len_range[0], len_range[1] + 1, size=n_fil)]
+        side = int(g.choice(sides))
+        steps = int(g.integers(steps_range[0], steps_range[1] + 1))
+        wseed = int(g.integers(0, 2**31 - 1))
+        w = random_world(wseed, side, side, lengths, amp=0.5) if make_world else None
+        jobs.append(Job(job_id=j, arrival=t, steps=steps, world=w))
+    return jobs
+
