@@ -1,0 +1,212 @@
+/*
+ * microcosm.h -- C ABI of the MI355X filament-fluid timestep library
+ * (libmicrocosm.so).
+ *
+ * One step advances elastic filament chains immersed in a periodic 2D viscous
+ * fluid, following the Methods section of "Microcosmos: Reimagining
+ * Artificial Life for the GPU Era" (arXiv 2607.02954):
+ *   S0 actuation: time-dependent rest angle (Experiments, Hand-designed
+ *      locomotion: sinusoidal wave along the body);
+ *   S1 elastic force from position-based Cosserat constraints, a bending pass
+ *      (Eq. 1) then a position pass (Eqs. 2-4), iterated;
+ *   S2-S4 steric repulsion: node density deposited on the grid, Gaussian
+ *      filtered, its gradient gives repulsion (Methods, Fields);
+ *   S5 force spread onto the grid (immersed boundary method, Methods,
+ *      Fluid-filament Interaction);
+ *   S6 D2Q9 lattice Boltzmann update with two-relaxation-time collision
+ *      (Methods, Fields; Fluid-filament Interaction);
+ *   S7 grid velocity gathered back to the nodes, which are integrated.
+ *
+ * Conventions shared by every entry point:
+ *  - Lattice units: cell (ix, iy) is centred at (ix, iy); the grid is
+ *    periodic; grid arrays are row-major [ny][nx] with x fastest.
+ *  - All array pointers are DEVICE pointers owned by the caller; they must
+ *    stay valid while a world or batch refers to them.  The library never
+ *    allocates device memory: all scratch lives in caller-provided workspace
+ *    or pool memory, sized with the *_size queries.
+ *  - `stream` arguments are hipStream_t values passed as void*; all work is
+ *    enqueued asynchronously on that stream.  Only sim_sync, sim_batch_sync,
+ *    sim_batch_retire and sim_create/sim_batch_admit (which read the CSR
+ *    offsets back) synchronise.
+ *  - Every call returns a sim_status.  SIM_E_INVALID / SIM_E_WORKSPACE /
+ *    SIM_E_FULL are detected on the host before any work is enqueued and
+ *    leave all state untouched.  sim_last_error() returns a thread-local
+ *    message for the last non-OK status.  Nothing aborts or throws across
+ *    this boundary.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MICROCOSM_H
+#define MICROCOSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sim_status {
+  SIM_OK = 0,
+  SIM_E_INVALID = 1,   /* bad argument, size or layout                         */
+  SIM_E_WORKSPACE = 2, /* workspace / pool / checkpoint buffer too small        */
+  SIM_E_HIP = 3,       /* a HIP runtime call failed (message in sim_last_error) */
+  SIM_E_UNSTABLE = 4,  /* a world produced NaN or |u| > u_max (Mach guard)      */
+  SIM_E_STATE = 5,     /* call not valid in the handle's current state          */
+  SIM_E_FULL = 6       /* batch has no free slot                                */
+} sim_status;
+
+/* sim_params.flags */
+enum {
+  SIM_SPLAT_SORTED = 1u << 0 /* deterministic sorted-segment particle->grid transfer */
+};
+
+/* Physical and numerical constants of one world (host struct, copied). */
+typedef struct sim_params {
+  int32_t nx, ny;          /* periodic grid, cells; each >= 8                         */
+  float tau;               /* relaxation time, viscosity nu = (tau - 1/2)/3, > 0.5   */
+  float trt_magic;         /* TRT magic parameter Lambda (default 1/4), > 0          */
+  float k_bend;            /* bending stiffness of Eq. 1, in [0, 1]                  */
+  float k_stretch;         /* stretch stiffness of Eq. 3, in [0, 1]                  */
+  float k_shear;           /* shear blend of Eq. 3, in [0, 1]                        */
+  int32_t pbd_iters;       /* PBD iterations per step, >= 0                          */
+  float k_elastic;         /* elastic force F_el = k_elastic (y - x)                 */
+  float k_repulse;         /* steric repulsion strength                              */
+  float sigma_repulse;     /* Gaussian filter width (cells), > 0                     */
+  int32_t repulse_radius;  /* Gaussian filter truncation radius, 1..8                */
+  float u_max;             /* Mach guard: |u| above this flags the world unstable    */
+  uint32_t flags;          /* SIM_SPLAT_SORTED ...                                   */
+} sim_params;
+
+/* State and per-node arrays of one world (DEVICE pointers, caller-owned).
+ * N = n_particles, F = n_filaments.  Node i of filament f is in
+ * [fil_offset[f], fil_offset[f+1]). */
+typedef struct sim_arrays {
+  int32_t n_filaments, n_particles;
+  const int32_t *fil_offset;  /* [F+1] nondecreasing CSR offsets, [0]=0, [F]=N; every
+                                 filament has 1..1024 nodes                              */
+  int32_t *cell;              /* [2][N] integer part of x (row 0) and y (row 1),
+                                 unwrapped (not reduced mod the grid)                    */
+  float *frac;                /* [2][N] fractional part in [0, 1); position = cell+frac  */
+  const float *rest_angle;    /* [N] rest angle of the joint at interior node i
+                                 (between edges i-1 and i); ignored at filament ends     */
+  const float *rest_length;   /* [N] rest length of edge (i, i+1); ignored at last node   */
+  const float *act_amp;       /* [F] actuation amplitude (rad)                           */
+  const float *act_period;    /* [F] actuation period (steps), > 0                        */
+  const float *act_phase;     /* [F] actuation phase offset (rad)                        */
+  float *f;                   /* [9][ny][nx] pre-collision populations at the current
+                                 step, stored SHIFTED by the lattice weights: f_q - w_q.
+                                 Velocity order: rest, +x, +y, -x, -y, (+1,+1), (-1,+1),
+                                 (-1,-1), (+1,-1).                                        */
+  float *u;                   /* [2][ny][nx] out: fluid velocity of the last step taken   */
+} sim_arrays;
+
+typedef struct sim_world sim_world;
+typedef struct sim_batch sim_batch;
+
+/* Fill *p with the defaults (tau 1, Lambda 1/4, k_bend 0.5, k_stretch 1,
+ * k_shear 0.5, 4 PBD iterations, k_elastic 0.05, k_repulse 0.1, sigma 1,
+ * radius 4, u_max 0.3, flags 0) for an nx x ny grid. */
+void sim_params_default(sim_params *p, int32_t nx, int32_t ny);
+
+/* Bytes of device workspace sim_create needs for a world of this size. */
+sim_status sim_workspace_size(const sim_params *p, int32_t n_filaments, int32_t n_particles,
+                              size_t *bytes);
+
+/* Create a world over caller arrays.  Reads fil_offset back to the host
+ * (synchronous), validates it, lays out the workspace (256-byte aligned
+ * pointer, ws_bytes >= sim_workspace_size) and uploads the work tables.
+ * The world's time index is set by each sim_step / sim_rollout call. */
+sim_status sim_create(const sim_params *p, const sim_arrays *a, void *workspace, size_t ws_bytes,
+                      void *stream, sim_world **out);
+
+/* One step at time index t (S0-S7).  Positions, f and u are updated in the
+ * caller's arrays when the stream reaches the end of the call. */
+sim_status sim_step(sim_world *w, int64_t t);
+
+/* n_steps steps starting at time index t0, launched as captured HIP graphs.
+ * If ckpt_every > 0, the state (cell, frac, f) before steps t0, t0+k, ...
+ * (k = ckpt_every) is stored into ckpt, which must hold
+ * sim_checkpoint_size(w, n_steps, ckpt_every) bytes; ckpt may be NULL iff
+ * ckpt_every == 0. */
+sim_status sim_rollout(sim_world *w, int64_t t0, int32_t n_steps, int32_t ckpt_every, void *ckpt,
+                       size_t ckpt_bytes);
+
+sim_status sim_checkpoint_size(const sim_world *w, int32_t n_steps, int32_t ckpt_every,
+                               size_t *bytes);
+
+/* Reverse mode of a rollout (the paper differentiates end to end through the
+ * PBD solver and the fluid, Experiments, Filament Folding).  Given the
+ * checkpoints written by sim_rollout(t0, n_steps, ckpt_every) and g_pos =
+ * dL/dx at the final step ([2][N] device floats), ACCUMULATES dL/d(rest_angle)
+ * into g_rest_angle ([N], caller zeroes) and, if g_pos0 is not NULL, WRITES
+ * dL/dx at t0 into g_pos0 ([2][N]).  Each segment is recomputed forward from
+ * its checkpoint into adj_ws, then hand-written adjoint kernels run step by
+ * step in reverse.  adj_ws must hold sim_backward_workspace_size bytes.
+ * The world's own state arrays are not modified. */
+sim_status sim_backward_workspace_size(const sim_world *w, int32_t ckpt_every, size_t *bytes);
+sim_status sim_backward(sim_world *w, int64_t t0, int32_t n_steps, int32_t ckpt_every,
+                        const void *ckpt, const float *g_pos, float *g_rest_angle, float *g_pos0,
+                        void *adj_ws, size_t adj_ws_bytes);
+
+/* Wait for the world's stream; report asynchronous HIP errors and the sticky
+ * Mach/NaN flag (SIM_E_UNSTABLE). */
+sim_status sim_sync(sim_world *w);
+/* Clear the sticky Mach/NaN flag (enqueued on the stream). */
+sim_status sim_clear_flags(sim_world *w);
+/* Release host-side resources (graphs, pinned staging).  Does not touch the
+ * caller's device memory. */
+void sim_destroy(sim_world *w);
+const char *sim_last_error(void);
+
+/* Test hook: run a single sub-step kernel of step t on the current state
+ * (which: 0 elastic force + deposit, 1 filter, 2 repulsion + spread,
+ * 3 fluid update, 4 gather + integrate), and expose the world's internal
+ * per-step buffers (which: 0 deposit s [ny][nx], 1 filtered s~ [ny][nx],
+ * 2 grid force [2][ny][nx], 3 node force [2][N]).  For parity tests. */
+sim_status sim_debug_substep(sim_world *w, int32_t which, int64_t t);
+sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
+
+/* Measurement hook: run n_steps ordinary steps from time index t0 (kernels
+ * launched directly, not from a graph) with HIP events on the world's stream
+ * around every kernel group, and write the mean device time in milliseconds
+ * of each group to ms_out[6]: 0 elastic force + deposit, 1 sorted-transfer
+ * sort (0 in atomic mode), 2 filter, 3 repulsion + spread, 4 fluid update,
+ * 5 gather + integrate.  The state advances exactly as with sim_rollout.
+ * Synchronises the stream. */
+sim_status sim_profile_steps(sim_world *w, int64_t t0, int32_t n_steps, float *ms_out);
+
+/* ---- Batched worlds: many independent worlds of uneven size advanced by the
+ * same kernels in one persistent, graph-captured launch per chunk of steps.
+ * World state lives in a caller-provided device pool (the HBM budget). ---- */
+
+/* Pool bytes one world of this size occupies inside a batch pool. */
+sim_status sim_batch_world_bytes(const sim_params *p, int32_t n_filaments, int32_t n_particles,
+                                 size_t *bytes);
+/* max_worlds slots; pool is a device buffer of pool_bytes (256-byte aligned). */
+sim_status sim_batch_create(int32_t max_worlds, void *pool, size_t pool_bytes, void *stream,
+                            sim_batch **out);
+/* Copy a world's initial state (device arrays in *init) into the pool and
+ * give it slot *slot.  It will run `steps` steps from time index t0 and then
+ * idle.  SIM_E_FULL: no free slot; SIM_E_WORKSPACE: pool exhausted. */
+sim_status sim_batch_admit(sim_batch *b, const sim_params *p, const sim_arrays *init, int64_t t0,
+                           int32_t steps, int32_t *slot);
+/* Advance every resident world by up to n_steps steps (worlds whose step
+ * budget runs out idle); one graph launch per chunk. */
+sim_status sim_batch_advance(sim_batch *b, int32_t n_steps);
+/* Steps still to run for a slot (host bookkeeping, no sync). */
+sim_status sim_batch_remaining(const sim_batch *b, int32_t slot, int32_t *remaining);
+/* Copy a slot's state (cell, frac, f, u) into caller arrays *out (same sizes
+ * as at admission; enqueued on the stream, then synchronised) and free it.
+ * Returns SIM_E_UNSTABLE (and still frees) if that world was flagged. */
+sim_status sim_batch_retire(sim_batch *b, int32_t slot, const sim_arrays *out);
+sim_status sim_batch_sync(sim_batch *b);
+/* Tunables chosen by the autotuner: steps per captured chunk and the
+ * persistent grid size (blocks) of the cell and node kernels. */
+sim_status sim_batch_set_tuning(sim_batch *b, int32_t chunk_steps, int32_t cell_blocks,
+                                int32_t node_blocks);
+void sim_batch_destroy(sim_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MICROCOSM_H */

@@ -1,0 +1,1038 @@
+// Host runtime of libmicrocosm: world and batch engines, workspace/pool
+// layout, work tables, HIP graph capture, and the extern "C" boundary.
+//
+// A single world and a batch share one Engine: a table of world descriptors
+// in device memory plus work lists (node packs, fluid items, filter tiles,
+// scan items).  Steps alternate between two descriptor sets (A: populations
+// buffer 0 -> 1, B: 1 -> 0), so a captured chunk of an even number of steps
+// leaves every running world's state where it started.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "microcosm.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sim_status fail(sim_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(SIM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carve-out of a device region.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+sim_status check_params(const sim_params* p) {
+  if (!p) return fail(SIM_E_INVALID, "params is NULL");
+  if (p->nx < 8 || p->ny < 8) return fail(SIM_E_INVALID, "grid must be at least 8x8 (got %dx%d)", p->nx, p->ny);
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return fail(SIM_E_INVALID, "grid too large");
+  if (!(p->tau > 0.5f)) return fail(SIM_E_INVALID, "tau must exceed 1/2");
+  if (!(p->trt_magic > 0.f)) return fail(SIM_E_INVALID, "trt_magic must be positive");
+  if (p->pbd_iters < 0 || p->pbd_iters > 1000) return fail(SIM_E_INVALID, "pbd_iters out of range");
+  if (p->repulse_radius < 1 || p->repulse_radius > mc::kMaxRadius)
+    return fail(SIM_E_INVALID, "repulse_radius must be in 1..%d", mc::kMaxRadius);
+  if (!(p->sigma_repulse > 0.f)) return fail(SIM_E_INVALID, "sigma_repulse must be positive");
+  if (p->flags & ~(uint32_t)SIM_SPLAT_SORTED) return fail(SIM_E_INVALID, "unknown flag bits");
+  return SIM_OK;
+}
+
+// Per-world device buffers beyond the caller's arrays.
+struct WorldBufs {
+  float* f_alt = nullptr;
+  float* s = nullptr;
+  float* st = nullptr;
+  float* Fg = nullptr;
+  float* fel = nullptr;
+  int* key = nullptr;
+  int* rank = nullptr;
+  int* cnt = nullptr;
+  int* start = nullptr;
+  int* perm = nullptr;
+  float4* rec = nullptr;
+  int* part = nullptr;
+};
+
+void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) {
+  const size_t ncell = (size_t)p.nx * p.ny;
+  const size_t N = std::max(n_part, 1);
+  b.f_alt = c.take<float>(9 * ncell);
+  b.st = c.take<float>(ncell);
+  b.fel = c.take<float>(2 * N);
+  if (p.flags & SIM_SPLAT_SORTED) {
+    b.key = c.take<int>(N);
+    b.rank = c.take<int>(N);
+    b.cnt = c.take<int>(ncell);
+    b.start = c.take<int>(ncell + 1);
+    b.perm = c.take<int>(N);
+    b.rec = c.take<float4>(N);
+    b.part = c.take<int>((ncell + 1023) / 1024 + 1);
+  } else {
+    b.s = c.take<float>(ncell);
+    b.Fg = c.take<float>(2 * ncell);
+  }
+}
+
+struct Slot {
+  bool used = false;
+  sim_params p{};
+  int n_fil = 0, n_part = 0, max_len = 0;
+  std::vector<int> h_off;
+  int* fil_offset = nullptr;
+  int* cell = nullptr;
+  float* frac = nullptr;
+  float* rest_angle = nullptr;
+  float* rest_length = nullptr;
+  float* amp = nullptr;
+  float* period = nullptr;
+  float* phase = nullptr;
+  float* fbuf[2] = {nullptr, nullptr};
+  float* u = nullptr;
+  WorldBufs b;
+  int cur = 0;          // populations buffer that holds the state
+  int remaining = 0;    // host mirror of the steps left (batch)
+  size_t pool_off = 0, pool_len = 0;
+  bool needs_zero = false;   // cnt must be cleared before first use
+};
+
+// Zero an int array with a kernel (never a memset node; see graph capture).
+__global__ void k_zero_i32(int* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+struct Engine {
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  int max_worlds = 0;
+  // device tables
+  mc::WorldDev* desc[2] = {nullptr, nullptr};
+  mc::Ctl* ctl[2] = {nullptr, nullptr};
+  unsigned* flags = nullptr;
+  int* counts = nullptr;
+  mc::Pack* packs = nullptr;
+  int2* items = nullptr;
+  int2* tiles = nullptr;
+  int2* scan = nullptr;
+  size_t max_packs = 0, max_items = 0, max_tiles = 0, max_scan = 0;
+  mc::Tables tab{};
+  mc::Grid grid{};
+  bool fixed_grid = false;
+  bool any_sorted = false;
+  std::vector<Slot> slots;
+  // host staging (pinned) for table uploads
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  // captured graphs
+  hipGraphExec_t g_chunk = nullptr;
+  int chunk_steps = 0;
+  int want_chunk = 20;
+  hipGraphExec_t g_pair = nullptr;
+
+  size_t n_packs = 0, n_items = 0, n_tiles = 0, n_scan = 0;
+
+  static size_t table_bytes(int max_worlds, size_t mp, size_t mi, size_t mt, size_t ms) {
+    Carver c{nullptr};
+    c.take<mc::WorldDev>(max_worlds);
+    c.take<mc::WorldDev>(max_worlds);
+    c.take<mc::Ctl>(max_worlds);
+    c.take<mc::Ctl>(max_worlds);
+    c.take<unsigned>(max_worlds);
+    c.take<int>(8);
+    c.take<mc::Pack>(mp);
+    c.take<int2>(mi);
+    c.take<int2>(mt);
+    c.take<int2>(ms);
+    return c.off;
+  }
+
+  void carve_tables(Carver& c) {
+    desc[0] = c.take<mc::WorldDev>(max_worlds);
+    desc[1] = c.take<mc::WorldDev>(max_worlds);
+    ctl[0] = c.take<mc::Ctl>(max_worlds);
+    ctl[1] = c.take<mc::Ctl>(max_worlds);
+    flags = c.take<unsigned>(max_worlds);
+    counts = c.take<int>(8);
+    packs = c.take<mc::Pack>(max_packs);
+    items = c.take<int2>(max_items);
+    tiles = c.take<int2>(max_tiles);
+    scan = c.take<int2>(max_scan);
+    tab.packs = packs;
+    tab.n_packs = counts + 0;
+    tab.items = items;
+    tab.n_items = counts + 1;
+    tab.tiles = tiles;
+    tab.n_tiles = counts + 2;
+    tab.scan = scan;
+    tab.n_scan = counts + 3;
+  }
+
+  ~Engine() {
+    if (g_chunk) hipGraphExecDestroy(g_chunk);
+    if (g_pair) hipGraphExecDestroy(g_pair);
+    if (upload_done) hipEventDestroy(upload_done);
+    if (pinned) hipHostFree(pinned);
+    if (cap) hipStreamDestroy(cap);
+  }
+
+  sim_status init_host(size_t staging) {
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&upload_done, hipEventDisableTiming));
+    pinned_bytes = staging;
+    HIPCHK(hipHostMalloc((void**)&pinned, pinned_bytes, hipHostMallocDefault));
+    return SIM_OK;
+  }
+
+  mc::WorldDev make_desc(int w, int parity) const {
+    const Slot& s = slots[w];
+    const sim_params& p = s.p;
+    mc::WorldDev d{};
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.n_part = s.n_part;
+    d.n_fil = s.n_fil;
+    d.om_p = 1.0f / p.tau;
+    d.om_m = (float)(1.0 / ((double)p.trt_magic / ((double)p.tau - 0.5) + 0.5));
+    d.k_bend = p.k_bend;
+    d.k_stretch = p.k_stretch;
+    d.k_shear = p.k_shear;
+    d.k_el = p.k_elastic;
+    d.k_rep = p.k_repulse;
+    d.u_max2 = p.u_max * p.u_max;
+    d.pbd_iters = p.pbd_iters;
+    d.radius = p.repulse_radius;
+    d.sorted = (p.flags & SIM_SPLAT_SORTED) ? 1 : 0;
+    {
+      double g[mc::kMaxRadius + 1];
+      double sum = 0.0;
+      const double s2 = 2.0 * (double)p.sigma_repulse * (double)p.sigma_repulse;
+      for (int k = 0; k <= p.repulse_radius; ++k) {
+        g[k] = std::exp(-(double)k * k / s2);
+        sum += (k == 0 ? 1.0 : 2.0) * g[k];
+      }
+      for (int k = 0; k <= mc::kMaxRadius; ++k) d.gtap[k] = k <= p.repulse_radius ? (float)(g[k] / sum) : 0.f;
+    }
+    d.fil_offset = s.fil_offset;
+    d.cell_in = s.cell;
+    d.frac_in = s.frac;
+    d.cell_out = s.cell;
+    d.frac_out = s.frac;
+    d.rest_angle = s.rest_angle;
+    d.rest_length = s.rest_length;
+    d.act_amp = s.amp;
+    d.act_period = s.period;
+    d.act_phase = s.phase;
+    const int src = parity == 0 ? s.cur : 1 - s.cur;
+    d.f_src = s.fbuf[src];
+    d.f_dst = s.fbuf[1 - src];
+    d.u = s.u;
+    d.s = s.b.s;
+    d.st = s.b.st;
+    d.Fg = s.b.Fg;
+    d.fel = s.b.fel;
+    d.ctl_src = ctl[parity] + w;
+    d.ctl_dst = ctl[1 - parity] + w;
+    d.flags = flags + w;
+    d.key = s.b.key;
+    d.rank = s.b.rank;
+    d.cnt = s.b.cnt;
+    d.start = s.b.start;
+    d.perm = s.b.perm;
+    d.rec = s.b.rec;
+    d.part = s.b.part;
+    return d;
+  }
+
+  // Rebuild work tables and descriptors from the slot list and upload them.
+  sim_status rebuild() {
+    std::vector<mc::Pack> pk;
+    std::vector<int2> it, tl, sc;
+    any_sorted = false;
+    for (int w = 0; w < (int)slots.size(); ++w) {
+      const Slot& s = slots[w];
+      if (!s.used) continue;
+      const int cap_nodes = grid.pack;
+      int f = 0;
+      while (f < s.n_fil) {
+        mc::Pack p{};
+        p.world = w;
+        p.fil_begin = f;
+        p.node_begin = s.h_off[f];
+        int end = f;
+        while (end < s.n_fil && s.h_off[end + 1] - p.node_begin <= cap_nodes) ++end;
+        p.fil_end = end;
+        p.node_end = s.h_off[end];
+        pk.push_back(p);
+        f = end;
+      }
+      const int ncell = s.p.nx * s.p.ny;
+      for (int c = 0; c < ncell; c += mc::kCellsPerItem) it.push_back(make_int2(w, c));
+      const int ntx = (s.p.nx + mc::kTileX - 1) / mc::kTileX;
+      const int nty = (s.p.ny + mc::kTileY - 1) / mc::kTileY;
+      for (int t = 0; t < ntx * nty; ++t) tl.push_back(make_int2(w, t));
+      if (s.p.flags & SIM_SPLAT_SORTED) {
+        any_sorted = true;
+        const int nb = (ncell + 1023) / 1024;
+        for (int b = 0; b < nb; ++b) sc.push_back(make_int2(w, b));
+      }
+    }
+    if (pk.size() > max_packs || it.size() > max_items || tl.size() > max_tiles || sc.size() > max_scan)
+      return fail(SIM_E_WORKSPACE, "work tables exceed their capacity");
+    n_packs = pk.size();
+    n_items = it.size();
+    n_tiles = tl.size();
+    n_scan = sc.size();
+    if (!fixed_grid) {
+      grid.node_blocks = (int)std::max<size_t>(1, n_packs);
+      grid.cell_blocks = (int)std::max<size_t>(1, n_items);
+      grid.tile_blocks = (int)std::max<size_t>(1, n_tiles);
+      grid.scan_blocks = (int)std::max<size_t>(1, n_scan);
+    }
+    // stage into pinned memory once the previous upload has been consumed
+    HIPCHK(hipEventSynchronize(upload_done));
+    const size_t need = 2 * max_worlds * sizeof(mc::WorldDev) + 8 * sizeof(int) + pk.size() * sizeof(mc::Pack) +
+                        (it.size() + tl.size() + sc.size()) * sizeof(int2);
+    if (need > pinned_bytes) {
+      if (pinned) HIPCHK(hipHostFree(pinned));
+      pinned_bytes = need * 2;
+      HIPCHK(hipHostMalloc((void**)&pinned, pinned_bytes, hipHostMallocDefault));
+    }
+    char* h = pinned;
+    size_t off = 0;
+    auto put = [&](void* dev, const void* src, size_t bytes) -> sim_status {
+      if (!bytes) return SIM_OK;
+      std::memcpy(h + off, src, bytes);
+      HIPCHK(hipMemcpyAsync(dev, h + off, bytes, hipMemcpyHostToDevice, stream));
+      off += bytes;
+      return SIM_OK;
+    };
+    std::vector<mc::WorldDev> d0(max_worlds), d1(max_worlds);
+    for (int w = 0; w < (int)slots.size(); ++w) {
+      if (!slots[w].used) continue;
+      d0[w] = make_desc(w, 0);
+      d1[w] = make_desc(w, 1);
+    }
+    sim_status st;
+    if ((st = put(desc[0], d0.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
+    if ((st = put(desc[1], d1.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
+    int cnt[8] = {(int)n_packs, (int)n_items, (int)n_tiles, (int)n_scan, 0, 0, 0, 0};
+    if ((st = put(counts, cnt, sizeof(cnt)))) return st;
+    if ((st = put(packs, pk.data(), pk.size() * sizeof(mc::Pack)))) return st;
+    if ((st = put(items, it.data(), it.size() * sizeof(int2)))) return st;
+    if ((st = put(tiles, tl.data(), tl.size() * sizeof(int2)))) return st;
+    if ((st = put(scan, sc.data(), sc.size() * sizeof(int2)))) return st;
+    HIPCHK(hipEventRecord(upload_done, stream));
+    return SIM_OK;
+  }
+
+  void enqueue_step(int parity, hipStream_t s) const {
+    const mc::WorldDev* d = desc[parity];
+    mc::launch_elastic(d, tab, grid, s);
+    mc::launch_sort(d, tab, grid, s, any_sorted);
+    mc::launch_filter(d, tab, grid, s);
+    mc::launch_repulse(d, tab, grid, s);
+    mc::launch_lbm(d, tab, grid, s);
+    mc::launch_integrate(d, tab, grid, s);
+  }
+
+  sim_status capture(int steps, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < steps; ++k) enqueue_step(k & 1, cap);
+    hipError_t le = hipGetLastError();
+    hipError_t ee = hipStreamEndCapture(cap, &g);
+    if (le != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return fail(SIM_E_HIP, "kernel launch during capture: %s", hipGetErrorString(le));
+    }
+    if (ee != hipSuccess) return fail(SIM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(SIM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    return SIM_OK;
+  }
+
+  void drop_graphs() {
+    if (g_chunk) hipGraphExecDestroy(g_chunk);
+    if (g_pair) hipGraphExecDestroy(g_pair);
+    g_chunk = g_pair = nullptr;
+    chunk_steps = 0;
+  }
+
+  // Run n steps with parity starting at 0; n even uses graphs only.  An odd
+  // tail step is launched directly with descriptor set A.
+  sim_status run_steps(int n) {
+    if (n <= 0) return SIM_OK;
+    if (n >= want_chunk && (!g_chunk || chunk_steps != want_chunk)) {
+      if (g_chunk) hipGraphExecDestroy(g_chunk);
+      g_chunk = nullptr;
+      sim_status st = capture(want_chunk, &g_chunk);
+      if (st) return st;
+      chunk_steps = want_chunk;
+    }
+    if (n >= 2 && !g_pair) {
+      sim_status st = capture(2, &g_pair);
+      if (st) return st;
+    }
+    int left = n;
+    while (chunk_steps > 0 && left >= chunk_steps) {
+      HIPCHK(hipGraphLaunch(g_chunk, stream));
+      left -= chunk_steps;
+    }
+    while (left >= 2) {
+      HIPCHK(hipGraphLaunch(g_pair, stream));
+      left -= 2;
+    }
+    if (left == 1) {
+      enqueue_step(0, stream);
+      HIPCHK(hipGetLastError());
+    }
+    return SIM_OK;
+  }
+
+  sim_status set_ctl(int w, long long t, int remaining) {
+    mc::launch_set_ctl(ctl[0] + w, t, remaining, stream);
+    HIPCHK(hipGetLastError());
+    return SIM_OK;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single world
+// ---------------------------------------------------------------------------
+struct sim_world {
+  Engine eng;
+  sim_arrays arr{};
+  size_t ws_bytes = 0;
+  void* ws = nullptr;
+};
+
+namespace {
+
+size_t world_table_bytes(const sim_params& p, int n_fil) {
+  const size_t ncell = (size_t)p.nx * p.ny;
+  const size_t items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
+  const size_t tiles = (size_t)((p.nx + mc::kTileX - 1) / mc::kTileX) * ((p.ny + mc::kTileY - 1) / mc::kTileY);
+  const size_t scans = (ncell + 1023) / 1024;
+  return Engine::table_bytes(1, std::max(n_fil, 1), items, tiles, scans);
+}
+
+size_t world_buf_bytes(const sim_params& p, int n_part) {
+  Carver c{nullptr};
+  WorldBufs b;
+  carve_world_bufs(c, p, n_part, b);
+  return c.off;
+}
+
+sim_status read_offsets(const sim_arrays* a, hipStream_t stream, std::vector<int>& h) {
+  h.assign(a->n_filaments + 1, 0);
+  HIPCHK(hipMemcpyAsync(h.data(), a->fil_offset, h.size() * sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (h[0] != 0) return fail(SIM_E_INVALID, "fil_offset[0] must be 0");
+  if (h[a->n_filaments] != a->n_particles) return fail(SIM_E_INVALID, "fil_offset[F] != n_particles");
+  for (int f = 0; f < a->n_filaments; ++f) {
+    const int len = h[f + 1] - h[f];
+    if (len < 1 || len > mc::kMaxFilament)
+      return fail(SIM_E_INVALID, "filament %d has %d nodes (allowed 1..%d)", f, len, mc::kMaxFilament);
+  }
+  return SIM_OK;
+}
+
+sim_status check_arrays(const sim_arrays* a) {
+  if (!a) return fail(SIM_E_INVALID, "arrays is NULL");
+  if (a->n_particles < 0 || a->n_filaments < 0) return fail(SIM_E_INVALID, "negative sizes");
+  if ((a->n_particles > 0) != (a->n_filaments > 0)) return fail(SIM_E_INVALID, "filaments and particles must both be zero or both positive");
+  if (!a->f || !a->u) return fail(SIM_E_INVALID, "f and u must be given");
+  if (a->n_particles > 0 &&
+      (!a->fil_offset || !a->cell || !a->frac || !a->rest_angle || !a->rest_length || !a->act_amp ||
+       !a->act_period || !a->act_phase))
+    return fail(SIM_E_INVALID, "node arrays must be given");
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sim_params_default(sim_params* p, int32_t nx, int32_t ny) {
+  if (!p) return;
+  p->nx = nx;
+  p->ny = ny;
+  p->tau = 1.0f;
+  p->trt_magic = 0.25f;
+  p->k_bend = 0.5f;
+  p->k_stretch = 1.0f;
+  p->k_shear = 0.5f;
+  p->pbd_iters = 4;
+  p->k_elastic = 0.05f;
+  p->k_repulse = 0.1f;
+  p->sigma_repulse = 1.0f;
+  p->repulse_radius = 4;
+  p->u_max = 0.3f;
+  p->flags = 0;
+}
+
+const char* sim_last_error(void) { return g_err.c_str(); }
+
+sim_status sim_workspace_size(const sim_params* p, int32_t n_filaments, int32_t n_particles, size_t* bytes) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if (!bytes) return fail(SIM_E_INVALID, "bytes is NULL");
+  if (n_filaments < 0 || n_particles < 0) return fail(SIM_E_INVALID, "negative sizes");
+  *bytes = world_table_bytes(*p, n_filaments) + world_buf_bytes(*p, n_particles);
+  return SIM_OK;
+}
+
+sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace, size_t ws_bytes, void* stream,
+                      sim_world** out) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_arrays(a))) return st;
+  if (!out) return fail(SIM_E_INVALID, "out is NULL");
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(SIM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  sim_workspace_size(p, a->n_filaments, a->n_particles, &need);
+  if (ws_bytes < need) return fail(SIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int> h_off;
+  if (a->n_filaments > 0) {
+    if ((st = read_offsets(a, s, h_off))) return st;
+  } else {
+    h_off.assign(1, 0);
+  }
+  int max_len = 0;
+  for (int f = 0; f < a->n_filaments; ++f) max_len = std::max(max_len, h_off[f + 1] - h_off[f]);
+
+  sim_world* w = new sim_world();
+  w->arr = *a;
+  w->ws = workspace;
+  w->ws_bytes = ws_bytes;
+  Engine& e = w->eng;
+  e.stream = s;
+  e.max_worlds = 1;
+  const size_t ncell = (size_t)p->nx * p->ny;
+  e.max_packs = std::max(a->n_filaments, 1);
+  e.max_items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
+  e.max_tiles = (size_t)((p->nx + mc::kTileX - 1) / mc::kTileX) * ((p->ny + mc::kTileY - 1) / mc::kTileY);
+  e.max_scan = (ncell + 1023) / 1024;
+  e.grid.pack = max_len <= 256 ? 256 : 1024;
+  Carver c{(char*)workspace};
+  e.carve_tables(c);
+  Slot sl;
+  sl.used = true;
+  sl.p = *p;
+  sl.n_fil = a->n_filaments;
+  sl.n_part = a->n_particles;
+  sl.max_len = max_len;
+  sl.h_off = h_off;
+  sl.fil_offset = const_cast<int*>(a->fil_offset);
+  sl.cell = a->cell;
+  sl.frac = a->frac;
+  sl.rest_angle = const_cast<float*>(a->rest_angle);
+  sl.rest_length = const_cast<float*>(a->rest_length);
+  sl.amp = const_cast<float*>(a->act_amp);
+  sl.period = const_cast<float*>(a->act_period);
+  sl.phase = const_cast<float*>(a->act_phase);
+  carve_world_bufs(c, *p, a->n_particles, sl.b);
+  sl.fbuf[0] = a->f;
+  sl.fbuf[1] = sl.b.f_alt;
+  sl.u = a->u;
+  e.slots.push_back(sl);
+  if ((st = e.init_host(64 << 10))) {
+    delete w;
+    return st;
+  }
+  // clear flags, control words and (sorted mode) the per-cell counters
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.flags, (size_t)1);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[0], sizeof(mc::Ctl) / 4);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[1], sizeof(mc::Ctl) / 4);
+  if (sl.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, sl.b.cnt, ncell);
+  if (hipGetLastError() != hipSuccess) {
+    delete w;
+    return fail(SIM_E_HIP, "initialisation kernels failed to launch");
+  }
+  if ((st = e.rebuild())) {
+    delete w;
+    return st;
+  }
+  *out = w;
+  return SIM_OK;
+}
+
+static sim_status world_run(sim_world* w, int64_t t, int n) {
+  Engine& e = w->eng;
+  Slot& s = e.slots[0];
+  sim_status st;
+  if ((st = e.set_ctl(0, t, n))) return st;
+  if ((st = e.run_steps(n))) return st;
+  if (n & 1) {
+    // the state ended in the alternate populations buffer: copy it back
+    const size_t ncell = (size_t)s.p.nx * s.p.ny;
+    HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
+  }
+  return SIM_OK;
+}
+
+sim_status sim_step(sim_world* w, int64_t t) {
+  if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  return world_run(w, t, 1);
+}
+
+sim_status sim_checkpoint_size(const sim_world* w, int32_t n_steps, int32_t ckpt_every, size_t* bytes) {
+  if (!w || !bytes) return fail(SIM_E_INVALID, "NULL argument");
+  if (n_steps < 0 || ckpt_every <= 0) return fail(SIM_E_INVALID, "need n_steps >= 0 and ckpt_every > 0");
+  const Slot& s = w->eng.slots[0];
+  const size_t nseg = (size_t)(n_steps + ckpt_every - 1) / ckpt_every;
+  const size_t per = align_up(4 * (size_t)s.n_part * 4) + align_up(9 * (size_t)s.p.nx * s.p.ny * 4);
+  *bytes = std::max<size_t>(nseg, 1) * per;
+  return SIM_OK;
+}
+
+sim_status sim_rollout(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_every, void* ckpt, size_t ckpt_bytes) {
+  if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  if (n_steps < 0) return fail(SIM_E_INVALID, "n_steps must be >= 0");
+  if (ckpt_every < 0) return fail(SIM_E_INVALID, "ckpt_every must be >= 0");
+  if (ckpt_every == 0) return world_run(w, t0, n_steps);
+  if (!ckpt) return fail(SIM_E_INVALID, "ckpt is NULL but ckpt_every > 0");
+  size_t need = 0;
+  sim_checkpoint_size(w, n_steps, ckpt_every, &need);
+  if (ckpt_bytes < need) return fail(SIM_E_WORKSPACE, "checkpoint buffer has %zu bytes, needs %zu", ckpt_bytes, need);
+  Engine& e = w->eng;
+  Slot& s = e.slots[0];
+  const size_t N = s.n_part, ncell = (size_t)s.p.nx * s.p.ny;
+  const size_t per = align_up(4 * N * 4) + align_up(9 * ncell * 4);
+  char* base = (char*)ckpt;
+  int seg = 0;
+  for (int k = 0; k < n_steps; k += ckpt_every, ++seg) {
+    char* dst = base + seg * per;
+    if (N) {
+      HIPCHK(hipMemcpyAsync(dst, s.cell, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+      HIPCHK(hipMemcpyAsync(dst + 2 * N * 4, s.frac, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+    }
+    HIPCHK(hipMemcpyAsync(dst + align_up(4 * N * 4), s.fbuf[0], 9 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
+    sim_status st = world_run(w, t0 + k, std::min(ckpt_every, n_steps - k));
+    if (st) return st;
+  }
+  return SIM_OK;
+}
+
+sim_status sim_sync(sim_world* w) {
+  if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  Engine& e = w->eng;
+  HIPCHK(hipStreamSynchronize(e.stream));
+  HIPCHK(hipGetLastError());
+  unsigned f = 0;
+  HIPCHK(hipMemcpy(&f, e.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (f) return fail(SIM_E_UNSTABLE, "world produced NaN or |u| > u_max");
+  return SIM_OK;
+}
+
+sim_status sim_clear_flags(sim_world* w) {
+  if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, w->eng.stream, (int*)w->eng.flags, (size_t)1);
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+void sim_destroy(sim_world* w) { delete w; }
+
+sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
+  if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  Engine& e = w->eng;
+  sim_status st;
+  if ((st = e.set_ctl(0, t, 1))) return st;
+  const mc::WorldDev* d = e.desc[0];
+  switch (which) {
+    case 0:
+      mc::launch_elastic(d, e.tab, e.grid, e.stream);
+      mc::launch_sort(d, e.tab, e.grid, e.stream, e.any_sorted);
+      break;
+    case 1: mc::launch_filter(d, e.tab, e.grid, e.stream); break;
+    case 2: mc::launch_repulse(d, e.tab, e.grid, e.stream); break;
+    case 3: {
+      mc::launch_lbm(d, e.tab, e.grid, e.stream);
+      Slot& s = e.slots[0];
+      const size_t ncell = (size_t)s.p.nx * s.p.ny;
+      HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
+      break;
+    }
+    case 4: mc::launch_integrate(d, e.tab, e.grid, e.stream); break;
+    default: return fail(SIM_E_INVALID, "unknown sub-step %d", which);
+  }
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* ms_out) {
+  if (!w || !ms_out) return fail(SIM_E_INVALID, "NULL argument");
+  if (n_steps < 1) return fail(SIM_E_INVALID, "n_steps must be >= 1");
+  Engine& e = w->eng;
+  Slot& s = e.slots[0];
+  constexpr int kGroups = 6;
+  std::vector<hipEvent_t> ev((size_t)n_steps * (kGroups + 1), nullptr);
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  sim_status st = e.set_ctl(0, t0, n_steps);
+  if (st) return st;
+  for (int k = 0; k < n_steps; ++k) {
+    const mc::WorldDev* d = e.desc[k & 1];
+    hipEvent_t* E = ev.data() + (size_t)k * (kGroups + 1);
+    HIPCHK(hipEventRecord(E[0], e.stream));
+    mc::launch_elastic(d, e.tab, e.grid, e.stream);
+    HIPCHK(hipEventRecord(E[1], e.stream));
+    mc::launch_sort(d, e.tab, e.grid, e.stream, e.any_sorted);
+    HIPCHK(hipEventRecord(E[2], e.stream));
+    mc::launch_filter(d, e.tab, e.grid, e.stream);
+    HIPCHK(hipEventRecord(E[3], e.stream));
+    mc::launch_repulse(d, e.tab, e.grid, e.stream);
+    HIPCHK(hipEventRecord(E[4], e.stream));
+    mc::launch_lbm(d, e.tab, e.grid, e.stream);
+    HIPCHK(hipEventRecord(E[5], e.stream));
+    mc::launch_integrate(d, e.tab, e.grid, e.stream);
+    HIPCHK(hipEventRecord(E[6], e.stream));
+    HIPCHK(hipGetLastError());
+  }
+  if (n_steps & 1) {
+    const size_t ncell = (size_t)s.p.nx * s.p.ny;
+    HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
+  }
+  HIPCHK(hipStreamSynchronize(e.stream));
+  for (int g = 0; g < kGroups; ++g) {
+    double tot = 0.0;
+    for (int k = 0; k < n_steps; ++k) {
+      float ms = 0.f;
+      hipEvent_t* E = ev.data() + (size_t)k * (kGroups + 1);
+      HIPCHK(hipEventElapsedTime(&ms, E[g], E[g + 1]));
+      tot += ms;
+    }
+    ms_out[g] = (float)(tot / n_steps);
+  }
+  for (auto& x : ev) hipEventDestroy(x);
+  return SIM_OK;
+}
+
+sim_status sim_debug_buffer(sim_world* w, int32_t which, void** ptr) {
+  if (!w || !ptr) return fail(SIM_E_INVALID, "NULL argument");
+  const Slot& s = w->eng.slots[0];
+  switch (which) {
+    case 0: *ptr = s.b.s; break;
+    case 1: *ptr = s.b.st; break;
+    case 2: *ptr = s.b.Fg; break;
+    case 3: *ptr = s.b.fel; break;
+    default: return fail(SIM_E_INVALID, "unknown buffer %d", which);
+  }
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batch of worlds in a caller pool
+// ---------------------------------------------------------------------------
+struct sim_batch {
+  Engine eng;
+  char* pool = nullptr;
+  size_t pool_bytes = 0;
+  size_t table_bytes = 0;
+  std::map<size_t, size_t> free_list;   // offset -> length, inside the pool
+};
+
+namespace {
+
+struct BatchWorldLayout {
+  size_t bytes = 0;
+};
+
+void carve_batch_world(Carver& c, const sim_params& p, int n_fil, int n_part, Slot& s) {
+  const size_t ncell = (size_t)p.nx * p.ny;
+  const size_t N = std::max(n_part, 1), F = std::max(n_fil, 1);
+  s.fil_offset = c.take<int>(F + 1);
+  s.cell = c.take<int>(2 * N);
+  s.frac = c.take<float>(2 * N);
+  s.rest_angle = c.take<float>(N);
+  s.rest_length = c.take<float>(N);
+  s.amp = c.take<float>(F);
+  s.period = c.take<float>(F);
+  s.phase = c.take<float>(F);
+  s.fbuf[0] = c.take<float>(9 * ncell);
+  s.u = c.take<float>(2 * ncell);
+  carve_world_bufs(c, p, n_part, s.b);
+  s.fbuf[1] = s.b.f_alt;
+}
+
+bool pool_alloc(sim_batch* b, size_t bytes, size_t* off) {
+  for (auto it = b->free_list.begin(); it != b->free_list.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      b->free_list.erase(it);
+      if (rest) b->free_list[roff] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(sim_batch* b, size_t off, size_t len) {
+  auto it = b->free_list.emplace(off, len).first;
+  auto nx = std::next(it);
+  if (nx != b->free_list.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    b->free_list.erase(nx);
+  }
+  if (it != b->free_list.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      b->free_list.erase(it);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_batch_world_bytes(const sim_params* p, int32_t n_filaments, int32_t n_particles, size_t* bytes) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if (!bytes || n_filaments < 0 || n_particles < 0) return fail(SIM_E_INVALID, "bad argument");
+  Carver c{nullptr};
+  Slot s;
+  carve_batch_world(c, *p, n_filaments, n_particles, s);
+  *bytes = c.off;
+  return SIM_OK;
+}
+
+sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, void* stream, sim_batch** out) {
+  if (max_worlds < 1 || max_worlds > 65536) return fail(SIM_E_INVALID, "max_worlds must be in 1..65536");
+  if (!pool || ((uintptr_t)pool % kAlign) || !out) return fail(SIM_E_INVALID, "pool must be 256-byte aligned");
+  sim_batch* b = new sim_batch();
+  Engine& e = b->eng;
+  e.stream = (hipStream_t)stream;
+  e.max_worlds = max_worlds;
+  // table capacities bounded by what the pool can hold: every cell costs at
+  // least 96 bytes, every node at least 36 bytes
+  const size_t max_cells = pool_bytes / 96 + 1;
+  const size_t max_nodes = pool_bytes / 36 + 1;
+  e.max_items = max_cells / mc::kCellsPerItem + max_worlds;
+  e.max_tiles = 2 * e.max_items + max_worlds;
+  e.max_scan = max_cells / 1024 + max_worlds;
+  e.max_packs = 2 * (max_nodes / 256) + 2 * (size_t)max_worlds;
+  b->table_bytes = Engine::table_bytes(max_worlds, e.max_packs, e.max_items, e.max_tiles, e.max_scan);
+  if (b->table_bytes >= pool_bytes / 2) {
+    delete b;
+    return fail(SIM_E_WORKSPACE, "pool too small for %d worlds", max_worlds);
+  }
+  Carver c{(char*)pool};
+  e.carve_tables(c);
+  b->pool = (char*)pool;
+  b->pool_bytes = pool_bytes;
+  b->free_list[align_up(b->table_bytes)] = pool_bytes - align_up(b->table_bytes);
+  e.slots.resize(max_worlds);
+  e.fixed_grid = true;
+  e.grid.pack = 256;
+  e.grid.node_blocks = 2048;
+  e.grid.cell_blocks = 4096;
+  e.grid.tile_blocks = 2048;
+  e.grid.scan_blocks = 1024;
+  e.want_chunk = 20;
+  sim_status st = e.init_host(1 << 20);
+  if (st) {
+    delete b;
+    return st;
+  }
+  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)e.flags, (size_t)max_worlds);
+  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)e.ctl[0], max_worlds * sizeof(mc::Ctl) / 4);
+  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)e.ctl[1], max_worlds * sizeof(mc::Ctl) / 4);
+  if (hipGetLastError() != hipSuccess) {
+    delete b;
+    return fail(SIM_E_HIP, "initialisation kernels failed to launch");
+  }
+  if ((st = e.rebuild())) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return SIM_OK;
+}
+
+sim_status sim_batch_set_tuning(sim_batch* b, int32_t chunk_steps, int32_t cell_blocks, int32_t node_blocks) {
+  if (!b) return fail(SIM_E_INVALID, "batch is NULL");
+  if (chunk_steps < 2 || (chunk_steps & 1) || cell_blocks < 1 || node_blocks < 1)
+    return fail(SIM_E_INVALID, "chunk_steps must be even and >= 2; block counts >= 1");
+  Engine& e = b->eng;
+  e.want_chunk = chunk_steps;
+  e.grid.cell_blocks = cell_blocks;
+  e.grid.node_blocks = node_blocks;
+  e.grid.tile_blocks = std::max(1, cell_blocks / 2);
+  e.grid.scan_blocks = std::max(1, cell_blocks / 4);
+  e.drop_graphs();
+  return SIM_OK;
+}
+
+sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* init, int64_t t0, int32_t steps,
+                           int32_t* slot) {
+  if (!b || !slot) return fail(SIM_E_INVALID, "NULL argument");
+  sim_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_arrays(init))) return st;
+  if (steps < 0) return fail(SIM_E_INVALID, "steps must be >= 0");
+  Engine& e = b->eng;
+  int w = -1;
+  for (int k = 0; k < e.max_worlds; ++k)
+    if (!e.slots[k].used) {
+      w = k;
+      break;
+    }
+  if (w < 0) return fail(SIM_E_FULL, "no free slot");
+  std::vector<int> h_off;
+  if (init->n_filaments > 0) {
+    if ((st = read_offsets(init, e.stream, h_off))) return st;
+  } else {
+    h_off.assign(1, 0);
+  }
+  int max_len = 0;
+  for (int f = 0; f < init->n_filaments; ++f) max_len = std::max(max_len, h_off[f + 1] - h_off[f]);
+  if (max_len > e.grid.pack) return fail(SIM_E_INVALID, "batched filaments are limited to %d nodes", e.grid.pack);
+  size_t bytes = 0;
+  sim_batch_world_bytes(p, init->n_filaments, init->n_particles, &bytes);
+  size_t off = 0;
+  if (!pool_alloc(b, bytes, &off)) return fail(SIM_E_WORKSPACE, "pool exhausted (world needs %zu bytes)", bytes);
+  Slot s;
+  s.used = true;
+  s.p = *p;
+  s.n_fil = init->n_filaments;
+  s.n_part = init->n_particles;
+  s.max_len = max_len;
+  s.h_off = h_off;
+  s.pool_off = off;
+  s.pool_len = bytes;
+  Carver c{b->pool + off};
+  carve_batch_world(c, *p, s.n_fil, s.n_part, s);
+  const size_t N = s.n_part, F = s.n_fil, ncell = (size_t)p->nx * p->ny;
+  auto cp = [&](void* dst, const void* src, size_t by) -> sim_status {
+    if (by) HIPCHK(hipMemcpyAsync(dst, src, by, hipMemcpyDeviceToDevice, e.stream));
+    return SIM_OK;
+  };
+  if (N) {
+    if ((st = cp(s.fil_offset, init->fil_offset, (F + 1) * 4))) return st;
+    if ((st = cp(s.cell, init->cell, 2 * N * 4))) return st;
+    if ((st = cp(s.frac, init->frac, 2 * N * 4))) return st;
+    if ((st = cp(s.rest_angle, init->rest_angle, N * 4))) return st;
+    if ((st = cp(s.rest_length, init->rest_length, N * 4))) return st;
+    if ((st = cp(s.amp, init->act_amp, F * 4))) return st;
+    if ((st = cp(s.period, init->act_period, F * 4))) return st;
+    if ((st = cp(s.phase, init->act_phase, F * 4))) return st;
+  }
+  if ((st = cp(s.fbuf[0], init->f, 9 * ncell * 4))) return st;
+  if (s.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, s.b.cnt, ncell);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, e.stream, (int*)(e.flags + w), (size_t)1);
+  HIPCHK(hipGetLastError());
+  s.cur = 0;
+  s.remaining = steps;
+  e.slots[w] = s;
+  if ((st = e.set_ctl(w, t0, steps))) return st;
+  if ((st = e.rebuild())) {
+    e.slots[w] = Slot();
+    pool_free(b, off, bytes);
+    return st;
+  }
+  *slot = w;
+  return SIM_OK;
+}
+
+sim_status sim_batch_advance(sim_batch* b, int32_t n_steps) {
+  if (!b) return fail(SIM_E_INVALID, "batch is NULL");
+  if (n_steps < 0 || (n_steps & 1)) return fail(SIM_E_INVALID, "n_steps must be even and >= 0");
+  Engine& e = b->eng;
+  sim_status st = e.run_steps(n_steps);
+  if (st) return st;
+  for (auto& s : e.slots) {
+    if (!s.used) continue;
+    const int ran = std::min(s.remaining, n_steps);
+    s.cur ^= (ran & 1);
+    s.remaining -= ran;
+  }
+  return SIM_OK;
+}
+
+sim_status sim_batch_remaining(const sim_batch* b, int32_t slot, int32_t* remaining) {
+  if (!b || !remaining) return fail(SIM_E_INVALID, "NULL argument");
+  if (slot < 0 || slot >= b->eng.max_worlds || !b->eng.slots[slot].used) return fail(SIM_E_INVALID, "bad slot");
+  *remaining = b->eng.slots[slot].remaining;
+  return SIM_OK;
+}
+
+sim_status sim_batch_retire(sim_batch* b, int32_t slot, const sim_arrays* out) {
+  if (!b) return fail(SIM_E_INVALID, "batch is NULL");
+  Engine& e = b->eng;
+  if (slot < 0 || slot >= e.max_worlds || !e.slots[slot].used) return fail(SIM_E_INVALID, "bad slot");
+  Slot& s = e.slots[slot];
+  const size_t N = s.n_part, ncell = (size_t)s.p.nx * s.p.ny;
+  if (out) {
+    if (out->n_particles != s.n_part) return fail(SIM_E_INVALID, "output arrays have the wrong size");
+    if (N) {
+      HIPCHK(hipMemcpyAsync(out->cell, s.cell, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+      HIPCHK(hipMemcpyAsync(out->frac, s.frac, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+    }
+    if (out->f) HIPCHK(hipMemcpyAsync(out->f, s.fbuf[s.cur], 9 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
+    if (out->u) HIPCHK(hipMemcpyAsync(out->u, s.u, 2 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
+  }
+  unsigned* hflag = (unsigned*)e.pinned;   // staging is idle after the event sync below
+  HIPCHK(hipEventSynchronize(e.upload_done));
+  HIPCHK(hipMemcpyAsync(hflag, e.flags + slot, sizeof(unsigned), hipMemcpyDeviceToHost, e.stream));
+  HIPCHK(hipStreamSynchronize(e.stream));
+  const unsigned fl = *hflag;
+  pool_free(b, s.pool_off, s.pool_len);
+  s = Slot();
+  sim_status st = e.rebuild();
+  if (st) return st;
+  if (fl) return fail(SIM_E_UNSTABLE, "world in slot %d produced NaN or |u| > u_max", slot);
+  return SIM_OK;
+}
+
+sim_status sim_batch_sync(sim_batch* b) {
+  if (!b) return fail(SIM_E_INVALID, "batch is NULL");
+  HIPCHK(hipStreamSynchronize(b->eng.stream));
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+void sim_batch_destroy(sim_batch* b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,248 @@
+"""Python binding of libmicrocosm (ctypes; argument marshalling only).
+
+Every step of the method runs in the library's HIP kernels.  Torch provides
+device memory (state, workspace, pools, checkpoints) and the stream; nothing
+here computes physics.  If the shared library is missing the binding raises:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmicrocosm.so")
+
+SIM_OK, SIM_E_INVALID, SIM_E_WORKSPACE, SIM_E_HIP, SIM_E_UNSTABLE, SIM_E_STATE, SIM_E_FULL = range(7)
+SIM_SPLAT_SORTED = 1
+
+# D2Q9 weights in the library's velocity order; the library stores f - w.
+LATTICE_WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+EXPORTS = [
+    "sim_params_default", "sim_workspace_size", "sim_create", "sim_step", "sim_rollout",
+    "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
+    "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
+    "sim_profile_steps",
+    "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
+    "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
+    "sim_batch_destroy",
+]
+
+
+class SimError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("tau", ctypes.c_float), ("trt_magic", ctypes.c_float),
+        ("k_bend", ctypes.c_float), ("k_stretch", ctypes.c_float), ("k_shear", ctypes.c_float),
+        ("pbd_iters", ctypes.c_int32),
+        ("k_elastic", ctypes.c_float), ("k_repulse", ctypes.c_float),
+        ("sigma_repulse", ctypes.c_float), ("repulse_radius", ctypes.c_int32),
+        ("u_max", ctypes.c_float), ("flags", ctypes.c_uint32),
+    ]
+
+
+class SimArrays(ctypes.Structure):
+    _fields_ = [
+        ("n_filaments", ctypes.c_int32), ("n_particles", ctypes.c_int32),
+        ("fil_offset", ctypes.c_void_p), ("cell", ctypes.c_void_p), ("frac", ctypes.c_void_p),
+        ("rest_angle", ctypes.c_void_p), ("rest_length", ctypes.c_void_p),
+        ("act_amp", ctypes.c_void_p), ("act_period", ctypes.c_void_p), ("act_phase", ctypes.c_void_p),
+        ("f", ctypes.c_void_p), ("u", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmicrocosm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_02954_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "sim_params_default": (None, [P(SimParams), i32, i32]),
+        "sim_workspace_size": (i32, [P(SimParams), i32, i32, P(sz)]),
+        "sim_create": (i32, [P(SimParams), P(SimArrays), vp, sz, vp, P(vp)]),
+        "sim_step": (i32, [vp, i64]),
+        "sim_rollout": (i32, [vp, i64, i32, i32, vp, sz]),
+        "sim_checkpoint_size": (i32, [vp, i32, i32, P(sz)]),
+        "sim_backward_workspace_size": (i32, [vp, i32, P(sz)]),
+        "sim_backward": (i32, [vp, i64, i32, i32, vp, vp, vp, vp, vp, sz]),
+        "sim_sync": (i32, [vp]),
+        "sim_clear_flags": (i32, [vp]),
+        "sim_destroy": (None, [vp]),
+        "sim_last_error": (ctypes.c_char_p, []),
+        "sim_debug_substep": (i32, [vp, i32, i64]),
+        "sim_debug_buffer": (i32, [vp, i32, P(vp)]),
+        "sim_profile_steps": (i32, [vp, i64, i32, P(ctypes.c_float)]),
+        "sim_batch_world_bytes": (i32, [P(SimParams), i32, i32, P(sz)]),
+        "sim_batch_create": (i32, [i32, vp, sz, vp, P(vp)]),
+        "sim_batch_admit": (i32, [vp, P(SimParams), P(SimArrays), i64, i32, P(i32)]),
+        "sim_batch_advance": (i32, [vp, i32]),
+        "sim_batch_remaining": (i32, [vp, i32, P(i32)]),
+        "sim_batch_retire": (i32, [vp, i32, P(SimArrays)]),
+        "sim_batch_sync": (i32, [vp]),
+        "sim_batch_set_tuning": (i32, [vp, i32, i32, i32]),
+        "sim_batch_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != SIM_OK:
+        raise SimError(status, lib().sim_last_error().decode())
+
+
+@dataclass
+class Params:
+    """Python mirror of sim_params (defaults equal sim_params_default)."""
+
+    nx: int
+    ny: int
+    tau: float = 1.0
+    trt_magic: float = 0.25
+    k_bend: float = 0.5
+    k_stretch: float = 1.0
+    k_shear: float = 0.5
+    pbd_iters: int = 4
+    k_elastic: float = 0.05
+    k_repulse: float = 0.1
+    sigma_repulse: float = 1.0
+    repulse_radius: int = 4
+    u_max: float = 0.3
+    sorted: bool = False
+
+    def c(self) -> SimParams:
+        return SimParams(self.nx, self.ny, self.tau, self.trt_magic, self.k_bend, self.k_stretch,
+                         self.k_shear, self.pbd_iters, self.k_elastic, self.k_repulse,
+                         self.sigma_repulse, self.repulse_radius, self.u_max,
+                         SIM_SPLAT_SORTED if self.sorted else 0)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class DeviceState:
+    """Device tensors of one world's inputs and state (filament-contiguous SoA)."""
+
+    def __init__(self, w, device="cuda"):
+        dev = torch.device(device)
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
+        self.nx, self.ny = int(w.nx), int(w.ny)
+        self.n_fil, self.n_part = int(w.n_filaments), int(w.n_particles)
+        self.fil_offset = t(w.fil_offset, torch.int32)
+        self.cell = t(w.cell, torch.int32).reshape(2, -1).contiguous()
+        self.frac = t(w.frac, torch.float32).reshape(2, -1).contiguous()
+        self.rest_angle = t(w.rest_angle, torch.float32)
+        self.rest_length = t(w.rest_length, torch.float32)
+        self.act_amp = t(w.act_amp, torch.float32)
+        self.act_period = t(w.act_period, torch.float32)
+        self.act_phase = t(w.act_phase, torch.float32)
+        self.f = torch.zeros(9, self.ny, self.nx, device=dev, dtype=torch.float32)   # fluid at rest
+        self.u = torch.zeros(2, self.ny, self.nx, device=dev, dtype=torch.float32)
+
+    def arrays(self) -> SimArrays:
+        return SimArrays(self.n_fil, self.n_part, _ptr(self.fil_offset), _ptr(self.cell), _ptr(self.frac),
+                         _ptr(self.rest_angle), _ptr(self.rest_length), _ptr(self.act_amp),
+                         _ptr(self.act_period), _ptr(self.act_phase), _ptr(self.f), _ptr(self.u))
+
+    def positions64(self) -> np.ndarray:
+        return self.cell.cpu().numpy().astype(np.float64) + self.frac.cpu().numpy().astype(np.float64)
+
+    def populations64(self) -> np.ndarray:
+        return self.f.cpu().numpy().astype(np.float64) + LATTICE_WEIGHTS.reshape(9, 1, 1)
+
+
+def _stream_handle(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class World:
+    """A single world: caller-owned device state plus the library handle."""
+
+    def __init__(self, w, params: Optional[Params] = None, device="cuda", stream=None):
+        L = lib()
+        self.params = params or Params(nx=w.nx, ny=w.ny)
+        self.state = DeviceState(w, device)
+        self.stream = stream
+        cp = self.params.c()
+        nbytes = ctypes.c_size_t()
+        check(L.sim_workspace_size(ctypes.byref(cp), self.state.n_fil, self.state.n_part, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=device)
+        self._arrays = self.state.arrays()
+        h = ctypes.c_void_p()
+        check(L.sim_create(ctypes.byref(cp), ctypes.byref(self._arrays), _ptr(self.workspace),
+                           self.workspace.numel(), _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, t: int):
+        check(lib().sim_step(self.handle, int(t)))
+
+    def rollout(self, t0: int, n: int, ckpt_every: int = 0, ckpt: Optional[torch.Tensor] = None):
+        check(lib().sim_rollout(self.handle, int(t0), int(n), int(ckpt_every), _ptr(ckpt),
+                                0 if ckpt is None else ckpt.numel() * ckpt.element_size()))
+
+    def checkpoint_bytes(self, n: int, ckpt_every: int) -> int:
+        b = ctypes.c_size_t()
+        check(lib().sim_checkpoint_size(self.handle, int(n), int(ckpt_every), ctypes.byref(b)))
+        return int(b.value)
+
+    def sync(self):
+        check(lib().sim_sync(self.handle))
+
+    def profile(self, t0: int, n: int):
+        """Mean ms per kernel group over n real steps (see sim_profile_steps)."""
+        out = (ctypes.c_float * 6)()
+        check(lib().sim_profile_steps(self.handle, int(t0), int(n), out))
+        return list(out)
+
+    def substep(self, which: int, t: int):
+        check(lib().sim_debug_substep(self.handle, int(which), int(t)))
+
+    def buffer(self, which: int, shape, dtype=torch.float32) -> torch.Tensor:
+        """A torch view (copy) of an internal per-step buffer, for tests."""
+        p = ctypes.c_void_p()
+        check(lib().sim_debug_buffer(self.handle, int(which), ctypes.byref(p)))
+        n = int(np.prod(shape))
+        out = torch.empty(n, dtype=dtype, device=self.workspace.device)
+        base = self.workspace.data_ptr()
+        off = p.value - base
+        assert 0 <= off and off + n * out.element_size() <= self.workspace.numel()
+        src = self.workspace[off:off + n * out.element_size()].view(dtype)
+        out.copy_(src)
+        return out.reshape(shape)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sim_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

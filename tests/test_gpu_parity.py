@@ -1,0 +1,219 @@
+"""GPU (HIP, FP32) versus the FP64 oracle, element by element, through the C ABI.
+
+Acceptance (per step, measured errors printed):
+  e_x = max_i |x_gpu - x_ref|_inf / max_i |x_ref|_inf  <= 1e-5
+  e_u = max_c |u_gpu - u_ref|_inf / max_c |u_ref|_inf  <= 1e-4
+Sub-steps are compared normwise with tolerances derived from FP32 rounding of
+O(10)-term sums (a few 1e-7 relative), allowing for atomics' arbitrary order.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_02954_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-5
+TOL_U = 1e-4
+DT = torch.float64
+
+
+def _sim():
+    from paper_2607_02954_amd import sim
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sim
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.max(np.abs(b)) if b.size else 0.0
+    num = np.max(np.abs(a - b)) if b.size else 0.0
+    return num / den if den > 0 else num
+
+
+def oracle_params(p):
+    return O.Params(nx=p.nx, ny=p.ny, tau=p.tau, trt_magic=p.trt_magic, k_bend=p.k_bend,
+                    k_stretch=p.k_stretch, k_shear=p.k_shear, pbd_iters=p.pbd_iters,
+                    k_elastic=p.k_elastic, k_repulse=p.k_repulse, sigma=p.sigma_repulse,
+                    radius=p.repulse_radius, u_max=p.u_max)
+
+
+def ragged_world(seed=0):
+    # lengths that straddle pack boundaries, single-node and two-node filaments,
+    # a grid that is not a multiple of the filter tile
+    lengths = [3, 1, 2, 40, 17, 64, 9, 130, 5]
+    return wl.random_world(seed, 80, 72, lengths, amp=0.5)
+
+
+def gpu_state(W):
+    x = torch.from_numpy(W.state.positions64())
+    f = torch.from_numpy(W.state.populations64())
+    return x, f
+
+
+def _mk(sim, w, sorted_=False, **kw):
+    p = sim.Params(nx=w.nx, ny=w.ny, sorted=sorted_, **kw)
+    return sim.World(w, p), oracle_params(p)
+
+
+@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
+def test_substeps_match_oracle(sorted_):
+    sim = _sim()
+    w = ragged_world(1)
+    W, op = _mk(sim, w, sorted_)
+    inp = O.inputs_from_world(w)
+    W.rollout(0, 6)                       # non-trivial shared state
+    torch.cuda.synchronize()
+    t = 6
+    x, f = gpu_state(W)
+    tr = {}
+    O.step(x, f, t, inp, op, trace=tr)
+    N, ny, nx = w.n_particles, w.ny, w.nx
+    W.substep(0, t)
+    fel = W.buffer(3, (2, N)).cpu().numpy()
+    e_el = rel(fel, tr["f_el"].numpy())
+    assert e_el < 2e-5, e_el
+    if not sorted_:
+        s = W.buffer(0, (ny, nx)).cpu().numpy()
+        assert rel(s, tr["s"].numpy()) < 1e-6
+    W.substep(1, t)
+    st = W.buffer(1, (ny, nx)).cpu().numpy()
+    assert rel(st, tr["st"].numpy()) < 1e-6
+    W.substep(2, t)
+    F = W.buffer(3, (2, N)).cpu().numpy()
+    assert rel(F, tr["force"].numpy()) < 2e-5
+    if not sorted_:
+        Fg = W.buffer(2, (2, ny, nx)).cpu().numpy()
+        assert rel(Fg, tr["Fg"].numpy()) < 2e-5
+    W.substep(3, t)
+    torch.cuda.synchronize()
+    u = W.state.u.cpu().numpy()
+    e_u = rel(u, tr["u"].numpy())
+    assert e_u < TOL_U, e_u
+    fref = O.lbm_stream(tr["fstar"]).numpy()
+    fg = W.state.populations64()
+    assert np.max(np.abs(fg - fref)) < 1e-6
+    W.substep(4, t)
+    torch.cuda.synchronize()
+    xref = (x + O.interpolate(x, tr["u"], op)).numpy()
+    assert rel(W.state.positions64(), xref) < TOL_X
+    print(f"substeps[{'sorted' if sorted_ else 'atomic'}]: e_el={e_el:.2e} e_u={e_u:.2e}")
+
+
+def _rollout_compare(sim, w, n, sorted_, step_api=True, **kw):
+    W, op = _mk(sim, w, sorted_, **kw)
+    inp = O.inputs_from_world(w)
+    x = O.positions_from_world(w)
+    f = O.rest_populations(op)
+    ex_max = eu_max = 0.0
+    for t in range(n):
+        W.step(t)
+        x, f, u = O.step(x, f, t, inp, op)
+        torch.cuda.synchronize()
+        ex = rel(W.state.positions64(), x.numpy())
+        eu = rel(W.state.u.cpu().numpy(), u.numpy())
+        ex_max, eu_max = max(ex_max, ex), max(eu_max, eu)
+        assert ex <= TOL_X, (t, ex)
+        assert eu <= TOL_U, (t, eu)
+    W.sync()
+    return ex_max, eu_max
+
+
+@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
+def test_single_chain_100_steps(sorted_):
+    sim = _sim()
+    ex, eu = _rollout_compare(sim, wl.parity_single(0), 100, sorted_)
+    print(f"single chain 32 nodes 64^2, 100 steps: max e_x={ex:.2e} max e_u={eu:.2e}")
+
+
+@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
+def test_ragged_population_100_steps(sorted_):
+    sim = _sim()
+    ex, eu = _rollout_compare(sim, ragged_world(2), 100, sorted_)
+    print(f"ragged population: max e_x={ex:.2e} max e_u={eu:.2e}")
+
+
+def test_graph_rollout_equals_stepwise_and_sorted_is_deterministic():
+    sim = _sim()
+    w = ragged_world(3)
+    runs = []
+    for mode in ("rollout", "rollout", "step"):
+        W, _ = _mk(sim, w, True)
+        if mode == "rollout":
+            W.rollout(0, 37)
+        else:
+            for t in range(37):
+                W.step(t)
+        torch.cuda.synchronize()
+        runs.append((W.state.cell.cpu().clone(), W.state.frac.cpu().clone(), W.state.f.cpu().clone(),
+                     W.state.u.cpu().clone()))
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)            # bitwise reproducible
+    for a, b in zip(runs[0], runs[2]):
+        assert torch.equal(a, b)            # graph path == plain launches
+    Wa, _ = _mk(sim, w, False)
+    Wa.rollout(0, 37)
+    torch.cuda.synchronize()
+    xs = runs[0][0].numpy() + runs[0][1].numpy().astype(np.float64)
+    assert rel(Wa.state.positions64(), xs) < TOL_X
+
+
+def test_checkpoints_hold_segment_start_states():
+    sim = _sim()
+    w = ragged_world(4)
+    W, _ = _mk(sim, w, True)
+    nb = W.checkpoint_bytes(30, 10)
+    ck = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    W.rollout(0, 30, 10, ck)
+    torch.cuda.synchronize()
+    ref, _ = _mk(sim, w, True)
+    N = w.n_particles
+    per = nb // 3
+    for seg in range(3):
+        blob = ck[seg * per:(seg + 1) * per]
+        cell = blob[: 8 * N].view(torch.int32).reshape(2, N).cpu()
+        assert torch.equal(cell, ref.state.cell.cpu())
+        ref.rollout(seg * 10, 10)
+        torch.cuda.synchronize()
+    assert torch.equal(W.state.cell.cpu(), ref.state.cell.cpu())
+    assert torch.equal(W.state.frac.cpu(), ref.state.frac.cpu())
+
+
+@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
+def test_edge_cases(sorted_):
+    sim = _sim()
+    # empty world: fluid stays at rest
+    empty = wl._assemble(32, 24, [], [], [], [], [], [])
+    W, _ = _mk(sim, empty, sorted_)
+    W.rollout(0, 5)
+    W.sync()
+    assert float(W.state.f.abs().max()) < 1e-7
+    # one long filament (> 256 nodes uses the 1024-node pack) plus single nodes
+    long = wl.random_world(5, 96, 96, [600, 1, 1, 2], amp=0.5)
+    ex, eu = _rollout_compare(sim, long, 10, sorted_)
+    print(f"long filament: e_x={ex:.2e} e_u={eu:.2e}")
+
+
+def test_mach_guard_flags_world():
+    sim = _sim()
+    W, _ = _mk(sim, ragged_world(6), False, u_max=1e-9)
+    W.rollout(0, 4)
+    with pytest.raises(sim.SimError) as ei:
+        W.sync()
+    assert ei.value.status == sim.SIM_E_UNSTABLE
+
+
+@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
+def test_uniform_population_full_size_steps(sorted_):
+    # 1024 chains x 64 nodes on 512^2 with active bending: every element of
+    # positions and u after each of 3 steps from the shared state
+    sim = _sim()
+    w = wl.uniform_population(0)
+    ex, eu = _rollout_compare(sim, w, 3, sorted_)
+    print(f"uniform 65536 nodes 512^2: e_x={ex:.2e} e_u={eu:.2e}")
