@@ -581,6 +581,8 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[0], sizeof(mc::Ctl) / 4);
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[1], sizeof(mc::Ctl) / 4);
   if (sl.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, sl.b.cnt, ncell);
+  if (sl.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.s, ncell);
+  if (sl.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.Fg, 2 * ncell);
   if (hipGetLastError() != hipSuccess) {
     delete w;
     return fail(SIM_E_HIP, "initialisation kernels failed to launch");
@@ -961,6 +963,8 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
   }
   if ((st = cp(s.fbuf[0], init->f, 9 * ncell * 4))) return st;
   if (s.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, s.b.cnt, ncell);
+  if (s.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.b.s, ncell);
+  if (s.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.b.Fg, 2 * ncell);
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, e.stream, (int*)(e.flags + w), (size_t)1);
   HIPCHK(hipGetLastError());
   s.cur = 0;
