@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 FLUID_BYTES_PER_CELL = 88     # populations read + write (72), force read (8), velocity write (8)
 STEP_BYTES_PER_CELL = 120     # whole-step algorithmic bytes per cell
 STEP_BYTES_PER_NODE = 24      # whole-step algorithmic bytes per node
+KERNELS = ["elastic", "bin_or_sort", "filter", "repulse", "fluid", "integrate"]
 
 
 def time_rollout(W, warmup, steps, t0=0):
@@ -102,19 +103,19 @@ def main():
     del W
     torch.cuda.empty_cache()
 
-    sorted_res = None
+    variants = {}
     if not args.no_sorted:
-        Ws = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, sorted=True))
-        s_secs = time_rollout(Ws, args.warmup, args.steps)
-        skms = Ws.profile(args.warmup + args.steps, args.profile_steps)
-        sorted_res = {
-            "value": N * args.steps / s_secs,
-            "ms_per_step": 1000.0 * s_secs / args.steps,
-            "kernel_ms": dict(zip(["elastic", "sort", "filter", "repulse", "fluid", "integrate"],
-                                  [round(v, 5) for v in skms])),
-        }
-        Ws.close()
-        del Ws
+        for mode in ("sorted", "direct"):
+            Ws = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, transfer=mode))
+            s_secs = time_rollout(Ws, args.warmup, args.steps)
+            skms = Ws.profile(args.warmup + args.steps, args.profile_steps)
+            variants[mode] = {
+                "value": N * args.steps / s_secs,
+                "ms_per_step": 1000.0 * s_secs / args.steps,
+                "kernel_ms": dict(zip(KERNELS, [round(v, 5) for v in skms])),
+            }
+            Ws.close()
+            del Ws
 
     out = {
         "metric": "particle-steps/s (1M particles)",
@@ -131,7 +132,7 @@ def main():
         "data": "synthetic (seeded chains, uniform centres and orientations)",
         "config": {
             "workload": "scaling: 1,048,576 nodes, chain lengths U{16..256}, 2048x2048 periodic grid, "
-                        "active bending 0.5 rad, atomic particle-to-grid transfer",
+                        "active bending 0.5 rad, tile-binned particle-to-grid transfer",
             "particles": N, "filaments": world.n_filaments, "grid": [world.nx, world.ny],
             "seed": args.seed,
         },
@@ -151,9 +152,8 @@ def main():
             "achieved_GBs": step_bytes / (ms_step * 1e-3) / 1e9,
             "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
-        "kernel_ms": dict(zip(["elastic", "sort", "filter", "repulse", "fluid", "integrate"],
-                              [round(v, 5) for v in kms])),
-        "sorted_variant": sorted_res,
+        "kernel_ms": dict(zip(KERNELS, [round(v, 5) for v in kms])),
+        "transfer_variants": variants,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(world, args.cpu_steps)

@@ -56,8 +56,14 @@ typedef enum sim_status {
 } sim_status;
 
 /* sim_params.flags */
+/* Particle -> grid transfer (deposit and force spread).  Default (no flag):
+ * nodes are binned by the 32x32 grid tiles their support touches and every
+ * tile sums its nodes' contributions in on-chip memory before writing each
+ * cell once.  The two flags are exclusive. */
 enum {
-  SIM_SPLAT_SORTED = 1u << 0 /* deterministic sorted-segment particle->grid transfer */
+  SIM_SPLAT_SORTED = 1u << 0, /* deterministic: counting sort by home cell, fixed-order
+                                 segmented sums; results are bitwise reproducible       */
+  SIM_SPLAT_DIRECT = 1u << 1  /* global float atomics into HBM accumulators (reference) */
 };
 
 /* Physical and numerical constants of one world (host struct, copied). */
@@ -74,7 +80,7 @@ typedef struct sim_params {
   float sigma_repulse;     /* Gaussian filter width (cells), > 0                     */
   int32_t repulse_radius;  /* Gaussian filter truncation radius, 1..8                */
   float u_max;             /* Mach guard: |u| above this flags the world unstable    */
-  uint32_t flags;          /* SIM_SPLAT_SORTED ...                                   */
+  uint32_t flags;          /* SIM_SPLAT_SORTED or SIM_SPLAT_DIRECT, else binned      */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).
@@ -161,8 +167,9 @@ const char *sim_last_error(void);
 /* Test hook: run a single sub-step kernel of step t on the current state
  * (which: 0 elastic force + deposit, 1 filter, 2 repulsion + spread,
  * 3 fluid update, 4 gather + integrate), and expose the world's internal
- * per-step buffers (which: 0 deposit s [ny][nx], 1 filtered s~ [ny][nx],
- * 2 grid force [2][ny][nx], 3 node force [2][N]).  For parity tests. */
+ * per-step buffers (which: 0 deposit s [ny][nx] and 2 grid force [2][ny][nx],
+ * both SIM_SPLAT_DIRECT only, else NULL; 1 filtered s~ [ny][nx]; 3 node force
+ * [2][N]).  For parity tests. */
 sim_status sim_debug_substep(sim_world *w, int32_t which, int64_t t);
 sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
 

@@ -12,10 +12,16 @@
 
 namespace mc {
 
-constexpr int kCellsPerItem = 256;   // cells per fluid work item (one block)
-constexpr int kTileX = 64;           // filter output tile (x)
-constexpr int kTileY = 16;           // filter output tile (y)
+constexpr int kTile = 32;            // square grid tile of the filter and fluid kernels
 constexpr int kMaxRadius = 8;        // largest Gaussian truncation radius
+constexpr int kMaxBinsPerNode = 9;   // tiles one node's extended support can touch
+
+// Particle -> grid transfer modes (per world).
+enum TransferMode : int {
+  kBinned = 0,   // nodes binned by tile; sums formed in LDS, tiles written whole
+  kSorted = 1,   // counting sort by home cell; fixed-order segmented sums
+  kDirect = 2    // global float atomics into HBM accumulators
+};
 constexpr int kMaxFilament = 1024;   // longest filament a node pack can hold
 
 // Per-world control word, double-buffered by step parity: kernels of a step
@@ -31,7 +37,8 @@ struct WorldDev {
   int nx, ny, n_part, n_fil;
   float om_p, om_m;                     // TRT rates: 1/tau and 1/(Lambda/(tau-1/2) + 1/2)
   float k_bend, k_stretch, k_shear, k_el, k_rep, u_max2;
-  int pbd_iters, radius, sorted, pad0;
+  int pbd_iters, radius, mode, ntx;     // ntx, nty: tiles per row / column
+  int nty, pad0, pad1, pad2;
   float gtap[kMaxRadius + 1];           // normalised Gaussian taps g[0..R]
   const int* fil_offset;                // [F+1]
   const int* cell_in;  const float* frac_in;     // positions at the start of the step
@@ -40,9 +47,9 @@ struct WorldDev {
   const float* act_amp; const float* act_period; const float* act_phase;
   const float* f_src;  float* f_dst;    // shifted populations f - w, [9][ny][nx]
   float* u;                             // [2][ny][nx]
-  float* s;                             // deposit accumulator [ny][nx]
+  float* s;                             // deposit accumulator [ny][nx] (direct mode)
   float* st;                            // filtered density [ny][nx]
-  float* Fg;                            // grid force accumulator [2][ny][nx]
+  float* Fg;                            // grid force accumulator [2][ny][nx] (direct mode)
   float* fel;                           // node force [2][N] (elastic, then total)
   const Ctl* ctl_src; Ctl* ctl_dst;
   unsigned* flags;                      // sticky: bit 0 = NaN or |u| > u_max
@@ -54,6 +61,11 @@ struct WorldDev {
   int* perm;                            // [N] node index of each sorted slot
   float4* rec;                          // [N] sorted records (frac x, frac y, Fx, Fy)
   int* part;                            // scan partials
+  // tile bins (binned mode): node indices grouped by the tiles they affect
+  int* bin_cnt;                         // [ntx*nty] entries per tile (zeroed after use)
+  int* bin_fill;                        // [ntx*nty] fill cursors (zeroed after use)
+  int* bin_start;                       // [ntx*nty + 1] exclusive prefix of bin_cnt
+  int* bin_idx;                         // [9N] node index per entry
 };
 
 // A node pack: whole filaments with at most `pack` nodes, run by one block.
@@ -64,20 +76,21 @@ struct Pack {
 
 struct Tables {
   const Pack* packs;  const int* n_packs;
-  const int2* items;  const int* n_items;    // (world, first cell) of 256 cells
-  const int2* tiles;  const int* n_tiles;    // (world, tile index) for the filter
-  const int2* scan;   const int* n_scan;     // (world, block) for the cell scan
+  const int2* tiles;  const int* n_tiles;    // (world, tile index), 32x32 cells
+  const int2* scan;   const int* n_scan;     // (world, block) for the cell scan (sorted mode)
+  const int2* worlds; const int* n_worlds;   // (world, 0) for per-world kernels
 };
 
 struct Grid {
-  int node_blocks, cell_blocks, tile_blocks, scan_blocks;
+  int node_blocks, tile_blocks, scan_blocks, world_blocks;
   int pack;                                  // node pack capacity: 256 or 1024
+  int any_sorted, any_binned, pad;
 };
 
 // Forward step launchers (kernels.hip).  `W` points at a device array of
 // world descriptors.
 void launch_elastic(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
-void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, bool any_sorted);
+void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);

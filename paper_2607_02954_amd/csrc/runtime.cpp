@@ -65,7 +65,9 @@ sim_status check_params(const sim_params* p) {
   if (p->repulse_radius < 1 || p->repulse_radius > mc::kMaxRadius)
     return fail(SIM_E_INVALID, "repulse_radius must be in 1..%d", mc::kMaxRadius);
   if (!(p->sigma_repulse > 0.f)) return fail(SIM_E_INVALID, "sigma_repulse must be positive");
-  if (p->flags & ~(uint32_t)SIM_SPLAT_SORTED) return fail(SIM_E_INVALID, "unknown flag bits");
+  if (p->flags & ~(uint32_t)(SIM_SPLAT_SORTED | SIM_SPLAT_DIRECT)) return fail(SIM_E_INVALID, "unknown flag bits");
+  if ((p->flags & SIM_SPLAT_SORTED) && (p->flags & SIM_SPLAT_DIRECT))
+    return fail(SIM_E_INVALID, "SIM_SPLAT_SORTED and SIM_SPLAT_DIRECT are exclusive");
   return SIM_OK;
 }
 
@@ -83,7 +85,17 @@ struct WorldBufs {
   int* perm = nullptr;
   float4* rec = nullptr;
   int* part = nullptr;
+  int* bin_cnt = nullptr;
+  int* bin_fill = nullptr;
+  int* bin_start = nullptr;
+  int* bin_idx = nullptr;
 };
+
+inline int mode_of(const sim_params& p) {
+  return (p.flags & SIM_SPLAT_SORTED) ? mc::kSorted : (p.flags & SIM_SPLAT_DIRECT) ? mc::kDirect : mc::kBinned;
+}
+inline int tiles_x(const sim_params& p) { return (p.nx + mc::kTile - 1) / mc::kTile; }
+inline int tiles_y(const sim_params& p) { return (p.ny + mc::kTile - 1) / mc::kTile; }
 
 void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) {
   const size_t ncell = (size_t)p.nx * p.ny;
@@ -91,7 +103,8 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
   b.f_alt = c.take<float>(9 * ncell);
   b.st = c.take<float>(ncell);
   b.fel = c.take<float>(2 * N);
-  if (p.flags & SIM_SPLAT_SORTED) {
+  const int mode = mode_of(p);
+  if (mode == mc::kSorted) {
     b.key = c.take<int>(N);
     b.rank = c.take<int>(N);
     b.cnt = c.take<int>(ncell);
@@ -99,9 +112,15 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.perm = c.take<int>(N);
     b.rec = c.take<float4>(N);
     b.part = c.take<int>((ncell + 1023) / 1024 + 1);
-  } else {
+  } else if (mode == mc::kDirect) {
     b.s = c.take<float>(ncell);
     b.Fg = c.take<float>(2 * ncell);
+  } else {
+    const size_t nt = (size_t)tiles_x(p) * tiles_y(p);
+    b.bin_cnt = c.take<int>(nt);
+    b.bin_fill = c.take<int>(nt);
+    b.bin_start = c.take<int>(nt + 1);
+    b.bin_idx = c.take<int>((size_t)mc::kMaxBinsPerNode * N);
   }
 }
 
@@ -142,10 +161,10 @@ struct Engine {
   unsigned* flags = nullptr;
   int* counts = nullptr;
   mc::Pack* packs = nullptr;
-  int2* items = nullptr;
   int2* tiles = nullptr;
   int2* scan = nullptr;
-  size_t max_packs = 0, max_items = 0, max_tiles = 0, max_scan = 0;
+  int2* wlist = nullptr;
+  size_t max_packs = 0, max_tiles = 0, max_scan = 0;
   mc::Tables tab{};
   mc::Grid grid{};
   bool fixed_grid = false;
@@ -161,9 +180,9 @@ struct Engine {
   int want_chunk = 20;
   hipGraphExec_t g_pair = nullptr;
 
-  size_t n_packs = 0, n_items = 0, n_tiles = 0, n_scan = 0;
+  size_t n_packs = 0, n_tiles = 0, n_scan = 0, n_worlds = 0;
 
-  static size_t table_bytes(int max_worlds, size_t mp, size_t mi, size_t mt, size_t ms) {
+  static size_t table_bytes(int max_worlds, size_t mp, size_t mt, size_t ms) {
     Carver c{nullptr};
     c.take<mc::WorldDev>(max_worlds);
     c.take<mc::WorldDev>(max_worlds);
@@ -172,9 +191,9 @@ struct Engine {
     c.take<unsigned>(max_worlds);
     c.take<int>(8);
     c.take<mc::Pack>(mp);
-    c.take<int2>(mi);
     c.take<int2>(mt);
     c.take<int2>(ms);
+    c.take<int2>(max_worlds);
     return c.off;
   }
 
@@ -186,17 +205,17 @@ struct Engine {
     flags = c.take<unsigned>(max_worlds);
     counts = c.take<int>(8);
     packs = c.take<mc::Pack>(max_packs);
-    items = c.take<int2>(max_items);
     tiles = c.take<int2>(max_tiles);
     scan = c.take<int2>(max_scan);
+    wlist = c.take<int2>(max_worlds);
     tab.packs = packs;
     tab.n_packs = counts + 0;
-    tab.items = items;
-    tab.n_items = counts + 1;
     tab.tiles = tiles;
-    tab.n_tiles = counts + 2;
+    tab.n_tiles = counts + 1;
     tab.scan = scan;
-    tab.n_scan = counts + 3;
+    tab.n_scan = counts + 2;
+    tab.worlds = wlist;
+    tab.n_worlds = counts + 3;
   }
 
   ~Engine() {
@@ -233,7 +252,9 @@ struct Engine {
     d.u_max2 = p.u_max * p.u_max;
     d.pbd_iters = p.pbd_iters;
     d.radius = p.repulse_radius;
-    d.sorted = (p.flags & SIM_SPLAT_SORTED) ? 1 : 0;
+    d.mode = mode_of(p);
+    d.ntx = tiles_x(p);
+    d.nty = tiles_y(p);
     {
       double g[mc::kMaxRadius + 1];
       double sum = 0.0;
@@ -272,14 +293,19 @@ struct Engine {
     d.perm = s.b.perm;
     d.rec = s.b.rec;
     d.part = s.b.part;
+    d.bin_cnt = s.b.bin_cnt;
+    d.bin_fill = s.b.bin_fill;
+    d.bin_start = s.b.bin_start;
+    d.bin_idx = s.b.bin_idx;
     return d;
   }
 
   // Rebuild work tables and descriptors from the slot list and upload them.
   sim_status rebuild() {
     std::vector<mc::Pack> pk;
-    std::vector<int2> it, tl, sc;
+    std::vector<int2> tl, sc, wl;
     any_sorted = false;
+    bool any_binned = false;
     for (int w = 0; w < (int)slots.size(); ++w) {
       const Slot& s = slots[w];
       if (!s.used) continue;
@@ -298,32 +324,37 @@ struct Engine {
         f = end;
       }
       const int ncell = s.p.nx * s.p.ny;
-      for (int c = 0; c < ncell; c += mc::kCellsPerItem) it.push_back(make_int2(w, c));
-      const int ntx = (s.p.nx + mc::kTileX - 1) / mc::kTileX;
-      const int nty = (s.p.ny + mc::kTileY - 1) / mc::kTileY;
-      for (int t = 0; t < ntx * nty; ++t) tl.push_back(make_int2(w, t));
-      if (s.p.flags & SIM_SPLAT_SORTED) {
+      for (int t = 0; t < tiles_x(s.p) * tiles_y(s.p); ++t) tl.push_back(make_int2(w, t));
+      wl.push_back(make_int2(w, 0));
+      const int mode = mode_of(s.p);
+      if (mode == mc::kSorted) {
         any_sorted = true;
         const int nb = (ncell + 1023) / 1024;
         for (int b = 0; b < nb; ++b) sc.push_back(make_int2(w, b));
       }
+      if (mode == mc::kBinned) any_binned = true;
     }
-    if (pk.size() > max_packs || it.size() > max_items || tl.size() > max_tiles || sc.size() > max_scan)
+    if (pk.size() > max_packs || tl.size() > max_tiles || sc.size() > max_scan)
       return fail(SIM_E_WORKSPACE, "work tables exceed their capacity");
     n_packs = pk.size();
-    n_items = it.size();
     n_tiles = tl.size();
     n_scan = sc.size();
+    n_worlds = wl.size();
     if (!fixed_grid) {
       grid.node_blocks = (int)std::max<size_t>(1, n_packs);
-      grid.cell_blocks = (int)std::max<size_t>(1, n_items);
       grid.tile_blocks = (int)std::max<size_t>(1, n_tiles);
       grid.scan_blocks = (int)std::max<size_t>(1, n_scan);
+      grid.world_blocks = (int)std::max<size_t>(1, n_worlds);
     }
+    // a kernel family stays in the captured graphs once any world needed it
+    const bool more = (any_sorted && !grid.any_sorted) || (any_binned && !grid.any_binned);
+    grid.any_sorted |= any_sorted ? 1 : 0;
+    grid.any_binned |= any_binned ? 1 : 0;
+    if (more) drop_graphs();
     // stage into pinned memory once the previous upload has been consumed
     HIPCHK(hipEventSynchronize(upload_done));
     const size_t need = 2 * max_worlds * sizeof(mc::WorldDev) + 8 * sizeof(int) + pk.size() * sizeof(mc::Pack) +
-                        (it.size() + tl.size() + sc.size()) * sizeof(int2);
+                        (tl.size() + sc.size() + wl.size()) * sizeof(int2);
     if (need > pinned_bytes) {
       if (pinned) HIPCHK(hipHostFree(pinned));
       pinned_bytes = need * 2;
@@ -347,12 +378,12 @@ struct Engine {
     sim_status st;
     if ((st = put(desc[0], d0.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
     if ((st = put(desc[1], d1.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
-    int cnt[8] = {(int)n_packs, (int)n_items, (int)n_tiles, (int)n_scan, 0, 0, 0, 0};
+    int cnt[8] = {(int)n_packs, (int)n_tiles, (int)n_scan, (int)n_worlds, 0, 0, 0, 0};
     if ((st = put(counts, cnt, sizeof(cnt)))) return st;
     if ((st = put(packs, pk.data(), pk.size() * sizeof(mc::Pack)))) return st;
-    if ((st = put(items, it.data(), it.size() * sizeof(int2)))) return st;
     if ((st = put(tiles, tl.data(), tl.size() * sizeof(int2)))) return st;
     if ((st = put(scan, sc.data(), sc.size() * sizeof(int2)))) return st;
+    if ((st = put(wlist, wl.data(), wl.size() * sizeof(int2)))) return st;
     HIPCHK(hipEventRecord(upload_done, stream));
     return SIM_OK;
   }
@@ -360,7 +391,7 @@ struct Engine {
   void enqueue_step(int parity, hipStream_t s) const {
     const mc::WorldDev* d = desc[parity];
     mc::launch_elastic(d, tab, grid, s);
-    mc::launch_sort(d, tab, grid, s, any_sorted);
+    mc::launch_sort(d, tab, grid, s);
     mc::launch_filter(d, tab, grid, s);
     mc::launch_repulse(d, tab, grid, s);
     mc::launch_lbm(d, tab, grid, s);
@@ -445,10 +476,9 @@ namespace {
 
 size_t world_table_bytes(const sim_params& p, int n_fil) {
   const size_t ncell = (size_t)p.nx * p.ny;
-  const size_t items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
-  const size_t tiles = (size_t)((p.nx + mc::kTileX - 1) / mc::kTileX) * ((p.ny + mc::kTileY - 1) / mc::kTileY);
+  const size_t tiles = (size_t)tiles_x(p) * tiles_y(p);
   const size_t scans = (ncell + 1023) / 1024;
-  return Engine::table_bytes(1, std::max(n_fil, 1), items, tiles, scans);
+  return Engine::table_bytes(1, std::max(n_fil, 1), tiles, scans);
 }
 
 size_t world_buf_bytes(const sim_params& p, int n_part) {
@@ -546,8 +576,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   e.max_worlds = 1;
   const size_t ncell = (size_t)p->nx * p->ny;
   e.max_packs = std::max(a->n_filaments, 1);
-  e.max_items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
-  e.max_tiles = (size_t)((p->nx + mc::kTileX - 1) / mc::kTileX) * ((p->ny + mc::kTileY - 1) / mc::kTileY);
+  e.max_tiles = (size_t)tiles_x(*p) * tiles_y(*p);
   e.max_scan = (ncell + 1023) / 1024;
   e.grid.pack = max_len <= 256 ? 256 : 1024;
   Carver c{(char*)workspace};
@@ -583,6 +612,11 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   if (sl.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, sl.b.cnt, ncell);
   if (sl.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.s, ncell);
   if (sl.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.Fg, 2 * ncell);
+  if (sl.b.bin_cnt) {
+    const size_t nt = (size_t)tiles_x(*p) * tiles_y(*p);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_fill, nt);
+  }
   if (hipGetLastError() != hipSuccess) {
     delete w;
     return fail(SIM_E_HIP, "initialisation kernels failed to launch");
@@ -681,7 +715,7 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
   switch (which) {
     case 0:
       mc::launch_elastic(d, e.tab, e.grid, e.stream);
-      mc::launch_sort(d, e.tab, e.grid, e.stream, e.any_sorted);
+      mc::launch_sort(d, e.tab, e.grid, e.stream);
       break;
     case 1: mc::launch_filter(d, e.tab, e.grid, e.stream); break;
     case 2: mc::launch_repulse(d, e.tab, e.grid, e.stream); break;
@@ -715,7 +749,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     HIPCHK(hipEventRecord(E[0], e.stream));
     mc::launch_elastic(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[1], e.stream));
-    mc::launch_sort(d, e.tab, e.grid, e.stream, e.any_sorted);
+    mc::launch_sort(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[2], e.stream));
     mc::launch_filter(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[3], e.stream));
@@ -851,11 +885,11 @@ sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, v
   // least 96 bytes, every node at least 36 bytes
   const size_t max_cells = pool_bytes / 96 + 1;
   const size_t max_nodes = pool_bytes / 36 + 1;
-  e.max_items = max_cells / mc::kCellsPerItem + max_worlds;
-  e.max_tiles = 2 * e.max_items + max_worlds;
+  // a world of c cells has at most c/1024 + nx/32 + ny/32 + 1 <= c/64 + 1 tiles
+  e.max_tiles = max_cells / 64 + max_worlds;
   e.max_scan = max_cells / 1024 + max_worlds;
   e.max_packs = 2 * (max_nodes / 256) + 2 * (size_t)max_worlds;
-  b->table_bytes = Engine::table_bytes(max_worlds, e.max_packs, e.max_items, e.max_tiles, e.max_scan);
+  b->table_bytes = Engine::table_bytes(max_worlds, e.max_packs, e.max_tiles, e.max_scan);
   if (b->table_bytes >= pool_bytes / 2) {
     delete b;
     return fail(SIM_E_WORKSPACE, "pool too small for %d worlds", max_worlds);
@@ -869,9 +903,9 @@ sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, v
   e.fixed_grid = true;
   e.grid.pack = 256;
   e.grid.node_blocks = 2048;
-  e.grid.cell_blocks = 4096;
   e.grid.tile_blocks = 2048;
   e.grid.scan_blocks = 1024;
+  e.grid.world_blocks = 256;
   e.want_chunk = 20;
   sim_status st = e.init_host(1 << 20);
   if (st) {
@@ -899,10 +933,9 @@ sim_status sim_batch_set_tuning(sim_batch* b, int32_t chunk_steps, int32_t cell_
     return fail(SIM_E_INVALID, "chunk_steps must be even and >= 2; block counts >= 1");
   Engine& e = b->eng;
   e.want_chunk = chunk_steps;
-  e.grid.cell_blocks = cell_blocks;
+  e.grid.tile_blocks = cell_blocks;
   e.grid.node_blocks = node_blocks;
-  e.grid.tile_blocks = std::max(1, cell_blocks / 2);
-  e.grid.scan_blocks = std::max(1, cell_blocks / 4);
+  e.grid.scan_blocks = std::max(1, cell_blocks / 2);
   e.drop_graphs();
   return SIM_OK;
 }
@@ -965,6 +998,11 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
   if (s.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, s.b.cnt, ncell);
   if (s.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.b.s, ncell);
   if (s.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.b.Fg, 2 * ncell);
+  if (s.b.bin_cnt) {
+    const size_t nt = (size_t)tiles_x(*p) * tiles_y(*p);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_cnt, nt);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_fill, nt);
+  }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, e.stream, (int*)(e.flags + w), (size_t)1);
   HIPCHK(hipGetLastError());
   s.cur = 0;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmicrocosm.so")
 
 SIM_OK, SIM_E_INVALID, SIM_E_WORKSPACE, SIM_E_HIP, SIM_E_UNSTABLE, SIM_E_STATE, SIM_E_FULL = range(7)
 SIM_SPLAT_SORTED = 1
+SIM_SPLAT_DIRECT = 2
 
 # D2Q9 weights in the library's velocity order; the library stores f - w.
 LATTICE_WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
@@ -132,13 +133,16 @@ class Params:
     sigma_repulse: float = 1.0
     repulse_radius: int = 4
     u_max: float = 0.3
-    sorted: bool = False
+    transfer: str = "binned"          # "binned" (default), "sorted" or "direct"
+
+    def flags(self) -> int:
+        return {"binned": 0, "sorted": SIM_SPLAT_SORTED, "direct": SIM_SPLAT_DIRECT}[self.transfer]
 
     def c(self) -> SimParams:
         return SimParams(self.nx, self.ny, self.tau, self.trt_magic, self.k_bend, self.k_stretch,
                          self.k_shear, self.pbd_iters, self.k_elastic, self.k_repulse,
                          self.sigma_repulse, self.repulse_radius, self.u_max,
-                         SIM_SPLAT_SORTED if self.sorted else 0)
+                         self.flags())
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -57,16 +57,19 @@ def gpu_state(W):
     return x, f
 
 
-def _mk(sim, w, sorted_=False, **kw):
-    p = sim.Params(nx=w.nx, ny=w.ny, sorted=sorted_, **kw)
+MODES = ["binned", "sorted", "direct"]
+
+
+def _mk(sim, w, mode="binned", **kw):
+    p = sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw)
     return sim.World(w, p), oracle_params(p)
 
 
-@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
-def test_substeps_match_oracle(sorted_):
+@pytest.mark.parametrize("mode", MODES)
+def test_substeps_match_oracle(mode):
     sim = _sim()
     w = ragged_world(1)
-    W, op = _mk(sim, w, sorted_)
+    W, op = _mk(sim, w, mode)
     inp = O.inputs_from_world(w)
     W.rollout(0, 6)                       # non-trivial shared state
     torch.cuda.synchronize()
@@ -79,7 +82,7 @@ def test_substeps_match_oracle(sorted_):
     fel = W.buffer(3, (2, N)).cpu().numpy()
     e_el = rel(fel, tr["f_el"].numpy())
     assert e_el < 2e-5, e_el
-    if not sorted_:
+    if mode == "direct":
         s = W.buffer(0, (ny, nx)).cpu().numpy()
         assert rel(s, tr["s"].numpy()) < 1e-6
     W.substep(1, t)
@@ -88,7 +91,7 @@ def test_substeps_match_oracle(sorted_):
     W.substep(2, t)
     F = W.buffer(3, (2, N)).cpu().numpy()
     assert rel(F, tr["force"].numpy()) < 2e-5
-    if not sorted_:
+    if mode == "direct":
         Fg = W.buffer(2, (2, ny, nx)).cpu().numpy()
         assert rel(Fg, tr["Fg"].numpy()) < 2e-5
     W.substep(3, t)
@@ -103,11 +106,11 @@ def test_substeps_match_oracle(sorted_):
     torch.cuda.synchronize()
     xref = (x + O.interpolate(x, tr["u"], op)).numpy()
     assert rel(W.state.positions64(), xref) < TOL_X
-    print(f"substeps[{'sorted' if sorted_ else 'atomic'}]: e_el={e_el:.2e} e_u={e_u:.2e}")
+    print(f"substeps[{mode}]: e_el={e_el:.2e} e_u={e_u:.2e}")
 
 
-def _rollout_compare(sim, w, n, sorted_, step_api=True, **kw):
-    W, op = _mk(sim, w, sorted_, **kw)
+def _rollout_compare(sim, w, n, mode, **kw):
+    W, op = _mk(sim, w, mode, **kw)
     inp = O.inputs_from_world(w)
     x = O.positions_from_world(w)
     f = O.rest_populations(op)
@@ -125,17 +128,17 @@ def _rollout_compare(sim, w, n, sorted_, step_api=True, **kw):
     return ex_max, eu_max
 
 
-@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
-def test_single_chain_100_steps(sorted_):
+@pytest.mark.parametrize("mode", MODES)
+def test_single_chain_100_steps(mode):
     sim = _sim()
-    ex, eu = _rollout_compare(sim, wl.parity_single(0), 100, sorted_)
+    ex, eu = _rollout_compare(sim, wl.parity_single(0), 100, mode)
     print(f"single chain 32 nodes 64^2, 100 steps: max e_x={ex:.2e} max e_u={eu:.2e}")
 
 
-@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
-def test_ragged_population_100_steps(sorted_):
+@pytest.mark.parametrize("mode", MODES)
+def test_ragged_population_100_steps(mode):
     sim = _sim()
-    ex, eu = _rollout_compare(sim, ragged_world(2), 100, sorted_)
+    ex, eu = _rollout_compare(sim, ragged_world(2), 100, mode)
     print(f"ragged population: max e_x={ex:.2e} max e_u={eu:.2e}")
 
 
@@ -144,7 +147,7 @@ def test_graph_rollout_equals_stepwise_and_sorted_is_deterministic():
     w = ragged_world(3)
     runs = []
     for mode in ("rollout", "rollout", "step"):
-        W, _ = _mk(sim, w, True)
+        W, _ = _mk(sim, w, "sorted")
         if mode == "rollout":
             W.rollout(0, 37)
         else:
@@ -157,7 +160,7 @@ def test_graph_rollout_equals_stepwise_and_sorted_is_deterministic():
         assert torch.equal(a, b)            # bitwise reproducible
     for a, b in zip(runs[0], runs[2]):
         assert torch.equal(a, b)            # graph path == plain launches
-    Wa, _ = _mk(sim, w, False)
+    Wa, _ = _mk(sim, w, "binned")
     Wa.rollout(0, 37)
     torch.cuda.synchronize()
     xs = runs[0][0].numpy() + runs[0][1].numpy().astype(np.float64)
@@ -167,12 +170,12 @@ def test_graph_rollout_equals_stepwise_and_sorted_is_deterministic():
 def test_checkpoints_hold_segment_start_states():
     sim = _sim()
     w = ragged_world(4)
-    W, _ = _mk(sim, w, True)
+    W, _ = _mk(sim, w, "sorted")
     nb = W.checkpoint_bytes(30, 10)
     ck = torch.zeros(nb, dtype=torch.uint8, device="cuda")
     W.rollout(0, 30, 10, ck)
     torch.cuda.synchronize()
-    ref, _ = _mk(sim, w, True)
+    ref, _ = _mk(sim, w, "sorted")
     N = w.n_particles
     per = nb // 3
     for seg in range(3):
@@ -185,35 +188,66 @@ def test_checkpoints_hold_segment_start_states():
     assert torch.equal(W.state.frac.cpu(), ref.state.frac.cpu())
 
 
-@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
-def test_edge_cases(sorted_):
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_cases(mode):
     sim = _sim()
     # empty world: fluid stays at rest
     empty = wl._assemble(32, 24, [], [], [], [], [], [])
-    W, _ = _mk(sim, empty, sorted_)
+    W, _ = _mk(sim, empty, mode)
     W.rollout(0, 5)
     W.sync()
     assert float(W.state.f.abs().max()) < 1e-7
     # one long filament (> 256 nodes uses the 1024-node pack) plus single nodes
     long = wl.random_world(5, 96, 96, [600, 1, 1, 2], amp=0.5)
-    ex, eu = _rollout_compare(sim, long, 10, sorted_)
+    ex, eu = _rollout_compare(sim, long, 10, mode)
     print(f"long filament: e_x={ex:.2e} e_u={eu:.2e}")
 
 
 def test_mach_guard_flags_world():
     sim = _sim()
-    W, _ = _mk(sim, ragged_world(6), False, u_max=1e-9)
+    W, _ = _mk(sim, ragged_world(6), "binned", u_max=1e-9)
     W.rollout(0, 4)
     with pytest.raises(sim.SimError) as ei:
         W.sync()
     assert ei.value.status == sim.SIM_E_UNSTABLE
 
 
-@pytest.mark.parametrize("sorted_", [False, True], ids=["atomic", "sorted"])
-def test_uniform_population_full_size_steps(sorted_):
+@pytest.mark.parametrize("mode", MODES)
+def test_uniform_population_full_size_steps(mode):
     # 1024 chains x 64 nodes on 512^2 with active bending: every element of
     # positions and u after each of 3 steps from the shared state
     sim = _sim()
     w = wl.uniform_population(0)
-    ex, eu = _rollout_compare(sim, w, 3, sorted_)
+    ex, eu = _rollout_compare(sim, w, 3, mode)
     print(f"uniform 65536 nodes 512^2: e_x={ex:.2e} e_u={eu:.2e}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_small_and_ragged_grids(mode):
+    # grids narrower than a tile, not multiples of the tile, and wrapping
+    # supports that alias inside the filter halo
+    sim = _sim()
+    for (nx, ny, lens) in [(8, 8, [3]), (40, 24, [6, 4]), (72, 50, [20, 1, 9])]:
+        w = wl.random_world(7, nx, ny, lens, amp=0.5)
+        ex, eu = _rollout_compare(sim, w, 12, mode)
+        print(f"{nx}x{ny}: e_x={ex:.2e} e_u={eu:.2e}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_scaling_workload_full_size(mode):
+    # the benchmark's million-node workload, in the benchmark's launch
+    # configuration (captured-graph rollout), two steps, every node and cell
+    sim = _sim()
+    w = wl.scaling_population(0)
+    W, op = _mk(sim, w, mode)
+    W.rollout(0, 2)
+    W.sync()
+    inp = O.inputs_from_world(w)
+    x, f = O.positions_from_world(w), O.rest_populations(op)
+    with torch.no_grad():
+        for t in range(2):
+            x, f, u = O.step(x, f, t, inp, op)
+    ex = rel(W.state.positions64(), x.numpy())
+    eu = rel(W.state.u.cpu().numpy(), u.numpy())
+    print(f"scaling 1M nodes 2048^2 [{mode}]: e_x={ex:.2e} e_u={eu:.2e}")
+    assert ex <= TOL_X and eu <= TOL_U
