@@ -103,7 +103,8 @@ typedef struct sim_arrays {
                                  step, stored SHIFTED by the lattice weights: f_q - w_q.
                                  Velocity order: rest, +x, +y, -x, -y, (+1,+1), (-1,+1),
                                  (-1,-1), (+1,-1).                                        */
-  float *u;                   /* [2][ny][nx] out: fluid velocity of the last step taken   */
+  float *u;                   /* [ny][nx][2] out: fluid velocity (x, y interleaved) of
+                                 the last step taken                                     */
 } sim_arrays;
 
 typedef struct sim_world sim_world;
@@ -167,18 +168,18 @@ const char *sim_last_error(void);
 /* Test hook: run a single sub-step kernel of step t on the current state
  * (which: 0 elastic force + deposit, 1 filter, 2 repulsion + spread,
  * 3 fluid update, 4 gather + integrate), and expose the world's internal
- * per-step buffers (which: 0 deposit s [ny][nx] and 2 grid force [2][ny][nx],
- * both SIM_SPLAT_DIRECT only, else NULL; 1 filtered s~ [ny][nx]; 3 node force
- * [2][N]).  For parity tests. */
+ * per-step buffers (which: 0 deposit s [ny][nx], SIM_SPLAT_DIRECT only, else
+ * NULL; 1 central difference of the filtered density [ny][nx][2]; 2 grid
+ * force [ny][nx][2]; 3 node force [2][N]).  For parity tests. */
 sim_status sim_debug_substep(sim_world *w, int32_t which, int64_t t);
 sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
 
 /* Measurement hook: run n_steps ordinary steps from time index t0 (kernels
  * launched directly, not from a graph) with HIP events on the world's stream
  * around every kernel group, and write the mean device time in milliseconds
- * of each group to ms_out[6]: 0 elastic force + deposit, 1 sorted-transfer
- * sort (0 in atomic mode), 2 filter, 3 repulsion + spread, 4 fluid update,
- * 5 gather + integrate.  The state advances exactly as with sim_rollout.
+ * of each group to ms_out[6]: 0 elastic force, 1 transfer preparation
+ * (tile binning or sorting; 0 in direct mode), 2 deposit + filter,
+ * 3 repulsion + spread, 4 fluid update, 5 gather + integrate.  The state advances exactly as with sim_rollout.
  * Synchronises the stream. */
 sim_status sim_profile_steps(sim_world *w, int64_t t0, int32_t n_steps, float *ms_out);
 

@@ -1,21 +1,524 @@
-// Reverse-mode (adjoint) kernels of the filament-fluid step.
-#include "engine.h"
-#include "microcosm.h"
+// Reverse mode of one filament-fluid step (hand-written adjoint kernels).
+//
+// The paper differentiates end to end through the PBD solver and the fluid
+// (Methods; Experiments, Filament Folding).  Given dL/dx_{t+1} and
+// dL/dg_{t+1}, one reversed step produces dL/dx_t, dL/dg_t and accumulates
+// dL/d(rest angle), visiting the forward sub-steps backwards:
+//   k_adj_u       S7: u~ = spread(dL/dx_{t+1})                 (tile, LDS)
+//   k_adj_lbm     S6: streaming^T (pull) and the collision Jacobian^T per
+//                     cell -> dL/dg_t, dL/dF_grid
+//   k_adj_force   S5, S4, S7: dL/dF_i = gather(dL/dF_grid); the derivative
+//                     terms of the three node gathers/spreads w.r.t. x_t
+//   k_adj_grad    S4: dL/dG = -k_rep spread(dL/dF)              (tile, LDS)
+//   k_adj_filter  S3: dL/ds = G (D^T dL/dG): the central difference and the
+//                     symmetric Gaussian transposed                (tile, LDS)
+//   k_adj_pbd     S2, S1, S0: the deposit derivative, then the PBD iterations
+//                     reversed pass by pass (forward states recomputed and
+//                     kept in registers), atan2 of the initial edge angles and
+//                     the actuation -> dL/dx_t and dL/d(rest angle)
+// Every forward field the adjoint needs (x_t, g_t, G_t, F_t, F_grid, u_t and
+// the tile bins of x_t) is taken from the tape written by the recomputed
+// forward step; the descriptor passed in points at that tape slot.
+#include "device_util.h"
 
-extern "C" {
+namespace mc {
 
-sim_status sim_backward_workspace_size(const sim_world* w, int32_t ckpt_every, size_t* bytes) {
-  (void)w;
-  (void)ckpt_every;
-  if (bytes) *bytes = 0;
-  return SIM_E_STATE;
+constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registers
+
+// ---------------------------------------------------------------------------
+// Node -> grid spreads of adjoint node vectors (u~ and G~), tile-binned.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__ W, Tables T, const float* v,
+                                                    float scale_is_rep, float2* out) {
+  __shared__ long long s_x[kTile * kTile];
+  __shared__ long long s_y[kTile * kTile];
+  const int nt = *T.n_tiles;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    const int2 tl = T.tiles[it];
+    const WorldDev& w = W[tl.x];
+    const int nx = w.nx, ny = w.ny;
+    const int x0 = (tl.y % w.ntx) * kTile;
+    const int y0 = (tl.y / w.ntx) * kTile;
+    const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
+    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+      s_x[k] = 0;
+      s_y[k] = 0;
+    }
+    __syncthreads();
+    const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
+    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y);
+    __syncthreads();
+    MC_GLOBAL vf2* o = glbv<vf2>(out);
+    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+      const int ly = k >> 5, lx = k & (kTile - 1);
+      if (lx >= tw || ly >= th) continue;
+      const vf2 val = {fix_to_float(s_x[k]), fix_to_float(s_y[k])};
+      o[(size_t)(y0 + ly) * nx + x0 + lx] = val;
+    }
+    __syncthreads();
+  }
 }
 
-sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_every, const void* ckpt,
-                        const float* g_pos, float* g_rest_angle, float* g_pos0, void* adj_ws, size_t adj_ws_bytes) {
-  (void)w; (void)t0; (void)n_steps; (void)ckpt_every; (void)ckpt; (void)g_pos; (void)g_rest_angle;
-  (void)g_pos0; (void)adj_ws; (void)adj_ws_bytes;
-  return SIM_E_STATE;
+// ---------------------------------------------------------------------------
+// S6 reversed: pull-streaming transpose and the TRT/Guo collision Jacobian
+// transposed, per cell.  Reads g_t, F_grid_t (tape) and u~ (from k_adj_u).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+  const int nit = *T.n_items;
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    const int2 item = T.items[it];
+    const WorldDev& w = W[item.x];
+    const int nx = w.nx, ny = w.ny;
+    const int ncell = nx * ny;
+    const int c = item.y + threadIdx.x;
+    if (c >= ncell) continue;
+    const int y = c / nx;
+    const int x = c - y * nx;
+    const MC_GLOBAL float* src = glb(w.f_src);
+    const MC_GLOBAL float* gin = glb(A.gbar_in);
+    float g[9], gs[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      g[q] = src[(size_t)q * ncell + c];
+      const int xn = wrap_near(x + kCX[q], nx);
+      const int yn = wrap_near(y + kCY[q], ny);
+      gs[q] = gin[(size_t)q * ncell + (size_t)yn * nx + xn];     // dL/dg*_q(c)
+    }
+    const vf2 F = glbv<const vf2>(w.Fg)[c];
+    const vf2 ubv = glbv<const vf2>(A.ubar)[c];
+    // forward moments
+    const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float rho = 1.0f + drho;
+    const float jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const float jy = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
+    const float inv = 1.0f / rho;
+    const float ux = (jx + 0.5f * F.x) * inv;
+    const float uy = (jy + 0.5f * F.y) * inv;
+    const float usq = ux * ux + uy * uy;
+    const float op = w.om_p, om = w.om_m;
+    const float ap = 1.0f - 0.5f * op, am = 1.0f - 0.5f * om;
+    // g* = g - op P+ (g - geq) - om P- (g - geq) + ap P+ S + am P- S, with
+    // self-adjoint projectors P+- onto the parts (anti)symmetric under
+    // q <-> opposite(q)
+    float gdir[9], geqb[9], Sb[9];
+    gdir[0] = gs[0] - op * gs[0];
+    geqb[0] = op * gs[0];
+    Sb[0] = ap * gs[0];
+#pragma unroll
+    for (int pr = 0; pr < 4; ++pr) {
+      const int q = pr < 2 ? 1 + pr : 5 + (pr - 2);
+      const int qb = q + 2;
+      const float sp = 0.5f * (gs[q] + gs[qb]);
+      const float sm = 0.5f * (gs[q] - gs[qb]);
+      gdir[q] = gs[q] - op * sp - om * sm;
+      gdir[qb] = gs[qb] - op * sp + om * sm;
+      geqb[q] = op * sp + om * sm;
+      geqb[qb] = op * sp - om * sm;
+      Sb[q] = ap * sp + am * sm;
+      Sb[qb] = ap * sp - am * sm;
+    }
+    // geq_q = w_q (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)),
+    // S_q = w_q (3 c.F - 3 u.F + 9 (c.u)(c.F))
+    float ubx = ubv.x, uby = ubv.y, drb = 0.f, Fbx = 0.f, Fby = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const float wq = q == 0 ? (4.0f / 9.0f) : (q < 5 ? (1.0f / 9.0f) : (1.0f / 36.0f));
+      const float cxq = (float)kCX[q], cyq = (float)kCY[q];
+      const float cu = cxq * ux + cyq * uy;
+      const float cF = cxq * F.x + cyq * F.y;
+      const float e = geqb[q] * wq;
+      drb += e * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * usq);
+      const float er = e * rho;
+      ubx += er * (3.0f * cxq + 9.0f * cu * cxq - 3.0f * ux);
+      uby += er * (3.0f * cyq + 9.0f * cu * cyq - 3.0f * uy);
+      const float sb = Sb[q] * wq;
+      ubx += sb * (-3.0f * F.x + 9.0f * cF * cxq);
+      uby += sb * (-3.0f * F.y + 9.0f * cF * cyq);
+      Fbx += sb * (3.0f * cxq - 3.0f * ux + 9.0f * cu * cxq);
+      Fby += sb * (3.0f * cyq - 3.0f * uy + 9.0f * cu * cyq);
+    }
+    // u = (j + F/2) / rho
+    Fbx += 0.5f * ubx * inv;
+    Fby += 0.5f * uby * inv;
+    const float jbx = ubx * inv, jby = uby * inv;
+    drb -= (ubx * ux + uby * uy) * inv;
+    MC_GLOBAL float* gout = glb(A.gbar);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      gout[(size_t)q * ncell + c] = gdir[q] + drb + (float)kCX[q] * jbx + (float)kCY[q] * jby;
+    const vf2 fb = {Fbx, Fby};
+    glbv<vf2>(A.Fgbar)[c] = fb;
+  }
 }
 
+// ---------------------------------------------------------------------------
+// S5/S4/S7 node terms: dL/dF_i = sum_c W(c - x_i) dL/dF_grid(c), and the
+// derivative of the three node<->grid transfers with respect to x_t.
+// ---------------------------------------------------------------------------
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+  const int npk = *T.n_packs;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    const int gi = pk.node_begin + threadIdx.x;
+    if (gi >= pk.node_end) continue;
+    const int N = w.n_part, nx = w.nx, ny = w.ny;
+    const MC_GLOBAL int* cell = glb(w.cell_in);
+    const MC_GLOBAL float* frac = glb(w.frac_in);
+    const int bx = wrap_index(cell[gi], nx), by = wrap_index(cell[N + gi], ny);
+    float wx[4], dwx[4], wy[4], dwy[4];
+    peskin4_d(frac[gi], wx, dwx);
+    peskin4_d(frac[N + gi], wy, dwy);
+    const float xbx = A.xbar_in[gi], xby = A.xbar_in[N + gi];
+    const float Fx = w.fel[gi], Fy = w.fel[N + gi];
+    const MC_GLOBAL vf2* u = glbv<const vf2>(w.u);
+    const MC_GLOBAL vf2* Fgb = glbv<const vf2>(A.Fgbar);
+    const MC_GLOBAL vf2* Gr = glbv<const vf2>(w.grad);
+    int ix[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ix[a] = wrap_near(bx - 1 + a, nx);
+    float fbx = 0.f, fby = 0.f;       // dL/dF_i
+    float sux = 0.f, suy = 0.f;       // d/dx of  sum_c W (u_c . xbar')
+    float sfx = 0.f, sfy = 0.f;       // d/dx of  sum_c W (F_i . Fgbar_c)
+    float grx[4][4], gry[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const size_t row = (size_t)wrap_near(by - 1 + b, ny) * nx;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const vf2 uc = u[row + ix[a]];
+        const vf2 fc = Fgb[row + ix[a]];
+        const vf2 gc = Gr[row + ix[a]];
+        grx[b][a] = gc.x;
+        gry[b][a] = gc.y;
+        const float W0 = wx[a] * wy[b], Wx = dwx[a] * wy[b], Wy = wx[a] * dwy[b];
+        fbx += W0 * fc.x;
+        fby += W0 * fc.y;
+        const float pu = uc.x * xbx + uc.y * xby;
+        sux += Wx * pu;
+        suy += Wy * pu;
+        const float pf = Fx * fc.x + Fy * fc.y;
+        sfx += Wx * pf;
+        sfy += Wy * pf;
+      }
+    }
+    // repulsion F_rep = -k sum_c W G_c : d/dx of (-k sum_c W (G_c . Fbar))
+    float srx = 0.f, sry = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const float pg = grx[b][a] * fbx + gry[b][a] * fby;
+        srx += dwx[a] * wy[b] * pg;
+        sry += wx[a] * dwy[b] * pg;
+      }
+    const float kr = w.k_rep;
+    A.Fbar[gi] = fbx;
+    A.Fbar[N + gi] = fby;
+    A.xbar[gi] = xbx + sux + sfx - kr * srx;
+    A.xbar[N + gi] = xby + suy + sfy - kr * sry;
+  }
 }
+
+// ---------------------------------------------------------------------------
+// S3 reversed: dL/ds = G (D^T dL/dG) on a 32x32 tile.  dL/dG is staged with
+// an (R+1)-cell halo; D^T maps it to an R-cell halo; the symmetric Gaussian
+// then runs as in the forward filter.
+// ---------------------------------------------------------------------------
+constexpr int kAdjRing = kTile + 2;
+constexpr int kAdjRegion = kAdjRing + 2 * kMaxRadius;
+constexpr int kAdjInner = kTile + 2 * kMaxRadius;
+
+__global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+  __shared__ float s_gx[kAdjRegion * kAdjRegion];
+  __shared__ float s_gy[kAdjRegion * kAdjRegion];
+  __shared__ float s_in[kAdjInner * kAdjInner];
+  __shared__ float s_mid[kAdjInner * kTile];
+  const int nt = *T.n_tiles;
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    const int2 tl = T.tiles[it];
+    const WorldDev& w = W[tl.x];
+    const int R = w.radius;
+    const int nx = w.nx, ny = w.ny;
+    const int x0 = (tl.y % w.ntx) * kTile;
+    const int y0 = (tl.y / w.ntx) * kTile;
+    const int rega = kAdjRing + 2 * R;       // dL/dG region, origin (x0-R-1, y0-R-1)
+    const int regb = kTile + 2 * R;          // D^T dL/dG region, origin (x0-R, y0-R)
+    const MC_GLOBAL vf2* gb = glbv<const vf2>(A.Gbar);
+    for (int k = tid; k < rega * rega; k += 256) {
+      const int r = k / rega, c = k - (k / rega) * rega;
+      const vf2 v = gb[(size_t)wrap_index(y0 - R - 1 + r, ny) * nx + wrap_index(x0 - R - 1 + c, nx)];
+      s_gx[k] = v.x;
+      s_gy[k] = v.y;
+    }
+    __syncthreads();
+    // (D^T h)(c) = (h_x(c - e_x) - h_x(c + e_x)) / 2 + (h_y(c - e_y) - h_y(c + e_y)) / 2
+    for (int k = tid; k < regb * regb; k += 256) {
+      const int r = k / regb, c = k - (k / regb) * regb;
+      const int ra = r + 1, ca = c + 1;
+      s_in[k] = 0.5f * (s_gx[ra * rega + ca - 1] - s_gx[ra * rega + ca + 1]) +
+                0.5f * (s_gy[(ra - 1) * rega + ca] - s_gy[(ra + 1) * rega + ca]);
+    }
+    __syncthreads();
+    for (int k = tid; k < regb * kTile; k += 256) {
+      const int r = k / kTile, c = k - (k / kTile) * kTile;
+      const float* row = s_in + r * regb + c + R;
+      float acc = w.gtap[0] * row[0];
+      for (int m = 1; m <= R; ++m) acc += w.gtap[m] * (row[-m] + row[m]);
+      s_mid[r * kTile + c] = acc;
+    }
+    __syncthreads();
+    MC_GLOBAL float* sb = glb(A.sbar);
+    for (int k = tid; k < kTile * kTile; k += 256) {
+      const int r = k >> 5, c = k & (kTile - 1);
+      const float* col = s_mid + (r + R) * kTile + c;
+      float acc = w.gtap[0] * col[0];
+      for (int m = 1; m <= R; ++m) acc += w.gtap[m] * (col[-m * kTile] + col[m * kTile]);
+      const int gx = x0 + c, gy = y0 + r;
+      if (gx < nx && gy < ny) sb[(size_t)gy * nx + gx] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S2 + S1 + S0 reversed, one block per node pack.
+// ---------------------------------------------------------------------------
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+  __shared__ float s_th[PACK];
+  __shared__ float s_dx[PACK];
+  __shared__ float s_dy[PACK];
+  __shared__ float s_gx[PACK];     // dL/dd per node
+  __shared__ float s_gy[PACK];
+  __shared__ float s_gth[PACK];    // dL/dtheta per edge
+  __shared__ int s_off[PACK + 1];
+  const int npk = *T.n_packs;
+  const int li = threadIdx.x;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    const int N = w.n_part, nx = w.nx, ny = w.ny;
+    const MC_GLOBAL int* cell = glb(w.cell_in);
+    const MC_GLOBAL float* frac = glb(w.frac_in);
+    const int nf = pk.fil_end - pk.fil_begin;
+    for (int k = li; k <= nf; k += PACK) s_off[k] = glb(w.fil_offset)[pk.fil_begin + k] - pk.node_begin;
+    __syncthreads();
+    const int gi = pk.node_begin + li;
+    const bool active = gi < pk.node_end;
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= li) lo = mid; else hi = mid - 1;
+    }
+    const int o = s_off[lo];
+    const int n = s_off[lo + 1] - o;
+    const int k = li - o;
+    const bool has_edge = active && k < n - 1;
+    const bool is_joint = active && k >= 1 && k <= n - 2;
+    const int j = k - 1;
+
+    int cx = 0, cy = 0;
+    float fx = 0.f, fy = 0.f;
+    if (active) {
+      cx = cell[gi]; cy = cell[N + gi];
+      fx = frac[gi]; fy = frac[N + gi];
+    }
+    float v0x = 0.f, v0y = 0.f, L = 0.f, th = 0.f;
+    if (has_edge) {
+      v0x = (float)(cell[gi + 1] - cx) + (frac[gi + 1] - fx);
+      v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
+      L = glb(w.rest_length)[gi];
+      th = atan2f(v0y, v0x);
+    }
+    float th_hat = 0.f;
+    if (is_joint) {
+      const int f = pk.fil_begin + lo;
+      const float amp = glb(w.act_amp)[f];
+      const float ra = glb(w.rest_angle)[gi];
+      if (amp != 0.0f) {
+        const double arg = kTwoPiD * (double)A.t / (double)glb(w.act_period)[f] +
+                           (double)glb(w.act_phase)[f] - kTwoPiD * (double)j / (double)(n - 2);
+        th_hat = (float)((double)ra + (double)amp * sin(arg));
+      } else {
+        th_hat = ra;
+      }
+    }
+    // dL/dx_t so far (written by k_adj_force) plus the deposit derivative
+    float xbx = 0.f, xby = 0.f;
+    if (active) {
+      xbx = A.xbar[gi];
+      xby = A.xbar[N + gi];
+      const int bx = wrap_index(cx, nx), by = wrap_index(cy, ny);
+      float wx[4], dwx[4], wy[4], dwy[4];
+      peskin4_d(fx, wx, dwx);
+      peskin4_d(fy, wy, dwy);
+      const MC_GLOBAL float* sb = glb(A.sbar);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const size_t row = (size_t)wrap_near(by - 1 + b, ny) * nx;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float sv = sb[row + wrap_near(bx - 1 + a, nx)];
+          xbx += dwx[a] * wy[b] * sv;
+          xby += wx[a] * dwy[b] * sv;
+        }
+      }
+    }
+
+    // forward PBD again, keeping the state each position pass starts from
+    const int K = w.pbd_iters;
+    const float hb = 0.5f * w.k_bend;
+    const float hs = 0.5f * w.k_stretch;
+    const float ksh = w.k_shear;
+    float d_pe_x[kMaxAdjIters], d_pe_y[kMaxAdjIters], d_po_x[kMaxAdjIters], d_po_y[kMaxAdjIters];
+    float th_p[kMaxAdjIters];
+    s_th[li] = th;
+    s_dx[li] = 0.f;
+    s_dy[li] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int iter = 0; iter < kMaxAdjIters; ++iter) {
+      if (iter < K) {
+        for (int par = 0; par < 2; ++par) {
+          if (is_joint && (j & 1) == par) {
+            const float t1 = s_th[li - 1];
+            const float t2 = s_th[li];
+            const float c = wrap_angle(t2 - t1) - th_hat;
+            s_th[li - 1] = t1 + hb * c;
+            s_th[li] = t2 - hb * c;
+          }
+          __syncthreads();
+        }
+        th_p[iter] = s_th[li];
+        for (int par = 0; par < 2; ++par) {
+          const float mdx = s_dx[li], mdy = s_dy[li];
+          if (par == 0) {
+            d_pe_x[iter] = mdx;
+            d_pe_y[iter] = mdy;
+          } else {
+            d_po_x[iter] = mdx;
+            d_po_y[iter] = mdy;
+          }
+          __syncthreads();
+          if (has_edge && (k & 1) == par) {
+            const float d0x = s_dx[li], d0y = s_dy[li];
+            const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
+            const float vx = v0x + (d1x - d0x);
+            const float vy = v0y + (d1y - d0y);
+            const float ell = sqrtf(vx * vx + vy * vy);
+            const float sc = (ell - L) / ell;
+            const float csx = sc * vx, csy = sc * vy;
+            float sn, cs;
+            sincosf(th_p[iter], &sn, &cs);
+            const float dx = hs * (csx + ksh * (vx - L * cs - csx));
+            const float dy = hs * (csy + ksh * (vy - L * sn - csy));
+            s_dx[li] = d0x + dx;
+            s_dy[li] = d0y + dy;
+            s_dx[li + 1] = d1x - dx;
+            s_dy[li + 1] = d1y - dy;
+          }
+          __syncthreads();
+        }
+      }
+    }
+
+    // reverse: F_el = k_el d  ->  dL/dd = k_el dL/dF
+    const float kel = w.k_el;
+    s_gx[li] = active ? kel * A.Fbar[gi] : 0.f;
+    s_gy[li] = active ? kel * A.Fbar[N + gi] : 0.f;
+    s_gth[li] = 0.f;
+    float v0bx = 0.f, v0by = 0.f, thhb = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int iter = kMaxAdjIters - 1; iter >= 0; --iter) {
+      if (iter < K) {
+        for (int par = 1; par >= 0; --par) {
+          s_dx[li] = par == 0 ? d_pe_x[iter] : d_po_x[iter];
+          s_dy[li] = par == 0 ? d_pe_y[iter] : d_po_y[iter];
+          __syncthreads();
+          if (has_edge && (k & 1) == par) {
+            const float d0x = s_dx[li], d0y = s_dy[li];
+            const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
+            const float vx = v0x + (d1x - d0x);
+            const float vy = v0y + (d1y - d0y);
+            const float ell = sqrtf(vx * vx + vy * vy);
+            const float hx = vx / ell, hy = vy / ell;
+            const float Dbx = s_gx[li] - s_gx[li + 1];
+            const float Dby = s_gy[li] - s_gy[li + 1];
+            // M = hs [(1 - ksh) (I - (L/ell)(I - h h^T)) + ksh I]
+            const float a = 1.0f - ksh;
+            const float lr = L / ell;
+            const float hd = hx * Dbx + hy * Dby;
+            const float mbx = hs * (Dbx - a * lr * (Dbx - hx * hd));
+            const float mby = hs * (Dby - a * lr * (Dby - hy * hd));
+            s_gx[li] -= mbx;
+            s_gy[li] -= mby;
+            s_gx[li + 1] += mbx;
+            s_gy[li + 1] += mby;
+            v0bx += mbx;
+            v0by += mby;
+            float sn, cs;
+            sincosf(th_p[iter], &sn, &cs);
+            s_gth[li] += -hs * ksh * L * (-sn * Dbx + cs * Dby);
+          }
+          __syncthreads();
+        }
+        for (int par = 1; par >= 0; --par) {
+          if (is_joint && (j & 1) == par) {
+            const float cb = hb * (s_gth[li - 1] - s_gth[li]);
+            s_gth[li - 1] -= cb;
+            s_gth[li] += cb;
+            thhb -= cb;
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // theta_e = atan2(v0): d theta / d v0 = (-v0y, v0x) / |v0|^2
+    if (has_edge) {
+      const float r2 = v0x * v0x + v0y * v0y;
+      const float tb = s_gth[li];
+      v0bx += tb * (-v0y / r2);
+      v0by += tb * (v0x / r2);
+    }
+    __syncthreads();
+    // v0_e = x_{e+1} - x_e
+    s_dx[li] = has_edge ? v0bx : 0.f;
+    s_dy[li] = has_edge ? v0by : 0.f;
+    __syncthreads();
+    if (active) {
+      xbx -= s_dx[li];
+      xby -= s_dy[li];
+      if (k >= 1) {
+        xbx += s_dx[li - 1];
+        xby += s_dy[li - 1];
+      }
+      A.xbar[gi] = xbx;
+      A.xbar[N + gi] = xby;
+      if (is_joint) A.g_rest[gi] += thhb;     // theta_hat = theta_rest + actuation
+    }
+    __syncthreads();
+  }
+}
+
+#define MC_ADJ_PACK(KERNEL, G, ...)                                              \
+  do {                                                                           \
+    if ((G).pack == 256)                                                         \
+      KERNEL<256><<<(G).node_blocks, 256, 0, s>>>(__VA_ARGS__);                  \
+    else                                                                         \
+      KERNEL<1024><<<(G).node_blocks, 1024, 0, s>>>(__VA_ARGS__);                \
+  } while (0)
+
+void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s) {
+  k_adj_spread<<<G.tile_blocks, 256, 0, s>>>(W, T, A.xbar_in, 0.f, A.ubar);
+  k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
+  MC_ADJ_PACK(k_adj_force, G, W, T, A);
+  k_adj_spread<<<G.tile_blocks, 256, 0, s>>>(W, T, A.Fbar, 1.f, A.Gbar);
+  k_adj_filter<<<G.tile_blocks, 256, 0, s>>>(W, T, A);
+  MC_ADJ_PACK(k_adj_pbd, G, W, T, A);
+}
+
+}  // namespace mc

@@ -12,13 +12,32 @@
 
 namespace mc {
 
-constexpr int kTile = 32;            // square grid tile of the filter and fluid kernels
+// Pointers read from the world table carry no address space, so the compiler
+// would access them with flat instructions, whose completion counter is
+// shared with LDS operations.  Kernels cast them to the global address space
+// once per work item.
+#define MC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MC_GLOBAL T* glb(T* p) {
+  return (MC_GLOBAL T*)p;
+}
+// Vector element types for global-address-space access (HIP's float2/int4
+// classes cannot be copied through address-space-qualified references).
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef int vi4 __attribute__((ext_vector_type(4)));
+template <class V, class T>
+__device__ __forceinline__ MC_GLOBAL V* glbv(T* p) {
+  return (MC_GLOBAL V*)p;
+}
+
+constexpr int kTile = 32;            // square grid tile of the filter and spread kernels
+constexpr int kCellsPerItem = 256;   // contiguous cells per fluid work item
 constexpr int kMaxRadius = 8;        // largest Gaussian truncation radius
-constexpr int kMaxBinsPerNode = 9;   // tiles one node's extended support can touch
 
 // Particle -> grid transfer modes (per world).
 enum TransferMode : int {
-  kBinned = 0,   // nodes binned by tile; sums formed in LDS, tiles written whole
+  kBinned = 0,   // nodes binned by home tile; sums formed in LDS, tiles written whole
   kSorted = 1,   // counting sort by home cell; fixed-order segmented sums
   kDirect = 2    // global float atomics into HBM accumulators
 };
@@ -46,10 +65,10 @@ struct WorldDev {
   const float* rest_angle; const float* rest_length;
   const float* act_amp; const float* act_period; const float* act_phase;
   const float* f_src;  float* f_dst;    // shifted populations f - w, [9][ny][nx]
-  float* u;                             // [2][ny][nx]
+  float2* u;                            // [ny][nx] fluid velocity (x, y interleaved)
   float* s;                             // deposit accumulator [ny][nx] (direct mode)
-  float* st;                            // filtered density [ny][nx]
-  float* Fg;                            // grid force accumulator [2][ny][nx] (direct mode)
+  float2* grad;                         // [ny][nx] central difference of the filtered density
+  float2* Fg;                           // [ny][nx] grid force
   float* fel;                           // node force [2][N] (elastic, then total)
   const Ctl* ctl_src; Ctl* ctl_dst;
   unsigned* flags;                      // sticky: bit 0 = NaN or |u| > u_max
@@ -61,11 +80,11 @@ struct WorldDev {
   int* perm;                            // [N] node index of each sorted slot
   float4* rec;                          // [N] sorted records (frac x, frac y, Fx, Fy)
   int* part;                            // scan partials
-  // tile bins (binned mode): node indices grouped by the tiles they affect
-  int* bin_cnt;                         // [ntx*nty] entries per tile (zeroed after use)
+  // tile bins (binned mode): one record per node, grouped by home tile
+  int* bin_cnt;                         // [ntx*nty] nodes per tile (zeroed after use)
   int* bin_fill;                        // [ntx*nty] fill cursors (zeroed after use)
   int* bin_start;                       // [ntx*nty + 1] exclusive prefix of bin_cnt
-  int* bin_idx;                         // [9N] node index per entry
+  int4* bin_rec;                        // [N] record: (x | y << 16 home cell, frac x, frac y, node)
 };
 
 // A node pack: whole filaments with at most `pack` nodes, run by one block.
@@ -77,15 +96,34 @@ struct Pack {
 struct Tables {
   const Pack* packs;  const int* n_packs;
   const int2* tiles;  const int* n_tiles;    // (world, tile index), 32x32 cells
+  const int2* items;  const int* n_items;    // (world, first cell) of 256 contiguous cells
   const int2* scan;   const int* n_scan;     // (world, block) for the cell scan (sorted mode)
   const int2* worlds; const int* n_worlds;   // (world, 0) for per-world kernels
 };
 
 struct Grid {
-  int node_blocks, tile_blocks, scan_blocks, world_blocks;
+  int node_blocks, tile_blocks, scan_blocks, world_blocks, item_blocks;
   int pack;                                  // node pack capacity: 256 or 1024
   int any_sorted, any_binned, pad;
 };
+
+// Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at
+// t+1); the kernels produce dL/d(state at t).
+struct AdjDev {
+  long long t;            // time index of the step being reversed
+  const float* xbar_in;   // [2][N]
+  float* xbar;            // [2][N]
+  const float* gbar_in;   // [9][ny][nx]
+  float* gbar;            // [9][ny][nx]
+  float2* ubar;           // [ny][nx]
+  float2* Fgbar;          // [ny][nx]
+  float2* Gbar;           // [ny][nx]
+  float* sbar;            // [ny][nx]
+  float* Fbar;            // [2][N]
+  float* g_rest;          // [N] accumulated dL/d(rest angle)
+};
+
+void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s);
 
 // Forward step launchers (kernels.hip).  `W` points at a device array of
 // world descriptors.
@@ -93,6 +131,7 @@ void launch_elastic(const WorldDev* W, const Tables& T, const Grid& G, hipStream
 void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s);

@@ -58,7 +58,8 @@ struct Carver {
 sim_status check_params(const sim_params* p) {
   if (!p) return fail(SIM_E_INVALID, "params is NULL");
   if (p->nx < 8 || p->ny < 8) return fail(SIM_E_INVALID, "grid must be at least 8x8 (got %dx%d)", p->nx, p->ny);
-  if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) return fail(SIM_E_INVALID, "grid too large");
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 30 || p->nx > 32768 || p->ny > 32768)
+    return fail(SIM_E_INVALID, "grid too large (at most 2^30 cells and 32768 per side)");
   if (!(p->tau > 0.5f)) return fail(SIM_E_INVALID, "tau must exceed 1/2");
   if (!(p->trt_magic > 0.f)) return fail(SIM_E_INVALID, "trt_magic must be positive");
   if (p->pbd_iters < 0 || p->pbd_iters > 1000) return fail(SIM_E_INVALID, "pbd_iters out of range");
@@ -75,8 +76,8 @@ sim_status check_params(const sim_params* p) {
 struct WorldBufs {
   float* f_alt = nullptr;
   float* s = nullptr;
-  float* st = nullptr;
-  float* Fg = nullptr;
+  float2* grad = nullptr;
+  float2* Fg = nullptr;
   float* fel = nullptr;
   int* key = nullptr;
   int* rank = nullptr;
@@ -88,7 +89,7 @@ struct WorldBufs {
   int* bin_cnt = nullptr;
   int* bin_fill = nullptr;
   int* bin_start = nullptr;
-  int* bin_idx = nullptr;
+  int4* bin_rec = nullptr;
 };
 
 inline int mode_of(const sim_params& p) {
@@ -101,7 +102,8 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
   const size_t ncell = (size_t)p.nx * p.ny;
   const size_t N = std::max(n_part, 1);
   b.f_alt = c.take<float>(9 * ncell);
-  b.st = c.take<float>(ncell);
+  b.grad = c.take<float2>(ncell);
+  b.Fg = c.take<float2>(ncell);
   b.fel = c.take<float>(2 * N);
   const int mode = mode_of(p);
   if (mode == mc::kSorted) {
@@ -114,13 +116,12 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.part = c.take<int>((ncell + 1023) / 1024 + 1);
   } else if (mode == mc::kDirect) {
     b.s = c.take<float>(ncell);
-    b.Fg = c.take<float>(2 * ncell);
   } else {
     const size_t nt = (size_t)tiles_x(p) * tiles_y(p);
     b.bin_cnt = c.take<int>(nt);
     b.bin_fill = c.take<int>(nt);
     b.bin_start = c.take<int>(nt + 1);
-    b.bin_idx = c.take<int>((size_t)mc::kMaxBinsPerNode * N);
+    b.bin_rec = c.take<int4>(N);
   }
 }
 
@@ -162,9 +163,10 @@ struct Engine {
   int* counts = nullptr;
   mc::Pack* packs = nullptr;
   int2* tiles = nullptr;
+  int2* items = nullptr;
   int2* scan = nullptr;
   int2* wlist = nullptr;
-  size_t max_packs = 0, max_tiles = 0, max_scan = 0;
+  size_t max_packs = 0, max_tiles = 0, max_items = 0, max_scan = 0;
   mc::Tables tab{};
   mc::Grid grid{};
   bool fixed_grid = false;
@@ -180,9 +182,9 @@ struct Engine {
   int want_chunk = 20;
   hipGraphExec_t g_pair = nullptr;
 
-  size_t n_packs = 0, n_tiles = 0, n_scan = 0, n_worlds = 0;
+  size_t n_packs = 0, n_tiles = 0, n_items = 0, n_scan = 0, n_worlds = 0;
 
-  static size_t table_bytes(int max_worlds, size_t mp, size_t mt, size_t ms) {
+  static size_t table_bytes(int max_worlds, size_t mp, size_t mt, size_t mi, size_t ms) {
     Carver c{nullptr};
     c.take<mc::WorldDev>(max_worlds);
     c.take<mc::WorldDev>(max_worlds);
@@ -192,6 +194,7 @@ struct Engine {
     c.take<int>(8);
     c.take<mc::Pack>(mp);
     c.take<int2>(mt);
+    c.take<int2>(mi);
     c.take<int2>(ms);
     c.take<int2>(max_worlds);
     return c.off;
@@ -206,6 +209,7 @@ struct Engine {
     counts = c.take<int>(8);
     packs = c.take<mc::Pack>(max_packs);
     tiles = c.take<int2>(max_tiles);
+    items = c.take<int2>(max_items);
     scan = c.take<int2>(max_scan);
     wlist = c.take<int2>(max_worlds);
     tab.packs = packs;
@@ -216,6 +220,8 @@ struct Engine {
     tab.n_scan = counts + 2;
     tab.worlds = wlist;
     tab.n_worlds = counts + 3;
+    tab.items = items;
+    tab.n_items = counts + 4;
   }
 
   ~Engine() {
@@ -278,9 +284,9 @@ struct Engine {
     const int src = parity == 0 ? s.cur : 1 - s.cur;
     d.f_src = s.fbuf[src];
     d.f_dst = s.fbuf[1 - src];
-    d.u = s.u;
+    d.u = (float2*)s.u;
     d.s = s.b.s;
-    d.st = s.b.st;
+    d.grad = s.b.grad;
     d.Fg = s.b.Fg;
     d.fel = s.b.fel;
     d.ctl_src = ctl[parity] + w;
@@ -296,14 +302,14 @@ struct Engine {
     d.bin_cnt = s.b.bin_cnt;
     d.bin_fill = s.b.bin_fill;
     d.bin_start = s.b.bin_start;
-    d.bin_idx = s.b.bin_idx;
+    d.bin_rec = s.b.bin_rec;
     return d;
   }
 
   // Rebuild work tables and descriptors from the slot list and upload them.
   sim_status rebuild() {
     std::vector<mc::Pack> pk;
-    std::vector<int2> tl, sc, wl;
+    std::vector<int2> tl, sc, wl, it;
     any_sorted = false;
     bool any_binned = false;
     for (int w = 0; w < (int)slots.size(); ++w) {
@@ -325,6 +331,7 @@ struct Engine {
       }
       const int ncell = s.p.nx * s.p.ny;
       for (int t = 0; t < tiles_x(s.p) * tiles_y(s.p); ++t) tl.push_back(make_int2(w, t));
+      for (int c = 0; c < ncell; c += mc::kCellsPerItem) it.push_back(make_int2(w, c));
       wl.push_back(make_int2(w, 0));
       const int mode = mode_of(s.p);
       if (mode == mc::kSorted) {
@@ -334,13 +341,15 @@ struct Engine {
       }
       if (mode == mc::kBinned) any_binned = true;
     }
-    if (pk.size() > max_packs || tl.size() > max_tiles || sc.size() > max_scan)
+    if (pk.size() > max_packs || tl.size() > max_tiles || it.size() > max_items || sc.size() > max_scan)
       return fail(SIM_E_WORKSPACE, "work tables exceed their capacity");
     n_packs = pk.size();
     n_tiles = tl.size();
     n_scan = sc.size();
     n_worlds = wl.size();
+    n_items = it.size();
     if (!fixed_grid) {
+      grid.item_blocks = (int)std::max<size_t>(1, n_items);
       grid.node_blocks = (int)std::max<size_t>(1, n_packs);
       grid.tile_blocks = (int)std::max<size_t>(1, n_tiles);
       grid.scan_blocks = (int)std::max<size_t>(1, n_scan);
@@ -354,7 +363,7 @@ struct Engine {
     // stage into pinned memory once the previous upload has been consumed
     HIPCHK(hipEventSynchronize(upload_done));
     const size_t need = 2 * max_worlds * sizeof(mc::WorldDev) + 8 * sizeof(int) + pk.size() * sizeof(mc::Pack) +
-                        (tl.size() + sc.size() + wl.size()) * sizeof(int2);
+                        (tl.size() + sc.size() + wl.size() + it.size()) * sizeof(int2);
     if (need > pinned_bytes) {
       if (pinned) HIPCHK(hipHostFree(pinned));
       pinned_bytes = need * 2;
@@ -378,22 +387,25 @@ struct Engine {
     sim_status st;
     if ((st = put(desc[0], d0.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
     if ((st = put(desc[1], d1.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
-    int cnt[8] = {(int)n_packs, (int)n_tiles, (int)n_scan, (int)n_worlds, 0, 0, 0, 0};
+    int cnt[8] = {(int)n_packs, (int)n_tiles, (int)n_scan, (int)n_worlds, (int)n_items, 0, 0, 0};
     if ((st = put(counts, cnt, sizeof(cnt)))) return st;
     if ((st = put(packs, pk.data(), pk.size() * sizeof(mc::Pack)))) return st;
     if ((st = put(tiles, tl.data(), tl.size() * sizeof(int2)))) return st;
     if ((st = put(scan, sc.data(), sc.size() * sizeof(int2)))) return st;
     if ((st = put(wlist, wl.data(), wl.size() * sizeof(int2)))) return st;
+    if ((st = put(items, it.data(), it.size() * sizeof(int2)))) return st;
     HIPCHK(hipEventRecord(upload_done, stream));
     return SIM_OK;
   }
 
-  void enqueue_step(int parity, hipStream_t s) const {
-    const mc::WorldDev* d = desc[parity];
+  void enqueue_step(int parity, hipStream_t s) const { enqueue_step_with(desc[parity], grid, s); }
+
+  void enqueue_step_with(const mc::WorldDev* d, const mc::Grid& grid, hipStream_t s) const {
     mc::launch_elastic(d, tab, grid, s);
     mc::launch_sort(d, tab, grid, s);
     mc::launch_filter(d, tab, grid, s);
     mc::launch_repulse(d, tab, grid, s);
+    mc::launch_spread(d, tab, grid, s);
     mc::launch_lbm(d, tab, grid, s);
     mc::launch_integrate(d, tab, grid, s);
   }
@@ -477,8 +489,9 @@ namespace {
 size_t world_table_bytes(const sim_params& p, int n_fil) {
   const size_t ncell = (size_t)p.nx * p.ny;
   const size_t tiles = (size_t)tiles_x(p) * tiles_y(p);
+  const size_t items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
   const size_t scans = (ncell + 1023) / 1024;
-  return Engine::table_bytes(1, std::max(n_fil, 1), tiles, scans);
+  return Engine::table_bytes(1, std::max(n_fil, 1), tiles, items, scans);
 }
 
 size_t world_buf_bytes(const sim_params& p, int n_part) {
@@ -577,6 +590,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   const size_t ncell = (size_t)p->nx * p->ny;
   e.max_packs = std::max(a->n_filaments, 1);
   e.max_tiles = (size_t)tiles_x(*p) * tiles_y(*p);
+  e.max_items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
   e.max_scan = (ncell + 1023) / 1024;
   e.grid.pack = max_len <= 256 ? 256 : 1024;
   Carver c{(char*)workspace};
@@ -718,7 +732,10 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
       mc::launch_sort(d, e.tab, e.grid, e.stream);
       break;
     case 1: mc::launch_filter(d, e.tab, e.grid, e.stream); break;
-    case 2: mc::launch_repulse(d, e.tab, e.grid, e.stream); break;
+    case 2:
+      mc::launch_repulse(d, e.tab, e.grid, e.stream);
+      mc::launch_spread(d, e.tab, e.grid, e.stream);
+      break;
     case 3: {
       mc::launch_lbm(d, e.tab, e.grid, e.stream);
       Slot& s = e.slots[0];
@@ -754,6 +771,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     mc::launch_filter(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[3], e.stream));
     mc::launch_repulse(d, e.tab, e.grid, e.stream);
+    mc::launch_spread(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[4], e.stream));
     mc::launch_lbm(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[5], e.stream));
@@ -785,11 +803,203 @@ sim_status sim_debug_buffer(sim_world* w, int32_t which, void** ptr) {
   const Slot& s = w->eng.slots[0];
   switch (which) {
     case 0: *ptr = s.b.s; break;
-    case 1: *ptr = s.b.st; break;
+    case 1: *ptr = s.b.grad; break;
     case 2: *ptr = s.b.Fg; break;
     case 3: *ptr = s.b.fel; break;
     default: return fail(SIM_E_INVALID, "unknown buffer %d", which);
   }
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Reverse mode (sim_backward)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Layout of the backward workspace for segments of up to m steps.
+struct AdjLayout {
+  int m = 0;
+  size_t N = 0, ncell = 0, nt = 0;
+  int* cell[2] = {};           // unused placeholders for alignment bookkeeping
+  size_t bytes = 0;
+  // per tape slot
+  std::vector<int*> x_cell;    // m+1 slots of [2][N]
+  std::vector<float*> x_frac;  // m+1 slots of [2][N]
+  std::vector<float*> g;       // m+1 slots of [9][ncell]
+  std::vector<float2*> grad, Fg, u;   // m slots of [ncell]
+  std::vector<float*> F;       // m slots of [2][N]
+  std::vector<int*> bstart;    // m slots of [nt+1]
+  std::vector<int4*> brec;     // m slots of [N]
+  int* bin_cnt = nullptr;
+  int* bin_fill = nullptr;
+  mc::WorldDev* desc = nullptr;      // m descriptors
+  float* xbar[2] = {};
+  float* gbar[2] = {};
+  float2* ubar = nullptr;
+  float2* Fgbar = nullptr;
+  float2* Gbar = nullptr;
+  float* sbar = nullptr;
+  float* Fbar = nullptr;
+};
+
+void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) {
+  L.m = m;
+  L.N = std::max(n_part, 1);
+  L.ncell = (size_t)p.nx * p.ny;
+  L.nt = (size_t)tiles_x(p) * tiles_y(p);
+  L.x_cell.resize(m + 1);
+  L.x_frac.resize(m + 1);
+  L.g.resize(m + 1);
+  for (int j = 0; j <= m; ++j) {
+    L.x_cell[j] = c.take<int>(2 * L.N);
+    L.x_frac[j] = c.take<float>(2 * L.N);
+    L.g[j] = c.take<float>(9 * L.ncell);
+  }
+  L.grad.resize(m);
+  L.Fg.resize(m);
+  L.u.resize(m);
+  L.F.resize(m);
+  L.bstart.resize(m);
+  L.brec.resize(m);
+  for (int j = 0; j < m; ++j) {
+    L.grad[j] = c.take<float2>(L.ncell);
+    L.Fg[j] = c.take<float2>(L.ncell);
+    L.u[j] = c.take<float2>(L.ncell);
+    L.F[j] = c.take<float>(2 * L.N);
+    L.bstart[j] = c.take<int>(L.nt + 1);
+    L.brec[j] = c.take<int4>(L.N);
+  }
+  L.bin_cnt = c.take<int>(L.nt);
+  L.bin_fill = c.take<int>(L.nt);
+  L.desc = c.take<mc::WorldDev>(m);
+  for (int k = 0; k < 2; ++k) {
+    L.xbar[k] = c.take<float>(2 * L.N);
+    L.gbar[k] = c.take<float>(9 * L.ncell);
+  }
+  L.ubar = c.take<float2>(L.ncell);
+  L.Fgbar = c.take<float2>(L.ncell);
+  L.Gbar = c.take<float2>(L.ncell);
+  L.sbar = c.take<float>(L.ncell);
+  L.Fbar = c.take<float>(2 * L.N);
+  L.bytes = c.off;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_backward_workspace_size(const sim_world* w, int32_t ckpt_every, size_t* bytes) {
+  if (!w || !bytes) return fail(SIM_E_INVALID, "NULL argument");
+  if (ckpt_every < 1) return fail(SIM_E_INVALID, "ckpt_every must be >= 1");
+  const Slot& s = w->eng.slots[0];
+  Carver c{nullptr};
+  AdjLayout L;
+  carve_adj(c, s.p, s.n_part, ckpt_every, L);
+  *bytes = L.bytes;
+  return SIM_OK;
+}
+
+sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_every, const void* ckpt,
+                        const float* g_pos, float* g_rest_angle, float* g_pos0, void* adj_ws, size_t adj_ws_bytes) {
+  if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  if (n_steps < 1 || ckpt_every < 1) return fail(SIM_E_INVALID, "need n_steps >= 1 and ckpt_every >= 1");
+  if (!ckpt || !g_pos || !g_rest_angle || !adj_ws) return fail(SIM_E_INVALID, "NULL buffer");
+  if ((uintptr_t)adj_ws % kAlign) return fail(SIM_E_WORKSPACE, "adjoint workspace must be 256-byte aligned");
+  Engine& e = w->eng;
+  Slot& s = e.slots[0];
+  if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
+  size_t need = 0;
+  sim_backward_workspace_size(w, ckpt_every, &need);
+  if (adj_ws_bytes < need) return fail(SIM_E_WORKSPACE, "adjoint workspace has %zu bytes, needs %zu", adj_ws_bytes, need);
+  Carver c{(char*)adj_ws};
+  AdjLayout L;
+  carve_adj(c, s.p, s.n_part, ckpt_every, L);
+  const size_t N = s.n_part, ncell = L.ncell;
+  const size_t per_ck = align_up(4 * N * 4) + align_up(9 * ncell * 4);
+  const int nseg = (n_steps + ckpt_every - 1) / ckpt_every;
+  hipStream_t st = e.stream;
+  mc::Grid g = e.grid;
+  g.any_binned = 1;
+  g.any_sorted = 0;
+
+  // per-step descriptors (identical for every segment; uploaded once)
+  std::vector<mc::WorldDev> hd(L.m);
+  for (int j = 0; j < L.m; ++j) {
+    mc::WorldDev d = e.make_desc(0, 0);
+    d.mode = mc::kBinned;
+    d.cell_in = L.x_cell[j];
+    d.frac_in = L.x_frac[j];
+    d.cell_out = L.x_cell[j + 1];
+    d.frac_out = L.x_frac[j + 1];
+    d.f_src = L.g[j];
+    d.f_dst = L.g[j + 1];
+    d.grad = L.grad[j];
+    d.Fg = L.Fg[j];
+    d.u = L.u[j];
+    d.fel = L.F[j];
+    d.bin_cnt = L.bin_cnt;
+    d.bin_fill = L.bin_fill;
+    d.bin_start = L.bstart[j];
+    d.bin_rec = L.brec[j];
+    d.s = nullptr;
+    hd[j] = d;
+  }
+  HIPCHK(hipEventSynchronize(e.upload_done));
+  const size_t dbytes = hd.size() * sizeof(mc::WorldDev);
+  if (dbytes > e.pinned_bytes) {
+    HIPCHK(hipHostFree(e.pinned));
+    e.pinned_bytes = dbytes * 2;
+    HIPCHK(hipHostMalloc((void**)&e.pinned, e.pinned_bytes, hipHostMallocDefault));
+  }
+  std::memcpy(e.pinned, hd.data(), dbytes);
+  HIPCHK(hipMemcpyAsync(L.desc, e.pinned, dbytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(e.upload_done, st));
+  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, st, L.bin_cnt, L.nt);
+  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, st, L.bin_fill, L.nt);
+  // dL/dx_T and dL/dg_T = 0
+  int cur = 0;
+  if (N) HIPCHK(hipMemcpyAsync(L.xbar[0], g_pos, 2 * N * 4, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, st, (int*)L.gbar[0], 9 * ncell);
+  HIPCHK(hipGetLastError());
+
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int k0 = seg * ckpt_every;
+    const int m = std::min(ckpt_every, n_steps - k0);
+    const char* ck = (const char*)ckpt + seg * per_ck;
+    if (N) {
+      HIPCHK(hipMemcpyAsync(L.x_cell[0], ck, 2 * N * 4, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(L.x_frac[0], ck + 2 * N * 4, 2 * N * 4, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(L.g[0], ck + align_up(4 * N * 4), 9 * ncell * 4, hipMemcpyDeviceToDevice, st));
+    // recompute the segment forward, writing every step's fields to the tape
+    for (int j = 0; j < m; ++j) {
+      sim_status r = e.set_ctl(0, t0 + k0 + j, 1);
+      if (r) return r;
+      e.enqueue_step_with(L.desc + j, g, st);
+    }
+    HIPCHK(hipGetLastError());
+    // reverse the segment step by step
+    for (int j = m - 1; j >= 0; --j) {
+      mc::AdjDev A{};
+      A.t = t0 + k0 + j;
+      A.xbar_in = L.xbar[cur];
+      A.xbar = L.xbar[1 - cur];
+      A.gbar_in = L.gbar[cur];
+      A.gbar = L.gbar[1 - cur];
+      A.ubar = L.ubar;
+      A.Fgbar = L.Fgbar;
+      A.Gbar = L.Gbar;
+      A.sbar = L.sbar;
+      A.Fbar = L.Fbar;
+      A.g_rest = g_rest_angle;
+      mc::launch_adjoint_step(L.desc + j, e.tab, g, A, st);
+      cur = 1 - cur;
+    }
+    HIPCHK(hipGetLastError());
+  }
+  if (g_pos0 && N) HIPCHK(hipMemcpyAsync(g_pos0, L.xbar[cur], 2 * N * 4, hipMemcpyDeviceToDevice, st));
   return SIM_OK;
 }
 
@@ -887,9 +1097,10 @@ sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, v
   const size_t max_nodes = pool_bytes / 36 + 1;
   // a world of c cells has at most c/1024 + nx/32 + ny/32 + 1 <= c/64 + 1 tiles
   e.max_tiles = max_cells / 64 + max_worlds;
+  e.max_items = max_cells / mc::kCellsPerItem + max_worlds;
   e.max_scan = max_cells / 1024 + max_worlds;
   e.max_packs = 2 * (max_nodes / 256) + 2 * (size_t)max_worlds;
-  b->table_bytes = Engine::table_bytes(max_worlds, e.max_packs, e.max_tiles, e.max_scan);
+  b->table_bytes = Engine::table_bytes(max_worlds, e.max_packs, e.max_tiles, e.max_items, e.max_scan);
   if (b->table_bytes >= pool_bytes / 2) {
     delete b;
     return fail(SIM_E_WORKSPACE, "pool too small for %d worlds", max_worlds);
@@ -906,6 +1117,7 @@ sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, v
   e.grid.tile_blocks = 2048;
   e.grid.scan_blocks = 1024;
   e.grid.world_blocks = 256;
+  e.grid.item_blocks = 4096;
   e.want_chunk = 20;
   sim_status st = e.init_host(1 << 20);
   if (st) {
@@ -933,7 +1145,8 @@ sim_status sim_batch_set_tuning(sim_batch* b, int32_t chunk_steps, int32_t cell_
     return fail(SIM_E_INVALID, "chunk_steps must be even and >= 2; block counts >= 1");
   Engine& e = b->eng;
   e.want_chunk = chunk_steps;
-  e.grid.tile_blocks = cell_blocks;
+  e.grid.tile_blocks = std::max(1, cell_blocks / 4);
+  e.grid.item_blocks = cell_blocks;
   e.grid.node_blocks = node_blocks;
   e.grid.scan_blocks = std::max(1, cell_blocks / 2);
   e.drop_graphs();

@@ -166,7 +166,7 @@ class DeviceState:
         self.act_period = t(w.act_period, torch.float32)
         self.act_phase = t(w.act_phase, torch.float32)
         self.f = torch.zeros(9, self.ny, self.nx, device=dev, dtype=torch.float32)   # fluid at rest
-        self.u = torch.zeros(2, self.ny, self.nx, device=dev, dtype=torch.float32)
+        self.u = torch.zeros(self.ny, self.nx, 2, device=dev, dtype=torch.float32)
 
     def arrays(self) -> SimArrays:
         return SimArrays(self.n_fil, self.n_part, _ptr(self.fil_offset), _ptr(self.cell), _ptr(self.frac),
@@ -175,6 +175,10 @@ class DeviceState:
 
     def positions64(self) -> np.ndarray:
         return self.cell.cpu().numpy().astype(np.float64) + self.frac.cpu().numpy().astype(np.float64)
+
+    def velocity64(self) -> np.ndarray:
+        """u as float64 [2, ny, nx] (the library stores it interleaved)."""
+        return self.u.permute(2, 0, 1).cpu().numpy().astype(np.float64)
 
     def populations64(self) -> np.ndarray:
         return self.f.cpu().numpy().astype(np.float64) + LATTICE_WEIGHTS.reshape(9, 1, 1)
@@ -250,3 +254,58 @@ class World:
             self.close()
         except Exception:
             pass
+
+
+def _world_backward(self, t0: int, n: int, ckpt_every: int, ckpt: torch.Tensor, g_pos: torch.Tensor,
+                    g_rest: torch.Tensor, g_pos0: Optional[torch.Tensor] = None):
+    """dL/d(rest angle) (accumulated into g_rest) and optionally dL/dx_t0 (into
+    g_pos0) of a rollout recorded with checkpoints, given g_pos = dL/dx_T."""
+    L = lib()
+    nb = ctypes.c_size_t()
+    check(L.sim_backward_workspace_size(self.handle, int(ckpt_every), ctypes.byref(nb)))
+    ws = getattr(self, "_adj_ws", None)
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.workspace.device)
+        self._adj_ws = ws
+    assert g_pos.dtype == torch.float32 and g_pos.is_contiguous() and g_pos.numel() == 2 * self.state.n_part
+    assert g_rest.dtype == torch.float32 and g_rest.is_contiguous() and g_rest.numel() == self.state.n_part
+    check(L.sim_backward(self.handle, int(t0), int(n), int(ckpt_every), _ptr(ckpt), _ptr(g_pos), _ptr(g_rest),
+                         _ptr(g_pos0), _ptr(ws), ws.numel()))
+
+
+def _positions(self) -> torch.Tensor:
+    """Node positions as a float64 device tensor [2, N] (cell + frac)."""
+    return self.state.cell.double() + self.state.frac.double()
+
+
+World.backward = _world_backward
+World.positions = _positions
+
+
+class Rollout(torch.autograd.Function):
+    """x_T = rollout(rest_angle) on the GPU, differentiable in the rest angles.
+
+    Forward: copies rest_angle into the world, runs n_steps with checkpoints
+    every ckpt_every steps and returns the final positions (float64 [2, N]).
+    Backward: sim_backward recomputes each segment from its checkpoint and runs
+    the hand-written adjoint kernels, returning dL/d(rest_angle).
+    """
+
+    @staticmethod
+    def forward(ctx, rest_angle, world, t0, n_steps, ckpt_every):
+        with torch.no_grad():
+            world.state.rest_angle.copy_(rest_angle.detach().to(torch.float32))
+        ckpt = torch.empty(world.checkpoint_bytes(n_steps, ckpt_every), dtype=torch.uint8,
+                           device=world.workspace.device)
+        world.rollout(t0, n_steps, ckpt_every, ckpt)
+        ctx.world, ctx.ckpt, ctx.args = world, ckpt, (t0, n_steps, ckpt_every)
+        ctx.dtype = rest_angle.dtype
+        return world.positions()
+
+    @staticmethod
+    def backward(ctx, g_x):
+        t0, n, k = ctx.args
+        g_pos = g_x.detach().to(torch.float32).contiguous()
+        g_rest = torch.zeros(ctx.world.state.n_part, dtype=torch.float32, device=g_pos.device)
+        ctx.world.backward(t0, n, k, ctx.ckpt, g_pos, g_rest)
+        return g_rest.to(ctx.dtype), None, None, None, None

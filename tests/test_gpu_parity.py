@@ -86,17 +86,17 @@ def test_substeps_match_oracle(mode):
         s = W.buffer(0, (ny, nx)).cpu().numpy()
         assert rel(s, tr["s"].numpy()) < 1e-6
     W.substep(1, t)
-    st = W.buffer(1, (ny, nx)).cpu().numpy()
-    assert rel(st, tr["st"].numpy()) < 1e-6
+    G = W.buffer(1, (ny, nx, 2)).permute(2, 0, 1).cpu().numpy()
+    Gref = O.central_difference(tr["st"]).numpy()
+    assert rel(G, Gref) < 1e-5
     W.substep(2, t)
     F = W.buffer(3, (2, N)).cpu().numpy()
     assert rel(F, tr["force"].numpy()) < 2e-5
-    if mode == "direct":
-        Fg = W.buffer(2, (2, ny, nx)).cpu().numpy()
-        assert rel(Fg, tr["Fg"].numpy()) < 2e-5
+    Fg = W.buffer(2, (ny, nx, 2)).permute(2, 0, 1).cpu().numpy()
+    assert rel(Fg, tr["Fg"].numpy()) < 2e-5
     W.substep(3, t)
     torch.cuda.synchronize()
-    u = W.state.u.cpu().numpy()
+    u = W.state.velocity64()
     e_u = rel(u, tr["u"].numpy())
     assert e_u < TOL_U, e_u
     fref = O.lbm_stream(tr["fstar"]).numpy()
@@ -120,7 +120,7 @@ def _rollout_compare(sim, w, n, mode, **kw):
         x, f, u = O.step(x, f, t, inp, op)
         torch.cuda.synchronize()
         ex = rel(W.state.positions64(), x.numpy())
-        eu = rel(W.state.u.cpu().numpy(), u.numpy())
+        eu = rel(W.state.velocity64(), u.numpy())
         ex_max, eu_max = max(ex_max, ex), max(eu_max, eu)
         assert ex <= TOL_X, (t, ex)
         assert eu <= TOL_U, (t, eu)
@@ -248,6 +248,21 @@ def test_scaling_workload_full_size(mode):
         for t in range(2):
             x, f, u = O.step(x, f, t, inp, op)
     ex = rel(W.state.positions64(), x.numpy())
-    eu = rel(W.state.u.cpu().numpy(), u.numpy())
+    eu = rel(W.state.velocity64(), u.numpy())
     print(f"scaling 1M nodes 2048^2 [{mode}]: e_x={ex:.2e} e_u={eu:.2e}")
     assert ex <= TOL_X and eu <= TOL_U
+
+
+def test_binned_transfer_is_bitwise_reproducible():
+    # the binned transfer sums in 64-bit fixed point, so the order in which
+    # nodes land in their bins cannot change any result
+    sim = _sim()
+    w = wl.uniform_population(1, n_fil=300, length=40, nx=192, ny=160)
+    out = []
+    for _ in range(2):
+        W, _ = _mk(sim, w, "binned")
+        W.rollout(0, 40)
+        torch.cuda.synchronize()
+        out.append((W.state.cell.cpu(), W.state.frac.cpu(), W.state.f.cpu(), W.state.u.cpu()))
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
