@@ -84,10 +84,26 @@ static __device__ __forceinline__ int tiles_covering(int lo, int hi, int n, int 
 // 64-bit fixed-point accumulation in LDS (2^-36 resolution, range +-2^27).
 constexpr float kFixScale = 68719476736.0f;           // 2^36
 constexpr float kFixInv = 1.4551915228366852e-11f;    // 2^-36
-static __device__ __forceinline__ void lds_fix_add(long long* p, float v) {
-  atomicAdd((unsigned long long*)p, (unsigned long long)__float2ll_rn(v * kFixScale));
+// Nearest 64-bit integer to a float x with |x| < 2^62, from 32-bit
+// conversions: |x| = hi 2^32 + lo, where hi = floor(|x| / 2^32) and
+// lo = |x| - hi 2^32 in [0, 2^32) are both exact in FP32 (|x| has 24
+// significant bits, and so do its bits below 2^32), and lo only has a
+// fraction when it is below 2^24.
+static __device__ __forceinline__ long long f32_to_fix(float x) {
+  const float ax = fabsf(x);
+  const float hf = floorf(ax * 2.3283064365386963e-10f);
+  const float lof = fmaf(hf, -4294967296.0f, ax);
+  const long long m = (long long)(((unsigned long long)(unsigned)hf << 32) + (unsigned long long)__float2uint_rn(lof));
+  return x < 0.0f ? -m : m;
 }
-static __device__ __forceinline__ float fix_to_float(long long v) { return (float)v * kFixInv; }
+static __device__ __forceinline__ void lds_fix_add(long long* p, float v) {
+  atomicAdd((unsigned long long*)p, (unsigned long long)f32_to_fix(v * kFixScale));
+}
+static __device__ __forceinline__ float fix_to_float(long long v) {
+  const int hi = (int)(v >> 32);
+  const unsigned lo = (unsigned)v;
+  return (float)((double)hi * 4294967296.0 + (double)lo) * kFixInv;
+}
 
 // Wavefront-aggregated atomic increment: lanes that target the same counter
 // are served by one atomic from a leader lane.  Returns, for lanes with `has`,
@@ -157,8 +173,8 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
       const int e1 = bstart[tile + 1];
       for (int e = bstart[tile] + threadIdx.x; e < e1; e += blockDim.x) {
         const vi4 r = recs[e];
-        const int dx = wrap_index((r.x & 0xffff) - 1 - x0, nx);
-        const int dy = wrap_index((r.x >> 16) - 1 - y0, ny);
+        const int dx = wrap_near((r.x & 0xffff) - 1 - x0, nx);   // home in [0,n), x0 in [0,n)
+        const int dy = wrap_near((r.x >> 16) - 1 - y0, ny);
         if ((dx >= tw && dx + 3 < nx) || (dy >= th && dy + 3 < ny)) continue;   // misses the tile
         float wx[4], wy[4];
         peskin4(__int_as_float(r.y), wx);

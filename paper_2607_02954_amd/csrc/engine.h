@@ -104,7 +104,8 @@ struct Tables {
 struct Grid {
   int node_blocks, tile_blocks, scan_blocks, world_blocks, item_blocks;
   int pack;                                  // node pack capacity: 256 or 1024
-  int any_sorted, any_binned, pad;
+  int any_sorted, any_binned, any_node;      // which transfer families the table holds
+                                             // (any_node: a world not in binned mode)
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at

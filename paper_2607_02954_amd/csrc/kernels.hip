@@ -417,6 +417,7 @@ constexpr int kRegion = kRing + 2 * kMaxRadius;     // largest density region si
 
 __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, Tables T) {
   __shared__ long long s_reg[kRegion * kRegion];   // density, 64-bit fixed point
+  __shared__ float s_regf[kRegion * kRegion];      // the same, as float
   __shared__ float s_mid[kRegion * kRing];
   __shared__ float s_st[kRing * kRing];
   __shared__ float s_tap[kMaxRadius + 1];
@@ -449,8 +450,10 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
           const int e1 = bstart[tile + 1];
           for (int e = bstart[tile] + tid; e < e1; e += 256) {
             const vi4 r = recs[e];
-            const int dx = wrap_index((r.x & 0xffff) - 1 - xo, nx);
-            const int dy = wrap_index((r.x >> 16) - 1 - yo, ny);
+            // home cells lie in [0, n) and the origin in [-R-1, n), so one
+            // wrap suffices (the offset lies in [-n, 2n))
+            const int dx = wrap_near((r.x & 0xffff) - 1 - xo, nx);
+            const int dy = wrap_near((r.x >> 16) - 1 - yo, ny);
             if ((dx >= reg && dx + 3 < nx) || (dy >= reg && dy + 3 < ny)) continue;   // misses the region
             float wx[4], wy[4];
             peskin4(__int_as_float(r.y), wx);
@@ -474,22 +477,25 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
       const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
       for (int k = tid; k < reg * reg; k += 256) {
         const int r = k / reg, c = k - (k / reg) * reg;
-        s_reg[k] = __float2ll_rn(kFixScale *
-                                 gather_density(start, rec, nx, ny, wrap_index(xo + c, nx), wrap_index(yo + r, ny)));
+        s_regf[k] = gather_density(start, rec, nx, ny, wrap_index(xo + c, nx), wrap_index(yo + r, ny));
       }
     } else {
       const MC_GLOBAL float* sd = glb(w.s);
       for (int k = tid; k < reg * reg; k += 256) {
         const int r = k / reg, c = k - (k / reg) * reg;
-        s_reg[k] = __float2ll_rn(kFixScale * sd[(size_t)wrap_index(yo + r, ny) * nx + wrap_index(xo + c, nx)]);
+        s_regf[k] = sd[(size_t)wrap_index(yo + r, ny) * nx + wrap_index(xo + c, nx)];
       }
     }
     __syncthreads();
+    if (mode == kBinned) {
+      for (int k = tid; k < reg * reg; k += 256) s_regf[k] = fix_to_float(s_reg[k]);
+      __syncthreads();
+    }
     for (int k = tid; k < reg * kRing; k += 256) {
       const int r = k / kRing, c = k - (k / kRing) * kRing;
-      const long long* row = s_reg + r * reg + c + R;
-      float acc = s_tap[0] * fix_to_float(row[0]);
-      for (int m = 1; m <= R; ++m) acc += s_tap[m] * (fix_to_float(row[-m]) + fix_to_float(row[m]));
+      const float* row = s_regf + r * reg + c + R;
+      float acc = s_tap[0] * row[0];
+      for (int m = 1; m <= R; ++m) acc += s_tap[m] * (row[-m] + row[m]);
       s_mid[r * kRing + c] = acc;
     }
     __syncthreads();
@@ -526,7 +532,7 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
-    if (w.ctl_src->remaining <= 0) continue;
+    if (w.mode == kBinned || w.ctl_src->remaining <= 0) continue;   // binned: k_repulse_tile
     const int sl = pk.node_begin + threadIdx.x;      // node index, or sorted slot
     if (sl >= pk.node_end) continue;
     const int mode = w.mode;
@@ -734,7 +740,7 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
-    if (w.ctl_src->remaining <= 0) continue;
+    if (w.mode == kBinned || w.ctl_src->remaining <= 0) continue;   // binned: k_integrate_tile
     const int gi = pk.node_begin + threadIdx.x;
     if (gi >= pk.node_end) continue;
     const int N = w.n_part;
@@ -778,6 +784,124 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
     cell_out[N + gi] = ncy;
     frac_out[gi] = nfx;
     frac_out[N + gi] = nfy;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Binned worlds: the node gathers of S4 (G) and S7 (u) per 32x32 tile.  The
+// field is staged in LDS for the tile plus the support margin (cells
+// x0-1 .. x0+33) with coalesced loads; every node whose home cell lies in the
+// tile (its bin) gathers its 4x4 window from LDS.
+// ---------------------------------------------------------------------------
+constexpr int kStage = kTile + 3;
+
+__device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, float* sx,
+                                            float* sy) {
+  for (int k = threadIdx.x; k < kStage * kStage; k += 256) {
+    const int r = k / kStage, c = k - (k / kStage) * kStage;
+    const vf2 v = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
+    sx[k] = v.x;
+    sy[k] = v.y;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_repulse_tile(const WorldDev* __restrict__ W, Tables T) {
+  __shared__ float s_gx[kStage * kStage];
+  __shared__ float s_gy[kStage * kStage];
+  const int nt = *T.n_tiles;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    const int2 tl = T.tiles[it];
+    const WorldDev& w = W[tl.x];
+    if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
+    const int nx = w.nx, ny = w.ny, N = w.n_part;
+    const int x0 = (tl.y % w.ntx) * kTile;
+    const int y0 = (tl.y / w.ntx) * kTile;
+    stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_gx, s_gy);
+    __syncthreads();
+    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
+    MC_GLOBAL float* fel = glb(w.fel);
+    const float kr = w.k_rep;
+    const int e1 = glb(w.bin_start)[tl.y + 1];
+    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += 256) {
+      const vi4 r = recs[e];
+      const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;   // home in the tile
+      float wx[4], wy[4];
+      peskin4(__int_as_float(r.y), wx);
+      peskin4(__int_as_float(r.z), wy);
+      float gx = 0.f, gy = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const float* rx = s_gx + (ly + b) * kStage + lx;
+        const float* ry = s_gy + (ly + b) * kStage + lx;
+        float ax = 0.f, ay = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ax += wx[a] * rx[a];
+          ay += wx[a] * ry[a];
+        }
+        gx += wy[b] * ax;
+        gy += wy[b] * ay;
+      }
+      fel[r.w] = fel[r.w] - kr * gx;
+      fel[N + r.w] = fel[N + r.w] - kr * gy;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
+  __shared__ float s_ux[kStage * kStage];
+  __shared__ float s_uy[kStage * kStage];
+  const int nt = *T.n_tiles;
+  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+    const int2 tl = T.tiles[it];
+    const WorldDev& w = W[tl.x];
+    if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
+    const int nx = w.nx, ny = w.ny, N = w.n_part;
+    const int x0 = (tl.y % w.ntx) * kTile;
+    const int y0 = (tl.y / w.ntx) * kTile;
+    stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_ux, s_uy);
+    __syncthreads();
+    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
+    const MC_GLOBAL int* cell = glb(w.cell_in);
+    MC_GLOBAL int* cell_out = glb(w.cell_out);
+    MC_GLOBAL float* frac_out = glb(w.frac_out);
+    const int e1 = glb(w.bin_start)[tl.y + 1];
+    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += 256) {
+      const vi4 r = recs[e];
+      const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
+      const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);
+      float wx[4], wy[4];
+      peskin4(fx, wx);
+      peskin4(fy, wy);
+      float dux = 0.f, duy = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const float* rx = s_ux + (ly + b) * kStage + lx;
+        const float* ry = s_uy + (ly + b) * kStage + lx;
+        float ax = 0.f, ay = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ax += wx[a] * rx[a];
+          ay += wx[a] * ry[a];
+        }
+        dux += wy[b] * ax;
+        duy += wy[b] * ay;
+      }
+      const int gi = r.w;
+      float nfx = fx + dux, nfy = fy + duy;
+      const float flx = floorf(nfx), fly = floorf(nfy);
+      int ncx = cell[gi] + (int)flx, ncy = cell[N + gi] + (int)fly;
+      nfx -= flx;
+      nfy -= fly;
+      if (nfx >= 1.0f) { nfx = 0.0f; ncx += 1; }
+      if (nfy >= 1.0f) { nfy = 0.0f; ncy += 1; }
+      cell_out[gi] = ncx;
+      cell_out[N + gi] = ncy;
+      frac_out[gi] = nfx;
+      frac_out[N + gi] = nfy;
+    }
+    __syncthreads();
   }
 }
 
@@ -825,7 +949,8 @@ void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_
 }
 
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  MC_PACK_DISPATCH(k_repulse, G, W, T);
+  if (G.any_node) MC_PACK_DISPATCH(k_repulse, G, W, T);
+  if (G.any_binned) k_repulse_tile<<<G.tile_blocks, 256, 0, s>>>(W, T);
 }
 
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
@@ -837,7 +962,8 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 }
 
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  MC_PACK_DISPATCH(k_integrate, G, W, T);
+  if (G.any_node) MC_PACK_DISPATCH(k_integrate, G, W, T);
+  if (G.any_binned) k_integrate_tile<<<G.tile_blocks, 256, 0, s>>>(W, T);
 }
 
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s) {

@@ -356,9 +356,14 @@ struct Engine {
       grid.world_blocks = (int)std::max<size_t>(1, n_worlds);
     }
     // a kernel family stays in the captured graphs once any world needed it
-    const bool more = (any_sorted && !grid.any_sorted) || (any_binned && !grid.any_binned);
+    bool more = (any_sorted && !grid.any_sorted) || (any_binned && !grid.any_binned);
+    bool any_node = false;
+    for (const auto& sl : slots)
+      if (sl.used && mode_of(sl.p) != mc::kBinned) any_node = true;
+    more = more || (any_node && !grid.any_node);
     grid.any_sorted |= any_sorted ? 1 : 0;
     grid.any_binned |= any_binned ? 1 : 0;
+    grid.any_node |= any_node ? 1 : 0;
     if (more) drop_graphs();
     // stage into pinned memory once the previous upload has been consumed
     HIPCHK(hipEventSynchronize(upload_done));
@@ -923,6 +928,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
   mc::Grid g = e.grid;
   g.any_binned = 1;
   g.any_sorted = 0;
+  g.any_node = 0;
 
   // per-step descriptors (identical for every segment; uploaded once)
   std::vector<mc::WorldDev> hd(L.m);
