@@ -32,6 +32,9 @@ __global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__
                                                     float scale_is_rep, float2* out) {
   __shared__ long long s_x[kTile * kTile];
   __shared__ long long s_y[kTile * kTile];
+  __shared__ vi4 s_list[kListCap];
+  __shared__ int s_count;
+  __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   for (int it = blockIdx.x; it < nt; it += gridDim.x) {
     const int2 tl = T.tiles[it];
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__
     }
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
-    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y);
+    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_count, &s_bs);
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < kTile * kTile; k += 256) {

@@ -153,6 +153,78 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 }
 
 
+// Records of a set of home-tile bins (the set lives in LDS, built by one
+// thread), visited in chunks: the records for which keep(r) holds are first
+// compacted into an LDS list (wavefront ballots, one LDS atomic per
+// wavefront), then body(r) runs over the dense list, so lanes holding
+// irrelevant records do not idle through the work.
+constexpr int kListCap = 1024;
+
+struct BinSet {
+  int n;
+  int start[16];
+  int pre[17];
+};
+
+// Build the bin set of the tiles tx[ntx] x ty[nty] in LDS: one thread per
+// bin loads its range (independent loads, no chain), then a short prefix.
+// All threads call it with the same tile lists.
+static __device__ __forceinline__ void make_binset(const MC_GLOBAL int* bstart, int tiles_per_row, const int* tx,
+                                                   int ntx, const int* ty, int nty, BinSet* bs) {
+  const int n = ntx * nty;
+  const int i = threadIdx.x;
+  if (i < n) {
+    const int t = ty[i / ntx] * tiles_per_row + tx[i - (i / ntx) * ntx];
+    const int b0 = bstart[t];
+    bs->start[i] = b0;
+    bs->pre[i + 1] = bstart[t + 1] - b0;      // length, turned into a prefix below
+  }
+  __syncthreads();
+  if (i == 0) {
+    bs->n = n;
+    bs->pre[0] = 0;
+    for (int k = 1; k <= n; ++k) bs->pre[k] += bs->pre[k - 1];
+  }
+  __syncthreads();
+}
+
+template <class Keep, class Body>
+static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs, const BinSet& bs, vi4* s_list,
+                                                       int* s_count, Keep keep, Body body) {
+  constexpr int kPer = kListCap / 256;         // records each thread loads per round
+  const int total = bs.pre[bs.n];
+  const int lane = __lane_id();
+  for (int base = 0; base < total; base += kListCap) {
+    if (threadIdx.x == 0) *s_count = 0;
+    vi4 r[kPer];
+    bool k[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {           // issue every load before any use
+      const int f = base + i * 256 + (int)threadIdx.x;
+      k[i] = f < total;
+      if (k[i]) {
+        int b = 0;
+        while (f >= bs.pre[b + 1]) ++b;
+        r[i] = recs[bs.start[b] + (f - bs.pre[b])];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const bool kk = k[i] && keep(r[i]);
+      const unsigned long long m = __ballot(kk);
+      int base_i = 0;
+      if (lane == 0 && m) base_i = atomicAdd(s_count, __popcll(m));
+      base_i = __shfl(base_i, 0);
+      if (kk) s_list[base_i + __popcll(m & ((1ull << lane) - 1ull))] = r[i];
+    }
+    __syncthreads();
+    const int n = *s_count;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) body(s_list[i]);
+    __syncthreads();
+  }
+}
+
 // Add, for every node whose 4x4 support meets the tile [x0, x0+tw) x
 // [y0, y0+th), the values scale * W(c - x_i) * (v[i], v[N + i]) to the tile's
 // LDS accumulators (64-bit fixed point, row stride kTile).  Nodes are read
@@ -160,22 +232,24 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 // call it; accumulators must be zeroed (and synchronised) beforehand.
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
-                                       long long* s_y) {
+                                       long long* s_y, vi4* s_list, int* s_count, BinSet* s_bs) {
   const int nx = w.nx, ny = w.ny, N = w.n_part;
-  const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
-  const MC_GLOBAL int* bstart = glb(w.bin_start);
-  int txs[4], tys[4];
-  const int ntxs = tiles_covering(x0 - 2, x0 + tw, nx, w.ntx, txs);
-  const int ntys = tiles_covering(y0 - 2, y0 + th, ny, w.nty, tys);
-  for (int bj = 0; bj < ntys; ++bj) {
-    for (int bi = 0; bi < ntxs; ++bi) {
-      const int tile = tys[bj] * w.ntx + txs[bi];
-      const int e1 = bstart[tile + 1];
-      for (int e = bstart[tile] + threadIdx.x; e < e1; e += blockDim.x) {
-        const vi4 r = recs[e];
+  {
+    int txs[4], tys[4];
+    const int ntxs = tiles_covering(x0 - 2, x0 + tw, nx, w.ntx, txs);
+    const int ntys = tiles_covering(y0 - 2, y0 + th, ny, w.nty, tys);
+    make_binset(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys, s_bs);
+  }
+  for_bin_records(
+      glbv<const vi4>(w.bin_rec), *s_bs, s_list, s_count,
+      [&](const vi4& r) {
         const int dx = wrap_near((r.x & 0xffff) - 1 - x0, nx);   // home in [0,n), x0 in [0,n)
         const int dy = wrap_near((r.x >> 16) - 1 - y0, ny);
-        if ((dx >= tw && dx + 3 < nx) || (dy >= th && dy + 3 < ny)) continue;   // misses the tile
+        return !((dx >= tw && dx + 3 < nx) || (dy >= th && dy + 3 < ny));
+      },
+      [&](const vi4& r) {
+        const int dx = wrap_near((r.x & 0xffff) - 1 - x0, nx);
+        const int dy = wrap_near((r.x >> 16) - 1 - y0, ny);
         float wx[4], wy[4];
         peskin4(__int_as_float(r.y), wx);
         peskin4(__int_as_float(r.z), wy);
@@ -195,9 +269,7 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
             lds_fix_add(&s_y[ly * kTile + lx], ww * Vy);
           }
         }
-      }
-    }
-  }
+      });
 }
 
 }  // namespace mc

@@ -416,11 +416,19 @@ constexpr int kRing = kTile + 2;                    // tile plus the one-cell ri
 constexpr int kRegion = kRing + 2 * kMaxRadius;     // largest density region side
 
 __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, Tables T) {
-  __shared__ long long s_reg[kRegion * kRegion];   // density, 64-bit fixed point
-  __shared__ float s_regf[kRegion * kRegion];      // the same, as float
-  __shared__ float s_mid[kRegion * kRing];
-  __shared__ float s_st[kRing * kRing];
+  // LDS phases share one buffer: [A | B] with A = density (int64) then the x
+  // pass and the filtered ring, B = compacted records then the density as float
+  constexpr int kA = kRegion * kRegion * 8;
+  constexpr int kB = kListCap * 16;
+  __shared__ __align__(16) unsigned char smem[kA + kB];
   __shared__ float s_tap[kMaxRadius + 1];
+  __shared__ int s_count;
+  __shared__ BinSet s_bs;
+  long long* s_reg = (long long*)smem;
+  vi4* s_list = (vi4*)(smem + kA);
+  float* s_regf = (float*)(smem + kA);
+  float* s_mid = (float*)smem;
+  float* s_st = (float*)smem + kRegion * kRing;
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < nt; it += gridDim.x) {
@@ -436,42 +444,58 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
     if (tid <= R) s_tap[tid] = w.gtap[tid];
     if (mode == kBinned) {
       for (int k = tid; k < reg * reg; k += 256) s_reg[k] = 0;
-      __syncthreads();
       // nodes whose support meets the region have home cells in
       // [origin - 2, origin + reg] on each axis
-      int txs[4], tys[4];
-      const int ntxs = tiles_covering(xo - 2, xo + reg, nx, w.ntx, txs);
-      const int ntys = tiles_covering(yo - 2, yo + reg, ny, w.nty, tys);
-      const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
-      const MC_GLOBAL int* bstart = glb(w.bin_start);
-      for (int bj = 0; bj < ntys; ++bj) {
-        for (int bi = 0; bi < ntxs; ++bi) {
-          const int tile = tys[bj] * w.ntx + txs[bi];
-          const int e1 = bstart[tile + 1];
-          for (int e = bstart[tile] + tid; e < e1; e += 256) {
-            const vi4 r = recs[e];
+      {
+        int txs[4], tys[4];
+        const int ntxs = tiles_covering(xo - 2, xo + reg, nx, w.ntx, txs);
+        const int ntys = tiles_covering(yo - 2, yo + reg, ny, w.nty, tys);
+        make_binset(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys, &s_bs);
+      }
+      const bool alias = reg > nx || reg > ny;    // region wraps onto itself (small grids)
+      for_bin_records(
+          glbv<const vi4>(w.bin_rec), s_bs, s_list, &s_count,
+          [&](const vi4& r) {
             // home cells lie in [0, n) and the origin in [-R-1, n), so one
             // wrap suffices (the offset lies in [-n, 2n))
             const int dx = wrap_near((r.x & 0xffff) - 1 - xo, nx);
             const int dy = wrap_near((r.x >> 16) - 1 - yo, ny);
-            if ((dx >= reg && dx + 3 < nx) || (dy >= reg && dy + 3 < ny)) continue;   // misses the region
+            return !((dx >= reg && dx + 3 < nx) || (dy >= reg && dy + 3 < ny));
+          },
+          [&](const vi4& r) {
+            const int dx = wrap_near((r.x & 0xffff) - 1 - xo, nx);
+            const int dy = wrap_near((r.x >> 16) - 1 - yo, ny);
             float wx[4], wy[4];
             peskin4(__int_as_float(r.y), wx);
             peskin4(__int_as_float(r.z), wy);
-            for (int b = 0; b < 4; ++b) {
-              int ly = dy + b;
-              ly = ly >= ny ? ly - ny : ly;
-              for (; ly < reg; ly += ny) {
+            if (!alias) {
+#pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                int ly = dy + b;
+                ly = ly >= ny ? ly - ny : ly;
+                if (ly >= reg) continue;
+#pragma unroll
                 for (int a = 0; a < 4; ++a) {
                   int lx = dx + a;
                   lx = lx >= nx ? lx - nx : lx;
-                  for (; lx < reg; lx += nx) lds_fix_add(&s_reg[ly * reg + lx], wx[a] * wy[b]);
+                  if (lx < reg) lds_fix_add(&s_reg[ly * reg + lx], wx[a] * wy[b]);
+                }
+              }
+            } else {
+              for (int b = 0; b < 4; ++b) {
+                int ly = dy + b;
+                ly = ly >= ny ? ly - ny : ly;
+                for (; ly < reg; ly += ny) {
+                  for (int a = 0; a < 4; ++a) {
+                    int lx = dx + a;
+                    lx = lx >= nx ? lx - nx : lx;
+                    for (; lx < reg; lx += nx) lds_fix_add(&s_reg[ly * reg + lx], wx[a] * wy[b]);
+                  }
                 }
               }
             }
-          }
-        }
-      }
+          });
+      for (int k = tid; k < reg * reg; k += 256) s_regf[k] = fix_to_float(s_reg[k]);
     } else if (mode == kSorted) {
       const MC_GLOBAL int* start = glb(w.start);
       const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
@@ -487,10 +511,6 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
       }
     }
     __syncthreads();
-    if (mode == kBinned) {
-      for (int k = tid; k < reg * reg; k += 256) s_regf[k] = fix_to_float(s_reg[k]);
-      __syncthreads();
-    }
     for (int k = tid; k < reg * kRing; k += 256) {
       const int r = k / kRing, c = k - (k / kRing) * kRing;
       const float* row = s_regf + r * reg + c + R;
@@ -596,6 +616,9 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
 __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, Tables T) {
   __shared__ long long s_fx[kTile * kTile];      // 64-bit fixed point
   __shared__ long long s_fy[kTile * kTile];
+  __shared__ vi4 s_list[kListCap];
+  __shared__ int s_count;
+  __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < nt; it += gridDim.x) {
@@ -613,7 +636,7 @@ __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, 
         s_fy[k] = 0;
       }
       __syncthreads();
-      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy);
+      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, &s_count, &s_bs);
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
@@ -797,11 +820,23 @@ constexpr int kStage = kTile + 3;
 
 __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, float* sx,
                                             float* sy) {
-  for (int k = threadIdx.x; k < kStage * kStage; k += 256) {
-    const int r = k / kStage, c = k - (k / kStage) * kStage;
-    const vf2 v = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
-    sx[k] = v.x;
-    sy[k] = v.y;
+  constexpr int kIt = (kStage * kStage + 255) / 256;
+  vf2 v[kIt];
+#pragma unroll
+  for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
+    const int k = (int)threadIdx.x + 256 * i;
+    if (k < kStage * kStage) {
+      const int r = k / kStage, c = k - (k / kStage) * kStage;
+      v[i] = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kIt; ++i) {
+    const int k = (int)threadIdx.x + 256 * i;
+    if (k < kStage * kStage) {
+      sx[k] = v[i].x;
+      sy[k] = v[i].y;
+    }
   }
 }
 
