@@ -7,9 +7,12 @@ elastic force, deposit, Gaussian filter, repulsion, force spread, D2Q9 TRT
 fluid update, gather + integrate).  Inputs are resident in HBM before the
 timed region; the timed region is K steps of sim_rollout (captured graphs).
 
-Prints one JSON line.  Also reports the deterministic sorted-segment transfer
-variant, a live per-kernel timing of the dominant (fluid) kernel against the
-HBM roofline, and the FP64 oracle on a bounded sample of host-CPU work.
+Prints one JSON line.  Also reports the deterministic sorted-segment and the
+direct-atomic transfer variants, a live per-kernel timing of the dominant
+(fluid) kernel against the HBM roofline, the differentiation workload
+(backward / forward cost), the batched + served workload (rollouts/s and
+p50/p99 latency against the plain per-world path), and the FP64 oracle on a
+bounded sample of host-CPU work.
 """
 from __future__ import annotations
 
@@ -34,6 +37,10 @@ STEP_BYTES_PER_NODE = 24      # whole-step algorithmic bytes per node
 KERNELS = ["elastic", "bin_or_sort", "filter", "repulse", "fluid", "integrate"]
 
 
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def time_rollout(W, warmup, steps, t0=0):
     W.rollout(t0, warmup)
     torch.cuda.synchronize()
@@ -45,6 +52,148 @@ def time_rollout(W, warmup, steps, t0=0):
     torch.cuda.synchronize()
     W.sync()
     return start.elapsed_time(end) / 1000.0
+
+
+def bench_served(seed, pool_gib, tune_steps):
+    """Served workload: 256 rollout jobs (filament counts log-uniform 1..512,
+    lengths U{8..128}, grids 128^2..512^2, 200..2000 steps), Poisson arrivals
+    at 50 jobs/s, continuous batching through one pool of world slots.
+
+    Also runs the same jobs (a) all arrived at once through the same batch
+    engine (throughput capacity) and (b) one at a time through the plain
+    per-world sim_rollout path, whose FIFO latencies under the same arrivals
+    are replayed from the measured per-job times.  Every served result is
+    compared bitwise with its per-world run."""
+    from dataclasses import replace
+    from paper_2607_02954_amd import autotune, batch, serve
+
+    jobs = wl.served_jobs(seed)
+    pf = lambda job: sim.Params(nx=job.world.nx, ny=job.world.ny)
+    pool_bytes = int(pool_gib * (1 << 30))
+    # tuning on a representative scratch batch (every 8th job)
+    rep = [j.world for j in jobs[::8]]
+    best, table = autotune.tune(rep, lambda w: sim.Params(nx=w.nx, ny=w.ny), pool_bytes,
+                                steps_per_trial=tune_steps, use_cache=False,
+                                candidates={"chunk_steps": [10, 20, 40], "cell_blocks": [2048, 4096, 8192],
+                                            "node_blocks": [1024, 2048]})
+    torch.cuda.empty_cache()
+
+    def run(js):
+        eng = batch.BatchEngine(max_worlds=len(js), pool_bytes=pool_bytes)
+        eng.set_tuning(best["chunk_steps"], best["cell_blocks"], best["node_blocks"])
+        srv = serve.Server(serve.GpuExecutor(eng, pf), chunk_steps=best["chunk_steps"])
+        torch.cuda.synchronize()
+        stats = srv.run(js)
+        torch.cuda.synchronize()
+        eng.close()
+        return stats
+
+    log(f"served: tuned {best}")
+    served = run(jobs)
+    log(f"served: Poisson run done {served.summary()['makespan_s']:.2f} s")
+    offline = run([replace(j, arrival=0.0) for j in jobs])
+    s_sum, o_sum = served.summary(), offline.summary()
+    log("served: all-arrived run done; per-world runs next")
+
+    # plain per-world path, one job at a time
+    service, equal = [], 0
+    for job, r in zip(jobs, served.results):
+        t0 = time.perf_counter()
+        W = sim.World(job.world, pf(job))
+        W.rollout(0, job.steps)
+        W.sync()
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        if r.ok and all(torch.equal(getattr(W.state, k), getattr(r.state, k)) for k in ("cell", "frac", "f", "u")):
+            equal += 1
+        W.close()
+        del W
+        r.state = None
+    finish, lat = 0.0, []
+    for job, s in zip(sorted(jobs, key=lambda j: j.arrival), [service[j.job_id] for j in
+                                                               sorted(jobs, key=lambda j: j.arrival)]):
+        finish = max(finish, job.arrival) + s
+        lat.append(finish - job.arrival)
+    total = float(sum(service))
+    steps = sum(j.steps for j in jobs)
+    return {
+        "workload": "256 served rollout jobs: filaments log-uniform 1..512, lengths U{8..128}, "
+                    "grids 128^2..512^2 (step 32), 200..2000 steps, Poisson arrivals 50 jobs/s",
+        "world_steps": steps,
+        "particle_steps": int(sum(j.world.n_particles * j.steps for j in jobs)),
+        "pool_bytes": pool_bytes,
+        "tuning": best,
+        "served": {k: s_sum[k] for k in ("completed", "rollouts_per_s", "p50_latency_s", "p99_latency_s",
+                                         "makespan_s", "chunks", "peak_resident", "peak_bytes")},
+        "batched_all_arrived": {k: o_sum[k] for k in ("completed", "rollouts_per_s", "p50_latency_s",
+                                                      "p99_latency_s", "makespan_s", "chunks")},
+        "per_world": {
+            "rollouts_per_s": len(jobs) / total,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "busy_s": total,
+            "latency": "FIFO replay of the measured per-job times under the same arrivals",
+        },
+        "batched_vs_per_world_throughput": o_sum["rollouts_per_s"] * total / len(jobs),
+        "served_equal_to_per_world_bitwise": f"{equal}/{len(jobs)}",
+    }
+
+
+def bench_adjoint(seed, reps=5):
+    """Differentiation workload: 64 chains x 48 nodes on 256^2, 200 steps,
+    checkpoints every 20; loss = mean squared distance to the seeded target
+    fold; gradient in the rest angles through the autograd Function."""
+    w = wl.folding_population(seed)
+    p = sim.Params(nx=w.nx, ny=w.ny)
+    n, k = 200, 20
+    W = sim.World(w, p)
+    tgt = torch.tensor(w.target, dtype=torch.float64, device="cuda")
+    cell0, frac0 = W.state.cell.clone(), W.state.frac.clone()
+
+    def reset():
+        W.state.cell.copy_(cell0)
+        W.state.frac.copy_(frac0)
+        W.state.f.zero_()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    plain, fwd, bwd = [], [], []
+    for r in range(reps + 1):
+        reset()
+        torch.cuda.synchronize()
+        ev[0].record()
+        W.rollout(0, n)
+        ev[1].record()
+        torch.cuda.synchronize()
+        reset()
+        ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        ev[2].record()
+        xT = sim.Rollout.apply(ra, W, 0, n, k)
+        loss = ((xT - tgt) ** 2).sum() / xT.shape[1]
+        ev[3].record()
+        torch.cuda.synchronize()
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record()
+        loss.backward()
+        b1.record()
+        torch.cuda.synchronize()
+        if r:                                    # first repetition warms up
+            plain.append(ev[0].elapsed_time(ev[1]))
+            fwd.append(ev[2].elapsed_time(ev[3]))
+            bwd.append(b0.elapsed_time(b1))
+    W.close()
+    pm, fm, bm = float(np.median(plain)), float(np.median(fwd)), float(np.median(bwd))
+    return {
+        "workload": "folding: 64 chains x 48 nodes on 256x256, 200 steps, checkpoints every 20, "
+                    "gradient of the target-fold loss in the rest angles",
+        "plain_rollout_ms": pm,
+        "checkpointed_forward_ms": fm,
+        "backward_ms": bm,
+        "bwd_over_fwd": bm / fm,
+        "bwd_over_plain_fwd": bm / pm,
+        "loss": float(loss),
+    }
 
 
 def cpu_baseline(world, sample_steps):
@@ -80,6 +229,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sorted", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--pool-gib", type=float, default=8.0, help="HBM budget of the served pool")
+    ap.add_argument("--tune-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -167,8 +320,16 @@ def main():
         "kernel_ms": dict(zip(KERNELS, [round(v, 5) for v in kms])),
         "transfer_variants": variants,
     }
+    log(f"scaling workload done: {ms_step:.4f} ms/step")
+    if not args.no_adjoint:
+        out["differentiation"] = bench_adjoint(args.seed)
+        log("differentiation done")
+    if not args.no_served:
+        out["batched_served"] = bench_served(args.seed, args.pool_gib, args.tune_steps)
+        log("served done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(world, args.cpu_steps)
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
