@@ -30,32 +30,32 @@ constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registe
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__ W, Tables T, const float* v,
                                                     float scale_is_rep, float2* out) {
-  __shared__ long long s_x[kTile * kTile];
-  __shared__ long long s_y[kTile * kTile];
-  __shared__ vi4 s_list[kListCap];
-  __shared__ int s_count;
+  __shared__ long long s_x[kSpreadCells];
+  __shared__ long long s_y[kSpreadCells];
+  __shared__ vi4 s_list[4 * kWaveList];
   __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     const int nx = w.nx, ny = w.ny;
     const int x0 = (tl.y % w.ntx) * kTile;
     const int y0 = (tl.y / w.ntx) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
-    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+    for (int k = threadIdx.x; k < kSpreadCells; k += 256) {
       s_x[k] = 0;
       s_y[k] = 0;
     }
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
-    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_count, &s_bs);
+    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_bs);
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
       const int ly = k >> 5, lx = k & (kTile - 1);
       if (lx >= tw || ly >= th) continue;
-      const vf2 val = {fix_to_float(s_x[k]), fix_to_float(s_y[k])};
+      const vf2 val = {fix_to_float(spread_cell(s_x, lx, ly, nx, ny)), fix_to_float(spread_cell(s_y, lx, ly, nx, ny))};
       o[(size_t)(y0 + ly) * nx + x0 + lx] = val;
     }
     __syncthreads();
@@ -240,7 +240,8 @@ __global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__
   __shared__ float s_mid[kAdjInner * kTile];
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     const int R = w.radius;
@@ -330,24 +331,23 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
       fx = frac[gi]; fy = frac[N + gi];
     }
     float v0x = 0.f, v0y = 0.f, L = 0.f, th = 0.f;
+    float u0x = 1.f, u0y = 0.f;
     if (has_edge) {
       v0x = (float)(cell[gi + 1] - cx) + (frac[gi + 1] - fx);
       v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
       L = glb(w.rest_length)[gi];
       th = atan2f(v0y, v0x);
+      const float l0 = sqrtf(v0x * v0x + v0y * v0y);
+      if (l0 > 0.f) {
+        u0x = v0x / l0;
+        u0y = v0y / l0;
+      }
     }
     float th_hat = 0.f;
     if (is_joint) {
       const int f = pk.fil_begin + lo;
-      const float amp = glb(w.act_amp)[f];
-      const float ra = glb(w.rest_angle)[gi];
-      if (amp != 0.0f) {
-        const double arg = kTwoPiD * (double)A.t / (double)glb(w.act_period)[f] +
-                           (double)glb(w.act_phase)[f] - kTwoPiD * (double)j / (double)(n - 2);
-        th_hat = (float)((double)ra + (double)amp * sin(arg));
-      } else {
-        th_hat = ra;
-      }
+      th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[f], glb(w.act_period)[f],
+                              glb(w.act_phase)[f], A.t, j, n);
     }
     // dL/dx_t so far (written by k_adj_force) plus the deposit derivative
     float xbx = 0.f, xby = 0.f;
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
             const float sc = (ell - L) / ell;
             const float csx = sc * vx, csy = sc * vy;
             float sn, cs;
-            sincosf(th_p[iter], &sn, &cs);
+            edge_direction(th_p[iter], th, u0x, u0y, &cs, &sn);
             const float dx = hs * (csx + ksh * (vx - L * cs - csx));
             const float dy = hs * (csy + ksh * (vy - L * sn - csy));
             s_dx[li] = d0x + dx;
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
             v0bx += mbx;
             v0by += mby;
             float sn, cs;
-            sincosf(th_p[iter], &sn, &cs);
+            edge_direction(th_p[iter], th, u0x, u0y, &cs, &sn);
             s_gth[li] += -hs * ksh * L * (-sn * Dbx + cs * Dby);
           }
           __syncthreads();

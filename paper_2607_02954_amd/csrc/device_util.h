@@ -9,7 +9,6 @@ namespace mc {
 
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kTwoPi = 6.28318530717958647692f;
-constexpr double kTwoPiD = 6.28318530717958647692;
 
 static __device__ __forceinline__ int wrap_index(int i, int n) {
   int r = i % n;
@@ -28,8 +27,13 @@ static __device__ __forceinline__ float wrap_angle(float d) {
 // The four 1D weights of Peskin's 4-point function for offsets
 // (-1 - f, -f, 1 - f, 2 - f), f in [0, 1): with q = sqrt(1 + 4f - 4f^2) they
 // are (3 - 2f - q)/8, (3 - 2f + q)/8, (1 + 2f + q)/8, (1 + 2f - q)/8.
+// The square root's argument lies in [1, 2], where the hardware square root
+// (within 1 ulp) needs none of the scaling of the library's sqrtf.
+static __device__ __forceinline__ float peskin_q(float f) {
+  return __builtin_amdgcn_sqrtf(fmaf(4.0f * f, 1.0f - f, 1.0f));
+}
 static __device__ __forceinline__ void peskin4(float f, float w[4]) {
-  const float q = sqrtf(fmaf(4.0f * f, 1.0f - f, 1.0f));
+  const float q = peskin_q(f);
   const float a = 3.0f - 2.0f * f;
   const float b = 1.0f + 2.0f * f;
   w[0] = 0.125f * (a - q);
@@ -41,7 +45,7 @@ static __device__ __forceinline__ void peskin4(float f, float w[4]) {
 // Derivatives of the four weights above with respect to f:
 // with q' = (2 - 4f)/q they are (-2 - q')/8, (-2 + q')/8, (2 + q')/8, (2 - q')/8.
 static __device__ __forceinline__ void peskin4_d(float f, float w[4], float dw[4]) {
-  const float q = sqrtf(fmaf(4.0f * f, 1.0f - f, 1.0f));
+  const float q = peskin_q(f);
   const float a = 3.0f - 2.0f * f;
   const float b = 1.0f + 2.0f * f;
   w[0] = 0.125f * (a - q);
@@ -53,6 +57,37 @@ static __device__ __forceinline__ void peskin4_d(float f, float w[4], float dw[4
   dw[1] = 0.125f * (-2.0f + qd);
   dw[2] = 0.125f * (2.0f + qd);
   dw[3] = 0.125f * (2.0f - qd);
+}
+
+// Actuated rest angle of joint j (of n - 2) of a filament at time step t:
+// ra + amp sin(2 pi t / period + phase - 2 pi j / (n - 2)).  The phase is
+// formed in revolutions and reduced to [-1/2, 1/2] (the integer part of
+// t / period is removed in FP64), so FP32 sinf sees a small argument.
+static __device__ __forceinline__ float actuated_angle(float ra, float amp, float period, float phase, long long t,
+                                                       int j, int n) {
+  if (amp == 0.0f) return ra;
+  const double q = (double)t / (double)period;
+  float r = (float)(q - floor(q)) + phase * (1.0f / kTwoPi) - (float)j / (float)(n - 2);
+  r -= rintf(r);
+  return ra + amp * sinf(kTwoPi * r);
+}
+
+// (cos t, sin t) of an edge angle t that started the step at t0, whose unit
+// vector (c0, s0) is known: the rotation of (c0, s0) by d = t - t0, with
+// cos d and sin d from their Taylor series (to d^8 and d^9; truncation below
+// 3e-8 for |d| <= pi/4).  Larger turns take sincosf.
+static __device__ __forceinline__ void edge_direction(float t, float t0, float c0, float s0, float* c, float* s) {
+  const float d = t - t0;
+  if (fabsf(d) <= 0.25f * kPi) {
+    const float d2 = d * d;
+    const float cd = fmaf(d2, fmaf(d2, fmaf(d2, fmaf(d2, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
+    const float sd = d * fmaf(d2, fmaf(d2, fmaf(d2, fmaf(d2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f),
+                                       -1.0f / 6.0f), 1.0f);
+    *c = c0 * cd - s0 * sd;
+    *s = s0 * cd + c0 * sd;
+  } else {
+    sincosf(t, s, c);
+  }
 }
 
 // D2Q9 lattice: velocity q has components (CX[q], CY[q]); q and q+2 are
@@ -105,6 +140,47 @@ static __device__ __forceinline__ float fix_to_float(long long v) {
   return (float)((double)hi * 4294967296.0 + (double)lo) * kFixInv;
 }
 
+// Density deposits use the 1D weights rounded to multiples of 2^-23 (each
+// weight is at most 1/2, so it is an integer below 2^23): a 2D weight is then
+// the exact product of two such integers, a multiple of 2^-46 formed by two
+// 24-bit multiplies, and sums of them are exact in 64 bits.
+constexpr float kWeightQ = 8388608.0f;                   // 2^23
+constexpr double kDensityInv = 1.4210854715202004e-14;   // 2^-46
+static __device__ __forceinline__ void peskin4_quant(float f, unsigned q[4]) {
+  float w[4];
+  peskin4(f, w);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) q[a] = __float2uint_rn(w[a] * kWeightQ) & 0xffffffu;
+}
+static __device__ __forceinline__ unsigned long long weight_product(unsigned a, unsigned b) {
+  return (unsigned long long)(a & 0xffffffu) * (b & 0xffffffu);   // v_mul_u32_u24 + v_mul_hi_u32_u24
+}
+static __device__ __forceinline__ float density_to_float(unsigned long long v) {
+  return (float)(((double)(unsigned)(v >> 32) * 4294967296.0 + (double)(unsigned)v) * kDensityInv);
+}
+
+// Work-item order of the tile kernels.  The hardware hands workgroups to the
+// eight XCDs in turn (block b to XCD b mod 8) and each XCD has its own L2, so
+// a plain grid-stride loop puts neighbouring tiles, which read each other's
+// halos and bins, on different XCDs.  Here the blocks of each XCD take one
+// contiguous share of the item list instead.
+struct XcdLoop {
+  int first, end, step;
+  __device__ __forceinline__ explicit XcdLoop(int n) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G < 8) {
+      first = b;
+      end = n;
+      step = G;
+      return;
+    }
+    const int x = b & 7, per = (n + 7) >> 3;
+    first = x * per + (b >> 3);
+    end = min(n, x * per + per);
+    step = (G - x + 7) >> 3;                   // blocks on this XCD
+  }
+};
+
 // Wavefront-aggregated atomic increment: lanes that target the same counter
 // are served by one atomic from a leader lane.  Returns, for lanes with `has`,
 // a distinct slot (the counter's old value plus the lane's rank among the
@@ -153,18 +229,27 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 }
 
 
-// Records of a set of home-tile bins (the set lives in LDS, built by one
-// thread), visited in chunks: the records for which keep(r) holds are first
-// compacted into an LDS list (wavefront ballots, one LDS atomic per
-// wavefront), then body(r) runs over the dense list, so lanes holding
-// irrelevant records do not idle through the work.
-constexpr int kListCap = 1024;
+// Records of a set of home-tile bins (the set lives in LDS).  Every
+// wavefront streams its share of the records (PER loads in flight per lane)
+// and appends those for which keep(r) holds to its own LDS list (one ballot
+// per record batch); whenever the list holds a full wavefront of records the
+// wavefront runs body(r) on 64 of them.  No block barrier is needed until all
+// records are done, body always runs on full wavefronts (except for the last
+// partial one), and lanes holding irrelevant records never idle through it.
+// body(r) may only use per-lane work and LDS atomics.
+constexpr int kWaveList = 128;             // records per wavefront list
+constexpr int kListBytes = 4 * kWaveList * 16;
 
 struct BinSet {
   int n;
   int start[16];
   int pre[17];
 };
+
+static __device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 // Build the bin set of the tiles tx[ntx] x ty[nty] in LDS: one thread per
 // bin loads its range (independent loads, no chain), then a short prefix.
@@ -188,51 +273,84 @@ static __device__ __forceinline__ void make_binset(const MC_GLOBAL int* bstart, 
   __syncthreads();
 }
 
-template <class Keep, class Body>
+template <int PER, class Keep, class Body>
 static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs, const BinSet& bs, vi4* s_list,
-                                                       int* s_count, Keep keep, Body body) {
-  constexpr int kPer = kListCap / 256;         // records each thread loads per round
+                                                       Keep keep, Body body) {
   const int total = bs.pre[bs.n];
   const int lane = __lane_id();
-  for (int base = 0; base < total; base += kListCap) {
-    if (threadIdx.x == 0) *s_count = 0;
-    vi4 r[kPer];
-    bool k[kPer];
+  vi4* wl = s_list + (threadIdx.x >> 6) * kWaveList;
+  int cnt = 0;                                 // wavefront-uniform list length
+  int b = 0;                                   // bin of this lane's next record
+  for (int base = 0; base < total; base += PER * 256) {
+    vi4 r[PER];
+    bool k[PER];
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {           // issue every load before any use
+    for (int i = 0; i < PER; ++i) {            // issue every load before any use
       const int f = base + i * 256 + (int)threadIdx.x;
       k[i] = f < total;
       if (k[i]) {
-        int b = 0;
         while (f >= bs.pre[b + 1]) ++b;
         r[i] = recs[bs.start[b] + (f - bs.pre[b])];
       }
     }
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
+    for (int i = 0; i < PER; ++i) {
       const bool kk = k[i] && keep(r[i]);
       const unsigned long long m = __ballot(kk);
-      int base_i = 0;
-      if (lane == 0 && m) base_i = atomicAdd(s_count, __popcll(m));
-      base_i = __shfl(base_i, 0);
-      if (kk) s_list[base_i + __popcll(m & ((1ull << lane) - 1ull))] = r[i];
+      if (kk) wl[cnt + __popcll(m & ((1ull << lane) - 1ull))] = r[i];
+      cnt += __popcll(m);
+      if (cnt >= 64) {
+        wave_sync();
+        body(wl[lane]);
+        const bool mv = lane < cnt - 64;
+        vi4 rest;
+        if (mv) rest = wl[64 + lane];
+        wave_sync();
+        if (mv) wl[lane] = rest;
+        cnt -= 64;
+        wave_sync();
+      }
     }
-    __syncthreads();
-    const int n = *s_count;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) body(s_list[i]);
-    __syncthreads();
   }
+  wave_sync();
+  if (lane < cnt) body(wl[lane]);
+  __syncthreads();
 }
 
-// Add, for every node whose 4x4 support meets the tile [x0, x0+tw) x
-// [y0, y0+th), the values scale * W(c - x_i) * (v[i], v[N + i]) to the tile's
-// LDS accumulators (64-bit fixed point, row stride kTile).  Nodes are read
-// from the home-tile bins of the neighbourhood.  All threads of the block
-// call it; accumulators must be zeroed (and synchronised) beforehand.
+// Node -> grid accumulation over a padded window.  A window of side S covers
+// grid cells o + c (c in [0, S), o = origin, periodic); a node whose home
+// cell is h adds to window cells h - 1 - o + (0..3).  With the home offset
+// d = (h - 1 - o) mod n in [0, n) every contribution lands inside the window
+// provided d + 3 < S, so the inner loops carry no bounds or wrap tests:
+//   * when the window does not wrap onto itself (S <= n) only nodes with
+//     d <= need + 2 can touch the `need` cells [3, 3 + need) the caller
+//     reads, and those are the nodes kept;
+//   * otherwise (small grids) every node of the bins is kept and window
+//     cells that are the same grid cell are summed when read.
+// The first three and last three window cells only catch the spill of nodes
+// at the edge of the needed range.
+
+// Window cell sum for needed cell i (window cell 3 + i) on an axis of n cells:
+// one term unless the window wraps onto itself.
+static __device__ __forceinline__ int first_image(int i, int n) {
+  const int c = i + 3;
+  return c < n ? c : c % n;
+}
+
+// Tile spread: for every node whose 4x4 support meets the tile [x0, x0+tw) x
+// [y0, y0+th), add scale * W(c - x_i) * (v[i], v[N + i]) to the window
+// accumulators s_x, s_y (64-bit fixed point, side kSpreadSide, origin
+// (x0 - 3, y0 - 3)).  Nodes are read from the home-tile bins of the
+// neighbourhood.  All threads of the block call it; the accumulators must be
+// zeroed (and synchronised) beforehand.  Values whose fixed-point image fits
+// 32 bits (|scale v| < 1/8, as nearly all forces) are converted by one
+// truncating 32-bit conversion; larger ones by the exact 64-bit split.
+constexpr int kSpreadSide = kTile + 8;
+constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
+
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
-                                       long long* s_y, vi4* s_list, int* s_count, BinSet* s_bs) {
+                                       long long* s_y, vi4* s_list, BinSet* s_bs) {
   const int nx = w.nx, ny = w.ny, N = w.n_part;
   {
     int txs[4], tys[4];
@@ -240,36 +358,60 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
     const int ntys = tiles_covering(y0 - 2, y0 + th, ny, w.nty, tys);
     make_binset(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys, s_bs);
   }
-  for_bin_records(
-      glbv<const vi4>(w.bin_rec), *s_bs, s_list, s_count,
+  const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
+  const int keep_x = tw + 6 <= nx ? tw + 2 : nx;     // largest kept home offset
+  const int keep_y = th + 6 <= ny ? th + 2 : ny;
+  for_bin_records<4>(
+      glbv<const vi4>(w.bin_rec), *s_bs, s_list,
       [&](const vi4& r) {
-        const int dx = wrap_near((r.x & 0xffff) - 1 - x0, nx);   // home in [0,n), x0 in [0,n)
-        const int dy = wrap_near((r.x >> 16) - 1 - y0, ny);
-        return !((dx >= tw && dx + 3 < nx) || (dy >= th && dy + 3 < ny));
+        const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
+        const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
+        return dx <= keep_x && dy <= keep_y;
       },
       [&](const vi4& r) {
-        const int dx = wrap_near((r.x & 0xffff) - 1 - x0, nx);
-        const int dy = wrap_near((r.x >> 16) - 1 - y0, ny);
+        const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
+        const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
         float wx[4], wy[4];
         peskin4(__int_as_float(r.y), wx);
         peskin4(__int_as_float(r.z), wy);
         const float Vx = scale * v[r.w], Vy = scale * v[N + r.w];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          int ly = dy + b;
-          ly = ly >= ny ? ly - ny : ly;
-          if (ly >= th) continue;
+        unsigned long long* px = (unsigned long long*)(s_x + dy * kSpreadSide + dx);
+        unsigned long long* py = (unsigned long long*)(s_y + dy * kSpreadSide + dx);
+        if (fmaxf(fabsf(Vx), fabsf(Vy)) < 0.125f) {
+          float ax[4], ay[4];
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
-            int lx = dx + a;
-            lx = lx >= nx ? lx - nx : lx;
-            if (lx >= tw) continue;
-            const float ww = wx[a] * wy[b];
-            lds_fix_add(&s_x[ly * kTile + lx], ww * Vx);
-            lds_fix_add(&s_y[ly * kTile + lx], ww * Vy);
+            ax[a] = (Vx * kFixScale) * wx[a];
+            ay[a] = (Vy * kFixScale) * wx[a];
           }
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              atomicAdd(px + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ax[a] * wy[b]));
+              atomicAdd(py + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
+            }
+        } else {
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const float ww = wx[a] * wy[b];
+              atomicAdd(px + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vx * kFixScale));
+              atomicAdd(py + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
+            }
         }
       });
+}
+
+// The accumulated value of tile cell (lx, ly) of a spread window.
+static __device__ __forceinline__ long long spread_cell(const long long* s, int lx, int ly, int nx, int ny) {
+  const int cx0 = first_image(lx, nx), cy0 = first_image(ly, ny);
+  if (cx0 + nx >= kSpreadSide && cy0 + ny >= kSpreadSide) return s[cy0 * kSpreadSide + cx0];
+  long long acc = 0;
+  for (int cy = cy0; cy < kSpreadSide; cy += ny)
+    for (int cx = cx0; cx < kSpreadSide; cx += nx) acc += s[cy * kSpreadSide + cx];
+  return acc;
 }
 
 }  // namespace mc

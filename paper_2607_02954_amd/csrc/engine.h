@@ -106,6 +106,7 @@ struct Grid {
   int pack;                                  // node pack capacity: 256 or 1024
   int any_sorted, any_binned, any_node;      // which transfer families the table holds
                                              // (any_node: a world not in binned mode)
+  int max_radius;                            // largest Gaussian radius of any world (LDS sizing)
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at

@@ -84,24 +84,23 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
       fx = frac[gi]; fy = frac[N + gi];
     }
     float v0x = 0.f, v0y = 0.f, L = 0.f, th = 0.f;
+    float u0x = 1.f, u0y = 0.f;                  // unit edge direction, (cos th, sin th)
     if (has_edge) {
       v0x = (float)(cell[gi + 1] - cx) + (frac[gi + 1] - fx);
       v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
       L = glb(w.rest_length)[gi];
       th = atan2f(v0y, v0x);
+      const float l0 = sqrtf(v0x * v0x + v0y * v0y);
+      if (l0 > 0.f) {
+        u0x = v0x / l0;
+        u0y = v0y / l0;
+      }
     }
     float th_hat = 0.f;
     if (is_joint) {
       const int f = pk.fil_begin + lo;
-      const float amp = glb(w.act_amp)[f];
-      const float ra = glb(w.rest_angle)[gi];
-      if (amp != 0.0f) {
-        const double arg = kTwoPiD * (double)ctl.t / (double)glb(w.act_period)[f] +
-                           (double)glb(w.act_phase)[f] - kTwoPiD * (double)j / (double)(n - 2);
-        th_hat = (float)((double)ra + (double)amp * sin(arg));
-      } else {
-        th_hat = ra;
-      }
+      th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[f], glb(w.act_period)[f],
+                              glb(w.act_phase)[f], ctl.t, j, n);
     }
     s_th[li] = th;
     s_dx[li] = 0.f;
@@ -135,7 +134,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           const float sc = (ell - L) / ell;
           const float csx = sc * vx, csy = sc * vy;
           float sn, cs;
-          sincosf(s_th[li], &sn, &cs);
+          edge_direction(s_th[li], th, u0x, u0y, &cs, &sn);
           const float dx = hs * (csx + ksh * (vx - L * cs - csx));
           const float dy = hs * (csy + ksh * (vy - L * sn - csy));
           s_dx[li] = d0x + dx;
@@ -184,6 +183,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
 // writes a record (home cell, fractions, index) into each bin it belongs to.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bin_scan(const WorldDev* __restrict__ W, Tables T) {
+  constexpr int kPer = 16;                      // consecutive tiles per thread, loaded together
   __shared__ int s_wave[4];
   const int nw = *T.n_worlds;
   for (int it = blockIdx.x; it < nw; it += gridDim.x) {
@@ -193,22 +193,29 @@ __global__ __launch_bounds__(256) void k_bin_scan(const WorldDev* __restrict__ W
     MC_GLOBAL int* fill = glb(w.bin_fill);
     MC_GLOBAL int* start = glb(w.bin_start);
     const int nt = w.ntx * w.nty;
-    const int per = (nt + 255) / 256;
-    const int b0 = threadIdx.x * per;
-    int loc = 0;
-    for (int k = 0; k < per; ++k) loc += (b0 + k < nt) ? cnt[b0 + k] : 0;
-    int total;
-    int run = block_scan256(loc, s_wave, &total);
-    for (int k = 0; k < per; ++k) {
-      if (b0 + k < nt) {
-        const int v = cnt[b0 + k];
-        start[b0 + k] = run;
-        cnt[b0 + k] = 0;
-        fill[b0 + k] = 0;
-        run += v;
+    int carry = 0;
+    for (int c0 = 0; c0 < nt; c0 += 256 * kPer) {
+      const int b0 = c0 + (int)threadIdx.x * kPer;
+      int v[kPer];
+      int loc = 0;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) v[k] = b0 + k < nt ? cnt[b0 + k] : 0;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) loc += v[k];
+      int total;
+      int run = carry + block_scan256(loc, s_wave, &total);
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        if (b0 + k < nt) {
+          start[b0 + k] = run;
+          cnt[b0 + k] = 0;
+          fill[b0 + k] = 0;
+          run += v[k];
+        }
       }
+      carry += total;
     }
-    if (threadIdx.x == 0) start[nt] = total;
+    if (threadIdx.x == 0) start[nt] = carry;
   }
 }
 
@@ -411,27 +418,43 @@ __device__ __forceinline__ vf2 gather_force(const MC_GLOBAL int* start, const MC
 // the separable circular Gaussian (x pass, then y pass, both in LDS) on the
 // tile plus a one-cell ring, and the central difference G = D s~ of the
 // tile, written as interleaved float2.
+//
+// Binned mode deposits the neighbourhood's nodes into a padded window (three
+// spare cells per side, see the window note with tile_spread_vec) as exact
+// integer products of quantised weights, so the sums are order-independent
+// and the inner loop is two 24-bit multiplies and an LDS add per cell.
+// Dynamic LDS: [window: filter_window_bytes(max radius) | list / density].
 // ---------------------------------------------------------------------------
 constexpr int kRing = kTile + 2;                    // tile plus the one-cell ring
 constexpr int kRegion = kRing + 2 * kMaxRadius;     // largest density region side
 
-__global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, Tables T) {
-  // LDS phases share one buffer: [A | B] with A = density (int64) then the x
-  // pass and the filtered ring, B = compacted records then the density as float
-  constexpr int kA = kRegion * kRegion * 8;
-  constexpr int kB = kListCap * 16;
-  __shared__ __align__(16) unsigned char smem[kA + kB];
-  __shared__ float s_tap[kMaxRadius + 1];
-  __shared__ int s_count;
+static __host__ __device__ constexpr int filter_window_bytes(int max_radius) {
+  return (kRing + 2 * max_radius + 8) * (kRing + 2 * max_radius + 8) * 8;
+}
+static __host__ __device__ constexpr int filter_list_bytes(int max_radius) {
+  return (kRing + 2 * max_radius) * (kRing + 2 * max_radius) * 4 > kListBytes
+             ? (kRing + 2 * max_radius) * (kRing + 2 * max_radius) * 4
+             : kListBytes;
+}
+static_assert(filter_window_bytes(1) >= (kRegion * kRing + kRing * kRing) * 4, "passes must fit the window");
+
+// q = k / d for 0 <= k < 2^16 and 0 < d <= 64: (k + 1/2) / d is at least
+// 1/(2d) away from an integer, far beyond the FP32 rounding of the product.
+static __device__ __forceinline__ int div_small(int k, float inv_d) {
+  return (int)(((float)k + 0.5f) * inv_d);
+}
+
+__global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ BinSet s_bs;
-  long long* s_reg = (long long*)smem;
-  vi4* s_list = (vi4*)(smem + kA);
-  float* s_regf = (float*)(smem + kA);
+  unsigned long long* s_win = (unsigned long long*)smem;
+  vi4* s_list = (vi4*)(smem + window_bytes);
+  float* s_regf = (float*)(smem + window_bytes);
   float* s_mid = (float*)smem;
-  float* s_st = (float*)smem + kRegion * kRing;
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     if (w.ctl_src->remaining <= 0) continue;
@@ -440,90 +463,89 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
     const int x0 = (tl.y % w.ntx) * kTile;
     const int y0 = (tl.y / w.ntx) * kTile;
     const int reg = kRing + 2 * R;
+    const float inv_reg = 1.0f / (float)reg;
     const int xo = x0 - R - 1, yo = y0 - R - 1;   // region origin (unwrapped)
-    if (tid <= R) s_tap[tid] = w.gtap[tid];
+    float* s_st = s_mid + reg * kRing;
     if (mode == kBinned) {
-      for (int k = tid; k < reg * reg; k += 256) s_reg[k] = 0;
-      // nodes whose support meets the region have home cells in
-      // [origin - 2, origin + reg] on each axis
+      const int S = reg + 8;                      // window side; window origin (xo - 3, yo - 3)
+      for (int k = tid; k < S * S; k += 256) s_win[k] = 0;
       {
         int txs[4], tys[4];
         const int ntxs = tiles_covering(xo - 2, xo + reg, nx, w.ntx, txs);
         const int ntys = tiles_covering(yo - 2, yo + reg, ny, w.nty, tys);
         make_binset(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys, &s_bs);
       }
-      const bool alias = reg > nx || reg > ny;    // region wraps onto itself (small grids)
-      for_bin_records(
-          glbv<const vi4>(w.bin_rec), s_bs, s_list, &s_count,
+      const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
+      const int keep_x = reg + 6 <= nx ? reg + 2 : nx;
+      const int keep_y = reg + 6 <= ny ? reg + 2 : ny;
+      for_bin_records<4>(
+          glbv<const vi4>(w.bin_rec), s_bs, s_list,
           [&](const vi4& r) {
-            // home cells lie in [0, n) and the origin in [-R-1, n), so one
-            // wrap suffices (the offset lies in [-n, 2n))
-            const int dx = wrap_near((r.x & 0xffff) - 1 - xo, nx);
-            const int dy = wrap_near((r.x >> 16) - 1 - yo, ny);
-            return !((dx >= reg && dx + 3 < nx) || (dy >= reg && dy + 3 < ny));
+            const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
+            const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
+            return dx <= keep_x && dy <= keep_y;
           },
           [&](const vi4& r) {
-            const int dx = wrap_near((r.x & 0xffff) - 1 - xo, nx);
-            const int dy = wrap_near((r.x >> 16) - 1 - yo, ny);
-            float wx[4], wy[4];
-            peskin4(__int_as_float(r.y), wx);
-            peskin4(__int_as_float(r.z), wy);
-            if (!alias) {
+            const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
+            const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
+            unsigned qx[4], qy[4];
+            peskin4_quant(__int_as_float(r.y), qx);
+            peskin4_quant(__int_as_float(r.z), qy);
+            unsigned long long* p = s_win + dy * S + dx;
 #pragma unroll
-              for (int b = 0; b < 4; ++b) {
-                int ly = dy + b;
-                ly = ly >= ny ? ly - ny : ly;
-                if (ly >= reg) continue;
+            for (int b = 0; b < 4; ++b)
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                  int lx = dx + a;
-                  lx = lx >= nx ? lx - nx : lx;
-                  if (lx < reg) lds_fix_add(&s_reg[ly * reg + lx], wx[a] * wy[b]);
-                }
-              }
-            } else {
-              for (int b = 0; b < 4; ++b) {
-                int ly = dy + b;
-                ly = ly >= ny ? ly - ny : ly;
-                for (; ly < reg; ly += ny) {
-                  for (int a = 0; a < 4; ++a) {
-                    int lx = dx + a;
-                    lx = lx >= nx ? lx - nx : lx;
-                    for (; lx < reg; lx += nx) lds_fix_add(&s_reg[ly * reg + lx], wx[a] * wy[b]);
-                  }
-                }
-              }
-            }
+              for (int a = 0; a < 4; ++a) atomicAdd(p + b * S + a, weight_product(qx[a], qy[b]));
           });
-      for (int k = tid; k < reg * reg; k += 256) s_regf[k] = fix_to_float(s_reg[k]);
+      // (the list area is free again after the barrier that ends for_bin_records)
+      const bool single = reg + 6 <= nx && reg + 6 <= ny;
+      for (int k = tid; k < reg * reg; k += 256) {
+        const int r = div_small(k, inv_reg), c = k - r * reg;
+        unsigned long long v;
+        if (single) {
+          v = s_win[(r + 3) * S + c + 3];
+        } else {
+          v = 0;
+          for (int cy = first_image(r, ny); cy < S; cy += ny)
+            for (int cx = first_image(c, nx); cx < S; cx += nx) v += s_win[cy * S + cx];
+        }
+        s_regf[k] = density_to_float(v);
+      }
     } else if (mode == kSorted) {
       const MC_GLOBAL int* start = glb(w.start);
       const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
       for (int k = tid; k < reg * reg; k += 256) {
-        const int r = k / reg, c = k - (k / reg) * reg;
+        const int r = div_small(k, inv_reg), c = k - r * reg;
         s_regf[k] = gather_density(start, rec, nx, ny, wrap_index(xo + c, nx), wrap_index(yo + r, ny));
       }
     } else {
       const MC_GLOBAL float* sd = glb(w.s);
       for (int k = tid; k < reg * reg; k += 256) {
-        const int r = k / reg, c = k - (k / reg) * reg;
+        const int r = div_small(k, inv_reg), c = k - r * reg;
         s_regf[k] = sd[(size_t)wrap_index(yo + r, ny) * nx + wrap_index(xo + c, nx)];
       }
     }
+    float g[kMaxRadius + 1];
+#pragma unroll
+    for (int m = 0; m <= kMaxRadius; ++m) g[m] = w.gtap[m];
     __syncthreads();
     for (int k = tid; k < reg * kRing; k += 256) {
       const int r = k / kRing, c = k - (k / kRing) * kRing;
       const float* row = s_regf + r * reg + c + R;
-      float acc = s_tap[0] * row[0];
-      for (int m = 1; m <= R; ++m) acc += s_tap[m] * (row[-m] + row[m]);
+      float acc = g[0] * row[0];
+#pragma unroll
+      for (int m = 1; m <= kMaxRadius; ++m)
+        if (m <= R) acc += g[m] * (row[-m] + row[m]);
       s_mid[r * kRing + c] = acc;
     }
     __syncthreads();
     for (int k = tid; k < kRing * kRing; k += 256) {
       const int r = k / kRing, c = k - (k / kRing) * kRing;
       const float* col = s_mid + (r + R) * kRing + c;
-      float acc = s_tap[0] * col[0];
-      for (int m = 1; m <= R; ++m) acc += s_tap[m] * (col[-m * kRing] + col[m * kRing]);
+      float acc = g[0] * col[0];
+#pragma unroll
+      for (int m = 1; m <= kMaxRadius; ++m)
+        if (m <= R) acc += g[m] * (col[-m * kRing] + col[m * kRing]);
       s_st[k] = acc;
     }
     __syncthreads();
@@ -533,8 +555,8 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
       const int gx = x0 + c, gy = y0 + r;
       if (gx < nx && gy < ny) {
         const float* p = s_st + (r + 1) * kRing + (c + 1);
-        const vf2 g = {0.5f * (p[1] - p[-1]), 0.5f * (p[kRing] - p[-kRing])};
-        grad[(size_t)gy * nx + gx] = g;
+        const vf2 gr = {0.5f * (p[1] - p[-1]), 0.5f * (p[kRing] - p[-kRing])};
+        grad[(size_t)gy * nx + gx] = gr;
       }
     }
     __syncthreads();
@@ -614,14 +636,14 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
 // tile is written once.  Direct mode accumulates in k_repulse instead.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, Tables T) {
-  __shared__ long long s_fx[kTile * kTile];      // 64-bit fixed point
-  __shared__ long long s_fy[kTile * kTile];
-  __shared__ vi4 s_list[kListCap];
-  __shared__ int s_count;
+  __shared__ long long s_fx[kSpreadCells];      // 64-bit fixed point, padded window
+  __shared__ long long s_fy[kSpreadCells];
+  __shared__ vi4 s_list[4 * kWaveList];
   __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     if (w.mode == kDirect || w.ctl_src->remaining <= 0) continue;
@@ -631,12 +653,12 @@ __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, 
     const int y0 = (tl.y / w.ntx) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
     if (mode == kBinned) {
-      for (int k = tid; k < kTile * kTile; k += 256) {
+      for (int k = tid; k < kSpreadCells; k += 256) {
         s_fx[k] = 0;
         s_fy[k] = 0;
       }
       __syncthreads();
-      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, &s_count, &s_bs);
+      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, &s_bs);
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
@@ -647,8 +669,8 @@ __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, 
       if (lx >= tw || ly >= th) continue;
       vf2 F;
       if (mode == kBinned) {
-        F.x = fix_to_float(s_fx[k]);
-        F.y = fix_to_float(s_fy[k]);
+        F.x = fix_to_float(spread_cell(s_fx, lx, ly, nx, ny));
+        F.y = fix_to_float(spread_cell(s_fy, lx, ly, nx, ny));
       } else {
         F = gather_force(start, rec, nx, ny, x0 + lx, y0 + ly);
       }
@@ -844,7 +866,8 @@ __global__ __launch_bounds__(256) void k_repulse_tile(const WorldDev* __restrict
   __shared__ float s_gx[kStage * kStage];
   __shared__ float s_gy[kStage * kStage];
   const int nt = *T.n_tiles;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
@@ -888,7 +911,8 @@ __global__ __launch_bounds__(256) void k_integrate_tile(const WorldDev* __restri
   __shared__ float s_ux[kStage * kStage];
   __shared__ float s_uy[kStage * kStage];
   const int nt = *T.n_tiles;
-  for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
@@ -980,7 +1004,8 @@ void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t 
 }
 
 void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  k_filter<<<G.tile_blocks, 256, 0, s>>>(W, T);
+  const int wb = filter_window_bytes(G.max_radius);
+  k_filter<<<G.tile_blocks, 256, wb + filter_list_bytes(G.max_radius), s>>>(W, T, wb);
 }
 
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {

@@ -361,6 +361,13 @@ struct Engine {
     for (const auto& sl : slots)
       if (sl.used && mode_of(sl.p) != mc::kBinned) any_node = true;
     more = more || (any_node && !grid.any_node);
+    int max_r = 1;                          // the filter's LDS window is sized for this radius
+    for (const auto& sl : slots)
+      if (sl.used) max_r = std::max(max_r, sl.p.repulse_radius);
+    if (max_r > grid.max_radius) {
+      grid.max_radius = max_r;
+      more = true;
+    }
     grid.any_sorted |= any_sorted ? 1 : 0;
     grid.any_binned |= any_binned ? 1 : 0;
     grid.any_node |= any_node ? 1 : 0;
