@@ -31,10 +31,37 @@ sys.path.insert(0, ROOT)
 from paper_2607_02954_amd import sim, workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-FLUID_BYTES_PER_CELL = 88     # populations read + write (72), force read (8), velocity write (8)
+# dominant kernel: the fluid update k_lbm, which per launch must move the
+# populations (read + write, 72 B/cell), the grid force (read, 8 B/cell) and
+# the velocity (write, 8 B/cell)
+FLUID_BYTES_PER_CELL = 88
 STEP_BYTES_PER_CELL = 120     # whole-step algorithmic bytes per cell
 STEP_BYTES_PER_NODE = 24      # whole-step algorithmic bytes per node
-KERNELS = ["elastic", "bin_or_sort", "filter", "repulse", "fluid", "integrate"]
+KERNELS = ["elastic", "bin_or_sort", "filter", "repulse_spread", "fluid", "integrate"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lbm_scaling_2048.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_02954_amd", "csrc", n)
+                  for n in ("kernels.hip", "device_util.h", "engine.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    return d["bytes_per_launch"]
 
 
 def log(msg):
@@ -262,7 +289,8 @@ def main():
     # live per-kernel timing (HIP events on the world's stream), same state
     kms = W.profile(args.warmup + args.steps, args.profile_steps)
     fluid_ms = kms[4]
-    fluid_gbs = FLUID_BYTES_PER_CELL * ncell / (fluid_ms * 1e-3) / 1e9
+    fluid_bytes = FLUID_BYTES_PER_CELL * ncell
+    fluid_gbs = fluid_bytes / (fluid_ms * 1e-3) / 1e9
     step_bytes = STEP_BYTES_PER_CELL * ncell + STEP_BYTES_PER_NODE * N
     W.close()
     del W
@@ -303,14 +331,14 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_lbm (D2Q9 TRT fluid update)",
+            "kernel": "k_lbm (D2Q9 TRT fluid update with Guo forcing)",
             "achieved": fluid_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": fluid_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel_ms": fluid_ms,
-            "bytes_per_launch": FLUID_BYTES_PER_CELL * ncell,
+            "bytes_per_launch": fluid_bytes,
         },
         "step_roofline": {
             "algorithmic_bytes_per_step": step_bytes,

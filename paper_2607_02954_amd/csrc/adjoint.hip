@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__
     }
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
-    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_bs);
+    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_bs, spread_fetch(w, x0, y0, tw, th));
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < kTile * kTile; k += 256) {

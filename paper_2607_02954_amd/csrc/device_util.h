@@ -95,17 +95,23 @@ static __device__ __forceinline__ void edge_direction(float t, float t0, float c
 static __constant__ int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static __constant__ int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-// Distinct tiles (of kTile cells) holding the cells lo..hi of a periodic
-// axis of n cells split into ntile tiles.  The ranges used here are at most
-// 53 cells wide, so they touch at most 4 tiles.
-static __device__ __forceinline__ int tiles_covering(int lo, int hi, int n, int ntile, int t[4]) {
+// Bin (home tile) of a wrapped home cell (bx, by) of a world with ntx tiles
+// per row, and the bin at tile column sx, row sy.
+static __device__ __forceinline__ int bin_of(int bx, int by, int ntx) { return (by >> 5) * ntx + (bx >> 5); }
+static __device__ __forceinline__ int bin_at(int sx, int sy, int ntx) { return sy * ntx + sx; }
+
+// Distinct tile columns holding the cells lo..hi of a periodic axis of n
+// cells.  The ranges used here are at most 53 cells wide, so they touch at
+// most 4 columns (with the partial last tile of an axis when they wrap).
+constexpr int kMaxBinCols = 4;
+static __device__ __forceinline__ int bins_covering(int lo, int hi, int n, int t[kMaxBinCols]) {
   int cnt = 0;
-  if (hi - lo + 1 >= n) {                       // whole axis (then ntile <= 2)
-    for (int k = 0; k < ntile && cnt < 4; ++k) t[cnt++] = k;
+  if (hi - lo + 1 >= n) {                       // whole axis (then n <= 53: at most 2 columns)
+    for (int k = 0; k * kTile < n && cnt < kMaxBinCols; ++k) t[cnt++] = k;
     return cnt;
   }
   int c = lo;
-  while (c <= hi && cnt < 4) {
+  while (c <= hi && cnt < kMaxBinCols) {
     const int cc = wrap_index(c, n);
     const int tt = cc / kTile;
     bool seen = false;
@@ -145,7 +151,6 @@ static __device__ __forceinline__ float fix_to_float(long long v) {
 // the exact product of two such integers, a multiple of 2^-46 formed by two
 // 24-bit multiplies, and sums of them are exact in 64 bits.
 constexpr float kWeightQ = 8388608.0f;                   // 2^23
-constexpr double kDensityInv = 1.4210854715202004e-14;   // 2^-46
 static __device__ __forceinline__ void peskin4_quant(float f, unsigned q[4]) {
   float w[4];
   peskin4(f, w);
@@ -155,8 +160,10 @@ static __device__ __forceinline__ void peskin4_quant(float f, unsigned q[4]) {
 static __device__ __forceinline__ unsigned long long weight_product(unsigned a, unsigned b) {
   return (unsigned long long)(a & 0xffffffu) * (b & 0xffffffu);   // v_mul_u32_u24 + v_mul_hi_u32_u24
 }
+// The high word converts exactly (densities stay far below 2^14), the low
+// word with one FP32 rounding (an absolute error below 2^-38), then one fma.
 static __device__ __forceinline__ float density_to_float(unsigned long long v) {
-  return (float)(((double)(unsigned)(v >> 32) * 4294967296.0 + (double)(unsigned)v) * kDensityInv);
+  return fmaf((float)(unsigned)(v >> 32), 6.103515625e-05f, (float)(unsigned)v * 1.4210854715202004e-14f);
 }
 
 // Work-item order of the tile kernels.  The hardware hands workgroups to the
@@ -202,10 +209,11 @@ static __device__ __forceinline__ int agg_atomic_inc(MC_GLOBAL int* counters, in
   return slot;
 }
 
-// Block-wide exclusive scan of one int per thread (256 threads), wave
-// shuffles plus one LDS exchange.  Returns the exclusive prefix; *total gets
-// the block sum.  All threads must call it.
-static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* total) {
+// Block-wide exclusive scan of one int per thread (NT threads), wave
+// shuffles plus one LDS exchange (s_wave holds NT/64 ints).  Returns the
+// exclusive prefix; *total gets the block sum.  All threads must call it.
+template <int NT>
+static __device__ __forceinline__ int block_scan(int v, int* s_wave, int* total) {
   const int lane = __lane_id();
   const int wid = threadIdx.x >> 6;
   int x = v;
@@ -218,7 +226,7 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
   __syncthreads();
   int before = 0, all = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NT / 64; ++k) {
     const int sw = s_wave[k];
     before += (k < wid) ? sw : 0;
     all += sw;
@@ -226,6 +234,9 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
   __syncthreads();
   *total = all;
   return before + x - v;
+}
+static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* total) {
+  return block_scan<256>(v, s_wave, total);
 }
 
 
@@ -242,8 +253,8 @@ constexpr int kListBytes = 4 * kWaveList * 16;
 
 struct BinSet {
   int n;
-  int start[16];
-  int pre[17];
+  int start[kMaxBinCols * kMaxBinCols];
+  int pre[kMaxBinCols * kMaxBinCols + 1];
 };
 
 static __device__ __forceinline__ void wave_sync() {
@@ -251,24 +262,48 @@ static __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Build the bin set of the tiles tx[ntx] x ty[nty] in LDS: one thread per
-// bin loads its range (independent loads, no chain), then a short prefix.
-// All threads call it with the same tile lists.
-static __device__ __forceinline__ void make_binset(const MC_GLOBAL int* bstart, int tiles_per_row, const int* tx,
-                                                   int ntx, const int* ty, int nty, BinSet* bs) {
-  const int n = ntx * nty;
+// A bin set in flight: thread i < n holds the first record and the length of
+// bin i.  Fetching it (the bin ranges of bin columns tx[ntx] x rows ty[nty])
+// only issues loads, so a kernel can fetch the next tile's set while it works
+// on the current tile; committing writes it to LDS with its prefix (one
+// wavefront scan) and synchronises the block.
+struct BinFetch {
+  int n;
+  int b0, len;
+};
+
+static __device__ __forceinline__ BinFetch binset_fetch(const MC_GLOBAL int* bstart, int tiles_per_row, const int* tx,
+                                                        int ntx, const int* ty, int nty) {
+  BinFetch f;
+  f.n = ntx * nty;
+  f.b0 = 0;
+  f.len = 0;
   const int i = threadIdx.x;
-  if (i < n) {
-    const int t = ty[i / ntx] * tiles_per_row + tx[i - (i / ntx) * ntx];
-    const int b0 = bstart[t];
-    bs->start[i] = b0;
-    bs->pre[i + 1] = bstart[t + 1] - b0;      // length, turned into a prefix below
+  if (i < f.n) {
+    const int t = bin_at(tx[i - (i / ntx) * ntx], ty[i / ntx], tiles_per_row);
+    f.b0 = bstart[t];
+    f.len = bstart[t + 1] - f.b0;
   }
-  __syncthreads();
-  if (i == 0) {
-    bs->n = n;
-    bs->pre[0] = 0;
-    for (int k = 1; k <= n; ++k) bs->pre[k] += bs->pre[k - 1];
+  return f;
+}
+
+static __device__ __forceinline__ void binset_commit(const BinFetch& f, BinSet* bs) {
+  const int i = threadIdx.x;
+  if (i < 64) {                                // the set has at most 16 bins: wavefront 0
+    int x = i < f.n ? f.len : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (i >= off) x += y;
+    }
+    if (i < f.n) {
+      bs->start[i] = f.b0;
+      bs->pre[i + 1] = x;
+    }
+    if (i == 0) {
+      bs->n = f.n;
+      bs->pre[0] = 0;
+    }
   }
   __syncthreads();
 }
@@ -348,16 +383,19 @@ static __device__ __forceinline__ int first_image(int i, int n) {
 constexpr int kSpreadSide = kTile + 8;
 constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
 
+// The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th].
+static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x0, int y0, int tw, int th) {
+  int txs[kMaxBinCols], tys[kMaxBinCols];
+  const int ntxs = bins_covering(x0 - 2, x0 + tw, w.nx, txs);
+  const int ntys = bins_covering(y0 - 2, y0 + th, w.ny, tys);
+  return binset_fetch(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys);
+}
+
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
-                                       long long* s_y, vi4* s_list, BinSet* s_bs) {
+                                       long long* s_y, vi4* s_list, BinSet* s_bs, const BinFetch& bins) {
   const int nx = w.nx, ny = w.ny, N = w.n_part;
-  {
-    int txs[4], tys[4];
-    const int ntxs = tiles_covering(x0 - 2, x0 + tw, nx, w.ntx, txs);
-    const int ntys = tiles_covering(y0 - 2, y0 + th, ny, w.nty, tys);
-    make_binset(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys, s_bs);
-  }
+  binset_commit(bins, s_bs);
   const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
   const int keep_x = tw + 6 <= nx ? tw + 2 : nx;     // largest kept home offset
   const int keep_y = th + 6 <= ny ? th + 2 : ny;

@@ -43,6 +43,11 @@ enum TransferMode : int {
 };
 constexpr int kMaxFilament = 1024;   // longest filament a node pack can hold
 
+// Sticky per-world flag bits.
+constexpr unsigned kFlagUnstable = 1u;   // NaN or |u| > u_max
+constexpr unsigned kFlagBins = 2u;       // a node found its tile bin full (positions changed
+                                         // without a bin pre-pass); the record was dropped
+
 // Per-world control word, double-buffered by step parity: kernels of a step
 // read ctl_src; the fluid kernel writes the next step's values to ctl_dst.
 struct Ctl {
@@ -71,7 +76,7 @@ struct WorldDev {
   float2* Fg;                           // [ny][nx] grid force
   float* fel;                           // node force [2][N] (elastic, then total)
   const Ctl* ctl_src; Ctl* ctl_dst;
-  unsigned* flags;                      // sticky: bit 0 = NaN or |u| > u_max
+  unsigned* flags;                      // sticky: kFlagUnstable, kFlagBins
   // deterministic sorted-segment transfer (SIM_SPLAT_SORTED)
   int* key;                             // [N] home cell of each node
   int* rank;                            // [N] arrival rank within its home cell
@@ -84,6 +89,8 @@ struct WorldDev {
   int* bin_cnt;                         // [ntx*nty] nodes per tile (zeroed after use)
   int* bin_fill;                        // [ntx*nty] fill cursors (zeroed after use)
   int* bin_start;                       // [ntx*nty + 1] exclusive prefix of bin_cnt
+  int* bin_start_next;                  // where the scan after integrate puts the next step's
+                                        // starts (bin_start itself, except on the adjoint tape)
   int4* bin_rec;                        // [N] record: (x | y << 16 home cell, frac x, frac y, node)
 };
 
@@ -130,6 +137,7 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
 // Forward step launchers (kernels.hip).  `W` points at a device array of
 // world descriptors.
 void launch_elastic(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+void launch_bin_prepass(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);

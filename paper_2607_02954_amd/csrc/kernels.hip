@@ -154,8 +154,20 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
       fel[N + gi] = w.k_el * s_dy[li];
     }
     if (mode == kBinned) {
-      const int tile = (by / kTile) * w.ntx + bx / kTile;
-      agg_atomic_inc(glb(w.bin_cnt), tile, active);
+      // this node's record in its home-tile bin (bins sized by the counts
+      // of these positions: the previous step's integrate or the pre-pass)
+      const int tile = bin_of(bx, by, w.ntx);
+      const int slot = agg_atomic_inc(glb(w.bin_fill), tile, active);
+      if (active) {
+        const MC_GLOBAL int* bstart = glb(w.bin_start);
+        const int e = bstart[tile] + slot;
+        if (e < bstart[tile + 1]) {
+          const vi4 rec = {bx | (by << 16), __float_as_int(fx), __float_as_int(fy), gi};
+          glbv<vi4>(w.bin_rec)[e] = rec;
+        } else {
+          atomicOr((unsigned*)glb(w.flags), kFlagBins);
+        }
+      }
     } else if (active && mode == kSorted) {
       const int key = by * nx + bx;
       glb(w.key)[gi] = key;
@@ -182,65 +194,85 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
 // Binned transfer: per-world exclusive scan of tile counts, then every node
 // writes a record (home cell, fractions, index) into each bin it belongs to.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bin_scan(const WorldDev* __restrict__ W, Tables T) {
-  constexpr int kPer = 16;                      // consecutive tiles per thread, loaded together
-  __shared__ int s_wave[4];
+// next: write the starts for the next step's bins (bin_start_next; after
+// integrate) rather than for the current positions (bin_start; pre-pass).
+__global__ __launch_bounds__(1024) void k_bin_scan(const WorldDev* __restrict__ W, Tables T, int next) {
+  // every wavefront scans a segment of 1024 consecutive bins (16 coalesced
+  // rows of 64, one shuffle scan per row, no barrier), then one exchange of
+  // the 16 segment totals; a round covers 16384 bins
+  constexpr int kRows = 16;
+  __shared__ int s_tot[16];
   const int nw = *T.n_worlds;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int it = blockIdx.x; it < nw; it += gridDim.x) {
     const WorldDev& w = W[T.worlds[it].x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
     MC_GLOBAL int* cnt = glb(w.bin_cnt);
     MC_GLOBAL int* fill = glb(w.bin_fill);
-    MC_GLOBAL int* start = glb(w.bin_start);
-    const int nt = w.ntx * w.nty;
+    MC_GLOBAL int* start = glb(next ? w.bin_start_next : w.bin_start);
+    const int nt = w.ntx * w.nty;               // bins (one per tile)
     int carry = 0;
-    for (int c0 = 0; c0 < nt; c0 += 256 * kPer) {
-      const int b0 = c0 + (int)threadIdx.x * kPer;
-      int v[kPer];
-      int loc = 0;
+    for (int c0 = 0; c0 < nt; c0 += 1024 * kRows) {
+      const int seg = c0 + wv * 64 * kRows;
+      int v[kRows];
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) v[k] = b0 + k < nt ? cnt[b0 + k] : 0;
+      for (int k = 0; k < kRows; ++k) {
+        const int i = seg + 64 * k + lane;
+        v[k] = i < nt ? cnt[i] : 0;
+      }
+      int run = 0;
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) loc += v[k];
-      int total;
-      int run = carry + block_scan256(loc, s_wave, &total);
+      for (int k = 0; k < kRows; ++k) {
+        int x = v[k];
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        if (b0 + k < nt) {
-          start[b0 + k] = run;
-          cnt[b0 + k] = 0;
-          fill[b0 + k] = 0;
-          run += v[k];
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(x, off);
+          if (lane >= off) x += y;
+        }
+        const int ex = run + x - v[k];
+        run += __shfl(x, 63);
+        v[k] = ex;                              // exclusive prefix within the segment
+      }
+      if (lane == 0) s_tot[wv] = run;
+      __syncthreads();
+      int before = carry, all = 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int t = s_tot[j];
+        before += j < wv ? t : 0;
+        all += t;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const int i = seg + 64 * k + lane;
+        if (i < nt) {
+          start[i] = before + v[k];
+          cnt[i] = 0;
+          fill[i] = 0;
         }
       }
-      carry += total;
+      carry += all;
     }
-    if (threadIdx.x == 0) start[nt] = carry;
+    if (tid == 0) start[nt] = carry;
   }
 }
 
+// Pre-pass: tile-bin counts of the current positions (a rollout's first step
+// needs them; later steps get them from the previous step's integrate).
 template <int PACK>
-__global__ __launch_bounds__(PACK) void k_bin_fill(const WorldDev* __restrict__ W, Tables T) {
+__global__ __launch_bounds__(PACK) void k_bin_count(const WorldDev* __restrict__ W, Tables T) {
   const int npk = *T.n_packs;
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
-    const int N = w.n_part, nx = w.nx, ny = w.ny;
+    const int N = w.n_part;
     const int gi = pk.node_begin + threadIdx.x;
     const bool active = gi < pk.node_end;
     int tile = 0;
-    vi4 rec = {0, 0, 0, gi};
-    if (active) {
-      const int bx = wrap_index(glb(w.cell_in)[gi], nx);
-      const int by = wrap_index(glb(w.cell_in)[N + gi], ny);
-      tile = (by / kTile) * w.ntx + bx / kTile;
-      rec.x = bx | (by << 16);
-      rec.y = __float_as_int(glb(w.frac_in)[gi]);
-      rec.z = __float_as_int(glb(w.frac_in)[N + gi]);
-    }
-    const int slot = agg_atomic_inc(glb(w.bin_fill), tile, active);
-    if (active) glbv<vi4>(w.bin_rec)[glb(w.bin_start)[tile] + slot] = rec;
+    if (active) tile = bin_of(wrap_index(glb(w.cell_in)[gi], w.nx), wrap_index(glb(w.cell_in)[N + gi], w.ny), w.ntx);
+    agg_atomic_inc(glb(w.bin_cnt), tile, active);
   }
 }
 
@@ -444,6 +476,17 @@ static __device__ __forceinline__ int div_small(int k, float inv_d) {
   return (int)(((float)k + 0.5f) * inv_d);
 }
 
+// The bin set a filter tile reads: homes in [xo - 2, xo + reg] per axis
+// (xo = x0 - R - 1, reg = 34 + 2R), whose supports meet the density region.
+static __device__ __forceinline__ BinFetch filter_fetch(const WorldDev& w, int tile) {
+  const int R = w.radius, reg = kRing + 2 * R;
+  const int xo = (tile % w.ntx) * kTile - R - 1, yo = (tile / w.ntx) * kTile - R - 1;
+  int txs[kMaxBinCols], tys[kMaxBinCols];
+  const int ntxs = bins_covering(xo - 2, xo + reg, w.nx, txs);
+  const int ntys = bins_covering(yo - 2, yo + reg, w.ny, tys);
+  return binset_fetch(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys);
+}
+
 __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ BinSet s_bs;
@@ -469,12 +512,7 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
     if (mode == kBinned) {
       const int S = reg + 8;                      // window side; window origin (xo - 3, yo - 3)
       for (int k = tid; k < S * S; k += 256) s_win[k] = 0;
-      {
-        int txs[4], tys[4];
-        const int ntxs = tiles_covering(xo - 2, xo + reg, nx, w.ntx, txs);
-        const int ntys = tiles_covering(yo - 2, yo + reg, ny, w.nty, tys);
-        make_binset(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys, &s_bs);
-      }
+      binset_commit(filter_fetch(w, tl.y), &s_bs);
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 6 <= nx ? reg + 2 : nx;
       const int keep_y = reg + 6 <= ny ? reg + 2 : ny;
@@ -657,8 +695,8 @@ __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, 
         s_fx[k] = 0;
         s_fy[k] = 0;
       }
-      __syncthreads();
-      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, &s_bs);
+      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, &s_bs,
+                      spread_fetch(w, x0, y0, tw, th));
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
@@ -731,7 +769,7 @@ __global__ __launch_bounds__(256) void k_lbm(const WorldDev* __restrict__ W, Tab
     const float usq = ux * ux + uy * uy;
     const vf2 uv = {ux, uy};
     glbv<vf2>(w.u)[c] = uv;
-    if (!(usq <= w.u_max2)) atomicOr((unsigned*)glb(w.flags), 1u);
+    if (!(usq <= w.u_max2)) atomicOr((unsigned*)glb(w.flags), kFlagUnstable);
 
     // equilibrium minus weights: w_q (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2));
     // Guo source: w_q (3 (c - u) + 9 (c.u) c) . F; split into the parts
@@ -959,6 +997,8 @@ __global__ __launch_bounds__(256) void k_integrate_tile(const WorldDev* __restri
       cell_out[N + gi] = ncy;
       frac_out[gi] = nfx;
       frac_out[N + gi] = nfy;
+      // next step's tile-bin counts
+      agg_atomic_inc(glb(w.bin_cnt), bin_of(wrap_index(ncx, nx), wrap_index(ncy, ny), w.ntx), true);
     }
     __syncthreads();
   }
@@ -989,11 +1029,13 @@ void launch_elastic(const WorldDev* W, const Tables& T, const Grid& G, hipStream
   MC_PACK_DISPATCH(k_elastic, G, W, T);
 }
 
+void launch_bin_prepass(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
+  if (!G.any_binned) return;
+  MC_PACK_DISPATCH(k_bin_count, G, W, T);
+  k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 0);
+}
+
 void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  if (G.any_binned) {
-    k_bin_scan<<<G.world_blocks, 256, 0, s>>>(W, T);
-    MC_PACK_DISPATCH(k_bin_fill, G, W, T);
-  }
   if (G.any_sorted) {
     k_scan_reduce<<<G.scan_blocks, 256, 0, s>>>(W, T);
     k_scan_partials<<<G.world_blocks, 256, 0, s>>>(W, T);
@@ -1023,7 +1065,10 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_node) MC_PACK_DISPATCH(k_integrate, G, W, T);
-  if (G.any_binned) k_integrate_tile<<<G.tile_blocks, 256, 0, s>>>(W, T);
+  if (G.any_binned) {
+    k_integrate_tile<<<G.tile_blocks, 256, 0, s>>>(W, T);
+    k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
+  }
 }
 
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s) {

@@ -97,6 +97,7 @@ inline int mode_of(const sim_params& p) {
 }
 inline int tiles_x(const sim_params& p) { return (p.nx + mc::kTile - 1) / mc::kTile; }
 inline int tiles_y(const sim_params& p) { return (p.ny + mc::kTile - 1) / mc::kTile; }
+inline size_t n_bins(const sim_params& p) { return (size_t)tiles_x(p) * tiles_y(p); }
 
 void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) {
   const size_t ncell = (size_t)p.nx * p.ny;
@@ -117,7 +118,7 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
   } else if (mode == mc::kDirect) {
     b.s = c.take<float>(ncell);
   } else {
-    const size_t nt = (size_t)tiles_x(p) * tiles_y(p);
+    const size_t nt = n_bins(p);
     b.bin_cnt = c.take<int>(nt);
     b.bin_fill = c.take<int>(nt);
     b.bin_start = c.take<int>(nt + 1);
@@ -302,6 +303,7 @@ struct Engine {
     d.bin_cnt = s.b.bin_cnt;
     d.bin_fill = s.b.bin_fill;
     d.bin_start = s.b.bin_start;
+    d.bin_start_next = s.b.bin_start;
     d.bin_rec = s.b.bin_rec;
     return d;
   }
@@ -450,6 +452,9 @@ struct Engine {
   // tail step is launched directly with descriptor set A.
   sim_status run_steps(int n) {
     if (n <= 0) return SIM_OK;
+    // tile-bin counts of the current positions for the first step (each
+    // step's integrate then counts for the next)
+    mc::launch_bin_prepass(desc[0], tab, grid, stream);
     if (n >= want_chunk && (!g_chunk || chunk_steps != want_chunk)) {
       if (g_chunk) hipGraphExecDestroy(g_chunk);
       g_chunk = nullptr;
@@ -639,7 +644,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   if (sl.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.s, ncell);
   if (sl.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.Fg, 2 * ncell);
   if (sl.b.bin_cnt) {
-    const size_t nt = (size_t)tiles_x(*p) * tiles_y(*p);
+    const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_fill, nt);
   }
@@ -719,6 +724,7 @@ sim_status sim_sync(sim_world* w) {
   HIPCHK(hipGetLastError());
   unsigned f = 0;
   HIPCHK(hipMemcpy(&f, e.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (f & mc::kFlagBins) return fail(SIM_E_STATE, "node positions changed without a tile-bin pre-pass");
   if (f) return fail(SIM_E_UNSTABLE, "world produced NaN or |u| > u_max");
   return SIM_OK;
 }
@@ -740,6 +746,7 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
   const mc::WorldDev* d = e.desc[0];
   switch (which) {
     case 0:
+      mc::launch_bin_prepass(d, e.tab, e.grid, e.stream);
       mc::launch_elastic(d, e.tab, e.grid, e.stream);
       mc::launch_sort(d, e.tab, e.grid, e.stream);
       break;
@@ -772,6 +779,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
   sim_status st = e.set_ctl(0, t0, n_steps);
   if (st) return st;
+  mc::launch_bin_prepass(e.desc[0], e.tab, e.grid, e.stream);
   for (int k = 0; k < n_steps; ++k) {
     const mc::WorldDev* d = e.desc[k & 1];
     hipEvent_t* E = ev.data() + (size_t)k * (kGroups + 1);
@@ -842,7 +850,7 @@ struct AdjLayout {
   std::vector<float*> g;       // m+1 slots of [9][ncell]
   std::vector<float2*> grad, Fg, u;   // m slots of [ncell]
   std::vector<float*> F;       // m slots of [2][N]
-  std::vector<int*> bstart;    // m slots of [nt+1]
+  std::vector<int*> bstart;    // m + 1 slots of [nt+1] (step j's bins; slot m is scratch)
   std::vector<int4*> brec;     // m slots of [N]
   int* bin_cnt = nullptr;
   int* bin_fill = nullptr;
@@ -860,7 +868,7 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
   L.m = m;
   L.N = std::max(n_part, 1);
   L.ncell = (size_t)p.nx * p.ny;
-  L.nt = (size_t)tiles_x(p) * tiles_y(p);
+  L.nt = n_bins(p);
   L.x_cell.resize(m + 1);
   L.x_frac.resize(m + 1);
   L.g.resize(m + 1);
@@ -873,7 +881,7 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
   L.Fg.resize(m);
   L.u.resize(m);
   L.F.resize(m);
-  L.bstart.resize(m);
+  L.bstart.resize(m + 1);
   L.brec.resize(m);
   for (int j = 0; j < m; ++j) {
     L.grad[j] = c.take<float2>(L.ncell);
@@ -883,6 +891,7 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
     L.bstart[j] = c.take<int>(L.nt + 1);
     L.brec[j] = c.take<int4>(L.N);
   }
+  L.bstart[m] = c.take<int>(L.nt + 1);
   L.bin_cnt = c.take<int>(L.nt);
   L.bin_fill = c.take<int>(L.nt);
   L.desc = c.take<mc::WorldDev>(m);
@@ -955,6 +964,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     d.bin_cnt = L.bin_cnt;
     d.bin_fill = L.bin_fill;
     d.bin_start = L.bstart[j];
+    d.bin_start_next = L.bstart[j + 1];
     d.bin_rec = L.brec[j];
     d.s = nullptr;
     hd[j] = d;
@@ -990,6 +1000,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     for (int j = 0; j < m; ++j) {
       sim_status r = e.set_ctl(0, t0 + k0 + j, 1);
       if (r) return r;
+      if (j == 0) mc::launch_bin_prepass(L.desc, e.tab, g, st);
       e.enqueue_step_with(L.desc + j, g, st);
     }
     HIPCHK(hipGetLastError());
@@ -1225,7 +1236,7 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
   if (s.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.b.s, ncell);
   if (s.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.b.Fg, 2 * ncell);
   if (s.b.bin_cnt) {
-    const size_t nt = (size_t)tiles_x(*p) * tiles_y(*p);
+    const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_fill, nt);
   }
@@ -1290,6 +1301,7 @@ sim_status sim_batch_retire(sim_batch* b, int32_t slot, const sim_arrays* out) {
   s = Slot();
   sim_status st = e.rebuild();
   if (st) return st;
+  if (fl & mc::kFlagBins) return fail(SIM_E_STATE, "world in slot %d: tile bins out of date", slot);
   if (fl) return fail(SIM_E_UNSTABLE, "world in slot %d produced NaN or |u| > u_max", slot);
   return SIM_OK;
 }
