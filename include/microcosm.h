@@ -155,8 +155,9 @@ sim_status sim_backward(sim_world *w, int64_t t0, int32_t n_steps, int32_t ckpt_
                         const void *ckpt, const float *g_pos, float *g_rest_angle, float *g_pos0,
                         void *adj_ws, size_t adj_ws_bytes);
 
-/* Wait for the world's stream; report asynchronous HIP errors and the sticky
- * Mach/NaN flag (SIM_E_UNSTABLE). */
+/* Wait for the world's stream; report asynchronous HIP errors, the sticky
+ * Mach/NaN flag (SIM_E_UNSTABLE), and SIM_E_STATE if a node found its tile
+ * bin full, which only happens when sub-steps are run out of order. */
 sim_status sim_sync(sim_world *w);
 /* Clear the sticky Mach/NaN flag (enqueued on the stream). */
 sim_status sim_clear_flags(sim_world *w);
@@ -170,7 +171,8 @@ const char *sim_last_error(void);
  * 3 fluid update, 4 gather + integrate), and expose the world's internal
  * per-step buffers (which: 0 deposit s [ny][nx], SIM_SPLAT_DIRECT only, else
  * NULL; 1 central difference of the filtered density [ny][nx][2]; 2 grid
- * force [ny][nx][2]; 3 node force [2][N]).  For parity tests. */
+ * force [ny][nx][2]; 3 node force [2][N]).  For parity tests.  The
+ * sub-steps of one step must be run in order, starting with 0. */
 sim_status sim_debug_substep(sim_world *w, int32_t which, int64_t t);
 sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
 
@@ -182,6 +184,14 @@ sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
  * 3 repulsion + spread, 4 fluid update, 5 gather + integrate.  The state advances exactly as with sim_rollout.
  * Synchronises the stream. */
 sim_status sim_profile_steps(sim_world *w, int64_t t0, int32_t n_steps, float *ms_out);
+
+/* Measurement hook: n_launches (even, >= 2) back-to-back launches of the
+ * fluid update alone on the world's stream, bracketed by one pair of HIP
+ * events; writes the mean device time per launch in milliseconds.  The
+ * populations advance n_launches lattice Boltzmann steps with the current
+ * grid force and end in the caller's buffer; u is overwritten.  Meant for a
+ * world that is about to be discarded.  Synchronises the stream. */
+sim_status sim_profile_fluid(sim_world *w, int32_t n_launches, float *ms_per_launch);
 
 /* ---- Batched worlds: many independent worlds of uneven size advanced by the
  * same kernels in one persistent, graph-captured launch per chunk of steps.

@@ -28,11 +28,11 @@ constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registe
 // ---------------------------------------------------------------------------
 // Node -> grid spreads of adjoint node vectors (u~ and G~), tile-binned.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__ W, Tables T, const float* v,
+__global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __restrict__ W, Tables T, const float* v,
                                                     float scale_is_rep, float2* out) {
   __shared__ long long s_x[kSpreadCells];
   __shared__ long long s_y[kSpreadCells];
-  __shared__ vi4 s_list[4 * kWaveList];
+  __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
   __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__
     const int x0 = (tl.y % w.ntx) * kTile;
     const int y0 = (tl.y / w.ntx) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
-    for (int k = threadIdx.x; k < kSpreadCells; k += 256) {
+    for (int k = threadIdx.x; k < kSpreadCells; k += kTileThreads) {
       s_x[k] = 0;
       s_y[k] = 0;
     }
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_adj_spread(const WorldDev* __restrict__
     tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_bs, spread_fetch(w, x0, y0, tw, th));
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
-    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+    for (int k = threadIdx.x; k < kTile * kTile; k += kTileThreads) {
       const int ly = k >> 5, lx = k & (kTile - 1);
       if (lx >= tw || ly >= th) continue;
       const vf2 val = {fix_to_float(spread_cell(s_x, lx, ly, nx, ny)), fix_to_float(spread_cell(s_y, lx, ly, nx, ny))};
@@ -516,10 +516,10 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
   } while (0)
 
 void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s) {
-  k_adj_spread<<<G.tile_blocks, 256, 0, s>>>(W, T, A.xbar_in, 0.f, A.ubar);
+  k_adj_spread<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T, A.xbar_in, 0.f, A.ubar);
   k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
   MC_ADJ_PACK(k_adj_force, G, W, T, A);
-  k_adj_spread<<<G.tile_blocks, 256, 0, s>>>(W, T, A.Fbar, 1.f, A.Gbar);
+  k_adj_spread<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T, A.Fbar, 1.f, A.Gbar);
   k_adj_filter<<<G.tile_blocks, 256, 0, s>>>(W, T, A);
   MC_ADJ_PACK(k_adj_pbd, G, W, T, A);
 }

@@ -249,7 +249,7 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 // partial one), and lanes holding irrelevant records never idle through it.
 // body(r) may only use per-lane work and LDS atomics.
 constexpr int kWaveList = 128;             // records per wavefront list
-constexpr int kListBytes = 4 * kWaveList * 16;
+constexpr int kListBytes = (kTileThreads / 64) * kWaveList * 16;
 
 struct BinSet {
   int n;
@@ -316,12 +316,12 @@ static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs
   vi4* wl = s_list + (threadIdx.x >> 6) * kWaveList;
   int cnt = 0;                                 // wavefront-uniform list length
   int b = 0;                                   // bin of this lane's next record
-  for (int base = 0; base < total; base += PER * 256) {
+  for (int base = 0; base < total; base += PER * kTileThreads) {
     vi4 r[PER];
     bool k[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {            // issue every load before any use
-      const int f = base + i * 256 + (int)threadIdx.x;
+      const int f = base + i * kTileThreads + (int)threadIdx.x;
       k[i] = f < total;
       if (k[i]) {
         while (f >= bs.pre[b + 1]) ++b;

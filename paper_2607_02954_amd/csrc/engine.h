@@ -32,6 +32,7 @@ __device__ __forceinline__ MC_GLOBAL V* glbv(T* p) {
 }
 
 constexpr int kTile = 32;            // square grid tile of the filter and spread kernels
+constexpr int kTileThreads = 256;    // threads per block of the tile kernels
 constexpr int kCellsPerItem = 256;   // contiguous cells per fluid work item
 constexpr int kMaxRadius = 8;        // largest Gaussian truncation radius
 

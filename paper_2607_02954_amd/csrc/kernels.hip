@@ -487,7 +487,7 @@ static __device__ __forceinline__ BinFetch filter_fetch(const WorldDev& w, int t
   return binset_fetch(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys);
 }
 
-__global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
+__global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ BinSet s_bs;
   unsigned long long* s_win = (unsigned long long*)smem;
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
     float* s_st = s_mid + reg * kRing;
     if (mode == kBinned) {
       const int S = reg + 8;                      // window side; window origin (xo - 3, yo - 3)
-      for (int k = tid; k < S * S; k += 256) s_win[k] = 0;
+      for (int k = tid; k < S * S; k += kTileThreads) s_win[k] = 0;
       binset_commit(filter_fetch(w, tl.y), &s_bs);
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 6 <= nx ? reg + 2 : nx;
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
           });
       // (the list area is free again after the barrier that ends for_bin_records)
       const bool single = reg + 6 <= nx && reg + 6 <= ny;
-      for (int k = tid; k < reg * reg; k += 256) {
+      for (int k = tid; k < reg * reg; k += kTileThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         unsigned long long v;
         if (single) {
@@ -552,13 +552,13 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
     } else if (mode == kSorted) {
       const MC_GLOBAL int* start = glb(w.start);
       const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
-      for (int k = tid; k < reg * reg; k += 256) {
+      for (int k = tid; k < reg * reg; k += kTileThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         s_regf[k] = gather_density(start, rec, nx, ny, wrap_index(xo + c, nx), wrap_index(yo + r, ny));
       }
     } else {
       const MC_GLOBAL float* sd = glb(w.s);
-      for (int k = tid; k < reg * reg; k += 256) {
+      for (int k = tid; k < reg * reg; k += kTileThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         s_regf[k] = sd[(size_t)wrap_index(yo + r, ny) * nx + wrap_index(xo + c, nx)];
       }
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
 #pragma unroll
     for (int m = 0; m <= kMaxRadius; ++m) g[m] = w.gtap[m];
     __syncthreads();
-    for (int k = tid; k < reg * kRing; k += 256) {
+    for (int k = tid; k < reg * kRing; k += kTileThreads) {
       const int r = k / kRing, c = k - (k / kRing) * kRing;
       const float* row = s_regf + r * reg + c + R;
       float acc = g[0] * row[0];
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
       s_mid[r * kRing + c] = acc;
     }
     __syncthreads();
-    for (int k = tid; k < kRing * kRing; k += 256) {
+    for (int k = tid; k < kRing * kRing; k += kTileThreads) {
       const int r = k / kRing, c = k - (k / kRing) * kRing;
       const float* col = s_mid + (r + R) * kRing + c;
       float acc = g[0] * col[0];
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(256) void k_filter(const WorldDev* __restrict__ W, 
     }
     __syncthreads();
     MC_GLOBAL vf2* grad = glbv<vf2>(w.grad);
-    for (int k = tid; k < kTile * kTile; k += 256) {
+    for (int k = tid; k < kTile * kTile; k += kTileThreads) {
       const int r = k >> 5, c = k & (kTile - 1);
       const int gx = x0 + c, gy = y0 + r;
       if (gx < nx && gy < ny) {
@@ -673,10 +673,10 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
 // or by fixed-order gathers over sorted segments (sorted); every cell of the
 // tile is written once.  Direct mode accumulates in k_repulse instead.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, Tables T) {
+__global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restrict__ W, Tables T) {
   __shared__ long long s_fx[kSpreadCells];      // 64-bit fixed point, padded window
   __shared__ long long s_fy[kSpreadCells];
-  __shared__ vi4 s_list[4 * kWaveList];
+  __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
   __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
@@ -691,7 +691,7 @@ __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, 
     const int y0 = (tl.y / w.ntx) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
     if (mode == kBinned) {
-      for (int k = tid; k < kSpreadCells; k += 256) {
+      for (int k = tid; k < kSpreadCells; k += kTileThreads) {
         s_fx[k] = 0;
         s_fy[k] = 0;
       }
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(256) void k_spread(const WorldDev* __restrict__ W, 
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
     const MC_GLOBAL int* start = glb(w.start);
     const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
-    for (int k = tid; k < kTile * kTile; k += 256) {
+    for (int k = tid; k < kTile * kTile; k += kTileThreads) {
       const int ly = k >> 5, lx = k & (kTile - 1);
       if (lx >= tw || ly >= th) continue;
       vf2 F;
@@ -880,11 +880,11 @@ constexpr int kStage = kTile + 3;
 
 __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, float* sx,
                                             float* sy) {
-  constexpr int kIt = (kStage * kStage + 255) / 256;
+  constexpr int kIt = (kStage * kStage + kTileThreads - 1) / kTileThreads;
   vf2 v[kIt];
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
-    const int k = (int)threadIdx.x + 256 * i;
+    const int k = (int)threadIdx.x + kTileThreads * i;
     if (k < kStage * kStage) {
       const int r = k / kStage, c = k - (k / kStage) * kStage;
       v[i] = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
@@ -892,7 +892,7 @@ __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int 
   }
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
-    const int k = (int)threadIdx.x + 256 * i;
+    const int k = (int)threadIdx.x + kTileThreads * i;
     if (k < kStage * kStage) {
       sx[k] = v[i].x;
       sy[k] = v[i].y;
@@ -900,7 +900,7 @@ __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int 
   }
 }
 
-__global__ __launch_bounds__(256) void k_repulse_tile(const WorldDev* __restrict__ W, Tables T) {
+__global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* __restrict__ W, Tables T) {
   __shared__ float s_gx[kStage * kStage];
   __shared__ float s_gy[kStage * kStage];
   const int nt = *T.n_tiles;
@@ -918,7 +918,7 @@ __global__ __launch_bounds__(256) void k_repulse_tile(const WorldDev* __restrict
     MC_GLOBAL float* fel = glb(w.fel);
     const float kr = w.k_rep;
     const int e1 = glb(w.bin_start)[tl.y + 1];
-    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += 256) {
+    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += kTileThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;   // home in the tile
       float wx[4], wy[4];
@@ -945,7 +945,7 @@ __global__ __launch_bounds__(256) void k_repulse_tile(const WorldDev* __restrict
   }
 }
 
-__global__ __launch_bounds__(256) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
+__global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
   __shared__ float s_ux[kStage * kStage];
   __shared__ float s_uy[kStage * kStage];
   const int nt = *T.n_tiles;
@@ -964,7 +964,7 @@ __global__ __launch_bounds__(256) void k_integrate_tile(const WorldDev* __restri
     MC_GLOBAL int* cell_out = glb(w.cell_out);
     MC_GLOBAL float* frac_out = glb(w.frac_out);
     const int e1 = glb(w.bin_start)[tl.y + 1];
-    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += 256) {
+    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += kTileThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
       const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);
@@ -1047,16 +1047,16 @@ void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t 
 
 void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   const int wb = filter_window_bytes(G.max_radius);
-  k_filter<<<G.tile_blocks, 256, wb + filter_list_bytes(G.max_radius), s>>>(W, T, wb);
+  k_filter<<<G.tile_blocks, kTileThreads, wb + filter_list_bytes(G.max_radius), s>>>(W, T, wb);
 }
 
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_node) MC_PACK_DISPATCH(k_repulse, G, W, T);
-  if (G.any_binned) k_repulse_tile<<<G.tile_blocks, 256, 0, s>>>(W, T);
+  if (G.any_binned) k_repulse_tile<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
 }
 
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  k_spread<<<G.tile_blocks, 256, 0, s>>>(W, T);
+  k_spread<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
 }
 
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
@@ -1066,7 +1066,7 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_node) MC_PACK_DISPATCH(k_integrate, G, W, T);
   if (G.any_binned) {
-    k_integrate_tile<<<G.tile_blocks, 256, 0, s>>>(W, T);
+    k_integrate_tile<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
     k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
   }
 }

@@ -744,25 +744,26 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
   sim_status st;
   if ((st = e.set_ctl(0, t, 1))) return st;
   const mc::WorldDev* d = e.desc[0];
+  const mc::Grid& g = e.grid;
   switch (which) {
     case 0:
-      mc::launch_bin_prepass(d, e.tab, e.grid, e.stream);
-      mc::launch_elastic(d, e.tab, e.grid, e.stream);
-      mc::launch_sort(d, e.tab, e.grid, e.stream);
+      mc::launch_bin_prepass(d, e.tab, g, e.stream);
+      mc::launch_elastic(d, e.tab, g, e.stream);
+      mc::launch_sort(d, e.tab, g, e.stream);
       break;
-    case 1: mc::launch_filter(d, e.tab, e.grid, e.stream); break;
+    case 1: mc::launch_filter(d, e.tab, g, e.stream); break;
     case 2:
-      mc::launch_repulse(d, e.tab, e.grid, e.stream);
-      mc::launch_spread(d, e.tab, e.grid, e.stream);
+      mc::launch_repulse(d, e.tab, g, e.stream);
+      mc::launch_spread(d, e.tab, g, e.stream);
       break;
     case 3: {
-      mc::launch_lbm(d, e.tab, e.grid, e.stream);
+      mc::launch_lbm(d, e.tab, g, e.stream);
       Slot& s = e.slots[0];
       const size_t ncell = (size_t)s.p.nx * s.p.ny;
       HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
       break;
     }
-    case 4: mc::launch_integrate(d, e.tab, e.grid, e.stream); break;
+    case 4: mc::launch_integrate(d, e.tab, g, e.stream); break;
     default: return fail(SIM_E_INVALID, "unknown sub-step %d", which);
   }
   HIPCHK(hipGetLastError());
@@ -815,6 +816,28 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     ms_out[g] = (float)(tot / n_steps);
   }
   for (auto& x : ev) hipEventDestroy(x);
+  return SIM_OK;
+}
+
+sim_status sim_profile_fluid(sim_world* w, int32_t n_launches, float* ms_per_launch) {
+  if (!w || !ms_per_launch) return fail(SIM_E_INVALID, "NULL argument");
+  if (n_launches < 2 || (n_launches & 1)) return fail(SIM_E_INVALID, "n_launches must be even and >= 2");
+  Engine& e = w->eng;
+  sim_status st = e.set_ctl(0, 0, n_launches);
+  if (st) return st;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  HIPCHK(hipEventRecord(a, e.stream));
+  for (int k = 0; k < n_launches; ++k) mc::launch_lbm(e.desc[k & 1], e.tab, e.grid, e.stream);
+  HIPCHK(hipEventRecord(b, e.stream));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *ms_per_launch = ms / (float)n_launches;
   return SIM_OK;
 }
 
