@@ -287,11 +287,10 @@ def main():
     ms_step = 1000.0 * secs / args.steps
     value = N * args.steps / secs
     # live per-kernel timing (HIP events on the world's stream), same state
+    # live per-kernel timing on the world's stream; the fluid kernel's time
+    # comes from its dispatch's own start and end timestamps
     kms = W.profile(args.warmup + args.steps, args.profile_steps)
-    # the dominant kernel alone, back-to-back launches bracketed by one pair
-    # of HIP events on the world's stream (per-launch event pairs would add
-    # the dispatch gap to every launch)
-    fluid_ms = W.profile_fluid(2 * max(1, args.profile_steps // 2))
+    fluid_ms = kms[4]
     fluid_bytes = FLUID_BYTES_PER_CELL * ncell
     fluid_gbs = fluid_bytes / (fluid_ms * 1e-3) / 1e9
     step_bytes = STEP_BYTES_PER_CELL * ncell + STEP_BYTES_PER_NODE * N

@@ -180,18 +180,14 @@ sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
  * launched directly, not from a graph) with HIP events on the world's stream
  * around every kernel group, and write the mean device time in milliseconds
  * of each group to ms_out[6]: 0 elastic force, 1 transfer preparation
- * (tile binning or sorting; 0 in direct mode), 2 deposit + filter,
- * 3 repulsion + spread, 4 fluid update, 5 gather + integrate.  The state advances exactly as with sim_rollout.
+ * (sorting; the tile bins are built by groups 0 and 5), 2 deposit + filter,
+ * 3 repulsion + spread, 4 fluid update, 5 gather + integrate.  Group 4 is the
+ * fluid kernel's own execution time (its dispatch's start and end
+ * timestamps); the other groups are event pairs around their launches and
+ * include dispatch gaps.  The state advances exactly as with sim_rollout.
  * Synchronises the stream. */
 sim_status sim_profile_steps(sim_world *w, int64_t t0, int32_t n_steps, float *ms_out);
 
-/* Measurement hook: n_launches (even, >= 2) back-to-back launches of the
- * fluid update alone on the world's stream, bracketed by one pair of HIP
- * events; writes the mean device time per launch in milliseconds.  The
- * populations advance n_launches lattice Boltzmann steps with the current
- * grid force and end in the caller's buffer; u is overwritten.  Meant for a
- * world that is about to be discarded.  Synchronises the stream. */
-sim_status sim_profile_fluid(sim_world *w, int32_t n_launches, float *ms_per_launch);
 
 /* ---- Batched worlds: many independent worlds of uneven size advanced by the
  * same kernels in one persistent, graph-captured launch per chunk of steps.

@@ -337,10 +337,11 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
       v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
       L = glb(w.rest_length)[gi];
       th = atan2f(v0y, v0x);
-      const float l0 = sqrtf(v0x * v0x + v0y * v0y);
+      const float l0 = hw_sqrt(v0x * v0x + v0y * v0y);
       if (l0 > 0.f) {
-        u0x = v0x / l0;
-        u0y = v0y / l0;
+        const float il = hw_rcp(l0);
+        u0x = v0x * il;
+        u0y = v0y * il;
       }
     }
     float th_hat = 0.f;
@@ -411,8 +412,8 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
             const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
             const float vx = v0x + (d1x - d0x);
             const float vy = v0y + (d1y - d0y);
-            const float ell = sqrtf(vx * vx + vy * vy);
-            const float sc = (ell - L) / ell;
+            const float ell = hw_sqrt(vx * vx + vy * vy);
+            const float sc = (ell - L) * hw_rcp(ell);
             const float csx = sc * vx, csy = sc * vy;
             float sn, cs;
             edge_direction(th_p[iter], th, u0x, u0y, &cs, &sn);

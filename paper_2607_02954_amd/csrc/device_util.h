@@ -19,10 +19,16 @@ static __device__ __forceinline__ int wrap_near(int v, int n) {   // v in [-n, 2
   return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
-// Map an angle difference into (-pi, pi].
+// Map an angle difference into (-pi, pi] (the quotient by 2 pi is formed
+// with its reciprocal; that can only matter at the boundary itself).
 static __device__ __forceinline__ float wrap_angle(float d) {
-  return d - kTwoPi * ceilf((d - kPi) / kTwoPi);
+  return d - kTwoPi * ceilf((d - kPi) * (1.0f / kTwoPi));
 }
+
+// Hardware square root and reciprocal (within 1 ulp; the edge lengths they
+// see are near 1, far from denormals).
+static __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+static __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // The four 1D weights of Peskin's 4-point function for offsets
 // (-1 - f, -f, 1 - f, 2 - f), f in [0, 1): with q = sqrt(1 + 4f - 4f^2) they
@@ -66,8 +72,21 @@ static __device__ __forceinline__ void peskin4_d(float f, float w[4], float dw[4
 static __device__ __forceinline__ float actuated_angle(float ra, float amp, float period, float phase, long long t,
                                                        int j, int n) {
   if (amp == 0.0f) return ra;
-  const double q = (double)t / (double)period;
-  float r = (float)(q - floor(q)) + phase * (1.0f / kTwoPi) - (float)j / (float)(n - 2);
+  float frac_t;                                 // (t / period) mod 1
+  if (t < (1ll << 24)) {
+    // t is exact in FP32; t - k period is formed with one rounding (fma), so
+    // the remainder keeps FP32 accuracy whatever the size of t / period
+    const float tf = (float)t;
+    const float k = floorf(tf * hw_rcp(period));
+    float rem = fmaf(-k, period, tf);
+    if (rem < 0.0f) rem += period;
+    if (rem >= period) rem -= period;
+    frac_t = rem * hw_rcp(period);
+  } else {
+    const double q = (double)t / (double)period;
+    frac_t = (float)(q - floor(q));
+  }
+  float r = frac_t + phase * (1.0f / kTwoPi) - (float)j / (float)(n - 2);
   r -= rintf(r);
   return ra + amp * sinf(kTwoPi * r);
 }

@@ -144,6 +144,9 @@ void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+// the same launch with the dispatch's own start and end timestamps in two events
+void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, hipEvent_t start,
+                      hipEvent_t stop);
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s);
 

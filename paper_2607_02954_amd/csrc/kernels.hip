@@ -30,6 +30,8 @@
 // filament-contiguous SoA), so neighbour exchange along a chain stays in LDS.
 // Positions are an integer cell plus a float fraction, so the quantities the
 // physics needs (edge vectors, kernel offsets) are formed from small numbers.
+#include <hip/hip_ext.h>
+
 #include "device_util.h"
 
 namespace mc {
@@ -90,10 +92,11 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
       v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
       L = glb(w.rest_length)[gi];
       th = atan2f(v0y, v0x);
-      const float l0 = sqrtf(v0x * v0x + v0y * v0y);
+      const float l0 = hw_sqrt(v0x * v0x + v0y * v0y);
       if (l0 > 0.f) {
-        u0x = v0x / l0;
-        u0y = v0y / l0;
+        const float il = hw_rcp(l0);
+        u0x = v0x * il;
+        u0y = v0y * il;
       }
     }
     float th_hat = 0.f;
@@ -130,8 +133,8 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
           const float vx = v0x + (d1x - d0x);
           const float vy = v0y + (d1y - d0y);
-          const float ell = sqrtf(vx * vx + vy * vy);
-          const float sc = (ell - L) / ell;
+          const float ell = hw_sqrt(vx * vx + vy * vy);
+          const float sc = (ell - L) * hw_rcp(ell);
           const float csx = sc * vx, csy = sc * vy;
           float sn, cs;
           edge_direction(s_th[li], th, u0x, u0y, &cs, &sn);
@@ -1061,6 +1064,11 @@ void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_
 
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   k_lbm<<<G.item_blocks, 256, 0, s>>>(W, T);
+}
+
+void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, hipEvent_t start,
+                      hipEvent_t stop) {
+  hipExtLaunchKernelGGL(k_lbm, dim3(G.item_blocks), dim3(256), 0, s, start, stop, 0, W, T);
 }
 
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {

@@ -778,6 +778,8 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
   constexpr int kGroups = 6;
   std::vector<hipEvent_t> ev((size_t)n_steps * (kGroups + 1), nullptr);
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  std::vector<hipEvent_t> fl(2 * (size_t)n_steps, nullptr);   // the fluid dispatch's own timestamps
+  for (auto& x : fl) HIPCHK(hipEventCreate(&x));
   sim_status st = e.set_ctl(0, t0, n_steps);
   if (st) return st;
   mc::launch_bin_prepass(e.desc[0], e.tab, e.grid, e.stream);
@@ -794,7 +796,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     mc::launch_repulse(d, e.tab, e.grid, e.stream);
     mc::launch_spread(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[4], e.stream));
-    mc::launch_lbm(d, e.tab, e.grid, e.stream);
+    mc::launch_lbm_timed(d, e.tab, e.grid, e.stream, fl[2 * k], fl[2 * k + 1]);
     HIPCHK(hipEventRecord(E[5], e.stream));
     mc::launch_integrate(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[6], e.stream));
@@ -810,34 +812,16 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     for (int k = 0; k < n_steps; ++k) {
       float ms = 0.f;
       hipEvent_t* E = ev.data() + (size_t)k * (kGroups + 1);
-      HIPCHK(hipEventElapsedTime(&ms, E[g], E[g + 1]));
+      if (g == 4)
+        HIPCHK(hipEventElapsedTime(&ms, fl[2 * k], fl[2 * k + 1]));
+      else
+        HIPCHK(hipEventElapsedTime(&ms, E[g], E[g + 1]));
       tot += ms;
     }
     ms_out[g] = (float)(tot / n_steps);
   }
   for (auto& x : ev) hipEventDestroy(x);
-  return SIM_OK;
-}
-
-sim_status sim_profile_fluid(sim_world* w, int32_t n_launches, float* ms_per_launch) {
-  if (!w || !ms_per_launch) return fail(SIM_E_INVALID, "NULL argument");
-  if (n_launches < 2 || (n_launches & 1)) return fail(SIM_E_INVALID, "n_launches must be even and >= 2");
-  Engine& e = w->eng;
-  sim_status st = e.set_ctl(0, 0, n_launches);
-  if (st) return st;
-  hipEvent_t a = nullptr, b = nullptr;
-  HIPCHK(hipEventCreate(&a));
-  HIPCHK(hipEventCreate(&b));
-  HIPCHK(hipEventRecord(a, e.stream));
-  for (int k = 0; k < n_launches; ++k) mc::launch_lbm(e.desc[k & 1], e.tab, e.grid, e.stream);
-  HIPCHK(hipEventRecord(b, e.stream));
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipEventSynchronize(b));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, a, b));
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  *ms_per_launch = ms / (float)n_launches;
+  for (auto& x : fl) hipEventDestroy(x);
   return SIM_OK;
 }
 

@@ -30,7 +30,6 @@ EXPORTS = [
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
     "sim_profile_steps",
-    "sim_profile_fluid",
     "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
     "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
     "sim_batch_destroy",
@@ -94,7 +93,6 @@ def lib():
         "sim_debug_substep": (i32, [vp, i32, i64]),
         "sim_debug_buffer": (i32, [vp, i32, P(vp)]),
         "sim_profile_steps": (i32, [vp, i64, i32, P(ctypes.c_float)]),
-        "sim_profile_fluid": (i32, [vp, i32, P(ctypes.c_float)]),
         "sim_batch_world_bytes": (i32, [P(SimParams), i32, i32, P(sz)]),
         "sim_batch_create": (i32, [i32, vp, sz, vp, P(vp)]),
         "sim_batch_admit": (i32, [vp, P(SimParams), P(SimArrays), i64, i32, P(i32)]),
@@ -229,13 +227,6 @@ class World:
         out = (ctypes.c_float * 6)()
         check(lib().sim_profile_steps(self.handle, int(t0), int(n), out))
         return list(out)
-
-    def profile_fluid(self, n: int) -> float:
-        """Mean ms per launch of the fluid update alone, n back-to-back launches
-        (see sim_profile_fluid; the world's state is not meaningful afterwards)."""
-        out = ctypes.c_float()
-        check(lib().sim_profile_fluid(self.handle, int(n), ctypes.byref(out)))
-        return float(out.value)
 
     def substep(self, which: int, t: int):
         check(lib().sim_debug_substep(self.handle, int(which), int(t)))
