@@ -293,22 +293,41 @@ struct BinFetch {
 
 static __device__ __forceinline__ BinFetch binset_fetch(const MC_GLOBAL int* bstart, int tiles_per_row, const int* tx,
                                                         int ntx, const int* ty, int nty) {
+  // Bins of one tile row are stored by increasing column, so a run of
+  // consecutive columns is one contiguous record range.  The column list is a
+  // cyclic run, broken at most once where it wraps: at most two runs per row.
+  int c0[2], m[2];
+  int nrun = 1;
+  c0[0] = tx[0];
+  m[0] = 1;
+  m[1] = 0;
+  c0[1] = 0;
+  for (int k = 1; k < ntx; ++k) {
+    if (tx[k] == tx[k - 1] + 1) {
+      ++m[nrun - 1];
+    } else {
+      c0[nrun] = tx[k];
+      m[nrun] = 1;
+      ++nrun;
+    }
+  }
   BinFetch f;
-  f.n = ntx * nty;
+  f.n = nrun * nty;
   f.b0 = 0;
   f.len = 0;
   const int i = threadIdx.x;
   if (i < f.n) {
-    const int t = bin_at(tx[i - (i / ntx) * ntx], ty[i / ntx], tiles_per_row);
-    f.b0 = bstart[t];
-    f.len = bstart[t + 1] - f.b0;
+    const int row = ty[i / nrun], j = i - (i / nrun) * nrun;
+    const int first = bin_at(c0[j], row, tiles_per_row);
+    f.b0 = bstart[first];
+    f.len = bstart[first + m[j]] - f.b0;
   }
   return f;
 }
 
 static __device__ __forceinline__ void binset_commit(const BinFetch& f, BinSet* bs) {
   const int i = threadIdx.x;
-  if (i < 64) {                                // the set has at most 16 bins: wavefront 0
+  if (i < 64) {                                // the set has at most 8 ranges: wavefront 0
     int x = i < f.n ? f.len : 0;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -336,17 +355,22 @@ static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs
   int cnt = 0;                                 // wavefront-uniform list length
   int b = 0;                                   // bin of this lane's next record
   for (int base = 0; base < total; base += PER * kTileThreads) {
-    vi4 r[PER];
+    // record indices first, then every load unconditionally (lanes past the
+    // end reload the last record and drop it), so all PER loads are in flight
+    // together instead of each waiting inside its own branch
+    int idx[PER];
     bool k[PER];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {            // issue every load before any use
+    for (int i = 0; i < PER; ++i) {
       const int f = base + i * kTileThreads + (int)threadIdx.x;
       k[i] = f < total;
-      if (k[i]) {
-        while (f >= bs.pre[b + 1]) ++b;
-        r[i] = recs[bs.start[b] + (f - bs.pre[b])];
-      }
+      const int fc = k[i] ? f : total - 1;
+      while (fc >= bs.pre[b + 1]) ++b;
+      idx[i] = bs.start[b] + (fc - bs.pre[b]);
     }
+    vi4 r[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) r[i] = recs[idx[i]];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const bool kk = k[i] && keep(r[i]);

@@ -61,11 +61,27 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     const MC_GLOBAL float* frac = glb(w.frac_in);
     const MC_GLOBAL int* foff = glb(w.fil_offset);
     const int nf = pk.fil_end - pk.fil_begin;
-    for (int k = li; k <= nf; k += PACK) s_off[k] = foff[pk.fil_begin + k] - pk.node_begin;
-    __syncthreads();
-
+    // every load this node needs is issued before anything waits: the
+    // filament offsets first (they go to LDS), then the node's own data at
+    // clamped indices (lanes past the pack's end, and the pack's last node
+    // for its successor, read an in-range node and ignore it)
+    const int off_a = foff[pk.fil_begin + min(li, nf)];      // nf <= PACK filaments
+    const int off_b = foff[pk.fil_begin + nf];
+    __builtin_amdgcn_sched_barrier(0);           // keep these two loads ahead of the node loads
     const int gi = pk.node_begin + li;
     const bool active = gi < pk.node_end;
+    const int gic = min(gi, pk.node_end - 1);
+    const int gin = min(gic + 1, N - 1);
+    const int c0x = cell[gic], c0y = cell[N + gic];
+    const float f0x = frac[gic], f0y = frac[N + gic];
+    const int c1x = cell[gin], c1y = cell[N + gin];
+    const float f1x = frac[gin], f1y = frac[N + gin];
+    const float L_r = glb(w.rest_length)[gic];
+    const float ra = glb(w.rest_angle)[gic];
+    if (li < nf) s_off[li] = off_a - pk.node_begin;
+    if (li == 0) s_off[nf] = off_b - pk.node_begin;
+    __syncthreads();
+
     // filament of this node: largest f with s_off[f] <= li
     int lo = 0, hi = nf - 1;
     while (lo < hi) {
@@ -78,19 +94,17 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     const bool has_edge = active && k < n - 1;
     const bool is_joint = active && k >= 1 && k <= n - 2;
     const int j = k - 1;
+    const int fil = pk.fil_begin + lo;
+    const float amp = glb(w.act_amp)[fil], period = glb(w.act_period)[fil], phase = glb(w.act_phase)[fil];
 
-    int cx = 0, cy = 0;
-    float fx = 0.f, fy = 0.f;
-    if (active) {
-      cx = cell[gi]; cy = cell[N + gi];
-      fx = frac[gi]; fy = frac[N + gi];
-    }
+    const int cx = active ? c0x : 0, cy = active ? c0y : 0;
+    const float fx = active ? f0x : 0.f, fy = active ? f0y : 0.f;
     float v0x = 0.f, v0y = 0.f, L = 0.f, th = 0.f;
     float u0x = 1.f, u0y = 0.f;                  // unit edge direction, (cos th, sin th)
     if (has_edge) {
-      v0x = (float)(cell[gi + 1] - cx) + (frac[gi + 1] - fx);
-      v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
-      L = glb(w.rest_length)[gi];
+      v0x = (float)(c1x - cx) + (f1x - fx);
+      v0y = (float)(c1y - cy) + (f1y - fy);
+      L = L_r;
       th = atan2f(v0y, v0x);
       const float l0 = hw_sqrt(v0x * v0x + v0y * v0y);
       if (l0 > 0.f) {
@@ -100,11 +114,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
       }
     }
     float th_hat = 0.f;
-    if (is_joint) {
-      const int f = pk.fil_begin + lo;
-      th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[f], glb(w.act_period)[f],
-                              glb(w.act_phase)[f], ctl.t, j, n);
-    }
+    if (is_joint) th_hat = actuated_angle(ra, amp, period, phase, ctl.t, j, n);
     s_th[li] = th;
     s_dx[li] = 0.f;
     s_dy[li] = 0.f;
