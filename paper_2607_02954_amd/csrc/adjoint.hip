@@ -40,8 +40,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __r
     const int2 tl = T.tiles[it];
     const WorldDev& w = W[tl.x];
     const int nx = w.nx, ny = w.ny;
-    const int x0 = (tl.y % w.ntx) * kTile;
-    const int y0 = (tl.y / w.ntx) * kTile;
+    const int x0 = tile_x(tl.y) * kTile;
+    const int y0 = tile_y(tl.y) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
     for (int k = threadIdx.x; k < kSpreadCells; k += kTileThreads) {
       s_x[k] = 0;
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__
     const WorldDev& w = W[tl.x];
     const int R = w.radius;
     const int nx = w.nx, ny = w.ny;
-    const int x0 = (tl.y % w.ntx) * kTile;
-    const int y0 = (tl.y / w.ntx) * kTile;
+    const int x0 = tile_x(tl.y) * kTile;
+    const int y0 = tile_y(tl.y) * kTile;
     const int rega = kAdjRing + 2 * R;       // dL/dG region, origin (x0-R-1, y0-R-1)
     const int regb = kTile + 2 * R;          // D^T dL/dG region, origin (x0-R, y0-R)
     const MC_GLOBAL vf2* gb = glbv<const vf2>(A.Gbar);

@@ -10,10 +10,18 @@ namespace mc {
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kTwoPi = 6.28318530717958647692f;
 
+// i mod n in [0, n) for any i; integer division only outside [-n, 2n).
 static __device__ __forceinline__ int wrap_index(int i, int n) {
-  int r = i % n;
+  if (i >= 0 && i < n) return i;
+  if (i >= n && i < 2 * n) return i - n;
+  if (i < 0 && i >= -n) return i + n;
+  const int r = i % n;
   return r < 0 ? r + n : r;
 }
+
+// Tile table entries hold (world, tx | ty << 16).
+static __device__ __forceinline__ int tile_x(int packed) { return packed & 0xffff; }
+static __device__ __forceinline__ int tile_y(int packed) { return packed >> 16; }
 
 static __device__ __forceinline__ int wrap_near(int v, int n) {   // v in [-n, 2n)
   return v < 0 ? v + n : (v >= n ? v - n : v);

@@ -103,7 +103,7 @@ struct Pack {
 
 struct Tables {
   const Pack* packs;  const int* n_packs;
-  const int2* tiles;  const int* n_tiles;    // (world, tile index), 32x32 cells
+  const int2* tiles;  const int* n_tiles;    // (world, tx | ty << 16), 32x32 cells
   const int2* items;  const int* n_items;    // (world, first cell) of 256 contiguous cells
   const int2* scan;   const int* n_scan;     // (world, block) for the cell scan (sorted mode)
   const int2* worlds; const int* n_worlds;   // (world, 0) for per-world kernels

@@ -493,7 +493,7 @@ static __device__ __forceinline__ int div_small(int k, float inv_d) {
 // (xo = x0 - R - 1, reg = 34 + 2R), whose supports meet the density region.
 static __device__ __forceinline__ BinFetch filter_fetch(const WorldDev& w, int tile) {
   const int R = w.radius, reg = kRing + 2 * R;
-  const int xo = (tile % w.ntx) * kTile - R - 1, yo = (tile / w.ntx) * kTile - R - 1;
+  const int xo = tile_x(tile) * kTile - R - 1, yo = tile_y(tile) * kTile - R - 1;
   int txs[kMaxBinCols], tys[kMaxBinCols];
   const int ntxs = bins_covering(xo - 2, xo + reg, w.nx, txs);
   const int ntys = bins_covering(yo - 2, yo + reg, w.ny, tys);
@@ -516,8 +516,8 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     if (w.ctl_src->remaining <= 0) continue;
     const int R = w.radius, mode = w.mode;
     const int nx = w.nx, ny = w.ny;
-    const int x0 = (tl.y % w.ntx) * kTile;
-    const int y0 = (tl.y / w.ntx) * kTile;
+    const int x0 = tile_x(tl.y) * kTile;
+    const int y0 = tile_y(tl.y) * kTile;
     const int reg = kRing + 2 * R;
     const float inv_reg = 1.0f / (float)reg;
     const int xo = x0 - R - 1, yo = y0 - R - 1;   // region origin (unwrapped)
@@ -700,8 +700,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
     if (w.mode == kDirect || w.ctl_src->remaining <= 0) continue;
     const int mode = w.mode;
     const int nx = w.nx, ny = w.ny;
-    const int x0 = (tl.y % w.ntx) * kTile;
-    const int y0 = (tl.y / w.ntx) * kTile;
+    const int x0 = tile_x(tl.y) * kTile;
+    const int y0 = tile_y(tl.y) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
     if (mode == kBinned) {
       for (int k = tid; k < kSpreadCells; k += kTileThreads) {
@@ -923,15 +923,15 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;
-    const int x0 = (tl.y % w.ntx) * kTile;
-    const int y0 = (tl.y / w.ntx) * kTile;
+    const int x0 = tile_x(tl.y) * kTile;
+    const int y0 = tile_y(tl.y) * kTile;
     stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_gx, s_gy);
     __syncthreads();
     const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
     MC_GLOBAL float* fel = glb(w.fel);
     const float kr = w.k_rep;
-    const int e1 = glb(w.bin_start)[tl.y + 1];
-    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += kTileThreads) {
+    const int e1 = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y) + 1];
+    for (int e = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y)] + threadIdx.x; e < e1; e += kTileThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;   // home in the tile
       float wx[4], wy[4];
@@ -968,16 +968,16 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;
-    const int x0 = (tl.y % w.ntx) * kTile;
-    const int y0 = (tl.y / w.ntx) * kTile;
+    const int x0 = tile_x(tl.y) * kTile;
+    const int y0 = tile_y(tl.y) * kTile;
     stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_ux, s_uy);
     __syncthreads();
     const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
     const MC_GLOBAL int* cell = glb(w.cell_in);
     MC_GLOBAL int* cell_out = glb(w.cell_out);
     MC_GLOBAL float* frac_out = glb(w.frac_out);
-    const int e1 = glb(w.bin_start)[tl.y + 1];
-    for (int e = glb(w.bin_start)[tl.y] + threadIdx.x; e < e1; e += kTileThreads) {
+    const int e1 = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y) + 1];
+    for (int e = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y)] + threadIdx.x; e < e1; e += kTileThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
       const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);

@@ -332,7 +332,8 @@ struct Engine {
         f = end;
       }
       const int ncell = s.p.nx * s.p.ny;
-      for (int t = 0; t < tiles_x(s.p) * tiles_y(s.p); ++t) tl.push_back(make_int2(w, t));
+      for (int ty = 0; ty < tiles_y(s.p); ++ty)
+        for (int tx = 0; tx < tiles_x(s.p); ++tx) tl.push_back(make_int2(w, tx | (ty << 16)));
       for (int c = 0; c < ncell; c += mc::kCellsPerItem) it.push_back(make_int2(w, c));
       wl.push_back(make_int2(w, 0));
       const int mode = mode_of(s.p);
