@@ -739,6 +739,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
 // the HBM accumulators for the next step.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_lbm(const WorldDev* __restrict__ W, Tables T) {
+  constexpr int CPT = kCellsPerItem / 256;      // cells per thread, loaded together
   const int nit = *T.n_items;
   for (int it = blockIdx.x; it < nit; it += gridDim.x) {
     const int2 item = T.items[it];
@@ -753,78 +754,94 @@ __global__ __launch_bounds__(256) void k_lbm(const WorldDev* __restrict__ W, Tab
     if (!live) continue;
     const int nx = w.nx, ny = w.ny;
     const int ncell = nx * ny;
-    const int c = item.y + threadIdx.x;
-    if (c >= ncell) continue;
-    const int y = c / nx;
-    const int x = c - y * nx;
+    const int ry = item.y / nx;                 // row and column of the item's first cell
+    const int rx = item.y - ry * nx;
     const MC_GLOBAL float* src = glb(w.f_src);
     MC_GLOBAL float* dst = glb(w.f_dst);
+    float gg[CPT][9];
+    vf2 FF[CPT];
+#pragma unroll
+    for (int h = 0; h < CPT; ++h) {             // every load of every cell first
+      const int c = min(item.y + (int)threadIdx.x + 256 * h, ncell - 1);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) gg[h][q] = src[(size_t)q * ncell + c];
+      FF[h] = glbv<vf2>(w.Fg)[c];
+    }
+#pragma unroll
+    for (int h = 0; h < CPT; ++h) {
+      const int c = item.y + (int)threadIdx.x + 256 * h;
+      if (c >= ncell) continue;
+      int x = rx + (int)threadIdx.x + 256 * h, y = ry;
+      while (x >= nx) {                           // items may run over row ends
+        x -= nx;
+        ++y;
+      }
+      const float* g = gg[h];
+      const vf2 F = FF[h];
+      if (w.mode == kDirect) {
+        const vf2 zero = {0.f, 0.f};
+        glbv<vf2>(w.Fg)[c] = zero;
+        glb(w.s)[c] = 0.f;
+      }
+      const float Fx = F.x, Fy = F.y;
+      // moments (the lattice weights have zero first moment, so the shift does
+      // not change the momentum sum)
+      const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+      const float rho = 1.0f + drho;
+      const float jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+      const float jy = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
+      const float inv = 1.0f / rho;
+      const float ux = (jx + 0.5f * Fx) * inv;
+      const float uy = (jy + 0.5f * Fy) * inv;
+      const float usq = ux * ux + uy * uy;
+      const vf2 uv = {ux, uy};
+      glbv<vf2>(w.u)[c] = uv;
+      if (!(usq <= w.u_max2)) atomicOr((unsigned*)glb(w.flags), kFlagUnstable);
 
-    float g[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = src[(size_t)q * ncell + c];
-    const vf2 F = glbv<vf2>(w.Fg)[c];
-    if (w.mode == kDirect) {
-      const vf2 zero = {0.f, 0.f};
-      glbv<vf2>(w.Fg)[c] = zero;
-      glb(w.s)[c] = 0.f;
-    }
-    const float Fx = F.x, Fy = F.y;
-    // moments (the lattice weights have zero first moment, so the shift does
-    // not change the momentum sum)
-    const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-    const float rho = 1.0f + drho;
-    const float jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const float jy = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
-    const float inv = 1.0f / rho;
-    const float ux = (jx + 0.5f * Fx) * inv;
-    const float uy = (jy + 0.5f * Fy) * inv;
-    const float usq = ux * ux + uy * uy;
-    const vf2 uv = {ux, uy};
-    glbv<vf2>(w.u)[c] = uv;
-    if (!(usq <= w.u_max2)) atomicOr((unsigned*)glb(w.flags), kFlagUnstable);
-
-    // equilibrium minus weights: w_q (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2));
-    // Guo source: w_q (3 (c - u) + 9 (c.u) c) . F; split into the parts
-    // symmetric and antisymmetric under q <-> opposite(q)
-    const float op = w.om_p, om = w.om_m;
-    const float sp = 1.0f - 0.5f * op, sm = 1.0f - 0.5f * om;
-    const float base = 1.5f * usq;
-    const float uF = ux * Fx + uy * Fy;
-    float out[9];
-    {
-      const float w0 = 4.0f / 9.0f;
-      const float geq0 = w0 * (drho - rho * base);
-      const float S0 = w0 * (-3.0f * uF);
-      out[0] = g[0] - op * (g[0] - geq0) + sp * S0;
-    }
-#pragma unroll
-    for (int pr = 0; pr < 4; ++pr) {
-      const int q = pr < 2 ? 1 + pr : 5 + (pr - 2);
-      const int qb = q + 2;
-      const float wq = pr < 2 ? (1.0f / 9.0f) : (1.0f / 36.0f);
-      const float cxq = (float)kCX[q], cyq = (float)kCY[q];
-      const float cu = cxq * ux + cyq * uy;
-      const float cF = cxq * Fx + cyq * Fy;
-      const float eqp = wq * (drho + rho * (4.5f * cu * cu - base));
-      const float eqm = wq * rho * 3.0f * cu;
-      const float Sp = wq * (9.0f * cu * cF - 3.0f * uF);
-      const float Sm = wq * 3.0f * cF;
-      const float gp = 0.5f * (g[q] + g[qb]);
-      const float gm = 0.5f * (g[q] - g[qb]);
-      const float relp = -op * (gp - eqp) + sp * Sp;
-      const float relm = -om * (gm - eqm) + sm * Sm;
-      out[q] = g[q] + relp + relm;
-      out[qb] = g[qb] + relp - relm;
-    }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const int xn = wrap_near(x + kCX[q], nx);
-      const int yn = wrap_near(y + kCY[q], ny);
-      dst[(size_t)q * ncell + (size_t)yn * nx + xn] = out[q];
+      // equilibrium minus weights: w_q (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2));
+      // Guo source: w_q (3 (c - u) + 9 (c.u) c) . F; split into the parts
+      // symmetric and antisymmetric under q <-> opposite(q)
+      const float op = w.om_p, om = w.om_m;
+      const float sp = 1.0f - 0.5f * op, sm = 1.0f - 0.5f * om;
+      const float base = 1.5f * usq;
+      const float uF = ux * Fx + uy * Fy;
+      float out[9];
+      {
+        const float w0 = 4.0f / 9.0f;
+        const float geq0 = w0 * (drho - rho * base);
+        const float S0 = w0 * (-3.0f * uF);
+        out[0] = g[0] - op * (g[0] - geq0) + sp * S0;
+      }
+  #pragma unroll
+      for (int pr = 0; pr < 4; ++pr) {
+        const int q = pr < 2 ? 1 + pr : 5 + (pr - 2);
+        const int qb = q + 2;
+        const float wq = pr < 2 ? (1.0f / 9.0f) : (1.0f / 36.0f);
+        const float cxq = (float)kCX[q], cyq = (float)kCY[q];
+        const float cu = cxq * ux + cyq * uy;
+        const float cF = cxq * Fx + cyq * Fy;
+        const float eqp = wq * (drho + rho * (4.5f * cu * cu - base));
+        const float eqm = wq * rho * 3.0f * cu;
+        const float Sp = wq * (9.0f * cu * cF - 3.0f * uF);
+        const float Sm = wq * 3.0f * cF;
+        const float gp = 0.5f * (g[q] + g[qb]);
+        const float gm = 0.5f * (g[q] - g[qb]);
+        const float relp = -op * (gp - eqp) + sp * Sp;
+        const float relm = -om * (gm - eqm) + sm * Sm;
+        out[q] = g[q] + relp + relm;
+        out[qb] = g[qb] + relp - relm;
+      }
+  #pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const int xn = wrap_near(x + kCX[q], nx);
+        const int yn = wrap_near(y + kCY[q], ny);
+        dst[(size_t)q * ncell + (size_t)yn * nx + xn] = out[q];
+      }
     }
   }
 }
+
+
 
 // ---------------------------------------------------------------------------
 // S7: gather the step's fluid velocity at each node and integrate
@@ -925,14 +942,23 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * kTile;
     const int y0 = tile_y(tl.y) * kTile;
-    stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_gx, s_gy);
-    __syncthreads();
     const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
     MC_GLOBAL float* fel = glb(w.fel);
     const float kr = w.k_rep;
-    const int e1 = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y) + 1];
-    for (int e = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y)] + threadIdx.x; e < e1; e += kTileThreads) {
-      const vi4 r = recs[e];
+    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
+    // this thread's first record is loaded beside the staged field (record 0
+    // always exists: the record buffer holds at least one)
+    const vi4 r0 = recs[e0 + (int)threadIdx.x < e1 ? e0 + (int)threadIdx.x : 0];
+    stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_gx, s_gy);
+    const bool has0 = e0 + (int)threadIdx.x < e1;
+    float f0x = 0.f, f0y = 0.f;                 // in flight across the barrier
+    if (has0) {
+      f0x = fel[r0.w];
+      f0y = fel[N + r0.w];
+    }
+    __syncthreads();
+    auto node = [&](const vi4& r, float fex, float fey) {
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;   // home in the tile
       float wx[4], wy[4];
       peskin4(__int_as_float(r.y), wx);
@@ -951,8 +977,14 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
         gx += wy[b] * ax;
         gy += wy[b] * ay;
       }
-      fel[r.w] = fel[r.w] - kr * gx;
-      fel[N + r.w] = fel[N + r.w] - kr * gy;
+      fel[r.w] = fex - kr * gx;
+      fel[N + r.w] = fey - kr * gy;
+    };
+    // the first record (already loaded), then any further ones
+    if (has0) node(r0, f0x, f0y);
+    for (int e = e0 + threadIdx.x + kTileThreads; e < e1; e += kTileThreads) {
+      const vi4 r = recs[e];
+      node(r, fel[r.w], fel[N + r.w]);
     }
     __syncthreads();
   }
@@ -970,15 +1002,24 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * kTile;
     const int y0 = tile_y(tl.y) * kTile;
-    stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_ux, s_uy);
-    __syncthreads();
     const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
     const MC_GLOBAL int* cell = glb(w.cell_in);
     MC_GLOBAL int* cell_out = glb(w.cell_out);
     MC_GLOBAL float* frac_out = glb(w.frac_out);
-    const int e1 = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y) + 1];
-    for (int e = glb(w.bin_start)[tile_y(tl.y) * w.ntx + tile_x(tl.y)] + threadIdx.x; e < e1; e += kTileThreads) {
-      const vi4 r = recs[e];
+    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
+    // this thread's first record is loaded beside the staged field (record 0
+    // always exists: the record buffer holds at least one)
+    const vi4 r0 = recs[e0 + (int)threadIdx.x < e1 ? e0 + (int)threadIdx.x : 0];
+    stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_ux, s_uy);
+    const bool has0 = e0 + (int)threadIdx.x < e1;
+    int c0x = 0, c0y = 0;                       // in flight across the barrier
+    if (has0) {                                 // (an empty world has no positions at all)
+      c0x = cell[r0.w];
+      c0y = cell[N + r0.w];
+    }
+    __syncthreads();
+    auto node = [&](const vi4& r, int cxo, int cyo) {
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
       const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);
       float wx[4], wy[4];
@@ -1001,7 +1042,7 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
       const int gi = r.w;
       float nfx = fx + dux, nfy = fy + duy;
       const float flx = floorf(nfx), fly = floorf(nfy);
-      int ncx = cell[gi] + (int)flx, ncy = cell[N + gi] + (int)fly;
+      int ncx = cxo + (int)flx, ncy = cyo + (int)fly;
       nfx -= flx;
       nfy -= fly;
       if (nfx >= 1.0f) { nfx = 0.0f; ncx += 1; }
@@ -1012,6 +1053,12 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
       frac_out[N + gi] = nfy;
       // next step's tile-bin counts
       agg_atomic_inc(glb(w.bin_cnt), bin_of(wrap_index(ncx, nx), wrap_index(ncy, ny), w.ntx), true);
+    };
+    // the first record (already loaded), then any further ones
+    if (has0) node(r0, c0x, c0y);
+    for (int e = e0 + threadIdx.x + kTileThreads; e < e1; e += kTileThreads) {
+      const vi4 r = recs[e];
+      node(r, cell[r.w], cell[N + r.w]);
     }
     __syncthreads();
   }
