@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __r
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = T.tiles[it];
+    const int2 tl = tile_entry(T, it);
     const WorldDev& w = W[tl.x];
     const int nx = w.nx, ny = w.ny;
     const int x0 = tile_x(tl.y) * kTile;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = T.tiles[it];
+    const int2 tl = tile_entry(T, it);
     const WorldDev& w = W[tl.x];
     const int R = w.radius;
     const int nx = w.nx, ny = w.ny;

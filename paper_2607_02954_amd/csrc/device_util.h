@@ -19,6 +19,16 @@ static __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Tile table entry it: (world, tx | ty << 16); computed rather than read when
+// the tables hold a single world.
+static __device__ __forceinline__ int2 tile_entry(const Tables& T, int it) {
+  if (T.single_ntx > 0) {
+    const int ty = it / T.single_ntx;
+    return make_int2(0, (it - ty * T.single_ntx) | (ty << 16));
+  }
+  return T.tiles[it];
+}
+
 // Tile table entries hold (world, tx | ty << 16).
 static __device__ __forceinline__ int tile_x(int packed) { return packed & 0xffff; }
 static __device__ __forceinline__ int tile_y(int packed) { return packed >> 16; }

@@ -107,6 +107,8 @@ struct Tables {
   const int2* items;  const int* n_items;    // (world, first cell) of 256 contiguous cells
   const int2* scan;   const int* n_scan;     // (world, block) for the cell scan (sorted mode)
   const int2* worlds; const int* n_worlds;   // (world, 0) for per-world kernels
+  int single_ntx;                            // > 0: the tables hold one world whose tiles are
+                                             // its row-major tiles, ntx per row (no table read)
 };
 
 struct Grid {

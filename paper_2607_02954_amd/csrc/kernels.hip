@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = T.tiles[it];
+    const int2 tl = tile_entry(T, it);
     const WorldDev& w = W[tl.x];
     if (w.ctl_src->remaining <= 0) continue;
     const int R = w.radius, mode = w.mode;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = T.tiles[it];
+    const int2 tl = tile_entry(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode == kDirect || w.ctl_src->remaining <= 0) continue;
     const int mode = w.mode;
@@ -936,7 +936,7 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = T.tiles[it];
+    const int2 tl = tile_entry(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;
@@ -996,7 +996,7 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = T.tiles[it];
+    const int2 tl = tile_entry(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;

@@ -611,6 +611,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   e.max_items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
   e.max_scan = (ncell + 1023) / 1024;
   e.grid.pack = max_len <= 256 ? 256 : 1024;
+  e.tab.single_ntx = tiles_x(*p);               // one world: tile entries are computed
   Carver c{(char*)workspace};
   e.carve_tables(c);
   Slot sl;
