@@ -209,11 +209,13 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
 // ---------------------------------------------------------------------------
 // next: write the starts for the next step's bins (bin_start_next; after
 // integrate) rather than for the current positions (bin_start; pre-pass).
+// Every node has exactly one record, so the counts must add up to the
+// world's node count: the starts are clamped to it (no bin range can leave
+// the record buffer) and a mismatch raises kFlagBins.
 __global__ __launch_bounds__(1024) void k_bin_scan(const WorldDev* __restrict__ W, Tables T, int next) {
-  // every wavefront scans a segment of 1024 consecutive bins (16 coalesced
-  // rows of 64, one shuffle scan per row, no barrier), then one exchange of
-  // the 16 segment totals; a round covers 16384 bins
-  constexpr int kRows = 16;
+  // every thread sums 4 consecutive bins (one 16-byte load), the wavefronts
+  // scan those sums with shuffles, one exchange of the 16 wavefront totals;
+  // a round covers 4096 bins
   __shared__ int s_tot[16];
   const int nw = *T.n_worlds;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -224,29 +226,27 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const WorldDev* __restrict__ 
     MC_GLOBAL int* fill = glb(w.bin_fill);
     MC_GLOBAL int* start = glb(next ? w.bin_start_next : w.bin_start);
     const int nt = w.ntx * w.nty;               // bins (one per tile)
+    const int N = w.n_part;
     int carry = 0;
-    for (int c0 = 0; c0 < nt; c0 += 1024 * kRows) {
-      const int seg = c0 + wv * 64 * kRows;
-      int v[kRows];
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        const int i = seg + 64 * k + lane;
-        v[k] = i < nt ? cnt[i] : 0;
+    for (int c0 = 0; c0 < nt; c0 += 4096) {
+      const int i0 = c0 + 4 * tid;              // a multiple of 4: 16-byte aligned
+      const bool whole = i0 + 3 < nt;
+      vi4 v = {0, 0, 0, 0};
+      if (whole) {
+        v = *(const MC_GLOBAL vi4*)(cnt + i0);
+      } else {
+        if (i0 < nt) v.x = cnt[i0];
+        if (i0 + 1 < nt) v.y = cnt[i0 + 1];
+        if (i0 + 2 < nt) v.z = cnt[i0 + 2];
       }
-      int run = 0;
+      const int sum = v.x + v.y + v.z + v.w;
+      int x = sum;
 #pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        int x = v[k];
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const int y = __shfl_up(x, off);
-          if (lane >= off) x += y;
-        }
-        const int ex = run + x - v[k];
-        run += __shfl(x, 63);
-        v[k] = ex;                              // exclusive prefix within the segment
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
       }
-      if (lane == 0) s_tot[wv] = run;
+      if (lane == 63) s_tot[wv] = x;
       __syncthreads();
       int before = carry, all = 0;
 #pragma unroll
@@ -256,18 +256,24 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const WorldDev* __restrict__ 
         all += t;
       }
       __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        const int i = seg + 64 * k + lane;
-        if (i < nt) {
-          start[i] = before + v[k];
-          cnt[i] = 0;
-          fill[i] = 0;
-        }
+      const int e = before + x - sum;           // start of bin i0
+      const vi4 st = {min(e, N), min(e + v.x, N), min(e + v.x + v.y, N), min(e + v.x + v.y + v.z, N)};
+      const vi4 zero = {0, 0, 0, 0};
+      if (whole) {
+        *(MC_GLOBAL vi4*)(start + i0) = st;
+        *(MC_GLOBAL vi4*)(cnt + i0) = zero;
+        *(MC_GLOBAL vi4*)(fill + i0) = zero;
+      } else {
+        if (i0 < nt) { start[i0] = st.x; cnt[i0] = 0; fill[i0] = 0; }
+        if (i0 + 1 < nt) { start[i0 + 1] = st.y; cnt[i0 + 1] = 0; fill[i0 + 1] = 0; }
+        if (i0 + 2 < nt) { start[i0 + 2] = st.z; cnt[i0 + 2] = 0; fill[i0 + 2] = 0; }
       }
       carry += all;
     }
-    if (tid == 0) start[nt] = carry;
+    if (tid == 0) {
+      start[nt] = min(carry, N);
+      if (carry != N) atomicOr((unsigned*)glb(w.flags), kFlagBins);
+    }
   }
 }
 
