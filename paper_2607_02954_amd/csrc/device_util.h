@@ -413,16 +413,19 @@ static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs
   __syncthreads();
 }
 
-// Node -> grid accumulation over a padded window.  A window of side S covers
-// grid cells o + c (c in [0, S), o = origin, periodic); a node whose home
-// cell is h adds to window cells h - 1 - o + (0..3).  With the home offset
-// d = (h - 1 - o) mod n in [0, n) every contribution lands inside the window
-// provided d + 3 < S, so the inner loops carry no bounds or wrap tests:
-//   * when the window does not wrap onto itself (S <= n) only nodes with
-//     d <= need + 2 can touch the `need` cells [3, 3 + need) the caller
-//     reads, and those are the nodes kept;
-//   * otherwise (small grids) every node of the bins is kept and window
-//     cells that are the same grid cell are summed when read.
+// Node -> grid accumulation over a padded window.  A window of side
+// S = need + 6 covers grid cells o + c (c in [0, S), o = origin, periodic)
+// for a caller that reads the `need` cells [3, 3 + need); a node whose home
+// cell is h adds to window cells d + (0..3), d = (h - 1 - o) mod n in [0, n).
+// Every contribution lands inside the window, so the inner loops carry no
+// bounds or wrap tests:
+//   * when need + 3 <= n, a node with d > need + 2 cannot touch the needed
+//     cells (its support lies past them, and the part that wraps lands in
+//     cells 0..2), so only nodes with d <= need + 2 are kept: their cells
+//     reach at most need + 5;
+//   * otherwise (small grids, n < need + 3) every node of the bins is kept,
+//     its cells reach at most n + 2 < S, and window cells that are the same
+//     grid cell are summed when read.
 // The first three and last three window cells only catch the spill of nodes
 // at the edge of the needed range.
 
@@ -441,7 +444,7 @@ static __device__ __forceinline__ int first_image(int i, int n) {
 // zeroed (and synchronised) beforehand.  Values whose fixed-point image fits
 // 32 bits (|scale v| < 1/8, as nearly all forces) are converted by one
 // truncating 32-bit conversion; larger ones by the exact 64-bit split.
-constexpr int kSpreadSide = kTile + 8;
+constexpr int kSpreadSide = kTile + 6;
 constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
 
 // The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th].
@@ -458,8 +461,8 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
   const int nx = w.nx, ny = w.ny, N = w.n_part;
   binset_commit(bins, s_bs);
   const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
-  const int keep_x = tw + 6 <= nx ? tw + 2 : nx;     // largest kept home offset
-  const int keep_y = th + 6 <= ny ? th + 2 : ny;
+  const int keep_x = tw + 3 <= nx ? tw + 2 : nx;     // largest kept home offset
+  const int keep_y = th + 3 <= ny ? th + 2 : ny;
   for_bin_records<4>(
       glbv<const vi4>(w.bin_rec), *s_bs, s_list,
       [&](const vi4& r) {

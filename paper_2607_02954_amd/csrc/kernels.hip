@@ -480,7 +480,7 @@ constexpr int kRing = kTile + 2;                    // tile plus the one-cell ri
 constexpr int kRegion = kRing + 2 * kMaxRadius;     // largest density region side
 
 static __host__ __device__ constexpr int filter_window_bytes(int max_radius) {
-  return (kRing + 2 * max_radius + 8) * (kRing + 2 * max_radius + 8) * 8;
+  return (kRing + 2 * max_radius + 6) * (kRing + 2 * max_radius + 6) * 8;
 }
 static __host__ __device__ constexpr int filter_list_bytes(int max_radius) {
   return (kRing + 2 * max_radius) * (kRing + 2 * max_radius) * 4 > kListBytes
@@ -529,12 +529,12 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     const int xo = x0 - R - 1, yo = y0 - R - 1;   // region origin (unwrapped)
     float* s_st = s_mid + reg * kRing;
     if (mode == kBinned) {
-      const int S = reg + 8;                      // window side; window origin (xo - 3, yo - 3)
+      const int S = reg + 6;                      // window side; window origin (xo - 3, yo - 3)
       for (int k = tid; k < S * S; k += kTileThreads) s_win[k] = 0;
       binset_commit(filter_fetch(w, tl.y), &s_bs);
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
-      const int keep_x = reg + 6 <= nx ? reg + 2 : nx;
-      const int keep_y = reg + 6 <= ny ? reg + 2 : ny;
+      const int keep_x = reg + 3 <= nx ? reg + 2 : nx;
+      const int keep_y = reg + 3 <= ny ? reg + 2 : ny;
       for_bin_records<4>(
           glbv<const vi4>(w.bin_rec), s_bs, s_list,
           [&](const vi4& r) {
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
               for (int a = 0; a < 4; ++a) atomicAdd(p + b * S + a, weight_product(qx[a], qy[b]));
           });
       // (the list area is free again after the barrier that ends for_bin_records)
-      const bool single = reg + 6 <= nx && reg + 6 <= ny;
+      const bool single = reg + 3 <= nx && reg + 3 <= ny;   // one image per needed cell
       for (int k = tid; k < reg * reg; k += kTileThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         unsigned long long v;
@@ -746,8 +746,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_lbm(const WorldDev* __restrict__ W, Tables T) {
   constexpr int CPT = kCellsPerItem / 256;      // cells per thread, loaded together
-  const int nit = *T.n_items;
-  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+  const XcdLoop items(*T.n_items);
+  for (int it = items.first; it < items.end; it += items.step) {
     const int2 item = T.items[it];
     const WorldDev& w = W[item.x];
     const Ctl cs = *w.ctl_src;
