@@ -33,7 +33,6 @@ __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __r
   __shared__ long long s_x[kSpreadCells];
   __shared__ long long s_y[kSpreadCells];
   __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
-  __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
@@ -49,7 +48,7 @@ __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __r
     }
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
-    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, &s_bs, spread_fetch(w, x0, y0, tw, th));
+    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, spread_fetch(w, x0, y0, tw, th));
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < kTile * kTile; k += kTileThreads) {

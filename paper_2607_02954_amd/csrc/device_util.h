@@ -277,21 +277,25 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 }
 
 
-// Records of a set of home-tile bins (the set lives in LDS).  Every
-// wavefront streams its share of the records (PER loads in flight per lane)
-// and appends those for which keep(r) holds to its own LDS list (one ballot
-// per record batch); whenever the list holds a full wavefront of records the
-// wavefront runs body(r) on 64 of them.  No block barrier is needed until all
-// records are done, body always runs on full wavefronts (except for the last
-// partial one), and lanes holding irrelevant records never idle through it.
-// body(r) may only use per-lane work and LDS atomics.
-constexpr int kWaveList = 128;             // records per wavefront list
+// Records of a set of home-tile bins.  Every wavefront streams its share of
+// the records (PER loads in flight per lane) and appends those for which
+// keep(r) holds to its own LDS list (one ballot per record batch); whenever
+// the list reaches a full wavefront of records the wavefront runs body(r) on
+// them and starts the list again with the batch's overflow.  No block barrier
+// is needed until all records are done, body always runs on full wavefronts
+// (except for the last partial one), and lanes holding irrelevant records
+// never idle through it.  body(r) may only use per-lane work and LDS atomics.
+constexpr int kWaveList = 64;              // records per wavefront list
 constexpr int kListBytes = (kTileThreads / 64) * kWaveList * 16;
+constexpr int kMaxRanges = 8;              // record ranges of a bin set
 
+// A bin set as every wavefront holds it, in scalar registers: range j covers
+// flat record numbers [pre[j], pre[j + 1]) (pre = 2^31 - 1 past the last
+// range), and flat number f of range j is record f + delta[j].
 struct BinSet {
-  int n;
-  int start[kMaxBinCols * kMaxBinCols];
-  int pre[kMaxBinCols * kMaxBinCols + 1];
+  int total;
+  int pre[kMaxRanges];
+  int delta[kMaxRanges];
 };
 
 static __device__ __forceinline__ void wave_sync() {
@@ -299,11 +303,10 @@ static __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// A bin set in flight: thread i < n holds the first record and the length of
-// bin i.  Fetching it (the bin ranges of bin columns tx[ntx] x rows ty[nty])
-// only issues loads, so a kernel can fetch the next tile's set while it works
-// on the current tile; committing writes it to LDS with its prefix (one
-// wavefront scan) and synchronises the block.
+// A bin set in flight: lane i < n of every wavefront holds the first record
+// and the length of range i.  Fetching it (the bin ranges of bin columns
+// tx[ntx] x rows ty[nty]) only issues loads; committing forms the prefix and
+// moves the set into scalar registers, then synchronises the block.
 struct BinFetch {
   int n;
   int b0, len;
@@ -313,7 +316,8 @@ static __device__ __forceinline__ BinFetch binset_fetch(const MC_GLOBAL int* bst
                                                         int ntx, const int* ty, int nty) {
   // Bins of one tile row are stored by increasing column, so a run of
   // consecutive columns is one contiguous record range.  The column list is a
-  // cyclic run, broken at most once where it wraps: at most two runs per row.
+  // cyclic run, broken at most once where it wraps: at most two runs per row,
+  // so at most 2 * kMaxBinCols = kMaxRanges ranges.
   int c0[2], m[2];
   int nrun = 1;
   c0[0] = tx[0];
@@ -333,7 +337,7 @@ static __device__ __forceinline__ BinFetch binset_fetch(const MC_GLOBAL int* bst
   f.n = nrun * nty;
   f.b0 = 0;
   f.len = 0;
-  const int i = threadIdx.x;
+  const int i = __lane_id();
   if (i < f.n) {
     const int row = ty[i / nrun], j = i - (i / nrun) * nrun;
     const int first = bin_at(c0[j], row, tiles_per_row);
@@ -343,35 +347,37 @@ static __device__ __forceinline__ BinFetch binset_fetch(const MC_GLOBAL int* bst
   return f;
 }
 
-static __device__ __forceinline__ void binset_commit(const BinFetch& f, BinSet* bs) {
-  const int i = threadIdx.x;
-  if (i < 64) {                                // the set has at most 8 ranges: wavefront 0
-    int x = i < f.n ? f.len : 0;
+static __device__ __forceinline__ BinSet binset_commit(const BinFetch& f) {
+  const int lane = __lane_id();
+  const int len = lane < f.n ? f.len : 0;
+  int x = len;                                 // inclusive prefix over lanes 0..7
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(x, off);
-      if (i >= off) x += y;
-    }
-    if (i < f.n) {
-      bs->start[i] = f.b0;
-      bs->pre[i + 1] = x;
-    }
-    if (i == 0) {
-      bs->n = f.n;
-      bs->pre[0] = 0;
-    }
+  for (int off = 1; off < kMaxRanges; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  const int excl = x - len;
+  const int pre = lane < f.n ? excl : 0x7fffffff;
+  const int del = f.b0 - excl;
+  BinSet bs;
+  bs.total = __builtin_amdgcn_readlane(x, kMaxRanges - 1);
+#pragma unroll
+  for (int j = 0; j < kMaxRanges; ++j) {
+    bs.pre[j] = __builtin_amdgcn_readlane(pre, j);
+    bs.delta[j] = __builtin_amdgcn_readlane(del, j);
   }
   __syncthreads();
+  return bs;
 }
 
 template <int PER, class Keep, class Body>
 static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs, const BinSet& bs, vi4* s_list,
                                                        Keep keep, Body body) {
-  const int total = bs.pre[bs.n];
+  const int total = bs.total;
   const int lane = __lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
   vi4* wl = s_list + (threadIdx.x >> 6) * kWaveList;
-  int cnt = 0;                                 // wavefront-uniform list length
-  int b = 0;                                   // bin of this lane's next record
+  int cnt = 0;                                 // wavefront-uniform list length (< 64)
   for (int base = 0; base < total; base += PER * kTileThreads) {
     // record indices first, then every load unconditionally (lanes past the
     // end reload the last record and drop it), so all PER loads are in flight
@@ -383,8 +389,10 @@ static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs
       const int f = base + i * kTileThreads + (int)threadIdx.x;
       k[i] = f < total;
       const int fc = k[i] ? f : total - 1;
-      while (fc >= bs.pre[b + 1]) ++b;
-      idx[i] = bs.start[b] + (fc - bs.pre[b]);
+      int d = bs.delta[0];
+#pragma unroll
+      for (int j = 1; j < kMaxRanges; ++j) d = fc >= bs.pre[j] ? bs.delta[j] : d;
+      idx[i] = fc + d;
     }
     vi4 r[PER];
 #pragma unroll
@@ -393,17 +401,15 @@ static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs
     for (int i = 0; i < PER; ++i) {
       const bool kk = k[i] && keep(r[i]);
       const unsigned long long m = __ballot(kk);
-      if (kk) wl[cnt + __popcll(m & ((1ull << lane) - 1ull))] = r[i];
+      const int pos = cnt + __popcll(m & below);
+      if (kk && pos < kWaveList) wl[pos] = r[i];
       cnt += __popcll(m);
-      if (cnt >= 64) {
+      if (cnt >= kWaveList) {
         wave_sync();
         body(wl[lane]);
-        const bool mv = lane < cnt - 64;
-        vi4 rest;
-        if (mv) rest = wl[64 + lane];
         wave_sync();
-        if (mv) wl[lane] = rest;
-        cnt -= 64;
+        if (kk && pos >= kWaveList) wl[pos - kWaveList] = r[i];
+        cnt -= kWaveList;
         wave_sync();
       }
     }
@@ -457,14 +463,14 @@ static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x
 
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
-                                       long long* s_y, vi4* s_list, BinSet* s_bs, const BinFetch& bins) {
+                                       long long* s_y, vi4* s_list, const BinFetch& bins) {
   const int nx = w.nx, ny = w.ny, N = w.n_part;
-  binset_commit(bins, s_bs);
+  const BinSet bs = binset_commit(bins);
   const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
   const int keep_x = tw + 3 <= nx ? tw + 2 : nx;     // largest kept home offset
   const int keep_y = th + 3 <= ny ? th + 2 : ny;
   for_bin_records<4>(
-      glbv<const vi4>(w.bin_rec), *s_bs, s_list,
+      glbv<const vi4>(w.bin_rec), bs, s_list,
       [&](const vi4& r) {
         const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
         const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);

@@ -508,7 +508,6 @@ static __device__ __forceinline__ BinFetch filter_fetch(const WorldDev& w, int t
 
 __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ BinSet s_bs;
   unsigned long long* s_win = (unsigned long long*)smem;
   vi4* s_list = (vi4*)(smem + window_bytes);
   float* s_regf = (float*)(smem + window_bytes);
@@ -531,12 +530,12 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     if (mode == kBinned) {
       const int S = reg + 6;                      // window side; window origin (xo - 3, yo - 3)
       for (int k = tid; k < S * S; k += kTileThreads) s_win[k] = 0;
-      binset_commit(filter_fetch(w, tl.y), &s_bs);
+      const BinSet bs = binset_commit(filter_fetch(w, tl.y));
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 3 <= nx ? reg + 2 : nx;
       const int keep_y = reg + 3 <= ny ? reg + 2 : ny;
       for_bin_records<4>(
-          glbv<const vi4>(w.bin_rec), s_bs, s_list,
+          glbv<const vi4>(w.bin_rec), bs, s_list,
           [&](const vi4& r) {
             const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
             const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
@@ -696,7 +695,6 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
   __shared__ long long s_fx[kSpreadCells];      // 64-bit fixed point, padded window
   __shared__ long long s_fy[kSpreadCells];
   __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
-  __shared__ BinSet s_bs;
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
@@ -714,8 +712,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
         s_fx[k] = 0;
         s_fy[k] = 0;
       }
-      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, &s_bs,
-                      spread_fetch(w, x0, y0, tw, th));
+      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, spread_fetch(w, x0, y0, tw, th));
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
