@@ -287,7 +287,6 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 // never idle through it.  body(r) may only use per-lane work and LDS atomics.
 constexpr int kWaveList = 64;              // records per wavefront list
 constexpr int kListBytes = (kTileThreads / 64) * kWaveList * 16;
-constexpr int kMaxRanges = 8;              // record ranges of a bin set
 
 // A bin set as every wavefront holds it, in scalar registers: range j covers
 // flat record numbers [pre[j], pre[j + 1]) (pre = 2^31 - 1 past the last
@@ -304,45 +303,50 @@ static __device__ __forceinline__ void wave_sync() {
 }
 
 // A bin set in flight: lane i < n of every wavefront holds the first record
-// and the length of range i.  Fetching it (the bin ranges of bin columns
-// tx[ntx] x rows ty[nty]) only issues loads; committing forms the prefix and
-// moves the set into scalar registers, then synchronises the block.
+// and the length of range i.  Fetching it only issues loads; committing forms
+// the prefix and moves the set into scalar registers, then synchronises the
+// block.
 struct BinFetch {
   int n;
   int b0, len;
 };
 
-static __device__ __forceinline__ BinFetch binset_fetch(const MC_GLOBAL int* bstart, int tiles_per_row, const int* tx,
-                                                        int ntx, const int* ty, int nty) {
-  // Bins of one tile row are stored by increasing column, so a run of
-  // consecutive columns is one contiguous record range.  The column list is a
-  // cyclic run, broken at most once where it wraps: at most two runs per row,
-  // so at most 2 * kMaxBinCols = kMaxRanges ranges.
-  int c0[2], m[2];
-  int nrun = 1;
-  c0[0] = tx[0];
-  m[0] = 1;
-  m[1] = 0;
-  c0[1] = 0;
-  for (int k = 1; k < ntx; ++k) {
-    if (tx[k] == tx[k - 1] + 1) {
-      ++m[nrun - 1];
-    } else {
-      c0[nrun] = tx[k];
-      m[nrun] = 1;
-      ++nrun;
+// The bins holding homes in [lox, hix] x [loy, hiy] (periodic), as runs of
+// consecutive bins (first, end), written to out[kMaxRanges] and padded with
+// (0, 0).  Bins of one tile row are stored by increasing column, so a run of
+// consecutive columns is one contiguous record range; the column list is a
+// cyclic run, broken at most once where it wraps: at most two runs per row.
+static __device__ void tile_runs(int lox, int hix, int loy, int hiy, int nx, int ny, int ntx, int2* out) {
+  int tx[kMaxBinCols], ty[kMaxBinCols];
+  const int ncx = bins_covering(lox, hix, nx, tx);
+  const int ncy = bins_covering(loy, hiy, ny, ty);
+  int n = 0;
+  for (int r = 0; r < ncy; ++r) {
+    int c = 0;
+    while (c < ncx) {
+      int m = 1;
+      while (c + m < ncx && tx[c + m] == tx[c + m - 1] + 1) ++m;
+      const int first = bin_at(tx[c], ty[r], ntx);
+      out[n++] = make_int2(first, first + m);
+      c += m;
     }
   }
+  for (; n < kMaxRanges; ++n) out[n] = make_int2(0, 0);
+}
+
+// Fetch of the bin set of tile `tile` (row-major index) for reader `kind`
+// (0 filter, 1 spread) from the world's run table.
+static __device__ __forceinline__ BinFetch binset_fetch(const WorldDev& w, int tile, int kind) {
+  const int lane = __lane_id();
   BinFetch f;
-  f.n = nrun * nty;
+  f.n = kMaxRanges;
   f.b0 = 0;
   f.len = 0;
-  const int i = __lane_id();
-  if (i < f.n) {
-    const int row = ty[i / nrun], j = i - (i / nrun) * nrun;
-    const int first = bin_at(c0[j], row, tiles_per_row);
-    f.b0 = bstart[first];
-    f.len = bstart[first + m[j]] - f.b0;
+  if (lane < kMaxRanges) {
+    const vi2 run = glbv<const vi2>(w.tile_rng)[((size_t)tile * 2 + kind) * kMaxRanges + lane];
+    const MC_GLOBAL int* bstart = glb(w.bin_start);
+    f.b0 = bstart[run.x];
+    f.len = bstart[run.y] - f.b0;
   }
   return f;
 }
@@ -453,12 +457,10 @@ static __device__ __forceinline__ int first_image(int i, int n) {
 constexpr int kSpreadSide = kTile + 6;
 constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
 
-// The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th].
-static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x0, int y0, int tw, int th) {
-  int txs[kMaxBinCols], tys[kMaxBinCols];
-  const int ntxs = bins_covering(x0 - 2, x0 + tw, w.nx, txs);
-  const int ntys = bins_covering(y0 - 2, y0 + th, w.ny, tys);
-  return binset_fetch(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys);
+// The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th]
+// (run table kind 1).
+static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x0, int y0) {
+  return binset_fetch(w, (y0 >> 5) * w.ntx + (x0 >> 5), 1);
 }
 
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,

@@ -25,6 +25,7 @@ __device__ __forceinline__ MC_GLOBAL T* glb(T* p) {
 // classes cannot be copied through address-space-qualified references).
 typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef int vi2 __attribute__((ext_vector_type(2)));
 typedef int vi4 __attribute__((ext_vector_type(4)));
 template <class V, class T>
 __device__ __forceinline__ MC_GLOBAL V* glbv(T* p) {
@@ -35,6 +36,7 @@ constexpr int kTile = 32;            // square grid tile of the filter and sprea
 constexpr int kTileThreads = 256;    // threads per block of the tile kernels
 constexpr int kCellsPerItem = 256;   // contiguous cells per fluid work item
 constexpr int kMaxRadius = 8;        // largest Gaussian truncation radius
+constexpr int kMaxRanges = 8;        // bin runs a tile reads (binned transfer)
 
 // Particle -> grid transfer modes (per world).
 enum TransferMode : int {
@@ -93,6 +95,8 @@ struct WorldDev {
   int* bin_start_next;                  // where the scan after integrate puts the next step's
                                         // starts (bin_start itself, except on the adjoint tape)
   int4* bin_rec;                        // [N] record: (x | y << 16 home cell, frac x, frac y, node)
+  const int2* tile_rng;                 // [ntx*nty][2][8] bin runs (first, end) that the filter (0)
+                                        // and the spread (1) of each tile read; unused runs (0, 0)
 };
 
 // A node pack: whole filaments with at most `pack` nodes, run by one block.
@@ -150,6 +154,8 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, hipEvent_t start,
                       hipEvent_t stop);
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+// set-up: the bin runs of every tile of an nx x ny world of Gaussian radius R
+void launch_tile_ranges(int nx, int ny, int R, int2* out, hipStream_t s);
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s);
 
 }  // namespace mc

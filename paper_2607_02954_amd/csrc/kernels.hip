@@ -496,14 +496,23 @@ static __device__ __forceinline__ int div_small(int k, float inv_d) {
 }
 
 // The bin set a filter tile reads: homes in [xo - 2, xo + reg] per axis
-// (xo = x0 - R - 1, reg = 34 + 2R), whose supports meet the density region.
+// (xo = x0 - R - 1, reg = 34 + 2R), whose supports meet the density region
+// (run table kind 0).
 static __device__ __forceinline__ BinFetch filter_fetch(const WorldDev& w, int tile) {
-  const int R = w.radius, reg = kRing + 2 * R;
-  const int xo = tile_x(tile) * kTile - R - 1, yo = tile_y(tile) * kTile - R - 1;
-  int txs[kMaxBinCols], tys[kMaxBinCols];
-  const int ntxs = bins_covering(xo - 2, xo + reg, w.nx, txs);
-  const int ntys = bins_covering(yo - 2, yo + reg, w.ny, tys);
-  return binset_fetch(glb(w.bin_start), w.ntx, txs, ntxs, tys, ntys);
+  return binset_fetch(w, tile_y(tile) * w.ntx + tile_x(tile), 0);
+}
+
+// Set-up: the runs of bins that the filter and the spread of every tile read
+// (they depend on the grid and the radius only).
+__global__ void k_tile_ranges(int nx, int ny, int R, int2* out) {
+  const int ntx = (nx + kTile - 1) / kTile, nty = (ny + kTile - 1) / kTile;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntx * nty; t += gridDim.x * blockDim.x) {
+    const int x0 = (t % ntx) * kTile, y0 = (t / ntx) * kTile;
+    const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
+    const int reg = kRing + 2 * R, xo = x0 - R - 1, yo = y0 - R - 1;
+    tile_runs(xo - 2, xo + reg, yo - 2, yo + reg, nx, ny, ntx, out + (size_t)(2 * t) * kMaxRanges);
+    tile_runs(x0 - 2, x0 + tw, y0 - 2, y0 + th, nx, ny, ntx, out + (size_t)(2 * t + 1) * kMaxRanges);
+  }
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
@@ -712,7 +721,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
         s_fx[k] = 0;
         s_fy[k] = 0;
       }
-      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, spread_fetch(w, x0, y0, tw, th));
+      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, spread_fetch(w, x0, y0));
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
@@ -1137,6 +1146,11 @@ void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStre
     k_integrate_tile<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
     k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
   }
+}
+
+void launch_tile_ranges(int nx, int ny, int R, int2* out, hipStream_t s) {
+  const int nt = ((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
+  k_tile_ranges<<<(nt + 255) / 256, 256, 0, s>>>(nx, ny, R, out);
 }
 
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s) {

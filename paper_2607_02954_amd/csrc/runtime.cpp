@@ -90,6 +90,7 @@ struct WorldBufs {
   int* bin_fill = nullptr;
   int* bin_start = nullptr;
   int4* bin_rec = nullptr;
+  int2* tile_rng = nullptr;
 };
 
 inline int mode_of(const sim_params& p) {
@@ -123,6 +124,7 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.bin_fill = c.take<int>(nt);
     b.bin_start = c.take<int>(nt + 1);
     b.bin_rec = c.take<int4>(N);
+    b.tile_rng = c.take<int2>((size_t)tiles_x(p) * tiles_y(p) * 2 * mc::kMaxRanges);
   }
 }
 
@@ -305,6 +307,7 @@ struct Engine {
     d.bin_start = s.b.bin_start;
     d.bin_start_next = s.b.bin_start;
     d.bin_rec = s.b.bin_rec;
+    d.tile_rng = s.b.tile_rng;
     return d;
   }
 
@@ -649,6 +652,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
     const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_fill, nt);
+    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, sl.b.tile_rng, s);
   }
   if (hipGetLastError() != hipSuccess) {
     delete w;
@@ -1248,6 +1252,7 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
     const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_fill, nt);
+    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, s.b.tile_rng, e.stream);
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, e.stream, (int*)(e.flags + w), (size_t)1);
   HIPCHK(hipGetLastError());
