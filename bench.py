@@ -277,7 +277,18 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"calibration_copy_bytes_each_way": n * 4, "launches": 3}), flush=True)
+        # the same copy timed (read + write bytes over the launch time): the
+        # HBM rate a plain streaming kernel reaches on this device
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        t0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        print(json.dumps({"calibration_copy_bytes_each_way": n * 4, "launches": 3 + reps,
+                          "copy_ms": ms, "copy_GBs": 2 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
         return
 
     world = wl.scaling_population(args.seed)

@@ -479,8 +479,12 @@ __device__ __forceinline__ vf2 gather_force(const MC_GLOBAL int* start, const MC
 constexpr int kRing = kTile + 2;                    // tile plus the one-cell ring
 constexpr int kRegion = kRing + 2 * kMaxRadius;     // largest density region side
 
+// Window rows are kWinPad elements longer than the window side: an even
+// row length of 64-bit words puts vertically adjacent cells, which nodes
+// next to each other on a chain often deposit to at once, in the same LDS bank.
+constexpr int kWinPad = 1;
 static __host__ __device__ constexpr int filter_window_bytes(int max_radius) {
-  return (kRing + 2 * max_radius + 6) * (kRing + 2 * max_radius + 6) * 8;
+  return (kRing + 2 * max_radius + 6) * (kRing + 2 * max_radius + 6 + kWinPad) * 8;
 }
 static __host__ __device__ constexpr int filter_list_bytes(int max_radius) {
   return (kRing + 2 * max_radius) * (kRing + 2 * max_radius) * 4 > kListBytes
@@ -538,7 +542,8 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     float* s_st = s_mid + reg * kRing;
     if (mode == kBinned) {
       const int S = reg + 6;                      // window side; window origin (xo - 3, yo - 3)
-      for (int k = tid; k < S * S; k += kTileThreads) s_win[k] = 0;
+      const int P = S + kWinPad;                  // row pitch
+      for (int k = tid; k < S * P; k += kTileThreads) s_win[k] = 0;
       const BinSet bs = binset_commit(filter_fetch(w, tl.y));
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 3 <= nx ? reg + 2 : nx;
@@ -556,11 +561,11 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
             unsigned qx[4], qy[4];
             peskin4_quant(__int_as_float(r.y), qx);
             peskin4_quant(__int_as_float(r.z), qy);
-            unsigned long long* p = s_win + dy * S + dx;
+            unsigned long long* p = s_win + dy * P + dx;
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
-              for (int a = 0; a < 4; ++a) atomicAdd(p + b * S + a, weight_product(qx[a], qy[b]));
+              for (int a = 0; a < 4; ++a) atomicAdd(p + b * P + a, weight_product(qx[a], qy[b]));
           });
       // (the list area is free again after the barrier that ends for_bin_records)
       const bool single = reg + 3 <= nx && reg + 3 <= ny;   // one image per needed cell
@@ -568,11 +573,11 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
         const int r = div_small(k, inv_reg), c = k - r * reg;
         unsigned long long v;
         if (single) {
-          v = s_win[(r + 3) * S + c + 3];
+          v = s_win[(r + 3) * P + c + 3];
         } else {
           v = 0;
           for (int cy = first_image(r, ny); cy < S; cy += ny)
-            for (int cx = first_image(c, nx); cx < S; cx += nx) v += s_win[cy * S + cx];
+            for (int cx = first_image(c, nx); cx < S; cx += nx) v += s_win[cy * P + cx];
         }
         s_regf[k] = density_to_float(v);
       }
