@@ -234,6 +234,21 @@ def test_small_and_ragged_grids(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_partial_tiles_and_radii(mode):
+    # four or more tiles per axis with a narrow partial last tile (a filter or
+    # spread window then reaches across it into the tile beyond), with the
+    # smallest and largest Gaussian radii: every bin run and padded window
+    # shape of the binned transfer at a periodic seam
+    sim = _sim()
+    for (nx, ny, R, sig, lens) in [(100, 97, 8, 2.0, [30, 12, 1, 50, 8]),
+                                   (130, 66, 1, 0.5, [25, 7, 80, 2]),
+                                   (97, 129, 6, 1.5, [40, 3, 60, 2, 33])]:
+        w = wl.random_world(11, nx, ny, lens, amp=0.5)
+        ex, eu = _rollout_compare(sim, w, 8, mode, repulse_radius=R, sigma_repulse=sig)
+        print(f"{nx}x{ny} R={R}: e_x={ex:.2e} e_u={eu:.2e}")
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_scaling_workload_full_size(mode):
     # the benchmark's million-node workload, in the benchmark's launch
     # configuration (captured-graph rollout), two steps, every node and cell
