@@ -931,11 +931,9 @@ __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int 
   vf2 v[kIt];
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
-    const int k = (int)threadIdx.x + kTileThreads * i;
-    if (k < kStage * kStage) {
-      const int r = k / kStage, c = k - (k / kStage) * kStage;
-      v[i] = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
-    }
+    const int k = min((int)threadIdx.x + kTileThreads * i, kStage * kStage - 1);
+    const int r = k / kStage, c = k - (k / kStage) * kStage;
+    v[i] = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
   }
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
@@ -964,16 +962,17 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
     const float kr = w.k_rep;
     const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
     const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
-    // this thread's first record is loaded beside the staged field (record 0
-    // always exists: the record buffer holds at least one)
-    const vi4 r0 = recs[e0 + (int)threadIdx.x < e1 ? e0 + (int)threadIdx.x : 0];
+    // this thread's first two records and their forces are loaded beside the
+    // staged field, unconditionally (record 0 and node 0 always exist: the
+    // library's buffers hold at least one)
+    const int ea = e0 + (int)threadIdx.x, eb = ea + kTileThreads;
+    const bool has0 = ea < e1, has1 = eb < e1;
+    const vi4 r0 = recs[has0 ? ea : 0];
+    const vi4 r1 = recs[has1 ? eb : 0];
     stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_gx, s_gy);
-    const bool has0 = e0 + (int)threadIdx.x < e1;
-    float f0x = 0.f, f0y = 0.f;                 // in flight across the barrier
-    if (has0) {
-      f0x = fel[r0.w];
-      f0y = fel[N + r0.w];
-    }
+    const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
+    const float f0x = fel[g0], f0y = fel[N + g0];   // in flight across the barrier
+    const float f1x = fel[g1], f1y = fel[N + g1];
     __syncthreads();
     auto node = [&](const vi4& r, float fex, float fey) {
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;   // home in the tile
@@ -997,9 +996,10 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
       fel[r.w] = fex - kr * gx;
       fel[N + r.w] = fey - kr * gy;
     };
-    // the first record (already loaded), then any further ones
+    // the first two records (already loaded), then any further ones
     if (has0) node(r0, f0x, f0y);
-    for (int e = e0 + threadIdx.x + kTileThreads; e < e1; e += kTileThreads) {
+    if (has1) node(r1, f1x, f1y);
+    for (int e = eb + kTileThreads; e < e1; e += kTileThreads) {
       const vi4 r = recs[e];
       node(r, fel[r.w], fel[N + r.w]);
     }
@@ -1025,15 +1025,21 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
     MC_GLOBAL float* frac_out = glb(w.frac_out);
     const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
     const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
-    // this thread's first record is loaded beside the staged field (record 0
-    // always exists: the record buffer holds at least one)
-    const vi4 r0 = recs[e0 + (int)threadIdx.x < e1 ? e0 + (int)threadIdx.x : 0];
+    // this thread's first two records and their cells are loaded beside the
+    // staged field, unconditionally (record 0 always exists: the record
+    // buffer holds at least one; an empty world has no positions at all)
+    const int ea = e0 + (int)threadIdx.x, eb = ea + kTileThreads;
+    const bool has0 = ea < e1, has1 = eb < e1;
+    const vi4 r0 = recs[has0 ? ea : 0];
+    const vi4 r1 = recs[has1 ? eb : 0];
     stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_ux, s_uy);
-    const bool has0 = e0 + (int)threadIdx.x < e1;
-    int c0x = 0, c0y = 0;                       // in flight across the barrier
-    if (has0) {                                 // (an empty world has no positions at all)
-      c0x = cell[r0.w];
-      c0y = cell[N + r0.w];
+    int c0x = 0, c0y = 0, c1x = 0, c1y = 0;    // in flight across the barrier
+    if (N > 0) {
+      const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
+      c0x = cell[g0];
+      c0y = cell[N + g0];
+      c1x = cell[g1];
+      c1y = cell[N + g1];
     }
     __syncthreads();
     auto node = [&](const vi4& r, int cxo, int cyo) {
@@ -1071,9 +1077,10 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
       // next step's tile-bin counts
       agg_atomic_inc(glb(w.bin_cnt), bin_of(wrap_index(ncx, nx), wrap_index(ncy, ny), w.ntx), true);
     };
-    // the first record (already loaded), then any further ones
+    // the first two records (already loaded), then any further ones
     if (has0) node(r0, c0x, c0y);
-    for (int e = e0 + threadIdx.x + kTileThreads; e < e1; e += kTileThreads) {
+    if (has1) node(r1, c1x, c1y);
+    for (int e = eb + kTileThreads; e < e1; e += kTileThreads) {
       const vi4 r = recs[e];
       node(r, cell[r.w], cell[N + r.w]);
     }
