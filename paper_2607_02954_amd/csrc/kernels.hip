@@ -2,9 +2,8 @@
 //
 // Step order (one launch per sub-step, all worlds of a table at once):
 //   k_elastic     S0 actuation + S1 PBD Cosserat projection (Eqs. 1-4) -> node
-//                 elastic force; registers each node with the tiles it affects
-//   k_bin_scan    per-world prefix over home-tile counts (binned transfer)
-//   k_bin_fill    node records into their home-tile bins (binned transfer)
+//                 elastic force; writes each node's record into its
+//                 home-tile bin (binned transfer)
 //   k_filter      S2 deposit + S3 separable circular Gaussian filter on a
 //                 32x32 tile with an (R+1)-cell halo, all in LDS; writes the
 //                 central difference G = D s~ of the filtered density
@@ -12,7 +11,10 @@
 //   k_spread      S5 force spread onto a 32x32 tile, summed in LDS
 //   k_lbm         S6 D2Q9 TRT/Guo collision and push streaming over
 //                 contiguous cells; exports u
-//   k_integrate   S7 gather u at the nodes and move them
+//   k_integrate   S7 gather u at the nodes and move them; counts the nodes
+//                 of every home tile at the new positions (binned transfer)
+//   k_bin_scan    per-world prefix of those counts: the bin starts of the
+//                 next step (binned transfer)
 //
 // Particle -> grid transfer has three modes, chosen per world:
 //   binned  nodes are binned by the 32x32 tile of their home cell; each tile
@@ -38,9 +40,9 @@ namespace mc {
 
 
 // ---------------------------------------------------------------------------
-// S0 + S1: actuation and PBD elastic force.  Then, by transfer mode: tile-bin
-// counts (binned), home-cell key and rank (sorted) or the density deposit
-// with global atomics (direct).
+// S0 + S1: actuation and PBD elastic force.  Then, by transfer mode: the
+// node's record in its home-tile bin (binned), home-cell key and rank
+// (sorted) or the density deposit with global atomics (direct).
 // ---------------------------------------------------------------------------
 template <int PACK>
 __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W, Tables T) {
@@ -204,8 +206,8 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
 }
 
 // ---------------------------------------------------------------------------
-// Binned transfer: per-world exclusive scan of tile counts, then every node
-// writes a record (home cell, fractions, index) into each bin it belongs to.
+// Binned transfer: per-world exclusive scan of the home-tile counts; every
+// node then writes one record (home cell, fractions, index) into its bin.
 // ---------------------------------------------------------------------------
 // next: write the starts for the next step's bins (bin_start_next; after
 // integrate) rather than for the current positions (bin_start; pre-pass).
