@@ -875,6 +875,7 @@ struct AdjLayout {
   float2* Gbar = nullptr;
   float* sbar = nullptr;
   float* Fbar = nullptr;
+  mc::Ctl* ctl = nullptr;            // m + 1 control words: step j reads ctl[j], writes ctl[j + 1]
 };
 
 void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) {
@@ -917,6 +918,7 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
   L.Gbar = c.take<float2>(L.ncell);
   L.sbar = c.take<float>(L.ncell);
   L.Fbar = c.take<float>(2 * L.N);
+  L.ctl = c.take<mc::Ctl>(m + 1);
   L.bytes = c.off;
 }
 
@@ -979,6 +981,8 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     d.bin_start = L.bstart[j];
     d.bin_start_next = L.bstart[j + 1];
     d.bin_rec = L.brec[j];
+    d.ctl_src = L.ctl + j;                   // the fluid kernel of step j advances it into j + 1
+    d.ctl_dst = L.ctl + j + 1;
     d.s = nullptr;
     hd[j] = d;
   }
@@ -1010,12 +1014,11 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     }
     HIPCHK(hipMemcpyAsync(L.g[0], ck + align_up(4 * N * 4), 9 * ncell * 4, hipMemcpyDeviceToDevice, st));
     // recompute the segment forward, writing every step's fields to the tape
-    for (int j = 0; j < m; ++j) {
-      sim_status r = e.set_ctl(0, t0 + k0 + j, 1);
-      if (r) return r;
-      if (j == 0) mc::launch_bin_prepass(L.desc, e.tab, g, st);
-      e.enqueue_step_with(L.desc + j, g, st);
-    }
+    // (one control word write per segment: each step's fluid kernel sets the
+    // next step's time index)
+    mc::launch_set_ctl(L.ctl, t0 + k0, m, st);
+    mc::launch_bin_prepass(L.desc, e.tab, g, st);
+    for (int j = 0; j < m; ++j) e.enqueue_step_with(L.desc + j, g, st);
     HIPCHK(hipGetLastError());
     // reverse the segment step by step
     for (int j = m - 1; j >= 0; --j) {
