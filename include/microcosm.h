@@ -57,9 +57,10 @@ typedef enum sim_status {
 
 /* sim_params.flags */
 /* Particle -> grid transfer (deposit and force spread).  Default (no flag):
- * nodes are binned by the 32x32 grid tiles their support touches and every
- * tile sums its nodes' contributions in on-chip memory before writing each
- * cell once.  The two flags are exclusive. */
+ * nodes are binned by the 32x32 grid tile of their home cell; every tile
+ * reads the bins of its neighbourhood, sums the contributions that reach it
+ * in on-chip memory (integer fixed point: results are bitwise reproducible)
+ * and writes each cell once.  The two flags are exclusive. */
 enum {
   SIM_SPLAT_SORTED = 1u << 0, /* deterministic: counting sort by home cell, fixed-order
                                  segmented sums; results are bitwise reproducible       */
@@ -156,8 +157,10 @@ sim_status sim_backward(sim_world *w, int64_t t0, int32_t n_steps, int32_t ckpt_
                         void *adj_ws, size_t adj_ws_bytes);
 
 /* Wait for the world's stream; report asynchronous HIP errors, the sticky
- * Mach/NaN flag (SIM_E_UNSTABLE), and SIM_E_STATE if a node found its tile
- * bin full, which only happens when sub-steps are run out of order. */
+ * Mach/NaN flag (SIM_E_UNSTABLE), and SIM_E_STATE if the tile bins did not
+ * match the positions (a node found its bin full, or the bin counts did not
+ * add up to the node count), which only happens when sub-steps are run out
+ * of order. */
 sim_status sim_sync(sim_world *w);
 /* Clear the sticky Mach/NaN flag (enqueued on the stream). */
 sim_status sim_clear_flags(sim_world *w);
