@@ -521,6 +521,54 @@ __global__ void k_tile_ranges(int nx, int ny, int R, int2* out) {
   }
 }
 
+// The two passes of the separable Gaussian (radius R) over the density
+// region s_regf (reg x reg, reg = 34 + 2R) into the filtered tile-plus-ring
+// s_st (34 x 34), through s_mid (reg rows x 34).  Every thread forms two
+// adjacent outputs from taps read as aligned pairs (rows have even lengths);
+// each output is summed in the same order as a one-output loop would.
+// Ends with a barrier.
+template <int R>
+static __device__ __forceinline__ void filter_passes(const float* s_regf, float* s_mid, float* s_st, const float* g) {
+  constexpr int reg = kRing + 2 * R, kHalf = kRing / 2;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < reg * kHalf; k += kTileThreads) {
+    const int r = k / kHalf, c = 2 * (k - (k / kHalf) * kHalf);
+    const vf2* row = (const vf2*)(s_regf + r * reg + c);   // cells c .. c + 2R + 1 of row r
+    float v[2 * R + 2];
+#pragma unroll
+    for (int i = 0; i <= R; ++i) {
+      const vf2 t = row[i];
+      v[2 * i] = t.x;
+      v[2 * i + 1] = t.y;
+    }
+    float a0 = g[0] * v[R], a1 = g[0] * v[R + 1];
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {
+      a0 += g[m] * (v[R - m] + v[R + m]);
+      a1 += g[m] * (v[R + 1 - m] + v[R + 1 + m]);
+    }
+    const vf2 out = {a0, a1};
+    *(vf2*)(s_mid + r * kRing + c) = out;
+  }
+  __syncthreads();
+  for (int k = tid; k < kRing * kHalf; k += kTileThreads) {
+    const int r = k / kHalf, c = 2 * (k - (k / kHalf) * kHalf);
+    const vf2* col = (const vf2*)(s_mid + (r + R) * kRing + c);
+    vf2 t[2 * R + 1];
+#pragma unroll
+    for (int m = -R; m <= R; ++m) t[m + R] = col[m * kHalf];
+    float a0 = g[0] * t[R].x, a1 = g[0] * t[R].y;
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {
+      a0 += g[m] * (t[R - m].x + t[R + m].x);
+      a1 += g[m] * (t[R - m].y + t[R + m].y);
+    }
+    const vf2 out = {a0, a1};
+    *(vf2*)(s_st + r * kRing + c) = out;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned long long* s_win = (unsigned long long*)smem;
@@ -601,26 +649,16 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
 #pragma unroll
     for (int m = 0; m <= kMaxRadius; ++m) g[m] = w.gtap[m];
     __syncthreads();
-    for (int k = tid; k < reg * kRing; k += kTileThreads) {
-      const int r = k / kRing, c = k - (k / kRing) * kRing;
-      const float* row = s_regf + r * reg + c + R;
-      float acc = g[0] * row[0];
-#pragma unroll
-      for (int m = 1; m <= kMaxRadius; ++m)
-        if (m <= R) acc += g[m] * (row[-m] + row[m]);
-      s_mid[r * kRing + c] = acc;
+    switch (R) {                                  // uniform: the world's radius
+      case 1: filter_passes<1>(s_regf, s_mid, s_st, g); break;
+      case 2: filter_passes<2>(s_regf, s_mid, s_st, g); break;
+      case 3: filter_passes<3>(s_regf, s_mid, s_st, g); break;
+      case 4: filter_passes<4>(s_regf, s_mid, s_st, g); break;
+      case 5: filter_passes<5>(s_regf, s_mid, s_st, g); break;
+      case 6: filter_passes<6>(s_regf, s_mid, s_st, g); break;
+      case 7: filter_passes<7>(s_regf, s_mid, s_st, g); break;
+      default: filter_passes<8>(s_regf, s_mid, s_st, g); break;
     }
-    __syncthreads();
-    for (int k = tid; k < kRing * kRing; k += kTileThreads) {
-      const int r = k / kRing, c = k - (k / kRing) * kRing;
-      const float* col = s_mid + (r + R) * kRing + c;
-      float acc = g[0] * col[0];
-#pragma unroll
-      for (int m = 1; m <= kMaxRadius; ++m)
-        if (m <= R) acc += g[m] * (col[-m * kRing] + col[m * kRing]);
-      s_st[k] = acc;
-    }
-    __syncthreads();
     MC_GLOBAL vf2* grad = glbv<vf2>(w.grad);
     for (int k = tid; k < kTile * kTile; k += kTileThreads) {
       const int r = k >> 5, c = k & (kTile - 1);
