@@ -965,8 +965,7 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int kStage = kTile + 3;
 
-__device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, float* sx,
-                                            float* sy) {
+__device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, vf2* st) {
   constexpr int kIt = (kStage * kStage + kTileThreads - 1) / kTileThreads;
   vf2 v[kIt];
 #pragma unroll
@@ -978,16 +977,33 @@ __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int 
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
     const int k = (int)threadIdx.x + kTileThreads * i;
-    if (k < kStage * kStage) {
-      sx[k] = v[i].x;
-      sy[k] = v[i].y;
-    }
+    if (k < kStage * kStage) st[k] = v[i];
   }
 }
 
+// 4x4 kernel-weighted sum of a staged vector field at a node whose home
+// cell sits at (lx, ly) of the tile (weights wx, wy along x and y).
+__device__ __forceinline__ vf2 gather_staged(const vf2* st, int lx, int ly, const float* wx, const float* wy) {
+  float gx = 0.f, gy = 0.f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const vf2* row = st + (ly + b) * kStage + lx;
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const vf2 t = row[a];
+      ax += wx[a] * t.x;
+      ay += wx[a] * t.y;
+    }
+    gx += wy[b] * ax;
+    gy += wy[b] * ay;
+  }
+  const vf2 out = {gx, gy};
+  return out;
+}
+
 __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* __restrict__ W, Tables T) {
-  __shared__ float s_gx[kStage * kStage];
-  __shared__ float s_gy[kStage * kStage];
+  __shared__ vf2 s_g[kStage * kStage];        // staged gradient, x and y interleaved
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
@@ -1009,7 +1025,7 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
     const bool has0 = ea < e1, has1 = eb < e1;
     const vi4 r0 = recs[has0 ? ea : 0];
     const vi4 r1 = recs[has1 ? eb : 0];
-    stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_gx, s_gy);
+    stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_g);
     const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
     const float f0x = fel[g0], f0y = fel[N + g0];   // in flight across the barrier
     const float f1x = fel[g1], f1y = fel[N + g1];
@@ -1019,22 +1035,9 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
       float wx[4], wy[4];
       peskin4(__int_as_float(r.y), wx);
       peskin4(__int_as_float(r.z), wy);
-      float gx = 0.f, gy = 0.f;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const float* rx = s_gx + (ly + b) * kStage + lx;
-        const float* ry = s_gy + (ly + b) * kStage + lx;
-        float ax = 0.f, ay = 0.f;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ax += wx[a] * rx[a];
-          ay += wx[a] * ry[a];
-        }
-        gx += wy[b] * ax;
-        gy += wy[b] * ay;
-      }
-      fel[r.w] = fex - kr * gx;
-      fel[N + r.w] = fey - kr * gy;
+      const vf2 G = gather_staged(s_g, lx, ly, wx, wy);
+      fel[r.w] = fex - kr * G.x;
+      fel[N + r.w] = fey - kr * G.y;
     };
     // the first two records (already loaded), then any further ones
     if (has0) node(r0, f0x, f0y);
@@ -1048,8 +1051,7 @@ __global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* _
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
-  __shared__ float s_ux[kStage * kStage];
-  __shared__ float s_uy[kStage * kStage];
+  __shared__ vf2 s_u[kStage * kStage];        // staged velocity, x and y interleaved
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
@@ -1072,7 +1074,7 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
     const bool has0 = ea < e1, has1 = eb < e1;
     const vi4 r0 = recs[has0 ? ea : 0];
     const vi4 r1 = recs[has1 ? eb : 0];
-    stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_ux, s_uy);
+    stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_u);
     int c0x = 0, c0y = 0, c1x = 0, c1y = 0;    // in flight across the barrier
     if (N > 0) {
       const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
@@ -1088,20 +1090,8 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
       float wx[4], wy[4];
       peskin4(fx, wx);
       peskin4(fy, wy);
-      float dux = 0.f, duy = 0.f;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const float* rx = s_ux + (ly + b) * kStage + lx;
-        const float* ry = s_uy + (ly + b) * kStage + lx;
-        float ax = 0.f, ay = 0.f;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ax += wx[a] * rx[a];
-          ay += wx[a] * ry[a];
-        }
-        dux += wy[b] * ax;
-        duy += wy[b] * ay;
-      }
+      const vf2 du = gather_staged(s_u, lx, ly, wx, wy);
+      const float dux = du.x, duy = du.y;
       const int gi = r.w;
       float nfx = fx + dux, nfy = fy + duy;
       const float flx = floorf(nfx), fly = floorf(nfy);
