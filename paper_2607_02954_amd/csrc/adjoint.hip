@@ -30,8 +30,8 @@ constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registe
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __restrict__ W, Tables T, const float* v,
                                                     float scale_is_rep, float2* out) {
-  __shared__ long long s_x[kSpreadCells];
-  __shared__ long long s_y[kSpreadCells];
+  __shared__ __align__(16) long long s_x[kSpreadCells];
+  __shared__ __align__(16) long long s_y[kSpreadCells];
   __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
   const int nt = *T.n_tiles;
   const XcdLoop tiles(nt);
@@ -42,10 +42,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __r
     const int x0 = tile_x(tl.y) * kTile;
     const int y0 = tile_y(tl.y) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
-    for (int k = threadIdx.x; k < kSpreadCells; k += kTileThreads) {
-      s_x[k] = 0;
-      s_y[k] = 0;
-    }
+    zero_lds_u64(s_x, kSpreadCells);
+    zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
     tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, spread_fetch(w, x0, y0));

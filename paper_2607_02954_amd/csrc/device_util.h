@@ -225,6 +225,15 @@ struct XcdLoop {
   }
 };
 
+// Clear n 64-bit words of LDS at a 16-byte aligned address, 16 bytes per
+// store (block-wide; the caller synchronises before use).
+static __device__ __forceinline__ void zero_lds_u64(void* p, int n) {
+  vi4* q = (vi4*)p;
+  const vi4 z = {0, 0, 0, 0};
+  for (int k = threadIdx.x; k < (n >> 1); k += blockDim.x) q[k] = z;
+  if ((n & 1) && threadIdx.x == 0) ((long long*)p)[n - 1] = 0;
+}
+
 // Wavefront-aggregated atomic increment: lanes that target the same counter
 // are served by one atomic from a leader lane.  Returns, for lanes with `has`,
 // a distinct slot (the counter's old value plus the lane's rank among the

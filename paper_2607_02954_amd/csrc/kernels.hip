@@ -593,7 +593,7 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     if (mode == kBinned) {
       const int S = reg + 6;                      // window side; window origin (xo - 3, yo - 3)
       const int P = S + kWinPad;                  // row pitch
-      for (int k = tid; k < S * P; k += kTileThreads) s_win[k] = 0;
+      zero_lds_u64(s_win, S * P);
       const BinSet bs = binset_commit(filter_fetch(w, tl.y));
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 3 <= nx ? reg + 2 : nx;
@@ -746,8 +746,8 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
 // tile is written once.  Direct mode accumulates in k_repulse instead.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restrict__ W, Tables T) {
-  __shared__ long long s_fx[kSpreadCells];      // 64-bit fixed point, padded window
-  __shared__ long long s_fy[kSpreadCells];
+  __shared__ __align__(16) long long s_fx[kSpreadCells];   // 64-bit fixed point, padded window
+  __shared__ __align__(16) long long s_fy[kSpreadCells];
   __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
@@ -762,10 +762,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
     const int y0 = tile_y(tl.y) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
     if (mode == kBinned) {
-      for (int k = tid; k < kSpreadCells; k += kTileThreads) {
-        s_fx[k] = 0;
-        s_fy[k] = 0;
-      }
+      zero_lds_u64(s_fx, kSpreadCells);
+      zero_lds_u64(s_fy, kSpreadCells);
       tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, spread_fetch(w, x0, y0));
       __syncthreads();
     }
