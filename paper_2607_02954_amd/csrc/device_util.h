@@ -466,6 +466,23 @@ static __device__ __forceinline__ int first_image(int i, int n) {
 constexpr int kSpreadSide = kTile + 6;
 constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
 
+// Whether a node with home cell (hx, hy) reaches the spread window of the
+// tile at (x0, y0) of size tw x th (the keep rule of tile_spread_vec).
+struct SpreadKeep {
+  int ox, oy, kx, ky, nx, ny;
+  __device__ __forceinline__ SpreadKeep(const WorldDev& w, int x0, int y0, int tw, int th) {
+    nx = w.nx;
+    ny = w.ny;
+    ox = wrap_index(x0 - 3, nx);
+    oy = wrap_index(y0 - 3, ny);
+    kx = tw + 3 <= nx ? tw + 2 : nx;
+    ky = th + 3 <= ny ? th + 2 : ny;
+  }
+  __device__ __forceinline__ bool operator()(const vi4& r) const {
+    return wrap_near((r.x & 0xffff) - 1 - ox, nx) <= kx && wrap_near((r.x >> 16) - 1 - oy, ny) <= ky;
+  }
+};
+
 // The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th]
 // (run table kind 1).
 static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x0, int y0) {
@@ -474,14 +491,15 @@ static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x
 
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
-                                       long long* s_y, vi4* s_list, const BinFetch& bins) {
+                                       long long* s_y, vi4* s_list, const MC_GLOBAL vi4* recs,
+                                       const BinFetch& bins) {
   const int nx = w.nx, ny = w.ny, N = w.n_part;
   const BinSet bs = binset_commit(bins);
   const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
   const int keep_x = tw + 3 <= nx ? tw + 2 : nx;     // largest kept home offset
   const int keep_y = th + 3 <= ny ? th + 2 : ny;
   for_bin_records<4>(
-      glbv<const vi4>(w.bin_rec), bs, s_list,
+      recs, bs, s_list,
       [&](const vi4& r) {
         const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
         const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);

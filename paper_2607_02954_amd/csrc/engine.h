@@ -37,6 +37,7 @@ constexpr int kTileThreads = 256;    // threads per block of the tile kernels
 constexpr int kCellsPerItem = 256;   // contiguous cells per fluid work item
 constexpr int kMaxRadius = 8;        // largest Gaussian truncation radius
 constexpr int kMaxRanges = 8;        // bin runs a tile reads (binned transfer)
+constexpr int kSpreadCap = 1024;     // records a tile's spread list holds (else it reads the bins)
 
 // Particle -> grid transfer modes (per world).
 enum TransferMode : int {
@@ -95,6 +96,8 @@ struct WorldDev {
   int* bin_start_next;                  // where the scan after integrate puts the next step's
                                         // starts (bin_start itself, except on the adjoint tape)
   int4* bin_rec;                        // [N] record: (x | y << 16 home cell, frac x, frac y, node)
+  int4* sp_rec;                         // [ntx*nty][kSpreadCap] the records each tile's spread reads,
+  int* sp_cnt;                          // [ntx*nty] and their number: both written by the filter
   const int2* tile_rng;                 // [ntx*nty][2][8] bin runs (first, end) that the filter (0)
                                         // and the spread (1) of each tile read; unused runs (0, 0)
 };

@@ -575,6 +575,7 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
   vi4* s_list = (vi4*)(smem + window_bytes);
   float* s_regf = (float*)(smem + window_bytes);
   float* s_mid = (float*)smem;
+  __shared__ int s_spn;                          // records appended to the spread list
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
@@ -594,10 +595,16 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
       const int S = reg + 6;                      // window side; window origin (xo - 3, yo - 3)
       const int P = S + kWinPad;                  // row pitch
       zero_lds_u64(s_win, S * P);
+      if (tid == 0) s_spn = 0;
       const BinSet bs = binset_commit(filter_fetch(w, tl.y));
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 3 <= nx ? reg + 2 : nx;
       const int keep_y = reg + 3 <= ny ? reg + 2 : ny;
+      // the records this tile's spread needs (a subset of the filter's: its
+      // window lies inside the filter's) go to the tile's spread list
+      const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+      const SpreadKeep sp_keep(w, x0, y0, min(kTile, nx - x0), min(kTile, ny - y0));
+      MC_GLOBAL vi4* sp_rec = glbv<vi4>(w.sp_rec) + (size_t)tix * kSpreadCap;
       for_bin_records<4>(
           glbv<const vi4>(w.bin_rec), bs, s_list,
           [&](const vi4& r) {
@@ -616,7 +623,19 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
             for (int b = 0; b < 4; ++b)
 #pragma unroll
               for (int a = 0; a < 4; ++a) atomicAdd(p + b * P + a, weight_product(qx[a], qy[b]));
+            // append to the spread list: one LDS atomic per wavefront
+            const bool sp = sp_keep(r);
+            const unsigned long long m = __ballot(sp);
+            if (m) {
+              const int leader = __ffsll((unsigned long long)m) - 1;
+              int base = 0;
+              if (__lane_id() == leader) base = atomicAdd(&s_spn, __popcll(m));
+              base = __shfl(base, leader);
+              const int slot = base + __popcll(m & ((1ull << __lane_id()) - 1ull));
+              if (sp && slot < kSpreadCap) sp_rec[slot] = r;
+            }
           });
+      if (tid == 0) glb(w.sp_cnt)[tix] = s_spn;   // (for_bin_records ended with a barrier)
       // (the list area is free again after the barrier that ends for_bin_records)
       const bool single = reg + 3 <= nx && reg + 3 <= ny;   // one image per needed cell
       for (int k = tid; k < reg * reg; k += kTileThreads) {
@@ -764,7 +783,20 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
     if (mode == kBinned) {
       zero_lds_u64(s_fx, kSpreadCells);
       zero_lds_u64(s_fy, kSpreadCells);
-      tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, spread_fetch(w, x0, y0));
+      // the tile's record list from the filter (one range), or, if it
+      // overflowed, the bins of the neighbourhood
+      const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+      const int cnt = glb(w.sp_cnt)[tix];
+      if (cnt >= 0 && cnt <= kSpreadCap) {
+        BinFetch f;
+        f.n = 1;
+        f.b0 = tix * kSpreadCap;
+        f.len = __lane_id() == 0 ? cnt : 0;
+        tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, glbv<const vi4>(w.sp_rec), f);
+      } else {
+        tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, glbv<const vi4>(w.bin_rec),
+                        spread_fetch(w, x0, y0));
+      }
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);

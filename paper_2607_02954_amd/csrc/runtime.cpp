@@ -91,6 +91,8 @@ struct WorldBufs {
   int* bin_start = nullptr;
   int4* bin_rec = nullptr;
   int2* tile_rng = nullptr;
+  int4* sp_rec = nullptr;
+  int* sp_cnt = nullptr;
 };
 
 inline int mode_of(const sim_params& p) {
@@ -125,6 +127,8 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.bin_start = c.take<int>(nt + 1);
     b.bin_rec = c.take<int4>(N);
     b.tile_rng = c.take<int2>((size_t)tiles_x(p) * tiles_y(p) * 2 * mc::kMaxRanges);
+    b.sp_rec = c.take<int4>((size_t)tiles_x(p) * tiles_y(p) * mc::kSpreadCap);
+    b.sp_cnt = c.take<int>((size_t)tiles_x(p) * tiles_y(p));
   }
 }
 
@@ -308,6 +312,8 @@ struct Engine {
     d.bin_start_next = s.b.bin_start;
     d.bin_rec = s.b.bin_rec;
     d.tile_rng = s.b.tile_rng;
+    d.sp_rec = s.b.sp_rec;
+    d.sp_cnt = s.b.sp_cnt;
     return d;
   }
 
@@ -653,6 +659,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_fill, nt);
     mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, sl.b.tile_rng, s);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.sp_cnt, (size_t)tiles_x(*p) * tiles_y(*p));
   }
   if (hipGetLastError() != hipSuccess) {
     delete w;
@@ -1256,6 +1263,7 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_fill, nt);
     mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, s.b.tile_rng, e.stream);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.sp_cnt, (size_t)tiles_x(*p) * tiles_y(*p));
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, e.stream, (int*)(e.flags + w), (size_t)1);
   HIPCHK(hipGetLastError());
