@@ -249,6 +249,18 @@ def test_partial_tiles_and_radii(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_dense_world(mode):
+    # about 0.73 nodes per cell: a tile's spread window (38 x 38 cells) then
+    # holds about 1050 nodes, so some tiles exceed the 1024-record list the
+    # filter fills for the spread and read the bins instead, beside tiles
+    # that use their list
+    sim = _sim()
+    w = wl.random_world(13, 64, 64, [60] * 50, amp=0.5)
+    ex, eu = _rollout_compare(sim, w, 6, mode)
+    print(f"dense 3000 nodes 64x64 [{mode}]: e_x={ex:.2e} e_u={eu:.2e}")
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_scaling_workload_full_size(mode):
     # the benchmark's million-node workload, in the benchmark's launch
     # configuration (captured-graph rollout), two steps, every node and cell
