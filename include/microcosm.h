@@ -174,7 +174,8 @@ const char *sim_last_error(void);
  * 3 fluid update, 4 gather + integrate), and expose the world's internal
  * per-step buffers (which: 0 deposit s [ny][nx], SIM_SPLAT_DIRECT only, else
  * NULL; 1 central difference of the filtered density [ny][nx][2]; 2 grid
- * force [ny][nx][2]; 3 node force [2][N]).  For parity tests.  The
+ * force [ny][nx][2]; 3 total node force [2][N]; 4 elastic node force
+ * [2][N]).  For parity tests.  The
  * sub-steps of one step must be run in order, starting with 0. */
 sim_status sim_debug_substep(sim_world *w, int32_t which, int64_t t);
 sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);

@@ -46,8 +46,8 @@ __global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __r
     zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
-    tile_spread_vec(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
-                    spread_fetch(w, x0, y0));
+    tile_spread_vec<false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
+                           spread_fetch(w, x0, y0), nullptr);
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < kTile * kTile; k += kTileThreads) {

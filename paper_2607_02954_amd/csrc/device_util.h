@@ -489,15 +489,24 @@ static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x
   return binset_fetch(w, (y0 >> 5) * w.ntx + (x0 >> 5), 1);
 }
 
+// With s_g (REP), the spread value of a node is its total force: v (the
+// elastic force) minus k_rep times the kernel-weighted gradient at its
+// support, read from s_g, the gradient staged over the same window; the home
+// tile of a node (the one tile holding its home cell) also writes that total
+// to w.fel.  The gradient sum runs in the same order as the repulsion gather
+// of the node kernels, so the forces are the same.
+template <bool REP>
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
                                        long long* s_y, vi4* s_list, const MC_GLOBAL vi4* recs,
-                                       const BinFetch& bins) {
+                                       const BinFetch& bins, const vf2* s_g) {
   const int nx = w.nx, ny = w.ny, N = w.n_part;
   const BinSet bs = binset_commit(bins);
   const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
   const int keep_x = tw + 3 <= nx ? tw + 2 : nx;     // largest kept home offset
   const int keep_y = th + 3 <= ny ? th + 2 : ny;
+  const float kr = w.k_rep;
+  MC_GLOBAL float* ftot = glb(w.fel);
   for_bin_records<4>(
       recs, bs, s_list,
       [&](const vi4& r) {
@@ -511,7 +520,33 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
         float wx[4], wy[4];
         peskin4(__int_as_float(r.y), wx);
         peskin4(__int_as_float(r.z), wy);
-        const float Vx = scale * v[r.w], Vy = scale * v[N + r.w];
+        float Vx, Vy;
+        if constexpr (REP) {
+          float gx = 0.f, gy = 0.f;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const vf2* row = s_g + (dy + b) * kSpreadSide + dx;
+            float ax = 0.f, ay = 0.f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const vf2 t = row[a];
+              ax += wx[a] * t.x;
+              ay += wx[a] * t.y;
+            }
+            gx += wy[b] * ax;
+            gy += wy[b] * ay;
+          }
+          Vx = v[r.w] - kr * gx;
+          Vy = v[N + r.w] - kr * gy;
+          const int hx = r.x & 0xffff, hy = r.x >> 16;
+          if (hx >= x0 && hx < x0 + tw && hy >= y0 && hy < y0 + th) {
+            ftot[r.w] = Vx;
+            ftot[N + r.w] = Vy;
+          }
+        } else {
+          Vx = scale * v[r.w];
+          Vy = scale * v[N + r.w];
+        }
         unsigned long long* px = (unsigned long long*)(s_x + dy * kSpreadSide + dx);
         unsigned long long* py = (unsigned long long*)(s_y + dy * kSpreadSide + dx);
         if (fmaxf(fabsf(Vx), fabsf(Vy)) < 0.125f) {

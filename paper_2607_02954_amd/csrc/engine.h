@@ -78,7 +78,8 @@ struct WorldDev {
   float* s;                             // deposit accumulator [ny][nx] (direct mode)
   float2* grad;                         // [ny][nx] central difference of the filtered density
   float2* Fg;                           // [ny][nx] grid force
-  float* fel;                           // node force [2][N] (elastic, then total)
+  float* fel;                           // node force [2][N]: total (elastic + repulsion)
+  float* fel_el;                        // node elastic force [2][N]
   const Ctl* ctl_src; Ctl* ctl_dst;
   unsigned* flags;                      // sticky: kFlagUnstable, kFlagBins
   // deterministic sorted-segment transfer (SIM_SPLAT_SORTED)

@@ -7,8 +7,10 @@
 //   k_filter      S2 deposit + S3 separable circular Gaussian filter on a
 //                 32x32 tile with an (R+1)-cell halo, all in LDS; writes the
 //                 central difference G = D s~ of the filtered density
-//   k_repulse     S4 repulsion -k_rep sum W G -> total node force
-//   k_spread      S5 force spread onto a 32x32 tile, summed in LDS
+//   k_repulse     S4 repulsion -k_rep sum W G -> total node force (sorted
+//                 and direct transfers)
+//   k_spread      S5 force spread onto a 32x32 tile, summed in LDS; for the
+//                 binned transfer it also forms S4 for the nodes it spreads
 //   k_lbm         S6 D2Q9 TRT/Guo collision and push streaming over
 //                 contiguous cells; exports u
 //   k_integrate   S7 gather u at the nodes and move them; counts the nodes
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     const int bx = wrap_index(cx, nx);
     const int by = wrap_index(cy, ny);
     if (active) {
-      MC_GLOBAL float* fel = glb(w.fel);
+      MC_GLOBAL float* fel = glb(w.fel_el);
       fel[gi] = w.k_el * s_dx[li];
       fel[N + gi] = w.k_el * s_dy[li];
     }
@@ -703,7 +705,7 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
-    if (w.mode == kBinned || w.ctl_src->remaining <= 0) continue;   // binned: k_repulse_tile
+    if (w.mode == kBinned || w.ctl_src->remaining <= 0) continue;   // binned: in k_spread
     const int sl = pk.node_begin + threadIdx.x;      // node index, or sorted slot
     if (sl >= pk.node_end) continue;
     const int mode = w.mode;
@@ -737,8 +739,9 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
       gx += wy[b] * rx;
       gy += wy[b] * ry;
     }
-    const float Fx = fel[gi] - w.k_rep * gx;
-    const float Fy = fel[N + gi] - w.k_rep * gy;
+    const MC_GLOBAL float* fe = glb(w.fel_el);
+    const float Fx = fe[gi] - w.k_rep * gx;
+    const float Fy = fe[N + gi] - w.k_rep * gy;
     fel[gi] = Fx;
     fel[N + gi] = Fy;
     if (mode == kSorted) {
@@ -768,6 +771,7 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
   __shared__ __align__(16) long long s_fx[kSpreadCells];   // 64-bit fixed point, padded window
   __shared__ __align__(16) long long s_fy[kSpreadCells];
   __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
+  __shared__ vf2 s_g[kSpreadCells];             // gradient over the window (binned)
   const int nt = *T.n_tiles;
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
@@ -781,6 +785,26 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
     const int y0 = tile_y(tl.y) * kTile;
     const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
     if (mode == kBinned) {
+      // S4 repulsion is formed here, per node, from the gradient staged over
+      // the window (grid cells (x0 - 3 + i, y0 - 3 + j), periodic); all loads
+      // first, then the stores (the barrier in the bin set commit follows)
+      {
+        constexpr int kIt = (kSpreadCells + kTileThreads - 1) / kTileThreads;
+        const MC_GLOBAL vf2* grad = glbv<const vf2>(w.grad);
+        const int gx0 = wrap_index(x0 - 3, nx), gy0 = wrap_index(y0 - 3, ny);
+        vf2 gv[kIt];
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+          const int k = min(tid + kTileThreads * i, kSpreadCells - 1);
+          const int j = k / kSpreadSide, c = k - (k / kSpreadSide) * kSpreadSide;
+          gv[i] = grad[(size_t)wrap_index(gy0 + j, ny) * nx + wrap_index(gx0 + c, nx)];
+        }
+#pragma unroll
+        for (int i = 0; i < kIt; ++i) {
+          const int k = tid + kTileThreads * i;
+          if (k < kSpreadCells) s_g[k] = gv[i];
+        }
+      }
       zero_lds_u64(s_fx, kSpreadCells);
       zero_lds_u64(s_fy, kSpreadCells);
       // the tile's record list from the filter (one range), or, if it
@@ -792,10 +816,11 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
         f.n = 1;
         f.b0 = tix * kSpreadCap;
         f.len = __lane_id() == 0 ? cnt : 0;
-        tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, glbv<const vi4>(w.sp_rec), f);
+        tile_spread_vec<true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                              glbv<const vi4>(w.sp_rec), f, s_g);
       } else {
-        tile_spread_vec(w, x0, y0, tw, th, glb(w.fel), 1.0f, s_fx, s_fy, s_list, glbv<const vi4>(w.bin_rec),
-                        spread_fetch(w, x0, y0));
+        tile_spread_vec<true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                              glbv<const vi4>(w.bin_rec), spread_fetch(w, x0, y0), s_g);
       }
       __syncthreads();
     }
@@ -1032,54 +1057,6 @@ __device__ __forceinline__ vf2 gather_staged(const vf2* st, int lx, int ly, cons
   return out;
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_repulse_tile(const WorldDev* __restrict__ W, Tables T) {
-  __shared__ vf2 s_g[kStage * kStage];        // staged gradient, x and y interleaved
-  const int nt = *T.n_tiles;
-  const XcdLoop tiles(nt);
-  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = tile_entry(T, it);
-    const WorldDev& w = W[tl.x];
-    if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
-    const int nx = w.nx, ny = w.ny, N = w.n_part;
-    const int x0 = tile_x(tl.y) * kTile;
-    const int y0 = tile_y(tl.y) * kTile;
-    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
-    MC_GLOBAL float* fel = glb(w.fel);
-    const float kr = w.k_rep;
-    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
-    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
-    // this thread's first two records and their forces are loaded beside the
-    // staged field, unconditionally (record 0 and node 0 always exist: the
-    // library's buffers hold at least one)
-    const int ea = e0 + (int)threadIdx.x, eb = ea + kTileThreads;
-    const bool has0 = ea < e1, has1 = eb < e1;
-    const vi4 r0 = recs[has0 ? ea : 0];
-    const vi4 r1 = recs[has1 ? eb : 0];
-    stage_field(glbv<const vf2>(w.grad), nx, ny, x0, y0, s_g);
-    const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
-    const float f0x = fel[g0], f0y = fel[N + g0];   // in flight across the barrier
-    const float f1x = fel[g1], f1y = fel[N + g1];
-    __syncthreads();
-    auto node = [&](const vi4& r, float fex, float fey) {
-      const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;   // home in the tile
-      float wx[4], wy[4];
-      peskin4(__int_as_float(r.y), wx);
-      peskin4(__int_as_float(r.z), wy);
-      const vf2 G = gather_staged(s_g, lx, ly, wx, wy);
-      fel[r.w] = fex - kr * G.x;
-      fel[N + r.w] = fey - kr * G.y;
-    };
-    // the first two records (already loaded), then any further ones
-    if (has0) node(r0, f0x, f0y);
-    if (has1) node(r1, f1x, f1y);
-    for (int e = eb + kTileThreads; e < e1; e += kTileThreads) {
-      const vi4 r = recs[e];
-      node(r, fel[r.w], fel[N + r.w]);
-    }
-    __syncthreads();
-  }
-}
-
 __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
   __shared__ vf2 s_u[kStage * kStage];        // staged velocity, x and y interleaved
   const int nt = *T.n_tiles;
@@ -1196,7 +1173,7 @@ void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_
 
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_node) MC_PACK_DISPATCH(k_repulse, G, W, T);
-  if (G.any_binned) k_repulse_tile<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
+  // binned worlds form the repulsion inside k_spread
 }
 
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {

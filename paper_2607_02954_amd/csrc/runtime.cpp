@@ -79,6 +79,7 @@ struct WorldBufs {
   float2* grad = nullptr;
   float2* Fg = nullptr;
   float* fel = nullptr;
+  float* fel_el = nullptr;
   int* key = nullptr;
   int* rank = nullptr;
   int* cnt = nullptr;
@@ -109,6 +110,7 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
   b.grad = c.take<float2>(ncell);
   b.Fg = c.take<float2>(ncell);
   b.fel = c.take<float>(2 * N);
+  b.fel_el = c.take<float>(2 * N);
   const int mode = mode_of(p);
   if (mode == mc::kSorted) {
     b.key = c.take<int>(N);
@@ -296,6 +298,7 @@ struct Engine {
     d.grad = s.b.grad;
     d.Fg = s.b.Fg;
     d.fel = s.b.fel;
+    d.fel_el = s.b.fel_el;
     d.ctl_src = ctl[parity] + w;
     d.ctl_dst = ctl[1 - parity] + w;
     d.flags = flags + w;
@@ -846,6 +849,7 @@ sim_status sim_debug_buffer(sim_world* w, int32_t which, void** ptr) {
     case 1: *ptr = s.b.grad; break;
     case 2: *ptr = s.b.Fg; break;
     case 3: *ptr = s.b.fel; break;
+    case 4: *ptr = s.b.fel_el; break;
     default: return fail(SIM_E_INVALID, "unknown buffer %d", which);
   }
   return SIM_OK;

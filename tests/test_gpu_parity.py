@@ -79,7 +79,7 @@ def test_substeps_match_oracle(mode):
     O.step(x, f, t, inp, op, trace=tr)
     N, ny, nx = w.n_particles, w.ny, w.nx
     W.substep(0, t)
-    fel = W.buffer(3, (2, N)).cpu().numpy()
+    fel = W.buffer(4, (2, N)).cpu().numpy()             # elastic force
     e_el = rel(fel, tr["f_el"].numpy())
     assert e_el < 2e-5, e_el
     if mode == "direct":
