@@ -1013,10 +1013,11 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Binned worlds: the node gathers of S4 (G) and S7 (u) per 32x32 tile.  The
-// field is staged in LDS for the tile plus the support margin (cells
-// x0-1 .. x0+33) with coalesced loads; every node whose home cell lies in the
-// tile (its bin) gathers its 4x4 window from LDS.
+// Binned worlds: the node gather of S7 (u) per 32x32 tile.  The field is
+// staged in LDS for the tile plus the support margin (cells x0-1 .. x0+33)
+// with coalesced loads; every node whose home cell lies in the tile (its bin)
+// gathers its 4x4 window from LDS.  (The S4 gather of binned worlds happens
+// inside k_spread.)
 // ---------------------------------------------------------------------------
 constexpr int kStage = kTile + 3;
 
