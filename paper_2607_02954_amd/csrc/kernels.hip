@@ -876,7 +876,8 @@ __global__ __launch_bounds__(256) void k_lbm(const WorldDev* __restrict__ W, Tab
     for (int h = 0; h < CPT; ++h) {             // every load of every cell first
       const int c = min(item.y + (int)threadIdx.x + 256 * h, ncell - 1);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) gg[h][q] = src[(size_t)q * ncell + c];
+      for (int q = 0; q < 9; ++q)                 // read once per step: no cache allocation
+        gg[h][q] = __builtin_nontemporal_load((const float*)(src + (size_t)q * ncell + c));
       FF[h] = glbv<vf2>(w.Fg)[c];
     }
 #pragma unroll
