@@ -948,7 +948,9 @@ __global__ __launch_bounds__(256) void k_lbm(const WorldDev* __restrict__ W, Tab
       for (int q = 0; q < 9; ++q) {
         const int xn = wrap_near(x + kCX[q], nx);
         const int yn = wrap_near(y + kCY[q], ny);
-        dst[(size_t)q * ncell + (size_t)yn * nx + xn] = out[q];
+        // (non-temporal: the next read is a step away; the caches keep
+        // what the following kernels read instead)
+        __builtin_nontemporal_store(out[q], (float*)(dst + (size_t)q * ncell + (size_t)yn * nx + xn));
       }
     }
   }
