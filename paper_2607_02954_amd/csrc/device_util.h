@@ -174,9 +174,6 @@ static __device__ __forceinline__ long long f32_to_fix(float x) {
   const long long m = (long long)(((unsigned long long)(unsigned)hf << 32) + (unsigned long long)__float2uint_rn(lof));
   return x < 0.0f ? -m : m;
 }
-static __device__ __forceinline__ void lds_fix_add(long long* p, float v) {
-  atomicAdd((unsigned long long*)p, (unsigned long long)f32_to_fix(v * kFixScale));
-}
 static __device__ __forceinline__ float fix_to_float(long long v) {
   const int hi = (int)(v >> 32);
   const unsigned lo = (unsigned)v;
