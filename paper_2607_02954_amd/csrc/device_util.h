@@ -380,6 +380,18 @@ static __device__ __forceinline__ BinSet binset_commit(const BinFetch& f) {
   return bs;
 }
 
+// A list whose every record is needed (the spread lists the filter writes):
+// threads take the records in turn, with no keep test and no compaction.
+template <class Body>
+static __device__ __forceinline__ void for_list_records(const MC_GLOBAL vi4* recs, const BinSet& bs, Body body) {
+  const int total = bs.total, off = bs.delta[0];
+  for (int f = (int)threadIdx.x; f < total; f += kTileThreads) {
+    const vi4 r = recs[f + off];
+    body(r);
+  }
+  __syncthreads();
+}
+
 template <int PER, class Keep, class Body>
 static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs, const BinSet& bs, vi4* s_list,
                                                        Keep keep, Body body) {
@@ -491,8 +503,10 @@ static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x
 // support, read from s_g, the gradient staged over the same window; the home
 // tile of a node (the one tile holding its home cell) also writes that total
 // to w.fel.  The gradient sum runs in the same order as the repulsion gather
-// of the node kernels, so the forces are the same.
-template <bool REP>
+// of the node kernels, so the forces are the same.  With LIST, `bins` names
+// one range of records that the tile needs, every one of them (its spread
+// list), so they skip the keep test.
+template <bool REP, bool LIST = false>
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
                                        long long* s_y, vi4* s_list, const MC_GLOBAL vi4* recs,
@@ -504,73 +518,73 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
   const int keep_y = th + 3 <= ny ? th + 2 : ny;
   const float kr = w.k_rep;
   MC_GLOBAL float* ftot = glb(w.fel);
-  for_bin_records<4>(
-      recs, bs, s_list,
-      [&](const vi4& r) {
-        const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
-        const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
-        return dx <= keep_x && dy <= keep_y;
-      },
-      [&](const vi4& r) {
-        const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
-        const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
-        float wx[4], wy[4];
-        peskin4(__int_as_float(r.y), wx);
-        peskin4(__int_as_float(r.z), wy);
-        float Vx, Vy;
-        if constexpr (REP) {
-          float gx = 0.f, gy = 0.f;
+  const auto keep = [&](const vi4& r) {
+    const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
+    const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
+    return dx <= keep_x && dy <= keep_y;
+  };
+  const auto body = [&](const vi4& r) {
+    const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
+    const int dy = wrap_near((r.x >> 16) - 1 - oy, ny);
+    float wx[4], wy[4];
+    peskin4(__int_as_float(r.y), wx);
+    peskin4(__int_as_float(r.z), wy);
+    float Vx, Vy;
+    if constexpr (REP) {
+      float gx = 0.f, gy = 0.f;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const vf2* row = s_g + (dy + b) * kSpreadSide + dx;
-            float ax = 0.f, ay = 0.f;
+      for (int b = 0; b < 4; ++b) {
+        const vf2* row = s_g + (dy + b) * kSpreadSide + dx;
+        float ax = 0.f, ay = 0.f;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const vf2 t = row[a];
-              ax += wx[a] * t.x;
-              ay += wx[a] * t.y;
-            }
-            gx += wy[b] * ax;
-            gy += wy[b] * ay;
-          }
-          Vx = v[r.w] - kr * gx;
-          Vy = v[N + r.w] - kr * gy;
-          const int hx = r.x & 0xffff, hy = r.x >> 16;
-          if (hx >= x0 && hx < x0 + tw && hy >= y0 && hy < y0 + th) {
-            ftot[r.w] = Vx;
-            ftot[N + r.w] = Vy;
-          }
-        } else {
-          Vx = scale * v[r.w];
-          Vy = scale * v[N + r.w];
+        for (int a = 0; a < 4; ++a) {
+          const vf2 t = row[a];
+          ax += wx[a] * t.x;
+          ay += wx[a] * t.y;
         }
-        unsigned long long* px = (unsigned long long*)(s_x + dy * kSpreadSide + dx);
-        unsigned long long* py = (unsigned long long*)(s_y + dy * kSpreadSide + dx);
-        if (fmaxf(fabsf(Vx), fabsf(Vy)) < 0.125f) {
-          float ax[4], ay[4];
+        gx += wy[b] * ax;
+        gy += wy[b] * ay;
+      }
+      Vx = v[r.w] - kr * gx;
+      Vy = v[N + r.w] - kr * gy;
+      const int hx = r.x & 0xffff, hy = r.x >> 16;
+      if (hx >= x0 && hx < x0 + tw && hy >= y0 && hy < y0 + th) {
+        ftot[r.w] = Vx;
+        ftot[N + r.w] = Vy;
+      }
+    } else {
+      Vx = scale * v[r.w];
+      Vy = scale * v[N + r.w];
+    }
+    unsigned long long* px = (unsigned long long*)(s_x + dy * kSpreadSide + dx);
+    unsigned long long* py = (unsigned long long*)(s_y + dy * kSpreadSide + dx);
+    if (fmaxf(fabsf(Vx), fabsf(Vy)) < 0.125f) {
+      float ax[4], ay[4];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            ax[a] = (Vx * kFixScale) * wx[a];
-            ay[a] = (Vy * kFixScale) * wx[a];
-          }
+      for (int a = 0; a < 4; ++a) {
+        ax[a] = (Vx * kFixScale) * wx[a];
+        ay[a] = (Vy * kFixScale) * wx[a];
+      }
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              atomicAdd(px + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ax[a] * wy[b]));
-              atomicAdd(py + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
-            }
-        } else {
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const float ww = wx[a] * wy[b];
-              atomicAdd(px + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vx * kFixScale));
-              atomicAdd(py + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
-            }
+        for (int a = 0; a < 4; ++a) {
+          atomicAdd(px + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ax[a] * wy[b]));
+          atomicAdd(py + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
         }
-      });
+    } else {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float ww = wx[a] * wy[b];
+          atomicAdd(px + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vx * kFixScale));
+          atomicAdd(py + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
+        }
+    }
+  };
+  if constexpr (LIST) for_list_records(recs, bs, body);
+  else for_bin_records<4>(recs, bs, s_list, keep, body);
 }
 
 // The accumulated value of tile cell (lx, ly) of a spread window.

@@ -816,8 +816,8 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
         f.n = 1;
         f.b0 = tix * kSpreadCap;
         f.len = __lane_id() == 0 ? cnt : 0;
-        tile_spread_vec<true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
-                              glbv<const vi4>(w.sp_rec), f, s_g);
+        tile_spread_vec<true, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                    glbv<const vi4>(w.sp_rec), f, s_g);
       } else {
         tile_spread_vec<true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
                               glbv<const vi4>(w.bin_rec), spread_fetch(w, x0, y0), s_g);
