@@ -250,12 +250,21 @@ def test_partial_tiles_and_radii(mode):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_dense_world(mode):
-    # about 0.73 nodes per cell: a tile's spread window (38 x 38 cells) then
-    # holds about 1050 nodes, so some tiles exceed the 1024-record list the
-    # filter fills for the spread and read the bins instead, beside tiles
-    # that use their list
+    # about 0.73 nodes per cell: a tile's spread list (nodes with homes in a
+    # 35 x 35 cell square) then holds 629 to 1116 nodes at the first step, so
+    # one tile exceeds the 1024-record list the filter fills for the spread
+    # and reads the bins instead, beside tiles that use their list (one of
+    # them one record short of the limit)
     sim = _sim()
     w = wl.random_world(13, 64, 64, [60] * 50, amp=0.5)
+    if mode == "binned":
+        # the first step's lists: nodes whose home cell lies in
+        # [x0 - 2, x0 + 32] x [y0 - 2, y0 + 32] (periodic) of each 32 x 32 tile
+        x = w.positions64()
+        hx, hy = np.floor(x[0]).astype(int) % 64, np.floor(x[1]).astype(int) % 64
+        per_tile = [int(((((hx - x0 + 2) % 64) <= 34) & (((hy - y0 + 2) % 64) <= 34)).sum())
+                    for y0 in (0, 32) for x0 in (0, 32)]
+        assert max(per_tile) > 1024 and min(per_tile) <= 1024, per_tile
     ex, eu = _rollout_compare(sim, w, 6, mode)
     print(f"dense 3000 nodes 64x64 [{mode}]: e_x={ex:.2e} e_u={eu:.2e}")
 
