@@ -1,0 +1,127 @@
+"""Geometry of the tile-binned particle/grid transfer (host-side, no GPU).
+
+The transfer (Methods, fluid-filament interaction; read as Peskin's 4-point
+kernel) puts a node whose home cell is h = floor(x) on the cells h-1 .. h+2
+of each periodic axis.  The tile kernels of the binned transfer keep, per
+32-cell tile, only the nodes whose home cell passes a keep rule, place each
+kept node's four cells at window offsets d .. d+3 with d = (h - 1 - o) mod n
+(o: window origin, three cells before the needed range) inside an LDS window
+of side need + 6, and read the records from the home-tile bins of a few tile
+columns.  The rules are separable, so one axis at a time suffices.
+
+For every axis length 1..199, every tile and every Gaussian radius 1..8 this
+checks, for the filter (needed: the density region of the tile, its
+central-difference ring and R cells of filter support each side) and for the
+spread (needed: the tile's own cells):
+  * every node touching a needed cell is kept, its bin column is read, and
+    its contribution lands on a window cell that the kernel reads for that
+    grid cell (the single image when need + 3 <= n, else an image that the
+    read sums);
+  * every kept node's four cells stay inside the window;
+  * the spread's kept nodes are kept by the filter and lie in the filter's
+    bins (the filter hands the spread its record list);
+  * a tile reads at most four bin columns in at most two runs, so a tile's
+    bin set has at most eight runs.
+"""
+import numpy as np
+import pytest
+
+TILE = 32
+MAX_COLS = 4
+
+
+def covering_columns(lo, hi, n):
+    """Tile columns holding cells lo..hi of a periodic axis, capped at four."""
+    t = []
+    if hi - lo + 1 >= n:
+        k = 0
+        while k * TILE < n and len(t) < MAX_COLS:
+            t.append(k)
+            k += 1
+        return t
+    c = lo
+    while c <= hi and len(t) < MAX_COLS:
+        cc = c % n
+        tt = cc // TILE
+        if tt not in t:
+            t.append(tt)
+        c += min((tt + 1) * TILE, n) - cc
+    return t
+
+
+def runs(cols):
+    """Runs of consecutive column indices in the order listed."""
+    r = 0
+    for i, c in enumerate(cols):
+        if i == 0 or c != cols[i - 1] + 1:
+            r += 1
+    return r
+
+
+def check_reader(n, first, need, cols, bound_shift=0, side_shift=0):
+    """Keep rule, window placement and bins of one reader on one axis.
+
+    first: first needed cell (unwrapped); need: needed cells.  Returns the
+    keep mask over home cells 0..n-1.  The shifts plant mistakes."""
+    o = (first - 3) % n
+    side = need + 6 + side_shift
+    single = need + 3 <= n
+    bound = (need + 2 if single else n) + bound_shift
+    h = np.arange(n)
+    d = (h - 1 - o) % n
+    kept = d <= bound
+    assert np.all(d[kept] + 3 <= side - 1), (n, first, need)
+    in_bins = np.isin(h // TILE, cols)
+    for k in range(4):
+        c = (h - 1 + k) % n                   # grid cell of the contribution
+        p = d + k                             # window offset it lands on
+        rel = (c - first) % n
+        needed = rel < need if need < n else np.ones(n, bool)
+        assert np.all(kept[needed]), (n, first, need, k)
+        assert np.all(in_bins[needed]), (n, first, need, k, cols)
+        if single:
+            assert np.all(p[needed] == 3 + rel[needed]), (n, first, need, k)
+        else:
+            assert np.all((p[needed] - 3 - rel[needed]) % n == 0), (n, first, need, k)
+    return kept
+
+
+def test_binned_transfer_windows_and_bins():
+    cases = 0
+    for n in range(1, 200):
+        for x0 in range(0, n, TILE):
+            tw = min(TILE, n - x0)
+            sp_cols = covering_columns(x0 - 2, x0 + tw, n)
+            assert len(sp_cols) <= MAX_COLS and runs(sp_cols) <= 2
+            sp_kept = check_reader(n, x0, tw, sp_cols)
+            for R in range(1, 9):
+                reg = TILE + 2 + 2 * R
+                xo = x0 - R - 1
+                f_cols = covering_columns(xo - 2, xo + reg, n)
+                assert len(f_cols) <= MAX_COLS and runs(f_cols) <= 2
+                f_kept = check_reader(n, xo, reg, f_cols)
+                h = np.arange(n)
+                assert np.all(f_kept[sp_kept]), (n, x0, R)
+                assert np.all(np.isin(h[sp_kept] // TILE, f_cols)), (n, x0, R)
+                cases += 1
+    assert cases > 5000
+
+
+@pytest.mark.parametrize("mistake", ["dropped column", "keep bound one short", "window one short"])
+def test_planted_mistakes_are_caught(mistake):
+    # the check is sharp: a filter tile with one bin column left out, a keep
+    # bound one cell short or a window one cell short fails it
+    n, x0, R = 160, 64, 4
+    reg = TILE + 2 + 2 * R
+    cols = covering_columns(x0 - R - 1 - 2, x0 - R - 1 + reg, n)
+    assert len(cols) == 3
+    check_reader(n, x0 - R - 1, reg, cols)
+    kw = {}
+    if mistake == "dropped column":
+        cols = cols[:-1]
+    elif mistake == "keep bound one short":
+        kw = {"bound_shift": -1}
+    else:
+        kw = {"side_shift": -1}
+    with pytest.raises(AssertionError):
+        check_reader(n, x0 - R - 1, reg, cols, **kw)
