@@ -264,7 +264,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: a world or a batch of worlds runs on one device; "
+                                   "--gpus must be 1"}))
         sys.exit(2)
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
