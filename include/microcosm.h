@@ -150,7 +150,11 @@ sim_status sim_checkpoint_size(const sim_world *w, int32_t n_steps, int32_t ckpt
  * dL/dx at t0 into g_pos0 ([2][N]).  Each segment is recomputed forward from
  * its checkpoint into adj_ws, then hand-written adjoint kernels run step by
  * step in reverse.  adj_ws must hold sim_backward_workspace_size bytes.
- * The world's own state arrays are not modified. */
+ * The world's own state arrays are not modified.  Only worlds that use the
+ * tile-binned transfer (flags without SIM_SPLAT_SORTED / SIM_SPLAT_DIRECT)
+ * can be differentiated: for the other two, SIM_E_INVALID is returned before
+ * anything is enqueued (their recompute would follow a different summation
+ * order than the recorded forward). */
 sim_status sim_backward_workspace_size(const sim_world *w, int32_t ckpt_every, size_t *bytes);
 sim_status sim_backward(sim_world *w, int64_t t0, int32_t n_steps, int32_t ckpt_every,
                         const void *ckpt, const float *g_pos, float *g_rest_angle, float *g_pos0,

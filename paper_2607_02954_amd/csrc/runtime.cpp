@@ -956,6 +956,9 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
   if ((uintptr_t)adj_ws % kAlign) return fail(SIM_E_WORKSPACE, "adjoint workspace must be 256-byte aligned");
   Engine& e = w->eng;
   Slot& s = e.slots[0];
+  if (mode_of(s.p) != mc::kBinned)
+    return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
+                mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
   if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   size_t need = 0;
   sim_backward_workspace_size(w, ckpt_every, &need);

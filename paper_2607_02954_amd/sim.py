@@ -293,19 +293,33 @@ class Rollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, rest_angle, world, t0, n_steps, ckpt_every):
+        if world.params.transfer != "binned":
+            # the same refusal as sim_backward's, raised before the forward runs
+            raise SimError(SIM_E_INVALID, "differentiation needs the tile-binned transfer "
+                                          f"(world uses '{world.params.transfer}')")
+        ra32 = rest_angle.detach().to(torch.float32).contiguous()
         with torch.no_grad():
-            world.state.rest_angle.copy_(rest_angle.detach().to(torch.float32))
+            world.state.rest_angle.copy_(ra32)
         ckpt = torch.empty(world.checkpoint_bytes(n_steps, ckpt_every), dtype=torch.uint8,
                            device=world.workspace.device)
         world.rollout(t0, n_steps, ckpt_every, ckpt)
         ctx.world, ctx.ckpt, ctx.args = world, ckpt, (t0, n_steps, ckpt_every)
+        # the rest angles this forward ran with: the backward recomputes with
+        # them even if the world's array has been rewritten in between
+        ctx.rest = ra32.clone()
         ctx.dtype = rest_angle.dtype
         return world.positions()
 
     @staticmethod
     def backward(ctx, g_x):
         t0, n, k = ctx.args
+        W = ctx.world
         g_pos = g_x.detach().to(torch.float32).contiguous()
-        g_rest = torch.zeros(ctx.world.state.n_part, dtype=torch.float32, device=g_pos.device)
-        ctx.world.backward(t0, n, k, ctx.ckpt, g_pos, g_rest)
+        g_rest = torch.zeros(W.state.n_part, dtype=torch.float32, device=g_pos.device)
+        current = W.state.rest_angle.clone()
+        W.state.rest_angle.copy_(ctx.rest)
+        try:
+            W.backward(t0, n, k, ctx.ckpt, g_pos, g_rest)
+        finally:
+            W.state.rest_angle.copy_(current)        # stream-ordered after the backward
         return g_rest.to(ctx.dtype), None, None, None, None
