@@ -68,13 +68,22 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+GRAPH_CHUNK = 20              # steps per captured chunk graph of a single world
+
+
 def time_rollout(W, warmup, steps, t0=0):
-    W.rollout(t0, warmup)
+    """Seconds for `steps` steps of sim_rollout after `warmup` untimed steps.
+
+    The untimed part runs at least one chunk and one step pair, so every graph
+    the timed rollout launches (the chunk graph and the pair graph) has been
+    captured and instantiated before the start event: capture is set-up, not
+    step work."""
+    W.rollout(t0, max(warmup, GRAPH_CHUNK + 2))
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record()
-    W.rollout(t0 + warmup, steps)
+    W.rollout(t0 + max(warmup, GRAPH_CHUNK + 2), steps)
     end.record()
     torch.cuda.synchronize()
     W.sync()
@@ -223,27 +232,90 @@ def bench_adjoint(seed, reps=5):
     }
 
 
-def cpu_baseline(world, sample_steps):
-    """The FP64 oracle (unchanged) on the host cores for a bounded number of steps."""
+def host_cpu():
+    """Host CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def oracle_rate(world, steps, threads):
+    """Particle-steps/s of the FP64 oracle (unchanged) on `threads` host
+    threads over `steps` steps, after one untimed step (first touch)."""
     import oracle as O
-    p = O.Params(nx=world.nx, ny=world.ny)
-    inp = O.inputs_from_world(world)
-    x = O.positions_from_world(world)
-    f = O.rest_populations(p)
-    with torch.no_grad():
-        x, f, _ = O.step(x, f, 0, inp, p)        # first-touch warm-up, untimed
-        t0 = time.perf_counter()
-        for k in range(sample_steps):
-            x, f, _ = O.step(x, f, 1 + k, inp, p)
-        dt = time.perf_counter() - t0
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        p = O.Params(nx=world.nx, ny=world.ny)
+        inp = O.inputs_from_world(world)
+        x = O.positions_from_world(world)
+        f = O.rest_populations(p)
+        with torch.no_grad():
+            x, f, _ = O.step(x, f, 0, inp, p)
+            t0 = time.perf_counter()
+            for k in range(steps):
+                x, f, _ = O.step(x, f, 1 + k, inp, p)
+            dt = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(prev)
+    return world.n_particles * steps / dt, dt
+
+
+def cpu_baseline(world, sample_steps, single_steps):
+    """The FP64 oracle on the host cores for a bounded number of steps, with
+    every usable core and with one."""
+    model, nproc, usable = host_cpu()
+    v_all, dt_all = oracle_rate(world, sample_steps, usable)
+    v_one, dt_one = oracle_rate(world, single_steps, 1) if single_steps > 0 else (None, 0.0)
     return {
-        "value": world.n_particles * sample_steps / dt,
+        "value": v_all,
         "unit": "particle-steps/s",
-        "cores": torch.get_num_threads(),
+        "cores": usable,
         "kind": "oracle",
         "sample": f"{sample_steps} steps of the same workload after one untimed step "
-                  f"({dt:.1f} s, float64, torch CPU)",
+                  f"({dt_all:.1f} s, float64, torch CPU, {usable} threads)",
+        "single_thread": {"value": v_one, "steps": single_steps, "seconds": dt_one},
+        "host": {"cpu_model": model, "nproc": nproc, "usable_cores": usable},
     }
+
+
+def bench_small_configs(seed, steps_c1, steps_c2, cpu_c1, cpu_c2, with_cpu):
+    """The parity configuration (one 32-node chain on 64^2) and the uniform
+    population (1024 chains x 64 nodes on 512^2, active bending): particle-
+    steps/s of the captured-graph rollout, the oracle beside each."""
+    out = {}
+    model, nproc, usable = host_cpu()
+    for name, world, steps, cpu_steps in (
+            ("parity_32_nodes_64x64", wl.parity_single(seed), steps_c1, cpu_c1),
+            ("uniform_65536_nodes_512x512", wl.uniform_population(seed), steps_c2, cpu_c2)):
+        W = sim.World(world, sim.Params(nx=world.nx, ny=world.ny))
+        secs = time_rollout(W, GRAPH_CHUNK, steps)
+        W.close()
+        del W
+        N = world.n_particles
+        rec = {"particles": N, "grid": [world.nx, world.ny], "steps": steps,
+               "ms_per_step": 1000.0 * secs / steps, "value": N * steps / secs,
+               "unit": "particle-steps/s",
+               "step_GBs": (STEP_BYTES_PER_CELL * world.nx * world.ny + STEP_BYTES_PER_NODE * N)
+                           / (secs / steps) / 1e9}
+        if with_cpu:
+            v_all, dt_all = oracle_rate(world, cpu_steps, usable)
+            v_one, dt_one = oracle_rate(world, max(1, cpu_steps // 4), 1)
+            rec["oracle"] = {"value": v_all, "cores": usable, "steps": cpu_steps, "seconds": dt_all,
+                             "single_thread_value": v_one, "single_thread_steps": max(1, cpu_steps // 4)}
+        out[name] = rec
+        log(f"{name}: {rec['ms_per_step']:.4f} ms/step")
+    return out
 
 
 def main():
@@ -252,7 +324,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-single-steps", type=int, default=1)
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^2 and 512^2 configurations")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sorted", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -298,10 +372,10 @@ def main():
     secs = time_rollout(W, args.warmup, args.steps)
     ms_step = 1000.0 * secs / args.steps
     value = N * args.steps / secs
-    # live per-kernel timing (HIP events on the world's stream), same state
-    # live per-kernel timing on the world's stream; the fluid kernel's time
-    # comes from its dispatch's own start and end timestamps
-    kms = W.profile(args.warmup + args.steps, args.profile_steps)
+    # live per-kernel timing on the world's stream, same state; the fluid
+    # kernel's time comes from its dispatch's own start and end timestamps
+    t_next = max(args.warmup, GRAPH_CHUNK + 2) + args.steps
+    kms = W.profile(t_next, args.profile_steps)
     fluid_ms = kms[4]
     fluid_bytes = FLUID_BYTES_PER_CELL * ncell
     fluid_gbs = fluid_bytes / (fluid_ms * 1e-3) / 1e9
@@ -315,7 +389,7 @@ def main():
         for mode in ("sorted", "direct"):
             Ws = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, transfer=mode))
             s_secs = time_rollout(Ws, args.warmup, args.steps)
-            skms = Ws.profile(args.warmup + args.steps, args.profile_steps)
+            skms = Ws.profile(t_next, args.profile_steps)
             variants[mode] = {
                 "value": N * args.steps / s_secs,
                 "ms_per_step": 1000.0 * s_secs / args.steps,
@@ -331,6 +405,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "graph_warmup_steps": max(args.warmup, GRAPH_CHUNK + 2),
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -363,14 +438,27 @@ def main():
         "transfer_variants": variants,
     }
     log(f"scaling workload done: {ms_step:.4f} ms/step")
+    # the atomic adds the transfers are built on: LDS float vs integer adds
+    # (the binned transfer sums in 64-bit fixed point) and global float
+    # atomics (the direct transfer), with the direct transfer's own rate
+    at = sim.measure_atomics()
+    if "direct" in variants:
+        kd = variants["direct"]["kernel_ms"]
+        # direct mode: 16 deposit atomics per node in the elastic kernel and
+        # 32 spread atomics per node in the repulsion kernel
+        at["direct_transfer_atomics_per_s"] = 48 * N / ((kd["elastic"] + kd["repulse_spread"]) * 1e-3)
+    out["atomic_throughput"] = at
     if not args.no_adjoint:
         out["differentiation"] = bench_adjoint(args.seed)
         log("differentiation done")
     if not args.no_served:
         out["batched_served"] = bench_served(args.seed, args.pool_gib, args.tune_steps)
         log("served done")
+    if not args.no_small:
+        out["small_configs"] = bench_small_configs(args.seed, 1000, 1000, 200, 8, not args.no_cpu)
+        log("small configurations done")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(world, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(world, args.cpu_steps, args.cpu_single_steps)
         log("cpu baseline done")
     print(json.dumps(out), flush=True)
 

@@ -196,6 +196,19 @@ sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
  * Synchronises the stream. */
 sim_status sim_profile_steps(sim_world *w, int64_t t0, int32_t n_steps, float *ms_out);
 
+/* Measurement hook: throughput of the atomic adds a particle -> grid transfer
+ * can be built on, on the current device.  buf is a caller DEVICE buffer of
+ * at least 64 MiB (256-byte aligned), overwritten.  Writes out[7]: lane
+ * operations per clock per compute unit of LDS adds, bank-conflict free,
+ * 1024 words per block, 8 blocks of 256 threads per compute unit:
+ *   out[0] float add whose result is used, out[1] float add (result unused),
+ *   out[2] 64-bit integer add, out[3] 32-bit integer add;
+ * out[4] global float atomic adds per clock, whole chip, at scattered words
+ * of buf; out[5] the clock (Hz) the rates are counted in (the device's
+ * reported peak engine clock); out[6] the compute-unit count.  Each figure is
+ * the mean of 5 launches after one warm-up.  Synchronises the stream. */
+sim_status sim_measure_atomics(void *buf, size_t buf_bytes, void *stream, double *out);
+
 
 /* ---- Batched worlds: many independent worlds of uneven size advanced by the
  * same kernels in one persistent, graph-captured launch per chunk of steps.

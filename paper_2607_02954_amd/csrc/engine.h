@@ -162,4 +162,7 @@ void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStre
 void launch_tile_ranges(int nx, int ny, int R, int2* out, hipStream_t s);
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s);
 
+// Record msg as the thread's last error message (sim_last_error) and return st.
+int report_error(int st, const char* msg);
+
 }  // namespace mc

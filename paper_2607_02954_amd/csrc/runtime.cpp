@@ -34,6 +34,14 @@ sim_status fail(sim_status st, const char* fmt, ...) {
   return st;
 }
 
+}  // namespace
+
+namespace mc {
+int report_error(int st, const char* msg) { return fail((sim_status)st, "%s", msg); }
+}  // namespace mc
+
+namespace {
+
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \

@@ -29,7 +29,7 @@ EXPORTS = [
     "sim_params_default", "sim_workspace_size", "sim_create", "sim_step", "sim_rollout",
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
-    "sim_profile_steps",
+    "sim_profile_steps", "sim_measure_atomics",
     "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
     "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
     "sim_batch_destroy",
@@ -93,6 +93,7 @@ def lib():
         "sim_debug_substep": (i32, [vp, i32, i64]),
         "sim_debug_buffer": (i32, [vp, i32, P(vp)]),
         "sim_profile_steps": (i32, [vp, i64, i32, P(ctypes.c_float)]),
+        "sim_measure_atomics": (i32, [vp, sz, vp, P(ctypes.c_double)]),
         "sim_batch_world_bytes": (i32, [P(SimParams), i32, i32, P(sz)]),
         "sim_batch_create": (i32, [i32, vp, sz, vp, P(vp)]),
         "sim_batch_admit": (i32, [vp, P(SimParams), P(SimArrays), i64, i32, P(i32)]),
@@ -187,6 +188,20 @@ class DeviceState:
 def _stream_handle(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def measure_atomics(device="cuda"):
+    """Atomic-add throughput of the device (see sim_measure_atomics)."""
+    buf = torch.empty(64 << 20, dtype=torch.uint8, device=device)
+    out = (ctypes.c_double * 7)()
+    check(lib().sim_measure_atomics(_ptr(buf), buf.numel(), _stream_handle(), out))
+    keys = ["lds_f32_add_returned", "lds_f32_add", "lds_u64_add", "lds_u32_add"]
+    res = {k: out[i] for i, k in enumerate(keys)}
+    res["unit"] = "lane-ops per clock per compute unit"
+    res["global_f32_atomic_per_clock_chip"] = out[4]
+    res["clock_hz"] = out[5]
+    res["compute_units"] = int(out[6])
+    return res
 
 
 class World:

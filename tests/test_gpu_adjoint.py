@@ -1,5 +1,9 @@
 """Hand-written adjoint (sim_backward) versus the FP64 oracle's reverse mode
-and central finite differences, through the C ABI and the autograd Function.
+and central finite differences, through the C ABI and the autograd Function,
+over the configurations the forward parity covers: Gaussian radii 1, 4 and
+8, a filament longer than 256 nodes (the 1024-node pack), a grid narrower
+than one 32-cell tile, and the folding workload at full size.  Worlds that do
+not use the tile-binned transfer are refused.
 
 Acceptance: normwise relative error of the rest-angle gradient <= 1e-3 and
 cosine similarity >= 0.9999 against the oracle adjoint; against central
@@ -179,3 +183,72 @@ def test_backward_is_independent_of_checkpoint_interval_and_repeatable():
     assert torch.equal(ga, gb) and torch.equal(xa, xb)
     assert torch.equal(ga, gc) and torch.equal(xa, xc)
     print(f"backward, intervals 10 and 5, repeated: max |g| {float(ga.abs().max()):.3e}, bitwise equal")
+
+
+@pytest.mark.parametrize("case", ["radius1", "radius8", "long_filament", "narrow_grid"])
+def test_adjoint_configurations_match_oracle(case):
+    sim = _sim()
+    kw = {}
+    if case == "radius1":
+        w = wl.random_world(21, 64, 56, [20, 9, 33], amp=0.5)
+        kw = dict(repulse_radius=1, sigma_repulse=0.5)
+    elif case == "radius8":
+        w = wl.random_world(22, 72, 64, [25, 12, 40], amp=0.5)
+        kw = dict(repulse_radius=8, sigma_repulse=2.0)
+    elif case == "long_filament":
+        w = wl.random_world(23, 96, 96, [300, 5, 2, 40], amp=0.5)
+    else:
+        w = wl.random_world(24, 24, 20, [6, 4, 3], amp=0.5)
+    x0 = w.positions64()
+    target = x0 + np.random.default_rng(1).normal(0, 0.5, size=x0.shape)
+    n, k = 12, 5
+    g, _, W, p = _gpu_grad(sim, w, target, n, k, **kw)
+    ref, _ = _oracle_grad(w, p, target, n, k)
+    err, cos = _compare(g, ref, _joints(w))
+    print(f"adjoint [{case}]: rel err {err:.2e} cos {cos:.6f}")
+    assert err <= 1e-3 and cos >= 0.9999
+
+
+@pytest.mark.parametrize("mode", ["sorted", "direct"])
+def test_backward_refuses_other_transfers(mode):
+    sim = _sim()
+    w = wl.random_world(3, 48, 40, [12, 7], amp=0.5)
+    W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode))
+    ck = torch.empty(W.checkpoint_bytes(4, 2), dtype=torch.uint8, device="cuda")
+    W.rollout(0, 4, 2, ck)
+    N = w.n_particles
+    g_pos = torch.zeros(2 * N, dtype=torch.float32, device="cuda")
+    g_rest = torch.zeros(N, dtype=torch.float32, device="cuda")
+    with pytest.raises(sim.SimError) as ei:
+        W.backward(0, 4, 2, ck, g_pos, g_rest)
+    assert ei.value.status == sim.SIM_E_INVALID
+    ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.raises(sim.SimError) as ei:
+        sim.Rollout.apply(ra, W, 0, 4, 2)
+    assert ei.value.status == sim.SIM_E_INVALID
+    W.sync()
+
+
+def test_backward_uses_the_forward_rest_angles():
+    # rewriting the world's rest angles between forward and backward must not
+    # change the gradient: the backward recomputes with the forward's angles
+    sim = _sim()
+    w = wl.random_world(5, 48, 48, [14, 9, 20], amp=0.5)
+    target = torch.tensor(w.positions64() + 0.3, dtype=torch.float64, device="cuda")
+
+    def grad(mutate):
+        W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny))
+        ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
+        xT = sim.Rollout.apply(ra, W, 0, 10, 5)
+        loss = ((xT - target) ** 2).sum() / xT.shape[1]
+        if mutate:
+            W.state.rest_angle.add_(0.3)
+        loss.backward()
+        torch.cuda.synchronize()
+        if mutate:       # the world's own (rewritten) angles are left as they were
+            assert torch.equal(W.state.rest_angle.cpu(),
+                               torch.tensor(w.rest_angle, dtype=torch.float32) + 0.3)
+        return ra.grad.cpu()
+
+    a, b = grad(False), grad(True)
+    assert float(a.abs().max()) > 0 and torch.equal(a, b)

@@ -2,7 +2,10 @@
 
 Each world's result in a batch (and in the served mix) must equal the same
 world run alone through sim_rollout: bitwise with the binned transfer, whose
-sums are order-independent 64-bit fixed point.
+sums are order-independent 64-bit fixed point.  Each retired world is also
+compared with the FP64 oracle run from its initial state for the same steps:
+positions (e_x <= 1e-5), the last step's grid velocity (e_u <= 1e-4) and the
+displacement over the run (e_d <= 1e-4); errors are printed.
 """
 import time
 
@@ -11,6 +14,7 @@ import pytest
 import torch
 
 from paper_2607_02954_amd import workloads as wl
+from parity_util import TOL_D, TOL_U, TOL_X, final_state_errors, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +44,13 @@ def _worlds():
                                                 (72, 50, [3, 1, 17]), (64, 96, [12] * 30)])]
 
 
+def _check_oracle(sim, w, st, steps, label):
+    op = oracle_params(sim.Params(nx=w.nx, ny=w.ny))
+    ex, ea, eu, ed = final_state_errors(w, st, op, 0, steps)
+    print(f"{label}, {steps} steps vs oracle: e_x={ex:.2e} e_a={ea:.2e} cells e_u={eu:.2e} e_d={ed:.2e}")
+    assert ex <= TOL_X and eu <= TOL_U and ed <= TOL_D, (label, ex, eu, ed)
+
+
 def test_batch_equals_single_worlds():
     sim, batch, _ = _mods()
     worlds = _worlds()
@@ -51,6 +62,7 @@ def test_batch_equals_single_worlds():
     for w, s, st in zip(worlds, slots, steps):
         got = eng.retire(s, w)
         assert _same(got, _alone(sim, w, st)), (w.nx, w.ny, st)
+        _check_oracle(sim, w, got, st, f"batch {w.nx}x{w.ny} N={w.n_particles}")
 
 
 def test_batch_pool_exhaustion_and_slot_limit():
@@ -100,6 +112,7 @@ def test_served_results_equal_alone_runs():
     assert stats.peak_resident >= 2
     for job, r in zip(jobs, stats.results):
         assert _same(r.state, _alone(sim, job.world, job.steps)), job.job_id
+        _check_oracle(sim, job.world, r.state, job.steps, f"served job {job.job_id}")
     print("served:", stats.summary())
 
 

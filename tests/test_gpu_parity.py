@@ -1,8 +1,10 @@
 """GPU (HIP, FP32) versus the FP64 oracle, element by element, through the C ABI.
 
-Acceptance (per step, measured errors printed):
+Acceptance (per step, measured errors printed; measures in parity_util):
   e_x = max_i |x_gpu - x_ref|_inf / max_i |x_ref|_inf  <= 1e-5
   e_u = max_c |u_gpu - u_ref|_inf / max_c |u_ref|_inf  <= 1e-4
+  e_d (each step's displacement, both sides from the GPU's state) <= 1e-4
+and the largest absolute position error in cells is printed beside them.
 Sub-steps are compared normwise with tolerances derived from FP32 rounding of
 O(10)-term sums (a few 1e-7 relative), allowing for atomics' arbitrary order.
 """
@@ -14,11 +16,11 @@ import torch
 
 import oracle as O
 from paper_2607_02954_amd import workloads as wl
+from parity_util import (TOL_D, TOL_U, TOL_X, abs_err, disp_err, oracle_from, oracle_params, rel,
+                         state64)
 
 pytestmark = pytest.mark.gpu
 
-TOL_X = 1e-5
-TOL_U = 1e-4
 DT = torch.float64
 
 
@@ -27,21 +29,6 @@ def _sim():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return sim
-
-
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    den = np.max(np.abs(b)) if b.size else 0.0
-    num = np.max(np.abs(a - b)) if b.size else 0.0
-    return num / den if den > 0 else num
-
-
-def oracle_params(p):
-    return O.Params(nx=p.nx, ny=p.ny, tau=p.tau, trt_magic=p.trt_magic, k_bend=p.k_bend,
-                    k_stretch=p.k_stretch, k_shear=p.k_shear, pbd_iters=p.pbd_iters,
-                    k_elastic=p.k_elastic, k_repulse=p.k_repulse, sigma=p.sigma_repulse,
-                    radius=p.repulse_radius, u_max=p.u_max)
 
 
 def ragged_world(seed=0):
@@ -104,42 +91,72 @@ def test_substeps_match_oracle(mode):
     assert np.max(np.abs(fg - fref)) < 1e-6
     W.substep(4, t)
     torch.cuda.synchronize()
-    xref = (x + O.interpolate(x, tr["u"], op)).numpy()
-    assert rel(W.state.positions64(), xref) < TOL_X
-    print(f"substeps[{mode}]: e_el={e_el:.2e} e_u={e_u:.2e}")
+    dref = O.interpolate(x, tr["u"], op).numpy()
+    xg = W.state.positions64()
+    xref = x.numpy() + dref
+    e_x, e_d = rel(xg, xref), disp_err(xg - x.numpy(), dref)
+    assert e_x < TOL_X and e_d < TOL_D, (e_x, e_d)
+    print(f"substeps[{mode}]: e_el={e_el:.2e} e_u={e_u:.2e} e_x={e_x:.2e} e_d={e_d:.2e} "
+          f"(max step {np.max(np.abs(dref)):.2e} cells, abs err {abs_err(xg, xref):.2e} cells)")
 
 
-def _rollout_compare(sim, w, n, mode, **kw):
+class Errs:
+    """Largest e_x, e_a, e_u, e_d seen over a run."""
+
+    def __init__(self):
+        self.ex = self.ea = self.eu = self.ed = 0.0
+
+    def add(self, ex, ea, eu, ed):
+        self.ex, self.ea = max(self.ex, ex), max(self.ea, ea)
+        self.eu, self.ed = max(self.eu, eu), max(self.ed, ed)
+
+    def __str__(self):
+        return f"e_x={self.ex:.2e} e_a={self.ea:.2e} cells e_u={self.eu:.2e} e_d={self.ed:.2e}"
+
+
+def _rollout_compare(sim, w, n, mode, report_every=0, **kw):
+    """n single steps on the GPU beside the oracle's own trajectory (e_x, e_a,
+    e_u at every step) and, every step, an oracle step from the GPU's state
+    (e_d of that step's displacement)."""
     W, op = _mk(sim, w, mode, **kw)
     inp = O.inputs_from_world(w)
     x = O.positions_from_world(w)
     f = O.rest_populations(op)
-    ex_max = eu_max = 0.0
+    E = Errs()
     for t in range(n):
+        xs, fs = gpu_state(W)                       # shared state of this step
+        xs_next, _, _ = oracle_from(xs, fs, t, 1, inp, op)
         W.step(t)
-        x, f, u = O.step(x, f, t, inp, op)
+        with torch.no_grad():
+            x, f, u = O.step(x, f, t, inp, op)
         torch.cuda.synchronize()
-        ex = rel(W.state.positions64(), x.numpy())
+        xg = W.state.positions64()
+        ex, ea = rel(xg, x.numpy()), abs_err(xg, x.numpy())
         eu = rel(W.state.velocity64(), u.numpy())
-        ex_max, eu_max = max(ex_max, ex), max(eu_max, eu)
+        ed = disp_err(xg - xs.numpy(), (xs_next - xs).numpy())
+        E.add(ex, ea, eu, ed)
         assert ex <= TOL_X, (t, ex)
         assert eu <= TOL_U, (t, eu)
+        assert ed <= TOL_D, (t, ed)
+        if report_every and (t + 1) % report_every == 0:
+            print(f"  [{mode}] step {t + 1:5d}: e_x={ex:.2e} e_a={ea:.2e} cells e_u={eu:.2e} e_d={ed:.2e} "
+                  f"(max so far: {E})", flush=True)
     W.sync()
-    return ex_max, eu_max
+    return E
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_single_chain_100_steps(mode):
     sim = _sim()
-    ex, eu = _rollout_compare(sim, wl.parity_single(0), 100, mode)
-    print(f"single chain 32 nodes 64^2, 100 steps: max e_x={ex:.2e} max e_u={eu:.2e}")
+    E = _rollout_compare(sim, wl.parity_single(0), 100, mode)
+    print(f"single chain 32 nodes 64^2, 100 steps [{mode}]: {E}")
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_ragged_population_100_steps(mode):
     sim = _sim()
-    ex, eu = _rollout_compare(sim, ragged_world(2), 100, mode)
-    print(f"ragged population: max e_x={ex:.2e} max e_u={eu:.2e}")
+    E = _rollout_compare(sim, ragged_world(2), 100, mode)
+    print(f"ragged population, 100 steps [{mode}]: {E}")
 
 
 def test_graph_rollout_equals_stepwise_and_sorted_is_deterministic():
@@ -199,8 +216,8 @@ def test_edge_cases(mode):
     assert float(W.state.f.abs().max()) < 1e-7
     # one long filament (> 256 nodes uses the 1024-node pack) plus single nodes
     long = wl.random_world(5, 96, 96, [600, 1, 1, 2], amp=0.5)
-    ex, eu = _rollout_compare(sim, long, 10, mode)
-    print(f"long filament: e_x={ex:.2e} e_u={eu:.2e}")
+    E = _rollout_compare(sim, long, 10, mode)
+    print(f"long filament [{mode}]: {E}")
 
 
 def test_mach_guard_flags_world():
@@ -218,8 +235,8 @@ def test_uniform_population_full_size_steps(mode):
     # positions and u after each of 3 steps from the shared state
     sim = _sim()
     w = wl.uniform_population(0)
-    ex, eu = _rollout_compare(sim, w, 3, mode)
-    print(f"uniform 65536 nodes 512^2: e_x={ex:.2e} e_u={eu:.2e}")
+    E = _rollout_compare(sim, w, 3, mode)
+    print(f"uniform 65536 nodes 512^2 [{mode}]: {E}")
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -229,8 +246,8 @@ def test_small_and_ragged_grids(mode):
     sim = _sim()
     for (nx, ny, lens) in [(8, 8, [3]), (40, 24, [6, 4]), (72, 50, [20, 1, 9])]:
         w = wl.random_world(7, nx, ny, lens, amp=0.5)
-        ex, eu = _rollout_compare(sim, w, 12, mode)
-        print(f"{nx}x{ny}: e_x={ex:.2e} e_u={eu:.2e}")
+        E = _rollout_compare(sim, w, 12, mode)
+        print(f"{nx}x{ny} [{mode}]: {E}")
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -244,8 +261,8 @@ def test_partial_tiles_and_radii(mode):
                                    (130, 66, 1, 0.5, [25, 7, 80, 2]),
                                    (97, 129, 6, 1.5, [40, 3, 60, 2, 33])]:
         w = wl.random_world(11, nx, ny, lens, amp=0.5)
-        ex, eu = _rollout_compare(sim, w, 8, mode, repulse_radius=R, sigma_repulse=sig)
-        print(f"{nx}x{ny} R={R}: e_x={ex:.2e} e_u={eu:.2e}")
+        E = _rollout_compare(sim, w, 8, mode, repulse_radius=R, sigma_repulse=sig)
+        print(f"{nx}x{ny} R={R} [{mode}]: {E}")
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -265,28 +282,42 @@ def test_dense_world(mode):
         per_tile = [int(((((hx - x0 + 2) % 64) <= 34) & (((hy - y0 + 2) % 64) <= 34)).sum())
                     for y0 in (0, 32) for x0 in (0, 32)]
         assert max(per_tile) > 1024 and min(per_tile) <= 1024, per_tile
-    ex, eu = _rollout_compare(sim, w, 6, mode)
-    print(f"dense 3000 nodes 64x64 [{mode}]: e_x={ex:.2e} e_u={eu:.2e}")
+    E = _rollout_compare(sim, w, 6, mode)
+    print(f"dense 3000 nodes 64x64 [{mode}]: {E}")
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_scaling_workload_full_size(mode):
-    # the benchmark's million-node workload, in the benchmark's launch
-    # configuration (captured-graph rollout), two steps, every node and cell
+    # the benchmark's million-node workload at full size: every node and cell.
+    # The tile-binned transfer (the benchmark's) runs one captured 20-step
+    # chunk graph, the launch configuration the benchmark times; the two
+    # reference transfers run two steps.  Positions, u of the last step, and
+    # the displacement over the run from the shared initial state.
     sim = _sim()
     w = wl.scaling_population(0)
+    n = 20 if mode == "binned" else 2
     W, op = _mk(sim, w, mode)
-    W.rollout(0, 2)
+    W.rollout(0, n)
     W.sync()
     inp = O.inputs_from_world(w)
-    x, f = O.positions_from_world(w), O.rest_populations(op)
-    with torch.no_grad():
-        for t in range(2):
-            x, f, u = O.step(x, f, t, inp, op)
-    ex = rel(W.state.positions64(), x.numpy())
+    x0 = O.positions_from_world(w)
+    x, _, u = oracle_from(x0, O.rest_populations(op), 0, n, inp, op)
+    xg = W.state.positions64()
+    ex, ea = rel(xg, x.numpy()), abs_err(xg, x.numpy())
     eu = rel(W.state.velocity64(), u.numpy())
-    print(f"scaling 1M nodes 2048^2 [{mode}]: e_x={ex:.2e} e_u={eu:.2e}")
-    assert ex <= TOL_X and eu <= TOL_U
+    ed = disp_err(xg - x0.numpy(), (x - x0).numpy())
+    print(f"scaling 1M nodes 2048^2, {n} steps [{mode}]: e_x={ex:.2e} e_a={ea:.2e} cells e_u={eu:.2e} "
+          f"e_d={ed:.2e} (max displacement {float((x - x0).abs().max()):.2e} cells)")
+    assert ex <= TOL_X and eu <= TOL_U and ed <= TOL_D
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_parity_config_1000_steps(mode):
+    # the parity configuration in full: one 32-node chain on 64^2, 1000 steps,
+    # per-step errors asserted and the error growth printed every 100 steps
+    sim = _sim()
+    E = _rollout_compare(sim, wl.parity_single(0), 1000, mode, report_every=100)
+    print(f"single chain 32 nodes 64^2, 1000 steps [{mode}]: {E}")
 
 
 def test_binned_transfer_is_bitwise_reproducible():
