@@ -334,6 +334,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--pool-gib", type=float, default=8.0, help="HBM budget of the served pool")
     ap.add_argument("--tune-steps", type=int, default=20)
+    ap.add_argument("--probe-atomics", action="store_true",
+                    help="only measure the atomic-add throughput of the device (sim_measure_atomics)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -344,6 +346,10 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+
+    if args.probe_atomics:
+        print(json.dumps(sim.measure_atomics()), flush=True)
+        return
 
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
