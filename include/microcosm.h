@@ -23,7 +23,8 @@
  *  - All array pointers are DEVICE pointers owned by the caller; they must
  *    stay valid while a world or batch refers to them.  The library never
  *    allocates device memory: all scratch lives in caller-provided workspace
- *    or pool memory, sized with the *_size queries.
+ *    or pool memory, sized with the *_size queries (sim_step_noalloc uses a
+ *    static device array of the library instead).
  *  - `stream` arguments are hipStream_t values passed as void*; all work is
  *    enqueued asynchronously on that stream.  Only sim_sync, sim_batch_sync,
  *    sim_batch_retire and sim_create/sim_batch_admit (which read the CSR
@@ -172,6 +173,29 @@ sim_status sim_clear_flags(sim_world *w);
  * caller's device memory. */
 void sim_destroy(sim_world *w);
 const char *sim_last_error(void);
+
+/* For callers that cannot allocate memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): one step at time
+ * index t of the world given by *p and *a, with no world handle and no
+ * allocation of any kind.  It runs the kernels sim_create + sim_step run and
+ * gives the same result; its workspace (work tables, descriptors, per-step
+ * buffers) is a static 32 MiB device array of the library, one per device,
+ * held until the process ends (enough for a 512 x 512 grid with 65,536
+ * nodes).  Everything is enqueued on `stream`, which must belong to the
+ * current device; nothing is read back or synchronised.
+ *   p, a    as for sim_create (device arrays, caller-owned); positions, f and
+ *           u are updated in place when the stream reaches the end of the
+ *           call.  Every filament gets a block of its own (up to 1024 nodes).
+ *   status  optional DEVICE int32: receives SIM_OK, SIM_E_INVALID (the
+ *           filament offsets failed their checks: nothing was changed),
+ *           SIM_E_UNSTABLE (NaN or |u| > u_max) or SIM_E_STATE, written at
+ *           the end of the step.  May be NULL.
+ * Returns SIM_E_INVALID for bad parameters or arrays and SIM_E_WORKSPACE when
+ * the world needs more than the static array holds, both before anything is
+ * enqueued.  All calls on one device share its array: calls whose work
+ * overlaps on the device (different streams, or host threads) race and give
+ * undefined results; calls on one stream are ordered and safe. */
+sim_status sim_step_noalloc(const sim_params *p, const sim_arrays *a, int64_t t, int32_t *status, void *stream);
 
 /* Test hook: run a single sub-step kernel of step t on the current state
  * (which: 0 elastic force + deposit, 1 filter, 2 repulsion + spread,

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,15 +23,14 @@
 
 namespace {
 
-thread_local std::string g_err;
+// Fixed-size message buffer: reporting an error allocates nothing.
+thread_local char g_err[512];
 
 sim_status fail(sim_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
-  g_err = buf;
   return st;
 }
 
@@ -164,6 +164,78 @@ struct Slot {
   bool needs_zero = false;   // cnt must be cleared before first use
 };
 
+// Device descriptor of a world whose buffers are described by s; parity 0
+// reads populations buffer s.cur, parity 1 the other one.
+mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::Ctl* ctl_dst, unsigned* flags) {
+  const sim_params& p = s.p;
+  mc::WorldDev d{};
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.n_part = s.n_part;
+  d.n_fil = s.n_fil;
+  d.om_p = 1.0f / p.tau;
+  d.om_m = (float)(1.0 / ((double)p.trt_magic / ((double)p.tau - 0.5) + 0.5));
+  d.k_bend = p.k_bend;
+  d.k_stretch = p.k_stretch;
+  d.k_shear = p.k_shear;
+  d.k_el = p.k_elastic;
+  d.k_rep = p.k_repulse;
+  d.u_max2 = p.u_max * p.u_max;
+  d.pbd_iters = p.pbd_iters;
+  d.radius = p.repulse_radius;
+  d.mode = mode_of(p);
+  d.ntx = tiles_x(p);
+  d.nty = tiles_y(p);
+  {
+    double g[mc::kMaxRadius + 1];
+    double sum = 0.0;
+    const double s2 = 2.0 * (double)p.sigma_repulse * (double)p.sigma_repulse;
+    for (int k = 0; k <= p.repulse_radius; ++k) {
+      g[k] = std::exp(-(double)k * k / s2);
+      sum += (k == 0 ? 1.0 : 2.0) * g[k];
+    }
+    for (int k = 0; k <= mc::kMaxRadius; ++k) d.gtap[k] = k <= p.repulse_radius ? (float)(g[k] / sum) : 0.f;
+  }
+  d.fil_offset = s.fil_offset;
+  d.cell_in = s.cell;
+  d.frac_in = s.frac;
+  d.cell_out = s.cell;
+  d.frac_out = s.frac;
+  d.rest_angle = s.rest_angle;
+  d.rest_length = s.rest_length;
+  d.act_amp = s.amp;
+  d.act_period = s.period;
+  d.act_phase = s.phase;
+  const int src = parity == 0 ? s.cur : 1 - s.cur;
+  d.f_src = s.fbuf[src];
+  d.f_dst = s.fbuf[1 - src];
+  d.u = (float2*)s.u;
+  d.s = s.b.s;
+  d.grad = s.b.grad;
+  d.Fg = s.b.Fg;
+  d.fel = s.b.fel;
+  d.fel_el = s.b.fel_el;
+  d.ctl_src = ctl_src;
+  d.ctl_dst = ctl_dst;
+  d.flags = flags;
+  d.key = s.b.key;
+  d.rank = s.b.rank;
+  d.cnt = s.b.cnt;
+  d.start = s.b.start;
+  d.perm = s.b.perm;
+  d.rec = s.b.rec;
+  d.part = s.b.part;
+  d.bin_cnt = s.b.bin_cnt;
+  d.bin_fill = s.b.bin_fill;
+  d.bin_start = s.b.bin_start;
+  d.bin_start_next = s.b.bin_start;
+  d.bin_rec = s.b.bin_rec;
+  d.tile_rng = s.b.tile_rng;
+  d.sp_rec = s.b.sp_rec;
+  d.sp_cnt = s.b.sp_cnt;
+  return d;
+}
+
 // Zero an int array with a kernel (never a memset node; see graph capture).
 __global__ void k_zero_i32(int* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
@@ -258,74 +330,7 @@ struct Engine {
   }
 
   mc::WorldDev make_desc(int w, int parity) const {
-    const Slot& s = slots[w];
-    const sim_params& p = s.p;
-    mc::WorldDev d{};
-    d.nx = p.nx;
-    d.ny = p.ny;
-    d.n_part = s.n_part;
-    d.n_fil = s.n_fil;
-    d.om_p = 1.0f / p.tau;
-    d.om_m = (float)(1.0 / ((double)p.trt_magic / ((double)p.tau - 0.5) + 0.5));
-    d.k_bend = p.k_bend;
-    d.k_stretch = p.k_stretch;
-    d.k_shear = p.k_shear;
-    d.k_el = p.k_elastic;
-    d.k_rep = p.k_repulse;
-    d.u_max2 = p.u_max * p.u_max;
-    d.pbd_iters = p.pbd_iters;
-    d.radius = p.repulse_radius;
-    d.mode = mode_of(p);
-    d.ntx = tiles_x(p);
-    d.nty = tiles_y(p);
-    {
-      double g[mc::kMaxRadius + 1];
-      double sum = 0.0;
-      const double s2 = 2.0 * (double)p.sigma_repulse * (double)p.sigma_repulse;
-      for (int k = 0; k <= p.repulse_radius; ++k) {
-        g[k] = std::exp(-(double)k * k / s2);
-        sum += (k == 0 ? 1.0 : 2.0) * g[k];
-      }
-      for (int k = 0; k <= mc::kMaxRadius; ++k) d.gtap[k] = k <= p.repulse_radius ? (float)(g[k] / sum) : 0.f;
-    }
-    d.fil_offset = s.fil_offset;
-    d.cell_in = s.cell;
-    d.frac_in = s.frac;
-    d.cell_out = s.cell;
-    d.frac_out = s.frac;
-    d.rest_angle = s.rest_angle;
-    d.rest_length = s.rest_length;
-    d.act_amp = s.amp;
-    d.act_period = s.period;
-    d.act_phase = s.phase;
-    const int src = parity == 0 ? s.cur : 1 - s.cur;
-    d.f_src = s.fbuf[src];
-    d.f_dst = s.fbuf[1 - src];
-    d.u = (float2*)s.u;
-    d.s = s.b.s;
-    d.grad = s.b.grad;
-    d.Fg = s.b.Fg;
-    d.fel = s.b.fel;
-    d.fel_el = s.b.fel_el;
-    d.ctl_src = ctl[parity] + w;
-    d.ctl_dst = ctl[1 - parity] + w;
-    d.flags = flags + w;
-    d.key = s.b.key;
-    d.rank = s.b.rank;
-    d.cnt = s.b.cnt;
-    d.start = s.b.start;
-    d.perm = s.b.perm;
-    d.rec = s.b.rec;
-    d.part = s.b.part;
-    d.bin_cnt = s.b.bin_cnt;
-    d.bin_fill = s.b.bin_fill;
-    d.bin_start = s.b.bin_start;
-    d.bin_start_next = s.b.bin_start;
-    d.bin_rec = s.b.bin_rec;
-    d.tile_rng = s.b.tile_rng;
-    d.sp_rec = s.b.sp_rec;
-    d.sp_cnt = s.b.sp_cnt;
-    return d;
+    return world_desc(slots[w], parity, ctl[parity] + w, ctl[1 - parity] + w, flags + w);
   }
 
   // Rebuild work tables and descriptors from the slot list and upload them.
@@ -587,7 +592,7 @@ void sim_params_default(sim_params* p, int32_t nx, int32_t ny) {
   p->flags = 0;
 }
 
-const char* sim_last_error(void) { return g_err.c_str(); }
+const char* sim_last_error(void) { return g_err; }
 
 sim_status sim_workspace_size(const sim_params* p, int32_t n_filaments, int32_t n_particles, size_t* bytes) {
   sim_status st = check_params(p);
@@ -860,6 +865,239 @@ sim_status sim_debug_buffer(sim_world* w, int32_t which, void** ptr) {
     case 4: *ptr = s.b.fel_el; break;
     default: return fail(SIM_E_INVALID, "unknown buffer %d", which);
   }
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One step with no world handle and no allocation (sim_step_noalloc)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;   // 32 MiB per device
+
+}  // namespace
+
+// The workspace of sim_step_noalloc: descriptors, work tables and per-step
+// buffers of one world.  Every device the call runs on holds its own copy
+// until the process ends.  Host code never passes this name to a kernel or a
+// copy (in host code it is not a device address): it uses the per-device
+// address that hipGetSymbolAddress returned.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+
+// Address of this device's scratch array, looked up once per device with
+// that device current (concurrent first calls look it up twice, harmlessly).
+sim_status scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SIM_E_INVALID, "device %d out of range", dev);
+  void* ptr = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!ptr) {
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr % kAlign)) return fail(SIM_E_HIP, "scratch array has no usable address");
+    g_scratch_ptr[dev].store(ptr, std::memory_order_release);
+  }
+  *out = ptr;
+  return SIM_OK;
+}
+
+// Layout of the scratch array for one world (base == nullptr: sizing only).
+struct NoallocLayout {
+  mc::WorldDev* desc = nullptr;   // [2]: step parity 0 and 1
+  mc::Ctl* ctl = nullptr;         // [2]
+  unsigned* flags = nullptr;      // [1] sticky world flags
+  int* counts = nullptr;          // [8] work-list lengths (as the engine's tables)
+  int* err = nullptr;             // [1] validation failures of the filament offsets
+  mc::Pack* packs = nullptr;      // [F] one filament per pack
+  int2* items = nullptr;          // fluid items
+  int2* scan = nullptr;           // scan items (sorted transfer)
+  int2* wlist = nullptr;          // [1]
+  WorldBufs b;
+  size_t bytes = 0;
+};
+
+void carve_noalloc(char* base, const sim_params& p, int n_fil, int n_part, NoallocLayout& L) {
+  Carver c{base};
+  const size_t ncell = (size_t)p.nx * p.ny;
+  L.desc = c.take<mc::WorldDev>(2);
+  L.ctl = c.take<mc::Ctl>(2);
+  L.flags = c.take<unsigned>(1);
+  L.counts = c.take<int>(8);
+  L.err = c.take<int>(1);
+  L.packs = c.take<mc::Pack>(std::max(n_fil, 1));
+  L.items = c.take<int2>((ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem);
+  L.scan = c.take<int2>((ncell + 1023) / 1024);
+  L.wlist = c.take<int2>(1);
+  carve_world_bufs(c, p, n_part, L.b);
+  L.bytes = c.off;
+}
+
+constexpr int kErrOffsets = 1;    // fil_offset[0] != 0 or fil_offset[F] != N
+constexpr int kErrLength = 2;     // a filament outside 1..kMaxFilament nodes
+
+// Work tables and descriptors of the world, written on the device (nothing
+// is read back to the host): filament f is pack f; its length is checked.
+__global__ void k_noalloc_setup(mc::WorldDev d0, mc::WorldDev d1, NoallocLayout L, const int* fil_offset, int n_fil,
+                                int n_part, int n_items, int n_scan, long long t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_fil) {
+    const int a = fil_offset[i], e = fil_offset[i + 1];
+    if (e - a < 1 || e - a > mc::kMaxFilament) atomicOr(L.err, kErrLength);
+    mc::Pack pk{};
+    pk.world = 0;
+    pk.node_begin = a;
+    pk.node_end = e;
+    pk.fil_begin = i;
+    pk.fil_end = i + 1;
+    L.packs[i] = pk;
+  }
+  if (i < n_items) L.items[i] = make_int2(0, i * mc::kCellsPerItem);
+  if (i < n_scan) L.scan[i] = make_int2(0, i);
+  if (i == 0) {
+    if (n_fil > 0 && (fil_offset[0] != 0 || fil_offset[n_fil] != n_part)) atomicOr(L.err, kErrOffsets);
+    L.desc[0] = d0;
+    L.desc[1] = d1;
+    mc::Ctl c0;
+    c0.t = t;
+    c0.remaining = 1;
+    c0.pad = 0;
+    L.ctl[0] = c0;
+    mc::Ctl c1 = c0;
+    c1.remaining = 0;
+    L.ctl[1] = c1;
+    *L.flags = 0u;
+    *L.wlist = make_int2(0, 0);
+  }
+}
+
+// Work-list lengths, or none at all (every kernel then idles) when the
+// offsets failed their checks.
+__global__ void k_noalloc_counts(NoallocLayout L, int n_packs, int n_tiles, int n_scan, int n_items) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const bool ok = *L.err == 0;
+  const int c[8] = {ok ? n_packs : 0, ok ? n_tiles : 0, ok ? n_scan : 0, ok ? 1 : 0, ok ? n_items : 0, 0, 0, 0};
+  for (int k = 0; k < 8; ++k) L.counts[k] = c[k];
+  if (!ok) L.ctl[0].remaining = 0;
+}
+
+// The step's populations back into the caller's array (skipped if the step
+// did not run).
+__global__ void k_noalloc_copy_back(const int* err, const float* src, float* dst, size_t n) {
+  if (*err) return;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_noalloc_status(const int* err, const unsigned* flags, int32_t* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned f = *flags;
+  *status = *err ? SIM_E_INVALID : (f & mc::kFlagBins) ? SIM_E_STATE : f ? SIM_E_UNSTABLE : SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t, int32_t* status, void* stream) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_arrays(a))) return st;
+  NoallocLayout L;
+  carve_noalloc(nullptr, *p, a->n_filaments, a->n_particles, L);
+  if (L.bytes > kScratchBytes)
+    return fail(SIM_E_WORKSPACE, "world needs %zu bytes of scratch; sim_step_noalloc holds %zu", L.bytes,
+                kScratchBytes);
+  void* base = nullptr;
+  if ((st = scratch_address(&base))) return st;
+  carve_noalloc((char*)base, *p, a->n_filaments, a->n_particles, L);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t ncell = (size_t)p->nx * p->ny;
+  const size_t nt = n_bins(*p);
+  const int n_items = (int)((ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem);
+  const int n_scan = (int)((ncell + 1023) / 1024);
+  const int n_fil = a->n_filaments, n_part = a->n_particles;
+
+  // the world as the engine would describe it, over the scratch buffers
+  Slot sl;
+  sl.used = true;
+  sl.p = *p;
+  sl.n_fil = n_fil;
+  sl.n_part = n_part;
+  sl.fil_offset = const_cast<int*>(a->fil_offset);
+  sl.cell = a->cell;
+  sl.frac = a->frac;
+  sl.rest_angle = const_cast<float*>(a->rest_angle);
+  sl.rest_length = const_cast<float*>(a->rest_length);
+  sl.amp = const_cast<float*>(a->act_amp);
+  sl.period = const_cast<float*>(a->act_period);
+  sl.phase = const_cast<float*>(a->act_phase);
+  sl.b = L.b;
+  sl.fbuf[0] = a->f;
+  sl.fbuf[1] = L.b.f_alt;
+  sl.u = a->u;
+  sl.cur = 0;
+  const mc::WorldDev d0 = world_desc(sl, 0, L.ctl + 0, L.ctl + 1, L.flags);
+  const mc::WorldDev d1 = world_desc(sl, 1, L.ctl + 1, L.ctl + 0, L.flags);
+
+  mc::Tables tab{};
+  tab.packs = L.packs;
+  tab.n_packs = L.counts + 0;
+  tab.tiles = nullptr;
+  tab.n_tiles = L.counts + 1;
+  tab.scan = L.scan;
+  tab.n_scan = L.counts + 2;
+  tab.worlds = L.wlist;
+  tab.n_worlds = L.counts + 3;
+  tab.items = L.items;
+  tab.n_items = L.counts + 4;
+  tab.single_ntx = tiles_x(*p);
+  mc::Grid g{};
+  g.pack = 1024;                                  // one filament (<= 1024 nodes) per pack
+  g.node_blocks = std::max(1, std::min(n_fil, 8192));
+  g.tile_blocks = (int)std::max<size_t>(1, nt);
+  g.item_blocks = std::max(1, n_items);
+  g.scan_blocks = std::max(1, n_scan);
+  g.world_blocks = 1;
+  const int mode = mode_of(*p);
+  g.any_sorted = mode == mc::kSorted;
+  g.any_binned = mode == mc::kBinned;
+  g.any_node = mode != mc::kBinned;
+  g.max_radius = p->repulse_radius;
+
+  // the array keeps the previous call's contents: clear what starts at zero
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, L.err, (size_t)1);
+  if (L.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)L.b.Fg, 2 * ncell);
+  if (L.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)L.b.s, ncell);
+  if (L.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, L.b.cnt, ncell);
+  if (L.b.bin_cnt) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_cnt, nt);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_fill, nt);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.sp_cnt, nt);
+    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, L.b.tile_rng, s);
+  }
+  const int setup_n = std::max({n_fil, n_items, n_scan, 1});
+  hipLaunchKernelGGL(k_noalloc_setup, dim3((setup_n + 255) / 256), dim3(256), 0, s, d0, d1, L, a->fil_offset, n_fil,
+                     n_part, n_items, n_scan, (long long)t);
+  hipLaunchKernelGGL(k_noalloc_counts, dim3(1), dim3(64), 0, s, L, n_fil, (int)nt, n_scan, n_items);
+  // the step itself: the kernels sim_step runs, with parity-0 descriptors
+  mc::launch_bin_prepass(L.desc, tab, g, s);
+  mc::launch_elastic(L.desc, tab, g, s);
+  mc::launch_sort(L.desc, tab, g, s);
+  mc::launch_filter(L.desc, tab, g, s);
+  mc::launch_repulse(L.desc, tab, g, s);
+  mc::launch_spread(L.desc, tab, g, s);
+  mc::launch_lbm(L.desc, tab, g, s);
+  mc::launch_integrate(L.desc, tab, g, s);
+  hipLaunchKernelGGL(k_noalloc_copy_back, dim3(std::min<size_t>(2048, (9 * ncell + 255) / 256)), dim3(256), 0, s,
+                     L.err, (const float*)L.b.f_alt, a->f, 9 * ncell);
+  if (status) hipLaunchKernelGGL(k_noalloc_status, dim3(1), dim3(64), 0, s, L.err, L.flags, status);
+  HIPCHK(hipGetLastError());
   return SIM_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "sim_params_default", "sim_workspace_size", "sim_create", "sim_step", "sim_rollout",
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
-    "sim_profile_steps", "sim_measure_atomics",
+    "sim_profile_steps", "sim_measure_atomics", "sim_step_noalloc",
     "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
     "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
     "sim_batch_destroy",
@@ -94,6 +94,7 @@ def lib():
         "sim_debug_buffer": (i32, [vp, i32, P(vp)]),
         "sim_profile_steps": (i32, [vp, i64, i32, P(ctypes.c_float)]),
         "sim_measure_atomics": (i32, [vp, sz, vp, P(ctypes.c_double)]),
+        "sim_step_noalloc": (i32, [P(SimParams), P(SimArrays), i64, vp, vp]),
         "sim_batch_world_bytes": (i32, [P(SimParams), i32, i32, P(sz)]),
         "sim_batch_create": (i32, [i32, vp, sz, vp, P(vp)]),
         "sim_batch_admit": (i32, [vp, P(SimParams), P(SimArrays), i64, i32, P(i32)]),
@@ -202,6 +203,18 @@ def measure_atomics(device="cuda"):
     res["clock_hz"] = out[5]
     res["compute_units"] = int(out[6])
     return res
+
+
+def step_noalloc(state: "DeviceState", params: "Params", t: int, status: Optional[torch.Tensor] = None,
+                 stream=None):
+    """One step of the world held in `state` through sim_step_noalloc (no
+    handle, no workspace: the library's static device scratch).  `status`,
+    if given, is a device int32 tensor that receives the step's status."""
+    cp = params.c()
+    arr = state.arrays()
+    if status is not None:
+        assert status.dtype == torch.int32 and status.is_cuda
+    check(lib().sim_step_noalloc(ctypes.byref(cp), ctypes.byref(arr), int(t), _ptr(status), _stream_handle(stream)))
 
 
 class World:

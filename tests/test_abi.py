@@ -67,3 +67,19 @@ def test_params_mirror_matches_header_defaults():
     q = sim.Params(nx=32, ny=32).c()
     for name, _ in sim.SimParams._fields_:
         assert abs(getattr(p, name) - getattr(q, name)) < 1e-7, name
+
+
+def test_noalloc_size_limit_checked_on_host():
+    """sim_step_noalloc refuses a world larger than its static scratch before
+    touching the device (the pointers are never dereferenced)."""
+    sim = _lib()
+    L = sim.lib()
+    p = sim.SimParams()
+    L.sim_params_default(ctypes.byref(p), 2048, 2048)
+    fake = ctypes.c_void_p(256)
+    a = sim.SimArrays(1, 16, fake, fake, fake, fake, fake, fake, fake, fake, fake, fake)
+    st = L.sim_step_noalloc(ctypes.byref(p), ctypes.byref(a), 0, None, None)
+    assert st == sim.SIM_E_WORKSPACE
+    assert b"scratch" in L.sim_last_error()
+    p.tau = 0.4
+    assert L.sim_step_noalloc(ctypes.byref(p), ctypes.byref(a), 0, None, None) == sim.SIM_E_INVALID
