@@ -20,6 +20,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -114,18 +115,34 @@ def bench_served(seed, pool_gib, tune_steps):
                                             "node_blocks": [1024, 2048]})
     torch.cuda.empty_cache()
 
-    def run(js):
+    def run(js, live=False):
         eng = batch.BatchEngine(max_worlds=len(js), pool_bytes=pool_bytes)
         eng.set_tuning(best["chunk_steps"], best["cell_blocks"], best["node_blocks"])
         srv = serve.Server(serve.GpuExecutor(eng, pf), chunk_steps=best["chunk_steps"])
         torch.cuda.synchronize()
-        stats = srv.run(js)
+        if live:
+            # a producer thread submits each job at its Poisson arrival time
+            # while the loop runs on this thread
+            def producer():
+                t0 = time.perf_counter()
+                for j in sorted(js, key=lambda j: j.arrival):
+                    time.sleep(max(0.0, j.arrival - (time.perf_counter() - t0)))
+                    srv.submit(j)
+                srv.close()
+            th = threading.Thread(target=producer)
+            th.start()
+            stats = srv.serve(idle_poll=0.001)
+            th.join()
+            by_id = {r.job_id: r for r in stats.results}
+            stats.results = [by_id[j.job_id] for j in js]
+        else:
+            stats = srv.run(js)
         torch.cuda.synchronize()
         eng.close()
         return stats
 
     log(f"served: tuned {best}")
-    served = run(jobs)
+    served = run(jobs, live=True)
     log(f"served: Poisson run done {served.summary()['makespan_s']:.2f} s")
     offline = run([replace(j, arrival=0.0) for j in jobs])
     s_sum, o_sum = served.summary(), offline.summary()
@@ -155,6 +172,7 @@ def bench_served(seed, pool_gib, tune_steps):
     return {
         "workload": "256 served rollout jobs: filaments log-uniform 1..512, lengths U{8..128}, "
                     "grids 128^2..512^2 (step 32), 200..2000 steps, Poisson arrivals 50 jobs/s",
+        "submission": "live: a producer thread submits each job at its arrival time while the loop runs",
         "world_steps": steps,
         "particle_steps": int(sum(j.world.n_particles * j.steps for j in jobs)),
         "pool_bytes": pool_bytes,

@@ -116,6 +116,38 @@ def test_served_results_equal_alone_runs():
     print("served:", stats.summary())
 
 
+def test_live_submissions_match_oracle():
+    """Jobs submitted by a producer thread while the loop runs: every result
+    equals the same world run alone (bitwise) and matches the oracle."""
+    import threading
+    sim, batch, serve = _mods()
+    jobs = wl.served_jobs(1, n_jobs=8, rate=200.0, max_fil=30, len_range=(8, 40), side_range=(64, 96),
+                          steps_range=(20, 60))
+    pf = lambda job: sim.Params(nx=job.world.nx, ny=job.world.ny)
+    need = max(batch.BatchEngine.world_bytes(pf(j), j.world.n_filaments, j.world.n_particles) for j in jobs)
+    eng = batch.BatchEngine(max_worlds=4, pool_bytes=int(3.2 * need) + (8 << 20))
+    srv = serve.Server(serve.GpuExecutor(eng, pf), chunk_steps=10)
+    futs = []
+
+    def producer():
+        t0 = time.perf_counter()
+        for j in jobs:                           # the trace's gaps, in real time
+            time.sleep(max(0.0, j.arrival - (time.perf_counter() - t0)))
+            futs.append((j, srv.submit(j)))
+        srv.close()
+
+    th = threading.Thread(target=producer)
+    th.start()
+    stats = srv.serve(idle_poll=0.002)
+    th.join()
+    assert len(futs) == len(jobs) and all(f.result().ok for _, f in futs)
+    for job, f in futs:
+        r = f.result()
+        assert _same(r.state, _alone(sim, job.world, job.steps)), job.job_id
+        _check_oracle(sim, job.world, r.state, job.steps, f"live job {job.job_id}")
+    print("live:", stats.summary())
+
+
 def test_autotuner_picks_a_measured_setting(tmp_path, monkeypatch):
     sim, batch, _ = _mods()
     from paper_2607_02954_amd import autotune

@@ -1,4 +1,5 @@
 """Continuous-batching policy on the CPU: a fake executor and a virtual clock."""
+import time
 from dataclasses import dataclass
 
 import pytest
@@ -123,3 +124,100 @@ def test_oversized_job_is_rejected_and_idle_waits_for_arrivals():
 def test_chunk_must_be_even():
     with pytest.raises(ValueError):
         Server(FakeExecutor(Clock()), chunk_steps=7)
+
+
+def test_live_submissions_join_the_running_batch():
+    """Jobs submitted while the loop runs (here from the chunk callback, on
+    the virtual clock) are admitted between chunks beside the running ones."""
+    clk = Clock()
+    ex = FakeExecutor(clk, slots=4, budget=100, step_cost=1e-3)
+    futures = {}
+    schedule = {2: 1, 4: 2, 6: 3}                    # chunk number -> job submitted after it
+    seen = {"chunks": 0}
+
+    def producer(srv, resident):
+        seen["chunks"] += 1
+        k = schedule.get(seen["chunks"])
+        if k is not None:
+            futures[k] = srv.submit(FakeJob(k, None, 30 + 10 * k, 20))
+            if k == 3:
+                srv.close()
+
+    srv = Server(ex, chunk_steps=10, clock=clk, wait=clk.wait, on_chunk=producer)
+    futures[0] = srv.submit(FakeJob(0, None, 200, 30))
+    st = srv.serve()
+    assert len(st.results) == 4 and all(r.ok for r in st.results)
+    assert [r.job_id for r in st.results] == [0, 1, 2, 3]          # submission order
+    for k, fut in futures.items():
+        assert fut.done() and fut.result().ok
+        assert ex.steps_run[k] == fut.result().steps                # exact step counts
+    r0 = futures[0].result()
+    for k in (1, 2, 3):
+        rk = futures[k].result()
+        assert rk.arrival > 0 and rk.admitted < r0.finished         # joined while job 0 ran
+        assert rk.admitted - rk.arrival <= 10 * ex.step_cost + 1e-12   # within one chunk
+
+
+class SleepyExecutor(FakeExecutor):
+    """Fake executor on the real clock: every chunk sleeps briefly."""
+
+    def advance(self, n):
+        for s in self.rem:
+            ran = min(self.rem[s], n)
+            self.rem[s] -= ran
+            self.steps_run[self.jobs[s].job_id] += ran
+        time.sleep(n * self.step_cost)
+
+
+def test_submissions_from_producer_threads():
+    import threading
+    clk = time.perf_counter
+    ex = SleepyExecutor(clk, slots=3, budget=100, step_cost=2e-4)
+    srv = Server(ex, chunk_steps=10)
+    futs, lock = [], threading.Lock()
+
+    def producer(base):
+        for i in range(6):
+            f = srv.submit(FakeJob(base + i, None, 20 + 10 * i, 20 + (i % 3) * 10))
+            with lock:
+                futs.append((base + i, f))
+            time.sleep(0.003)
+
+    threads = [threading.Thread(target=producer, args=(100 * k,)) for k in range(3)]
+    for t in threads:
+        t.start()
+    closer = threading.Thread(target=lambda: ([t.join() for t in threads], srv.close()))
+    closer.start()
+    st = srv.serve(idle_poll=0.005)
+    closer.join()
+    assert len(st.results) == 18 and all(r.ok for r in st.results)
+    for jid, f in futs:
+        r = f.result(timeout=1)
+        assert r.ok and r.job_id == jid and ex.steps_run[jid] == r.steps
+        assert r.finished >= r.admitted >= r.arrival
+    assert st.peak_resident <= 3 and st.peak_bytes <= 100
+    with pytest.raises(RuntimeError):
+        srv.submit(FakeJob(999, None, 10, 10))                      # closed
+
+
+def test_asyncio_producer():
+    import asyncio
+    import threading
+    ex = SleepyExecutor(time.perf_counter, slots=2, budget=100, step_cost=1e-4)
+    srv = Server(ex, chunk_steps=10)
+    out = {}
+
+    async def produce():
+        tasks = []
+        for i in range(5):
+            tasks.append(asyncio.ensure_future(srv.submit_async(FakeJob(i, None, 20 + 5 * i, 30))))
+            await asyncio.sleep(0.002)
+        out["res"] = await asyncio.gather(*tasks)
+        srv.close()
+
+    th = threading.Thread(target=lambda: asyncio.run(produce()))
+    th.start()
+    st = srv.serve(idle_poll=0.005)
+    th.join()
+    assert [r.job_id for r in out["res"]] == [0, 1, 2, 3, 4]
+    assert all(r.ok for r in out["res"]) and len(st.results) == 5
