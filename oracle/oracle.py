@@ -434,3 +434,45 @@ def rollout_gradient(x0, f0, t0, n, inp: Inputs, p: Params, grad_xT, segment=20)
         if gra is not None:
             g_ra = g_ra + gra.detach()
     return g_ra, gx
+
+
+# ---------------------------------------------------------------------------
+# Folding objective (Experiments, Filament Folding): mean squared error
+# between the Gaussian-splatted node density at the final step and a target
+# image.  Reading: the image covers the periodic world; pixel (a, b) of a
+# W x H image is centred at world point (-1/2 + (a + 1/2) nx / W,
+# -1/2 + (b + 1/2) ny / H) (cells are centred at integer coordinates); node i
+# adds amp * exp(-r^2 / (2 sigma^2)) to every pixel whose centre lies within
+# r <= 5 sigma of it (periodic minimum-image distance, sigma in cells).
+# ---------------------------------------------------------------------------
+
+SPLAT_CUTOFF = 5.0      # truncation radius in units of sigma
+
+
+def pixel_centres(nx, ny, width, height):
+    """World coordinates of the pixel centres along x (width) and y (height)."""
+    cx = -0.5 + (torch.arange(width, dtype=DT) + 0.5) * (nx / width)
+    cy = -0.5 + (torch.arange(height, dtype=DT) + 0.5) * (ny / height)
+    return cx, cy
+
+
+def min_image(d, n):
+    """Periodic difference d reduced to [-n/2, n/2)."""
+    return d - n * torch.floor(d / n + 0.5)
+
+
+def density_image(x, nx, ny, width, height, sigma, amp=1.0):
+    """Gaussian-splatted density image [height, width] of nodes x [2, N]
+    (every node against every pixel, then the cutoff)."""
+    cx, cy = pixel_centres(nx, ny, width, height)
+    dx = min_image(x[0][:, None, None] - cx[None, None, :], nx)      # [N, 1, W]
+    dy = min_image(x[1][:, None, None] - cy[None, :, None], ny)      # [N, H, 1]
+    r2 = dx * dx + dy * dy                                           # [N, H, W]
+    g = amp * torch.exp(-r2 / (2.0 * sigma * sigma))
+    g = torch.where(r2 <= (SPLAT_CUTOFF * sigma) ** 2, g, torch.zeros_like(g))
+    return g.sum(dim=0)
+
+
+def density_loss(image, target):
+    """Mean over pixels of the squared difference to the target image."""
+    return ((image - target) ** 2).mean()
