@@ -105,11 +105,15 @@ def bench_served(seed, pool_gib, tune_steps):
     from paper_2607_02954_amd import autotune, batch, serve
 
     jobs = wl.served_jobs(seed)
-    pf = lambda job: sim.Params(nx=job.world.nx, ny=job.world.ny)
     pool_bytes = int(pool_gib * (1 << 30))
-    # tuning on a representative scratch batch (every 8th job)
+    # tuning on a representative scratch batch (every 8th job): the tile side
+    # per grid-size class first, then chunk and block counts with those sides
     rep = [j.world for j in jobs[::8]]
-    best, table = autotune.tune(rep, lambda w: sim.Params(nx=w.nx, ny=w.ny), pool_bytes,
+    policy, tile_table = autotune.tune_tiles(rep, lambda w: sim.Params(nx=w.nx, ny=w.ny), pool_bytes,
+                                             steps_per_trial=tune_steps)
+    log(f"served: tile sides per class {policy.sides}, otherwise {policy.default}")
+    pf = lambda job: policy.params(job.world)
+    best, table = autotune.tune(rep, policy.params, pool_bytes,
                                 steps_per_trial=tune_steps, use_cache=False,
                                 candidates={"chunk_steps": [10, 20, 40], "cell_blocks": [2048, 4096, 8192],
                                             "node_blocks": [1024, 2048]})
@@ -177,6 +181,9 @@ def bench_served(seed, pool_gib, tune_steps):
         "particle_steps": int(sum(j.world.n_particles * j.steps for j in jobs)),
         "pool_bytes": pool_bytes,
         "tuning": best,
+        "tile_side_per_grid_class": policy.sides,
+        "tile_side_default": policy.default,
+        "tile_tuning": tile_table,
         "served": {k: s_sum[k] for k in ("completed", "rollouts_per_s", "p50_latency_s", "p99_latency_s",
                                          "makespan_s", "chunks", "peak_resident", "peak_bytes")},
         "batched_all_arrived": {k: o_sum[k] for k in ("completed", "rollouts_per_s", "p50_latency_s",
@@ -247,6 +254,46 @@ def bench_adjoint(seed, reps=5):
         "bwd_over_fwd": bm / fm,
         "bwd_over_plain_fwd": bm / pm,
         "loss": float(loss),
+    }
+
+
+def bench_density_folding(seed, reps=3):
+    """The paper's folding objective at its sizes: one 1000-node filament on
+    256^2, 250 steps with checkpoints every 25, loss = mean squared error of
+    the Gaussian-splatted density (128 x 128 image, sigma 2 cells) to a seeded
+    target image; gradient in the rest angles (autograd: DensityLoss after
+    Rollout)."""
+    w = wl.density_folding(seed)
+    n, k, sigma, amp = 250, 25, 2.0, 0.1
+    W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny))
+    T = torch.tensor(w.meta["image"], dtype=torch.float32, device="cuda")
+    cell0, frac0 = W.state.cell.clone(), W.state.frac.clone()
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        W.state.cell.copy_(cell0)
+        W.state.frac.copy_(frac0)
+        W.state.f.zero_()
+        ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        xT = sim.Rollout.apply(ra, W, 0, n, k)
+        loss = sim.DensityLoss.apply(xT, w.nx, w.ny, T, sigma, amp)
+        ev[1].record()
+        loss.backward()
+        ev[2].record()
+        torch.cuda.synchronize()
+        if r:
+            fwd.append(ev[0].elapsed_time(ev[1]))
+            bwd.append(ev[1].elapsed_time(ev[2]))
+    W.close()
+    fm, bm = float(np.median(fwd)), float(np.median(bwd))
+    return {
+        "workload": "density folding: one 1000-node filament on 256x256, 250 steps, checkpoints every 25, "
+                    "loss = MSE of the Gaussian-splatted density (128x128 image, sigma 2 cells) to a seeded "
+                    "target image, gradient in the rest angles",
+        "forward_ms": fm, "backward_ms": bm, "bwd_over_fwd": bm / fm, "loss": float(loss),
+        "grad_norm": float(ra.grad.norm()),
     }
 
 
@@ -352,6 +399,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--pool-gib", type=float, default=8.0, help="HBM budget of the served pool")
     ap.add_argument("--tune-steps", type=int, default=20)
+    ap.add_argument("--tile", type=int, default=0, choices=[0, 16, 32, 64],
+                    help="grid tile side of the scaling workload (0: the autotuner's choice)")
     ap.add_argument("--probe-atomics", action="store_true",
                     help="only measure the atomic-add throughput of the device (sim_measure_atomics)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -392,7 +441,15 @@ def main():
 
     world = wl.scaling_population(args.seed)
     N, ncell = world.n_particles, world.nx * world.ny
-    W = sim.World(world, sim.Params(nx=world.nx, ny=world.ny))
+    # the autotuner's tile side for this world (each side timed over 40 steps)
+    if args.tile:
+        tile, tile_rows = args.tile, []
+    else:
+        from paper_2607_02954_amd import autotune
+        tile, tile_rows = autotune.tune_world_tile(world, sim.Params(nx=world.nx, ny=world.ny), steps=40)
+        torch.cuda.empty_cache()
+    log(f"scaling workload: tile side {tile} {tile_rows}")
+    W = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, tile=tile))
     secs = time_rollout(W, args.warmup, args.steps)
     ms_step = 1000.0 * secs / args.steps
     value = N * args.steps / secs
@@ -411,7 +468,7 @@ def main():
     variants = {}
     if not args.no_sorted:
         for mode in ("sorted", "direct"):
-            Ws = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, transfer=mode))
+            Ws = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, transfer=mode, tile=tile))
             s_secs = time_rollout(Ws, args.warmup, args.steps)
             skms = Ws.profile(t_next, args.profile_steps)
             variants[mode] = {
@@ -440,8 +497,9 @@ def main():
             "workload": "scaling: 1,048,576 nodes, chain lengths U{16..256}, 2048x2048 periodic grid, "
                         "active bending 0.5 rad, tile-binned particle-to-grid transfer",
             "particles": N, "filaments": world.n_filaments, "grid": [world.nx, world.ny],
-            "seed": args.seed,
+            "seed": args.seed, "tile_side": tile,
         },
+        "tile_tuning": tile_rows,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_lbm (D2Q9 TRT fluid update with Guo forcing)",
@@ -475,6 +533,8 @@ def main():
     if not args.no_adjoint:
         out["differentiation"] = bench_adjoint(args.seed)
         log("differentiation done")
+        out["density_folding"] = bench_density_folding(args.seed)
+        log("density folding done")
     if not args.no_served:
         out["batched_served"] = bench_served(args.seed, args.pool_gib, args.tune_steps)
         log("served done")

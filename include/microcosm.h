@@ -58,7 +58,7 @@ typedef enum sim_status {
 
 /* sim_params.flags */
 /* Particle -> grid transfer (deposit and force spread).  Default (no flag):
- * nodes are binned by the 32x32 grid tile of their home cell; every tile
+ * nodes are binned by the grid tile (side tile_side) of their home cell; every tile
  * reads the bins of its neighbourhood, sums the contributions that reach it
  * in on-chip memory (integer fixed point: results are bitwise reproducible)
  * and writes each cell once.  The two flags are exclusive. */
@@ -83,6 +83,10 @@ typedef struct sim_params {
   int32_t repulse_radius;  /* Gaussian filter truncation radius, 1..8                */
   float u_max;             /* Mach guard: |u| above this flags the world unstable    */
   uint32_t flags;          /* SIM_SPLAT_SORTED or SIM_SPLAT_DIRECT, else binned      */
+  int32_t tile_side;       /* side of the square grid tiles the transfer and filter
+                              kernels work on (and of the node bins): 16, 32 or 64;
+                              0 means 32.  A tuning choice: results do not depend
+                              on it beyond rounding (binned: not at all).          */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).
@@ -114,7 +118,7 @@ typedef struct sim_batch sim_batch;
 
 /* Fill *p with the defaults (tau 1, Lambda 1/4, k_bend 0.5, k_stretch 1,
  * k_shear 0.5, 4 PBD iterations, k_elastic 0.05, k_repulse 0.1, sigma 1,
- * radius 4, u_max 0.3, flags 0) for an nx x ny grid. */
+ * radius 4, u_max 0.3, flags 0, tile side 32) for an nx x ny grid. */
 void sim_params_default(sim_params *p, int32_t nx, int32_t ny);
 
 /* Bytes of device workspace sim_create needs for a world of this size. */
@@ -160,6 +164,34 @@ sim_status sim_backward_workspace_size(const sim_world *w, int32_t ckpt_every, s
 sim_status sim_backward(sim_world *w, int64_t t0, int32_t n_steps, int32_t ckpt_every,
                         const void *ckpt, const float *g_pos, float *g_rest_angle, float *g_pos0,
                         void *adj_ws, size_t adj_ws_bytes);
+
+/* Folding objective (Experiments, Filament Folding: mean squared error
+ * between the Gaussian-splatted node density at the final step and a target
+ * image).  The image covers the periodic nx x ny world: pixel (a, b) of a
+ * width x height image is centred at world point
+ * (-1/2 + (a + 1/2) nx/width, -1/2 + (b + 1/2) ny/height); every node adds
+ * amp * exp(-r^2 / (2 sigma^2)) to each pixel whose centre lies within
+ * r <= 5 sigma of it (periodic minimum-image distance).
+ *   L = (1 / (width height)) sum_pixels (image - target)^2.
+ * The image is summed as 64-bit fixed point (bitwise reproducible). */
+typedef struct sim_splat_image {
+  int32_t width, height;   /* pixels, 1..16384 each                              */
+  float sigma;             /* Gaussian width in cells, > 0                        */
+  float amp;               /* peak value of one node's Gaussian                   */
+} sim_splat_image;
+
+/* Device workspace bytes sim_density_loss needs for this image. */
+sim_status sim_density_loss_workspace_size(const sim_splat_image *img, size_t *bytes);
+/* Loss of the nodes at cell + frac ([2][N] device arrays, as in sim_arrays)
+ * against target ([height][width] device floats).  Writes *loss (one device
+ * float), the image if `image` is not NULL ([height][width] device floats)
+ * and dL/dx ([2][N] device floats, overwritten) if `g_pos` is not NULL; feed
+ * g_pos to sim_backward for the gradient in the rest angles.  workspace: 256-
+ * byte aligned device buffer of sim_density_loss_workspace_size bytes.
+ * SIM_E_INVALID if a node's Gaussian would cover more than 65536 pixels. */
+sim_status sim_density_loss(const sim_splat_image *img, int32_t nx, int32_t ny, int32_t n_particles,
+                            const int32_t *cell, const float *frac, const float *target, float *image,
+                            float *loss, float *g_pos, void *workspace, size_t ws_bytes, void *stream);
 
 /* Wait for the world's stream; report asynchronous HIP errors, the sticky
  * Mach/NaN flag (SIM_E_UNSTABLE), and SIM_E_STATE if the tile bins did not

@@ -28,32 +28,37 @@ constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registe
 // ---------------------------------------------------------------------------
 // Node -> grid spreads of adjoint node vectors (u~ and G~), tile-binned.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads) void k_adj_spread(const WorldDev* __restrict__ W, Tables T, const float* v,
-                                                    float scale_is_rep, float2* out) {
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const WorldDev* __restrict__ W, Tables T,
+                                                                         const float* v, float scale_is_rep,
+                                                                         float2* out) {
+  using C = TileCfg<TILE>;
+  constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells;
   __shared__ __align__(16) long long s_x[kSpreadCells];
   __shared__ __align__(16) long long s_y[kSpreadCells];
-  __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
-  const int nt = *T.n_tiles;
+  __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
+  const int nt = n_tiles<TILE>(T);
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = tile_entry(T, it);
+    const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     const int nx = w.nx, ny = w.ny;
-    const int x0 = tile_x(tl.y) * kTile;
-    const int y0 = tile_y(tl.y) * kTile;
-    const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
+    const int x0 = tile_x(tl.y) * TILE;
+    const int y0 = tile_y(tl.y) * TILE;
+    const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
     zero_lds_u64(s_x, kSpreadCells);
     zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
     const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
-    tile_spread_vec<false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
-                           spread_fetch(w, x0, y0), nullptr);
+    tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
+                                 spread_fetch<TILE>(w, x0, y0), nullptr);
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
-    for (int k = threadIdx.x; k < kTile * kTile; k += kTileThreads) {
-      const int ly = k >> 5, lx = k & (kTile - 1);
+    for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
+      const int ly = k >> C::kShift, lx = k & (TILE - 1);
       if (lx >= tw || ly >= th) continue;
-      const vf2 val = {fix_to_float(spread_cell(s_x, lx, ly, nx, ny)), fix_to_float(spread_cell(s_y, lx, ly, nx, ny))};
+      const vf2 val = {fix_to_float(spread_cell<TILE>(s_x, lx, ly, nx, ny)),
+                       fix_to_float(spread_cell<TILE>(s_y, lx, ly, nx, ny))};
       o[(size_t)(y0 + ly) * nx + x0 + lx] = val;
     }
     __syncthreads();
@@ -223,24 +228,26 @@ __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// S3 reversed: dL/ds = G (D^T dL/dG) on a 32x32 tile.  dL/dG is staged with
-// an (R+1)-cell halo; D^T maps it to an R-cell halo; the symmetric Gaussian
+// S3 reversed: dL/ds = G (D^T dL/dG) on a tile.  dL/dG is staged with an
+// (R+1)-cell halo; D^T maps it to an R-cell halo; the symmetric Gaussian
 // then runs as in the forward filter.
 // ---------------------------------------------------------------------------
-constexpr int kAdjRing = kTile + 2;
-constexpr int kAdjRegion = kAdjRing + 2 * kMaxRadius;
-constexpr int kAdjInner = kTile + 2 * kMaxRadius;
-
-__global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const WorldDev* __restrict__ W, Tables T,
+                                                                         AdjDev A) {
+  constexpr int kTile = TILE, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kAdjRing = kTile + 2;
+  constexpr int kAdjRegion = kAdjRing + 2 * kMaxRadius;
+  constexpr int kAdjInner = kTile + 2 * kMaxRadius;
   __shared__ float s_gx[kAdjRegion * kAdjRegion];
   __shared__ float s_gy[kAdjRegion * kAdjRegion];
   __shared__ float s_in[kAdjInner * kAdjInner];
   __shared__ float s_mid[kAdjInner * kTile];
-  const int nt = *T.n_tiles;
+  const int nt = n_tiles<TILE>(T);
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = tile_entry(T, it);
+    const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     const int R = w.radius;
     const int nx = w.nx, ny = w.ny;
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__
     const int rega = kAdjRing + 2 * R;       // dL/dG region, origin (x0-R-1, y0-R-1)
     const int regb = kTile + 2 * R;          // D^T dL/dG region, origin (x0-R, y0-R)
     const MC_GLOBAL vf2* gb = glbv<const vf2>(A.Gbar);
-    for (int k = tid; k < rega * rega; k += 256) {
+    for (int k = tid; k < rega * rega; k += kThreads) {
       const int r = k / rega, c = k - (k / rega) * rega;
       const vf2 v = gb[(size_t)wrap_index(y0 - R - 1 + r, ny) * nx + wrap_index(x0 - R - 1 + c, nx)];
       s_gx[k] = v.x;
@@ -257,14 +264,14 @@ __global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__
     }
     __syncthreads();
     // (D^T h)(c) = (h_x(c - e_x) - h_x(c + e_x)) / 2 + (h_y(c - e_y) - h_y(c + e_y)) / 2
-    for (int k = tid; k < regb * regb; k += 256) {
+    for (int k = tid; k < regb * regb; k += kThreads) {
       const int r = k / regb, c = k - (k / regb) * regb;
       const int ra = r + 1, ca = c + 1;
       s_in[k] = 0.5f * (s_gx[ra * rega + ca - 1] - s_gx[ra * rega + ca + 1]) +
                 0.5f * (s_gy[(ra - 1) * rega + ca] - s_gy[(ra + 1) * rega + ca]);
     }
     __syncthreads();
-    for (int k = tid; k < regb * kTile; k += 256) {
+    for (int k = tid; k < regb * kTile; k += kThreads) {
       const int r = k / kTile, c = k - (k / kTile) * kTile;
       const float* row = s_in + r * regb + c + R;
       float acc = w.gtap[0] * row[0];
@@ -273,8 +280,8 @@ __global__ __launch_bounds__(256) void k_adj_filter(const WorldDev* __restrict__
     }
     __syncthreads();
     MC_GLOBAL float* sb = glb(A.sbar);
-    for (int k = tid; k < kTile * kTile; k += 256) {
-      const int r = k >> 5, c = k & (kTile - 1);
+    for (int k = tid; k < kTile * kTile; k += kThreads) {
+      const int r = k >> TileCfg<TILE>::kShift, c = k & (kTile - 1);
       const float* col = s_mid + (r + R) * kTile + c;
       float acc = w.gtap[0] * col[0];
       for (int m = 1; m <= R; ++m) acc += w.gtap[m] * (col[-m * kTile] + col[m * kTile]);
@@ -514,12 +521,20 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
       KERNEL<1024><<<(G).node_blocks, 1024, 0, s>>>(__VA_ARGS__);                \
   } while (0)
 
+// One launch of a tile kernel per tile family present.
+#define MC_ADJ_TILES(KERNEL, G, ...)                                                              \
+  do {                                                                                            \
+    if ((G).tile_blocks[0] > 0) KERNEL<16><<<(G).tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(__VA_ARGS__); \
+    if ((G).tile_blocks[1] > 0) KERNEL<32><<<(G).tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(__VA_ARGS__); \
+    if ((G).tile_blocks[2] > 0) KERNEL<64><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
+  } while (0)
+
 void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s) {
-  k_adj_spread<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T, A.xbar_in, 0.f, A.ubar);
+  MC_ADJ_TILES(k_adj_spread, G, W, T, A.xbar_in, 0.f, A.ubar);
   k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
   MC_ADJ_PACK(k_adj_force, G, W, T, A);
-  k_adj_spread<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T, A.Fbar, 1.f, A.Gbar);
-  k_adj_filter<<<G.tile_blocks, 256, 0, s>>>(W, T, A);
+  MC_ADJ_TILES(k_adj_spread, G, W, T, A.Fbar, 1.f, A.Gbar);
+  MC_ADJ_TILES(k_adj_filter, G, W, T, A);
   MC_ADJ_PACK(k_adj_pbd, G, W, T, A);
 }
 

@@ -19,14 +19,43 @@ static __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Tile table entry it: (world, tx | ty << 16); computed rather than read when
-// the tables hold a single world.
+// Compile-time shape of the tile kernels for tiles of side TILE.
+constexpr int kWaveList = 64;              // records per wavefront list (for_bin_records)
+template <int TILE>
+struct TileCfg {
+  static constexpr int kTile = TILE;
+  static constexpr int kShift = tile_shift_of_side(TILE);
+  static constexpr int kFamily = tile_family_of_side(TILE);
+  static constexpr int kThreads = TILE == 64 ? 1024 : 256;   // threads per tile block
+  // bin columns (and rows) a reader's home range can touch, and bin runs
+  // it reads: the filter's range is the tile plus R + 3 <= 11 < TILE cells
+  // on each side, so it touches the tile and one neighbour per side, and
+  // one tile more where that neighbour is the partial last tile of an axis
+  // (shorter than the margin) on one side: at most 4; a row of bins needs at
+  // most two runs (its cyclic column list is broken once at most)
+  static constexpr int kMaxCols = 4;
+  static constexpr int kRanges = 2 * kMaxCols;
+  static constexpr int kSpreadSide = TILE + 6;              // spread window side
+  static constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
+  static constexpr int kSpreadCap = spread_cap_of_side(TILE);
+  static constexpr int kListBytes = (kThreads / 64) * kWaveList * 16;
+  static_assert(kRanges <= kRunStride, "run table too narrow");
+};
+
+// Tile table entry it of a tile family: (world, tx | ty << 16); computed
+// rather than read when the family holds a single world.
+template <int TILE>
 static __device__ __forceinline__ int2 tile_entry(const Tables& T, int it) {
-  if (T.single_ntx > 0) {
-    const int ty = it / T.single_ntx;
-    return make_int2(0, (it - ty * T.single_ntx) | (ty << 16));
+  constexpr int f = TileCfg<TILE>::kFamily;
+  if (T.single_ntx[f] > 0) {
+    const int ty = it / T.single_ntx[f];
+    return make_int2(0, (it - ty * T.single_ntx[f]) | (ty << 16));
   }
-  return T.tiles[it];
+  return T.tiles[f][it];
+}
+template <int TILE>
+static __device__ __forceinline__ int n_tiles(const Tables& T) {
+  return *T.n_tiles[TileCfg<TILE>::kFamily];
 }
 
 // Tile table entries hold (world, tx | ty << 16).
@@ -133,28 +162,30 @@ static __constant__ int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static __constant__ int kCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // Bin (home tile) of a wrapped home cell (bx, by) of a world with ntx tiles
-// per row, and the bin at tile column sx, row sy.
-static __device__ __forceinline__ int bin_of(int bx, int by, int ntx) { return (by >> 5) * ntx + (bx >> 5); }
+// per row of side 1 << shift, and the bin at tile column sx, row sy.
+static __device__ __forceinline__ int bin_of(int bx, int by, int ntx, int shift) {
+  return (by >> shift) * ntx + (bx >> shift);
+}
 static __device__ __forceinline__ int bin_at(int sx, int sy, int ntx) { return sy * ntx + sx; }
 
 // Distinct tile columns holding the cells lo..hi of a periodic axis of n
-// cells.  The ranges used here are at most 53 cells wide, so they touch at
-// most 4 columns (with the partial last tile of an axis when they wrap).
-constexpr int kMaxBinCols = 4;
-static __device__ __forceinline__ int bins_covering(int lo, int hi, int n, int t[kMaxBinCols]) {
+// cells (at most TileCfg<TILE>::kMaxCols for the ranges the readers use).
+template <int TILE>
+static __device__ __forceinline__ int bins_covering(int lo, int hi, int n, int* t) {
+  constexpr int kMax = TileCfg<TILE>::kMaxCols;
   int cnt = 0;
-  if (hi - lo + 1 >= n) {                       // whole axis (then n <= 53: at most 2 columns)
-    for (int k = 0; k * kTile < n && cnt < kMaxBinCols; ++k) t[cnt++] = k;
+  if (hi - lo + 1 >= n) {                       // whole axis (a short one)
+    for (int k = 0; k * TILE < n && cnt < kMax; ++k) t[cnt++] = k;
     return cnt;
   }
   int c = lo;
-  while (c <= hi && cnt < kMaxBinCols) {
+  while (c <= hi && cnt < kMax) {
     const int cc = wrap_index(c, n);
-    const int tt = cc / kTile;
+    const int tt = cc / TILE;
     bool seen = false;
     for (int k = 0; k < cnt; ++k) seen |= (t[k] == tt);
     if (!seen) t[cnt++] = tt;
-    c += min((tt + 1) * kTile, n) - cc;         // jump to the next tile boundary
+    c += min((tt + 1) * TILE, n) - cc;          // jump to the next tile boundary
   }
   return cnt;
 }
@@ -291,16 +322,14 @@ static __device__ __forceinline__ int block_scan256(int v, int* s_wave, int* tot
 // is needed until all records are done, body always runs on full wavefronts
 // (except for the last partial one), and lanes holding irrelevant records
 // never idle through it.  body(r) may only use per-lane work and LDS atomics.
-constexpr int kWaveList = 64;              // records per wavefront list
-constexpr int kListBytes = (kTileThreads / 64) * kWaveList * 16;
-
-// A bin set as every wavefront holds it, in scalar registers: range j covers
-// flat record numbers [pre[j], pre[j + 1]) (pre = 2^31 - 1 past the last
-// range), and flat number f of range j is record f + delta[j].
+// A bin set as every wavefront holds it, in scalar registers: range j (of
+// NR) covers flat record numbers [pre[j], pre[j + 1]) (pre = 2^31 - 1 past
+// the last range), and flat number f of range j is record f + delta[j].
+template <int NR>
 struct BinSet {
   int total;
-  int pre[kMaxRanges];
-  int delta[kMaxRanges];
+  int pre[NR];
+  int delta[NR];
 };
 
 static __device__ __forceinline__ void wave_sync() {
@@ -318,14 +347,15 @@ struct BinFetch {
 };
 
 // The bins holding homes in [lox, hix] x [loy, hiy] (periodic), as runs of
-// consecutive bins (first, end), written to out[kMaxRanges] and padded with
+// consecutive bins (first, end), written to out[kRunStride] and padded with
 // (0, 0).  Bins of one tile row are stored by increasing column, so a run of
 // consecutive columns is one contiguous record range; the column list is a
 // cyclic run, broken at most once where it wraps: at most two runs per row.
+template <int TILE>
 static __device__ void tile_runs(int lox, int hix, int loy, int hiy, int nx, int ny, int ntx, int2* out) {
-  int tx[kMaxBinCols], ty[kMaxBinCols];
-  const int ncx = bins_covering(lox, hix, nx, tx);
-  const int ncy = bins_covering(loy, hiy, ny, ty);
+  int tx[TileCfg<TILE>::kMaxCols], ty[TileCfg<TILE>::kMaxCols];
+  const int ncx = bins_covering<TILE>(lox, hix, nx, tx);
+  const int ncy = bins_covering<TILE>(loy, hiy, ny, ty);
   int n = 0;
   for (int r = 0; r < ncy; ++r) {
     int c = 0;
@@ -337,19 +367,20 @@ static __device__ void tile_runs(int lox, int hix, int loy, int hiy, int nx, int
       c += m;
     }
   }
-  for (; n < kMaxRanges; ++n) out[n] = make_int2(0, 0);
+  for (; n < kRunStride; ++n) out[n] = make_int2(0, 0);
 }
 
 // Fetch of the bin set of tile `tile` (row-major index) for reader `kind`
-// (0 filter, 1 spread) from the world's run table.
+// (0 filter, 1 spread) from the world's run table (NR runs).
+template <int NR>
 static __device__ __forceinline__ BinFetch binset_fetch(const WorldDev& w, int tile, int kind) {
   const int lane = __lane_id();
   BinFetch f;
-  f.n = kMaxRanges;
+  f.n = NR;
   f.b0 = 0;
   f.len = 0;
-  if (lane < kMaxRanges) {
-    const vi2 run = glbv<const vi2>(w.tile_rng)[((size_t)tile * 2 + kind) * kMaxRanges + lane];
+  if (lane < NR) {
+    const vi2 run = glbv<const vi2>(w.tile_rng)[((size_t)tile * 2 + kind) * kRunStride + lane];
     const MC_GLOBAL int* bstart = glb(w.bin_start);
     f.b0 = bstart[run.x];
     f.len = bstart[run.y] - f.b0;
@@ -357,22 +388,23 @@ static __device__ __forceinline__ BinFetch binset_fetch(const WorldDev& w, int t
   return f;
 }
 
-static __device__ __forceinline__ BinSet binset_commit(const BinFetch& f) {
+template <int NR>
+static __device__ __forceinline__ BinSet<NR> binset_commit(const BinFetch& f) {
   const int lane = __lane_id();
   const int len = lane < f.n ? f.len : 0;
-  int x = len;                                 // inclusive prefix over lanes 0..7
+  int x = len;                                 // inclusive prefix over lanes 0..NR-1
 #pragma unroll
-  for (int off = 1; off < kMaxRanges; off <<= 1) {
+  for (int off = 1; off < NR; off <<= 1) {
     const int y = __shfl_up(x, off);
     if (lane >= off) x += y;
   }
   const int excl = x - len;
   const int pre = lane < f.n ? excl : 0x7fffffff;
   const int del = f.b0 - excl;
-  BinSet bs;
-  bs.total = __builtin_amdgcn_readlane(x, kMaxRanges - 1);
+  BinSet<NR> bs;
+  bs.total = __builtin_amdgcn_readlane(x, NR - 1);
 #pragma unroll
-  for (int j = 0; j < kMaxRanges; ++j) {
+  for (int j = 0; j < NR; ++j) {
     bs.pre[j] = __builtin_amdgcn_readlane(pre, j);
     bs.delta[j] = __builtin_amdgcn_readlane(del, j);
   }
@@ -381,26 +413,26 @@ static __device__ __forceinline__ BinSet binset_commit(const BinFetch& f) {
 }
 
 // A list whose every record is needed (the spread lists the filter writes):
-// threads take the records in turn, with no keep test and no compaction.
-template <class Body>
-static __device__ __forceinline__ void for_list_records(const MC_GLOBAL vi4* recs, const BinSet& bs, Body body) {
+// the NT threads take the records in turn, with no keep test and no compaction.
+template <int NT, int NR, class Body>
+static __device__ __forceinline__ void for_list_records(const MC_GLOBAL vi4* recs, const BinSet<NR>& bs, Body body) {
   const int total = bs.total, off = bs.delta[0];
-  for (int f = (int)threadIdx.x; f < total; f += kTileThreads) {
+  for (int f = (int)threadIdx.x; f < total; f += NT) {
     const vi4 r = recs[f + off];
     body(r);
   }
   __syncthreads();
 }
 
-template <int PER, class Keep, class Body>
-static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs, const BinSet& bs, vi4* s_list,
+template <int PER, int NT, int NR, class Keep, class Body>
+static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs, const BinSet<NR>& bs, vi4* s_list,
                                                        Keep keep, Body body) {
   const int total = bs.total;
   const int lane = __lane_id();
   const unsigned long long below = (1ull << lane) - 1ull;
   vi4* wl = s_list + (threadIdx.x >> 6) * kWaveList;
   int cnt = 0;                                 // wavefront-uniform list length (< 64)
-  for (int base = 0; base < total; base += PER * kTileThreads) {
+  for (int base = 0; base < total; base += PER * NT) {
     // record indices first, then every load unconditionally (lanes past the
     // end reload the last record and drop it), so all PER loads are in flight
     // together instead of each waiting inside its own branch
@@ -408,12 +440,12 @@ static __device__ __forceinline__ void for_bin_records(const MC_GLOBAL vi4* recs
     bool k[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int f = base + i * kTileThreads + (int)threadIdx.x;
+      const int f = base + i * NT + (int)threadIdx.x;
       k[i] = f < total;
       const int fc = k[i] ? f : total - 1;
       int d = bs.delta[0];
 #pragma unroll
-      for (int j = 1; j < kMaxRanges; ++j) d = fc >= bs.pre[j] ? bs.delta[j] : d;
+      for (int j = 1; j < NR; ++j) d = fc >= bs.pre[j] ? bs.delta[j] : d;
       idx[i] = fc + d;
     }
     vi4 r[PER];
@@ -472,8 +504,6 @@ static __device__ __forceinline__ int first_image(int i, int n) {
 // zeroed (and synchronised) beforehand.  Values whose fixed-point image fits
 // 32 bits (|scale v| < 1/8, as nearly all forces) are converted by one
 // truncating 32-bit conversion; larger ones by the exact 64-bit split.
-constexpr int kSpreadSide = kTile + 6;
-constexpr int kSpreadCells = kSpreadSide * kSpreadSide;
 
 // Whether a node with home cell (hx, hy) reaches the spread window of the
 // tile at (x0, y0) of size tw x th (the keep rule of tile_spread_vec).
@@ -494,8 +524,10 @@ struct SpreadKeep {
 
 // The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th]
 // (run table kind 1).
+template <int TILE>
 static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x0, int y0) {
-  return binset_fetch(w, (y0 >> 5) * w.ntx + (x0 >> 5), 1);
+  constexpr int sh = TileCfg<TILE>::kShift;
+  return binset_fetch<TileCfg<TILE>::kRanges>(w, (y0 >> sh) * w.ntx + (x0 >> sh), 1);
 }
 
 // With s_g (REP), the spread value of a node is its total force: v (the
@@ -506,13 +538,15 @@ static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x
 // of the node kernels, so the forces are the same.  With LIST, `bins` names
 // one range of records that the tile needs, every one of them (its spread
 // list), so they skip the keep test.
-template <bool REP, bool LIST = false>
+template <int TILE, bool REP, bool LIST = false>
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
                                        long long* s_y, vi4* s_list, const MC_GLOBAL vi4* recs,
                                        const BinFetch& bins, const vf2* s_g) {
+  using C = TileCfg<TILE>;
+  constexpr int kSpreadSide = C::kSpreadSide;
   const int nx = w.nx, ny = w.ny, N = w.n_part;
-  const BinSet bs = binset_commit(bins);
+  const auto bs = binset_commit<C::kRanges>(bins);
   const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
   const int keep_x = tw + 3 <= nx ? tw + 2 : nx;     // largest kept home offset
   const int keep_y = th + 3 <= ny ? th + 2 : ny;
@@ -583,12 +617,14 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
         }
     }
   };
-  if constexpr (LIST) for_list_records(recs, bs, body);
-  else for_bin_records<4>(recs, bs, s_list, keep, body);
+  if constexpr (LIST) for_list_records<C::kThreads>(recs, bs, body);
+  else for_bin_records<4, C::kThreads>(recs, bs, s_list, keep, body);
 }
 
 // The accumulated value of tile cell (lx, ly) of a spread window.
+template <int TILE>
 static __device__ __forceinline__ long long spread_cell(const long long* s, int lx, int ly, int nx, int ny) {
+  constexpr int kSpreadSide = TileCfg<TILE>::kSpreadSide;
   const int cx0 = first_image(lx, nx), cy0 = first_image(ly, ny);
   if (cx0 + nx >= kSpreadSide && cy0 + ny >= kSpreadSide) return s[cy0 * kSpreadSide + cx0];
   long long acc = 0;

@@ -32,12 +32,19 @@ __device__ __forceinline__ MC_GLOBAL V* glbv(T* p) {
   return (MC_GLOBAL V*)p;
 }
 
-constexpr int kTile = 32;            // square grid tile of the filter and spread kernels
-constexpr int kTileThreads = 256;    // threads per block of the tile kernels
+// Square grid tiles of the tile kernels (filter, spread, integrate; node bins
+// of the binned transfer): side 16, 32 or 64 cells, chosen per world.  Each
+// side is a family of kernel instances; a table of worlds launches the
+// families it holds.
+constexpr int kTileFamilies = 3;
+__host__ __device__ constexpr int tile_side_of_family(int f) { return 16 << f; }
+__host__ __device__ constexpr int tile_family_of_side(int side) { return side == 16 ? 0 : side == 64 ? 2 : 1; }
+__host__ __device__ constexpr int tile_shift_of_side(int side) { return side == 16 ? 4 : side == 64 ? 6 : 5; }
+// records a tile's spread list holds (else it reads the bins): one per cell
+__host__ __device__ constexpr int spread_cap_of_side(int side) { return side * side; }
+constexpr int kRunStride = 8;        // bin runs stored per tile and reader
 constexpr int kCellsPerItem = 256;   // contiguous cells per fluid work item
 constexpr int kMaxRadius = 8;        // largest Gaussian truncation radius
-constexpr int kMaxRanges = 8;        // bin runs a tile reads (binned transfer)
-constexpr int kSpreadCap = 1024;     // records a tile's spread list holds (else it reads the bins)
 
 // Particle -> grid transfer modes (per world).
 enum TransferMode : int {
@@ -66,7 +73,7 @@ struct WorldDev {
   float om_p, om_m;                     // TRT rates: 1/tau and 1/(Lambda/(tau-1/2) + 1/2)
   float k_bend, k_stretch, k_shear, k_el, k_rep, u_max2;
   int pbd_iters, radius, mode, ntx;     // ntx, nty: tiles per row / column
-  int nty, pad0, pad1, pad2;
+  int nty, tile_shift, pad1, pad2;      // tile side = 1 << tile_shift
   float gtap[kMaxRadius + 1];           // normalised Gaussian taps g[0..R]
   const int* fil_offset;                // [F+1]
   const int* cell_in;  const float* frac_in;     // positions at the start of the step
@@ -97,10 +104,11 @@ struct WorldDev {
   int* bin_start_next;                  // where the scan after integrate puts the next step's
                                         // starts (bin_start itself, except on the adjoint tape)
   int4* bin_rec;                        // [N] record: (x | y << 16 home cell, frac x, frac y, node)
-  int4* sp_rec;                         // [ntx*nty][kSpreadCap] the records each tile's spread reads,
+  int4* sp_rec;                         // [ntx*nty][side^2] the records each tile's spread reads,
   int* sp_cnt;                          // [ntx*nty] and their number: both written by the filter
-  const int2* tile_rng;                 // [ntx*nty][2][8] bin runs (first, end) that the filter (0)
-                                        // and the spread (1) of each tile read; unused runs (0, 0)
+  const int2* tile_rng;                 // [ntx*nty][2][kRunStride] bin runs (first, end) that the
+                                        // filter (0) and the spread (1) of each tile read; unused
+                                        // runs (0, 0)
 };
 
 // A node pack: whole filaments with at most `pack` nodes, run by one block.
@@ -111,16 +119,18 @@ struct Pack {
 
 struct Tables {
   const Pack* packs;  const int* n_packs;
-  const int2* tiles;  const int* n_tiles;    // (world, tx | ty << 16), 32x32 cells
+  // per tile family: (world, tx | ty << 16) of every tile of the worlds with that tile side
+  const int2* tiles[kTileFamilies];  const int* n_tiles[kTileFamilies];
   const int2* items;  const int* n_items;    // (world, first cell) of 256 contiguous cells
   const int2* scan;   const int* n_scan;     // (world, block) for the cell scan (sorted mode)
   const int2* worlds; const int* n_worlds;   // (world, 0) for per-world kernels
-  int single_ntx;                            // > 0: the tables hold one world whose tiles are
+  int single_ntx[kTileFamilies];             // > 0: the family holds one world whose tiles are
                                              // its row-major tiles, ntx per row (no table read)
 };
 
 struct Grid {
-  int node_blocks, tile_blocks, scan_blocks, world_blocks, item_blocks;
+  int node_blocks, scan_blocks, world_blocks, item_blocks;
+  int tile_blocks[kTileFamilies];            // 0: no world of that tile side (family not launched)
   int pack;                                  // node pack capacity: 256 or 1024
   int any_sorted, any_binned, any_node;      // which transfer families the table holds
                                              // (any_node: a world not in binned mode)
@@ -158,9 +168,17 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, hipEvent_t start,
                       hipEvent_t stop);
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
-// set-up: the bin runs of every tile of an nx x ny world of Gaussian radius R
-void launch_tile_ranges(int nx, int ny, int R, int2* out, hipStream_t s);
+// set-up: the bin runs of every tile (side `tile`) of an nx x ny world of Gaussian radius R
+void launch_tile_ranges(int nx, int ny, int R, int tile, int2* out, hipStream_t s);
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s);
+
+// Folding objective (loss.hip): Gaussian-splatted node density on a W x H
+// image over the nx x ny world, its mean squared error to `target` (written
+// to *loss), the image (if `image`) and dL/dx of every node (if `g_pos`).
+size_t density_loss_workspace(int W, int H);
+void launch_density_loss(int nx, int ny, int n, int W, int H, float sigma, float amp, const int* cell,
+                         const float* frac, const float* target, float* image, float* loss, float* g_pos,
+                         void* ws, hipStream_t s);
 
 // Record msg as the thread's last error message (sim_last_error) and return st.
 int report_error(int st, const char* msg);

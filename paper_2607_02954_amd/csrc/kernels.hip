@@ -173,7 +173,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     if (mode == kBinned) {
       // this node's record in its home-tile bin (bins sized by the counts
       // of these positions: the previous step's integrate or the pre-pass)
-      const int tile = bin_of(bx, by, w.ntx);
+      const int tile = bin_of(bx, by, w.ntx, w.tile_shift);
       const int slot = agg_atomic_inc(glb(w.bin_fill), tile, active);
       if (active) {
         const MC_GLOBAL int* bstart = glb(w.bin_start);
@@ -294,7 +294,8 @@ __global__ __launch_bounds__(PACK) void k_bin_count(const WorldDev* __restrict__
     const int gi = pk.node_begin + threadIdx.x;
     const bool active = gi < pk.node_end;
     int tile = 0;
-    if (active) tile = bin_of(wrap_index(glb(w.cell_in)[gi], w.nx), wrap_index(glb(w.cell_in)[N + gi], w.ny), w.ntx);
+    if (active)
+      tile = bin_of(wrap_index(glb(w.cell_in)[gi], w.nx), wrap_index(glb(w.cell_in)[N + gi], w.ny), w.ntx, w.tile_shift);
     agg_atomic_inc(glb(w.bin_cnt), tile, active);
   }
 }
@@ -469,7 +470,7 @@ __device__ __forceinline__ vf2 gather_force(const MC_GLOBAL int* start, const MC
 }
 
 // ---------------------------------------------------------------------------
-// S2 + S3: density on a 32x32 tile plus an (R+1)-cell halo, staged in LDS,
+// S2 + S3: density on a tile (side TILE) plus an (R+1)-cell halo, staged in LDS,
 // the separable circular Gaussian (x pass, then y pass, both in LDS) on the
 // tile plus a one-cell ring, and the central difference G = D s~ of the
 // tile, written as interleaved float2.
@@ -480,22 +481,24 @@ __device__ __forceinline__ vf2 gather_force(const MC_GLOBAL int* start, const MC
 // and the inner loop is two 24-bit multiplies and an LDS add per cell.
 // Dynamic LDS: [window: filter_window_bytes(max radius) | list / density].
 // ---------------------------------------------------------------------------
-constexpr int kRing = kTile + 2;                    // tile plus the one-cell ring
-constexpr int kRegion = kRing + 2 * kMaxRadius;     // largest density region side
-
 // Window rows are kWinPad elements longer than the window side: an even
 // row length of 64-bit words puts vertically adjacent cells, which nodes
 // next to each other on a chain often deposit to at once, in the same LDS bank.
 constexpr int kWinPad = 1;
+template <int TILE>
 static __host__ __device__ constexpr int filter_window_bytes(int max_radius) {
-  return (kRing + 2 * max_radius + 6) * (kRing + 2 * max_radius + 6 + kWinPad) * 8;
+  return (TILE + 2 + 2 * max_radius + 6) * (TILE + 2 + 2 * max_radius + 6 + kWinPad) * 8;
 }
+template <int TILE>
 static __host__ __device__ constexpr int filter_list_bytes(int max_radius) {
-  return (kRing + 2 * max_radius) * (kRing + 2 * max_radius) * 4 > kListBytes
-             ? (kRing + 2 * max_radius) * (kRing + 2 * max_radius) * 4
-             : kListBytes;
+  return (TILE + 2 + 2 * max_radius) * (TILE + 2 + 2 * max_radius) * 4 > TileCfg<TILE>::kListBytes
+             ? (TILE + 2 + 2 * max_radius) * (TILE + 2 + 2 * max_radius) * 4
+             : TileCfg<TILE>::kListBytes;
 }
-static_assert(filter_window_bytes(1) >= (kRegion * kRing + kRing * kRing) * 4, "passes must fit the window");
+// the passes' intermediate rows (region x ring) and the filtered ring fit the window
+static_assert(filter_window_bytes<16>(1) >= ((16 + 2 + 2 * kMaxRadius) * 18 + 18 * 18) * 4, "window");
+static_assert(filter_window_bytes<32>(1) >= ((32 + 2 + 2 * kMaxRadius) * 34 + 34 * 34) * 4, "window");
+static_assert(filter_window_bytes<64>(1) >= ((64 + 2 + 2 * kMaxRadius) * 66 + 66 * 66) * 4, "window");
 
 // q = k / d for 0 <= k < 2^16 and 0 < d <= 64: (k + 1/2) / d is at least
 // 1/(2d) away from an integer, far beyond the FP32 rounding of the product.
@@ -504,36 +507,39 @@ static __device__ __forceinline__ int div_small(int k, float inv_d) {
 }
 
 // The bin set a filter tile reads: homes in [xo - 2, xo + reg] per axis
-// (xo = x0 - R - 1, reg = 34 + 2R), whose supports meet the density region
-// (run table kind 0).
+// (xo = x0 - R - 1, reg = TILE + 2 + 2R), whose supports meet the density
+// region (run table kind 0).
+template <int TILE>
 static __device__ __forceinline__ BinFetch filter_fetch(const WorldDev& w, int tile) {
-  return binset_fetch(w, tile_y(tile) * w.ntx + tile_x(tile), 0);
+  return binset_fetch<TileCfg<TILE>::kRanges>(w, tile_y(tile) * w.ntx + tile_x(tile), 0);
 }
 
 // Set-up: the runs of bins that the filter and the spread of every tile read
-// (they depend on the grid and the radius only).
+// (they depend on the grid, the tile side and the radius only).
+template <int TILE>
 __global__ void k_tile_ranges(int nx, int ny, int R, int2* out) {
-  const int ntx = (nx + kTile - 1) / kTile, nty = (ny + kTile - 1) / kTile;
+  const int ntx = (nx + TILE - 1) / TILE, nty = (ny + TILE - 1) / TILE;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntx * nty; t += gridDim.x * blockDim.x) {
-    const int x0 = (t % ntx) * kTile, y0 = (t / ntx) * kTile;
-    const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
-    const int reg = kRing + 2 * R, xo = x0 - R - 1, yo = y0 - R - 1;
-    tile_runs(xo - 2, xo + reg, yo - 2, yo + reg, nx, ny, ntx, out + (size_t)(2 * t) * kMaxRanges);
-    tile_runs(x0 - 2, x0 + tw, y0 - 2, y0 + th, nx, ny, ntx, out + (size_t)(2 * t + 1) * kMaxRanges);
+    const int x0 = (t % ntx) * TILE, y0 = (t / ntx) * TILE;
+    const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
+    const int reg = TILE + 2 + 2 * R, xo = x0 - R - 1, yo = y0 - R - 1;
+    tile_runs<TILE>(xo - 2, xo + reg, yo - 2, yo + reg, nx, ny, ntx, out + (size_t)(2 * t) * kRunStride);
+    tile_runs<TILE>(x0 - 2, x0 + tw, y0 - 2, y0 + th, nx, ny, ntx, out + (size_t)(2 * t + 1) * kRunStride);
   }
 }
 
 // The two passes of the separable Gaussian (radius R) over the density
-// region s_regf (reg x reg, reg = 34 + 2R) into the filtered tile-plus-ring
-// s_st (34 x 34), through s_mid (reg rows x 34).  Every thread forms two
-// adjacent outputs from taps read as aligned pairs (rows have even lengths);
-// each output is summed in the same order as a one-output loop would.
-// Ends with a barrier.
-template <int R>
+// region s_regf (reg x reg, reg = ring + 2R) into the filtered tile-plus-ring
+// s_st (ring x ring, ring = TILE + 2), through s_mid (reg rows x ring).
+// Every thread forms two adjacent outputs from taps read as aligned pairs
+// (rows have even lengths); each output is summed in the same order as a
+// one-output loop would.  Ends with a barrier.
+template <int TILE, int R>
 static __device__ __forceinline__ void filter_passes(const float* s_regf, float* s_mid, float* s_st, const float* g) {
+  constexpr int kRing = TILE + 2, kThreads = TileCfg<TILE>::kThreads;
   constexpr int reg = kRing + 2 * R, kHalf = kRing / 2;
   const int tid = threadIdx.x;
-  for (int k = tid; k < reg * kHalf; k += kTileThreads) {
+  for (int k = tid; k < reg * kHalf; k += kThreads) {
     const int r = k / kHalf, c = 2 * (k - (k / kHalf) * kHalf);
     const vf2* row = (const vf2*)(s_regf + r * reg + c);   // cells c .. c + 2R + 1 of row r
     float v[2 * R + 2];
@@ -553,7 +559,7 @@ static __device__ __forceinline__ void filter_passes(const float* s_regf, float*
     *(vf2*)(s_mid + r * kRing + c) = out;
   }
   __syncthreads();
-  for (int k = tid; k < kRing * kHalf; k += kTileThreads) {
+  for (int k = tid; k < kRing * kHalf; k += kThreads) {
     const int r = k / kHalf, c = 2 * (k - (k / kHalf) * kHalf);
     const vf2* col = (const vf2*)(s_mid + (r + R) * kRing + c);
     vf2 t[2 * R + 1];
@@ -571,24 +577,28 @@ static __device__ __forceinline__ void filter_passes(const float* s_regf, float*
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restrict__ W, Tables T, int window_bytes) {
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_filter(const WorldDev* __restrict__ W, Tables T,
+                                                                     int window_bytes) {
+  using C = TileCfg<TILE>;
+  constexpr int kRing = TILE + 2, kThreads = C::kThreads, kSpreadCap = C::kSpreadCap;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned long long* s_win = (unsigned long long*)smem;
   vi4* s_list = (vi4*)(smem + window_bytes);
   float* s_regf = (float*)(smem + window_bytes);
   float* s_mid = (float*)smem;
   __shared__ int s_spn;                          // records appended to the spread list
-  const int nt = *T.n_tiles;
+  const int nt = n_tiles<TILE>(T);
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = tile_entry(T, it);
+    const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     if (w.ctl_src->remaining <= 0) continue;
     const int R = w.radius, mode = w.mode;
     const int nx = w.nx, ny = w.ny;
-    const int x0 = tile_x(tl.y) * kTile;
-    const int y0 = tile_y(tl.y) * kTile;
+    const int x0 = tile_x(tl.y) * TILE;
+    const int y0 = tile_y(tl.y) * TILE;
     const int reg = kRing + 2 * R;
     const float inv_reg = 1.0f / (float)reg;
     const int xo = x0 - R - 1, yo = y0 - R - 1;   // region origin (unwrapped)
@@ -598,16 +608,16 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
       const int P = S + kWinPad;                  // row pitch
       zero_lds_u64(s_win, S * P);
       if (tid == 0) s_spn = 0;
-      const BinSet bs = binset_commit(filter_fetch(w, tl.y));
+      const auto bs = binset_commit<C::kRanges>(filter_fetch<TILE>(w, tl.y));
       const int ox = wrap_index(xo - 3, nx), oy = wrap_index(yo - 3, ny);
       const int keep_x = reg + 3 <= nx ? reg + 2 : nx;
       const int keep_y = reg + 3 <= ny ? reg + 2 : ny;
       // the records this tile's spread needs (a subset of the filter's: its
       // window lies inside the filter's) go to the tile's spread list
       const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
-      const SpreadKeep sp_keep(w, x0, y0, min(kTile, nx - x0), min(kTile, ny - y0));
+      const SpreadKeep sp_keep(w, x0, y0, min(TILE, nx - x0), min(TILE, ny - y0));
       MC_GLOBAL vi4* sp_rec = glbv<vi4>(w.sp_rec) + (size_t)tix * kSpreadCap;
-      for_bin_records<4>(
+      for_bin_records<4, kThreads>(
           glbv<const vi4>(w.bin_rec), bs, s_list,
           [&](const vi4& r) {
             const int dx = wrap_near((r.x & 0xffff) - 1 - ox, nx);
@@ -640,7 +650,7 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
       if (tid == 0) glb(w.sp_cnt)[tix] = s_spn;   // (for_bin_records ended with a barrier)
       // (the list area is free again after the barrier that ends for_bin_records)
       const bool single = reg + 3 <= nx && reg + 3 <= ny;   // one image per needed cell
-      for (int k = tid; k < reg * reg; k += kTileThreads) {
+      for (int k = tid; k < reg * reg; k += kThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         unsigned long long v;
         if (single) {
@@ -655,13 +665,13 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     } else if (mode == kSorted) {
       const MC_GLOBAL int* start = glb(w.start);
       const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
-      for (int k = tid; k < reg * reg; k += kTileThreads) {
+      for (int k = tid; k < reg * reg; k += kThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         s_regf[k] = gather_density(start, rec, nx, ny, wrap_index(xo + c, nx), wrap_index(yo + r, ny));
       }
     } else {
       const MC_GLOBAL float* sd = glb(w.s);
-      for (int k = tid; k < reg * reg; k += kTileThreads) {
+      for (int k = tid; k < reg * reg; k += kThreads) {
         const int r = div_small(k, inv_reg), c = k - r * reg;
         s_regf[k] = sd[(size_t)wrap_index(yo + r, ny) * nx + wrap_index(xo + c, nx)];
       }
@@ -671,18 +681,18 @@ __global__ __launch_bounds__(kTileThreads) void k_filter(const WorldDev* __restr
     for (int m = 0; m <= kMaxRadius; ++m) g[m] = w.gtap[m];
     __syncthreads();
     switch (R) {                                  // uniform: the world's radius
-      case 1: filter_passes<1>(s_regf, s_mid, s_st, g); break;
-      case 2: filter_passes<2>(s_regf, s_mid, s_st, g); break;
-      case 3: filter_passes<3>(s_regf, s_mid, s_st, g); break;
-      case 4: filter_passes<4>(s_regf, s_mid, s_st, g); break;
-      case 5: filter_passes<5>(s_regf, s_mid, s_st, g); break;
-      case 6: filter_passes<6>(s_regf, s_mid, s_st, g); break;
-      case 7: filter_passes<7>(s_regf, s_mid, s_st, g); break;
-      default: filter_passes<8>(s_regf, s_mid, s_st, g); break;
+      case 1: filter_passes<TILE, 1>(s_regf, s_mid, s_st, g); break;
+      case 2: filter_passes<TILE, 2>(s_regf, s_mid, s_st, g); break;
+      case 3: filter_passes<TILE, 3>(s_regf, s_mid, s_st, g); break;
+      case 4: filter_passes<TILE, 4>(s_regf, s_mid, s_st, g); break;
+      case 5: filter_passes<TILE, 5>(s_regf, s_mid, s_st, g); break;
+      case 6: filter_passes<TILE, 6>(s_regf, s_mid, s_st, g); break;
+      case 7: filter_passes<TILE, 7>(s_regf, s_mid, s_st, g); break;
+      default: filter_passes<TILE, 8>(s_regf, s_mid, s_st, g); break;
     }
     MC_GLOBAL vf2* grad = glbv<vf2>(w.grad);
-    for (int k = tid; k < kTile * kTile; k += kTileThreads) {
-      const int r = k >> 5, c = k & (kTile - 1);
+    for (int k = tid; k < TILE * TILE; k += kThreads) {
+      const int r = k >> C::kShift, c = k & (TILE - 1);
       const int gx = x0 + c, gy = y0 + r;
       if (gx < nx && gy < ny) {
         const float* p = s_st + (r + 1) * kRing + (c + 1);
@@ -763,45 +773,49 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
 }
 
 // ---------------------------------------------------------------------------
-// S5: grid force of a 32x32 tile, summed in LDS over the tile's bin (binned)
+// S5: grid force of a tile, summed in LDS over the tile's bin (binned)
 // or by fixed-order gathers over sorted segments (sorted); every cell of the
 // tile is written once.  Direct mode accumulates in k_repulse instead.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restrict__ W, Tables T) {
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_spread(const WorldDev* __restrict__ W, Tables T) {
+  using C = TileCfg<TILE>;
+  constexpr int kThreads = C::kThreads, kSpreadSide = C::kSpreadSide, kSpreadCells = C::kSpreadCells;
+  constexpr int kSpreadCap = C::kSpreadCap;
   __shared__ __align__(16) long long s_fx[kSpreadCells];   // 64-bit fixed point, padded window
   __shared__ __align__(16) long long s_fy[kSpreadCells];
-  __shared__ vi4 s_list[(kTileThreads / 64) * kWaveList];
+  __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
   __shared__ vf2 s_g[kSpreadCells];             // gradient over the window (binned)
-  const int nt = *T.n_tiles;
+  const int nt = n_tiles<TILE>(T);
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = tile_entry(T, it);
+    const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode == kDirect || w.ctl_src->remaining <= 0) continue;
     const int mode = w.mode;
     const int nx = w.nx, ny = w.ny;
-    const int x0 = tile_x(tl.y) * kTile;
-    const int y0 = tile_y(tl.y) * kTile;
-    const int tw = min(kTile, nx - x0), th = min(kTile, ny - y0);
+    const int x0 = tile_x(tl.y) * TILE;
+    const int y0 = tile_y(tl.y) * TILE;
+    const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
     if (mode == kBinned) {
       // S4 repulsion is formed here, per node, from the gradient staged over
       // the window (grid cells (x0 - 3 + i, y0 - 3 + j), periodic); all loads
       // first, then the stores (the barrier in the bin set commit follows)
       {
-        constexpr int kIt = (kSpreadCells + kTileThreads - 1) / kTileThreads;
+        constexpr int kIt = (kSpreadCells + kThreads - 1) / kThreads;
         const MC_GLOBAL vf2* grad = glbv<const vf2>(w.grad);
         const int gx0 = wrap_index(x0 - 3, nx), gy0 = wrap_index(y0 - 3, ny);
         vf2 gv[kIt];
 #pragma unroll
         for (int i = 0; i < kIt; ++i) {
-          const int k = min(tid + kTileThreads * i, kSpreadCells - 1);
+          const int k = min(tid + kThreads * i, kSpreadCells - 1);
           const int j = k / kSpreadSide, c = k - (k / kSpreadSide) * kSpreadSide;
           gv[i] = grad[(size_t)wrap_index(gy0 + j, ny) * nx + wrap_index(gx0 + c, nx)];
         }
 #pragma unroll
         for (int i = 0; i < kIt; ++i) {
-          const int k = tid + kTileThreads * i;
+          const int k = tid + kThreads * i;
           if (k < kSpreadCells) s_g[k] = gv[i];
         }
       }
@@ -816,24 +830,24 @@ __global__ __launch_bounds__(kTileThreads) void k_spread(const WorldDev* __restr
         f.n = 1;
         f.b0 = tix * kSpreadCap;
         f.len = __lane_id() == 0 ? cnt : 0;
-        tile_spread_vec<true, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
-                                    glbv<const vi4>(w.sp_rec), f, s_g);
+        tile_spread_vec<TILE, true, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                          glbv<const vi4>(w.sp_rec), f, s_g);
       } else {
-        tile_spread_vec<true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
-                              glbv<const vi4>(w.bin_rec), spread_fetch(w, x0, y0), s_g);
+        tile_spread_vec<TILE, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                    glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), s_g);
       }
       __syncthreads();
     }
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
     const MC_GLOBAL int* start = glb(w.start);
     const MC_GLOBAL vf4* rec = glbv<const vf4>(w.rec);
-    for (int k = tid; k < kTile * kTile; k += kTileThreads) {
-      const int ly = k >> 5, lx = k & (kTile - 1);
+    for (int k = tid; k < TILE * TILE; k += kThreads) {
+      const int ly = k >> C::kShift, lx = k & (TILE - 1);
       if (lx >= tw || ly >= th) continue;
       vf2 F;
       if (mode == kBinned) {
-        F.x = fix_to_float(spread_cell(s_fx, lx, ly, nx, ny));
-        F.y = fix_to_float(spread_cell(s_fy, lx, ly, nx, ny));
+        F.x = fix_to_float(spread_cell<TILE>(s_fx, lx, ly, nx, ny));
+        F.y = fix_to_float(spread_cell<TILE>(s_fy, lx, ly, nx, ny));
       } else {
         F = gather_force(start, rec, nx, ny, x0 + lx, y0 + ly);
       }
@@ -1016,33 +1030,35 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Binned worlds: the node gather of S7 (u) per 32x32 tile.  The field is
-// staged in LDS for the tile plus the support margin (cells x0-1 .. x0+33)
+// Binned worlds: the node gather of S7 (u) per tile.  The field is staged in
+// LDS for the tile plus the support margin (cells x0-1 .. x0+TILE+1)
 // with coalesced loads; every node whose home cell lies in the tile (its bin)
 // gathers its 4x4 window from LDS.  (The S4 gather of binned worlds happens
 // inside k_spread.)
 // ---------------------------------------------------------------------------
-constexpr int kStage = kTile + 3;
-
+template <int TILE>
 __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, vf2* st) {
-  constexpr int kIt = (kStage * kStage + kTileThreads - 1) / kTileThreads;
+  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kIt = (kStage * kStage + kThreads - 1) / kThreads;
   vf2 v[kIt];
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
-    const int k = min((int)threadIdx.x + kTileThreads * i, kStage * kStage - 1);
+    const int k = min((int)threadIdx.x + kThreads * i, kStage * kStage - 1);
     const int r = k / kStage, c = k - (k / kStage) * kStage;
     v[i] = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
   }
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
-    const int k = (int)threadIdx.x + kTileThreads * i;
+    const int k = (int)threadIdx.x + kThreads * i;
     if (k < kStage * kStage) st[k] = v[i];
   }
 }
 
 // 4x4 kernel-weighted sum of a staged vector field at a node whose home
 // cell sits at (lx, ly) of the tile (weights wx, wy along x and y).
+template <int TILE>
 __device__ __forceinline__ vf2 gather_staged(const vf2* st, int lx, int ly, const float* wx, const float* wy) {
+  constexpr int kStage = TILE + 3;
   float gx = 0.f, gy = 0.f;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -1061,17 +1077,19 @@ __device__ __forceinline__ vf2 gather_staged(const vf2* st, int lx, int ly, cons
   return out;
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
+  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
   __shared__ vf2 s_u[kStage * kStage];        // staged velocity, x and y interleaved
-  const int nt = *T.n_tiles;
+  const int nt = n_tiles<TILE>(T);
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
-    const int2 tl = tile_entry(T, it);
+    const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;
-    const int x0 = tile_x(tl.y) * kTile;
-    const int y0 = tile_y(tl.y) * kTile;
+    const int x0 = tile_x(tl.y) * TILE;
+    const int y0 = tile_y(tl.y) * TILE;
     const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
     const MC_GLOBAL int* cell = glb(w.cell_in);
     MC_GLOBAL int* cell_out = glb(w.cell_out);
@@ -1081,11 +1099,11 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
     // this thread's first two records and their cells are loaded beside the
     // staged field, unconditionally (record 0 always exists: the record
     // buffer holds at least one; an empty world has no positions at all)
-    const int ea = e0 + (int)threadIdx.x, eb = ea + kTileThreads;
+    const int ea = e0 + (int)threadIdx.x, eb = ea + kThreads;
     const bool has0 = ea < e1, has1 = eb < e1;
     const vi4 r0 = recs[has0 ? ea : 0];
     const vi4 r1 = recs[has1 ? eb : 0];
-    stage_field(glbv<const vf2>(w.u), nx, ny, x0, y0, s_u);
+    stage_field<TILE>(glbv<const vf2>(w.u), nx, ny, x0, y0, s_u);
     int c0x = 0, c0y = 0, c1x = 0, c1y = 0;    // in flight across the barrier
     if (N > 0) {
       const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
@@ -1101,7 +1119,7 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
       float wx[4], wy[4];
       peskin4(fx, wx);
       peskin4(fy, wy);
-      const vf2 du = gather_staged(s_u, lx, ly, wx, wy);
+      const vf2 du = gather_staged<TILE>(s_u, lx, ly, wx, wy);
       const float dux = du.x, duy = du.y;
       const int gi = r.w;
       float nfx = fx + dux, nfy = fy + duy;
@@ -1116,12 +1134,13 @@ __global__ __launch_bounds__(kTileThreads) void k_integrate_tile(const WorldDev*
       frac_out[gi] = nfx;
       frac_out[N + gi] = nfy;
       // next step's tile-bin counts
-      agg_atomic_inc(glb(w.bin_cnt), bin_of(wrap_index(ncx, nx), wrap_index(ncy, ny), w.ntx), true);
+      agg_atomic_inc(glb(w.bin_cnt), bin_of(wrap_index(ncx, nx), wrap_index(ncy, ny), w.ntx, TileCfg<TILE>::kShift),
+                     true);
     };
     // the first two records (already loaded), then any further ones
     if (has0) node(r0, c0x, c0y);
     if (has1) node(r1, c1x, c1y);
-    for (int e = eb + kTileThreads; e < e1; e += kTileThreads) {
+    for (int e = eb + kThreads; e < e1; e += kThreads) {
       const vi4 r = recs[e];
       node(r, cell[r.w], cell[N + r.w]);
     }
@@ -1170,9 +1189,28 @@ void launch_sort(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t 
   }
 }
 
+// Tile kernels: one launch per tile family present.
+template <int TILE>
+static void launch_filter_t(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
+  constexpr int f = TileCfg<TILE>::kFamily;
+  if (G.tile_blocks[f] <= 0) return;
+  // the largest dynamic LDS any launch asks for (64-cell tiles exceed 64 KiB),
+  // declared once per process
+  static const bool lds_declared = [] {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_filter<TILE>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               filter_window_bytes<TILE>(kMaxRadius) + filter_list_bytes<TILE>(kMaxRadius)) ==
+           hipSuccess;
+  }();
+  (void)lds_declared;
+  const int wb = filter_window_bytes<TILE>(G.max_radius);
+  k_filter<TILE><<<G.tile_blocks[f], TileCfg<TILE>::kThreads, wb + filter_list_bytes<TILE>(G.max_radius), s>>>(W, T, wb);
+}
+
 void launch_filter(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  const int wb = filter_window_bytes(G.max_radius);
-  k_filter<<<G.tile_blocks, kTileThreads, wb + filter_list_bytes(G.max_radius), s>>>(W, T, wb);
+  launch_filter_t<16>(W, T, G, s);
+  launch_filter_t<32>(W, T, G, s);
+  launch_filter_t<64>(W, T, G, s);
 }
 
 void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
@@ -1181,7 +1219,9 @@ void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream
 }
 
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  k_spread<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
+  if (G.tile_blocks[0] > 0) k_spread<16><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T);
+  if (G.tile_blocks[1] > 0) k_spread<32><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T);
+  if (G.tile_blocks[2] > 0) k_spread<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
 }
 
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
@@ -1196,14 +1236,19 @@ void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStre
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_node) MC_PACK_DISPATCH(k_integrate, G, W, T);
   if (G.any_binned) {
-    k_integrate_tile<<<G.tile_blocks, kTileThreads, 0, s>>>(W, T);
+    if (G.tile_blocks[0] > 0) k_integrate_tile<16><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T);
+    if (G.tile_blocks[1] > 0) k_integrate_tile<32><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T);
+    if (G.tile_blocks[2] > 0) k_integrate_tile<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
     k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
   }
 }
 
-void launch_tile_ranges(int nx, int ny, int R, int2* out, hipStream_t s) {
-  const int nt = ((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
-  k_tile_ranges<<<(nt + 255) / 256, 256, 0, s>>>(nx, ny, R, out);
+void launch_tile_ranges(int nx, int ny, int R, int tile, int2* out, hipStream_t s) {
+  const int nt = ((nx + tile - 1) / tile) * ((ny + tile - 1) / tile);
+  const int blocks = nt > 0 ? (nt + 255) / 256 : 1;
+  if (tile == 16) k_tile_ranges<16><<<blocks, 256, 0, s>>>(nx, ny, R, out);
+  else if (tile == 64) k_tile_ranges<64><<<blocks, 256, 0, s>>>(nx, ny, R, out);
+  else k_tile_ranges<32><<<blocks, 256, 0, s>>>(nx, ny, R, out);
 }
 
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s) {

@@ -74,6 +74,8 @@ sim_status check_params(const sim_params* p) {
   if (p->repulse_radius < 1 || p->repulse_radius > mc::kMaxRadius)
     return fail(SIM_E_INVALID, "repulse_radius must be in 1..%d", mc::kMaxRadius);
   if (!(p->sigma_repulse > 0.f)) return fail(SIM_E_INVALID, "sigma_repulse must be positive");
+  if (p->tile_side != 0 && p->tile_side != 16 && p->tile_side != 32 && p->tile_side != 64)
+    return fail(SIM_E_INVALID, "tile_side must be 16, 32 or 64 (or 0 for 32)");
   if (p->flags & ~(uint32_t)(SIM_SPLAT_SORTED | SIM_SPLAT_DIRECT)) return fail(SIM_E_INVALID, "unknown flag bits");
   if ((p->flags & SIM_SPLAT_SORTED) && (p->flags & SIM_SPLAT_DIRECT))
     return fail(SIM_E_INVALID, "SIM_SPLAT_SORTED and SIM_SPLAT_DIRECT are exclusive");
@@ -107,8 +109,11 @@ struct WorldBufs {
 inline int mode_of(const sim_params& p) {
   return (p.flags & SIM_SPLAT_SORTED) ? mc::kSorted : (p.flags & SIM_SPLAT_DIRECT) ? mc::kDirect : mc::kBinned;
 }
-inline int tiles_x(const sim_params& p) { return (p.nx + mc::kTile - 1) / mc::kTile; }
-inline int tiles_y(const sim_params& p) { return (p.ny + mc::kTile - 1) / mc::kTile; }
+// Side of a world's grid tiles (0 in the parameters means the default, 32).
+inline int tile_side(const sim_params& p) { return p.tile_side ? p.tile_side : 32; }
+inline int tile_family(const sim_params& p) { return mc::tile_family_of_side(tile_side(p)); }
+inline int tiles_x(const sim_params& p) { return (p.nx + tile_side(p) - 1) / tile_side(p); }
+inline int tiles_y(const sim_params& p) { return (p.ny + tile_side(p) - 1) / tile_side(p); }
 inline size_t n_bins(const sim_params& p) { return (size_t)tiles_x(p) * tiles_y(p); }
 
 void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) {
@@ -136,8 +141,8 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.bin_fill = c.take<int>(nt);
     b.bin_start = c.take<int>(nt + 1);
     b.bin_rec = c.take<int4>(N);
-    b.tile_rng = c.take<int2>((size_t)tiles_x(p) * tiles_y(p) * 2 * mc::kMaxRanges);
-    b.sp_rec = c.take<int4>((size_t)tiles_x(p) * tiles_y(p) * mc::kSpreadCap);
+    b.tile_rng = c.take<int2>((size_t)tiles_x(p) * tiles_y(p) * 2 * mc::kRunStride);
+    b.sp_rec = c.take<int4>((size_t)tiles_x(p) * tiles_y(p) * mc::spread_cap_of_side(tile_side(p)));
     b.sp_cnt = c.take<int>((size_t)tiles_x(p) * tiles_y(p));
   }
 }
@@ -186,6 +191,7 @@ mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::C
   d.mode = mode_of(p);
   d.ntx = tiles_x(p);
   d.nty = tiles_y(p);
+  d.tile_shift = mc::tile_shift_of_side(tile_side(p));
   {
     double g[mc::kMaxRadius + 1];
     double sum = 0.0;
@@ -251,14 +257,16 @@ struct Engine {
   unsigned* flags = nullptr;
   int* counts = nullptr;
   mc::Pack* packs = nullptr;
-  int2* tiles = nullptr;
+  int2* tiles[mc::kTileFamilies] = {};
   int2* items = nullptr;
   int2* scan = nullptr;
   int2* wlist = nullptr;
-  size_t max_packs = 0, max_tiles = 0, max_items = 0, max_scan = 0;
+  size_t max_packs = 0, max_items = 0, max_scan = 0;
+  size_t max_tiles[mc::kTileFamilies] = {};
   mc::Tables tab{};
   mc::Grid grid{};
   bool fixed_grid = false;
+  int fixed_tile_blocks = 2048;     // tile-kernel blocks per family when the grid is fixed
   bool any_sorted = false;
   std::vector<Slot> slots;
   // host staging (pinned) for table uploads
@@ -271,9 +279,14 @@ struct Engine {
   int want_chunk = 20;
   hipGraphExec_t g_pair = nullptr;
 
-  size_t n_packs = 0, n_tiles = 0, n_items = 0, n_scan = 0, n_worlds = 0;
+  size_t n_packs = 0, n_items = 0, n_scan = 0, n_worlds = 0;
+  size_t n_tiles[mc::kTileFamilies] = {};
 
-  static size_t table_bytes(int max_worlds, size_t mp, size_t mt, size_t mi, size_t ms) {
+  // Device work-list lengths, in counts[]: packs, scan items, worlds, fluid
+  // items, then the tiles of each tile family.
+  static constexpr int kCntPacks = 0, kCntScan = 1, kCntWorlds = 2, kCntItems = 3, kCntTiles = 4;
+
+  static size_t table_bytes(int max_worlds, size_t mp, const size_t* mt, size_t mi, size_t ms) {
     Carver c{nullptr};
     c.take<mc::WorldDev>(max_worlds);
     c.take<mc::WorldDev>(max_worlds);
@@ -282,7 +295,7 @@ struct Engine {
     c.take<unsigned>(max_worlds);
     c.take<int>(8);
     c.take<mc::Pack>(mp);
-    c.take<int2>(mt);
+    for (int f = 0; f < mc::kTileFamilies; ++f) c.take<int2>(mt[f]);
     c.take<int2>(mi);
     c.take<int2>(ms);
     c.take<int2>(max_worlds);
@@ -297,20 +310,22 @@ struct Engine {
     flags = c.take<unsigned>(max_worlds);
     counts = c.take<int>(8);
     packs = c.take<mc::Pack>(max_packs);
-    tiles = c.take<int2>(max_tiles);
+    for (int f = 0; f < mc::kTileFamilies; ++f) tiles[f] = c.take<int2>(max_tiles[f]);
     items = c.take<int2>(max_items);
     scan = c.take<int2>(max_scan);
     wlist = c.take<int2>(max_worlds);
     tab.packs = packs;
-    tab.n_packs = counts + 0;
-    tab.tiles = tiles;
-    tab.n_tiles = counts + 1;
+    tab.n_packs = counts + kCntPacks;
+    for (int f = 0; f < mc::kTileFamilies; ++f) {
+      tab.tiles[f] = tiles[f];
+      tab.n_tiles[f] = counts + kCntTiles + f;
+    }
     tab.scan = scan;
-    tab.n_scan = counts + 2;
+    tab.n_scan = counts + kCntScan;
     tab.worlds = wlist;
-    tab.n_worlds = counts + 3;
+    tab.n_worlds = counts + kCntWorlds;
     tab.items = items;
-    tab.n_items = counts + 4;
+    tab.n_items = counts + kCntItems;
   }
 
   ~Engine() {
@@ -336,7 +351,7 @@ struct Engine {
   // Rebuild work tables and descriptors from the slot list and upload them.
   sim_status rebuild() {
     std::vector<mc::Pack> pk;
-    std::vector<int2> tl, sc, wl, it;
+    std::vector<int2> tl[mc::kTileFamilies], sc, wl, it;
     any_sorted = false;
     bool any_binned = false;
     for (int w = 0; w < (int)slots.size(); ++w) {
@@ -357,8 +372,9 @@ struct Engine {
         f = end;
       }
       const int ncell = s.p.nx * s.p.ny;
+      std::vector<int2>& tlf = tl[tile_family(s.p)];
       for (int ty = 0; ty < tiles_y(s.p); ++ty)
-        for (int tx = 0; tx < tiles_x(s.p); ++tx) tl.push_back(make_int2(w, tx | (ty << 16)));
+        for (int tx = 0; tx < tiles_x(s.p); ++tx) tlf.push_back(make_int2(w, tx | (ty << 16)));
       for (int c = 0; c < ncell; c += mc::kCellsPerItem) it.push_back(make_int2(w, c));
       wl.push_back(make_int2(w, 0));
       const int mode = mode_of(s.p);
@@ -369,22 +385,30 @@ struct Engine {
       }
       if (mode == mc::kBinned) any_binned = true;
     }
-    if (pk.size() > max_packs || tl.size() > max_tiles || it.size() > max_items || sc.size() > max_scan)
-      return fail(SIM_E_WORKSPACE, "work tables exceed their capacity");
+    bool over = pk.size() > max_packs || it.size() > max_items || sc.size() > max_scan;
+    for (int f = 0; f < mc::kTileFamilies; ++f) over = over || tl[f].size() > max_tiles[f];
+    if (over) return fail(SIM_E_WORKSPACE, "work tables exceed their capacity");
     n_packs = pk.size();
-    n_tiles = tl.size();
+    for (int f = 0; f < mc::kTileFamilies; ++f) n_tiles[f] = tl[f].size();
     n_scan = sc.size();
     n_worlds = wl.size();
     n_items = it.size();
+    // a kernel family stays in the captured graphs once any world needed it
+    bool more = false;
+    for (int f = 0; f < mc::kTileFamilies; ++f) {
+      if (n_tiles[f] > 0 && grid.tile_blocks[f] == 0) more = true;
+      if (!fixed_grid)
+        grid.tile_blocks[f] = (int)n_tiles[f];        // one block per tile; 0: family not launched
+      else if (n_tiles[f] > 0)
+        grid.tile_blocks[f] = fixed_tile_blocks;      // stays launched once a world needed it
+    }
     if (!fixed_grid) {
       grid.item_blocks = (int)std::max<size_t>(1, n_items);
       grid.node_blocks = (int)std::max<size_t>(1, n_packs);
-      grid.tile_blocks = (int)std::max<size_t>(1, n_tiles);
       grid.scan_blocks = (int)std::max<size_t>(1, n_scan);
       grid.world_blocks = (int)std::max<size_t>(1, n_worlds);
     }
-    // a kernel family stays in the captured graphs once any world needed it
-    bool more = (any_sorted && !grid.any_sorted) || (any_binned && !grid.any_binned);
+    more = more || (any_sorted && !grid.any_sorted) || (any_binned && !grid.any_binned);
     bool any_node = false;
     for (const auto& sl : slots)
       if (sl.used && mode_of(sl.p) != mc::kBinned) any_node = true;
@@ -403,7 +427,8 @@ struct Engine {
     // stage into pinned memory once the previous upload has been consumed
     HIPCHK(hipEventSynchronize(upload_done));
     const size_t need = 2 * max_worlds * sizeof(mc::WorldDev) + 8 * sizeof(int) + pk.size() * sizeof(mc::Pack) +
-                        (tl.size() + sc.size() + wl.size() + it.size()) * sizeof(int2);
+                        (tl[0].size() + tl[1].size() + tl[2].size() + sc.size() + wl.size() + it.size()) *
+                            sizeof(int2);
     if (need > pinned_bytes) {
       if (pinned) HIPCHK(hipHostFree(pinned));
       pinned_bytes = need * 2;
@@ -427,10 +452,16 @@ struct Engine {
     sim_status st;
     if ((st = put(desc[0], d0.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
     if ((st = put(desc[1], d1.data(), max_worlds * sizeof(mc::WorldDev)))) return st;
-    int cnt[8] = {(int)n_packs, (int)n_tiles, (int)n_scan, (int)n_worlds, (int)n_items, 0, 0, 0};
+    int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    cnt[kCntPacks] = (int)n_packs;
+    cnt[kCntScan] = (int)n_scan;
+    cnt[kCntWorlds] = (int)n_worlds;
+    cnt[kCntItems] = (int)n_items;
+    for (int f = 0; f < mc::kTileFamilies; ++f) cnt[kCntTiles + f] = (int)n_tiles[f];
     if ((st = put(counts, cnt, sizeof(cnt)))) return st;
     if ((st = put(packs, pk.data(), pk.size() * sizeof(mc::Pack)))) return st;
-    if ((st = put(tiles, tl.data(), tl.size() * sizeof(int2)))) return st;
+    for (int f = 0; f < mc::kTileFamilies; ++f)
+      if ((st = put(tiles[f], tl[f].data(), tl[f].size() * sizeof(int2)))) return st;
     if ((st = put(scan, sc.data(), sc.size() * sizeof(int2)))) return st;
     if ((st = put(wlist, wl.data(), wl.size() * sizeof(int2)))) return st;
     if ((st = put(items, it.data(), it.size() * sizeof(int2)))) return st;
@@ -531,7 +562,8 @@ namespace {
 
 size_t world_table_bytes(const sim_params& p, int n_fil) {
   const size_t ncell = (size_t)p.nx * p.ny;
-  const size_t tiles = (size_t)tiles_x(p) * tiles_y(p);
+  size_t tiles[mc::kTileFamilies] = {0, 0, 0};
+  tiles[tile_family(p)] = (size_t)tiles_x(p) * tiles_y(p);
   const size_t items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
   const size_t scans = (ncell + 1023) / 1024;
   return Engine::table_bytes(1, std::max(n_fil, 1), tiles, items, scans);
@@ -590,6 +622,7 @@ void sim_params_default(sim_params* p, int32_t nx, int32_t ny) {
   p->repulse_radius = 4;
   p->u_max = 0.3f;
   p->flags = 0;
+  p->tile_side = 32;
 }
 
 const char* sim_last_error(void) { return g_err; }
@@ -632,11 +665,11 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   e.max_worlds = 1;
   const size_t ncell = (size_t)p->nx * p->ny;
   e.max_packs = std::max(a->n_filaments, 1);
-  e.max_tiles = (size_t)tiles_x(*p) * tiles_y(*p);
+  e.max_tiles[tile_family(*p)] = (size_t)tiles_x(*p) * tiles_y(*p);
   e.max_items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
   e.max_scan = (ncell + 1023) / 1024;
   e.grid.pack = max_len <= 256 ? 256 : 1024;
-  e.tab.single_ntx = tiles_x(*p);               // one world: tile entries are computed
+  e.tab.single_ntx[tile_family(*p)] = tiles_x(*p);   // one world: tile entries are computed
   Carver c{(char*)workspace};
   e.carve_tables(c);
   Slot sl;
@@ -674,7 +707,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
     const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_fill, nt);
-    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, sl.b.tile_rng, s);
+    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, tile_side(*p), sl.b.tile_rng, s);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.sp_cnt, (size_t)tiles_x(*p) * tiles_y(*p));
   }
   if (hipGetLastError() != hipSuccess) {
@@ -978,10 +1011,15 @@ __global__ void k_noalloc_setup(mc::WorldDev d0, mc::WorldDev d1, NoallocLayout 
 
 // Work-list lengths, or none at all (every kernel then idles) when the
 // offsets failed their checks.
-__global__ void k_noalloc_counts(NoallocLayout L, int n_packs, int n_tiles, int n_scan, int n_items) {
+__global__ void k_noalloc_counts(NoallocLayout L, int n_packs, int n_tiles, int family, int n_scan, int n_items) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const bool ok = *L.err == 0;
-  const int c[8] = {ok ? n_packs : 0, ok ? n_tiles : 0, ok ? n_scan : 0, ok ? 1 : 0, ok ? n_items : 0, 0, 0, 0};
+  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  c[Engine::kCntPacks] = ok ? n_packs : 0;
+  c[Engine::kCntScan] = ok ? n_scan : 0;
+  c[Engine::kCntWorlds] = ok ? 1 : 0;
+  c[Engine::kCntItems] = ok ? n_items : 0;
+  c[Engine::kCntTiles + family] = ok ? n_tiles : 0;
   for (int k = 0; k < 8; ++k) L.counts[k] = c[k];
   if (!ok) L.ctl[0].remaining = 0;
 }
@@ -1046,21 +1084,24 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   const mc::WorldDev d1 = world_desc(sl, 1, L.ctl + 1, L.ctl + 0, L.flags);
 
   mc::Tables tab{};
+  const int fam = tile_family(*p);
   tab.packs = L.packs;
-  tab.n_packs = L.counts + 0;
-  tab.tiles = nullptr;
-  tab.n_tiles = L.counts + 1;
+  tab.n_packs = L.counts + Engine::kCntPacks;
+  for (int f = 0; f < mc::kTileFamilies; ++f) {
+    tab.tiles[f] = nullptr;
+    tab.n_tiles[f] = L.counts + Engine::kCntTiles + f;
+  }
   tab.scan = L.scan;
-  tab.n_scan = L.counts + 2;
+  tab.n_scan = L.counts + Engine::kCntScan;
   tab.worlds = L.wlist;
-  tab.n_worlds = L.counts + 3;
+  tab.n_worlds = L.counts + Engine::kCntWorlds;
   tab.items = L.items;
-  tab.n_items = L.counts + 4;
-  tab.single_ntx = tiles_x(*p);
+  tab.n_items = L.counts + Engine::kCntItems;
+  tab.single_ntx[fam] = tiles_x(*p);
   mc::Grid g{};
   g.pack = 1024;                                  // one filament (<= 1024 nodes) per pack
   g.node_blocks = std::max(1, std::min(n_fil, 8192));
-  g.tile_blocks = (int)std::max<size_t>(1, nt);
+  g.tile_blocks[fam] = (int)std::max<size_t>(1, nt);
   g.item_blocks = std::max(1, n_items);
   g.scan_blocks = std::max(1, n_scan);
   g.world_blocks = 1;
@@ -1079,12 +1120,12 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_fill, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.sp_cnt, nt);
-    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, L.b.tile_rng, s);
+    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, tile_side(*p), L.b.tile_rng, s);
   }
   const int setup_n = std::max({n_fil, n_items, n_scan, 1});
   hipLaunchKernelGGL(k_noalloc_setup, dim3((setup_n + 255) / 256), dim3(256), 0, s, d0, d1, L, a->fil_offset, n_fil,
                      n_part, n_items, n_scan, (long long)t);
-  hipLaunchKernelGGL(k_noalloc_counts, dim3(1), dim3(64), 0, s, L, n_fil, (int)nt, n_scan, n_items);
+  hipLaunchKernelGGL(k_noalloc_counts, dim3(1), dim3(64), 0, s, L, n_fil, (int)nt, fam, n_scan, n_items);
   // the step itself: the kernels sim_step runs, with parity-0 descriptors
   mc::launch_bin_prepass(L.desc, tab, g, s);
   mc::launch_elastic(L.desc, tab, g, s);
@@ -1097,6 +1138,56 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   hipLaunchKernelGGL(k_noalloc_copy_back, dim3(std::min<size_t>(2048, (9 * ncell + 255) / 256)), dim3(256), 0, s,
                      L.err, (const float*)L.b.f_alt, a->f, 9 * ncell);
   if (status) hipLaunchKernelGGL(k_noalloc_status, dim3(1), dim3(64), 0, s, L.err, L.flags, status);
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Folding objective (sim_density_loss)
+// ---------------------------------------------------------------------------
+namespace {
+
+sim_status check_splat(const sim_splat_image* img) {
+  if (!img) return fail(SIM_E_INVALID, "image description is NULL");
+  if (img->width < 1 || img->height < 1 || img->width > 16384 || img->height > 16384)
+    return fail(SIM_E_INVALID, "image sides must be in 1..16384");
+  if (!(img->sigma > 0.f) || !std::isfinite(img->sigma) || !std::isfinite(img->amp))
+    return fail(SIM_E_INVALID, "sigma must be positive and amp finite");
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_density_loss_workspace_size(const sim_splat_image* img, size_t* bytes) {
+  sim_status st = check_splat(img);
+  if (st) return st;
+  if (!bytes) return fail(SIM_E_INVALID, "bytes is NULL");
+  *bytes = mc::density_loss_workspace(img->width, img->height);
+  return SIM_OK;
+}
+
+sim_status sim_density_loss(const sim_splat_image* img, int32_t nx, int32_t ny, int32_t n_particles,
+                            const int32_t* cell, const float* frac, const float* target, float* image, float* loss,
+                            float* g_pos, void* workspace, size_t ws_bytes, void* stream) {
+  sim_status st = check_splat(img);
+  if (st) return st;
+  if (nx < 1 || ny < 1 || n_particles < 0) return fail(SIM_E_INVALID, "bad world size");
+  if (!target || !loss) return fail(SIM_E_INVALID, "target and loss must be given");
+  if (n_particles > 0 && (!cell || !frac)) return fail(SIM_E_INVALID, "positions must be given");
+  const float hx = (float)nx / img->width, hy = (float)ny / img->height;
+  const double wx = std::min<double>(img->width, 2.0 * std::floor(5.0 * img->sigma / hx + 0.5) + 3);
+  const double wy = std::min<double>(img->height, 2.0 * std::floor(5.0 * img->sigma / hy + 0.5) + 3);
+  if (wx * wy > 65536.0)
+    return fail(SIM_E_INVALID, "sigma covers %.0f pixels per node (at most 65536)", wx * wy);
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(SIM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = mc::density_loss_workspace(img->width, img->height);
+  if (ws_bytes < need) return fail(SIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  mc::launch_density_loss(nx, ny, n_particles, img->width, img->height, img->sigma, img->amp, cell, frac, target,
+                          image, loss, g_pos, workspace, (hipStream_t)stream);
   HIPCHK(hipGetLastError());
   return SIM_OK;
 }
@@ -1395,8 +1486,9 @@ sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, v
   // least 96 bytes, every node at least 36 bytes
   const size_t max_cells = pool_bytes / 96 + 1;
   const size_t max_nodes = pool_bytes / 36 + 1;
-  // a world of c cells has at most c/1024 + nx/32 + ny/32 + 1 <= c/64 + 1 tiles
-  e.max_tiles = max_cells / 64 + max_worlds;
+  // a world of c cells (both sides >= 8) has at most c/T^2 + nx/T + ny/T + 1
+  // <= 5c/256 + 1 tiles of side T >= 16
+  for (int f = 0; f < mc::kTileFamilies; ++f) e.max_tiles[f] = max_cells / 48 + max_worlds;
   e.max_items = max_cells / mc::kCellsPerItem + max_worlds;
   e.max_scan = max_cells / 1024 + max_worlds;
   e.max_packs = 2 * (max_nodes / 256) + 2 * (size_t)max_worlds;
@@ -1414,7 +1506,7 @@ sim_status sim_batch_create(int32_t max_worlds, void* pool, size_t pool_bytes, v
   e.fixed_grid = true;
   e.grid.pack = 256;
   e.grid.node_blocks = 2048;
-  e.grid.tile_blocks = 2048;
+  e.fixed_tile_blocks = 2048;
   e.grid.scan_blocks = 1024;
   e.grid.world_blocks = 256;
   e.grid.item_blocks = 4096;
@@ -1445,7 +1537,9 @@ sim_status sim_batch_set_tuning(sim_batch* b, int32_t chunk_steps, int32_t cell_
     return fail(SIM_E_INVALID, "chunk_steps must be even and >= 2; block counts >= 1");
   Engine& e = b->eng;
   e.want_chunk = chunk_steps;
-  e.grid.tile_blocks = std::max(1, cell_blocks / 4);
+  e.fixed_tile_blocks = std::max(1, cell_blocks / 4);
+  for (int f = 0; f < mc::kTileFamilies; ++f)
+    if (e.grid.tile_blocks[f] > 0) e.grid.tile_blocks[f] = e.fixed_tile_blocks;
   e.grid.item_blocks = cell_blocks;
   e.grid.node_blocks = node_blocks;
   e.grid.scan_blocks = std::max(1, cell_blocks / 2);
@@ -1515,7 +1609,7 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
     const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.bin_fill, nt);
-    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, s.b.tile_rng, e.stream);
+    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, tile_side(*p), s.b.tile_rng, e.stream);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, s.b.sp_cnt, (size_t)tiles_x(*p) * tiles_y(*p));
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, e.stream, (int*)(e.flags + w), (size_t)1);

@@ -30,6 +30,7 @@ EXPORTS = [
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
     "sim_profile_steps", "sim_measure_atomics", "sim_step_noalloc",
+    "sim_density_loss_workspace_size", "sim_density_loss",
     "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
     "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
     "sim_batch_destroy",
@@ -50,7 +51,7 @@ class SimParams(ctypes.Structure):
         ("pbd_iters", ctypes.c_int32),
         ("k_elastic", ctypes.c_float), ("k_repulse", ctypes.c_float),
         ("sigma_repulse", ctypes.c_float), ("repulse_radius", ctypes.c_int32),
-        ("u_max", ctypes.c_float), ("flags", ctypes.c_uint32),
+        ("u_max", ctypes.c_float), ("flags", ctypes.c_uint32), ("tile_side", ctypes.c_int32),
     ]
 
 
@@ -62,6 +63,11 @@ class SimArrays(ctypes.Structure):
         ("act_amp", ctypes.c_void_p), ("act_period", ctypes.c_void_p), ("act_phase", ctypes.c_void_p),
         ("f", ctypes.c_void_p), ("u", ctypes.c_void_p),
     ]
+
+
+class SimSplatImage(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("amp", ctypes.c_float)]
 
 
 _lib = None
@@ -95,6 +101,8 @@ def lib():
         "sim_profile_steps": (i32, [vp, i64, i32, P(ctypes.c_float)]),
         "sim_measure_atomics": (i32, [vp, sz, vp, P(ctypes.c_double)]),
         "sim_step_noalloc": (i32, [P(SimParams), P(SimArrays), i64, vp, vp]),
+        "sim_density_loss_workspace_size": (i32, [P(SimSplatImage), P(sz)]),
+        "sim_density_loss": (i32, [P(SimSplatImage), i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "sim_batch_world_bytes": (i32, [P(SimParams), i32, i32, P(sz)]),
         "sim_batch_create": (i32, [i32, vp, sz, vp, P(vp)]),
         "sim_batch_admit": (i32, [vp, P(SimParams), P(SimArrays), i64, i32, P(i32)]),
@@ -136,6 +144,7 @@ class Params:
     repulse_radius: int = 4
     u_max: float = 0.3
     transfer: str = "binned"          # "binned" (default), "sorted" or "direct"
+    tile: int = 32                    # grid tile side of the tile kernels: 16, 32 or 64
 
     def flags(self) -> int:
         return {"binned": 0, "sorted": SIM_SPLAT_SORTED, "direct": SIM_SPLAT_DIRECT}[self.transfer]
@@ -144,7 +153,7 @@ class Params:
         return SimParams(self.nx, self.ny, self.tau, self.trt_magic, self.k_bend, self.k_stretch,
                          self.k_shear, self.pbd_iters, self.k_elastic, self.k_repulse,
                          self.sigma_repulse, self.repulse_radius, self.u_max,
-                         self.flags())
+                         self.flags(), self.tile)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -351,3 +360,55 @@ class Rollout(torch.autograd.Function):
         finally:
             W.state.rest_angle.copy_(current)        # stream-ordered after the backward
         return g_rest.to(ctx.dtype), None, None, None, None
+
+
+def density_loss(nx: int, ny: int, cell: torch.Tensor, frac: torch.Tensor, target: torch.Tensor,
+                 sigma: float, amp: float = 1.0, want_grad: bool = True, want_image: bool = True,
+                 stream=None):
+    """Folding objective of nodes at cell + frac ([2, N] int32 / float32 device
+    tensors) against target ([H, W] float32 device tensor), through
+    sim_density_loss.  Returns (loss device float32 [1], image [H, W] or None,
+    dL/dx [2, N] float32 or None)."""
+    L = lib()
+    H, W = target.shape
+    img = SimSplatImage(int(W), int(H), float(sigma), float(amp))
+    nb = ctypes.c_size_t()
+    check(L.sim_density_loss_workspace_size(ctypes.byref(img), ctypes.byref(nb)))
+    dev = target.device
+    ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
+    N = int(cell.shape[1]) if cell.dim() == 2 else 0
+    assert cell.dtype == torch.int32 and frac.dtype == torch.float32 and target.dtype == torch.float32
+    assert cell.is_contiguous() and frac.is_contiguous() and target.is_contiguous()
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    image = torch.empty(H, W, dtype=torch.float32, device=dev) if want_image else None
+    g_pos = torch.empty(2, N, dtype=torch.float32, device=dev) if want_grad else None
+    check(L.sim_density_loss(ctypes.byref(img), int(nx), int(ny), N, _ptr(cell), _ptr(frac), _ptr(target),
+                             _ptr(image), _ptr(loss), _ptr(g_pos), _ptr(ws), ws.numel(), _stream_handle(stream)))
+    return loss, image, g_pos
+
+
+def split_positions(x: torch.Tensor):
+    """Float64 positions [2, N] as the library's (int32 cell, float32 fraction);
+    exact for positions that came from (cell, fraction) pairs."""
+    c = torch.floor(x)
+    return c.to(torch.int32).contiguous(), (x - c).to(torch.float32).contiguous()
+
+
+class DensityLoss(torch.autograd.Function):
+    """L(x) = mean over pixels of (splatted density image of x - target)^2 on
+    the GPU (sim_density_loss); x: float64 [2, N] positions (e.g. the output of
+    Rollout), differentiable.  Chained with Rollout it gives the paper's
+    folding objective's gradient in the rest angles."""
+
+    @staticmethod
+    def forward(ctx, x, nx, ny, target, sigma, amp):
+        cell, frac = split_positions(x.detach())
+        loss, _, g = density_loss(nx, ny, cell, frac, target, sigma, amp, want_grad=True, want_image=False)
+        ctx.save_for_backward(g)
+        ctx.dtype = x.dtype
+        return loss[0].to(x.dtype)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (g,) = ctx.saved_tensors
+        return g.to(ctx.dtype) * g_out, None, None, None, None, None

@@ -160,3 +160,32 @@ def test_autotuner_picks_a_measured_setting(tmp_path, monkeypatch):
     assert best["ms_per_step"] == min(r["ms_per_step"] for r in table)
     again, t2 = autotune.tune(worlds, lambda w: sim.Params(nx=w.nx, ny=w.ny), 256 << 20)
     assert again == best and t2 == []       # served from the cache
+
+
+def test_tile_tuner_picks_measured_side_per_class():
+    sim, batch, _ = _mods()
+    from paper_2607_02954_amd import autotune
+    worlds = _worlds()
+    policy, table = autotune.tune_tiles(worlds, lambda w: sim.Params(nx=w.nx, ny=w.ny), 256 << 20,
+                                        steps_per_trial=20)
+    classes = {autotune.grid_class(w) for w in worlds}
+    per_class = [r for r in table if r["class"] != "all"]
+    assert len(per_class) == 3 * len(classes)
+    whole = [r for r in table if r["class"] == "all"]
+    assert whole and whole[0]["policy"] == "per class"
+    print("tile tuning:", table)
+    best = min(whole, key=lambda r: r["ms_per_step"])["policy"]
+    if best == "per class":
+        for cls in classes:
+            rows = [r for r in per_class if r["class"] == cls]
+            assert policy.sides[cls] == min(rows, key=lambda r: r["ms_per_step"])["tile"]
+    else:
+        assert policy.sides == {} and policy.default == int(best.split()[1])
+    # worlds run with the chosen sides still equal their alone runs
+    w = worlds[2]
+    p = policy.params(w)
+    eng = batch.BatchEngine(max_worlds=2, pool_bytes=64 << 20)
+    s = eng.admit(w, p, 20)
+    eng.advance(20)
+    got = eng.retire(s, w)
+    assert _same(got, _alone(sim, w, 20, tile=p.tile))

@@ -3,7 +3,7 @@
 The transfer (Methods, fluid-filament interaction; read as Peskin's 4-point
 kernel) puts a node whose home cell is h = floor(x) on the cells h-1 .. h+2
 of each periodic axis.  The tile kernels of the binned transfer keep, per
-32-cell tile, only the nodes whose home cell passes a keep rule, place each
+tile (side 16, 32 or 64 cells), only the nodes whose home cell passes a keep rule, place each
 kept node's four cells at window offsets d .. d+3 with d = (h - 1 - o) mod n
 (o: window origin, three cells before the needed range) inside an LDS window
 of side need + 6, and read the records from the home-tile bins of a few tile
@@ -21,26 +21,29 @@ spread (needed: the tile's own cells):
   * the spread's kept nodes are kept by the filter and lie in the filter's
     bins (the filter hands the spread its record list);
   * a tile reads at most four bin columns in at most two runs, so a tile's
-    bin set has at most eight runs.
+    bin set has at most eight runs (for every tile side: the margins, at most
+    R + 3 = 11 cells, are shorter than a tile).
 """
 import numpy as np
 import pytest
 
-TILE = 32
-MAX_COLS = 4
+TILES = [16, 32, 64]
+MAX_COLS = {16: 4, 32: 4, 64: 4}      # the kernels' TileCfg<TILE>::kMaxCols
 
 
-def covering_columns(lo, hi, n):
-    """Tile columns holding cells lo..hi of a periodic axis, capped at four."""
+def covering_columns(lo, hi, n, TILE=32):
+    """Tile columns holding cells lo..hi of a periodic axis, capped at the
+    kernels' column limit (the check below asserts the cap never binds)."""
+    cap = MAX_COLS[TILE] + 1
     t = []
     if hi - lo + 1 >= n:
         k = 0
-        while k * TILE < n and len(t) < MAX_COLS:
+        while k * TILE < n and len(t) < cap:
             t.append(k)
             k += 1
         return t
     c = lo
-    while c <= hi and len(t) < MAX_COLS:
+    while c <= hi and len(t) < cap:
         cc = c % n
         tt = cc // TILE
         if tt not in t:
@@ -58,7 +61,7 @@ def runs(cols):
     return r
 
 
-def check_reader(n, first, need, cols, bound_shift=0, side_shift=0):
+def check_reader(n, first, need, cols, bound_shift=0, side_shift=0, TILE=32):
     """Keep rule, window placement and bins of one reader on one axis.
 
     first: first needed cell (unwrapped); need: needed cells.  Returns the
@@ -86,31 +89,46 @@ def check_reader(n, first, need, cols, bound_shift=0, side_shift=0):
     return kept
 
 
-def test_binned_transfer_windows_and_bins():
+@pytest.mark.parametrize("TILE", TILES)
+def test_binned_transfer_windows_and_bins(TILE):
     cases = 0
-    for n in range(1, 200):
+    top = 200 if TILE <= 32 else 300
+    for n in range(1, top):
         for x0 in range(0, n, TILE):
             tw = min(TILE, n - x0)
-            sp_cols = covering_columns(x0 - 2, x0 + tw, n)
-            assert len(sp_cols) <= MAX_COLS and runs(sp_cols) <= 2
-            sp_kept = check_reader(n, x0, tw, sp_cols)
+            sp_cols = covering_columns(x0 - 2, x0 + tw, n, TILE)
+            assert len(sp_cols) <= MAX_COLS[TILE] and runs(sp_cols) <= 2
+            sp_kept = check_reader(n, x0, tw, sp_cols, TILE=TILE)
             for R in range(1, 9):
                 reg = TILE + 2 + 2 * R
                 xo = x0 - R - 1
-                f_cols = covering_columns(xo - 2, xo + reg, n)
-                assert len(f_cols) <= MAX_COLS and runs(f_cols) <= 2
-                f_kept = check_reader(n, xo, reg, f_cols)
+                f_cols = covering_columns(xo - 2, xo + reg, n, TILE)
+                assert len(f_cols) <= MAX_COLS[TILE] and runs(f_cols) <= 2
+                f_kept = check_reader(n, xo, reg, f_cols, TILE=TILE)
                 h = np.arange(n)
                 assert np.all(f_kept[sp_kept]), (n, x0, R)
                 assert np.all(np.isin(h[sp_kept] // TILE, f_cols)), (n, x0, R)
                 cases += 1
-    assert cases > 5000
+    assert cases > 2000
+
+
+@pytest.mark.parametrize("TILE", TILES)
+def test_column_limit_is_reached(TILE):
+    # the column and run limits are tight: some axis and tile need them all
+    worst = 0
+    for n in range(1, 300):
+        for x0 in range(0, n, TILE):
+            R = 8
+            reg = TILE + 2 + 2 * R
+            worst = max(worst, len(covering_columns(x0 - R - 3, x0 - R - 1 + reg, n, TILE)))
+    assert worst == MAX_COLS[TILE]
 
 
 @pytest.mark.parametrize("mistake", ["dropped column", "keep bound one short", "window one short"])
 def test_planted_mistakes_are_caught(mistake):
     # the check is sharp: a filter tile with one bin column left out, a keep
     # bound one cell short or a window one cell short fails it
+    TILE = 32
     n, x0, R = 160, 64, 4
     reg = TILE + 2 + 2 * R
     cols = covering_columns(x0 - R - 1 - 2, x0 - R - 1 + reg, n)
