@@ -63,48 +63,77 @@ class Params:
 
 
 # ---------------------------------------------------------------------------
-# Filament topology (Methods, Filaments: chains with nearest-neighbour edges)
+# Filament topology (Methods, Filaments: nodes joined by edges; filaments "can
+# be extended to have loops ... with a graph representation")
 # ---------------------------------------------------------------------------
 
 class Topology:
-    """Index sets of a set of chains given by CSR offsets.
+    """Index sets of a set of filaments given by CSR offsets.
 
-    Edge e joins nodes (e, e+1) of one filament; joint i is an interior node
-    between edges i-1 and i.  Sets are split by the parity of the local index
-    (edge: e - o_f; joint: i - o_f - 1) for two-colour Gauss-Seidel sweeps.
+    Open chain: edge e joins nodes (e, e+1) of one filament; joint i is an
+    interior node, between edges i-1 and i.  Closed loop (``closed[f]``, at
+    least three nodes): also the edge of the last node, which joins it to the
+    first, and a joint at every node (the first node's joint is between the
+    closing edge and edge 0).  Edges and joints are stored at the index of
+    their node: edge e joins e and edge_next[e]; joint i is between edges
+    joint_prev[i] and i.  Sets are split by the parity of the local index
+    (edge: e - o_f; joint: i - o_f - 1 on chains, i - o_f on loops) for
+    two-colour Gauss-Seidel sweeps; on a loop of odd length the last edge
+    and the last joint (which meet the first ones) get a third colour.
     """
 
-    def __init__(self, fil_offset):
+    def __init__(self, fil_offset, closed=None):
         off = np.asarray(fil_offset, dtype=np.int64)
         self.fil_offset = off
         self.n_filaments = len(off) - 1
         self.n = int(off[-1])
-        edges, elocal, joints, jlocal, jfil, jcount = [], [], [], [], [], []
+        closed = np.zeros(self.n_filaments, dtype=bool) if closed is None else np.asarray(closed, dtype=bool)
+        self.closed = closed
+        edges, ecol, joints, jcol, jlocal, jfil, jcount = [], [], [], [], [], [], []
+        nxt = np.arange(self.n, dtype=np.int64) + 1
+        prv = np.arange(self.n, dtype=np.int64) - 1
         fil_of_node = np.zeros(self.n, dtype=np.int64)
         for f in range(self.n_filaments):
             a, b = int(off[f]), int(off[f + 1])
+            n = b - a
             fil_of_node[a:b] = f
-            for e in range(a, b - 1):
+            ring = bool(closed[f]) and n >= 3
+            for e in range(a, b if ring else b - 1):
                 edges.append(e)
-                elocal.append(e - a)
-            for i in range(a + 1, b - 1):
-                joints.append(i)
-                jlocal.append(i - a - 1)
-                jfil.append(f)
-                jcount.append(b - a - 2)
+                k = e - a
+                ecol.append(2 if (ring and n % 2 == 1 and k == n - 1) else k % 2)
+            if ring:
+                nxt[b - 1] = a
+                prv[a] = b - 1
+                for i in range(a, b):
+                    k = i - a
+                    joints.append(i)
+                    jlocal.append(k)
+                    jcol.append(2 if (n % 2 == 1 and k == n - 1) else k % 2)
+                    jfil.append(f)
+                    jcount.append(n)
+            else:
+                for i in range(a + 1, b - 1):
+                    joints.append(i)
+                    jlocal.append(i - a - 1)
+                    jcol.append((i - a - 1) % 2)
+                    jfil.append(f)
+                    jcount.append(n - 2)
         t = lambda v: torch.tensor(v, dtype=torch.int64)
         self.edges = t(edges)
+        self.edge_next = torch.from_numpy(nxt)
         self.joints = t(joints)
+        self.joint_prev = torch.from_numpy(prv)
         self.joint_local = t(jlocal)
         self.joint_fil = t(jfil)
-        self.joint_count = t(jcount)        # n_f - 2 for the joint's filament
+        self.joint_count = t(jcount)        # n_f - 2 for a chain's joint, n_f for a loop's
         self.fil_of_node = torch.from_numpy(fil_of_node)
-        el = np.array(elocal, dtype=np.int64)
-        jl = np.array(jlocal, dtype=np.int64)
+        ec = np.array(ecol, dtype=np.int64)
+        jc = np.array(jcol, dtype=np.int64)
         ed = np.array(edges, dtype=np.int64)
         jo = np.array(joints, dtype=np.int64)
-        self.edge_sets = [t(ed[el % 2 == 0]), t(ed[el % 2 == 1])]
-        self.joint_sets = [t(jo[jl % 2 == 0]), t(jo[jl % 2 == 1])]
+        self.edge_sets = [t(ed[ec == c]) for c in range(3)]
+        self.joint_sets = [t(jo[jc == c]) for c in range(3)]
 
 
 # ---------------------------------------------------------------------------
@@ -114,7 +143,8 @@ class Topology:
 # ---------------------------------------------------------------------------
 
 def actuation(rest_angle, topo: Topology, amp, period, phase, t):
-    """theta_hat_i = theta_rest_i + A_f sin(2 pi t / T_f + psi_f - 2 pi k / (n_f - 2))."""
+    """theta_hat_i = theta_rest_i + A_f sin(2 pi t / T_f + psi_f - 2 pi k / m_f), k the
+    joint's local index, m_f its filament's joint count (n_f - 2; n_f on a loop)."""
     theta_hat = rest_angle.clone()
     if topo.joints.numel() == 0:
         return theta_hat
@@ -135,56 +165,88 @@ def wrap_angle(d):
 
 
 def edge_angles(y, topo: Topology):
-    """theta_e = atan2 of edge vector y_{e+1} - y_e, for every edge (others 0)."""
+    """theta_e = atan2 of edge vector y_next(e) - y_e, for every edge (others 0)."""
     theta = torch.zeros(topo.n, dtype=DT)
     if topo.edges.numel() == 0:
         return theta
     e = topo.edges
-    v = y[:, e + 1] - y[:, e]
+    v = y[:, topo.edge_next[e]] - y[:, e]
     return theta.index_put((e,), torch.atan2(v[1], v[0]))
 
 
-def bend_pass(theta, joints, theta_hat, k_bend):
+def _at(k, idx):
+    """A stiffness: a scalar, or a per-node tensor read at the index set."""
+    return k[idx] if torch.is_tensor(k) else k
+
+
+def bend_pass(theta, joints, theta_hat, k_bend, prev=None):
     """Eq. 1 for a set of joints that share no edge: C = wrap(th_2 - th_1) - th_hat,
-    th_1 += k C / 2, th_2 -= k C / 2, with th_1 the edge before the joint."""
+    th_1 += k C / 2, th_2 -= k C / 2, with th_1 the edge before the joint
+    (prev[joint], default joint - 1).  k_bend: scalar or per joint (node)."""
     if joints.numel() == 0:
         return theta
-    c = wrap_angle(theta[joints] - theta[joints - 1]) - theta_hat[joints]
-    return theta.index_add(0, joints - 1, 0.5 * k_bend * c).index_add(0, joints, -0.5 * k_bend * c)
+    before = joints - 1 if prev is None else prev[joints]
+    c = wrap_angle(theta[joints] - theta[before]) - theta_hat[joints]
+    k = _at(k_bend, joints)
+    return theta.index_add(0, before, 0.5 * k * c).index_add(0, joints, -0.5 * k * c)
 
 
-def position_pass(y, theta, edges, rest_length, k_stretch, k_shear):
-    """Eqs. 2-4 for a set of edges that share no node."""
+def position_pass(y, theta, edges, rest_length, k_stretch, k_shear, nxt=None):
+    """Eqs. 2-4 for a set of edges that share no node; edge e joins e and
+    nxt[e] (default e + 1).  k_stretch, k_shear: scalars or per edge (node)."""
     if edges.numel() == 0:
         return y
-    v = y[:, edges + 1] - y[:, edges]
+    other = edges + 1 if nxt is None else nxt[edges]
+    v = y[:, other] - y[:, edges]
     ell = torch.sqrt(v[0] * v[0] + v[1] * v[1])
     L = rest_length[edges]
+    ks, ksh = _at(k_stretch, edges), _at(k_shear, edges)
     c_stretch = (ell - L) * v / ell                                          # Eq. 2
     d = torch.stack([torch.cos(theta[edges]), torch.sin(theta[edges])])
-    dx = 0.5 * k_stretch * (c_stretch + k_shear * (v - L * d - c_stretch))   # Eq. 3
-    return y.index_add(1, edges, dx).index_add(1, edges + 1, -dx)           # Eq. 4
+    dx = 0.5 * ks * (c_stretch + ksh * (v - L * d - c_stretch))              # Eq. 3
+    return y.index_add(1, edges, dx).index_add(1, other, -dx)               # Eq. 4
 
 
-def pbd_project(x, topo: Topology, theta_hat, rest_length, p: Params, iters=None):
-    """K iterations of (bend even, bend odd, position even, position odd) from y = x.
+def pbd_project(x, topo: Topology, theta_hat, rest_length, p: Params, iters=None, stiff=None):
+    """K iterations of (bend: colours 0, 1, 2; position: colours 0, 1, 2) from y = x.
 
-    Returns the projected positions y and the edge angles theta."""
+    ``stiff``: optional per-node (k_bend, k_stretch, k_shear) tensors (the
+    paper's per-edge stiffnesses), else the scalars of p.  Returns the
+    projected positions y and the edge angles theta."""
     iters = p.pbd_iters if iters is None else iters
+    kb, ks, ksh = (p.k_bend, p.k_stretch, p.k_shear) if stiff is None else stiff
     y = x
     theta = edge_angles(y, topo)
     for _ in range(iters):
         for js in topo.joint_sets:
-            theta = bend_pass(theta, js, theta_hat, p.k_bend)
+            theta = bend_pass(theta, js, theta_hat, kb, topo.joint_prev)
         for es in topo.edge_sets:
-            y = position_pass(y, theta, es, rest_length, p.k_stretch, p.k_shear)
+            y = position_pass(y, theta, es, rest_length, ks, ksh, topo.edge_next)
     return y, theta
 
 
-def elastic_force(x, topo: Topology, theta_hat, rest_length, p: Params):
+def elastic_force(x, topo: Topology, theta_hat, rest_length, p: Params, stiff=None):
     """F_el,i = k_el (y_i - x_i) with y the PBD projection of x."""
-    y, _ = pbd_project(x, topo, theta_hat, rest_length, p)
+    y, _ = pbd_project(x, topo, theta_hat, rest_length, p, stiff=stiff)
     return p.k_elastic * (y - x)
+
+
+# ---------------------------------------------------------------------------
+# Behavioural descriptors of the quality-diversity search (Experiments, QD
+# Search, Eqs. 5-6): bending effort E_bend = sum |theta_rest^{t-1} -
+# theta_rest^t|^2 and stretching effort E_pos = sum |L_rest^{t-1} -
+# L_rest^t|^2, per filament, for one change of the rest values (a controller
+# writing new ones); summed over the filament's joints and edges.
+# ---------------------------------------------------------------------------
+
+def rest_effort(topo: Topology, old_angle, new_angle, old_length, new_length):
+    """(E_bend, E_pos) per filament [2, F] for one change of the rest values."""
+    F = topo.n_filaments
+    eb = torch.zeros(F, dtype=DT).index_add(
+        0, topo.joint_fil, (old_angle[topo.joints] - new_angle[topo.joints]) ** 2)
+    ep = torch.zeros(F, dtype=DT).index_add(
+        0, topo.fil_of_node[topo.edges], (old_length[topo.edges] - new_length[topo.edges]) ** 2)
+    return torch.stack([eb, ep])
 
 
 # ---------------------------------------------------------------------------
@@ -347,17 +409,21 @@ class Inputs:
     amp: torch.Tensor
     period: torch.Tensor
     phase: torch.Tensor
+    stiff: tuple = None          # per-node (k_bend, k_stretch, k_shear), or None: Params scalars
 
 
 def inputs_from_world(w) -> Inputs:
     """Widen a workloads.World to float64 tensors (exact)."""
+    t = lambda a: torch.from_numpy(np.asarray(a).astype(np.float64))
+    stiff = getattr(w, "stiffness", None)
     return Inputs(
-        topo=Topology(w.fil_offset),
-        rest_angle=torch.from_numpy(w.rest_angle.astype(np.float64)),
-        rest_length=torch.from_numpy(w.rest_length.astype(np.float64)),
-        amp=torch.from_numpy(w.act_amp.astype(np.float64)),
-        period=torch.from_numpy(w.act_period.astype(np.float64)),
-        phase=torch.from_numpy(w.act_phase.astype(np.float64)),
+        topo=Topology(w.fil_offset, getattr(w, "closed", None)),
+        rest_angle=t(w.rest_angle),
+        rest_length=t(w.rest_length),
+        amp=t(w.act_amp),
+        period=t(w.act_period),
+        phase=t(w.act_phase),
+        stiff=None if stiff is None else tuple(t(k) for k in stiff),
     )
 
 
@@ -373,7 +439,7 @@ def step(x, f, t, inp: Inputs, p: Params, rest_angle=None, trace=None):
     """
     ra = inp.rest_angle if rest_angle is None else rest_angle
     theta_hat = actuation(ra, inp.topo, inp.amp, inp.period, inp.phase, t)      # S0
-    f_el = elastic_force(x, inp.topo, theta_hat, inp.rest_length, p)           # S1
+    f_el = elastic_force(x, inp.topo, theta_hat, inp.rest_length, p, inp.stiff)  # S1
     s = deposit(x, p)                                                           # S2
     st = gaussian_filter(s, p)                                                  # S3
     f_rep = repulsion(x, st, p)                                                 # S4
