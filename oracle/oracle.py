@@ -232,6 +232,43 @@ def elastic_force(x, topo: Topology, theta_hat, rest_length, p: Params, stiff=No
 
 
 # ---------------------------------------------------------------------------
+# Energy field (Methods, Fields: a persistent scalar field of Gaussian packets
+# at random positions, a chemotaxis target; Experiments, Neuroevolution of
+# Controller Circuit: each node senses the energy at its position, fitness
+# adds the total energy collected).  Reading: packets are Gaussians summed
+# into every cell (minimum image); at every step each node senses
+# e_i = I[E](x_i) with the transfer kernel at the step's starting position,
+# collects c_i = rate e_i, which is taken out of the field by the same kernel
+# (E <- E - S[c], so the field loses exactly what the nodes collect), and the
+# filament's collected total grows by the sum of its nodes' c_i.  The field
+# does not act on the motion.
+# ---------------------------------------------------------------------------
+
+def energy_packets(nx, ny, centres, amps, widths):
+    """E_c = sum_p A_p exp(-|c - c_p|^2 / (2 s_p^2)) over every cell (minimum
+    image); centres [2, P], amps [P], widths [P]."""
+    cx = torch.arange(nx, dtype=DT)
+    cy = torch.arange(ny, dtype=DT)
+    E = torch.zeros(ny, nx, dtype=DT)
+    for k in range(centres.shape[1]):
+        dx = min_image(cx - centres[0, k], nx)
+        dy = min_image(cy - centres[1, k], ny)
+        r2 = dy[:, None] ** 2 + dx[None, :] ** 2
+        E = E + amps[k] * torch.exp(-r2 / (2.0 * widths[k] ** 2))
+    return E
+
+
+def energy_update(x, E, topo: Topology, rate, p: Params):
+    """One step of sensing and collection at positions x: returns the sensed
+    values e [N], the energy collected per filament [F] and the field after
+    collection."""
+    e = interpolate(x, E[None], p)[0]
+    c = rate * e
+    collected = torch.zeros(topo.n_filaments, dtype=DT).index_add(0, topo.fil_of_node, c)
+    return e, collected, E - spread(x, c[None], p)[0]
+
+
+# ---------------------------------------------------------------------------
 # Behavioural descriptors of the quality-diversity search (Experiments, QD
 # Search, Eqs. 5-6): bending effort E_bend = sum |theta_rest^{t-1} -
 # theta_rest^t|^2 and stretching effort E_pos = sum |L_rest^{t-1} -
