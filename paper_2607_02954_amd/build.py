@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmicrocosm.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "probe.hip", "runtime.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "loss.hip", "probe.hip", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MICROCOSM_ARCH", "gfx950")

@@ -40,6 +40,9 @@ class World:
     act_phase: np.ndarray           # float32 [F] actuation phase offset (rad)
     target: Optional[np.ndarray] = None   # float64 [2, N] loss target (folding workload)
     meta: dict = field(default_factory=dict)
+    stiffness: Optional[tuple] = None     # float32 [N] x 3: per-edge (k_bend, k_stretch, k_shear)
+    closed: Optional[np.ndarray] = None   # bool [F]: filament f is a closed loop
+    energy: Optional[np.ndarray] = None   # float32 [ny, nx] initial energy field
 
     @property
     def n_particles(self) -> int:
@@ -117,6 +120,40 @@ def random_world(seed: int, nx: int, ny: int, lengths: List[int], *, angle_sd: f
     amps = np.full(F, amp, dtype=np.float64)
     return _assemble(nx, ny, chains, rest_angle, rest_length, amps, period, phase,
                      meta=dict(seed=seed, orient=orient, centres=centres))
+
+
+def polygon_loop(n: int, centre, angle: float = 0.0, bond: float = 1.0) -> np.ndarray:
+    """Nodes of a regular n-gon with sides ``bond``, float64 [2, n]."""
+    r = 0.5 * bond / math.sin(math.pi / n)
+    a = angle + 2.0 * math.pi * np.arange(n) / n
+    return np.stack([centre[0] + r * np.cos(a), centre[1] + r * np.sin(a)])
+
+
+def generality_world(seed: int, nx: int, ny: int, chain_lengths: List[int], loop_lengths: List[int], *,
+                     amp: float = 0.5, angle_sd: float = 0.3, stiffness_range=(0.2, 1.0)) -> World:
+    """Open chains and closed loops with per-edge stiffnesses: chains as in
+    random_world; loops are regular polygons (unit sides) with rest angles
+    2 pi / n + N(0, angle_sd^2) at every node; every node's k_bend,
+    k_stretch and k_shear ~ U(stiffness_range)."""
+    g = _rng(seed + 32452843)
+    base = random_world(seed, nx, ny, chain_lengths, angle_sd=angle_sd, amp=amp)
+    chains = [base.positions64()[:, base.fil_offset[f]:base.fil_offset[f + 1]] for f in range(base.n_filaments)]
+    ra = [base.rest_angle.astype(np.float64)]
+    for n in loop_lengths:
+        centre = g.uniform(0.0, 1.0, size=2) * np.array([nx, ny])
+        chains.append(polygon_loop(n, centre, g.uniform(0, 2 * math.pi)))
+        ra.append(2 * math.pi / n + g.normal(0.0, angle_sd, size=n))
+    F = len(chains)
+    N = sum(c.shape[1] for c in chains)
+    amps = np.full(F, amp)
+    period = np.concatenate([base.act_period, g.uniform(20.0, 100.0, size=len(loop_lengths))])
+    phase = np.concatenate([base.act_phase, g.uniform(0.0, 2 * math.pi, size=len(loop_lengths))])
+    w = _assemble(nx, ny, chains, np.concatenate(ra), np.ones(N), amps, period, phase,
+                  meta=dict(seed=seed, name="generality"))
+    w.closed = np.array([False] * len(chain_lengths) + [True] * len(loop_lengths))
+    lo, hi = stiffness_range
+    w.stiffness = tuple(g.uniform(lo, hi, size=N).astype(np.float32) for _ in range(3))
+    return w
 
 
 # ---------------------------------------------------------------------------
@@ -199,6 +236,65 @@ def folding_population(seed: int = 0, n_fil: int = 64, length: int = 48, nx: int
         tgt.append(pts)
     w.target = np.concatenate(tgt, axis=1)
     w.meta["name"] = "folding"
+    return w
+
+
+def curled_chain(g: np.random.Generator, n: int, centre, turn_sd: float, bond: float = 1.0) -> np.ndarray:
+    """A chain of unit bonds whose turning angles are i.i.d. N(0, turn_sd^2)
+    (a persistent random walk), centroid at ``centre``: [2, n]."""
+    heading = g.uniform(0.0, 2.0 * math.pi) + np.concatenate([[0.0], np.cumsum(g.normal(0.0, turn_sd, size=n - 2))])
+    pts = np.zeros((2, n))
+    pts[0, 1:] = np.cumsum(bond * np.cos(heading))
+    pts[1, 1:] = np.cumsum(bond * np.sin(heading))
+    return pts - pts.mean(axis=1, keepdims=True) + np.asarray(centre, dtype=np.float64)[:, None]
+
+
+def stroke_image(g: np.random.Generator, width: int, height: int, radius: float, stroke: float) -> np.ndarray:
+    """A seeded target image [height, width] in [0, 1]: a smooth closed random
+    curve (radius about ``radius`` pixels around the centre, three random
+    harmonics) drawn as a stroke of Gaussian profile (``stroke`` pixels)."""
+    s = np.linspace(0.0, 2.0 * math.pi, 720, endpoint=False)
+    r = radius * (1.0 + sum(g.normal(0.0, 0.12) * np.cos((m + 2) * s + g.uniform(0, 2 * math.pi))
+                            for m in range(3)))
+    px = width / 2.0 + r * np.cos(s) - 0.5
+    py = height / 2.0 + r * np.sin(s) - 0.5
+    a = np.arange(width, dtype=np.float64)
+    b = np.arange(height, dtype=np.float64)
+    d2 = np.full((height, width), np.inf)
+    for x, y in zip(px, py):
+        d2 = np.minimum(d2, (a[None, :] - x) ** 2 + (b[:, None] - y) ** 2)
+    return np.exp(-d2 / (2.0 * stroke * stroke))
+
+
+def density_folding(seed: int = 0, n: int = 1000, nx: int = 256, ny: int = 256, width: int = 128,
+                    height: int = 128) -> World:
+    """The paper's folding experiment at its sizes (one 1000-node filament, a
+    128 x 128 loss image): a curled chain (persistent random walk, turning
+    angles N(0, 0.5^2)) in the middle of a 256^2 world, rest angles
+    N(0, 0.3^2), no actuation; ``meta['image']`` holds a seeded target
+    image (a closed stroke, standing in for a digit image)."""
+    g = _rng(seed + 15485863)
+    chain = curled_chain(g, n, (nx / 2.0, ny / 2.0), 0.5)
+    ra = np.zeros(n)
+    ra[1:n - 1] = g.normal(0.0, 0.3, size=n - 2)
+    w = _assemble(nx, ny, [chain], ra, np.ones(n), [0.0], [50.0], [0.0],
+                  meta=dict(seed=seed, name="density_folding"))
+    w.meta["image"] = stroke_image(g, width, height, radius=0.22 * min(width, height), stroke=1.2)
+    return w
+
+
+def energy_world(seed: int = 0, nx: int = 256, ny: int = 256, n_fil: int = 64, length: int = 48,
+                 n_packets: int = 24, amp: float = 0.5) -> World:
+    """A chemotaxis world: swimming chains (sinusoidal bending) and packets
+    of energy at uniform random positions, amplitudes U(0.5, 2), widths
+    U(3, 12) cells (``meta['packets']`` = (centres [2, P], amps, widths)); the
+    initial field ``energy`` is left to be built from them."""
+    w = random_world(seed, nx, ny, [length] * n_fil, amp=amp)
+    g = _rng(seed + 49979687)
+    centres = g.uniform(0.0, 1.0, size=(2, n_packets)) * np.array([[nx], [ny]])
+    amps = g.uniform(0.5, 2.0, size=n_packets)
+    widths = g.uniform(3.0, 12.0, size=n_packets)
+    w.meta.update(name="energy", packets=(centres, amps, widths))
     return w
 
 
