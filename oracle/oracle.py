@@ -60,6 +60,8 @@ class Params:
     sigma: float = 1.0           # Gaussian filter width (cells)
     radius: int = 4              # Gaussian filter truncation radius (cells)
     u_max: float = 0.3           # Mach guard on |u|
+    mdf_iters: int = 1           # multi-direct forcing iterations (1: explicit coupling)
+    marker_offset: float = 0.0   # two-layer markers at +-offset along the normal (0: one layer)
 
 
 # ---------------------------------------------------------------------------
@@ -347,6 +349,85 @@ def interpolate(x, field, p: Params):
 
 
 # ---------------------------------------------------------------------------
+# Leakage fixes of the coupling (Methods, Fluid-filament Interaction: Multi-
+# Direct Forcing, and broadcasting the filament as a two-layer version of
+# itself).  Reading:
+#   * two layers: node i is broadcast as two markers X_i = x_i +- delta n_i
+#     (n_i the unit normal: the tangent is x_next - x_prev where the node has
+#     two neighbours, the edge direction at a chain end); spreading gives each
+#     marker half of the node's value, and a node samples the mean of its two
+#     markers' interpolated values; delta = 0 is the one-layer transfer;
+#   * MDF: the node's desired velocity is what the explicit coupling gives it,
+#     U_d = I2[u*] + F / 2 with u* = j / rho (the fluid velocity without the
+#     body force) and F the node force (the Guo half-force gain, rho_0 = 1);
+#     the first iteration spreads F itself; each further one samples
+#     u = (j + F_grid / 2) / rho at the markers and spreads the correction
+#     2 (U_d - I2[u]).  One iteration is the explicit coupling.
+# ---------------------------------------------------------------------------
+
+def marker_normals(x, topo: Topology):
+    """Unit normal (-t_y, t_x) at every node from its neighbours (zero for a
+    single-node filament)."""
+    N = topo.n
+    nxt = torch.arange(N) + 1
+    prv = torch.arange(N) - 1
+    has_next = torch.zeros(N, dtype=torch.bool)
+    has_prev = torch.zeros(N, dtype=torch.bool)
+    if topo.edges.numel():
+        e = topo.edges
+        nxt = nxt.index_put((e,), topo.edge_next[e])
+        has_next[e] = True
+        prv = prv.index_put((topo.edge_next[e],), e)
+        has_prev[topo.edge_next[e]] = True
+    i = torch.arange(N)
+    a = torch.where(has_prev, prv, i)
+    b = torch.where(has_next, nxt, i)
+    t = x[:, b.clamp(0, max(N - 1, 0))] - x[:, a.clamp(0, max(N - 1, 0))]
+    norm = torch.sqrt(t[0] ** 2 + t[1] ** 2)
+    safe = torch.where(norm > 0, norm, torch.ones_like(norm))
+    t = torch.where(norm > 0, t / safe, torch.zeros_like(t))
+    return torch.stack([-t[1], t[0]])
+
+
+def spread2(x, vals, topo: Topology, p: Params):
+    """Two-layer spread: half of each node's value from each of its markers."""
+    if p.marker_offset == 0.0:
+        return spread(x, vals, p)
+    d = p.marker_offset * marker_normals(x, topo)
+    return 0.5 * (spread(x + d, vals, p) + spread(x - d, vals, p))
+
+
+def interpolate2(x, field, topo: Topology, p: Params):
+    """Two-layer interpolation: the mean of the node's two markers' values."""
+    if p.marker_offset == 0.0:
+        return interpolate(x, field, p)
+    d = p.marker_offset * marker_normals(x, topo)
+    return 0.5 * (interpolate(x + d, field, p) + interpolate(x - d, field, p))
+
+
+def coupling_force(x, f, force, topo: Topology, p: Params, trace=None):
+    """Grid force of the step: the node forces spread (two-layer), then
+    mdf_iters - 1 multi-direct-forcing corrections."""
+    Fg = spread2(x, force, topo, p)
+    if p.mdf_iters <= 1:
+        return Fg
+    cx = C_Q[:, 0].reshape(9, 1, 1)
+    cy = C_Q[:, 1].reshape(9, 1, 1)
+    rho = f.sum(dim=0)
+    j = torch.stack([(f * cx).sum(dim=0), (f * cy).sum(dim=0)])
+    U_d = interpolate2(x, j / rho, topo, p) + 0.5 * force
+    mismatch = []
+    for _ in range(p.mdf_iters - 1):
+        U = interpolate2(x, (j + 0.5 * Fg) / rho, topo, p)
+        mismatch.append(float((U_d - U).abs().max()))
+        Fg = Fg + spread2(x, 2.0 * (U_d - U), topo, p)
+    if trace is not None:
+        trace["mdf_mismatch"] = mismatch
+        trace["U_d"] = U_d
+    return Fg
+
+
+# ---------------------------------------------------------------------------
 # S2-S4. Steric repulsion field (Methods, Fields: deposit, Gaussian filter,
 # gradient of the density gives repulsion)
 # ---------------------------------------------------------------------------
@@ -481,10 +562,10 @@ def step(x, f, t, inp: Inputs, p: Params, rest_angle=None, trace=None):
     st = gaussian_filter(s, p)                                                  # S3
     f_rep = repulsion(x, st, p)                                                 # S4
     force = f_el + f_rep
-    Fg = spread(x, force, p)                                                    # S5
+    Fg = coupling_force(x, f, force, inp.topo, p, trace)                        # S5
     fstar, u = lbm_collide(f, Fg, p)                                            # S6
     f_new = lbm_stream(fstar)
-    x_new = x + interpolate(x, u, p)                                            # S7
+    x_new = x + interpolate2(x, u, inp.topo, p)                                 # S7
     if trace is not None:
         trace.update(theta_hat=theta_hat, f_el=f_el, s=s, st=st, f_rep=f_rep, force=force,
                      Fg=Fg, u=u, fstar=fstar)
