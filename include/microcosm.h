@@ -87,6 +87,9 @@ typedef struct sim_params {
                               kernels work on (and of the node bins): 16, 32 or 64;
                               0 means 32.  A tuning choice: results do not depend
                               on it beyond rounding (binned: not at all).          */
+  float energy_rate;       /* energy field (sim_arrays.energy): fraction of the
+                              sensed energy a node collects per step, in [0, 1];
+                              0 disables the field                                 */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).
@@ -111,14 +114,39 @@ typedef struct sim_arrays {
                                  (-1,-1), (+1,-1).                                        */
   float *u;                   /* [ny][nx][2] out: fluid velocity (x, y interleaved) of
                                  the last step taken                                     */
+  /* Optional per-edge parameters and topology (Methods, Filaments: stiffness
+   * coefficients on the edge level; filaments with loops).  NULL: the
+   * scalars of sim_params, and open chains. */
+  const float *k_bend;        /* [N] bending stiffness of the joint at node i            */
+  const float *k_stretch;     /* [N] stretch stiffness of the edge leaving node i        */
+  const float *k_shear;       /* [N] shear blend of the edge leaving node i              */
+  const int32_t *fil_flags;   /* [F] SIM_FIL_CLOSED: filament f is a closed loop (at
+                                 least 3 nodes): its last node's edge joins it to the
+                                 first (rest_length of the last node), every node is a
+                                 joint (the first between the closing edge and edge 0),
+                                 and the actuation wave runs over all n joints          */
+  /* Optional energy field (Methods, Fields: persistent scalar field of Gaussian
+   * packets; Experiments, Neuroevolution: nodes sense the energy at their
+   * position, fitness adds the energy collected).  Used when
+   * sim_params.energy_rate > 0 and `energy` is given: at every step each node
+   * senses e = sum_c W(c - x) E_c at the step's starting position (the
+   * transfer kernel), collects energy_rate * e, and the field loses exactly
+   * that through the same kernel.  The field does not act on the motion. */
+  float *energy;              /* [ny][nx] in/out: the persistent field                 */
+  float *energy_sensed;       /* [N] out, may be NULL: e of the last step              */
+  float *energy_collected;    /* [F] ACCUMULATED, may be NULL: energy collected per
+                                 filament (caller zeroes)                              */
 } sim_arrays;
+
+enum { SIM_FIL_CLOSED = 1 };
 
 typedef struct sim_world sim_world;
 typedef struct sim_batch sim_batch;
 
 /* Fill *p with the defaults (tau 1, Lambda 1/4, k_bend 0.5, k_stretch 1,
  * k_shear 0.5, 4 PBD iterations, k_elastic 0.05, k_repulse 0.1, sigma 1,
- * radius 4, u_max 0.3, flags 0, tile side 32) for an nx x ny grid. */
+ * radius 4, u_max 0.3, flags 0, tile side 32, no energy field) for an nx x ny
+ * grid. */
 void sim_params_default(sim_params *p, int32_t nx, int32_t ny);
 
 /* Bytes of device workspace sim_create needs for a world of this size. */
@@ -152,7 +180,8 @@ sim_status sim_checkpoint_size(const sim_world *w, int32_t n_steps, int32_t ckpt
  * checkpoints written by sim_rollout(t0, n_steps, ckpt_every) and g_pos =
  * dL/dx at the final step ([2][N] device floats), ACCUMULATES dL/d(rest_angle)
  * into g_rest_angle ([N], caller zeroes) and, if g_pos0 is not NULL, WRITES
- * dL/dx at t0 into g_pos0 ([2][N]).  Each segment is recomputed forward from
+ * dL/dx at t0 into g_pos0 ([2][N]).  Worlds with closed loops are not
+ * differentiated (SIM_E_INVALID).  Each segment is recomputed forward from
  * its checkpoint into adj_ws, then hand-written adjoint kernels run step by
  * step in reverse.  adj_ws must hold sim_backward_workspace_size bytes.
  * The world's own state arrays are not modified.  Only worlds that use the
@@ -192,6 +221,26 @@ sim_status sim_density_loss_workspace_size(const sim_splat_image *img, size_t *b
 sim_status sim_density_loss(const sim_splat_image *img, int32_t nx, int32_t ny, int32_t n_particles,
                             const int32_t *cell, const float *frac, const float *target, float *image,
                             float *loss, float *g_pos, void *workspace, size_t ws_bytes, void *stream);
+
+/* Add Gaussian energy packets to a field ([ny][nx] device floats):
+ * field_c += sum_p amps[p] exp(-|c - c_p|^2 / (2 widths[p]^2)), over every cell
+ * (minimum-image distance; cell c centred at its integer coordinates).
+ * centres [2][P] (x row, y row), amps [P], widths [P]: device arrays. */
+sim_status sim_energy_packets(int32_t nx, int32_t ny, int32_t n_packets, const float *centres,
+                              const float *amps, const float *widths, float *field, void *stream);
+
+/* Behavioural descriptors of the quality-diversity search (Experiments, QD
+ * Search, Eqs. 5-6) for one change of the rest values (a controller writing
+ * new rest angles and lengths between steps): per filament f,
+ *   effort[f]     += sum over its joints of (old - new rest angle)^2  (E_bend)
+ *   effort[F + f] += sum over its edges  of (old - new rest length)^2 (E_pos)
+ * with joints and edges as in sim_arrays (fil_flags may be NULL: all open
+ * chains).  All arrays are device arrays; effort [2][F] is accumulated
+ * (caller zeroes).  Sums are formed in a fixed order (reproducible). */
+sim_status sim_rest_effort(int32_t n_filaments, const int32_t *fil_offset, const int32_t *fil_flags,
+                           const float *old_rest_angle, const float *new_rest_angle,
+                           const float *old_rest_length, const float *new_rest_length, float *effort,
+                           void *stream);
 
 /* Wait for the world's stream; report asynchronous HIP errors, the sticky
  * Mach/NaN flag (SIM_E_UNSTABLE), and SIM_E_STATE if the tile bins did not

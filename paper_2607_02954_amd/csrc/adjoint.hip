@@ -353,7 +353,7 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     if (is_joint) {
       const int f = pk.fil_begin + lo;
       th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[f], glb(w.act_period)[f],
-                              glb(w.act_phase)[f], A.t, j, n);
+                              glb(w.act_phase)[f], A.t, j, n - 2);
     }
     // dL/dx_t so far (written by k_adj_force) plus the deposit derivative
     float xbx = 0.f, xby = 0.f;
@@ -379,9 +379,12 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 
     // forward PBD again, keeping the state each position pass starts from
     const int K = w.pbd_iters;
-    const float hb = 0.5f * w.k_bend;
-    const float hs = 0.5f * w.k_stretch;
-    const float ksh = w.k_shear;
+    // per-edge stiffnesses of the joint and the edge at this node (chains only:
+    // worlds with loops are not differentiated)
+    const int gs = active ? gi : pk.node_begin;
+    const float hb = 0.5f * (w.kb_arr ? glb(w.kb_arr)[gs] : w.k_bend);
+    const float hs = 0.5f * (w.ks_arr ? glb(w.ks_arr)[gs] : w.k_stretch);
+    const float ksh = w.ksh_arr ? glb(w.ksh_arr)[gs] : w.k_shear;
     float d_pe_x[kMaxAdjIters], d_pe_y[kMaxAdjIters], d_po_x[kMaxAdjIters], d_po_y[kMaxAdjIters];
     float th_p[kMaxAdjIters];
     s_th[li] = th;

@@ -112,12 +112,12 @@ static __device__ __forceinline__ void peskin4_d(float f, float w[4], float dw[4
   dw[3] = 0.125f * (2.0f - qd);
 }
 
-// Actuated rest angle of joint j (of n - 2) of a filament at time step t:
-// ra + amp sin(2 pi t / period + phase - 2 pi j / (n - 2)).  The phase is
-// formed in revolutions and reduced to [-1/2, 1/2] (the integer part of
-// t / period is removed in FP64), so FP32 sinf sees a small argument.
+// Actuated rest angle of joint j (of m: n - 2 on a chain, n on a loop) of a
+// filament at time step t: ra + amp sin(2 pi t / period + phase - 2 pi j / m).
+// The phase is formed in revolutions and reduced to [-1/2, 1/2] (the integer
+// part of t / period is removed in FP64), so FP32 sinf sees a small argument.
 static __device__ __forceinline__ float actuated_angle(float ra, float amp, float period, float phase, long long t,
-                                                       int j, int n) {
+                                                       int j, int m) {
   if (amp == 0.0f) return ra;
   float frac_t;                                 // (t / period) mod 1
   if (t < (1ll << 24)) {
@@ -133,7 +133,7 @@ static __device__ __forceinline__ float actuated_angle(float ra, float amp, floa
     const double q = (double)t / (double)period;
     frac_t = (float)(q - floor(q));
   }
-  float r = frac_t + phase * (1.0f / kTwoPi) - (float)j / (float)(n - 2);
+  float r = frac_t + phase * (1.0f / kTwoPi) - (float)j / (float)m;
   r -= rintf(r);
   return ra + amp * sinf(kTwoPi * r);
 }

@@ -80,6 +80,15 @@ struct WorldDev {
   int* cell_out;       float* frac_out;          // positions after the step (may alias)
   const float* rest_angle; const float* rest_length;
   const float* act_amp; const float* act_period; const float* act_phase;
+  const float* kb_arr; const float* ks_arr; const float* ksh_arr;   // [N] per-edge stiffnesses, or null
+  const int* fil_flags;                 // [F] bit 0: closed loop, or null (all chains)
+  // energy field (null energy: none): sensed at the nodes, collected at
+  // `energy_rate` per step and taken out of the field
+  float energy_rate; int pad3;
+  float* energy;                        // [ny][nx] persistent field
+  float* e_node;                        // [2][N] sensed value (row 0; row 1 stays 0)
+  float* e_sensed;                      // [N] caller copy of the sensed values, or null
+  float* e_collected;                   // [F] accumulated collected energy, or null
   const float* f_src;  float* f_dst;    // shifted populations f - w, [9][ny][nx]
   float2* u;                            // [ny][nx] fluid velocity (x, y interleaved)
   float* s;                             // deposit accumulator [ny][nx] (direct mode)
@@ -135,6 +144,7 @@ struct Grid {
   int any_sorted, any_binned, any_node;      // which transfer families the table holds
                                              // (any_node: a world not in binned mode)
   int max_radius;                            // largest Gaussian radius of any world (LDS sizing)
+  int any_energy;                            // a world has an energy field
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at
@@ -168,6 +178,12 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, hipEvent_t start,
                       hipEvent_t stop);
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+// energy field: sensing and collection at the step's starting positions
+// (between the fluid update and the integration)
+void launch_energy(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+// add Gaussian packets to a field
+void launch_energy_packets(int nx, int ny, int n_packets, const float* centres, const float* amps,
+                           const float* widths, float* field, hipStream_t s);
 // set-up: the bin runs of every tile (side `tile`) of an nx x ny world of Gaussian radius R
 void launch_tile_ranges(int nx, int ny, int R, int tile, int2* out, hipStream_t s);
 void launch_set_ctl(Ctl* c, long long t, int remaining, hipStream_t s);
@@ -179,6 +195,11 @@ size_t density_loss_workspace(int W, int H);
 void launch_density_loss(int nx, int ny, int n, int W, int H, float sigma, float amp, const int* cell,
                          const float* frac, const float* target, float* image, float* loss, float* g_pos,
                          void* ws, hipStream_t s);
+
+// Bending and stretching effort of a change of the rest values, per filament
+// (accumulated into effort[2][F]).
+void launch_rest_effort(int n_fil, const int* fil_offset, const int* fil_flags, const float* old_a,
+                        const float* new_a, const float* old_l, const float* new_l, float* effort, hipStream_t s);
 
 // Record msg as the thread's last error message (sim_last_error) and return st.
 int report_error(int st, const char* msg);

@@ -78,10 +78,14 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     const int gin = min(gic + 1, N - 1);
     const int c0x = cell[gic], c0y = cell[N + gic];
     const float f0x = frac[gic], f0y = frac[N + gic];
-    const int c1x = cell[gin], c1y = cell[N + gin];
-    const float f1x = frac[gin], f1y = frac[N + gin];
+    int c1x = cell[gin], c1y = cell[N + gin];
+    float f1x = frac[gin], f1y = frac[N + gin];
     const float L_r = glb(w.rest_length)[gic];
     const float ra = glb(w.rest_angle)[gic];
+    // per-edge stiffnesses (joint and edge at this node), else the world's
+    const float kb_i = w.kb_arr ? glb(w.kb_arr)[gic] : w.k_bend;
+    const float ks_i = w.ks_arr ? glb(w.ks_arr)[gic] : w.k_stretch;
+    const float ksh_i = w.ksh_arr ? glb(w.ksh_arr)[gic] : w.k_shear;
     if (li < nf) s_off[li] = off_a - pk.node_begin;
     if (li == 0) s_off[nf] = off_b - pk.node_begin;
     __syncthreads();
@@ -95,10 +99,29 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     const int o = s_off[lo];
     const int n = s_off[lo + 1] - o;
     const int k = li - o;
-    const bool has_edge = active && k < n - 1;
-    const bool is_joint = active && k >= 1 && k <= n - 2;
-    const int j = k - 1;
     const int fil = pk.fil_begin + lo;
+    // a closed loop (at least three nodes): the last node's edge joins it to
+    // the first, and every node is a joint (the first between the closing
+    // edge and edge 0)
+    const bool ring = w.fil_flags && (glb(w.fil_flags)[fil] & 1) && n >= 3;
+    const bool has_edge = active && (k < n - 1 || ring);
+    const bool is_joint = active && (ring || (k >= 1 && k <= n - 2));
+    const int j = ring ? k : k - 1;              // joint's local index
+    const int m = ring ? n : n - 2;              // joints of the filament
+    const int li_prev = (ring && k == 0) ? o + n - 1 : li - 1;    // edge before the joint
+    const int li_next = (ring && k == n - 1) ? o : li + 1;        // far node of the edge
+    if (ring && k == n - 1) {                    // the closing edge's far node: the first
+      const int g0 = pk.node_begin + o;
+      c1x = cell[g0];
+      c1y = cell[N + g0];
+      f1x = frac[g0];
+      f1y = frac[N + g0];
+    }
+    // Gauss-Seidel colours: local parity; on a loop of odd length the last
+    // joint and the last edge meet the first ones and take a third colour
+    const int jcol = (ring && (n & 1) && j == n - 1) ? 2 : (j & 1);
+    const int ecol = (ring && (n & 1) && k == n - 1) ? 2 : (k & 1);
+    const int ncol = __syncthreads_or(active && ring && (n & 1)) ? 3 : 2;   // block-uniform
     const float amp = glb(w.act_amp)[fil], period = glb(w.act_period)[fil], phase = glb(w.act_phase)[fil];
 
     const int cx = active ? c0x : 0, cy = active ? c0y : 0;
@@ -118,33 +141,33 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
       }
     }
     float th_hat = 0.f;
-    if (is_joint) th_hat = actuated_angle(ra, amp, period, phase, ctl.t, j, n);
+    if (is_joint) th_hat = actuated_angle(ra, amp, period, phase, ctl.t, j, m);
     s_th[li] = th;
     s_dx[li] = 0.f;
     s_dy[li] = 0.f;
     __syncthreads();
 
-    const float hb = 0.5f * w.k_bend;
-    const float hs = 0.5f * w.k_stretch;
-    const float ksh = w.k_shear;
+    const float hb = 0.5f * kb_i;
+    const float hs = 0.5f * ks_i;
+    const float ksh = ksh_i;
     const int iters = w.pbd_iters;
     for (int iter = 0; iter < iters; ++iter) {
-      // bending pass (Eq. 1): even joints, then odd joints
-      for (int par = 0; par < 2; ++par) {
-        if (is_joint && (j & 1) == par) {
-          const float t1 = s_th[li - 1];
+      // bending pass (Eq. 1): even joints, then odd joints (then a loop's third colour)
+      for (int par = 0; par < ncol; ++par) {
+        if (is_joint && jcol == par) {
+          const float t1 = s_th[li_prev];
           const float t2 = s_th[li];
           const float c = wrap_angle(t2 - t1) - th_hat;
-          s_th[li - 1] = t1 + hb * c;
+          s_th[li_prev] = t1 + hb * c;
           s_th[li] = t2 - hb * c;
         }
         __syncthreads();
       }
-      // position pass (Eqs. 2-4): even edges, then odd edges
-      for (int par = 0; par < 2; ++par) {
-        if (has_edge && (k & 1) == par) {
+      // position pass (Eqs. 2-4): even edges, then odd edges (then the third colour)
+      for (int par = 0; par < ncol; ++par) {
+        if (has_edge && ecol == par) {
           const float d0x = s_dx[li], d0y = s_dy[li];
-          const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
+          const float d1x = s_dx[li_next], d1y = s_dy[li_next];
           const float vx = v0x + (d1x - d0x);
           const float vy = v0y + (d1y - d0y);
           const float ell = hw_sqrt(vx * vx + vy * vy);
@@ -156,8 +179,8 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           const float dy = hs * (csy + ksh * (vy - L * sn - csy));
           s_dx[li] = d0x + dx;
           s_dy[li] = d0y + dy;
-          s_dx[li + 1] = d1x - dx;
-          s_dy[li + 1] = d1y - dy;
+          s_dx[li_next] = d1x - dx;
+          s_dy[li_next] = d1y - dy;
         }
         __syncthreads();
       }
@@ -1148,6 +1171,147 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_integrate_tile(cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Energy field: every node senses e_i = sum_c W(c - x_i) E_c at the step's
+// starting position and collects rate * e_i, which its filament's total
+// gains (summed in node order by the filament's first node) and the field
+// loses through the same kernel (k_energy_deplete: tile-binned worlds spread
+// it over the spread lists in 64-bit fixed point; others with float atomics).
+// ---------------------------------------------------------------------------
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_energy_gather(const WorldDev* __restrict__ W, Tables T) {
+  __shared__ float s_c[PACK];
+  __shared__ int s_off[PACK + 1];
+  const int npk = *T.n_packs;
+  const int li = threadIdx.x;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    if (!w.energy || w.ctl_src->remaining <= 0) continue;     // block-uniform
+    const int N = w.n_part, nx = w.nx, ny = w.ny;
+    const int nf = pk.fil_end - pk.fil_begin;
+    for (int k = li; k <= nf; k += PACK) s_off[k] = glb(w.fil_offset)[pk.fil_begin + k] - pk.node_begin;
+    const int gi = pk.node_begin + li;
+    float c = 0.f;
+    if (gi < pk.node_end) {
+      const int bx = wrap_index(glb(w.cell_in)[gi], nx), by = wrap_index(glb(w.cell_in)[N + gi], ny);
+      float wx[4], wy[4];
+      peskin4(glb(w.frac_in)[gi], wx);
+      peskin4(glb(w.frac_in)[N + gi], wy);
+      const MC_GLOBAL float* E = glb(w.energy);
+      float e = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const size_t row = (size_t)wrap_near(by - 1 + b, ny) * nx;
+        float a = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a += wx[q] * E[row + wrap_near(bx - 1 + q, nx)];
+        e += wy[b] * a;
+      }
+      glb(w.e_node)[gi] = e;
+      if (w.e_sensed) glb(w.e_sensed)[gi] = e;
+      c = w.energy_rate * e;
+    }
+    s_c[li] = c;
+    __syncthreads();
+    if (w.e_collected && li < nf) {
+      float sum = 0.f;
+      for (int k = s_off[li]; k < s_off[li + 1]; ++k) sum += s_c[k];
+      glb(w.e_collected)[pk.fil_begin + li] += sum;
+    }
+    __syncthreads();
+  }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_energy_deplete(const WorldDev* __restrict__ W,
+                                                                             Tables T) {
+  using C = TileCfg<TILE>;
+  constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells, kSpreadCap = C::kSpreadCap;
+  __shared__ __align__(16) long long s_x[kSpreadCells];
+  __shared__ __align__(16) long long s_y[kSpreadCells];
+  __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    if (!w.energy || w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
+    const int nx = w.nx, ny = w.ny;
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
+    const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
+    zero_lds_u64(s_x, kSpreadCells);
+    zero_lds_u64(s_y, kSpreadCells);
+    __syncthreads();
+    const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int cnt = glb(w.sp_cnt)[tix];
+    // the tile's spread list of this step (the records of the step's
+    // starting positions), or the bins if it overflowed
+    if (cnt >= 0 && cnt <= kSpreadCap) {
+      BinFetch f;
+      f.n = 1;
+      f.b0 = tix * kSpreadCap;
+      f.len = __lane_id() == 0 ? cnt : 0;
+      tile_spread_vec<TILE, false, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, s_y, s_list,
+                                         glbv<const vi4>(w.sp_rec), f, nullptr);
+    } else {
+      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, s_y, s_list,
+                                   glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+    }
+    __syncthreads();
+    MC_GLOBAL float* E = glb(w.energy);
+    for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
+      const int ly = k >> C::kShift, lx = k & (TILE - 1);
+      if (lx >= tw || ly >= th) continue;
+      const size_t c = (size_t)(y0 + ly) * nx + x0 + lx;
+      E[c] += fix_to_float(spread_cell<TILE>(s_x, lx, ly, nx, ny));
+    }
+    __syncthreads();
+  }
+}
+
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_energy_deplete_atomic(const WorldDev* __restrict__ W, Tables T) {
+  const int npk = *T.n_packs;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    if (!w.energy || w.mode == kBinned || w.ctl_src->remaining <= 0) continue;
+    const int gi = pk.node_begin + threadIdx.x;
+    if (gi >= pk.node_end) continue;
+    const int N = w.n_part, nx = w.nx, ny = w.ny;
+    const int bx = wrap_index(glb(w.cell_in)[gi], nx), by = wrap_index(glb(w.cell_in)[N + gi], ny);
+    float wx[4], wy[4];
+    peskin4(glb(w.frac_in)[gi], wx);
+    peskin4(glb(w.frac_in)[N + gi], wy);
+    const float c = -w.energy_rate * glb(w.e_node)[gi];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      MC_GLOBAL float* row = glb(w.energy) + (size_t)wrap_near(by - 1 + b, ny) * nx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) unsafeAtomicAdd((float*)(row + wrap_near(bx - 1 + q, nx)), c * wx[q] * wy[b]);
+    }
+  }
+}
+
+// Gaussian packets added to a field, every cell (minimum image).
+__global__ void k_energy_packets(int nx, int ny, int n_packets, const float* centres, const float* amps,
+                                 const float* widths, float* field) {
+  const int n = nx * ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int y = c / nx, x = c - y * nx;
+    float acc = 0.f;
+    for (int p = 0; p < n_packets; ++p) {
+      float dx = (float)x - centres[p], dy = (float)y - centres[n_packets + p];
+      dx -= (float)nx * floorf(dx / (float)nx + 0.5f);
+      dy -= (float)ny * floorf(dy / (float)ny + 0.5f);
+      const float s = widths[p];
+      acc += amps[p] * expf(-(dx * dx + dy * dy) / (2.0f * s * s));
+    }
+    field[c] += acc;
+  }
+}
+
 __global__ void k_set_ctl(Ctl* c, long long t, int remaining) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     Ctl v;
@@ -1241,6 +1405,24 @@ void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStre
     if (G.tile_blocks[2] > 0) k_integrate_tile<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
     k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
   }
+}
+
+void launch_energy(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
+  if (!G.any_energy) return;
+  MC_PACK_DISPATCH(k_energy_gather, G, W, T);
+  if (G.any_binned) {
+    if (G.tile_blocks[0] > 0) k_energy_deplete<16><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T);
+    if (G.tile_blocks[1] > 0) k_energy_deplete<32><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T);
+    if (G.tile_blocks[2] > 0) k_energy_deplete<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
+  }
+  if (G.any_node) MC_PACK_DISPATCH(k_energy_deplete_atomic, G, W, T);
+}
+
+void launch_energy_packets(int nx, int ny, int n_packets, const float* centres, const float* amps,
+                           const float* widths, float* field, hipStream_t s) {
+  const int n = nx * ny;
+  k_energy_packets<<<n / 256 + 1 < 4096 ? n / 256 + 1 : 4096, 256, 0, s>>>(nx, ny, n_packets, centres, amps, widths,
+                                                                         field);
 }
 
 void launch_tile_ranges(int nx, int ny, int R, int tile, int2* out, hipStream_t s) {

@@ -76,6 +76,7 @@ sim_status check_params(const sim_params* p) {
   if (!(p->sigma_repulse > 0.f)) return fail(SIM_E_INVALID, "sigma_repulse must be positive");
   if (p->tile_side != 0 && p->tile_side != 16 && p->tile_side != 32 && p->tile_side != 64)
     return fail(SIM_E_INVALID, "tile_side must be 16, 32 or 64 (or 0 for 32)");
+  if (!(p->energy_rate >= 0.f && p->energy_rate <= 1.f)) return fail(SIM_E_INVALID, "energy_rate must be in [0, 1]");
   if (p->flags & ~(uint32_t)(SIM_SPLAT_SORTED | SIM_SPLAT_DIRECT)) return fail(SIM_E_INVALID, "unknown flag bits");
   if ((p->flags & SIM_SPLAT_SORTED) && (p->flags & SIM_SPLAT_DIRECT))
     return fail(SIM_E_INVALID, "SIM_SPLAT_SORTED and SIM_SPLAT_DIRECT are exclusive");
@@ -90,6 +91,7 @@ struct WorldBufs {
   float2* Fg = nullptr;
   float* fel = nullptr;
   float* fel_el = nullptr;
+  float* e_node = nullptr;      // [2][N] sensed energy (row 1 zero); worlds with an energy rate
   int* key = nullptr;
   int* rank = nullptr;
   int* cnt = nullptr;
@@ -124,6 +126,7 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
   b.Fg = c.take<float2>(ncell);
   b.fel = c.take<float>(2 * N);
   b.fel_el = c.take<float>(2 * N);
+  if (p.energy_rate > 0.f) b.e_node = c.take<float>(2 * N);
   const int mode = mode_of(p);
   if (mode == mc::kSorted) {
     b.key = c.take<int>(N);
@@ -160,6 +163,14 @@ struct Slot {
   float* amp = nullptr;
   float* period = nullptr;
   float* phase = nullptr;
+  float* kb = nullptr;          // optional per-edge stiffnesses [N]
+  float* ks = nullptr;
+  float* ksh = nullptr;
+  int* fil_flags = nullptr;     // optional [F] (SIM_FIL_CLOSED)
+  bool any_loop = false;
+  float* energy = nullptr;      // optional energy field [ny][nx] and its node / filament outputs
+  float* e_sensed = nullptr;
+  float* e_collected = nullptr;
   float* fbuf[2] = {nullptr, nullptr};
   float* u = nullptr;
   WorldBufs b;
@@ -212,6 +223,16 @@ mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::C
   d.act_amp = s.amp;
   d.act_period = s.period;
   d.act_phase = s.phase;
+  d.kb_arr = s.kb;
+  d.ks_arr = s.ks;
+  d.ksh_arr = s.ksh;
+  d.fil_flags = s.fil_flags;
+  const bool energy = p.energy_rate > 0.f && s.energy && s.b.e_node;
+  d.energy_rate = p.energy_rate;
+  d.energy = energy ? s.energy : nullptr;
+  d.e_node = s.b.e_node;
+  d.e_sensed = energy ? s.e_sensed : nullptr;
+  d.e_collected = energy ? s.e_collected : nullptr;
   const int src = parity == 0 ? s.cur : 1 - s.cur;
   d.f_src = s.fbuf[src];
   d.f_dst = s.fbuf[1 - src];
@@ -413,6 +434,13 @@ struct Engine {
     for (const auto& sl : slots)
       if (sl.used && mode_of(sl.p) != mc::kBinned) any_node = true;
     more = more || (any_node && !grid.any_node);
+    bool any_energy = false;
+    for (const auto& sl : slots)
+      if (sl.used && sl.p.energy_rate > 0.f && sl.energy) any_energy = true;
+    if (any_energy && !grid.any_energy) {
+      grid.any_energy = 1;
+      more = true;
+    }
     int max_r = 1;                          // the filter's LDS window is sized for this radius
     for (const auto& sl : slots)
       if (sl.used) max_r = std::max(max_r, sl.p.repulse_radius);
@@ -478,6 +506,7 @@ struct Engine {
     mc::launch_repulse(d, tab, grid, s);
     mc::launch_spread(d, tab, grid, s);
     mc::launch_lbm(d, tab, grid, s);
+    mc::launch_energy(d, tab, grid, s);
     mc::launch_integrate(d, tab, grid, s);
   }
 
@@ -590,6 +619,19 @@ sim_status read_offsets(const sim_arrays* a, hipStream_t stream, std::vector<int
   return SIM_OK;
 }
 
+// Whether any filament is a closed loop (reads the flags back: synchronous).
+sim_status read_loops(const sim_arrays* a, hipStream_t stream, bool* any) {
+  *any = false;
+  if (!a->fil_flags || a->n_filaments == 0) return SIM_OK;
+  std::vector<int> h(a->n_filaments);
+  HIPCHK(hipMemcpyAsync(h.data(), a->fil_flags, h.size() * sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  for (int v : h)
+    if (v & ~SIM_FIL_CLOSED) return fail(SIM_E_INVALID, "unknown filament flag bits");
+  for (int v : h) *any = *any || (v & SIM_FIL_CLOSED);
+  return SIM_OK;
+}
+
 sim_status check_arrays(const sim_arrays* a) {
   if (!a) return fail(SIM_E_INVALID, "arrays is NULL");
   if (a->n_particles < 0 || a->n_filaments < 0) return fail(SIM_E_INVALID, "negative sizes");
@@ -623,6 +665,7 @@ void sim_params_default(sim_params* p, int32_t nx, int32_t ny) {
   p->u_max = 0.3f;
   p->flags = 0;
   p->tile_side = 32;
+  p->energy_rate = 0.f;
 }
 
 const char* sim_last_error(void) { return g_err; }
@@ -687,6 +730,17 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   sl.amp = const_cast<float*>(a->act_amp);
   sl.period = const_cast<float*>(a->act_period);
   sl.phase = const_cast<float*>(a->act_phase);
+  sl.kb = const_cast<float*>(a->k_bend);
+  sl.ks = const_cast<float*>(a->k_stretch);
+  sl.ksh = const_cast<float*>(a->k_shear);
+  sl.fil_flags = const_cast<int*>(a->fil_flags);
+  sl.energy = a->energy;
+  sl.e_sensed = a->energy_sensed;
+  sl.e_collected = a->energy_collected;
+  if ((st = read_loops(a, s, &sl.any_loop))) {
+    delete w;
+    return st;
+  }
   carve_world_bufs(c, *p, a->n_particles, sl.b);
   sl.fbuf[0] = a->f;
   sl.fbuf[1] = sl.b.f_alt;
@@ -703,6 +757,8 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   if (sl.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, sl.b.cnt, ncell);
   if (sl.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.s, ncell);
   if (sl.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.Fg, 2 * ncell);
+  if (sl.b.e_node)
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)sl.b.e_node, 2 * (size_t)std::max(a->n_particles, 1));
   if (sl.b.bin_cnt) {
     const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
@@ -825,7 +881,10 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
       HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
       break;
     }
-    case 4: mc::launch_integrate(d, e.tab, g, e.stream); break;
+    case 4:
+      mc::launch_energy(d, e.tab, g, e.stream);
+      mc::launch_integrate(d, e.tab, g, e.stream);
+      break;
     default: return fail(SIM_E_INVALID, "unknown sub-step %d", which);
   }
   HIPCHK(hipGetLastError());
@@ -860,6 +919,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     HIPCHK(hipEventRecord(E[4], e.stream));
     mc::launch_lbm_timed(d, e.tab, e.grid, e.stream, fl[2 * k], fl[2 * k + 1]);
     HIPCHK(hipEventRecord(E[5], e.stream));
+    mc::launch_energy(d, e.tab, e.grid, e.stream);
     mc::launch_integrate(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[6], e.stream));
     HIPCHK(hipGetLastError());
@@ -1075,6 +1135,13 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   sl.amp = const_cast<float*>(a->act_amp);
   sl.period = const_cast<float*>(a->act_period);
   sl.phase = const_cast<float*>(a->act_phase);
+  sl.kb = const_cast<float*>(a->k_bend);
+  sl.ks = const_cast<float*>(a->k_stretch);
+  sl.ksh = const_cast<float*>(a->k_shear);
+  sl.fil_flags = const_cast<int*>(a->fil_flags);
+  sl.energy = a->energy;
+  sl.e_sensed = a->energy_sensed;
+  sl.e_collected = a->energy_collected;
   sl.b = L.b;
   sl.fbuf[0] = a->f;
   sl.fbuf[1] = L.b.f_alt;
@@ -1110,12 +1177,15 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   g.any_binned = mode == mc::kBinned;
   g.any_node = mode != mc::kBinned;
   g.max_radius = p->repulse_radius;
+  g.any_energy = p->energy_rate > 0.f && a->energy ? 1 : 0;
 
   // the array keeps the previous call's contents: clear what starts at zero
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, L.err, (size_t)1);
   if (L.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)L.b.Fg, 2 * ncell);
   if (L.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)L.b.s, ncell);
   if (L.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, L.b.cnt, ncell);
+  if (L.b.e_node)
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)L.b.e_node, 2 * (size_t)std::max(n_part, 1));
   if (L.b.bin_cnt) {
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_fill, nt);
@@ -1134,6 +1204,7 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   mc::launch_repulse(L.desc, tab, g, s);
   mc::launch_spread(L.desc, tab, g, s);
   mc::launch_lbm(L.desc, tab, g, s);
+  mc::launch_energy(L.desc, tab, g, s);
   mc::launch_integrate(L.desc, tab, g, s);
   hipLaunchKernelGGL(k_noalloc_copy_back, dim3(std::min<size_t>(2048, (9 * ncell + 255) / 256)), dim3(256), 0, s,
                      L.err, (const float*)L.b.f_alt, a->f, 9 * ncell);
@@ -1188,6 +1259,29 @@ sim_status sim_density_loss(const sim_splat_image* img, int32_t nx, int32_t ny, 
   if (ws_bytes < need) return fail(SIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
   mc::launch_density_loss(nx, ny, n_particles, img->width, img->height, img->sigma, img->amp, cell, frac, target,
                           image, loss, g_pos, workspace, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+sim_status sim_energy_packets(int32_t nx, int32_t ny, int32_t n_packets, const float* centres, const float* amps,
+                              const float* widths, float* field, void* stream) {
+  if (nx < 1 || ny < 1 || n_packets < 0 || !field) return fail(SIM_E_INVALID, "bad field or packet count");
+  if (n_packets == 0) return SIM_OK;
+  if (!centres || !amps || !widths) return fail(SIM_E_INVALID, "NULL packet array");
+  mc::launch_energy_packets(nx, ny, n_packets, centres, amps, widths, field, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
+sim_status sim_rest_effort(int32_t n_filaments, const int32_t* fil_offset, const int32_t* fil_flags,
+                           const float* old_rest_angle, const float* new_rest_angle, const float* old_rest_length,
+                           const float* new_rest_length, float* effort, void* stream) {
+  if (n_filaments < 0) return fail(SIM_E_INVALID, "negative filament count");
+  if (n_filaments == 0) return SIM_OK;
+  if (!fil_offset || !old_rest_angle || !new_rest_angle || !old_rest_length || !new_rest_length || !effort)
+    return fail(SIM_E_INVALID, "NULL array");
+  mc::launch_rest_effort(n_filaments, fil_offset, fil_flags, old_rest_angle, new_rest_angle, old_rest_length,
+                         new_rest_length, effort, (hipStream_t)stream);
   HIPCHK(hipGetLastError());
   return SIM_OK;
 }
@@ -1296,6 +1390,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
   if (mode_of(s.p) != mc::kBinned)
     return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
                 mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
+  if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
   if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   size_t need = 0;
   sim_backward_workspace_size(w, ckpt_every, &need);
@@ -1311,6 +1406,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
   g.any_binned = 1;
   g.any_sorted = 0;
   g.any_node = 0;
+  g.any_energy = 0;                      // the energy field does not act on the motion
 
   // per-step descriptors (identical for every segment; uploaded once)
   std::vector<mc::WorldDev> hd(L.m);
@@ -1335,6 +1431,9 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     d.ctl_src = L.ctl + j;                   // the fluid kernel of step j advances it into j + 1
     d.ctl_dst = L.ctl + j + 1;
     d.s = nullptr;
+    d.energy = nullptr;                    // the recompute leaves the world's energy field alone
+    d.e_sensed = nullptr;
+    d.e_collected = nullptr;
     hd[j] = d;
   }
   HIPCHK(hipEventSynchronize(e.upload_done));
@@ -1424,6 +1523,14 @@ void carve_batch_world(Carver& c, const sim_params& p, int n_fil, int n_part, Sl
   s.amp = c.take<float>(F);
   s.period = c.take<float>(F);
   s.phase = c.take<float>(F);
+  s.kb = c.take<float>(N);              // optional per-edge stiffnesses and filament flags:
+  s.ks = c.take<float>(N);              // pointed at only when the admitted world has them
+  s.ksh = c.take<float>(N);
+  s.fil_flags = c.take<int>(F);
+  if (p.energy_rate > 0.f) {             // energy field and collected totals live in the pool
+    s.energy = c.take<float>(ncell);
+    s.e_collected = c.take<float>(F);
+  }
   s.fbuf[0] = c.take<float>(9 * ncell);
   s.u = c.take<float>(2 * ncell);
   carve_world_bufs(c, p, n_part, s.b);
@@ -1571,6 +1678,8 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
   int max_len = 0;
   for (int f = 0; f < init->n_filaments; ++f) max_len = std::max(max_len, h_off[f + 1] - h_off[f]);
   if (max_len > e.grid.pack) return fail(SIM_E_INVALID, "batched filaments are limited to %d nodes", e.grid.pack);
+  bool any_loop = false;
+  if ((st = read_loops(init, e.stream, &any_loop))) return st;
   size_t bytes = 0;
   sim_batch_world_bytes(p, init->n_filaments, init->n_particles, &bytes);
   size_t off = 0;
@@ -1600,6 +1709,27 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
     if ((st = cp(s.amp, init->act_amp, F * 4))) return st;
     if ((st = cp(s.period, init->act_period, F * 4))) return st;
     if ((st = cp(s.phase, init->act_phase, F * 4))) return st;
+  }
+  // optional arrays: copied when given, else the slot uses the parameters
+  auto opt = [&](auto*& dst, const void* src, size_t by) -> sim_status {
+    if (!src || !by) {
+      dst = nullptr;
+      return SIM_OK;
+    }
+    return cp(dst, src, by);
+  };
+  if ((st = opt(s.kb, init->k_bend, N * 4))) return st;
+  if ((st = opt(s.ks, init->k_stretch, N * 4))) return st;
+  if ((st = opt(s.ksh, init->k_shear, N * 4))) return st;
+  if ((st = opt(s.fil_flags, init->fil_flags, F * 4))) return st;
+  if (s.energy) {
+    if (init->energy) {
+      if ((st = cp(s.energy, init->energy, ncell * 4))) return st;
+    } else {
+      hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.energy, ncell);
+    }
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)s.e_collected, std::max<size_t>(F, 1));
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)s.b.e_node, 2 * std::max<size_t>(N, 1));
   }
   if ((st = cp(s.fbuf[0], init->f, 9 * ncell * 4))) return st;
   if (s.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, s.b.cnt, ncell);
@@ -1663,6 +1793,11 @@ sim_status sim_batch_retire(sim_batch* b, int32_t slot, const sim_arrays* out) {
     }
     if (out->f) HIPCHK(hipMemcpyAsync(out->f, s.fbuf[s.cur], 9 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
     if (out->u) HIPCHK(hipMemcpyAsync(out->u, s.u, 2 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
+    if (s.energy && out->energy)
+      HIPCHK(hipMemcpyAsync(out->energy, s.energy, ncell * 4, hipMemcpyDeviceToDevice, e.stream));
+    if (s.energy && out->energy_collected && s.n_fil)
+      HIPCHK(hipMemcpyAsync(out->energy_collected, s.e_collected, (size_t)s.n_fil * 4, hipMemcpyDeviceToDevice,
+                            e.stream));
   }
   unsigned* hflag = (unsigned*)e.pinned;   // staging is idle after the event sync below
   HIPCHK(hipEventSynchronize(e.upload_done));

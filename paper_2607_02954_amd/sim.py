@@ -30,7 +30,7 @@ EXPORTS = [
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
     "sim_profile_steps", "sim_measure_atomics", "sim_step_noalloc",
-    "sim_density_loss_workspace_size", "sim_density_loss",
+    "sim_density_loss_workspace_size", "sim_density_loss", "sim_rest_effort", "sim_energy_packets",
     "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
     "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
     "sim_batch_destroy",
@@ -52,6 +52,7 @@ class SimParams(ctypes.Structure):
         ("k_elastic", ctypes.c_float), ("k_repulse", ctypes.c_float),
         ("sigma_repulse", ctypes.c_float), ("repulse_radius", ctypes.c_int32),
         ("u_max", ctypes.c_float), ("flags", ctypes.c_uint32), ("tile_side", ctypes.c_int32),
+        ("energy_rate", ctypes.c_float),
     ]
 
 
@@ -62,6 +63,9 @@ class SimArrays(ctypes.Structure):
         ("rest_angle", ctypes.c_void_p), ("rest_length", ctypes.c_void_p),
         ("act_amp", ctypes.c_void_p), ("act_period", ctypes.c_void_p), ("act_phase", ctypes.c_void_p),
         ("f", ctypes.c_void_p), ("u", ctypes.c_void_p),
+        ("k_bend", ctypes.c_void_p), ("k_stretch", ctypes.c_void_p), ("k_shear", ctypes.c_void_p),
+        ("fil_flags", ctypes.c_void_p),
+        ("energy", ctypes.c_void_p), ("energy_sensed", ctypes.c_void_p), ("energy_collected", ctypes.c_void_p),
     ]
 
 
@@ -103,6 +107,8 @@ def lib():
         "sim_step_noalloc": (i32, [P(SimParams), P(SimArrays), i64, vp, vp]),
         "sim_density_loss_workspace_size": (i32, [P(SimSplatImage), P(sz)]),
         "sim_density_loss": (i32, [P(SimSplatImage), i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "sim_rest_effort": (i32, [i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "sim_energy_packets": (i32, [i32, i32, i32, vp, vp, vp, vp, vp]),
         "sim_batch_world_bytes": (i32, [P(SimParams), i32, i32, P(sz)]),
         "sim_batch_create": (i32, [i32, vp, sz, vp, P(vp)]),
         "sim_batch_admit": (i32, [vp, P(SimParams), P(SimArrays), i64, i32, P(i32)]),
@@ -145,6 +151,7 @@ class Params:
     u_max: float = 0.3
     transfer: str = "binned"          # "binned" (default), "sorted" or "direct"
     tile: int = 32                    # grid tile side of the tile kernels: 16, 32 or 64
+    energy_rate: float = 0.0          # energy field collection rate (0: no field)
 
     def flags(self) -> int:
         return {"binned": 0, "sorted": SIM_SPLAT_SORTED, "direct": SIM_SPLAT_DIRECT}[self.transfer]
@@ -153,7 +160,7 @@ class Params:
         return SimParams(self.nx, self.ny, self.tau, self.trt_magic, self.k_bend, self.k_stretch,
                          self.k_shear, self.pbd_iters, self.k_elastic, self.k_repulse,
                          self.sigma_repulse, self.repulse_radius, self.u_max,
-                         self.flags(), self.tile)
+                         self.flags(), self.tile, self.energy_rate)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -178,11 +185,22 @@ class DeviceState:
         self.act_phase = t(w.act_phase, torch.float32)
         self.f = torch.zeros(9, self.ny, self.nx, device=dev, dtype=torch.float32)   # fluid at rest
         self.u = torch.zeros(self.ny, self.nx, 2, device=dev, dtype=torch.float32)
+        st = getattr(w, "stiffness", None)
+        self.k_bend, self.k_stretch, self.k_shear = ((None,) * 3 if st is None else
+                                                     tuple(t(k, torch.float32) for k in st))
+        closed = getattr(w, "closed", None)
+        self.fil_flags = None if closed is None else t(np.asarray(closed, dtype=np.int32), torch.int32)
+        E = getattr(w, "energy", None)
+        self.energy = None if E is None else t(E, torch.float32).reshape(self.ny, self.nx).contiguous()
+        self.energy_sensed = None if E is None else torch.zeros(self.n_part, device=dev, dtype=torch.float32)
+        self.energy_collected = None if E is None else torch.zeros(self.n_fil, device=dev, dtype=torch.float32)
 
     def arrays(self) -> SimArrays:
         return SimArrays(self.n_fil, self.n_part, _ptr(self.fil_offset), _ptr(self.cell), _ptr(self.frac),
                          _ptr(self.rest_angle), _ptr(self.rest_length), _ptr(self.act_amp),
-                         _ptr(self.act_period), _ptr(self.act_phase), _ptr(self.f), _ptr(self.u))
+                         _ptr(self.act_period), _ptr(self.act_phase), _ptr(self.f), _ptr(self.u),
+                         _ptr(self.k_bend), _ptr(self.k_stretch), _ptr(self.k_shear), _ptr(self.fil_flags),
+                         _ptr(self.energy), _ptr(self.energy_sensed), _ptr(self.energy_collected))
 
     def positions64(self) -> np.ndarray:
         return self.cell.cpu().numpy().astype(np.float64) + self.frac.cpu().numpy().astype(np.float64)
@@ -412,3 +430,31 @@ class DensityLoss(torch.autograd.Function):
     def backward(ctx, g_out):
         (g,) = ctx.saved_tensors
         return g.to(ctx.dtype) * g_out, None, None, None, None, None
+
+
+def rest_effort(state: "DeviceState", new_rest_angle: torch.Tensor, new_rest_length: torch.Tensor,
+                effort: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Bending and stretching effort ([2, F], accumulated into `effort`) of
+    replacing the world's rest angles and lengths by the new ones
+    (sim_rest_effort); the caller then writes the new values."""
+    if effort is None:
+        effort = torch.zeros(2, state.n_fil, dtype=torch.float32, device=state.f.device)
+    for t in (new_rest_angle, new_rest_length):
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.numel() == state.n_part
+    check(lib().sim_rest_effort(state.n_fil, _ptr(state.fil_offset), _ptr(state.fil_flags), _ptr(state.rest_angle),
+                                _ptr(new_rest_angle), _ptr(state.rest_length), _ptr(new_rest_length), _ptr(effort),
+                                _stream_handle(stream)))
+    return effort
+
+
+def energy_packets(nx: int, ny: int, centres: torch.Tensor, amps: torch.Tensor, widths: torch.Tensor,
+                   field: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Add Gaussian packets (centres [2, P], amps [P], widths [P], float32
+    device tensors) to a field [ny, nx] (sim_energy_packets); a new zero field
+    if none is given."""
+    if field is None:
+        field = torch.zeros(ny, nx, dtype=torch.float32, device=centres.device)
+    P = int(amps.numel())
+    check(lib().sim_energy_packets(int(nx), int(ny), P, _ptr(centres.contiguous()), _ptr(amps), _ptr(widths),
+                                   _ptr(field), _stream_handle(stream)))
+    return field

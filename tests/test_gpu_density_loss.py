@@ -5,7 +5,7 @@ the periodic seams, an image whose Gaussian window covers it whole, no nodes);
 then the objective chained with the rollout's adjoint: dL/d(rest angle) of
 the Gaussian-splatted density loss after a rollout, against the oracle's
 reverse mode (normwise relative error <= 1e-3, cosine >= 0.9999) and a
-central difference of the GPU forward along the gradient (<= 1e-2); last, the paper's folding sizes (a 1000-node
+central difference of the GPU forward along the gradient (h = 1e-2, <= 2e-2); last, the paper's folding sizes (a 1000-node
 filament, a 128 x 128 image, 250 steps) against the oracle.
 """
 import numpy as np
@@ -108,12 +108,13 @@ def test_rollout_gradient_of_density_loss_vs_oracle_and_differences():
     print(f"density loss {L:.6e} (oracle {Lr:.6e}); rest-angle gradient rel err {err:.2e} cos {cos:.6f}")
     assert abs(L - Lr) / Lr <= 1e-5 and err <= 1e-3 and cos >= 0.9999
     # central difference of the GPU forward along the gradient direction (the
-    # direction of largest change, so that FP32 rounding of the rollout stays
-    # small beside it): (L(ra + h d) - L(ra - h d)) / 2h against g . d
+    # direction of largest change): (L(ra + h d) - L(ra - h d)) / 2h against
+    # g . d.  h = 1e-2 moves the loss by ~2e-5 of its value, well above the
+    # FP32 rounding of the rollout and of the loss sum (~1e-7 of it)
     Tg = torch.tensor(T, dtype=torch.float32, device="cuda")
     d = np.zeros_like(ref)
     d[J] = ref[J] / np.linalg.norm(ref[J])
-    h = 1e-3
+    h = 1e-2
     vals = []
     for sgn in (+1, -1):
         Wp = sim.World(w, sim.Params(nx=w.nx, ny=w.ny))
@@ -127,7 +128,7 @@ def test_rollout_gradient_of_density_loss_vs_oracle_and_differences():
     gd = float(g @ d)
     print(f"directional central difference (h = {h}): {fd:.6e} against g.d {gd:.6e} "
           f"(rel err {abs(fd - gd) / abs(gd):.2e})")
-    assert abs(fd - gd) / abs(gd) <= 1e-2
+    assert abs(fd - gd) / abs(gd) <= 2e-2
 
 
 def test_folding_sizes_of_the_paper_vs_oracle():

@@ -1,0 +1,114 @@
+"""Energy field on the GPU against the FP64 oracle (Methods, Fields;
+Experiments, Neuroevolution: Gaussian packets, sensing at the node,
+collection).
+
+Packets: every cell of the field against the oracle's sum.  Steps: from the
+GPU's own state at the start of each step (shared state), the field after
+the step, each node's sensed value and each filament's collected energy
+against the oracle's energy update (relative max-norm error <= 1e-5; the
+field is FP32), in every transfer; the motion itself is unchanged by the
+field (positions and u equal to a run without it, bitwise for the binned
+transfer); the field loses what the nodes collect; a batch of energy worlds
+equals its worlds run alone.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_02954_amd import workloads as wl
+from parity_util import oracle_params, rel
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["binned", "sorted", "direct"]
+DT = torch.float64
+TOL_E = 1e-5
+
+
+def _sim():
+    from paper_2607_02954_amd import sim
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sim
+
+
+def _field(sim, w):
+    c, a, s = w.meta["packets"]
+    f = lambda v: torch.tensor(np.asarray(v), dtype=torch.float32, device="cuda")
+    E = sim.energy_packets(w.nx, w.ny, f(c), f(a), f(s))
+    ref = O.energy_packets(w.nx, w.ny, torch.tensor(c, dtype=DT), torch.tensor(a, dtype=DT), torch.tensor(s, dtype=DT))
+    return E, ref
+
+
+def test_packets_match_oracle():
+    sim = _sim()
+    w = wl.energy_world(0, nx=200, ny=150, n_fil=1)
+    E, ref = _field(sim, w)
+    torch.cuda.synchronize()
+    e = rel(E.cpu().double().numpy(), ref.numpy())
+    print(f"packets: rel err {e:.2e}")
+    assert e <= TOL_E
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_energy_steps_match_oracle(mode):
+    sim = _sim()
+    rate = 0.3
+    w = wl.energy_world(1, nx=96, ny=80, n_fil=10, length=24)
+    E, _ = _field(sim, w)
+    w.energy = E.cpu().numpy()
+    p = sim.Params(nx=w.nx, ny=w.ny, transfer=mode, energy_rate=rate)
+    W = sim.World(w, p)
+    plain = sim.World(wl.energy_world(1, nx=96, ny=80, n_fil=10, length=24), sim.Params(nx=w.nx, ny=w.ny,
+                                                                                        transfer=mode))
+    op = oracle_params(p)
+    topo = O.Topology(w.fil_offset)
+    worst = [0.0, 0.0, 0.0]
+    coll_ref = torch.zeros(w.n_filaments, dtype=DT)
+    E0 = float(W.state.energy.double().sum())
+    for t in range(20):
+        xs = torch.from_numpy(W.state.positions64())
+        Es = W.state.energy.cpu().double()
+        e_ref, c_ref, E_ref = O.energy_update(xs, Es, topo, rate, op)
+        coll_ref += c_ref
+        W.step(t)
+        plain.step(t)
+        torch.cuda.synchronize()
+        errs = [rel(W.state.energy.cpu().double().numpy(), E_ref.numpy()),
+                rel(W.state.energy_sensed.cpu().double().numpy(), e_ref.numpy()),
+                rel(W.state.energy_collected.cpu().double().numpy(), coll_ref.numpy())]
+        worst = [max(a, b) for a, b in zip(worst, errs)]
+        assert max(errs) <= TOL_E, (t, errs)
+        if mode == "binned":           # the field never acts on the motion
+            for k in ("cell", "frac", "f", "u"):
+                assert torch.equal(getattr(W.state, k), getattr(plain.state, k)), (t, k)
+    lost = E0 - float(W.state.energy.double().sum())
+    got = float(W.state.energy_collected.double().sum())
+    print(f"energy [{mode}], 20 steps: field {worst[0]:.2e} sensed {worst[1]:.2e} collected {worst[2]:.2e}; "
+          f"field lost {lost:.6e}, collected {got:.6e}")
+    assert abs(lost - got) <= 1e-4 * got
+
+
+def test_batch_of_energy_worlds_equals_alone():
+    sim = _sim()
+    from paper_2607_02954_amd import batch
+    worlds, steps = [], [20, 34, 12]
+    for i, (nx, ny) in enumerate([(64, 64), (96, 64), (128, 96)]):
+        w = wl.energy_world(10 + i, nx=nx, ny=ny, n_fil=6, length=20)
+        E, _ = _field(sim, w)
+        w.energy = E.cpu().numpy()
+        worlds.append(w)
+    p = lambda w: sim.Params(nx=w.nx, ny=w.ny, energy_rate=0.2)
+    eng = batch.BatchEngine(max_worlds=4, pool_bytes=128 << 20)
+    slots = [eng.admit(w, p(w), s) for w, s in zip(worlds, steps)]
+    while any(eng.remaining(s) > 0 for s in slots):
+        eng.advance(10)
+    for w, sl, st in zip(worlds, slots, steps):
+        got = eng.retire(sl, w)
+        W = sim.World(w, p(w))
+        W.rollout(0, st)
+        W.sync()
+        for k in ("cell", "frac", "f", "u", "energy", "energy_collected"):
+            assert torch.equal(getattr(got, k), getattr(W.state, k)), k
+    print("batched energy worlds bitwise equal to their runs alone")

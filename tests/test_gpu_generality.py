@@ -1,0 +1,148 @@
+"""Filament generality on the GPU against the FP64 oracle: closed loops (odd
+and even lengths, the third Gauss-Seidel colour), per-edge stiffness arrays
+and the bending/stretching effort (Methods, Filaments; Experiments, QD Search,
+Eqs. 5-6).
+
+Per step: e_x <= 1e-5, e_u <= 1e-4 and each step's displacement e_d <= 1e-4,
+in every transfer; a polygon loop at its rest shape feels no elastic force;
+stiffness arrays equal to the scalars change no bit; a batch of such worlds
+equals its worlds run alone; the allocation-free step equals sim_step; the
+adjoint with per-edge stiffness matches the oracle's, and worlds with loops
+are refused by sim_backward; sim_rest_effort matches the oracle's efforts.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2607_02954_amd import workloads as wl
+from parity_util import TOL_D, TOL_U, TOL_X, final_state_errors, oracle_params, rel
+from test_gpu_adjoint import _compare, _gpu_grad, _joints, _oracle_grad
+from test_gpu_parity import _rollout_compare
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["binned", "sorted", "direct"]
+
+
+def _sim():
+    from paper_2607_02954_amd import sim
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sim
+
+
+def _world(seed=0):
+    return wl.generality_world(seed, 96, 80, [30, 7, 2, 65], [9, 12, 3, 40, 25])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_loops_and_stiffness_match_oracle(mode):
+    sim = _sim()
+    E = _rollout_compare(sim, _world(1), 50, mode)
+    print(f"loops + per-edge stiffness, 50 steps [{mode}]: {E}")
+
+
+def test_polygon_loop_at_rest_feels_no_force():
+    sim = _sim()
+    for n in (7, 10):
+        c = wl.polygon_loop(n, (20.3, 17.8), 0.3)
+        w = wl._assemble(40, 40, [c], np.full(n, 2 * math.pi / n), np.ones(n), [0.0], [50.0], [0.0])
+        w.closed = np.array([True])
+        W = sim.World(w, sim.Params(nx=40, ny=40))
+        W.substep(0, 0)
+        torch.cuda.synchronize()
+        fel = W.buffer(4, (2, n)).abs().max().item()
+        print(f"polygon loop n={n} at rest: max |F_el| = {fel:.2e}")
+        assert fel < 1e-6
+
+
+def test_stiffness_arrays_equal_to_scalars_change_nothing():
+    sim = _sim()
+    w = wl.random_world(8, 80, 72, [3, 1, 40, 17, 64], amp=0.5)
+    p = sim.Params(nx=w.nx, ny=w.ny)
+    a = sim.World(w, p)
+    w2 = wl.random_world(8, 80, 72, [3, 1, 40, 17, 64], amp=0.5)
+    N = w2.n_particles
+    w2.stiffness = (np.full(N, p.k_bend, np.float32), np.full(N, p.k_stretch, np.float32),
+                    np.full(N, p.k_shear, np.float32))
+    w2.closed = np.zeros(w2.n_filaments, bool)
+    b = sim.World(w2, p)
+    a.rollout(0, 30)
+    b.rollout(0, 30)
+    torch.cuda.synchronize()
+    for k in ("cell", "frac", "f", "u"):
+        assert torch.equal(getattr(a.state, k), getattr(b.state, k)), k
+
+
+def test_batch_and_noalloc_with_loops():
+    sim = _sim()
+    from paper_2607_02954_amd import batch
+    worlds = [_world(2), wl.generality_world(3, 64, 64, [20], [11, 6]), _world(4)]
+    steps = [24, 40, 18]
+    eng = batch.BatchEngine(max_worlds=4, pool_bytes=128 << 20)
+    slots = [eng.admit(w, sim.Params(nx=w.nx, ny=w.ny), s) for w, s in zip(worlds, steps)]
+    while any(eng.remaining(s) > 0 for s in slots):
+        eng.advance(10)
+    for w, sl, st in zip(worlds, slots, steps):
+        got = eng.retire(sl, w)
+        W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny))
+        W.rollout(0, st)
+        W.sync()
+        assert all(torch.equal(getattr(got, k), getattr(W.state, k)) for k in ("cell", "frac", "f", "u"))
+        ex, ea, eu, ed = final_state_errors(w, got, oracle_params(sim.Params(nx=w.nx, ny=w.ny)), 0, st)
+        print(f"batch with loops {w.nx}x{w.ny}: e_x={ex:.2e} e_a={ea:.2e} e_u={eu:.2e} e_d={ed:.2e}")
+        assert ex <= TOL_X and eu <= TOL_U and ed <= TOL_D
+    # the allocation-free step on a world with loops and stiffness arrays
+    w = worlds[1]
+    p = sim.Params(nx=w.nx, ny=w.ny)
+    ref = sim.World(w, p)
+    st = sim.DeviceState(w, "cuda")
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    for t in range(3):
+        ref.step(t)
+        sim.step_noalloc(st, p, t, status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == sim.SIM_OK
+    assert all(torch.equal(getattr(st, k), getattr(ref.state, k)) for k in ("cell", "frac", "f", "u"))
+
+
+def test_adjoint_with_per_edge_stiffness_and_loop_refusal():
+    sim = _sim()
+    w = wl.generality_world(5, 64, 56, [12, 7, 20, 2, 30], [])
+    x0 = w.positions64()
+    target = x0 + np.random.default_rng(2).normal(0, 0.5, size=x0.shape)
+    g, _, W, p = _gpu_grad(sim, w, target, 12, 5)
+    ref, _ = _oracle_grad(w, p, target, 12, 5)
+    err, cos = _compare(g, ref, _joints(w))
+    print(f"adjoint with per-edge stiffness: rel err {err:.2e} cos {cos:.6f}")
+    assert err <= 1e-3 and cos >= 0.9999
+    wl_ = _world(6)
+    Wl = sim.World(wl_, sim.Params(nx=wl_.nx, ny=wl_.ny))
+    ck = torch.empty(Wl.checkpoint_bytes(4, 2), dtype=torch.uint8, device="cuda")
+    Wl.rollout(0, 4, 2, ck)
+    g_pos = torch.zeros(2, wl_.n_particles, dtype=torch.float32, device="cuda")
+    g_rest = torch.zeros(wl_.n_particles, dtype=torch.float32, device="cuda")
+    with pytest.raises(sim.SimError) as ei:
+        Wl.backward(0, 4, 2, ck, g_pos, g_rest)
+    assert ei.value.status == sim.SIM_E_INVALID
+
+
+def test_rest_effort_matches_oracle():
+    sim = _sim()
+    w = _world(7)
+    st = sim.DeviceState(w, "cuda")
+    rng = np.random.default_rng(4)
+    new_a = w.rest_angle + rng.normal(0, 0.1, size=w.n_particles).astype(np.float32)
+    new_l = w.rest_length + rng.normal(0, 0.05, size=w.n_particles).astype(np.float32)
+    eff = sim.rest_effort(st, torch.tensor(new_a, device="cuda"), torch.tensor(new_l, device="cuda"))
+    eff = sim.rest_effort(st, torch.tensor(new_a, device="cuda"), torch.tensor(new_l, device="cuda"), eff)
+    torch.cuda.synchronize()
+    topo = O.Topology(w.fil_offset, w.closed)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
+    ref = 2 * O.rest_effort(topo, t(w.rest_angle), t(new_a), t(w.rest_length), t(new_l))
+    e = rel(eff.cpu().double().numpy(), ref.numpy())
+    print(f"efforts (accumulated twice): rel err {e:.2e}")
+    assert e <= 1e-5
