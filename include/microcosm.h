@@ -90,6 +90,18 @@ typedef struct sim_params {
   float energy_rate;       /* energy field (sim_arrays.energy): fraction of the
                               sensed energy a node collects per step, in [0, 1];
                               0 disables the field                                 */
+  /* Leakage fixes of the coupling (Methods, Fluid-filament Interaction),
+   * with the direct transfer (SIM_SPLAT_DIRECT) only: */
+  int32_t mdf_iters;       /* multi-direct forcing iterations, 1..64 (0 or 1: the
+                              explicit coupling).  The first spreads the node
+                              forces F; each further one samples
+                              u = (j + F_grid/2)/rho at the node and spreads
+                              2 (U_d - u), U_d = (j/rho at the node) + F/2       */
+  float marker_offset;     /* two-layer broadcast: each node acts through two
+                              markers at +-marker_offset (cells, <= 1) along its
+                              normal (tangent x_next - x_prev; the edge at a
+                              chain end), half of its force at each, and moves
+                              with the mean of their velocities; 0: one layer  */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).
@@ -145,8 +157,8 @@ typedef struct sim_batch sim_batch;
 
 /* Fill *p with the defaults (tau 1, Lambda 1/4, k_bend 0.5, k_stretch 1,
  * k_shear 0.5, 4 PBD iterations, k_elastic 0.05, k_repulse 0.1, sigma 1,
- * radius 4, u_max 0.3, flags 0, tile side 32, no energy field) for an nx x ny
- * grid. */
+ * radius 4, u_max 0.3, flags 0, tile side 32, no energy field, explicit
+ * one-layer coupling) for an nx x ny grid. */
 void sim_params_default(sim_params *p, int32_t nx, int32_t ny);
 
 /* Bytes of device workspace sim_create needs for a world of this size. */

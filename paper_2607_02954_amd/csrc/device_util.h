@@ -156,6 +156,65 @@ static __device__ __forceinline__ void edge_direction(float t, float t0, float c
   }
 }
 
+// A marker displaced by (dx, dy) (|d| < 1 cell) from a node at cell (cx, cy)
+// + fraction (fx, fy): its wrapped home cell and fraction on an nx x ny grid.
+static __device__ __forceinline__ void marker_home(int c, float f, float d, int n, int* home, float* fr) {
+  const float m = f + d;
+  const float fl = floorf(m);
+  int h = c + (int)fl;
+  float r = m - fl;
+  if (r >= 1.0f) {
+    r = 0.0f;
+    h += 1;
+  }
+  *home = wrap_index(h, n);
+  *fr = r;
+}
+
+// Global float atomics of s * W(c - X) * (vx, vy) into an interleaved
+// float2 field, for a point X with wrapped home cell (bx, by) and fraction (fx, fy).
+static __device__ __forceinline__ void atomic_spread_vec(MC_GLOBAL float* field, int nx, int ny, int bx, int by,
+                                                         float fx, float fy, float vx, float vy) {
+  float wx[4], wy[4];
+  peskin4(fx, wx);
+  peskin4(fy, wy);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    MC_GLOBAL float* row = field + 2 * (size_t)wrap_near(by - 1 + b, ny) * nx;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int x = wrap_near(bx - 1 + a, nx);
+      const float ww = wx[a] * wy[b];
+      unsafeAtomicAdd((float*)(row + 2 * x), ww * vx);
+      unsafeAtomicAdd((float*)(row + 2 * x + 1), ww * vy);
+    }
+  }
+}
+
+// sum_c W(c - X) v_c of an interleaved float2 field at a point X.
+static __device__ __forceinline__ vf2 gather_vec(const MC_GLOBAL vf2* field, int nx, int ny, int bx, int by, float fx,
+                                                 float fy) {
+  float wx[4], wy[4];
+  peskin4(fx, wx);
+  peskin4(fy, wy);
+  float gx = 0.f, gy = 0.f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const MC_GLOBAL vf2* row = field + (size_t)wrap_near(by - 1 + b, ny) * nx;
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const vf2 v = row[wrap_near(bx - 1 + a, nx)];
+      ax += wx[a] * v.x;
+      ay += wx[a] * v.y;
+    }
+    gx += wy[b] * ax;
+    gy += wy[b] * ay;
+  }
+  const vf2 out = {gx, gy};
+  return out;
+}
+
 // D2Q9 lattice: velocity q has components (CX[q], CY[q]); q and q+2 are
 // opposite for q = 1, 2, 5, 6.
 static __constant__ int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};

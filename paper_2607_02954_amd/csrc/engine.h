@@ -89,6 +89,13 @@ struct WorldDev {
   float* e_node;                        // [2][N] sensed value (row 0; row 1 stays 0)
   float* e_sensed;                      // [N] caller copy of the sensed values, or null
   float* e_collected;                   // [F] accumulated collected energy, or null
+  // coupling leakage fixes (direct transfer): two-layer markers and MDF
+  int mdf_iters;                        // 1: explicit coupling
+  float marker_offset;                  // 0: one layer
+  float* d_marker;                      // [2][N] marker displacement offset * normal, or null
+  float* U_d;                           // [2][N] MDF desired node velocity
+  float4* rho_j;                        // [ny][nx] (rho, jx, jy, 0) of the step's populations
+  float2* u_mdf;                        // [ny][nx] fluid velocity of the current MDF force
   const float* f_src;  float* f_dst;    // shifted populations f - w, [9][ny][nx]
   float2* u;                            // [ny][nx] fluid velocity (x, y interleaved)
   float* s;                             // deposit accumulator [ny][nx] (direct mode)
@@ -145,6 +152,8 @@ struct Grid {
                                              // (any_node: a world not in binned mode)
   int max_radius;                            // largest Gaussian radius of any world (LDS sizing)
   int any_energy;                            // a world has an energy field
+  int any_markers;                           // a world broadcasts two-layer markers
+  int mdf_max;                               // most MDF iterations of any world (1: none)
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at
@@ -178,6 +187,10 @@ void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
 void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s, hipEvent_t start,
                       hipEvent_t stop);
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+// two-layer markers (before the force spread) and MDF corrections of the grid
+// force (after it, before the fluid update); direct-transfer worlds
+void launch_markers(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
+void launch_mdf(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 // energy field: sensing and collection at the step's starting positions
 // (between the fluid update and the integration)
 void launch_energy(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);

@@ -780,6 +780,18 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
     if (mode == kSorted) {
       const vf4 r = {fx, fy, Fx, Fy};
       glbv<vf4>(w.rec)[sl] = r;
+    } else if (mode == kDirect && w.d_marker) {
+      // two layers: half of the force from each marker
+      const float dx = glb(w.d_marker)[gi], dy = glb(w.d_marker)[N + gi];
+      const int cx = cell[gi], cy = cell[N + gi];
+#pragma unroll
+      for (int sgn = 1; sgn >= -1; sgn -= 2) {
+        int hx, hy;
+        float mx, my;
+        marker_home(cx, fx, sgn * dx, nx, &hx, &mx);
+        marker_home(cy, fy, sgn * dy, ny, &hy, &my);
+        atomic_spread_vec(glb((float*)w.Fg), nx, ny, hx, hy, mx, my, 0.5f * Fx, 0.5f * Fy);
+      }
     } else if (mode == kDirect) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -1023,6 +1035,20 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
 #pragma unroll
     for (int a = 0; a < 4; ++a) ix[a] = wrap_near(bx - 1 + a, nx);
     float dux = 0.f, duy = 0.f;
+    if (w.d_marker) {
+      // two layers: the mean of the markers' interpolated velocities
+      const float dx = glb(w.d_marker)[gi], dy = glb(w.d_marker)[N + gi];
+#pragma unroll
+      for (int sgn = 1; sgn >= -1; sgn -= 2) {
+        int hx, hy;
+        float mx, my;
+        marker_home(cx, fx, sgn * dx, nx, &hx, &mx);
+        marker_home(cy, fy, sgn * dy, ny, &hy, &my);
+        const vf2 v = gather_vec(u, nx, ny, hx, hy, mx, my);
+        dux += 0.5f * v.x;
+        duy += 0.5f * v.y;
+      }
+    } else {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const MC_GLOBAL vf2* row = u + (size_t)wrap_near(by - 1 + b, ny) * nx;
@@ -1035,6 +1061,7 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
       }
       dux += wy[b] * ax;
       duy += wy[b] * ay;
+    }
     }
     float nfx = fx + dux, nfy = fy + duy;
     const float flx = floorf(nfx), fly = floorf(nfy);
@@ -1312,6 +1339,192 @@ __global__ void k_energy_packets(int nx, int ny, int n_packets, const float* cen
   }
 }
 
+// ---------------------------------------------------------------------------
+// Coupling leakage fixes (direct transfer).  Two layers: node i is broadcast
+// as markers X = x_i +- d_i, d_i = offset * unit normal (the tangent is
+// x_next - x_prev where the node has two neighbours, the edge direction at a
+// chain end, none for a lone node).  MDF: desired node velocity
+// U_d = I2[j / rho] + F / 2; each further iteration samples
+// u = (j + F_grid / 2) / rho at the markers and spreads 2 (U_d - I2[u]).
+// ---------------------------------------------------------------------------
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_markers(const WorldDev* __restrict__ W, Tables T) {
+  __shared__ int s_off[PACK + 1];
+  const int npk = *T.n_packs;
+  const int li = threadIdx.x;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    if (!w.d_marker || w.ctl_src->remaining <= 0) continue;     // block-uniform
+    const int nf = pk.fil_end - pk.fil_begin;
+    for (int k = li; k <= nf; k += PACK) s_off[k] = glb(w.fil_offset)[pk.fil_begin + k] - pk.node_begin;
+    __syncthreads();
+    const int gi = pk.node_begin + li;
+    if (gi < pk.node_end) {
+      int lo = 0, hi = nf - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= li) lo = mid; else hi = mid - 1;
+      }
+      const int o = s_off[lo], n = s_off[lo + 1] - o, k = li - o;
+      const int fil = pk.fil_begin + lo;
+      const bool ring = w.fil_flags && (glb(w.fil_flags)[fil] & 1) && n >= 3;
+      const int first = pk.node_begin + o;
+      int a = gi, b = gi;                         // the nodes the tangent joins
+      if (k > 0) a = gi - 1; else if (ring) a = first + n - 1;
+      if (k < n - 1) b = gi + 1; else if (ring) b = first;
+      const int N = w.n_part;
+      const MC_GLOBAL int* cell = glb(w.cell_in);
+      const MC_GLOBAL float* frac = glb(w.frac_in);
+      const float tx = (float)(cell[b] - cell[a]) + (frac[b] - frac[a]);
+      const float ty = (float)(cell[N + b] - cell[N + a]) + (frac[N + b] - frac[N + a]);
+      const float len = sqrtf(tx * tx + ty * ty);
+      const float sc = len > 0.f ? w.marker_offset / len : 0.f;
+      glb(w.d_marker)[gi] = -ty * sc;
+      glb(w.d_marker)[N + gi] = tx * sc;
+    }
+    __syncthreads();
+  }
+}
+
+// (rho, j) of the step's populations (stored shifted by the weights, whose
+// first moment is zero), per cell.
+__global__ __launch_bounds__(256) void k_mdf_moments(const WorldDev* __restrict__ W, Tables T) {
+  const int nit = *T.n_items;
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    const int2 item = T.items[it];
+    const WorldDev& w = W[item.x];
+    if (w.mdf_iters <= 1 || w.ctl_src->remaining <= 0) continue;
+    const int ncell = w.nx * w.ny;
+    const int c = item.y + threadIdx.x;
+    if (c >= ncell) continue;
+    const MC_GLOBAL float* src = glb(w.f_src);
+    float g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = src[(size_t)q * ncell + c];
+    const float drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    const float jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const float jy = (g[2] - g[4]) + (g[5] - g[8]) + (g[6] - g[7]);
+    const vf4 m = {1.0f + drho, jx, jy, 0.f};
+    glbv<vf4>(w.rho_j)[c] = m;
+  }
+}
+
+// u = (j + F_grid / 2) / rho of the current grid force, per cell.
+__global__ __launch_bounds__(256) void k_mdf_velocity(const WorldDev* __restrict__ W, Tables T, int iter) {
+  const int nit = *T.n_items;
+  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+    const int2 item = T.items[it];
+    const WorldDev& w = W[item.x];
+    if (iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
+    const int ncell = w.nx * w.ny;
+    const int c = item.y + threadIdx.x;
+    if (c >= ncell) continue;
+    const vf4 m = glbv<const vf4>(w.rho_j)[c];
+    const vf2 F = glbv<const vf2>(w.Fg)[c];
+    const float inv = 1.0f / m.x;
+    const vf2 u = {(m.y + 0.5f * F.x) * inv, (m.z + 0.5f * F.y) * inv};
+    glbv<vf2>(w.u_mdf)[c] = u;
+  }
+}
+
+// Two-layer interpolation of a per-cell quantity at node gi: mean over its
+// markers (or the node itself with one layer) of sum_c W(c - X) value(c).
+template <class V>
+static __device__ __forceinline__ vf2 interp2(const WorldDev& w, int gi, V value) {
+  const int N = w.n_part, nx = w.nx, ny = w.ny;
+  const int cx = glb(w.cell_in)[gi], cy = glb(w.cell_in)[N + gi];
+  const float fx = glb(w.frac_in)[gi], fy = glb(w.frac_in)[N + gi];
+  const float dx = w.d_marker ? glb(w.d_marker)[gi] : 0.f, dy = w.d_marker ? glb(w.d_marker)[N + gi] : 0.f;
+  float sx = 0.f, sy = 0.f;
+  const int layers = w.d_marker ? 2 : 1;
+  for (int l = 0; l < layers; ++l) {
+    const float sg = l == 0 ? 1.f : -1.f;
+    int hx, hy;
+    float mx, my;
+    marker_home(cx, fx, sg * dx, nx, &hx, &mx);
+    marker_home(cy, fy, sg * dy, ny, &hy, &my);
+    float wx[4], wy[4];
+    peskin4(mx, wx);
+    peskin4(my, wy);
+    float gx = 0.f, gy = 0.f;
+    for (int b = 0; b < 4; ++b) {
+      const size_t row = (size_t)wrap_near(hy - 1 + b, ny) * nx;
+      float ax = 0.f, ay = 0.f;
+      for (int a = 0; a < 4; ++a) {
+        const vf2 v = value(row + wrap_near(hx - 1 + a, nx));
+        ax += wx[a] * v.x;
+        ay += wx[a] * v.y;
+      }
+      gx += wy[b] * ax;
+      gy += wy[b] * ay;
+    }
+    sx += gx;
+    sy += gy;
+  }
+  const float h = layers == 2 ? 0.5f : 1.0f;
+  const vf2 out = {h * sx, h * sy};
+  return out;
+}
+
+// Spread of (vx, vy) from node gi's markers (half each) or the node.
+static __device__ __forceinline__ void spread2_atomic(const WorldDev& w, int gi, float vx, float vy) {
+  const int N = w.n_part, nx = w.nx, ny = w.ny;
+  const int cx = glb(w.cell_in)[gi], cy = glb(w.cell_in)[N + gi];
+  const float fx = glb(w.frac_in)[gi], fy = glb(w.frac_in)[N + gi];
+  if (!w.d_marker) {
+    atomic_spread_vec(glb((float*)w.Fg), nx, ny, wrap_index(cx, nx), wrap_index(cy, ny), fx, fy, vx, vy);
+    return;
+  }
+  const float dx = glb(w.d_marker)[gi], dy = glb(w.d_marker)[N + gi];
+  for (int sg = 1; sg >= -1; sg -= 2) {
+    int hx, hy;
+    float mx, my;
+    marker_home(cx, fx, sg * dx, nx, &hx, &mx);
+    marker_home(cy, fy, sg * dy, ny, &hy, &my);
+    atomic_spread_vec(glb((float*)w.Fg), nx, ny, hx, hy, mx, my, 0.5f * vx, 0.5f * vy);
+  }
+}
+
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_mdf_desired(const WorldDev* __restrict__ W, Tables T) {
+  const int npk = *T.n_packs;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    if (w.mdf_iters <= 1 || w.ctl_src->remaining <= 0) continue;
+    const int gi = pk.node_begin + threadIdx.x;
+    if (gi >= pk.node_end) continue;
+    const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
+    const vf2 us = interp2(w, gi, [&](size_t c) {
+      const vf4 v = m[c];
+      const vf2 r = {v.y / v.x, v.z / v.x};
+      return r;
+    });
+    const int N = w.n_part;
+    glb(w.U_d)[gi] = us.x + 0.5f * glb(w.fel)[gi];
+    glb(w.U_d)[N + gi] = us.y + 0.5f * glb(w.fel)[N + gi];
+  }
+}
+
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_mdf_correct(const WorldDev* __restrict__ W, Tables T, int iter) {
+  const int npk = *T.n_packs;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    if (iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
+    const int gi = pk.node_begin + threadIdx.x;
+    if (gi >= pk.node_end) continue;
+    const MC_GLOBAL vf2* um = glbv<const vf2>(w.u_mdf);
+    const vf2 U = interp2(w, gi, [&](size_t c) { return um[c]; });
+    const int N = w.n_part;
+    const float cx = 2.0f * (glb(w.U_d)[gi] - U.x);
+    const float cy = 2.0f * (glb(w.U_d)[N + gi] - U.y);
+    spread2_atomic(w, gi, cx, cy);
+  }
+}
+
 __global__ void k_set_ctl(Ctl* c, long long t, int remaining) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     Ctl v;
@@ -1404,6 +1617,20 @@ void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStre
     if (G.tile_blocks[1] > 0) k_integrate_tile<32><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T);
     if (G.tile_blocks[2] > 0) k_integrate_tile<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
     k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
+  }
+}
+
+void launch_markers(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
+  if (G.any_markers) MC_PACK_DISPATCH(k_markers, G, W, T);
+}
+
+void launch_mdf(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
+  if (G.mdf_max <= 1) return;
+  k_mdf_moments<<<G.item_blocks, 256, 0, s>>>(W, T);
+  MC_PACK_DISPATCH(k_mdf_desired, G, W, T);
+  for (int iter = 1; iter < G.mdf_max; ++iter) {
+    k_mdf_velocity<<<G.item_blocks, 256, 0, s>>>(W, T, iter);
+    MC_PACK_DISPATCH(k_mdf_correct, G, W, T, iter);
   }
 }
 

@@ -77,6 +77,10 @@ sim_status check_params(const sim_params* p) {
   if (p->tile_side != 0 && p->tile_side != 16 && p->tile_side != 32 && p->tile_side != 64)
     return fail(SIM_E_INVALID, "tile_side must be 16, 32 or 64 (or 0 for 32)");
   if (!(p->energy_rate >= 0.f && p->energy_rate <= 1.f)) return fail(SIM_E_INVALID, "energy_rate must be in [0, 1]");
+  if (p->mdf_iters < 0 || p->mdf_iters > 64) return fail(SIM_E_INVALID, "mdf_iters must be in 1..64 (0 means 1)");
+  if (!(p->marker_offset >= 0.f && p->marker_offset <= 1.f)) return fail(SIM_E_INVALID, "marker_offset must be in [0, 1]");
+  if ((p->mdf_iters > 1 || p->marker_offset > 0.f) && !(p->flags & SIM_SPLAT_DIRECT))
+    return fail(SIM_E_INVALID, "multi-direct forcing and two-layer markers need SIM_SPLAT_DIRECT");
   if (p->flags & ~(uint32_t)(SIM_SPLAT_SORTED | SIM_SPLAT_DIRECT)) return fail(SIM_E_INVALID, "unknown flag bits");
   if ((p->flags & SIM_SPLAT_SORTED) && (p->flags & SIM_SPLAT_DIRECT))
     return fail(SIM_E_INVALID, "SIM_SPLAT_SORTED and SIM_SPLAT_DIRECT are exclusive");
@@ -92,6 +96,10 @@ struct WorldBufs {
   float* fel = nullptr;
   float* fel_el = nullptr;
   float* e_node = nullptr;      // [2][N] sensed energy (row 1 zero); worlds with an energy rate
+  float* d_marker = nullptr;    // [2][N] two-layer marker displacement (direct transfer)
+  float* U_d = nullptr;         // [2][N] MDF desired velocity
+  float4* rho_j = nullptr;      // [ncell] MDF moments
+  float2* u_mdf = nullptr;      // [ncell] MDF velocity
   int* key = nullptr;
   int* rank = nullptr;
   int* cnt = nullptr;
@@ -138,6 +146,12 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.part = c.take<int>((ncell + 1023) / 1024 + 1);
   } else if (mode == mc::kDirect) {
     b.s = c.take<float>(ncell);
+    if (p.marker_offset > 0.f) b.d_marker = c.take<float>(2 * N);
+    if (p.mdf_iters > 1) {
+      b.U_d = c.take<float>(2 * N);
+      b.rho_j = c.take<float4>(ncell);
+      b.u_mdf = c.take<float2>(ncell);
+    }
   } else {
     const size_t nt = n_bins(p);
     b.bin_cnt = c.take<int>(nt);
@@ -233,6 +247,12 @@ mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::C
   d.e_node = s.b.e_node;
   d.e_sensed = energy ? s.e_sensed : nullptr;
   d.e_collected = energy ? s.e_collected : nullptr;
+  d.mdf_iters = std::max(p.mdf_iters, 1);
+  d.marker_offset = p.marker_offset;
+  d.d_marker = s.b.d_marker;
+  d.U_d = s.b.U_d;
+  d.rho_j = s.b.rho_j;
+  d.u_mdf = s.b.u_mdf;
   const int src = parity == 0 ? s.cur : 1 - s.cur;
   d.f_src = s.fbuf[src];
   d.f_dst = s.fbuf[1 - src];
@@ -434,11 +454,24 @@ struct Engine {
     for (const auto& sl : slots)
       if (sl.used && mode_of(sl.p) != mc::kBinned) any_node = true;
     more = more || (any_node && !grid.any_node);
-    bool any_energy = false;
-    for (const auto& sl : slots)
-      if (sl.used && sl.p.energy_rate > 0.f && sl.energy) any_energy = true;
+    bool any_energy = false, any_markers = false;
+    int mdf_max = 1;
+    for (const auto& sl : slots) {
+      if (!sl.used) continue;
+      if (sl.p.energy_rate > 0.f && sl.energy) any_energy = true;
+      if (sl.b.d_marker) any_markers = true;
+      if (sl.b.U_d) mdf_max = std::max(mdf_max, sl.p.mdf_iters);
+    }
     if (any_energy && !grid.any_energy) {
       grid.any_energy = 1;
+      more = true;
+    }
+    if (any_markers && !grid.any_markers) {
+      grid.any_markers = 1;
+      more = true;
+    }
+    if (mdf_max > grid.mdf_max) {
+      grid.mdf_max = mdf_max;
       more = true;
     }
     int max_r = 1;                          // the filter's LDS window is sized for this radius
@@ -501,10 +534,12 @@ struct Engine {
 
   void enqueue_step_with(const mc::WorldDev* d, const mc::Grid& grid, hipStream_t s) const {
     mc::launch_elastic(d, tab, grid, s);
+    mc::launch_markers(d, tab, grid, s);
     mc::launch_sort(d, tab, grid, s);
     mc::launch_filter(d, tab, grid, s);
     mc::launch_repulse(d, tab, grid, s);
     mc::launch_spread(d, tab, grid, s);
+    mc::launch_mdf(d, tab, grid, s);
     mc::launch_lbm(d, tab, grid, s);
     mc::launch_energy(d, tab, grid, s);
     mc::launch_integrate(d, tab, grid, s);
@@ -666,6 +701,8 @@ void sim_params_default(sim_params* p, int32_t nx, int32_t ny) {
   p->flags = 0;
   p->tile_side = 32;
   p->energy_rate = 0.f;
+  p->mdf_iters = 1;
+  p->marker_offset = 0.f;
 }
 
 const char* sim_last_error(void) { return g_err; }
@@ -867,12 +904,14 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
     case 0:
       mc::launch_bin_prepass(d, e.tab, g, e.stream);
       mc::launch_elastic(d, e.tab, g, e.stream);
+      mc::launch_markers(d, e.tab, g, e.stream);
       mc::launch_sort(d, e.tab, g, e.stream);
       break;
     case 1: mc::launch_filter(d, e.tab, g, e.stream); break;
     case 2:
       mc::launch_repulse(d, e.tab, g, e.stream);
       mc::launch_spread(d, e.tab, g, e.stream);
+      mc::launch_mdf(d, e.tab, g, e.stream);
       break;
     case 3: {
       mc::launch_lbm(d, e.tab, g, e.stream);
@@ -909,6 +948,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     hipEvent_t* E = ev.data() + (size_t)k * (kGroups + 1);
     HIPCHK(hipEventRecord(E[0], e.stream));
     mc::launch_elastic(d, e.tab, e.grid, e.stream);
+    mc::launch_markers(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[1], e.stream));
     mc::launch_sort(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[2], e.stream));
@@ -916,6 +956,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
     HIPCHK(hipEventRecord(E[3], e.stream));
     mc::launch_repulse(d, e.tab, e.grid, e.stream);
     mc::launch_spread(d, e.tab, e.grid, e.stream);
+    mc::launch_mdf(d, e.tab, e.grid, e.stream);
     HIPCHK(hipEventRecord(E[4], e.stream));
     mc::launch_lbm_timed(d, e.tab, e.grid, e.stream, fl[2 * k], fl[2 * k + 1]);
     HIPCHK(hipEventRecord(E[5], e.stream));
@@ -1178,6 +1219,8 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   g.any_node = mode != mc::kBinned;
   g.max_radius = p->repulse_radius;
   g.any_energy = p->energy_rate > 0.f && a->energy ? 1 : 0;
+  g.any_markers = L.b.d_marker ? 1 : 0;
+  g.mdf_max = L.b.U_d ? std::max(p->mdf_iters, 1) : 1;
 
   // the array keeps the previous call's contents: clear what starts at zero
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, L.err, (size_t)1);
@@ -1199,10 +1242,12 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   // the step itself: the kernels sim_step runs, with parity-0 descriptors
   mc::launch_bin_prepass(L.desc, tab, g, s);
   mc::launch_elastic(L.desc, tab, g, s);
+  mc::launch_markers(L.desc, tab, g, s);
   mc::launch_sort(L.desc, tab, g, s);
   mc::launch_filter(L.desc, tab, g, s);
   mc::launch_repulse(L.desc, tab, g, s);
   mc::launch_spread(L.desc, tab, g, s);
+  mc::launch_mdf(L.desc, tab, g, s);
   mc::launch_lbm(L.desc, tab, g, s);
   mc::launch_energy(L.desc, tab, g, s);
   mc::launch_integrate(L.desc, tab, g, s);

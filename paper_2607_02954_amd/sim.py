@@ -52,7 +52,7 @@ class SimParams(ctypes.Structure):
         ("k_elastic", ctypes.c_float), ("k_repulse", ctypes.c_float),
         ("sigma_repulse", ctypes.c_float), ("repulse_radius", ctypes.c_int32),
         ("u_max", ctypes.c_float), ("flags", ctypes.c_uint32), ("tile_side", ctypes.c_int32),
-        ("energy_rate", ctypes.c_float),
+        ("energy_rate", ctypes.c_float), ("mdf_iters", ctypes.c_int32), ("marker_offset", ctypes.c_float),
     ]
 
 
@@ -152,6 +152,8 @@ class Params:
     transfer: str = "binned"          # "binned" (default), "sorted" or "direct"
     tile: int = 32                    # grid tile side of the tile kernels: 16, 32 or 64
     energy_rate: float = 0.0          # energy field collection rate (0: no field)
+    mdf_iters: int = 1                # multi-direct forcing iterations (direct transfer)
+    marker_offset: float = 0.0        # two-layer marker offset in cells (direct transfer)
 
     def flags(self) -> int:
         return {"binned": 0, "sorted": SIM_SPLAT_SORTED, "direct": SIM_SPLAT_DIRECT}[self.transfer]
@@ -160,7 +162,7 @@ class Params:
         return SimParams(self.nx, self.ny, self.tau, self.trt_magic, self.k_bend, self.k_stretch,
                          self.k_shear, self.pbd_iters, self.k_elastic, self.k_repulse,
                          self.sigma_repulse, self.repulse_radius, self.u_max,
-                         self.flags(), self.tile, self.energy_rate)
+                         self.flags(), self.tile, self.energy_rate, self.mdf_iters, self.marker_offset)
 
 
 def _ptr(t: Optional[torch.Tensor]):

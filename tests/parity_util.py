@@ -47,7 +47,8 @@ def oracle_params(p):
     return O.Params(nx=p.nx, ny=p.ny, tau=p.tau, trt_magic=p.trt_magic, k_bend=p.k_bend,
                     k_stretch=p.k_stretch, k_shear=p.k_shear, pbd_iters=p.pbd_iters,
                     k_elastic=p.k_elastic, k_repulse=p.k_repulse, sigma=p.sigma_repulse,
-                    radius=p.repulse_radius, u_max=p.u_max)
+                    radius=p.repulse_radius, u_max=p.u_max,
+                    mdf_iters=getattr(p, "mdf_iters", 1), marker_offset=getattr(p, "marker_offset", 0.0))
 
 
 def state64(st):

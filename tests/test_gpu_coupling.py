@@ -1,0 +1,79 @@
+"""Coupling leakage fixes on the GPU against the FP64 oracle (Methods,
+Fluid-filament Interaction: Multi-Direct Forcing; the filament broadcast as a
+two-layer version of itself), with the direct transfer.
+
+Per step: e_x <= 1e-5, e_u <= 1e-4 and each step's displacement e_d <= 1e-4
+from the GPU's state, for one and two layers, one to eight MDF iterations,
+chains and loops; worlds on the other transfers are refused; the
+allocation-free step and a batch give the single world's results (to the
+parity bar: the direct transfer sums with float atomics).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2607_02954_amd import workloads as wl
+from parity_util import TOL_D, TOL_U, TOL_X, disp_err, final_state_errors, oracle_params, rel
+from test_gpu_parity import _rollout_compare, ragged_world
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim():
+    from paper_2607_02954_amd import sim
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sim
+
+
+@pytest.mark.parametrize("mdf,offset", [(1, 0.5), (4, 0.0), (4, 0.5), (8, 1.0)])
+def test_mdf_and_two_layers_match_oracle(mdf, offset):
+    sim = _sim()
+    for w, n in ((ragged_world(2), 15), (wl.generality_world(3, 72, 64, [20, 2, 1], [9, 10]), 10)):
+        E = _rollout_compare(sim, w, n, "direct", mdf_iters=mdf, marker_offset=offset)
+        print(f"MDF {mdf}, offset {offset}, {w.nx}x{w.ny} N={w.n_particles}: {E}")
+
+
+def test_other_transfers_are_refused():
+    sim = _sim()
+    w = ragged_world(1)
+    for mode in ("binned", "sorted"):
+        for kw in ({"mdf_iters": 3}, {"marker_offset": 0.5}):
+            with pytest.raises(sim.SimError) as ei:
+                sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw))
+            assert ei.value.status == sim.SIM_E_INVALID
+
+
+def _close(sim, a, b, x_before):
+    xa, xb = a.positions64(), b.positions64()
+    return (rel(xa, xb), disp_err(xa - x_before, xb - x_before), rel(a.velocity64(), b.velocity64()))
+
+
+def test_noalloc_and_batch_with_mdf():
+    sim = _sim()
+    from paper_2607_02954_amd import batch
+    w = wl.random_world(5, 80, 64, [20, 9, 33], amp=0.5)
+    p = sim.Params(nx=w.nx, ny=w.ny, transfer="direct", mdf_iters=4, marker_offset=0.5)
+    ref = sim.World(w, p)
+    st = sim.DeviceState(w, "cuda")
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    for t in range(4):
+        x0 = st.positions64()
+        ref.step(t)
+        sim.step_noalloc(st, p, t, status)
+        torch.cuda.synchronize()
+        ex, ed, eu = _close(sim, st, ref.state, x0)
+        assert int(status.item()) == sim.SIM_OK and ex <= TOL_X and ed <= TOL_D and eu <= TOL_U, (t, ex, ed, eu)
+    worlds = [w, wl.generality_world(6, 64, 64, [15], [11])]
+    steps = [20, 14]
+    eng = batch.BatchEngine(max_worlds=2, pool_bytes=64 << 20)
+    slots = [eng.admit(x, sim.Params(nx=x.nx, ny=x.ny, transfer="direct", mdf_iters=4, marker_offset=0.5), s)
+             for x, s in zip(worlds, steps)]
+    while any(eng.remaining(s) > 0 for s in slots):
+        eng.advance(10)
+    for x, sl, s in zip(worlds, slots, steps):
+        got = eng.retire(sl, x)
+        op = oracle_params(sim.Params(nx=x.nx, ny=x.ny, mdf_iters=4, marker_offset=0.5))
+        ex, ea, eu, ed = final_state_errors(x, got, op, 0, s)
+        print(f"batched MDF world {x.nx}x{x.ny}, {s} steps vs oracle: e_x={ex:.2e} e_u={eu:.2e} e_d={ed:.2e}")
+        assert ex <= TOL_X and eu <= TOL_U and ed <= TOL_D
