@@ -299,6 +299,16 @@ sim_status sim_step_noalloc(const sim_params *p, const sim_arrays *a, int64_t t,
  * [2][N]).  For parity tests.  The
  * sub-steps of one step must be run in order, starting with 0. */
 sim_status sim_debug_substep(sim_world *w, int32_t which, int64_t t);
+/* Test hook: one linear sub-step of the hand-written adjoint on the world's
+ * current state, for transpose (dot-product) tests against the forward
+ * sub-steps: which 0: out [ny][nx][2] = spread of the node vector in [2][N]
+ * (the transpose of the velocity gather; binned worlds, after sub-step 0 of
+ * the step); 1: out [ny][nx] = the Gaussian filter applied to the transpose of
+ * the central difference of in [ny][nx][2]; 2: out [9][ny][nx] = the
+ * transposed Jacobian of the fluid update (collision and streaming, at the
+ * world's populations and grid force) applied to in [9][ny][nx]; scratch: 16
+ * bytes per cell.  Device pointers; enqueued on the world's stream. */
+sim_status sim_debug_adjoint(sim_world *w, int32_t which, const void *in, void *out, void *scratch);
 sim_status sim_debug_buffer(sim_world *w, int32_t which, void **ptr);
 
 /* Measurement hook: run n_steps ordinary steps from time index t0 (kernels

@@ -532,6 +532,18 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     if ((G).tile_blocks[2] > 0) KERNEL<64><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
   } while (0)
 
+// Single linear adjoint sub-steps, for transpose (dot-product) tests:
+// 0: out = S[v] (spread of a node vector, the transpose of the gather);
+// 1: A.sbar = G D^T A.Gbar (filter and central difference transposed);
+// 2: A.gbar = J^T A.gbar_in at the world's populations and grid force (the
+//    collision and streaming Jacobian transposed; A.ubar must be zero).
+void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int which, const AdjDev& A,
+                          const float* v, float2* out, hipStream_t s) {
+  if (which == 0) MC_ADJ_TILES(k_adj_spread, G, W, T, v, 0.f, out);
+  else if (which == 1) MC_ADJ_TILES(k_adj_filter, G, W, T, A);
+  else k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
+}
+
 void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s) {
   MC_ADJ_TILES(k_adj_spread, G, W, T, A.xbar_in, 0.f, A.ubar);
   k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);

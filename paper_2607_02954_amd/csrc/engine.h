@@ -173,6 +173,8 @@ struct AdjDev {
 };
 
 void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s);
+void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int which, const AdjDev& A,
+                          const float* v, float2* out, hipStream_t s);
 
 // Forward step launchers (kernels.hip).  `W` points at a device array of
 // world descriptors.

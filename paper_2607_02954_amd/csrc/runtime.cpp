@@ -988,6 +988,30 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
   return SIM_OK;
 }
 
+sim_status sim_debug_adjoint(sim_world* w, int32_t which, const void* in, void* out, void* scratch) {
+  if (!w || !in || !out) return fail(SIM_E_INVALID, "NULL argument");
+  Engine& e = w->eng;
+  const Slot& s = e.slots[0];
+  if (which == 0 && mode_of(s.p) != mc::kBinned) return fail(SIM_E_INVALID, "the spread transpose needs bins");
+  if (which == 2 && !scratch) return fail(SIM_E_INVALID, "scratch is needed");
+  if (which < 0 || which > 2) return fail(SIM_E_INVALID, "unknown adjoint sub-step %d", which);
+  const size_t ncell = (size_t)s.p.nx * s.p.ny;
+  mc::AdjDev A{};
+  if (which == 1) {
+    A.Gbar = (float2*)const_cast<void*>(in);
+    A.sbar = (float*)out;
+  } else if (which == 2) {
+    A.gbar_in = (const float*)in;
+    A.gbar = (float*)out;
+    A.ubar = (float2*)scratch;
+    A.Fgbar = (float2*)scratch + ncell;
+    hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)scratch, 2 * ncell);
+  }
+  mc::launch_adjoint_debug(e.desc[0], e.tab, e.grid, which, A, (const float*)in, (float2*)out, e.stream);
+  HIPCHK(hipGetLastError());
+  return SIM_OK;
+}
+
 sim_status sim_debug_buffer(sim_world* w, int32_t which, void** ptr) {
   if (!w || !ptr) return fail(SIM_E_INVALID, "NULL argument");
   const Slot& s = w->eng.slots[0];

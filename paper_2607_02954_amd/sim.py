@@ -29,7 +29,7 @@ EXPORTS = [
     "sim_params_default", "sim_workspace_size", "sim_create", "sim_step", "sim_rollout",
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
-    "sim_profile_steps", "sim_measure_atomics", "sim_step_noalloc",
+    "sim_profile_steps", "sim_measure_atomics", "sim_step_noalloc", "sim_debug_adjoint",
     "sim_density_loss_workspace_size", "sim_density_loss", "sim_rest_effort", "sim_energy_packets",
     "sim_batch_world_bytes", "sim_batch_create", "sim_batch_admit", "sim_batch_advance",
     "sim_batch_remaining", "sim_batch_retire", "sim_batch_sync", "sim_batch_set_tuning",
@@ -102,6 +102,7 @@ def lib():
         "sim_last_error": (ctypes.c_char_p, []),
         "sim_debug_substep": (i32, [vp, i32, i64]),
         "sim_debug_buffer": (i32, [vp, i32, P(vp)]),
+        "sim_debug_adjoint": (i32, [vp, i32, vp, vp, vp]),
         "sim_profile_steps": (i32, [vp, i64, i32, P(ctypes.c_float)]),
         "sim_measure_atomics": (i32, [vp, sz, vp, P(ctypes.c_double)]),
         "sim_step_noalloc": (i32, [P(SimParams), P(SimArrays), i64, vp, vp]),
@@ -288,18 +289,24 @@ class World:
     def substep(self, which: int, t: int):
         check(lib().sim_debug_substep(self.handle, int(which), int(t)))
 
-    def buffer(self, which: int, shape, dtype=torch.float32) -> torch.Tensor:
-        """A torch view (copy) of an internal per-step buffer, for tests."""
+    def adjoint_substep(self, which: int, x: torch.Tensor, out: torch.Tensor,
+                        scratch: Optional[torch.Tensor] = None):
+        """One linear adjoint sub-step (see sim_debug_adjoint), for tests."""
+        check(lib().sim_debug_adjoint(self.handle, int(which), _ptr(x), _ptr(out), _ptr(scratch)))
+
+    def buffer_view(self, which: int, shape, dtype=torch.float32) -> torch.Tensor:
+        """A torch view (no copy) of an internal per-step buffer, for tests."""
         p = ctypes.c_void_p()
         check(lib().sim_debug_buffer(self.handle, int(which), ctypes.byref(p)))
         n = int(np.prod(shape))
-        out = torch.empty(n, dtype=dtype, device=self.workspace.device)
-        base = self.workspace.data_ptr()
-        off = p.value - base
-        assert 0 <= off and off + n * out.element_size() <= self.workspace.numel()
-        src = self.workspace[off:off + n * out.element_size()].view(dtype)
-        out.copy_(src)
-        return out.reshape(shape)
+        size = n * torch.empty(0, dtype=dtype).element_size()
+        off = p.value - self.workspace.data_ptr()
+        assert 0 <= off and off + size <= self.workspace.numel()
+        return self.workspace[off:off + size].view(dtype).reshape(shape)
+
+    def buffer(self, which: int, shape, dtype=torch.float32) -> torch.Tensor:
+        """A copy of an internal per-step buffer, for tests."""
+        return self.buffer_view(which, shape, dtype).clone()
 
     def close(self):
         if getattr(self, "handle", None):
