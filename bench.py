@@ -253,7 +253,7 @@ def bench_adjoint(seed, reps=5):
         "backward_ms": bm,
         "bwd_over_fwd": bm / fm,
         "bwd_over_plain_fwd": bm / pm,
-        "loss": float(loss),
+        "loss": float(loss.detach()),
     }
 
 
@@ -292,7 +292,7 @@ def bench_density_folding(seed, reps=3):
         "workload": "density folding: one 1000-node filament on 256x256, 250 steps, checkpoints every 25, "
                     "loss = MSE of the Gaussian-splatted density (128x128 image, sigma 2 cells) to a seeded "
                     "target image, gradient in the rest angles",
-        "forward_ms": fm, "backward_ms": bm, "bwd_over_fwd": bm / fm, "loss": float(loss),
+        "forward_ms": fm, "backward_ms": bm, "bwd_over_fwd": bm / fm, "loss": float(loss.detach()),
         "grad_norm": float(ra.grad.norm()),
     }
 

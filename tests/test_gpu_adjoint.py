@@ -43,7 +43,7 @@ def _gpu_grad(sim, w, target, n, k, **kw):
     loss = ((xT - tgt) ** 2).sum() / xT.shape[1]
     loss.backward()
     torch.cuda.synchronize()
-    return ra.grad.cpu().numpy(), float(loss), W, p
+    return ra.grad.cpu().numpy(), float(loss.detach()), W, p
 
 
 def _oracle_grad(w, p, target, n, k):
