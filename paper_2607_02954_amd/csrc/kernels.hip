@@ -46,7 +46,9 @@ namespace mc {
 // node's record in its home-tile bin (binned), home-cell key and rank
 // (sorted) or the density deposit with global atomics (direct).
 // ---------------------------------------------------------------------------
-template <int PACK>
+// GEN: worlds may pass closed-loop flags and per-edge stiffness arrays; the
+// plain variant serves open chains with the world's scalar stiffnesses.
+template <int PACK, bool GEN>
 __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W, Tables T) {
   __shared__ float s_th[PACK];
   __shared__ float s_dx[PACK];
@@ -83,9 +85,9 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     const float L_r = glb(w.rest_length)[gic];
     const float ra = glb(w.rest_angle)[gic];
     // per-edge stiffnesses (joint and edge at this node), else the world's
-    const float kb_i = w.kb_arr ? glb(w.kb_arr)[gic] : w.k_bend;
-    const float ks_i = w.ks_arr ? glb(w.ks_arr)[gic] : w.k_stretch;
-    const float ksh_i = w.ksh_arr ? glb(w.ksh_arr)[gic] : w.k_shear;
+    const float kb_i = GEN && w.kb_arr ? glb(w.kb_arr)[gic] : w.k_bend;
+    const float ks_i = GEN && w.ks_arr ? glb(w.ks_arr)[gic] : w.k_stretch;
+    const float ksh_i = GEN && w.ksh_arr ? glb(w.ksh_arr)[gic] : w.k_shear;
     if (li < nf) s_off[li] = off_a - pk.node_begin;
     if (li == 0) s_off[nf] = off_b - pk.node_begin;
     __syncthreads();
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     // a closed loop (at least three nodes): the last node's edge joins it to
     // the first, and every node is a joint (the first between the closing
     // edge and edge 0)
-    const bool ring = w.fil_flags && (glb(w.fil_flags)[fil] & 1) && n >= 3;
+    const bool ring = GEN && w.fil_flags && (glb(w.fil_flags)[fil] & 1) && n >= 3;
     const bool has_edge = active && (k < n - 1 || ring);
     const bool is_joint = active && (ring || (k >= 1 && k <= n - 2));
     const int j = ring ? k : k - 1;              // joint's local index
@@ -121,7 +123,8 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     // joint and the last edge meet the first ones and take a third colour
     const int jcol = (ring && (n & 1) && j == n - 1) ? 2 : (j & 1);
     const int ecol = (ring && (n & 1) && k == n - 1) ? 2 : (k & 1);
-    const int ncol = __syncthreads_or(active && ring && (n & 1)) ? 3 : 2;   // block-uniform
+    int ncol = 2;                                // block-uniform
+    if constexpr (GEN) ncol = __syncthreads_or(active && ring && (n & 1)) ? 3 : 2;
     const float amp = glb(w.act_amp)[fil], period = glb(w.act_period)[fil], phase = glb(w.act_phase)[fil];
 
     const int cx = active ? c0x : 0, cy = active ? c0y : 0;
@@ -1547,7 +1550,17 @@ __global__ void k_set_ctl(Ctl* c, long long t, int remaining) {
   } while (0)
 
 void launch_elastic(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  MC_PACK_DISPATCH(k_elastic, G, W, T);
+  if (G.general) {
+    if (G.pack == 256)
+      k_elastic<256, true><<<G.node_blocks, 256, 0, s>>>(W, T);
+    else
+      k_elastic<1024, true><<<G.node_blocks, 1024, 0, s>>>(W, T);
+  } else {
+    if (G.pack == 256)
+      k_elastic<256, false><<<G.node_blocks, 256, 0, s>>>(W, T);
+    else
+      k_elastic<1024, false><<<G.node_blocks, 1024, 0, s>>>(W, T);
+  }
 }
 
 void launch_bin_prepass(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {

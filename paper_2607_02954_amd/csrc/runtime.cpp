@@ -194,6 +194,10 @@ struct Slot {
   bool needs_zero = false;   // cnt must be cleared before first use
 };
 
+// Whether a world needs the general elastic kernel: it passes loop flags or
+// per-edge stiffness arrays (their presence decides, not their contents).
+bool slot_general(const Slot& s) { return s.fil_flags || s.kb || s.ks || s.ksh; }
+
 // Device descriptor of a world whose buffers are described by s; parity 0
 // reads populations buffer s.cur, parity 1 the other one.
 mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::Ctl* ctl_dst, unsigned* flags) {
@@ -472,6 +476,13 @@ struct Engine {
     }
     if (mdf_max > grid.mdf_max) {
       grid.mdf_max = mdf_max;
+      more = true;
+    }
+    bool general = false;
+    for (const auto& sl : slots)
+      if (sl.used && slot_general(sl)) general = true;
+    if (general && !grid.general) {         // stays set once a world needed it
+      grid.general = 1;
       more = true;
     }
     int max_r = 1;                          // the filter's LDS window is sized for this radius
@@ -1245,6 +1256,7 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   g.any_energy = p->energy_rate > 0.f && a->energy ? 1 : 0;
   g.any_markers = L.b.d_marker ? 1 : 0;
   g.mdf_max = L.b.U_d ? std::max(p->mdf_iters, 1) : 1;
+  g.general = slot_general(sl) ? 1 : 0;
 
   // the array keeps the previous call's contents: clear what starts at zero
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, L.err, (size_t)1);
