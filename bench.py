@@ -17,6 +17,7 @@ bounded sample of host-CPU work.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -354,6 +355,106 @@ def cpu_baseline(world, sample_steps, single_steps):
     }
 
 
+def bench_widened(world, seed, tile, steps, warmup):
+    """The coupling, field and topology extensions timed against the plain
+    step on the same worlds (ms/step over `steps` captured steps each):
+
+    * MDF and two-layer markers (direct transfer): a quarter of the
+      million-node workload's nodes (262,144: lengths U{16..256}) on the same
+      2048^2 grid, with explicit coupling, with 4 MDF iterations, and with 4
+      iterations on two markers offset 0.5 cells along the normal; 100 steps
+      each (at the full workload's density the MDF iteration diverges where
+      markers crowd, a limit of the method);
+    * energy field (binned transfer): the same workload with a field of 4096
+      Gaussian packets (amplitudes U(0.5, 2), widths U(3, 12) cells) that the
+      nodes deplete at rate 0.05 per step;
+    * topology generality (binned): the workload with per-edge stiffness
+      arrays U(0.2, 1), and a world of chains plus closed loops (lengths
+      U{16..64}, 10% of the nodes) of the same size with stiffness arrays;
+      plus one rest-effort reduction (the descriptors of a rest-value change)
+      over the million nodes."""
+    from dataclasses import replace as dc_replace
+    N = world.n_particles
+    base = sim.Params(nx=world.nx, ny=world.ny, tile=tile)
+    out = {}
+
+    def timed(w, p, n, label):
+        W = sim.World(w, p)
+        secs = time_rollout(W, warmup, n)
+        W.close()
+        del W
+        torch.cuda.empty_cache()
+        ms = 1000.0 * secs / n
+        log(f"widened {label}: {ms:.4f} ms/step")
+        return {"ms_per_step": ms, "value": w.n_particles * n / secs}
+
+    # MDF and two-layer markers, direct transfer
+    wq = wl.random_world(seed, world.nx, world.ny, wl.scaling_lengths(seed, N // 4), amp=0.5)
+    direct = dc_replace(base, transfer="direct")
+    rows = {"binned_explicit": timed(wq, base, 100, "quarter binned explicit"),
+            "explicit": timed(wq, direct, 100, "quarter direct explicit"),
+            "mdf4": timed(wq, dc_replace(direct, mdf_iters=4), 100, "quarter direct mdf4"),
+            "mdf4_two_layer": timed(wq, dc_replace(direct, mdf_iters=4, marker_offset=0.5), 100,
+                                    "quarter direct mdf4 two layers")}
+    for k in ("mdf4", "mdf4_two_layer"):
+        rows[k]["over_explicit"] = rows[k]["ms_per_step"] / rows["explicit"]["ms_per_step"]
+    out["coupling"] = dict(workload=f"{wq.n_particles} nodes (lengths U{{16..256}}) on {wq.nx}x{wq.ny}, "
+                                    "100 steps", **rows)
+
+    # energy field, binned transfer
+    g = np.random.default_rng(seed + 104729)
+    P = 4096
+    c = torch.tensor(g.uniform(0.0, 1.0, size=(2, P)) * np.array([[world.nx], [world.ny]]), dtype=torch.float32,
+                     device="cuda")
+    a = torch.tensor(g.uniform(0.5, 2.0, size=P), dtype=torch.float32, device="cuda")
+    wd = torch.tensor(g.uniform(3.0, 12.0, size=P), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = sim.energy_packets(world.nx, world.ny, c, a, wd)
+    torch.cuda.synchronize()
+    packets_ms = 1000.0 * (time.perf_counter() - t0)
+    plain = timed(world, base, steps, "binned plain")
+    we = copy.copy(world)
+    we.energy = E.cpu().numpy()
+    del E
+    field = timed(we, dc_replace(base, energy_rate=0.05), steps, "binned energy")
+    out["energy"] = {"workload": f"scaling workload, binned, {P} packets, rate 0.05", "plain": plain, "field": field,
+                     "over_plain": field["ms_per_step"] / plain["ms_per_step"], "packets_build_ms": packets_ms}
+
+    # topology generality, binned transfer
+    ws = copy.copy(world)
+    ws.stiffness = tuple(g.uniform(0.2, 1.0, size=N).astype(np.float32) for _ in range(3))
+    stiff = timed(ws, base, steps, "binned per-edge stiffness")
+    n_loop = N // 10
+    loops = []
+    while n_loop - sum(loops) >= 64 + 16:
+        loops.append(int(g.integers(16, 65)))
+    loops.append(n_loop - sum(loops))            # 16..79 nodes
+    wg = wl.generality_world(seed, world.nx, world.ny, wl.scaling_lengths(seed, N - sum(loops)), loops)
+    gen = timed(wg, base, steps, "binned loops + stiffness")
+    dev = sim.DeviceState(ws, "cuda")
+    ra2 = dev.rest_angle + 0.01
+    rl2 = dev.rest_length * 1.01
+    sim.rest_effort(dev, ra2, rl2)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(10):
+        sim.rest_effort(dev, ra2, rl2)
+    ev[1].record()
+    torch.cuda.synchronize()
+    eff_ms = ev[0].elapsed_time(ev[1]) / 10
+    del dev
+    torch.cuda.empty_cache()
+    out["topology"] = {"workload": "scaling workload; loops world: same node count, 10% of the nodes in loops "
+                                   f"({len(loops)} loops of U{{16..64}} nodes)",
+                       "plain": plain, "per_edge_stiffness": stiff, "loops_and_stiffness": gen,
+                       "stiffness_over_plain": stiff["ms_per_step"] / plain["ms_per_step"],
+                       "loops_over_plain": gen["ms_per_step"] / plain["ms_per_step"],
+                       "rest_effort_ms": eff_ms}
+    return out
+
+
 def bench_small_configs(seed, steps_c1, steps_c2, cpu_c1, cpu_c2, with_cpu):
     """The parity configuration (one 32-node chain on 64^2) and the uniform
     population (1024 chains x 64 nodes on 512^2, active bending): particle-
@@ -397,6 +498,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-widened", action="store_true",
+                    help="skip the coupling, energy-field and topology extensions")
     ap.add_argument("--pool-gib", type=float, default=8.0, help="HBM budget of the served pool")
     ap.add_argument("--tune-steps", type=int, default=20)
     ap.add_argument("--tile", type=int, default=0, choices=[0, 16, 32, 64],
@@ -535,6 +638,9 @@ def main():
         log("differentiation done")
         out["density_folding"] = bench_density_folding(args.seed)
         log("density folding done")
+    if not args.no_widened:
+        out["widened"] = bench_widened(world, args.seed, tile, args.steps, args.warmup)
+        log("widened rows done")
     if not args.no_served:
         out["batched_served"] = bench_served(args.seed, args.pool_gib, args.tune_steps)
         log("served done")
