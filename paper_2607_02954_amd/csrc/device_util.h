@@ -596,8 +596,9 @@ static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x
 // to w.fel.  The gradient sum runs in the same order as the repulsion gather
 // of the node kernels, so the forces are the same.  With LIST, `bins` names
 // one range of records that the tile needs, every one of them (its spread
-// list), so they skip the keep test.
-template <int TILE, bool REP, bool LIST = false>
+// list), so they skip the keep test.  SCALAR spreads scale * v[i] alone into
+// s_x (s_y is not touched and may be null).
+template <int TILE, bool REP, bool LIST = false, bool SCALAR = false>
 static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw, int th,
                                        const MC_GLOBAL float* v, float scale, long long* s_x,
                                        long long* s_y, vi4* s_list, const MC_GLOBAL vi4* recs,
@@ -647,7 +648,7 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
       }
     } else {
       Vx = scale * v[r.w];
-      Vy = scale * v[N + r.w];
+      Vy = SCALAR ? 0.f : scale * v[N + r.w];
     }
     unsigned long long* px = (unsigned long long*)(s_x + dy * kSpreadSide + dx);
     unsigned long long* py = (unsigned long long*)(s_y + dy * kSpreadSide + dx);
@@ -663,7 +664,8 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           atomicAdd(px + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ax[a] * wy[b]));
-          atomicAdd(py + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
+          if constexpr (!SCALAR)
+            atomicAdd(py + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
         }
     } else {
 #pragma unroll
@@ -672,7 +674,8 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
         for (int a = 0; a < 4; ++a) {
           const float ww = wx[a] * wy[b];
           atomicAdd(px + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vx * kFixScale));
-          atomicAdd(py + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
+          if constexpr (!SCALAR)
+            atomicAdd(py + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
         }
     }
   };

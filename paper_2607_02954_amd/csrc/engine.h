@@ -86,7 +86,7 @@ struct WorldDev {
   // `energy_rate` per step and taken out of the field
   float energy_rate; int pad3;
   float* energy;                        // [ny][nx] persistent field
-  float* e_node;                        // [2][N] sensed value (row 0; row 1 stays 0)
+  float* e_node;                        // [N] sensed value
   float* e_sensed;                      // [N] caller copy of the sensed values, or null
   float* e_collected;                   // [F] accumulated collected energy, or null
   // coupling leakage fixes (direct transfer): two-layer markers and MDF

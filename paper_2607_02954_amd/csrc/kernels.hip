@@ -1259,7 +1259,6 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_energy_deplete(cons
   using C = TileCfg<TILE>;
   constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells, kSpreadCap = C::kSpreadCap;
   __shared__ __align__(16) long long s_x[kSpreadCells];
-  __shared__ __align__(16) long long s_y[kSpreadCells];
   __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
   const int nt = n_tiles<TILE>(T);
   const XcdLoop tiles(nt);
@@ -1271,7 +1270,6 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_energy_deplete(cons
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
     zero_lds_u64(s_x, kSpreadCells);
-    zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
     const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
     const int cnt = glb(w.sp_cnt)[tix];
@@ -1282,11 +1280,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_energy_deplete(cons
       f.n = 1;
       f.b0 = tix * kSpreadCap;
       f.len = __lane_id() == 0 ? cnt : 0;
-      tile_spread_vec<TILE, false, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, s_y, s_list,
-                                         glbv<const vi4>(w.sp_rec), f, nullptr);
+      tile_spread_vec<TILE, false, true, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, nullptr,
+                                               s_list, glbv<const vi4>(w.sp_rec), f, nullptr);
     } else {
-      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, s_y, s_list,
-                                   glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+      tile_spread_vec<TILE, false, false, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, nullptr,
+                                                s_list, glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0),
+                                                nullptr);
     }
     __syncthreads();
     MC_GLOBAL float* E = glb(w.energy);

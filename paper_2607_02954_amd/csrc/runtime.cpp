@@ -95,7 +95,7 @@ struct WorldBufs {
   float2* Fg = nullptr;
   float* fel = nullptr;
   float* fel_el = nullptr;
-  float* e_node = nullptr;      // [2][N] sensed energy (row 1 zero); worlds with an energy rate
+  float* e_node = nullptr;      // [N] sensed energy; worlds with an energy rate
   float* d_marker = nullptr;    // [2][N] two-layer marker displacement (direct transfer)
   float* U_d = nullptr;         // [2][N] MDF desired velocity
   float4* rho_j = nullptr;      // [ncell] MDF moments
@@ -134,7 +134,7 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
   b.Fg = c.take<float2>(ncell);
   b.fel = c.take<float>(2 * N);
   b.fel_el = c.take<float>(2 * N);
-  if (p.energy_rate > 0.f) b.e_node = c.take<float>(2 * N);
+  if (p.energy_rate > 0.f) b.e_node = c.take<float>(N);
   const int mode = mode_of(p);
   if (mode == mc::kSorted) {
     b.key = c.take<int>(N);
@@ -806,7 +806,7 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   if (sl.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.s, ncell);
   if (sl.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.Fg, 2 * ncell);
   if (sl.b.e_node)
-    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)sl.b.e_node, 2 * (size_t)std::max(a->n_particles, 1));
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)sl.b.e_node, (size_t)std::max(a->n_particles, 1));
   if (sl.b.bin_cnt) {
     const size_t nt = n_bins(*p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
@@ -1264,7 +1264,7 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   if (L.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)L.b.s, ncell);
   if (L.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, L.b.cnt, ncell);
   if (L.b.e_node)
-    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)L.b.e_node, 2 * (size_t)std::max(n_part, 1));
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)L.b.e_node, (size_t)std::max(n_part, 1));
   if (L.b.bin_cnt) {
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, L.b.bin_fill, nt);
@@ -1810,7 +1810,7 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
       hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, (int*)s.energy, ncell);
     }
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)s.e_collected, std::max<size_t>(F, 1));
-    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)s.b.e_node, 2 * std::max<size_t>(N, 1));
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, e.stream, (int*)s.b.e_node, std::max<size_t>(N, 1));
   }
   if ((st = cp(s.fbuf[0], init->f, 9 * ncell * 4))) return st;
   if (s.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, e.stream, s.b.cnt, ncell);
