@@ -90,18 +90,20 @@ typedef struct sim_params {
   float energy_rate;       /* energy field (sim_arrays.energy): fraction of the
                               sensed energy a node collects per step, in [0, 1];
                               0 disables the field                                 */
-  /* Leakage fixes of the coupling (Methods, Fluid-filament Interaction),
-   * with the direct transfer (SIM_SPLAT_DIRECT) only: */
+  /* Leakage fixes of the coupling (Methods, Fluid-filament Interaction): */
   int32_t mdf_iters;       /* multi-direct forcing iterations, 1..64 (0 or 1: the
                               explicit coupling).  The first spreads the node
                               forces F; each further one samples
                               u = (j + F_grid/2)/rho at the node and spreads
-                              2 (U_d - u), U_d = (j/rho at the node) + F/2       */
-  float marker_offset;     /* two-layer broadcast: each node acts through two
-                              markers at +-marker_offset (cells, <= 1) along its
-                              normal (tangent x_next - x_prev; the edge at a
-                              chain end), half of its force at each, and moves
-                              with the mean of their velocities; 0: one layer  */
+                              2 (U_d - u), U_d = (j/rho at the node) + F/2.
+                              The tile-binned and the direct transfer; not with
+                              SIM_SPLAT_SORTED; sim_backward refuses it.       */
+  float marker_offset;     /* two-layer broadcast (SIM_SPLAT_DIRECT only): each
+                              node acts through two markers at +-marker_offset
+                              (cells, <= 1) along its normal (tangent
+                              x_next - x_prev; the edge at a chain end), half
+                              of its force at each, and moves with the mean of
+                              their velocities; 0: one layer                   */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).

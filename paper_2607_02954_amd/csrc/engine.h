@@ -94,6 +94,7 @@ struct WorldDev {
   float marker_offset;                  // 0: one layer
   float* d_marker;                      // [2][N] marker displacement offset * normal, or null
   float* U_d;                           // [2][N] MDF desired node velocity
+  float* mdf_c;                         // [2][N] MDF correction per node (binned transfer)
   float4* rho_j;                        // [ny][nx] (rho, jx, jy, 0) of the step's populations
   float2* u_mdf;                        // [ny][nx] fluid velocity of the current MDF force
   const float* f_src;  float* f_dst;    // shifted populations f - w, [9][ny][nx]

@@ -1418,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_mdf_velocity(const WorldDev* __restrict
   for (int it = blockIdx.x; it < nit; it += gridDim.x) {
     const int2 item = T.items[it];
     const WorldDev& w = W[item.x];
-    if (iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
+    if (w.mode == kBinned || iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
     const int ncell = w.nx * w.ny;
     const int c = item.y + threadIdx.x;
     if (c >= ncell) continue;
@@ -1494,7 +1494,7 @@ __global__ __launch_bounds__(PACK) void k_mdf_desired(const WorldDev* __restrict
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
-    if (w.mdf_iters <= 1 || w.ctl_src->remaining <= 0) continue;
+    if (w.mode == kBinned || w.mdf_iters <= 1 || w.ctl_src->remaining <= 0) continue;
     const int gi = pk.node_begin + threadIdx.x;
     if (gi >= pk.node_end) continue;
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
@@ -1515,7 +1515,7 @@ __global__ __launch_bounds__(PACK) void k_mdf_correct(const WorldDev* __restrict
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
-    if (iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
+    if (w.mode == kBinned || iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
     const int gi = pk.node_begin + threadIdx.x;
     if (gi >= pk.node_end) continue;
     const MC_GLOBAL vf2* um = glbv<const vf2>(w.u_mdf);
@@ -1524,6 +1524,130 @@ __global__ __launch_bounds__(PACK) void k_mdf_correct(const WorldDev* __restrict
     const float cx = 2.0f * (glb(w.U_d)[gi] - U.x);
     const float cy = 2.0f * (glb(w.U_d)[N + gi] - U.y);
     spread2_atomic(w, gi, cx, cy);
+  }
+}
+
+// Binned transfer (one layer): the node passes of MDF as tile passes over
+// the home-tile bins, and the correction spread through the tiles' spread
+// lists, summed in LDS as 64-bit fixed point like the force spread:
+// deterministic and without HBM atomics.
+//   k_mdf_gather_tile<TILE, true>   U_d = I[j / rho] + F / 2 at the tile's nodes
+//   k_mdf_gather_tile<TILE, false>  c = 2 (U_d - I[(j + F_grid / 2) / rho])
+//   k_mdf_spread_tile<TILE>         F_grid += S[c] over the tile
+// The velocity is formed per staged cell from the moments and the grid force.
+template <int TILE, bool DESIRED>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_gather_tile(const WorldDev* __restrict__ W, Tables T,
+                                                                             int iter) {
+  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kIt = (kStage * kStage + kThreads - 1) / kThreads;
+  __shared__ vf2 s_u[kStage * kStage];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    if (w.mode != kBinned || w.mdf_iters <= 1 || (!DESIRED && iter >= w.mdf_iters) || w.ctl_src->remaining <= 0)
+      continue;
+    const int nx = w.nx, ny = w.ny, N = w.n_part;
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
+    const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
+    const MC_GLOBAL vf2* Fg = glbv<const vf2>(w.Fg);
+    vf4 mv[kIt];
+    vf2 fv[kIt];
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
+      const int k = min((int)threadIdx.x + kThreads * i, kStage * kStage - 1);
+      const int r = k / kStage, c = k - (k / kStage) * kStage;
+      const size_t idx = (size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx);
+      mv[i] = m[idx];
+      if (!DESIRED) fv[i] = Fg[idx];
+    }
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {
+      const int k = (int)threadIdx.x + kThreads * i;
+      if (k < kStage * kStage) {
+        const float inv = 1.0f / mv[i].x;
+        vf2 u;
+        if (DESIRED) {
+          u.x = mv[i].y / mv[i].x;
+          u.y = mv[i].z / mv[i].x;
+        } else {
+          u.x = (mv[i].y + 0.5f * fv[i].x) * inv;
+          u.y = (mv[i].z + 0.5f * fv[i].y) * inv;
+        }
+        s_u[k] = u;
+      }
+    }
+    __syncthreads();
+    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
+    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
+    MC_GLOBAL float* Ud = glb(w.U_d);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
+      const vi4 r = recs[e];
+      const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
+      float wx[4], wy[4];
+      peskin4(__int_as_float(r.y), wx);
+      peskin4(__int_as_float(r.z), wy);
+      const vf2 g = gather_staged<TILE>(s_u, lx, ly, wx, wy);
+      const int gi = r.w;
+      if (DESIRED) {
+        Ud[gi] = g.x + 0.5f * glb(w.fel)[gi];
+        Ud[N + gi] = g.y + 0.5f * glb(w.fel)[N + gi];
+      } else {
+        glb(w.mdf_c)[gi] = 2.0f * (Ud[gi] - g.x);
+        glb(w.mdf_c)[N + gi] = 2.0f * (Ud[N + gi] - g.y);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_spread_tile(const WorldDev* __restrict__ W, Tables T,
+                                                                             int iter) {
+  using C = TileCfg<TILE>;
+  constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells, kSpreadCap = C::kSpreadCap;
+  __shared__ __align__(16) long long s_fx[kSpreadCells];
+  __shared__ __align__(16) long long s_fy[kSpreadCells];
+  __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    if (w.mode != kBinned || iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
+    const int nx = w.nx, ny = w.ny;
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
+    const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
+    zero_lds_u64(s_fx, kSpreadCells);
+    zero_lds_u64(s_fy, kSpreadCells);
+    __syncthreads();
+    const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int cnt = glb(w.sp_cnt)[tix];
+    if (cnt >= 0 && cnt <= kSpreadCap) {
+      BinFetch f;
+      f.n = 1;
+      f.b0 = tix * kSpreadCap;
+      f.len = __lane_id() == 0 ? cnt : 0;
+      tile_spread_vec<TILE, false, true>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
+                                         glbv<const vi4>(w.sp_rec), f, nullptr);
+    } else {
+      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
+                                   glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+    }
+    __syncthreads();
+    MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
+    for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
+      const int ly = k >> C::kShift, lx = k & (TILE - 1);
+      if (lx >= tw || ly >= th) continue;
+      const size_t c = (size_t)(y0 + ly) * nx + x0 + lx;
+      vf2 F = Fg[c];
+      F.x += fix_to_float(spread_cell<TILE>(s_fx, lx, ly, nx, ny));
+      F.y += fix_to_float(spread_cell<TILE>(s_fy, lx, ly, nx, ny));
+      Fg[c] = F;
+    }
+    __syncthreads();
   }
 }
 
@@ -1636,13 +1760,37 @@ void launch_markers(const WorldDev* W, const Tables& T, const Grid& G, hipStream
   if (G.any_markers) MC_PACK_DISPATCH(k_markers, G, W, T);
 }
 
+// Binned MDF tile passes, once per tile family present.
+#define MC_TILE_DISPATCH(KERNEL, G, ...)                                                             \
+  do {                                                                                               \
+    if ((G).tile_blocks[0] > 0) KERNEL<16><<<(G).tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(__VA_ARGS__); \
+    if ((G).tile_blocks[1] > 0) KERNEL<32><<<(G).tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(__VA_ARGS__); \
+    if ((G).tile_blocks[2] > 0) KERNEL<64><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
+  } while (0)
+
 void launch_mdf(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.mdf_max <= 1) return;
   k_mdf_moments<<<G.item_blocks, 256, 0, s>>>(W, T);
-  MC_PACK_DISPATCH(k_mdf_desired, G, W, T);
+  if (G.any_node) MC_PACK_DISPATCH(k_mdf_desired, G, W, T);
+  if (G.any_binned) {
+    if (G.tile_blocks[0] > 0) k_mdf_gather_tile<16, true><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T, 0);
+    if (G.tile_blocks[1] > 0) k_mdf_gather_tile<32, true><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T, 0);
+    if (G.tile_blocks[2] > 0) k_mdf_gather_tile<64, true><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T, 0);
+  }
   for (int iter = 1; iter < G.mdf_max; ++iter) {
-    k_mdf_velocity<<<G.item_blocks, 256, 0, s>>>(W, T, iter);
-    MC_PACK_DISPATCH(k_mdf_correct, G, W, T, iter);
+    if (G.any_node) {
+      k_mdf_velocity<<<G.item_blocks, 256, 0, s>>>(W, T, iter);
+      MC_PACK_DISPATCH(k_mdf_correct, G, W, T, iter);
+    }
+    if (G.any_binned) {
+      if (G.tile_blocks[0] > 0)
+        k_mdf_gather_tile<16, false><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T, iter);
+      if (G.tile_blocks[1] > 0)
+        k_mdf_gather_tile<32, false><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T, iter);
+      if (G.tile_blocks[2] > 0)
+        k_mdf_gather_tile<64, false><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T, iter);
+      MC_TILE_DISPATCH(k_mdf_spread_tile, G, W, T, iter);
+    }
   }
 }
 

@@ -79,8 +79,10 @@ sim_status check_params(const sim_params* p) {
   if (!(p->energy_rate >= 0.f && p->energy_rate <= 1.f)) return fail(SIM_E_INVALID, "energy_rate must be in [0, 1]");
   if (p->mdf_iters < 0 || p->mdf_iters > 64) return fail(SIM_E_INVALID, "mdf_iters must be in 1..64 (0 means 1)");
   if (!(p->marker_offset >= 0.f && p->marker_offset <= 1.f)) return fail(SIM_E_INVALID, "marker_offset must be in [0, 1]");
-  if ((p->mdf_iters > 1 || p->marker_offset > 0.f) && !(p->flags & SIM_SPLAT_DIRECT))
-    return fail(SIM_E_INVALID, "multi-direct forcing and two-layer markers need SIM_SPLAT_DIRECT");
+  if (p->marker_offset > 0.f && !(p->flags & SIM_SPLAT_DIRECT))
+    return fail(SIM_E_INVALID, "two-layer markers need SIM_SPLAT_DIRECT");
+  if (p->mdf_iters > 1 && (p->flags & SIM_SPLAT_SORTED))
+    return fail(SIM_E_INVALID, "multi-direct forcing needs the binned or the direct transfer");
   if (p->flags & ~(uint32_t)(SIM_SPLAT_SORTED | SIM_SPLAT_DIRECT)) return fail(SIM_E_INVALID, "unknown flag bits");
   if ((p->flags & SIM_SPLAT_SORTED) && (p->flags & SIM_SPLAT_DIRECT))
     return fail(SIM_E_INVALID, "SIM_SPLAT_SORTED and SIM_SPLAT_DIRECT are exclusive");
@@ -98,6 +100,7 @@ struct WorldBufs {
   float* e_node = nullptr;      // [N] sensed energy; worlds with an energy rate
   float* d_marker = nullptr;    // [2][N] two-layer marker displacement (direct transfer)
   float* U_d = nullptr;         // [2][N] MDF desired velocity
+  float* mdf_c = nullptr;       // [2][N] MDF correction per node (binned transfer)
   float4* rho_j = nullptr;      // [ncell] MDF moments
   float2* u_mdf = nullptr;      // [ncell] MDF velocity
   int* key = nullptr;
@@ -161,6 +164,11 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.tile_rng = c.take<int2>((size_t)tiles_x(p) * tiles_y(p) * 2 * mc::kRunStride);
     b.sp_rec = c.take<int4>((size_t)tiles_x(p) * tiles_y(p) * mc::spread_cap_of_side(tile_side(p)));
     b.sp_cnt = c.take<int>((size_t)tiles_x(p) * tiles_y(p));
+    if (p.mdf_iters > 1) {
+      b.U_d = c.take<float>(2 * N);
+      b.mdf_c = c.take<float>(2 * N);
+      b.rho_j = c.take<float4>(ncell);
+    }
   }
 }
 
@@ -255,6 +263,7 @@ mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::C
   d.marker_offset = p.marker_offset;
   d.d_marker = s.b.d_marker;
   d.U_d = s.b.U_d;
+  d.mdf_c = s.b.mdf_c;
   d.rho_j = s.b.rho_j;
   d.u_mdf = s.b.u_mdf;
   const int src = parity == 0 ? s.cur : 1 - s.cur;
@@ -1472,6 +1481,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
                 mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
   if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
+  if (s.p.mdf_iters > 1) return fail(SIM_E_INVALID, "sim_backward does not differentiate multi-direct forcing");
   if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   size_t need = 0;
   sim_backward_workspace_size(w, ckpt_every, &need);

@@ -153,7 +153,7 @@ class Params:
     transfer: str = "binned"          # "binned" (default), "sorted" or "direct"
     tile: int = 32                    # grid tile side of the tile kernels: 16, 32 or 64
     energy_rate: float = 0.0          # energy field collection rate (0: no field)
-    mdf_iters: int = 1                # multi-direct forcing iterations (direct transfer)
+    mdf_iters: int = 1                # multi-direct forcing iterations (binned or direct transfer)
     marker_offset: float = 0.0        # two-layer marker offset in cells (direct transfer)
 
     def flags(self) -> int:

@@ -1,12 +1,15 @@
 """Coupling leakage fixes on the GPU against the FP64 oracle (Methods,
 Fluid-filament Interaction: Multi-Direct Forcing; the filament broadcast as a
-two-layer version of itself), with the direct transfer.
+two-layer version of itself): MDF on the direct and the tile-binned
+transfer, two layers on the direct transfer.
 
 Per step: e_x <= 1e-5, e_u <= 1e-4 and each step's displacement e_d <= 1e-4
 from the GPU's state, for one and two layers, one to eight MDF iterations,
-chains and loops; worlds on the other transfers are refused; the
-allocation-free step and a batch give the single world's results (to the
-parity bar: the direct transfer sums with float atomics).
+every tile side, chains and loops; the combinations that are not built are
+refused (MDF on the sorted transfer, two layers off the direct transfer, the
+adjoint of MDF); the allocation-free step and a batch of direct and binned
+MDF worlds give the single world's results (to the parity bar: the direct
+transfer sums with float atomics).
 """
 import numpy as np
 import pytest
@@ -26,22 +29,30 @@ def _sim():
     return sim
 
 
-@pytest.mark.parametrize("mdf,offset", [(1, 0.5), (4, 0.0), (4, 0.5), (8, 1.0)])
-def test_mdf_and_two_layers_match_oracle(mdf, offset):
+@pytest.mark.parametrize("mode,mdf,offset,tile", [("direct", 1, 0.5, 32), ("direct", 4, 0.0, 32),
+                                                  ("direct", 4, 0.5, 32), ("direct", 8, 1.0, 32),
+                                                  ("binned", 4, 0.0, 32), ("binned", 8, 0.0, 16),
+                                                  ("binned", 3, 0.0, 64)])
+def test_mdf_and_two_layers_match_oracle(mode, mdf, offset, tile):
     sim = _sim()
     for w, n in ((ragged_world(2), 15), (wl.generality_world(3, 72, 64, [20, 2, 1], [9, 10]), 10)):
-        E = _rollout_compare(sim, w, n, "direct", mdf_iters=mdf, marker_offset=offset)
-        print(f"MDF {mdf}, offset {offset}, {w.nx}x{w.ny} N={w.n_particles}: {E}")
+        E = _rollout_compare(sim, w, n, mode, mdf_iters=mdf, marker_offset=offset, tile=tile)
+        print(f"MDF {mdf}, offset {offset} [{mode}, tile {tile}], {w.nx}x{w.ny} N={w.n_particles}: {E}")
 
 
-def test_other_transfers_are_refused():
+def test_unbuilt_combinations_are_refused():
     sim = _sim()
     w = ragged_world(1)
-    for mode in ("binned", "sorted"):
-        for kw in ({"mdf_iters": 3}, {"marker_offset": 0.5}):
-            with pytest.raises(sim.SimError) as ei:
-                sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw))
-            assert ei.value.status == sim.SIM_E_INVALID
+    for mode, kw in (("sorted", {"mdf_iters": 3}), ("sorted", {"marker_offset": 0.5}),
+                     ("binned", {"marker_offset": 0.5}), ("binned", {"mdf_iters": 3, "marker_offset": 0.5})):
+        with pytest.raises(sim.SimError) as ei:
+            sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw))
+        assert ei.value.status == sim.SIM_E_INVALID
+    W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny, mdf_iters=3))
+    ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.raises(sim.SimError) as ei:
+        sim.Rollout.apply(ra, W, 0, 4, 2).sum().backward()
+    assert ei.value.status == sim.SIM_E_INVALID
 
 
 def _close(sim, a, b, x_before):
@@ -64,16 +75,17 @@ def test_noalloc_and_batch_with_mdf():
         torch.cuda.synchronize()
         ex, ed, eu = _close(sim, st, ref.state, x0)
         assert int(status.item()) == sim.SIM_OK and ex <= TOL_X and ed <= TOL_D and eu <= TOL_U, (t, ex, ed, eu)
-    worlds = [w, wl.generality_world(6, 64, 64, [15], [11])]
-    steps = [20, 14]
-    eng = batch.BatchEngine(max_worlds=2, pool_bytes=64 << 20)
-    slots = [eng.admit(x, sim.Params(nx=x.nx, ny=x.ny, transfer="direct", mdf_iters=4, marker_offset=0.5), s)
-             for x, s in zip(worlds, steps)]
+    worlds = [w, wl.generality_world(6, 64, 64, [15], [11]), wl.random_world(7, 72, 56, [12, 30], amp=0.5)]
+    steps = [20, 14, 16]
+    kws = [dict(transfer="direct", mdf_iters=4, marker_offset=0.5), dict(transfer="direct", mdf_iters=4, marker_offset=0.5),
+           dict(transfer="binned", mdf_iters=5)]
+    eng = batch.BatchEngine(max_worlds=3, pool_bytes=64 << 20)
+    slots = [eng.admit(x, sim.Params(nx=x.nx, ny=x.ny, **kw), s) for x, s, kw in zip(worlds, steps, kws)]
     while any(eng.remaining(s) > 0 for s in slots):
         eng.advance(10)
-    for x, sl, s in zip(worlds, slots, steps):
+    for x, sl, s, kw in zip(worlds, slots, steps, kws):
         got = eng.retire(sl, x)
-        op = oracle_params(sim.Params(nx=x.nx, ny=x.ny, mdf_iters=4, marker_offset=0.5))
+        op = oracle_params(sim.Params(nx=x.nx, ny=x.ny, mdf_iters=kw["mdf_iters"], marker_offset=kw.get("marker_offset", 0.0)))
         ex, ea, eu, ed = final_state_errors(x, got, op, 0, s)
         print(f"batched MDF world {x.nx}x{x.ny}, {s} steps vs oracle: e_x={ex:.2e} e_u={eu:.2e} e_d={ed:.2e}")
         assert ex <= TOL_X and eu <= TOL_U and ed <= TOL_D
