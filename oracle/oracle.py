@@ -65,8 +65,9 @@ class Params:
 
 
 # ---------------------------------------------------------------------------
-# Filament topology (Methods, Filaments: nodes joined by edges; filaments "can
-# be extended to have loops ... with a graph representation")
+# Filament topology (Methods, Filaments: filaments extend to loops and
+# branches through a graph representation; Discussion: topologies are cactus
+# graphs)
 # ---------------------------------------------------------------------------
 
 class Topology:
@@ -82,9 +83,21 @@ class Topology:
     (edge: e - o_f; joint: i - o_f - 1 on chains, i - o_f on loops) for
     two-colour Gauss-Seidel sweeps; on a loop of odd length the last edge
     and the last joint (which meet the first ones) get a third colour.
+
+    Branches (reading; the paper gives no equations for them): an open
+    filament f with ``parent[f] = p >= 0`` hangs from node p of an earlier
+    filament through an attachment edge from p to f's first node c0, with
+    rest length ``attach[0, f]``, a joint at p between p's entering edge
+    (prev[p]: p is a node of a loop or a non-first node of a chain) and the
+    attachment edge (rest angle ``attach[1, f]``), and a joint at c0
+    between the attachment edge and f's edge 0 (rest angle ``attach[2, f]``,
+    if f has two nodes or more).  A node carries at most one attached
+    filament, so every graph is a cactus of chains and loops whose branch
+    points have degree three.  The attachment joints are not actuated; the
+    attachment constraints use the world's scalar stiffnesses.
     """
 
-    def __init__(self, fil_offset, closed=None):
+    def __init__(self, fil_offset, closed=None, parent=None, attach=None):
         off = np.asarray(fil_offset, dtype=np.int64)
         self.fil_offset = off
         self.n_filaments = len(off) - 1
@@ -136,6 +149,35 @@ class Topology:
         jo = np.array(joints, dtype=np.int64)
         self.edge_sets = [t(ed[ec == c]) for c in range(3)]
         self.joint_sets = [t(jo[jc == c]) for c in range(3)]
+        # attachments (branches), one per child filament, in filament order
+        par = np.full(self.n_filaments, -1, dtype=np.int64) if parent is None else np.asarray(parent, np.int64)
+        att = np.zeros((3, self.n_filaments)) if attach is None else np.asarray(attach, dtype=np.float64)
+        kids = [f for f in range(self.n_filaments) if par[f] >= 0]
+        used = set()
+        for f in kids:
+            pn = int(par[f])
+            pf = int(fil_of_node[pn]) if 0 <= pn < self.n else -1
+            if not 0 <= pf < f:
+                raise ValueError(f"filament {f}: its parent node must lie in an earlier filament")
+            if closed[f]:
+                raise ValueError(f"filament {f}: a closed loop cannot hang from a parent node")
+            ring_p = bool(closed[pf]) and off[pf + 1] - off[pf] >= 3
+            if not ring_p and pn == off[pf]:
+                raise ValueError(f"filament {f}: its parent node has no entering edge")
+            if pn in used:
+                raise ValueError(f"node {pn} carries two attached filaments")
+            used.add(pn)
+        kid = np.array(kids, dtype=np.int64)
+        self.att_fil = t(kids)
+        self.att_parent = t(par[kid])                      # node p
+        self.att_child = t(off[kid])                       # node c0
+        self.att_in = t(prv[par[kid]])                     # p's entering edge (its node index)
+        self.att_length = torch.from_numpy(att[0, kid].copy())
+        self.att_angle_parent = torch.from_numpy(att[1, kid].copy())
+        self.att_angle_child = torch.from_numpy(att[2, kid].copy())
+        has_edge0 = (off[kid + 1] - off[kid]) >= 2
+        self.att_joint_child = t(kid[has_edge0].tolist())  # attachments with a joint at c0
+        self.att_joint_child_idx = t(np.nonzero(has_edge0)[0].tolist())
 
 
 # ---------------------------------------------------------------------------
@@ -209,21 +251,64 @@ def position_pass(y, theta, edges, rest_length, k_stretch, k_shear, nxt=None):
     return y.index_add(1, edges, dx).index_add(1, other, -dx)               # Eq. 4
 
 
+def attachment_angles(y, topo: Topology):
+    """Angle of every attachment edge p -> c0."""
+    v = y[:, topo.att_child] - y[:, topo.att_parent]
+    return torch.atan2(v[1], v[0])
+
+
+def bend_attachments(theta, th_att, topo: Topology, k_bend):
+    """Eq. 1 at the attachment joints: first at every parent node (edges:
+    p's entering edge, then the attachment edge), then at every child's
+    first node (the attachment edge, then the child's edge 0)."""
+    if topo.att_parent.numel() == 0:
+        return theta, th_att
+    a = topo.att_in
+    c = wrap_angle(th_att - theta[a]) - topo.att_angle_parent
+    theta = theta.index_add(0, a, 0.5 * k_bend * c)
+    th_att = th_att - 0.5 * k_bend * c
+    i, e = topo.att_joint_child_idx, topo.att_child[topo.att_joint_child_idx]
+    if i.numel():
+        c = wrap_angle(theta[e] - th_att[i]) - topo.att_angle_child[i]
+        th_att = th_att.index_add(0, i, 0.5 * k_bend * c)
+        theta = theta.index_add(0, e, -0.5 * k_bend * c)
+    return theta, th_att
+
+
+def position_attachments(y, th_att, topo: Topology, k_stretch, k_shear):
+    """Eqs. 2-4 on every attachment edge p -> c0."""
+    if topo.att_parent.numel() == 0:
+        return y
+    a, b = topo.att_parent, topo.att_child
+    v = y[:, b] - y[:, a]
+    ell = torch.sqrt(v[0] * v[0] + v[1] * v[1])
+    L = topo.att_length
+    c_stretch = (ell - L) * v / ell
+    d = torch.stack([torch.cos(th_att), torch.sin(th_att)])
+    dx = 0.5 * k_stretch * (c_stretch + k_shear * (v - L * d - c_stretch))
+    return y.index_add(1, a, dx).index_add(1, b, -dx)
+
+
 def pbd_project(x, topo: Topology, theta_hat, rest_length, p: Params, iters=None, stiff=None):
-    """K iterations of (bend: colours 0, 1, 2; position: colours 0, 1, 2) from y = x.
+    """K iterations of (bend: colours 0, 1, 2, then the attachment joints;
+    position: colours 0, 1, 2, then the attachment edges) from y = x.
 
     ``stiff``: optional per-node (k_bend, k_stretch, k_shear) tensors (the
-    paper's per-edge stiffnesses), else the scalars of p.  Returns the
-    projected positions y and the edge angles theta."""
+    paper's per-edge stiffnesses), else the scalars of p (the attachments
+    always take the scalars).  Returns the projected positions y and the
+    edge angles theta."""
     iters = p.pbd_iters if iters is None else iters
     kb, ks, ksh = (p.k_bend, p.k_stretch, p.k_shear) if stiff is None else stiff
     y = x
     theta = edge_angles(y, topo)
+    th_att = attachment_angles(y, topo)
     for _ in range(iters):
         for js in topo.joint_sets:
             theta = bend_pass(theta, js, theta_hat, kb, topo.joint_prev)
+        theta, th_att = bend_attachments(theta, th_att, topo, p.k_bend)
         for es in topo.edge_sets:
             y = position_pass(y, theta, es, rest_length, ks, ksh, topo.edge_next)
+        y = position_attachments(y, th_att, topo, p.k_stretch, p.k_shear)
     return y, theta
 
 
@@ -535,7 +620,8 @@ def inputs_from_world(w) -> Inputs:
     t = lambda a: torch.from_numpy(np.asarray(a).astype(np.float64))
     stiff = getattr(w, "stiffness", None)
     return Inputs(
-        topo=Topology(w.fil_offset, getattr(w, "closed", None)),
+        topo=Topology(w.fil_offset, getattr(w, "closed", None), getattr(w, "parent", None),
+                      getattr(w, "attach", None)),
         rest_angle=t(w.rest_angle),
         rest_length=t(w.rest_length),
         amp=t(w.act_amp),
