@@ -150,6 +150,26 @@ typedef struct sim_arrays {
   float *energy_sensed;       /* [N] out, may be NULL: e of the last step              */
   float *energy_collected;    /* [F] ACCUMULATED, may be NULL: energy collected per
                                  filament (caller zeroes)                              */
+  /* Optional branches (Methods, Filaments: loops and branches with a graph
+   * representation; Discussion: cactus graphs).  NULL: no filament hangs
+   * from another.  Filament f with fil_parent[f] = p >= 0 hangs from node p
+   * of an earlier filament of its creature through an attachment edge from
+   * p to f's first node c0.  Each iteration of the PBD projection then runs,
+   * after the regular colours of the bending pass, Eq. 1 at p (between p's
+   * entering edge and the attachment edge) and then at c0 (between the
+   * attachment edge and f's edge 0), and after the regular colours of the
+   * position pass, Eqs. 2-4 on the attachment edge; these take the scalar
+   * stiffnesses of sim_params and are not actuated.  Rules (SIM_E_INVALID
+   * otherwise): p lies in an earlier filament, and every filament between
+   * that one and f also hangs from a node (a creature is contiguous); p has
+   * an entering edge (a node of a loop, or not the first node of a chain);
+   * f is not a closed loop; a node carries at most one filament; a
+   * creature holds at most 1024 nodes (sim_batch_admit: the batch's pack
+   * capacity).  sim_backward and sim_step_noalloc refuse branched worlds. */
+  const int32_t *fil_parent;  /* [F] node filament f hangs from, or -1             */
+  const float *fil_attach;    /* [3][F] per filament: attachment rest length, rest
+                                 angle at p, rest angle at c0 (ignored for
+                                 filaments that hang from no node)                  */
 } sim_arrays;
 
 enum { SIM_FIL_CLOSED = 1 };

@@ -82,6 +82,9 @@ struct WorldDev {
   const float* act_amp; const float* act_period; const float* act_phase;
   const float* kb_arr; const float* ks_arr; const float* ksh_arr;   // [N] per-edge stiffnesses, or null
   const int* fil_flags;                 // [F] bit 0: closed loop, or null (all chains)
+  const int* fil_parent;                // [F] node filament f hangs from (-1: none), or null
+  const float* fil_attach;              // [3][F] attachment rest length, rest angle at the
+                                        // parent node, rest angle at the first node
   // energy field (null energy: none): sensed at the nodes, collected at
   // `energy_rate` per step and taken out of the field
   float energy_rate; int pad3;

@@ -46,13 +46,23 @@ namespace mc {
 // node's record in its home-tile bin (binned), home-cell key and rank
 // (sorted) or the density deposit with global atomics (direct).
 // ---------------------------------------------------------------------------
-// GEN: worlds may pass closed-loop flags and per-edge stiffness arrays; the
-// plain variant serves open chains with the world's scalar stiffnesses.
+// GEN: worlds may pass closed-loop flags, per-edge stiffness arrays and
+// branches; the plain variant serves open chains with the world's scalar
+// stiffnesses.
+//
+// Branches: the first node c0 of a filament that hangs from node p (of the
+// same pack: packs hold whole creatures) owns the attachment edge p -> c0,
+// whose angle lives in s_ta at c0's slot, and its two joints; after the
+// regular colours of each pass come the joints at the parent nodes, then
+// those at the first nodes (bending), and the attachment edges (position).
+// A node carries at most one attachment, so each of those phases touches
+// every angle and node once at most.
 template <int PACK, bool GEN>
 __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W, Tables T) {
   __shared__ float s_th[PACK];
   __shared__ float s_dx[PACK];
   __shared__ float s_dy[PACK];
+  __shared__ float s_ta[GEN ? PACK : 1];
   __shared__ int s_off[PACK + 1];
 
   const int npk = *T.n_packs;
@@ -148,7 +158,41 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     s_th[li] = th;
     s_dx[li] = 0.f;
     s_dy[li] = 0.f;
+    // branch attachment owned by this node (its filament's first node)
+    bool att = false, att_cj = false, any_att = false;
+    int p_l = 0, in_l = 0;
+    float a_vx = 0.f, a_vy = 0.f, a_th = 0.f, a_ux = 1.f, a_uy = 0.f, a_L = 0.f, a_al = 0.f, a_be = 0.f;
+    if constexpr (GEN) {
+      const int par = (w.fil_parent && active && k == 0) ? glb(w.fil_parent)[fil] : -1;
+      att = par >= 0;
+      if (att) {
+        p_l = par - pk.node_begin;
+        int lp = 0, hp = nf - 1;                   // p's filament: largest f with s_off[f] <= p_l
+        while (lp < hp) {
+          const int mid = (lp + hp + 1) >> 1;
+          if (s_off[mid] <= p_l) lp = mid; else hp = mid - 1;
+        }
+        in_l = p_l == s_off[lp] ? s_off[lp + 1] - 1 : p_l - 1;   // p's entering edge
+        const int F = w.n_fil;
+        a_L = glb(w.fil_attach)[fil];
+        a_al = glb(w.fil_attach)[F + fil];
+        a_be = glb(w.fil_attach)[2 * F + fil];
+        a_vx = (float)(cx - cell[par]) + (fx - frac[par]);
+        a_vy = (float)(cy - cell[N + par]) + (fy - frac[N + par]);
+        a_th = atan2f(a_vy, a_vx);
+        const float l0 = hw_sqrt(a_vx * a_vx + a_vy * a_vy);
+        if (l0 > 0.f) {
+          const float il = hw_rcp(l0);
+          a_ux = a_vx * il;
+          a_uy = a_vy * il;
+        }
+        att_cj = n >= 2;
+      }
+      s_ta[li] = a_th;
+      any_att = __syncthreads_or(att);
+    }
     __syncthreads();
+    const float hb_w = 0.5f * w.k_bend, hs_w = 0.5f * w.k_stretch, ksh_w = w.k_shear;
 
     const float hb = 0.5f * kb_i;
     const float hs = 0.5f * ks_i;
@@ -163,6 +207,22 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           const float c = wrap_angle(t2 - t1) - th_hat;
           s_th[li_prev] = t1 + hb * c;
           s_th[li] = t2 - hb * c;
+        }
+        __syncthreads();
+      }
+      if (GEN && any_att) {                      // attachment joints: at p, then at c0
+        if (att) {
+          const float t1 = s_th[in_l], t2 = s_ta[li];
+          const float c = wrap_angle(t2 - t1) - a_al;
+          s_th[in_l] = t1 + hb_w * c;
+          s_ta[li] = t2 - hb_w * c;
+        }
+        __syncthreads();
+        if (att_cj) {
+          const float t1 = s_ta[li], t2 = s_th[li];
+          const float c = wrap_angle(t2 - t1) - a_be;
+          s_ta[li] = t1 + hb_w * c;
+          s_th[li] = t2 - hb_w * c;
         }
         __syncthreads();
       }
@@ -184,6 +244,26 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           s_dy[li] = d0y + dy;
           s_dx[li_next] = d1x - dx;
           s_dy[li_next] = d1y - dy;
+        }
+        __syncthreads();
+      }
+      if (GEN && any_att) {                      // attachment edges p -> c0
+        if (att) {
+          const float d0x = s_dx[p_l], d0y = s_dy[p_l];
+          const float d1x = s_dx[li], d1y = s_dy[li];
+          const float vx = a_vx + (d1x - d0x);
+          const float vy = a_vy + (d1y - d0y);
+          const float ell = hw_sqrt(vx * vx + vy * vy);
+          const float sc = (ell - a_L) * hw_rcp(ell);
+          const float csx = sc * vx, csy = sc * vy;
+          float sn, cs;
+          edge_direction(s_ta[li], a_th, a_ux, a_uy, &cs, &sn);
+          const float dx = hs_w * (csx + ksh_w * (vx - a_L * cs - csx));
+          const float dy = hs_w * (csy + ksh_w * (vy - a_L * sn - csy));
+          s_dx[p_l] = d0x + dx;
+          s_dy[p_l] = d0y + dy;
+          s_dx[li] = d1x - dx;
+          s_dy[li] = d1y - dy;
         }
         __syncthreads();
       }

@@ -190,6 +190,10 @@ struct Slot {
   float* ksh = nullptr;
   int* fil_flags = nullptr;     // optional [F] (SIM_FIL_CLOSED)
   bool any_loop = false;
+  int* fil_parent = nullptr;    // optional [F] node a filament hangs from (branches), -1: none
+  float* fil_attach = nullptr;  // [3][F] attachment rest length and rest angles
+  bool any_branch = false;
+  std::vector<int> unit_next;   // per filament: the first filament of the next creature
   float* energy = nullptr;      // optional energy field [ny][nx] and its node / filament outputs
   float* e_sensed = nullptr;
   float* e_collected = nullptr;
@@ -204,7 +208,7 @@ struct Slot {
 
 // Whether a world needs the general elastic kernel: it passes loop flags or
 // per-edge stiffness arrays (their presence decides, not their contents).
-bool slot_general(const Slot& s) { return s.fil_flags || s.kb || s.ks || s.ksh; }
+bool slot_general(const Slot& s) { return s.fil_flags || s.kb || s.ks || s.ksh || s.fil_parent; }
 
 // Device descriptor of a world whose buffers are described by s; parity 0
 // reads populations buffer s.cur, parity 1 the other one.
@@ -253,6 +257,8 @@ mc::WorldDev world_desc(const Slot& s, int parity, const mc::Ctl* ctl_src, mc::C
   d.ks_arr = s.ks;
   d.ksh_arr = s.ksh;
   d.fil_flags = s.fil_flags;
+  d.fil_parent = s.fil_parent;
+  d.fil_attach = s.fil_attach;
   const bool energy = p.energy_rate > 0.f && s.energy && s.b.e_node;
   d.energy_rate = p.energy_rate;
   d.energy = energy ? s.energy : nullptr;
@@ -418,8 +424,13 @@ struct Engine {
         p.world = w;
         p.fil_begin = f;
         p.node_begin = s.h_off[f];
+        // whole creatures (a filament and those hanging from it) per pack
         int end = f;
-        while (end < s.n_fil && s.h_off[end + 1] - p.node_begin <= cap_nodes) ++end;
+        while (end < s.n_fil) {
+          const int next = s.unit_next.empty() ? end + 1 : s.unit_next[end];
+          if (s.h_off[next] - p.node_begin > cap_nodes) break;
+          end = next;
+        }
         p.fil_end = end;
         p.node_end = s.h_off[end];
         pk.push_back(p);
@@ -687,6 +698,57 @@ sim_status read_loops(const sim_arrays* a, hipStream_t stream, bool* any) {
   return SIM_OK;
 }
 
+// Branches: validate fil_parent / fil_attach (a filament hangs from a node
+// of an earlier filament with an entering edge, never a loop itself, at most
+// one filament per node, every creature contiguous in filament order) and
+// form the creature units the packs are built from: unit_next[f] is the
+// first filament after the creature that starts at f; *max_unit its largest
+// node count.
+sim_status read_branches(const sim_arrays* a, hipStream_t stream, const std::vector<int>& h_off,
+                         std::vector<int>* unit_next, int* max_unit, bool* any) {
+  const int F = a->n_filaments;
+  *any = false;
+  unit_next->assign(F, 0);
+  for (int f = 0; f < F; ++f) (*unit_next)[f] = f + 1;
+  *max_unit = 0;
+  for (int f = 0; f < F; ++f) *max_unit = std::max(*max_unit, h_off[f + 1] - h_off[f]);
+  if (!a->fil_parent || F == 0) return SIM_OK;
+  if (!a->fil_attach) return fail(SIM_E_INVALID, "fil_parent needs fil_attach");
+  std::vector<int> par(F), flags(F, 0);
+  HIPCHK(hipMemcpyAsync(par.data(), a->fil_parent, F * sizeof(int), hipMemcpyDeviceToHost, stream));
+  if (a->fil_flags) HIPCHK(hipMemcpyAsync(flags.data(), a->fil_flags, F * sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const int N = h_off[F];
+  std::vector<char> used(N, 0);
+  int last_root = -1;
+  for (int f = 0; f < F; ++f) {
+    const int pn = par[f];
+    if (pn < 0) {
+      last_root = f;
+      continue;
+    }
+    if (pn >= N) return fail(SIM_E_INVALID, "filament %d: parent node %d out of range", f, pn);
+    const int pf = int(std::upper_bound(h_off.begin(), h_off.end(), pn) - h_off.begin()) - 1;
+    if (pf >= f || pf < last_root)
+      return fail(SIM_E_INVALID, "filament %d: its parent node must lie in an earlier filament of its creature", f);
+    if (flags[f] & SIM_FIL_CLOSED) return fail(SIM_E_INVALID, "filament %d: a closed loop cannot hang from a node", f);
+    const bool ring_p = (flags[pf] & SIM_FIL_CLOSED) && h_off[pf + 1] - h_off[pf] >= 3;
+    if (!ring_p && pn == h_off[pf]) return fail(SIM_E_INVALID, "filament %d: its parent node has no entering edge", f);
+    if (used[pn]) return fail(SIM_E_INVALID, "node %d carries two attached filaments", pn);
+    used[pn] = 1;
+    *any = true;
+  }
+  *max_unit = 0;
+  for (int f = 0; f < F;) {
+    int g = f + 1;
+    while (g < F && par[g] >= 0) ++g;
+    (*unit_next)[f] = g;
+    *max_unit = std::max(*max_unit, h_off[g] - h_off[f]);
+    f = g;
+  }
+  return SIM_OK;
+}
+
 sim_status check_arrays(const sim_arrays* a) {
   if (!a) return fail(SIM_E_INVALID, "arrays is NULL");
   if (a->n_particles < 0 || a->n_filaments < 0) return fail(SIM_E_INVALID, "negative sizes");
@@ -753,8 +815,13 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   } else {
     h_off.assign(1, 0);
   }
+  std::vector<int> unit_next;
   int max_len = 0;
-  for (int f = 0; f < a->n_filaments; ++f) max_len = std::max(max_len, h_off[f + 1] - h_off[f]);
+  bool any_branch = false;
+  if ((st = read_branches(a, s, h_off, &unit_next, &max_len, &any_branch))) return st;
+  if (max_len > mc::kMaxFilament)
+    return fail(SIM_E_INVALID, "a creature (a filament with those hanging from it) holds %d nodes; at most %d",
+                max_len, mc::kMaxFilament);
 
   sim_world* w = new sim_world();
   w->arr = *a;
@@ -791,6 +858,10 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   sl.ks = const_cast<float*>(a->k_stretch);
   sl.ksh = const_cast<float*>(a->k_shear);
   sl.fil_flags = const_cast<int*>(a->fil_flags);
+  sl.fil_parent = any_branch ? const_cast<int*>(a->fil_parent) : nullptr;
+  sl.fil_attach = any_branch ? const_cast<float*>(a->fil_attach) : nullptr;
+  sl.any_branch = any_branch;
+  sl.unit_next = unit_next;
   sl.energy = a->energy;
   sl.e_sensed = a->energy_sensed;
   sl.e_collected = a->energy_collected;
@@ -1191,6 +1262,7 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   sim_status st = check_params(p);
   if (st) return st;
   if ((st = check_arrays(a))) return st;
+  if (a->fil_parent) return fail(SIM_E_INVALID, "sim_step_noalloc does not take branched worlds (fil_parent)");
   NoallocLayout L;
   carve_noalloc(nullptr, *p, a->n_filaments, a->n_particles, L);
   if (L.bytes > kScratchBytes)
@@ -1481,6 +1553,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
                 mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
   if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
+  if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
   if (s.p.mdf_iters > 1) return fail(SIM_E_INVALID, "sim_backward does not differentiate multi-direct forcing");
   if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   size_t need = 0;
@@ -1618,6 +1691,8 @@ void carve_batch_world(Carver& c, const sim_params& p, int n_fil, int n_part, Sl
   s.ks = c.take<float>(N);              // pointed at only when the admitted world has them
   s.ksh = c.take<float>(N);
   s.fil_flags = c.take<int>(F);
+  s.fil_parent = c.take<int>(F);
+  s.fil_attach = c.take<float>(3 * F);
   if (p.energy_rate > 0.f) {             // energy field and collected totals live in the pool
     s.energy = c.take<float>(ncell);
     s.e_collected = c.take<float>(F);
@@ -1766,9 +1841,12 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
   } else {
     h_off.assign(1, 0);
   }
+  std::vector<int> unit_next;
   int max_len = 0;
-  for (int f = 0; f < init->n_filaments; ++f) max_len = std::max(max_len, h_off[f + 1] - h_off[f]);
-  if (max_len > e.grid.pack) return fail(SIM_E_INVALID, "batched filaments are limited to %d nodes", e.grid.pack);
+  bool any_branch = false;
+  if ((st = read_branches(init, e.stream, h_off, &unit_next, &max_len, &any_branch))) return st;
+  if (max_len > e.grid.pack)
+    return fail(SIM_E_INVALID, "batched filaments (with those hanging from them) are limited to %d nodes", e.grid.pack);
   bool any_loop = false;
   if ((st = read_loops(init, e.stream, &any_loop))) return st;
   size_t bytes = 0;
@@ -1813,6 +1891,10 @@ sim_status sim_batch_admit(sim_batch* b, const sim_params* p, const sim_arrays* 
   if ((st = opt(s.ks, init->k_stretch, N * 4))) return st;
   if ((st = opt(s.ksh, init->k_shear, N * 4))) return st;
   if ((st = opt(s.fil_flags, init->fil_flags, F * 4))) return st;
+  if ((st = opt(s.fil_parent, any_branch ? init->fil_parent : nullptr, F * 4))) return st;
+  if ((st = opt(s.fil_attach, any_branch ? init->fil_attach : nullptr, 3 * F * 4))) return st;
+  s.any_branch = any_branch;
+  s.unit_next = unit_next;
   if (s.energy) {
     if (init->energy) {
       if ((st = cp(s.energy, init->energy, ncell * 4))) return st;

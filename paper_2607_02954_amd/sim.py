@@ -66,6 +66,7 @@ class SimArrays(ctypes.Structure):
         ("k_bend", ctypes.c_void_p), ("k_stretch", ctypes.c_void_p), ("k_shear", ctypes.c_void_p),
         ("fil_flags", ctypes.c_void_p),
         ("energy", ctypes.c_void_p), ("energy_sensed", ctypes.c_void_p), ("energy_collected", ctypes.c_void_p),
+        ("fil_parent", ctypes.c_void_p), ("fil_attach", ctypes.c_void_p),
     ]
 
 
@@ -193,6 +194,9 @@ class DeviceState:
                                                      tuple(t(k, torch.float32) for k in st))
         closed = getattr(w, "closed", None)
         self.fil_flags = None if closed is None else t(np.asarray(closed, dtype=np.int32), torch.int32)
+        par = getattr(w, "parent", None)
+        self.fil_parent = None if par is None else t(np.asarray(par, dtype=np.int32), torch.int32)
+        self.fil_attach = None if par is None else t(np.asarray(w.attach, dtype=np.float32), torch.float32).contiguous()
         E = getattr(w, "energy", None)
         self.energy = None if E is None else t(E, torch.float32).reshape(self.ny, self.nx).contiguous()
         self.energy_sensed = None if E is None else torch.zeros(self.n_part, device=dev, dtype=torch.float32)
@@ -203,7 +207,8 @@ class DeviceState:
                          _ptr(self.rest_angle), _ptr(self.rest_length), _ptr(self.act_amp),
                          _ptr(self.act_period), _ptr(self.act_phase), _ptr(self.f), _ptr(self.u),
                          _ptr(self.k_bend), _ptr(self.k_stretch), _ptr(self.k_shear), _ptr(self.fil_flags),
-                         _ptr(self.energy), _ptr(self.energy_sensed), _ptr(self.energy_collected))
+                         _ptr(self.energy), _ptr(self.energy_sensed), _ptr(self.energy_collected),
+                         _ptr(self.fil_parent), _ptr(self.fil_attach))
 
     def positions64(self) -> np.ndarray:
         return self.cell.cpu().numpy().astype(np.float64) + self.frac.cpu().numpy().astype(np.float64)

@@ -43,6 +43,8 @@ class World:
     stiffness: Optional[tuple] = None     # float32 [N] x 3: per-edge (k_bend, k_stretch, k_shear)
     closed: Optional[np.ndarray] = None   # bool [F]: filament f is a closed loop
     energy: Optional[np.ndarray] = None   # float32 [ny, nx] initial energy field
+    parent: Optional[np.ndarray] = None   # int32 [F]: node filament f hangs from (-1: none)
+    attach: Optional[np.ndarray] = None   # float [3, F]: attachment rest length, angle at the parent, angle at c0
 
     @property
     def n_particles(self) -> int:
@@ -153,6 +155,93 @@ def generality_world(seed: int, nx: int, ny: int, chain_lengths: List[int], loop
     w.closed = np.array([False] * len(chain_lengths) + [True] * len(loop_lengths))
     lo, hi = stiffness_range
     w.stiffness = tuple(g.uniform(lo, hi, size=N).astype(np.float32) for _ in range(3))
+    return w
+
+
+def branched_world(seed: int, nx: int, ny: int, n_creatures: int, *, amp: float = 0.5, loop_share: float = 0.3,
+                   angle_sd: float = 0.3, max_children: int = 3) -> World:
+    """Branched creatures (cactus graphs): a root filament (a chain of U{8..40}
+    nodes, or with probability ``loop_share`` a regular polygon loop of
+    U{6..16} unit sides) with 1..max_children chains of U{2..16} nodes hanging
+    from distinct nodes that have an entering edge (a loop's nodes, a chain's
+    non-first nodes), one of which may carry a grandchild chain.  Attachment
+    rest length U(0.8, 1.2), rest angle at the parent +-U(0.6, 1.4), at the
+    child's first node N(0, 0.2^2); each child starts straight along its
+    attachment's rest direction.  Regular rest angles as random_world (loops:
+    2 pi / n + noise); actuation amplitude ``amp`` on every filament."""
+    g = _rng(seed + 15485863)
+    chains, ra, closed, parent, attach = [], [], [], [], []
+    n_nodes = 0
+    for _ in range(n_creatures):
+        centre = g.uniform(0.0, 1.0, size=2) * np.array([nx, ny])
+        first = len(chains)
+        if g.uniform() < loop_share:
+            n = int(g.integers(6, 17))
+            x = polygon_loop(n, centre, g.uniform(0, 2 * math.pi))
+            chains.append(x)
+            ra.append(2 * math.pi / n + g.normal(0.0, angle_sd, size=n))
+            closed.append(True)
+        else:
+            n = int(g.integers(8, 41))
+            x = straight_chain(n, centre, g.uniform(0, 2 * math.pi))
+            chains.append(x)
+            r = np.zeros(n)
+            r[1:n - 1] = g.normal(0.0, angle_sd, size=n - 2)
+            ra.append(r)
+            closed.append(False)
+        parent.append(-1)
+        attach.append((0.0, 0.0, 0.0))
+        # candidate parent nodes: (global index, position, entering-edge angle)
+        def candidates(fi):
+            xs = chains[fi]
+            m = xs.shape[1]
+            off = n_nodes + sum(c.shape[1] for c in chains[first:fi])
+            out = []
+            for k in range(m):
+                if closed[fi]:
+                    prev = xs[:, k - 1]
+                elif k == 0:
+                    continue
+                else:
+                    prev = xs[:, k - 1]
+                d = xs[:, k] - prev
+                out.append((off + k, xs[:, k], math.atan2(d[1], d[0])))
+            return out
+        used = set()
+        kids = int(g.integers(1, max_children + 1))
+        for c in range(kids):
+            host = first if c == 0 or g.uniform() < 0.7 else len(chains) - 1
+            cand = [q for q in candidates(host) if q[0] not in used]
+            if not cand:
+                continue
+            node, pos, th_in = cand[int(g.integers(len(cand)))]
+            used.add(node)
+            La = g.uniform(0.8, 1.2)
+            al = g.choice([-1.0, 1.0]) * g.uniform(0.6, 1.4)
+            be = g.normal(0.0, 0.2)
+            m = int(g.integers(2, 17))
+            a0 = th_in + al
+            c0 = pos + La * np.array([math.cos(a0), math.sin(a0)])
+            a1 = a0 + be
+            xs = np.stack([c0[0] + np.arange(m) * math.cos(a1), c0[1] + np.arange(m) * math.sin(a1)])
+            chains.append(xs)
+            r = np.zeros(m)
+            if m >= 3:
+                r[1:m - 1] = g.normal(0.0, angle_sd, size=m - 2)
+            ra.append(r)
+            closed.append(False)
+            parent.append(node)
+            attach.append((La, al, be))
+        n_nodes += sum(c.shape[1] for c in chains[first:])
+    F = len(chains)
+    N = sum(c.shape[1] for c in chains)
+    period = g.uniform(20.0, 100.0, size=F)
+    phase = g.uniform(0.0, 2 * math.pi, size=F)
+    w = _assemble(nx, ny, chains, np.concatenate(ra), np.ones(N), np.full(F, amp),
+                  period, phase, meta=dict(seed=seed, name="branched"))
+    w.closed = np.array(closed)
+    w.parent = np.array(parent, dtype=np.int32)
+    w.attach = np.array(attach, dtype=np.float64).T.copy()
     return w
 
 

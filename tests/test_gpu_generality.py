@@ -1,14 +1,17 @@
 """Filament generality on the GPU against the FP64 oracle: closed loops (odd
-and even lengths, the third Gauss-Seidel colour), per-edge stiffness arrays
-and the bending/stretching effort (Methods, Filaments; Experiments, QD Search,
-Eqs. 5-6).
+and even lengths, the third Gauss-Seidel colour), branches (filaments hanging
+from nodes of other filaments: cactus graphs), per-edge stiffness arrays and
+the bending/stretching effort (Methods, Filaments; Discussion; Experiments,
+QD Search, Eqs. 5-6).
 
 Per step: e_x <= 1e-5, e_u <= 1e-4 and each step's displacement e_d <= 1e-4,
-in every transfer; a polygon loop at its rest shape feels no elastic force;
-stiffness arrays equal to the scalars change no bit; a batch of such worlds
-equals its worlds run alone; the allocation-free step equals sim_step; the
-adjoint with per-edge stiffness matches the oracle's, and worlds with loops
-are refused by sim_backward; sim_rest_effort matches the oracle's efforts.
+in every transfer; a polygon loop and a T-junction at their rest shapes feel
+no elastic force; stiffness arrays equal to the scalars change no bit; a
+batch of such worlds equals its worlds run alone; the allocation-free step
+equals sim_step; the adjoint with per-edge stiffness matches the oracle's,
+and worlds with loops or branches are refused by sim_backward (branched ones
+by the allocation-free step too); topologies that break the branch rules are
+refused at creation; sim_rest_effort matches the oracle's efforts.
 """
 import math
 
@@ -146,3 +149,83 @@ def test_rest_effort_matches_oracle():
     e = rel(eff.cpu().double().numpy(), ref.numpy())
     print(f"efforts (accumulated twice): rel err {e:.2e}")
     assert e <= 1e-5
+
+
+def _branched(seed=0):
+    return wl.branched_world(seed, 96, 80, 6)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_branches_match_oracle(mode):
+    sim = _sim()
+    w = _branched(1)
+    assert int((w.parent >= 0).sum()) >= 6
+    E = _rollout_compare(sim, w, 40, mode)
+    print(f"branched creatures (F={w.n_filaments}, N={w.n_particles}), 40 steps [{mode}]: {E}")
+
+
+def test_t_junction_at_rest_feels_no_force():
+    sim = _sim()
+    x = np.array([[10.3, 11.3, 12.3, 13.3, 14.3, 12.3, 12.3, 12.3], [20.6, 20.6, 20.6, 20.6, 20.6, 21.6, 22.6, 23.6]])
+    w = wl._assemble(40, 40, [x[:, :5], x[:, 5:]], np.zeros(8), np.ones(8), [0.0, 0.0], [50.0, 50.0], [0.0, 0.0])
+    w.parent = np.array([-1, 2], dtype=np.int32)
+    w.attach = np.array([[0.0, 1.0], [0.0, math.pi / 2], [0.0, 0.0]])
+    W = sim.World(w, sim.Params(nx=40, ny=40))
+    W.substep(0, 0)
+    torch.cuda.synchronize()
+    fel = W.buffer(4, (2, 8)).abs().max().item()
+    print(f"T-junction at rest: max |F_el| = {fel:.2e}")
+    assert fel < 1e-6
+
+
+def test_branch_batch_alone_and_refusals():
+    sim = _sim()
+    from paper_2607_02954_amd import batch
+    worlds = [_branched(2), wl.random_world(3, 64, 64, [20, 9], amp=0.5), wl.branched_world(4, 72, 64, 3)]
+    steps = [22, 30, 16]
+    eng = batch.BatchEngine(max_worlds=3, pool_bytes=128 << 20)
+    slots = [eng.admit(w, sim.Params(nx=w.nx, ny=w.ny), s) for w, s in zip(worlds, steps)]
+    while any(eng.remaining(s) > 0 for s in slots):
+        eng.advance(10)
+    for w, sl, st in zip(worlds, slots, steps):
+        got = eng.retire(sl, w)
+        W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny))
+        W.rollout(0, st)
+        W.sync()
+        assert all(torch.equal(getattr(got, k), getattr(W.state, k)) for k in ("cell", "frac", "f", "u"))
+        ex, ea, eu, ed = final_state_errors(w, got, oracle_params(sim.Params(nx=w.nx, ny=w.ny)), 0, st)
+        print(f"batch with branches {w.nx}x{w.ny}: e_x={ex:.2e} e_a={ea:.2e} e_u={eu:.2e} e_d={ed:.2e}")
+        assert ex <= TOL_X and eu <= TOL_U and ed <= TOL_D
+    # topologies that break the rules
+    base = wl.random_world(5, 64, 64, [6, 5, 4], amp=0.0)
+    att = np.ones((3, 3))
+    for par, closed in (([8, -1, -1], None),            # parent node in a later filament
+                        ([-1, 2, 2], None),             # two filaments on one node
+                        ([-1, 0, -1], None),            # parent node without an entering edge
+                        ([-1, 3, -1], [False, True, False]),   # a loop hanging from a node
+                        ([-1, -1, 3], None),            # a creature split by another root
+                        ([-1, 99, -1], None)):          # parent node out of range
+        w = wl.random_world(5, 64, 64, [6, 5, 4], amp=0.0)
+        w.parent = np.array(par, dtype=np.int32)
+        w.attach = att
+        if closed is not None:
+            w.closed = np.array(closed)
+        with pytest.raises(sim.SimError) as ei:
+            sim.World(w, sim.Params(nx=64, ny=64))
+        assert ei.value.status == sim.SIM_E_INVALID, par
+    # the allocation-free step and the adjoint refuse branched worlds
+    w = _branched(6)
+    p = sim.Params(nx=w.nx, ny=w.ny)
+    st = sim.DeviceState(w, "cuda")
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(sim.SimError) as ei:
+        sim.step_noalloc(st, p, 0, status)
+    assert ei.value.status == sim.SIM_E_INVALID
+    Wb = sim.World(w, p)
+    ck = torch.empty(Wb.checkpoint_bytes(4, 2), dtype=torch.uint8, device="cuda")
+    Wb.rollout(0, 4, 2, ck)
+    g_pos = torch.zeros(2, w.n_particles, dtype=torch.float32, device="cuda")
+    g_rest = torch.zeros(w.n_particles, dtype=torch.float32, device="cuda")
+    with pytest.raises(sim.SimError) as ei:
+        Wb.backward(0, 4, 2, ck, g_pos, g_rest)
+    assert ei.value.status == sim.SIM_E_INVALID
