@@ -370,8 +370,9 @@ def bench_widened(world, seed, tile, steps, warmup):
       Gaussian packets (amplitudes U(0.5, 2), widths U(3, 12) cells) that the
       nodes deplete at rate 0.05 per step;
     * topology generality (binned): the workload with per-edge stiffness
-      arrays U(0.2, 1), and a world of chains plus closed loops (lengths
-      U{16..64}, 10% of the nodes) of the same size with stiffness arrays;
+      arrays U(0.2, 1), a world of chains plus closed loops (lengths
+      U{16..64}, 10% of the nodes) of the same size with stiffness arrays,
+      and about a million nodes of branched creatures;
       plus one rest-effort reduction (the descriptors of a rest-value change)
       over the million nodes."""
     from dataclasses import replace as dc_replace
@@ -435,6 +436,13 @@ def bench_widened(world, seed, tile, steps, warmup):
     loops.append(n_loop - sum(loops))            # 16..79 nodes
     wg = wl.generality_world(seed, world.nx, world.ny, wl.scaling_lengths(seed, N - sum(loops)), loops)
     gen = timed(wg, base, steps, "binned loops + stiffness")
+    del wg
+    wb = wl.branched_world(seed, world.nx, world.ny, 26500)
+    branched = timed(wb, base, steps, "binned branched creatures")
+    branched["nodes"] = wb.n_particles
+    branched["filaments"] = wb.n_filaments
+    branched["attachments"] = int((wb.parent >= 0).sum())
+    del wb
     dev = sim.DeviceState(ws, "cuda")
     ra2 = dev.rest_angle + 0.01
     rl2 = dev.rest_length * 1.01
@@ -450,10 +458,13 @@ def bench_widened(world, seed, tile, steps, warmup):
     del dev
     torch.cuda.empty_cache()
     out["topology"] = {"workload": "scaling workload; loops world: same node count, 10% of the nodes in loops "
-                                   f"({len(loops)} loops of U{{16..64}} nodes)",
+                                   f"({len(loops)} loops of U{{16..64}} nodes); branched world: 26,500 creatures "
+                                   "(a chain or loop with chains hanging from its nodes) on the same grid",
                        "plain": plain, "per_edge_stiffness": stiff, "loops_and_stiffness": gen,
+                       "branched_creatures": branched,
                        "stiffness_over_plain": stiff["ms_per_step"] / plain["ms_per_step"],
                        "loops_over_plain": gen["ms_per_step"] / plain["ms_per_step"],
+                       "branched_over_plain": branched["ms_per_step"] / plain["ms_per_step"],
                        "rest_effort_ms": eff_ms}
     return out
 
