@@ -97,7 +97,8 @@ typedef struct sim_params {
                               u = (j + F_grid/2)/rho at the node and spreads
                               2 (U_d - u), U_d = (j/rho at the node) + F/2.
                               The tile-binned and the direct transfer; not with
-                              SIM_SPLAT_SORTED; sim_backward refuses it.       */
+                              SIM_SPLAT_SORTED; sim_backward differentiates it
+                              (binned transfer).                               */
   float marker_offset;     /* two-layer broadcast (SIM_SPLAT_DIRECT only): each
                               node acts through two markers at +-marker_offset
                               (cells, <= 1) along its normal (tangent

@@ -7,6 +7,8 @@
 //   k_adj_u       S7: u~ = spread(dL/dx_{t+1})                 (tile, LDS)
 //   k_adj_lbm     S6: streaming^T (pull) and the collision Jacobian^T per
 //                     cell -> dL/dg_t, dL/dF_grid
+//   (MDF)         S5 with multi-direct forcing: the iterates recomputed,
+//                     then reversed iteration by iteration (k_adj_mdf_*)
 //   k_adj_force   S5, S4, S7: dL/dF_i = gather(dL/dF_grid); the derivative
 //                     terms of the three node gathers/spreads w.r.t. x_t
 //   k_adj_grad    S4: dL/dG = -k_rep spread(dL/dF)              (tile, LDS)
@@ -28,10 +30,11 @@ constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registe
 // ---------------------------------------------------------------------------
 // Node -> grid spreads of adjoint node vectors (u~ and G~), tile-binned.
 // ---------------------------------------------------------------------------
+// out = add + scale S[v] (add may be null).
 template <int TILE>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const WorldDev* __restrict__ W, Tables T,
                                                                          const float* v, float scale_is_rep,
-                                                                         float2* out) {
+                                                                         const float2* add, float2* out) {
   using C = TileCfg<TILE>;
   constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells;
   __shared__ __align__(16) long long s_x[kSpreadCells];
@@ -57,9 +60,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const Wo
     for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
       const int ly = k >> C::kShift, lx = k & (TILE - 1);
       if (lx >= tw || ly >= th) continue;
-      const vf2 val = {fix_to_float(spread_cell<TILE>(s_x, lx, ly, nx, ny)),
-                       fix_to_float(spread_cell<TILE>(s_y, lx, ly, nx, ny))};
-      o[(size_t)(y0 + ly) * nx + x0 + lx] = val;
+      const size_t c = (size_t)(y0 + ly) * nx + x0 + lx;
+      vf2 val = {0.f, 0.f};
+      if (add) val = glbv<const vf2>(add)[c];
+      val.x += fix_to_float(spread_cell<TILE>(s_x, lx, ly, nx, ny));
+      val.y += fix_to_float(spread_cell<TILE>(s_y, lx, ly, nx, ny));
+      o[c] = val;
     }
     __syncthreads();
   }
@@ -209,6 +215,13 @@ __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__
         sfy += Wy * pf;
       }
     }
+    float mx = 0.f, my = 0.f;
+    if (A.mdf > 1) {                    // U_d = I[j / rho] + F / 2, and the MDF transfers' position terms
+      fbx += 0.5f * A.Udbar[gi];
+      fby += 0.5f * A.Udbar[N + gi];
+      mx = A.xbar_m[gi];
+      my = A.xbar_m[N + gi];
+    }
     // repulsion F_rep = -k sum_c W G_c : d/dx of (-k sum_c W (G_c . Fbar))
     float srx = 0.f, sry = 0.f;
 #pragma unroll
@@ -222,8 +235,8 @@ __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__
     const float kr = w.k_rep;
     A.Fbar[gi] = fbx;
     A.Fbar[N + gi] = fby;
-    A.xbar[gi] = xbx + sux + sfx - kr * srx;
-    A.xbar[N + gi] = xby + suy + sfy - kr * sry;
+    A.xbar[gi] = xbx + sux + sfx - kr * srx + mx;
+    A.xbar[N + gi] = xby + suy + sfy - kr * sry + my;
   }
 }
 
@@ -516,6 +529,276 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
   }
 }
 
+// ---------------------------------------------------------------------------
+// S5 with multi-direct forcing (binned, one layer), forward recomputed and
+// reversed.  Forward: F_grid_1 = S[F], U_d = I[j / rho] + F / 2, and for
+// k = 1 .. K-1: u_k = (j + F_grid_k / 2) / rho, c_k = 2 (U_d - I[u_k]),
+// F_grid_{k+1} = F_grid_k + S[c_k].  Given G~ = dL/dF_grid_{k+1}, iteration k
+// reversed: c~ = I[G~]; U_d~ += 2 c~; U_k~ = -2 c~; x~ gets the derivatives
+// of S[c_k] and I[u_k] in the node positions; u_k~ = S[U_k~] gives
+// G~ += u_k~ / (2 rho), j~ += u_k~ / rho, rho~ -= u_k~ . u_k / rho.  Then U_d:
+// F~ += U_d~ / 2 (in k_adj_force), x~ from I[j / rho], v~ = S[U_d~] gives
+// j~ += v~ / rho, rho~ -= v~ . (j / rho) / rho, and finally g~_q += rho~ + c_q . j~.
+// Node passes gather over each tile's own-bin nodes from fields staged over
+// the tile and a 3-cell halo; the spreads are the tile spread in 64-bit
+// fixed point.  The recomputed iterates use the forward's arithmetic and sums,
+// so they equal the forward's bit for bit.
+// ---------------------------------------------------------------------------
+__global__ void k_adj_zero(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, float* d, size_t nd) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < na + nb + nc + nd;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < na) a[i] = 0.f;
+    else if (i < na + nb) b[i - na] = 0.f;
+    else if (i < na + nb + nc) c[i - na - nb] = 0.f;
+    else d[i - na - nb - nc] = 0.f;
+  }
+}
+
+// Cells (x0 - 1 + c, y0 - 1 + r), c, r in [0, TILE + 3), of a tile: value(idx)
+// of each (periodic grid index) into st; all loads before the stores.
+template <int TILE, class V>
+static __device__ __forceinline__ void adj_stage(int nx, int ny, int x0, int y0, vf2* st, V value) {
+  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kIt = (kStage * kStage + kThreads - 1) / kThreads;
+  vf2 v[kIt];
+#pragma unroll
+  for (int i = 0; i < kIt; ++i) {
+    const int k = min((int)threadIdx.x + kThreads * i, kStage * kStage - 1);
+    const int r = k / kStage, c = k - (k / kStage) * kStage;
+    v[i] = value((size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx));
+  }
+#pragma unroll
+  for (int i = 0; i < kIt; ++i) {
+    const int k = (int)threadIdx.x + kThreads * i;
+    if (k < kStage * kStage) st[k] = v[i];
+  }
+}
+
+// U_d (DESIRED) or the correction c_k of the iterate Fgk at the tile's own nodes.
+template <int TILE, bool DESIRED>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(const WorldDev* __restrict__ W,
+                                                                                 Tables T, AdjDev A,
+                                                                                 const float2* Fgk) {
+  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  __shared__ vf2 s_u[kStage * kStage];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    const int nx = w.nx, ny = w.ny, N = w.n_part;
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
+    const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
+    const MC_GLOBAL vf2* Fg = glbv<const vf2>(Fgk);
+    adj_stage<TILE>(nx, ny, x0, y0, s_u, [&](size_t c) {
+      const vf4 mv = m[c];
+      vf2 u;
+      if (DESIRED) {
+        u.x = mv.y / mv.x;
+        u.y = mv.z / mv.x;
+      } else {
+        const vf2 fv = Fg[c];
+        const float inv = 1.0f / mv.x;
+        u.x = (mv.y + 0.5f * fv.x) * inv;
+        u.y = (mv.z + 0.5f * fv.y) * inv;
+      }
+      return u;
+    });
+    __syncthreads();
+    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
+    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
+      const vi4 r = recs[e];
+      const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
+      float wx[4], wy[4];
+      peskin4(__int_as_float(r.y), wx);
+      peskin4(__int_as_float(r.z), wy);
+      float gx = 0.f, gy = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const vf2* row = s_u + (ly + b) * kStage + lx;
+        float ax = 0.f, ay = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const vf2 t = row[a];
+          ax += wx[a] * t.x;
+          ay += wx[a] * t.y;
+        }
+        gx += wy[b] * ax;
+        gy += wy[b] * ay;
+      }
+      const int gi = r.w;
+      if (DESIRED) {
+        A.Ud[gi] = gx + 0.5f * glb(w.fel)[gi];
+        A.Ud[N + gi] = gy + 0.5f * glb(w.fel)[N + gi];
+      } else {
+        A.mc[gi] = 2.0f * (A.Ud[gi] - gx);
+        A.mc[N + gi] = 2.0f * (A.Ud[N + gi] - gy);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Reverse node pass.  MODE 0 (iteration k, iterate Fgk): c~ = I[G~],
+// U_k~ = -2 c~ (stored), U_d~ += 2 c~, x~ += dI/dx terms of S[c_k] and I[u_k].
+// MODE 1 (U_d): x~ += U_d~ . dI[j / rho]/dx.
+template <int TILE, int MODE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const WorldDev* __restrict__ W, Tables T,
+                                                                           AdjDev A, const float2* Fgk) {
+  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  __shared__ vf2 s_g[MODE == 0 ? kStage * kStage : 1];
+  __shared__ vf2 s_u[kStage * kStage];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    const int nx = w.nx, ny = w.ny, N = w.n_part;
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
+    const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
+    const MC_GLOBAL vf2* Fg = glbv<const vf2>(Fgk);
+    const MC_GLOBAL vf2* Gb = glbv<const vf2>(A.Fgbar);
+    if constexpr (MODE == 0) adj_stage<TILE>(nx, ny, x0, y0, s_g, [&](size_t c) { return Gb[c]; });
+    adj_stage<TILE>(nx, ny, x0, y0, s_u, [&](size_t c) {
+      const vf4 mv = m[c];
+      const float inv = 1.0f / mv.x;
+      vf2 u;
+      if (MODE == 0) {
+        const vf2 fv = Fg[c];
+        u.x = (mv.y + 0.5f * fv.x) * inv;
+        u.y = (mv.z + 0.5f * fv.y) * inv;
+      } else {
+        u.x = mv.y * inv;
+        u.y = mv.z * inv;
+      }
+      return u;
+    });
+    __syncthreads();
+    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
+    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
+      const vi4 r = recs[e];
+      const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
+      float wx[4], dwx[4], wy[4], dwy[4];
+      peskin4_d(__int_as_float(r.y), wx, dwx);
+      peskin4_d(__int_as_float(r.z), wy, dwy);
+      const int gi = r.w;
+      float cbx = 0.f, cby = 0.f, Ux = 0.f, Uy = 0.f;          // I[G~], I[u]
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int k = (ly + b) * kStage + lx + a;
+          const float W0 = wx[a] * wy[b];
+          if (MODE == 0) {
+            cbx += W0 * s_g[k].x;
+            cby += W0 * s_g[k].y;
+          }
+          Ux += W0 * s_u[k].x;
+          Uy += W0 * s_u[k].y;
+        }
+      float Ubx, Uby;                                            // dL/d(the sampled velocity)
+      float cx = 0.f, cy = 0.f;
+      if (MODE == 0) {
+        Ubx = -2.0f * cbx;
+        Uby = -2.0f * cby;
+        cx = 2.0f * (A.Ud[gi] - Ux);
+        cy = 2.0f * (A.Ud[N + gi] - Uy);
+        A.Ukbar[gi] = Ubx;
+        A.Ukbar[N + gi] = Uby;
+        A.Udbar[gi] += 2.0f * cbx;
+        A.Udbar[N + gi] += 2.0f * cby;
+      } else {
+        Ubx = A.Udbar[gi];
+        Uby = A.Udbar[N + gi];
+      }
+      float sx = 0.f, sy = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int k = (ly + b) * kStage + lx + a;
+          float p = Ubx * s_u[k].x + Uby * s_u[k].y;
+          if (MODE == 0) p += cx * s_g[k].x + cy * s_g[k].y;
+          sx += dwx[a] * wy[b] * p;
+          sy += wx[a] * dwy[b] * p;
+        }
+      A.xbar_m[gi] += sx;
+      A.xbar_m[N + gi] += sy;
+    }
+    __syncthreads();
+  }
+}
+
+// Reverse cell pass: w~ = S[nodevec] over the tile, then MODE 0 (iterate
+// Fgk): G~ += w~ / (2 rho), j~ += w~ / rho, rho~ -= w~ . u_k / rho; MODE 1
+// (U_d): j~ += w~ / rho, rho~ -= w~ . (j / rho) / rho, and g~_q += rho~ + c_q . j~.
+template <int TILE, int MODE>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_cell(const WorldDev* __restrict__ W, Tables T,
+                                                                           AdjDev A, const float* nodevec,
+                                                                           const float2* Fgk) {
+  using C = TileCfg<TILE>;
+  constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells;
+  __shared__ __align__(16) long long s_x[kSpreadCells];
+  __shared__ __align__(16) long long s_y[kSpreadCells];
+  __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    const int nx = w.nx, ny = w.ny;
+    const int ncell = nx * ny;
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
+    const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
+    zero_lds_u64(s_x, kSpreadCells);
+    zero_lds_u64(s_y, kSpreadCells);
+    __syncthreads();
+    tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(nodevec), 1.0f, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
+                                 spread_fetch<TILE>(w, x0, y0), nullptr);
+    __syncthreads();
+    const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
+    for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
+      const int ly = k >> C::kShift, lx = k & (TILE - 1);
+      if (lx >= tw || ly >= th) continue;
+      const size_t c = (size_t)(y0 + ly) * nx + x0 + lx;
+      const float wbx = fix_to_float(spread_cell<TILE>(s_x, lx, ly, nx, ny));
+      const float wby = fix_to_float(spread_cell<TILE>(s_y, lx, ly, nx, ny));
+      const vf4 mv = m[c];
+      const float inv = 1.0f / mv.x;
+      vf2 u;
+      if (MODE == 0) {
+        const vf2 fv = glbv<const vf2>(Fgk)[c];
+        u.x = (mv.y + 0.5f * fv.x) * inv;
+        u.y = (mv.z + 0.5f * fv.y) * inv;
+        vf2 gb = glbv<vf2>(A.Fgbar)[c];
+        gb.x += 0.5f * wbx * inv;
+        gb.y += 0.5f * wby * inv;
+        glbv<vf2>(A.Fgbar)[c] = gb;
+      } else {
+        u.x = mv.y * inv;
+        u.y = mv.z * inv;
+      }
+      vf2 jb = glbv<vf2>(A.jbar)[c];
+      jb.x += wbx * inv;
+      jb.y += wby * inv;
+      const float rb = A.rhobar[c] - (wbx * u.x + wby * u.y) * inv;
+      if (MODE == 0) {
+        glbv<vf2>(A.jbar)[c] = jb;
+        A.rhobar[c] = rb;
+      } else {
+        MC_GLOBAL float* gout = glb(A.gbar);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) gout[(size_t)q * ncell + c] += rb + (float)kCX[q] * jb.x + (float)kCY[q] * jb.y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 #define MC_ADJ_PACK(KERNEL, G, ...)                                              \
   do {                                                                           \
     if ((G).pack == 256)                                                         \
@@ -532,6 +815,14 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     if ((G).tile_blocks[2] > 0) KERNEL<64><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
   } while (0)
 
+// A tile kernel with a second template argument, once per tile family present.
+#define MC_ADJ_TILES2(KERNEL, ARG, G, ...)                                                        \
+  do {                                                                                            \
+    if ((G).tile_blocks[0] > 0) KERNEL<16, ARG><<<(G).tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(__VA_ARGS__); \
+    if ((G).tile_blocks[1] > 0) KERNEL<32, ARG><<<(G).tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(__VA_ARGS__); \
+    if ((G).tile_blocks[2] > 0) KERNEL<64, ARG><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
+  } while (0)
+
 // Single linear adjoint sub-steps, for transpose (dot-product) tests:
 // 0: out = S[v] (spread of a node vector, the transpose of the gather);
 // 1: A.sbar = G D^T A.Gbar (filter and central difference transposed);
@@ -539,16 +830,37 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 //    collision and streaming Jacobian transposed; A.ubar must be zero).
 void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int which, const AdjDev& A,
                           const float* v, float2* out, hipStream_t s) {
-  if (which == 0) MC_ADJ_TILES(k_adj_spread, G, W, T, v, 0.f, out);
+  if (which == 0) MC_ADJ_TILES(k_adj_spread, G, W, T, v, 0.f, nullptr, out);
   else if (which == 1) MC_ADJ_TILES(k_adj_filter, G, W, T, A);
   else k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
 }
 
-void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s) {
-  MC_ADJ_TILES(k_adj_spread, G, W, T, A.xbar_in, 0.f, A.ubar);
+void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, size_t ncell,
+                         size_t n_part, hipStream_t s) {
+  MC_ADJ_TILES(k_adj_spread, G, W, T, A.xbar_in, 0.f, nullptr, A.ubar);
   k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
+  if (A.mdf > 1) {
+    // recompute the step's MDF: moments, U_d, F_grid_1 = S[F], then
+    // F_grid_{k+1} = F_grid_k + S[c_k] up to K - 1
+    launch_mdf_moments(W, T, G, s);
+    k_adj_zero<<<64, 256, 0, s>>>(A.Udbar, 2 * n_part, A.xbar_m, 2 * n_part, (float*)A.jbar, 2 * ncell, A.rhobar,
+                                  ncell);
+    MC_ADJ_TILES2(k_adj_mdf_fwd_gather, true, G, W, T, A, nullptr);
+    MC_ADJ_TILES(k_adj_spread, G, W, T, A.F, 0.f, nullptr, A.Fgk);
+    for (int k = 1; k <= A.mdf - 2; ++k) {
+      MC_ADJ_TILES2(k_adj_mdf_fwd_gather, false, G, W, T, A, A.Fgk + (k - 1) * ncell);
+      MC_ADJ_TILES(k_adj_spread, G, W, T, A.mc, 0.f, A.Fgk + (k - 1) * ncell, A.Fgk + k * ncell);
+    }
+    // reverse: iterations K - 1 .. 1 (A.Fgbar becomes dL/dF_grid_k), then U_d
+    for (int k = A.mdf - 1; k >= 1; --k) {
+      MC_ADJ_TILES2(k_adj_mdf_node, 0, G, W, T, A, A.Fgk + (k - 1) * ncell);
+      MC_ADJ_TILES2(k_adj_mdf_cell, 0, G, W, T, A, A.Ukbar, A.Fgk + (k - 1) * ncell);
+    }
+    MC_ADJ_TILES2(k_adj_mdf_node, 1, G, W, T, A, nullptr);
+    MC_ADJ_TILES2(k_adj_mdf_cell, 1, G, W, T, A, A.Udbar, nullptr);
+  }
   MC_ADJ_PACK(k_adj_force, G, W, T, A);
-  MC_ADJ_TILES(k_adj_spread, G, W, T, A.Fbar, 1.f, A.Gbar);
+  MC_ADJ_TILES(k_adj_spread, G, W, T, A.Fbar, 1.f, nullptr, A.Gbar);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
   MC_ADJ_PACK(k_adj_pbd, G, W, T, A);
 }

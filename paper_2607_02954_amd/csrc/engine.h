@@ -175,9 +175,22 @@ struct AdjDev {
   float* sbar;            // [ny][nx]
   float* Fbar;            // [2][N]
   float* g_rest;          // [N] accumulated dL/d(rest angle)
+  // multi-direct forcing (binned worlds with mdf_iters > 1)
+  int mdf;                // the world's MDF iterations K (1: none; the rest unused)
+  const float* F;         // [2][N] the step's total node forces (tape)
+  float2* Fgk;            // [K-1][ny][nx] the iterates F_grid_1 .. F_grid_{K-1}, recomputed
+  float* Ud;              // [2][N] desired node velocity, recomputed
+  float* mc;              // [2][N] the correction of an iterate, recomputed
+  float* Ukbar;           // [2][N] dL/d(velocity sampled at the nodes) of one iteration
+  float* Udbar;           // [2][N] dL/dU_d
+  float* xbar_m;          // [2][N] the MDF transfers' terms of dL/dx_t
+  float2* jbar;           // [ny][nx] dL/dj through MDF
+  float* rhobar;          // [ny][nx] dL/drho through MDF
 };
+void launch_mdf_moments(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 
-void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, hipStream_t s);
+void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, size_t ncell,
+                         size_t n_part, hipStream_t s);
 void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int which, const AdjDev& A,
                           const float* v, float2* out, hipStream_t s);
 

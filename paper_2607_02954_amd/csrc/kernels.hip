@@ -1848,6 +1848,10 @@ void launch_markers(const WorldDev* W, const Tables& T, const Grid& G, hipStream
     if ((G).tile_blocks[2] > 0) KERNEL<64><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
   } while (0)
 
+void launch_mdf_moments(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
+  k_mdf_moments<<<G.item_blocks, 256, 0, s>>>(W, T);
+}
+
 void launch_mdf(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.mdf_max <= 1) return;
   k_mdf_moments<<<G.item_blocks, 256, 0, s>>>(W, T);

@@ -1480,6 +1480,15 @@ struct AdjLayout {
   float* sbar = nullptr;
   float* Fbar = nullptr;
   mc::Ctl* ctl = nullptr;            // m + 1 control words: step j reads ctl[j], writes ctl[j + 1]
+  // multi-direct forcing (worlds with mdf_iters K > 1)
+  float2* Fgk = nullptr;             // [K-1][ncell] recomputed iterates
+  float* Ud = nullptr;               // [2][N]
+  float* mc = nullptr;               // [2][N]
+  float* Ukbar = nullptr;            // [2][N]
+  float* Udbar = nullptr;            // [2][N]
+  float* xbar_m = nullptr;           // [2][N]
+  float2* jbar = nullptr;            // [ncell]
+  float* rhobar = nullptr;           // [ncell]
 };
 
 void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) {
@@ -1523,6 +1532,16 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
   L.sbar = c.take<float>(L.ncell);
   L.Fbar = c.take<float>(2 * L.N);
   L.ctl = c.take<mc::Ctl>(m + 1);
+  if (p.mdf_iters > 1) {
+    L.Fgk = c.take<float2>((size_t)(p.mdf_iters - 1) * L.ncell);
+    L.Ud = c.take<float>(2 * L.N);
+    L.mc = c.take<float>(2 * L.N);
+    L.Ukbar = c.take<float>(2 * L.N);
+    L.Udbar = c.take<float>(2 * L.N);
+    L.xbar_m = c.take<float>(2 * L.N);
+    L.jbar = c.take<float2>(L.ncell);
+    L.rhobar = c.take<float>(L.ncell);
+  }
   L.bytes = c.off;
 }
 
@@ -1554,7 +1573,6 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
                 mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
   if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
   if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
-  if (s.p.mdf_iters > 1) return fail(SIM_E_INVALID, "sim_backward does not differentiate multi-direct forcing");
   if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   size_t need = 0;
   sim_backward_workspace_size(w, ckpt_every, &need);
@@ -1648,7 +1666,17 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
       A.sbar = L.sbar;
       A.Fbar = L.Fbar;
       A.g_rest = g_rest_angle;
-      mc::launch_adjoint_step(L.desc + j, e.tab, g, A, st);
+      A.mdf = std::max(s.p.mdf_iters, 1);
+      A.F = L.F[j];
+      A.Fgk = L.Fgk;
+      A.Ud = L.Ud;
+      A.mc = L.mc;
+      A.Ukbar = L.Ukbar;
+      A.Udbar = L.Udbar;
+      A.xbar_m = L.xbar_m;
+      A.jbar = L.jbar;
+      A.rhobar = L.rhobar;
+      mc::launch_adjoint_step(L.desc + j, e.tab, g, A, ncell, N, st);
       cur = 1 - cur;
     }
     HIPCHK(hipGetLastError());

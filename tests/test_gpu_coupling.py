@@ -7,7 +7,7 @@ Per step: e_x <= 1e-5, e_u <= 1e-4 and each step's displacement e_d <= 1e-4
 from the GPU's state, for one and two layers, one to eight MDF iterations,
 every tile side, chains and loops; the combinations that are not built are
 refused (MDF on the sorted transfer, two layers off the direct transfer, the
-adjoint of MDF); the allocation-free step and a batch of direct and binned
+adjoint off the binned transfer); the allocation-free step and a batch of direct and binned
 MDF worlds give the single world's results (to the parity bar: the direct
 transfer sums with float atomics).
 """
@@ -48,7 +48,8 @@ def test_unbuilt_combinations_are_refused():
         with pytest.raises(sim.SimError) as ei:
             sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw))
         assert ei.value.status == sim.SIM_E_INVALID
-    W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny, mdf_iters=3))
+    # the adjoint takes MDF on the binned transfer only
+    W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer="direct", mdf_iters=3))
     ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
     with pytest.raises(sim.SimError) as ei:
         sim.Rollout.apply(ra, W, 0, 4, 2).sum().backward()
