@@ -159,6 +159,7 @@ struct Grid {
   int any_markers;                           // a world broadcasts two-layer markers
   int mdf_max;                               // most MDF iterations of any world (1: none)
   int general;                               // a world passes loop flags or per-edge stiffnesses
+  int branches;                              // a world has branches (filaments hanging from nodes)
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at

@@ -46,9 +46,9 @@ namespace mc {
 // node's record in its home-tile bin (binned), home-cell key and rank
 // (sorted) or the density deposit with global atomics (direct).
 // ---------------------------------------------------------------------------
-// GEN: worlds may pass closed-loop flags, per-edge stiffness arrays and
-// branches; the plain variant serves open chains with the world's scalar
-// stiffnesses.
+// GEN: worlds may pass closed-loop flags and per-edge stiffness arrays, BR
+// (with GEN) branches as well; the plain variant serves open chains with the
+// world's scalar stiffnesses.
 //
 // Branches: the first node c0 of a filament that hangs from node p (of the
 // same pack: packs hold whole creatures) owns the attachment edge p -> c0,
@@ -57,12 +57,13 @@ namespace mc {
 // those at the first nodes (bending), and the attachment edges (position).
 // A node carries at most one attachment, so each of those phases touches
 // every angle and node once at most.
-template <int PACK, bool GEN>
+template <int PACK, bool GEN, bool BR>
 __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W, Tables T) {
+  static_assert(GEN || !BR, "branches take the general variant");
   __shared__ float s_th[PACK];
   __shared__ float s_dx[PACK];
   __shared__ float s_dy[PACK];
-  __shared__ float s_ta[GEN ? PACK : 1];
+  __shared__ float s_ta[BR ? PACK : 1];
   __shared__ int s_off[PACK + 1];
 
   const int npk = *T.n_packs;
@@ -162,8 +163,8 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
     bool att = false, att_cj = false, any_att = false;
     int p_l = 0, in_l = 0;
     float a_vx = 0.f, a_vy = 0.f, a_th = 0.f, a_ux = 1.f, a_uy = 0.f, a_L = 0.f, a_al = 0.f, a_be = 0.f;
-    if constexpr (GEN) {
-      const int par = (w.fil_parent && active && k == 0) ? glb(w.fil_parent)[fil] : -1;
+    if (BR && w.fil_parent) {                    // block-uniform: the pack's world
+      const int par = (active && k == 0) ? glb(w.fil_parent)[fil] : -1;
       att = par >= 0;
       if (att) {
         p_l = par - pk.node_begin;
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
         }
         __syncthreads();
       }
-      if (GEN && any_att) {                      // attachment joints: at p, then at c0
+      if (BR && any_att) {                       // attachment joints: at p, then at c0
         if (att) {
           const float t1 = s_th[in_l], t2 = s_ta[li];
           const float c = wrap_angle(t2 - t1) - a_al;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
         }
         __syncthreads();
       }
-      if (GEN && any_att) {                      // attachment edges p -> c0
+      if (BR && any_att) {                       // attachment edges p -> c0
         if (att) {
           const float d0x = s_dx[p_l], d0y = s_dy[p_l];
           const float d1x = s_dx[li], d1y = s_dy[li];
@@ -1753,16 +1754,21 @@ __global__ void k_set_ctl(Ctl* c, long long t, int remaining) {
   } while (0)
 
 void launch_elastic(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  if (G.general) {
+  if (G.branches) {
     if (G.pack == 256)
-      k_elastic<256, true><<<G.node_blocks, 256, 0, s>>>(W, T);
+      k_elastic<256, true, true><<<G.node_blocks, 256, 0, s>>>(W, T);
     else
-      k_elastic<1024, true><<<G.node_blocks, 1024, 0, s>>>(W, T);
+      k_elastic<1024, true, true><<<G.node_blocks, 1024, 0, s>>>(W, T);
+  } else if (G.general) {
+    if (G.pack == 256)
+      k_elastic<256, true, false><<<G.node_blocks, 256, 0, s>>>(W, T);
+    else
+      k_elastic<1024, true, false><<<G.node_blocks, 1024, 0, s>>>(W, T);
   } else {
     if (G.pack == 256)
-      k_elastic<256, false><<<G.node_blocks, 256, 0, s>>>(W, T);
+      k_elastic<256, false, false><<<G.node_blocks, 256, 0, s>>>(W, T);
     else
-      k_elastic<1024, false><<<G.node_blocks, 1024, 0, s>>>(W, T);
+      k_elastic<1024, false, false><<<G.node_blocks, 1024, 0, s>>>(W, T);
   }
 }
 

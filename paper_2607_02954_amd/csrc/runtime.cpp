@@ -505,6 +505,13 @@ struct Engine {
       grid.general = 1;
       more = true;
     }
+    bool branches = false;
+    for (const auto& sl : slots)
+      if (sl.used && sl.fil_parent) branches = true;
+    if (branches && !grid.branches) {
+      grid.branches = 1;
+      more = true;
+    }
     int max_r = 1;                          // the filter's LDS window is sized for this radius
     for (const auto& sl : slots)
       if (sl.used) max_r = std::max(max_r, sl.p.repulse_radius);
