@@ -27,14 +27,19 @@ namespace mc {
 
 constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registers
 
+static __device__ __forceinline__ const AdjDev& adj_of(const AdjArg& a, int world) {
+  return a.arr ? a.arr[world] : a.one;
+}
+
 // ---------------------------------------------------------------------------
 // Node -> grid spreads of adjoint node vectors (u~ and G~), tile-binned.
 // ---------------------------------------------------------------------------
-// out = add + scale S[v] (add may be null).
+// out = add + scale S[v], the operands chosen by `which`: 0 u~ = S[x~'],
+// 1 G~ = -k_rep S[F~], 2 the MDF iterate F_grid_1 = S[F], 3 the iterate
+// F_grid_{k+1} = F_grid_k + S[c_k], 4 the test hook's vector and grid.
 template <int TILE>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const WorldDev* __restrict__ W, Tables T,
-                                                                         const float* v, float scale_is_rep,
-                                                                         const float2* add, float2* out) {
+                                                                         AdjArg AA, int which, int k) {
   using C = TileCfg<TILE>;
   constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells;
   __shared__ __align__(16) long long s_x[kSpreadCells];
@@ -45,14 +50,34 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const Wo
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    const AdjDev& A = adj_of(AA, tl.x);
     const int nx = w.nx, ny = w.ny;
+    const size_t ncell = (size_t)nx * ny;
     const int x0 = tile_x(tl.y) * TILE;
     const int y0 = tile_y(tl.y) * TILE;
     const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
+    const float* v = A.dbg_v;
+    float scale = 1.0f;
+    const float2* add = nullptr;
+    float2* out = A.dbg_out;
+    if (which == 0) {
+      v = A.xbar_in;
+      out = A.ubar;
+    } else if (which == 1) {
+      v = A.Fbar;
+      scale = -w.k_rep;
+      out = A.Gbar;
+    } else if (which == 2) {
+      v = A.F;
+      out = A.Fgk;
+    } else if (which == 3) {
+      v = A.mc;
+      add = A.Fgk + (size_t)(k - 1) * ncell;
+      out = A.Fgk + (size_t)k * ncell;
+    }
     zero_lds_u64(s_x, kSpreadCells);
     zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
-    const float scale = scale_is_rep != 0.f ? -w.k_rep : 1.0f;
     tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
                                  spread_fetch<TILE>(w, x0, y0), nullptr);
     __syncthreads();
@@ -75,11 +100,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const Wo
 // S6 reversed: pull-streaming transpose and the TRT/Guo collision Jacobian
 // transposed, per cell.  Reads g_t, F_grid_t (tape) and u~ (from k_adj_u).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+__global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
   const int nit = *T.n_items;
   for (int it = blockIdx.x; it < nit; it += gridDim.x) {
     const int2 item = T.items[it];
     const WorldDev& w = W[item.x];
+    const AdjDev& A = adj_of(AA, item.x);
     const int nx = w.nx, ny = w.ny;
     const int ncell = nx * ny;
     const int c = item.y + threadIdx.x;
@@ -168,11 +194,12 @@ __global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W,
 // derivative of the three node<->grid transfers with respect to x_t.
 // ---------------------------------------------------------------------------
 template <int PACK>
-__global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+__global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
   const int npk = *T.n_packs;
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
+    const AdjDev& A = adj_of(AA, pk.world);
     const int gi = pk.node_begin + threadIdx.x;
     if (gi >= pk.node_end) continue;
     const int N = w.n_part, nx = w.nx, ny = w.ny;
@@ -247,7 +274,7 @@ __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__
 // ---------------------------------------------------------------------------
 template <int TILE>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const WorldDev* __restrict__ W, Tables T,
-                                                                         AdjDev A) {
+                                                                         AdjArg AA) {
   constexpr int kTile = TILE, kThreads = TileCfg<TILE>::kThreads;
   constexpr int kAdjRing = kTile + 2;
   constexpr int kAdjRegion = kAdjRing + 2 * kMaxRadius;
@@ -262,6 +289,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const Wo
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    const AdjDev& A = adj_of(AA, tl.x);
     const int R = w.radius;
     const int nx = w.nx, ny = w.ny;
     const int x0 = tile_x(tl.y) * kTile;
@@ -309,7 +337,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const Wo
 // S2 + S1 + S0 reversed, one block per node pack.
 // ---------------------------------------------------------------------------
 template <int PACK>
-__global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W, Tables T, AdjDev A) {
+__global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
   __shared__ float s_th[PACK];
   __shared__ float s_dx[PACK];
   __shared__ float s_dy[PACK];
@@ -322,6 +350,7 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
   for (int it = blockIdx.x; it < npk; it += gridDim.x) {
     const Pack pk = T.packs[it];
     const WorldDev& w = W[pk.world];
+    const AdjDev& A = adj_of(AA, pk.world);
     const int N = w.n_part, nx = w.nx, ny = w.ny;
     const MC_GLOBAL int* cell = glb(w.cell_in);
     const MC_GLOBAL float* frac = glb(w.frac_in);
@@ -544,13 +573,20 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 // fixed point.  The recomputed iterates use the forward's arithmetic and sums,
 // so they equal the forward's bit for bit.
 // ---------------------------------------------------------------------------
-__global__ void k_adj_zero(float* a, size_t na, float* b, size_t nb, float* c, size_t nc, float* d, size_t nd) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < na + nb + nc + nd;
+// Zero U_d~, the MDF position terms, j~ and rho~ of every world (blockIdx.y:
+// the world table entry).
+__global__ void k_adj_mdf_zero(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
+  if ((int)blockIdx.y >= *T.n_worlds) return;
+  const int wi = T.worlds[blockIdx.y].x;
+  const WorldDev& w = W[wi];
+  const AdjDev& A = adj_of(AA, wi);
+  const size_t n2 = 2 * (size_t)w.n_part, nc = (size_t)w.nx * w.ny;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 2 * n2 + 3 * nc;
        i += (size_t)gridDim.x * blockDim.x) {
-    if (i < na) a[i] = 0.f;
-    else if (i < na + nb) b[i - na] = 0.f;
-    else if (i < na + nb + nc) c[i - na - nb] = 0.f;
-    else d[i - na - nb - nc] = 0.f;
+    if (i < n2) A.Udbar[i] = 0.f;
+    else if (i < 2 * n2) A.xbar_m[i - n2] = 0.f;
+    else if (i < 2 * n2 + 2 * nc) ((float*)A.jbar)[i - 2 * n2] = 0.f;
+    else A.rhobar[i - 2 * n2 - 2 * nc] = 0.f;
   }
 }
 
@@ -577,8 +613,7 @@ static __device__ __forceinline__ void adj_stage(int nx, int ny, int x0, int y0,
 // U_d (DESIRED) or the correction c_k of the iterate Fgk at the tile's own nodes.
 template <int TILE, bool DESIRED>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(const WorldDev* __restrict__ W,
-                                                                                 Tables T, AdjDev A,
-                                                                                 const float2* Fgk) {
+                                                                                 Tables T, AdjArg AA, int k) {
   constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
   __shared__ vf2 s_u[kStage * kStage];
   const int nt = n_tiles<TILE>(T);
@@ -586,6 +621,8 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    const AdjDev& A = adj_of(AA, tl.x);
+    const float2* Fgk = A.Fgk + (size_t)(k > 0 ? k - 1 : 0) * ((size_t)w.nx * w.ny);   // iterate k (k >= 1)
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
@@ -646,7 +683,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(
 // MODE 1 (U_d): x~ += U_d~ . dI[j / rho]/dx.
 template <int TILE, int MODE>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const WorldDev* __restrict__ W, Tables T,
-                                                                           AdjDev A, const float2* Fgk) {
+                                                                           AdjArg AA, int k) {
   constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
   __shared__ vf2 s_g[MODE == 0 ? kStage * kStage : 1];
   __shared__ vf2 s_u[kStage * kStage];
@@ -655,6 +692,8 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const 
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    const AdjDev& A = adj_of(AA, tl.x);
+    const float2* Fgk = A.Fgk + (size_t)(k > 0 ? k - 1 : 0) * ((size_t)w.nx * w.ny);   // iterate k (k >= 1)
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
@@ -738,8 +777,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const 
 // (U_d): j~ += w~ / rho, rho~ -= w~ . (j / rho) / rho, and g~_q += rho~ + c_q . j~.
 template <int TILE, int MODE>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_cell(const WorldDev* __restrict__ W, Tables T,
-                                                                           AdjDev A, const float* nodevec,
-                                                                           const float2* Fgk) {
+                                                                           AdjArg AA, int k) {
   using C = TileCfg<TILE>;
   constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells;
   __shared__ __align__(16) long long s_x[kSpreadCells];
@@ -750,6 +788,9 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_cell(const 
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    const AdjDev& A = adj_of(AA, tl.x);
+    const float2* Fgk = A.Fgk + (size_t)(k > 0 ? k - 1 : 0) * ((size_t)w.nx * w.ny);   // iterate k (k >= 1)
+    const float* nodevec = MODE == 0 ? A.Ukbar : A.Udbar;
     const int nx = w.nx, ny = w.ny;
     const int ncell = nx * ny;
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
@@ -830,37 +871,40 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_cell(const 
 //    collision and streaming Jacobian transposed; A.ubar must be zero).
 void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int which, const AdjDev& A,
                           const float* v, float2* out, hipStream_t s) {
-  if (which == 0) MC_ADJ_TILES(k_adj_spread, G, W, T, v, 0.f, nullptr, out);
-  else if (which == 1) MC_ADJ_TILES(k_adj_filter, G, W, T, A);
-  else k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
+  AdjArg a{};
+  a.arr = nullptr;
+  a.one = A;
+  a.one.dbg_v = v;
+  a.one.dbg_out = out;
+  if (which == 0) MC_ADJ_TILES(k_adj_spread, G, W, T, a, 4, 0);
+  else if (which == 1) MC_ADJ_TILES(k_adj_filter, G, W, T, a);
+  else k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, a);
 }
 
-void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, size_t ncell,
-                         size_t n_part, hipStream_t s) {
-  MC_ADJ_TILES(k_adj_spread, G, W, T, A.xbar_in, 0.f, nullptr, A.ubar);
+void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjArg& A, int mdf, hipStream_t s) {
+  MC_ADJ_TILES(k_adj_spread, G, W, T, A, 0, 0);
   k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
-  if (A.mdf > 1) {
+  if (mdf > 1) {
     // recompute the step's MDF: moments, U_d, F_grid_1 = S[F], then
     // F_grid_{k+1} = F_grid_k + S[c_k] up to K - 1
     launch_mdf_moments(W, T, G, s);
-    k_adj_zero<<<64, 256, 0, s>>>(A.Udbar, 2 * n_part, A.xbar_m, 2 * n_part, (float*)A.jbar, 2 * ncell, A.rhobar,
-                                  ncell);
-    MC_ADJ_TILES2(k_adj_mdf_fwd_gather, true, G, W, T, A, nullptr);
-    MC_ADJ_TILES(k_adj_spread, G, W, T, A.F, 0.f, nullptr, A.Fgk);
-    for (int k = 1; k <= A.mdf - 2; ++k) {
-      MC_ADJ_TILES2(k_adj_mdf_fwd_gather, false, G, W, T, A, A.Fgk + (k - 1) * ncell);
-      MC_ADJ_TILES(k_adj_spread, G, W, T, A.mc, 0.f, A.Fgk + (k - 1) * ncell, A.Fgk + k * ncell);
+    k_adj_mdf_zero<<<dim3(32, G.world_blocks), 256, 0, s>>>(W, T, A);
+    MC_ADJ_TILES2(k_adj_mdf_fwd_gather, true, G, W, T, A, 0);
+    MC_ADJ_TILES(k_adj_spread, G, W, T, A, 2, 0);
+    for (int k = 1; k <= mdf - 2; ++k) {
+      MC_ADJ_TILES2(k_adj_mdf_fwd_gather, false, G, W, T, A, k);
+      MC_ADJ_TILES(k_adj_spread, G, W, T, A, 3, k);
     }
-    // reverse: iterations K - 1 .. 1 (A.Fgbar becomes dL/dF_grid_k), then U_d
-    for (int k = A.mdf - 1; k >= 1; --k) {
-      MC_ADJ_TILES2(k_adj_mdf_node, 0, G, W, T, A, A.Fgk + (k - 1) * ncell);
-      MC_ADJ_TILES2(k_adj_mdf_cell, 0, G, W, T, A, A.Ukbar, A.Fgk + (k - 1) * ncell);
+    // reverse: iterations K - 1 .. 1 (the grid-force adjoint becomes dL/dF_grid_k), then U_d
+    for (int k = mdf - 1; k >= 1; --k) {
+      MC_ADJ_TILES2(k_adj_mdf_node, 0, G, W, T, A, k);
+      MC_ADJ_TILES2(k_adj_mdf_cell, 0, G, W, T, A, k);
     }
-    MC_ADJ_TILES2(k_adj_mdf_node, 1, G, W, T, A, nullptr);
-    MC_ADJ_TILES2(k_adj_mdf_cell, 1, G, W, T, A, A.Udbar, nullptr);
+    MC_ADJ_TILES2(k_adj_mdf_node, 1, G, W, T, A, 0);
+    MC_ADJ_TILES2(k_adj_mdf_cell, 1, G, W, T, A, 0);
   }
   MC_ADJ_PACK(k_adj_force, G, W, T, A);
-  MC_ADJ_TILES(k_adj_spread, G, W, T, A.Fbar, 1.f, nullptr, A.Gbar);
+  MC_ADJ_TILES(k_adj_spread, G, W, T, A, 1, 0);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
   MC_ADJ_PACK(k_adj_pbd, G, W, T, A);
 }

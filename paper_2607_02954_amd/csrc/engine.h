@@ -187,11 +187,18 @@ struct AdjDev {
   float* xbar_m;          // [2][N] the MDF transfers' terms of dL/dx_t
   float2* jbar;           // [ny][nx] dL/dj through MDF
   float* rhobar;          // [ny][nx] dL/drho through MDF
+  const float* dbg_v;     // test hook: the node vector a single spread reads
+  float2* dbg_out;        // and the grid it writes
+};
+// The adjoint buffers of the worlds of a launch: one set (arr null: a single
+// world) or an array indexed by the world of each work item (a set of worlds).
+struct AdjArg {
+  const AdjDev* arr;
+  AdjDev one;
 };
 void launch_mdf_moments(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s);
 
-void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjDev& A, size_t ncell,
-                         size_t n_part, hipStream_t s);
+void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjArg& A, int mdf, hipStream_t s);
 void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int which, const AdjDev& A,
                           const float* v, float2* out, hipStream_t s);
 

@@ -1683,7 +1683,10 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
       A.xbar_m = L.xbar_m;
       A.jbar = L.jbar;
       A.rhobar = L.rhobar;
-      mc::launch_adjoint_step(L.desc + j, e.tab, g, A, ncell, N, st);
+      mc::AdjArg a{};
+      a.arr = nullptr;
+      a.one = A;
+      mc::launch_adjoint_step(L.desc + j, e.tab, g, a, A.mdf, st);
       cur = 1 - cur;
     }
     HIPCHK(hipGetLastError());
