@@ -246,7 +246,7 @@ def bench_adjoint(seed, reps=5):
             bwd.append(b0.elapsed_time(b1))
     W.close()
     pm, fm, bm = float(np.median(plain)), float(np.median(fwd)), float(np.median(bwd))
-    return {
+    out = {
         "workload": "folding: 64 chains x 48 nodes on 256x256, 200 steps, checkpoints every 20, "
                     "gradient of the target-fold loss in the rest angles",
         "plain_rollout_ms": pm,
@@ -256,6 +256,43 @@ def bench_adjoint(seed, reps=5):
         "bwd_over_plain_fwd": bm / pm,
         "loss": float(loss.detach()),
     }
+    out["set_of_worlds"] = bench_adjoint_set(seed, n, k, fm + bm, reps=max(2, reps // 2))
+    return out
+
+
+def bench_adjoint_set(seed, n, k, alone_ms, n_worlds=16, reps=2):
+    """The same differentiation for 16 folding worlds (seeds seed..seed+15)
+    stepped and reversed together as one set of worlds (sim_create_set): one
+    forward with checkpoints and one backward for all of them, against 16
+    times the single world's forward + backward."""
+    worlds = [wl.folding_population(seed + i) for i in range(n_worlds)]
+    p = sim.Params(nx=worlds[0].nx, ny=worlds[0].ny)
+    S = sim.WorldSet(worlds, p)
+    tg = [torch.tensor(w.target, dtype=torch.float64, device="cuda") for w in worlds]
+    init = [(st.cell.clone(), st.frac.clone()) for st in S.states]
+    ra0 = torch.tensor(np.concatenate([w.rest_angle for w in worlds]), dtype=torch.float64, device="cuda")
+    times = []
+    for r in range(reps + 1):
+        for st, (c0, f0) in zip(S.states, init):
+            st.cell.copy_(c0)
+            st.frac.copy_(f0)
+            st.f.zero_()
+        ra = ra0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = sim.SetRollout.apply(ra, S, 0, n, k)
+        off, loss = 0, 0.0
+        for t, m in zip(tg, S.n_parts):
+            loss = loss + ((x[off:off + 2 * m].reshape(2, m) - t) ** 2).sum() / m
+            off += 2 * m
+        loss.backward()
+        torch.cuda.synchronize()
+        if r:
+            times.append(1000.0 * (time.perf_counter() - t0))
+    S.close()
+    ms = float(np.median(times))
+    return {"worlds": n_worlds, "forward_plus_backward_ms": ms, "per_world_ms": ms / n_worlds,
+            "alone_per_world_ms": alone_ms, "speedup_over_alone": alone_ms * n_worlds / ms}
 
 
 def bench_density_folding(seed, reps=3):

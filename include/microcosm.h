@@ -195,6 +195,23 @@ sim_status sim_workspace_size(const sim_params *p, int32_t n_filaments, int32_t 
 sim_status sim_create(const sim_params *p, const sim_arrays *a, void *workspace, size_t ws_bytes,
                       void *stream, sim_world **out);
 
+/* A set of n_worlds worlds with the same parameters, each with its own
+ * arrays (arrays: a host array of n_worlds sim_arrays), stepped together in
+ * the same kernel launches: for differentiating many small worlds at once
+ * (a population of creatures, Experiments: Filament Folding and the search
+ * experiments), where one world's kernels would leave the device idle.
+ * sim_step, sim_rollout, sim_checkpoint_size, sim_backward_workspace_size,
+ * sim_backward, sim_sync, sim_clear_flags and sim_destroy take a set as they
+ * take one world, with every world's part of the caller's buffers one after
+ * another in world order: checkpoints (each world's segments, world 0
+ * first), g_pos and g_pos0 ([2][N_w] per world), g_rest_angle ([N_w] per
+ * world).  The test and measurement hooks (sim_debug_*, sim_profile_steps)
+ * refuse sets.  Workspace: sim_set_workspace_size; errors as sim_create. */
+sim_status sim_set_workspace_size(const sim_params *p, int32_t n_worlds, const sim_arrays *arrays,
+                                  size_t *bytes);
+sim_status sim_create_set(const sim_params *p, int32_t n_worlds, const sim_arrays *arrays,
+                          void *workspace, size_t ws_bytes, void *stream, sim_world **out);
+
 /* One step at time index t (S0-S7).  Positions, f and u are updated in the
  * caller's arrays when the stream reaches the end of the call. */
 sim_status sim_step(sim_world *w, int64_t t);

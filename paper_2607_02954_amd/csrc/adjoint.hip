@@ -395,7 +395,7 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     if (is_joint) {
       const int f = pk.fil_begin + lo;
       th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[f], glb(w.act_period)[f],
-                              glb(w.act_phase)[f], A.t, j, n - 2);
+                              glb(w.act_phase)[f], w.ctl_src->t, j, n - 2);
     }
     // dL/dx_t so far (written by k_adj_force) plus the deposit derivative
     float xbx = 0.f, xby = 0.f;

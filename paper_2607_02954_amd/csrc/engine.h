@@ -163,9 +163,9 @@ struct Grid {
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at
-// t+1); the kernels produce dL/d(state at t).
+// t+1); the kernels produce dL/d(state at t).  The step's time index is the
+// one its descriptor's control word holds after the recomputed forward.
 struct AdjDev {
-  long long t;            // time index of the step being reversed
   const float* xbar_in;   // [2][N]
   float* xbar;            // [2][N]
   const float* gbar_in;   // [9][ny][nx]

@@ -805,17 +805,10 @@ sim_status sim_workspace_size(const sim_params* p, int32_t n_filaments, int32_t 
   return SIM_OK;
 }
 
-sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace, size_t ws_bytes, void* stream,
-                      sim_world** out) {
-  sim_status st = check_params(p);
-  if (st) return st;
-  if ((st = check_arrays(a))) return st;
-  if (!out) return fail(SIM_E_INVALID, "out is NULL");
-  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(SIM_E_WORKSPACE, "workspace must be 256-byte aligned");
-  size_t need = 0;
-  sim_workspace_size(p, a->n_filaments, a->n_particles, &need);
-  if (ws_bytes < need) return fail(SIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-  hipStream_t s = (hipStream_t)stream;
+// One world of a handle: validate and read its arrays' host-side facts
+// (offsets, branches, loops) and carve its buffers.
+static sim_status prepare_slot(const sim_params* p, const sim_arrays* a, hipStream_t s, Carver& c, Slot& sl) {
+  sim_status st;
   std::vector<int> h_off;
   if (a->n_filaments > 0) {
     if ((st = read_offsets(a, s, h_off))) return st;
@@ -829,24 +822,6 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   if (max_len > mc::kMaxFilament)
     return fail(SIM_E_INVALID, "a creature (a filament with those hanging from it) holds %d nodes; at most %d",
                 max_len, mc::kMaxFilament);
-
-  sim_world* w = new sim_world();
-  w->arr = *a;
-  w->ws = workspace;
-  w->ws_bytes = ws_bytes;
-  Engine& e = w->eng;
-  e.stream = s;
-  e.max_worlds = 1;
-  const size_t ncell = (size_t)p->nx * p->ny;
-  e.max_packs = std::max(a->n_filaments, 1);
-  e.max_tiles[tile_family(*p)] = (size_t)tiles_x(*p) * tiles_y(*p);
-  e.max_items = (ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem;
-  e.max_scan = (ncell + 1023) / 1024;
-  e.grid.pack = max_len <= 256 ? 256 : 1024;
-  e.tab.single_ntx[tile_family(*p)] = tiles_x(*p);   // one world: tile entries are computed
-  Carver c{(char*)workspace};
-  e.carve_tables(c);
-  Slot sl;
   sl.used = true;
   sl.p = *p;
   sl.n_fil = a->n_filaments;
@@ -872,35 +847,75 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   sl.energy = a->energy;
   sl.e_sensed = a->energy_sensed;
   sl.e_collected = a->energy_collected;
-  if ((st = read_loops(a, s, &sl.any_loop))) {
-    delete w;
-    return st;
-  }
+  if ((st = read_loops(a, s, &sl.any_loop))) return st;
   carve_world_bufs(c, *p, a->n_particles, sl.b);
   sl.fbuf[0] = a->f;
   sl.fbuf[1] = sl.b.f_alt;
   sl.u = a->u;
-  e.slots.push_back(sl);
-  if ((st = e.init_host(64 << 10))) {
-    delete w;
-    return st;
-  }
-  // clear flags, control words and (sorted mode) the per-cell counters
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.flags, (size_t)1);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[0], sizeof(mc::Ctl) / 4);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[1], sizeof(mc::Ctl) / 4);
+  return SIM_OK;
+}
+
+// Clear what a world's kernels expect to start at zero and build its tile
+// run tables.
+static void init_slot_buffers(const Slot& sl, hipStream_t s) {
+  const sim_params& p = sl.p;
+  const size_t ncell = (size_t)p.nx * p.ny;
   if (sl.b.cnt) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, sl.b.cnt, ncell);
   if (sl.b.s) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.s, ncell);
   if (sl.b.Fg) hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, (int*)sl.b.Fg, 2 * ncell);
   if (sl.b.e_node)
-    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)sl.b.e_node, (size_t)std::max(a->n_particles, 1));
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, (int*)sl.b.e_node, (size_t)std::max(sl.n_part, 1));
   if (sl.b.bin_cnt) {
-    const size_t nt = n_bins(*p);
+    const size_t nt = n_bins(p);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_cnt, nt);
     hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.bin_fill, nt);
-    mc::launch_tile_ranges(p->nx, p->ny, p->repulse_radius, tile_side(*p), sl.b.tile_rng, s);
-    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.sp_cnt, (size_t)tiles_x(*p) * tiles_y(*p));
+    mc::launch_tile_ranges(p.nx, p.ny, p.repulse_radius, tile_side(p), sl.b.tile_rng, s);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, sl.b.sp_cnt, (size_t)tiles_x(p) * tiles_y(p));
   }
+}
+
+// A handle over n worlds with the same parameters (n = 1: sim_create).
+static sim_status create_worlds(const sim_params* p, int n, const sim_arrays* arrays, void* workspace,
+                                size_t ws_bytes, void* stream, sim_world** out) {
+  hipStream_t s = (hipStream_t)stream;
+  sim_world* w = new sim_world();
+  w->arr = arrays[0];
+  w->ws = workspace;
+  w->ws_bytes = ws_bytes;
+  Engine& e = w->eng;
+  e.stream = s;
+  e.max_worlds = n;
+  const size_t ncell = (size_t)p->nx * p->ny;
+  size_t packs = 0;
+  for (int i = 0; i < n; ++i) packs += std::max(arrays[i].n_filaments, 1);
+  e.max_packs = packs;
+  e.max_tiles[tile_family(*p)] = (size_t)n * tiles_x(*p) * tiles_y(*p);
+  e.max_items = (size_t)n * ((ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem);
+  e.max_scan = (size_t)n * ((ncell + 1023) / 1024);
+  if (n == 1) e.tab.single_ntx[tile_family(*p)] = tiles_x(*p);   // one world: tile entries are computed
+  Carver c{(char*)workspace};
+  e.carve_tables(c);
+  int max_len = 0;
+  sim_status st;
+  for (int i = 0; i < n; ++i) {
+    Slot sl;
+    if ((st = prepare_slot(p, &arrays[i], s, c, sl))) {
+      delete w;
+      return st;
+    }
+    max_len = std::max(max_len, sl.max_len);
+    e.slots.push_back(sl);
+  }
+  e.grid.pack = max_len <= 256 ? 256 : 1024;
+  if ((st = e.init_host(64 << 10))) {
+    delete w;
+    return st;
+  }
+  // clear flags and control words, then each world's counters and tables
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.flags, (size_t)n);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[0], n * sizeof(mc::Ctl) / 4);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int*)e.ctl[1], n * sizeof(mc::Ctl) / 4);
+  for (const Slot& sl : e.slots) init_slot_buffers(sl, s);
   if (hipGetLastError() != hipSuccess) {
     delete w;
     return fail(SIM_E_HIP, "initialisation kernels failed to launch");
@@ -913,18 +928,72 @@ sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace,
   return SIM_OK;
 }
 
+sim_status sim_create(const sim_params* p, const sim_arrays* a, void* workspace, size_t ws_bytes, void* stream,
+                      sim_world** out) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_arrays(a))) return st;
+  if (!out) return fail(SIM_E_INVALID, "out is NULL");
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(SIM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  sim_workspace_size(p, a->n_filaments, a->n_particles, &need);
+  if (ws_bytes < need) return fail(SIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return create_worlds(p, 1, a, workspace, ws_bytes, stream, out);
+}
+
+sim_status sim_set_workspace_size(const sim_params* p, int32_t n_worlds, const sim_arrays* arrays, size_t* bytes) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if (n_worlds < 1 || !arrays || !bytes) return fail(SIM_E_INVALID, "need n_worlds >= 1 and non-NULL arrays, bytes");
+  const size_t ncell = (size_t)p->nx * p->ny;
+  size_t packs = 0, bufs = 0;
+  for (int i = 0; i < n_worlds; ++i) {
+    if (arrays[i].n_filaments < 0 || arrays[i].n_particles < 0) return fail(SIM_E_INVALID, "negative sizes");
+    packs += std::max(arrays[i].n_filaments, 1);
+    bufs += world_buf_bytes(*p, arrays[i].n_particles);
+  }
+  size_t tiles[mc::kTileFamilies] = {0, 0, 0};
+  tiles[tile_family(*p)] = (size_t)n_worlds * tiles_x(*p) * tiles_y(*p);
+  const size_t items = (size_t)n_worlds * ((ncell + mc::kCellsPerItem - 1) / mc::kCellsPerItem);
+  const size_t scans = (size_t)n_worlds * ((ncell + 1023) / 1024);
+  *bytes = Engine::table_bytes(n_worlds, packs, tiles, items, scans) + bufs;
+  return SIM_OK;
+}
+
+sim_status sim_create_set(const sim_params* p, int32_t n_worlds, const sim_arrays* arrays, void* workspace,
+                          size_t ws_bytes, void* stream, sim_world** out) {
+  sim_status st = check_params(p);
+  if (st) return st;
+  if (n_worlds < 1 || !arrays) return fail(SIM_E_INVALID, "need n_worlds >= 1 and non-NULL arrays");
+  for (int i = 0; i < n_worlds; ++i)
+    if ((st = check_arrays(&arrays[i]))) return st;
+  if (!out) return fail(SIM_E_INVALID, "out is NULL");
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return fail(SIM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  if ((st = sim_set_workspace_size(p, n_worlds, arrays, &need))) return st;
+  if (ws_bytes < need) return fail(SIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return create_worlds(p, n_worlds, arrays, workspace, ws_bytes, stream, out);
+}
+
 static sim_status world_run(sim_world* w, int64_t t, int n) {
   Engine& e = w->eng;
-  Slot& s = e.slots[0];
   sim_status st;
-  if ((st = e.set_ctl(0, t, n))) return st;
+  for (int k = 0; k < (int)e.slots.size(); ++k)
+    if ((st = e.set_ctl(k, t, n))) return st;
   if ((st = e.run_steps(n))) return st;
   if (n & 1) {
-    // the state ended in the alternate populations buffer: copy it back
-    const size_t ncell = (size_t)s.p.nx * s.p.ny;
-    HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
+    // the state ended in the alternate populations buffers: copy them back
+    for (const Slot& s : e.slots) {
+      const size_t ncell = (size_t)s.p.nx * s.p.ny;
+      HIPCHK(hipMemcpyAsync(s.fbuf[0], s.fbuf[1], 9 * ncell * sizeof(float), hipMemcpyDeviceToDevice, e.stream));
+    }
   }
   return SIM_OK;
+}
+
+// Bytes of one checkpoint (positions and populations) of a world.
+static size_t ckpt_per_world(const Slot& s) {
+  return align_up(4 * (size_t)s.n_part * 4) + align_up(9 * (size_t)s.p.nx * s.p.ny * 4);
 }
 
 sim_status sim_step(sim_world* w, int64_t t) {
@@ -935,10 +1004,10 @@ sim_status sim_step(sim_world* w, int64_t t) {
 sim_status sim_checkpoint_size(const sim_world* w, int32_t n_steps, int32_t ckpt_every, size_t* bytes) {
   if (!w || !bytes) return fail(SIM_E_INVALID, "NULL argument");
   if (n_steps < 0 || ckpt_every <= 0) return fail(SIM_E_INVALID, "need n_steps >= 0 and ckpt_every > 0");
-  const Slot& s = w->eng.slots[0];
-  const size_t nseg = (size_t)(n_steps + ckpt_every - 1) / ckpt_every;
-  const size_t per = align_up(4 * (size_t)s.n_part * 4) + align_up(9 * (size_t)s.p.nx * s.p.ny * 4);
-  *bytes = std::max<size_t>(nseg, 1) * per;
+  const size_t nseg = std::max<size_t>((size_t)(n_steps + ckpt_every - 1) / ckpt_every, 1);
+  size_t total = 0;
+  for (const Slot& s : w->eng.slots) total += nseg * ckpt_per_world(s);   // the worlds' blocks, one after another
+  *bytes = total;
   return SIM_OK;
 }
 
@@ -952,18 +1021,20 @@ sim_status sim_rollout(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_e
   sim_checkpoint_size(w, n_steps, ckpt_every, &need);
   if (ckpt_bytes < need) return fail(SIM_E_WORKSPACE, "checkpoint buffer has %zu bytes, needs %zu", ckpt_bytes, need);
   Engine& e = w->eng;
-  Slot& s = e.slots[0];
-  const size_t N = s.n_part, ncell = (size_t)s.p.nx * s.p.ny;
-  const size_t per = align_up(4 * N * 4) + align_up(9 * ncell * 4);
-  char* base = (char*)ckpt;
+  const size_t nseg = std::max<size_t>((size_t)(n_steps + ckpt_every - 1) / ckpt_every, 1);
   int seg = 0;
   for (int k = 0; k < n_steps; k += ckpt_every, ++seg) {
-    char* dst = base + seg * per;
-    if (N) {
-      HIPCHK(hipMemcpyAsync(dst, s.cell, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
-      HIPCHK(hipMemcpyAsync(dst + 2 * N * 4, s.frac, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+    char* block = (char*)ckpt;
+    for (const Slot& s : e.slots) {
+      const size_t N = s.n_part, ncell = (size_t)s.p.nx * s.p.ny, per = ckpt_per_world(s);
+      char* dst = block + seg * per;
+      if (N) {
+        HIPCHK(hipMemcpyAsync(dst, s.cell, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+        HIPCHK(hipMemcpyAsync(dst + 2 * N * 4, s.frac, 2 * N * 4, hipMemcpyDeviceToDevice, e.stream));
+      }
+      HIPCHK(hipMemcpyAsync(dst + align_up(4 * N * 4), s.fbuf[0], 9 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
+      block += nseg * per;
     }
-    HIPCHK(hipMemcpyAsync(dst + align_up(4 * N * 4), s.fbuf[0], 9 * ncell * 4, hipMemcpyDeviceToDevice, e.stream));
     sim_status st = world_run(w, t0 + k, std::min(ckpt_every, n_steps - k));
     if (st) return st;
   }
@@ -975,8 +1046,10 @@ sim_status sim_sync(sim_world* w) {
   Engine& e = w->eng;
   HIPCHK(hipStreamSynchronize(e.stream));
   HIPCHK(hipGetLastError());
+  std::vector<unsigned> fl(std::max<size_t>(e.slots.size(), 1), 0u);
+  HIPCHK(hipMemcpy(fl.data(), e.flags, fl.size() * sizeof(unsigned), hipMemcpyDeviceToHost));
   unsigned f = 0;
-  HIPCHK(hipMemcpy(&f, e.flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+  for (unsigned v : fl) f |= v;
   if (f & mc::kFlagBins) return fail(SIM_E_STATE, "node positions changed without a tile-bin pre-pass");
   if (f) return fail(SIM_E_UNSTABLE, "world produced NaN or |u| > u_max");
   return SIM_OK;
@@ -984,7 +1057,7 @@ sim_status sim_sync(sim_world* w) {
 
 sim_status sim_clear_flags(sim_world* w) {
   if (!w) return fail(SIM_E_INVALID, "world is NULL");
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, w->eng.stream, (int*)w->eng.flags, (size_t)1);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, w->eng.stream, (int*)w->eng.flags, w->eng.slots.size());
   HIPCHK(hipGetLastError());
   return SIM_OK;
 }
@@ -993,6 +1066,7 @@ void sim_destroy(sim_world* w) { delete w; }
 
 sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
   if (!w) return fail(SIM_E_INVALID, "world is NULL");
+  if (w->eng.slots.size() != 1) return fail(SIM_E_INVALID, "a single world only");
   Engine& e = w->eng;
   sim_status st;
   if ((st = e.set_ctl(0, t, 1))) return st;
@@ -1029,6 +1103,7 @@ sim_status sim_debug_substep(sim_world* w, int32_t which, int64_t t) {
 }
 
 sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* ms_out) {
+  if (w && w->eng.slots.size() != 1) return fail(SIM_E_INVALID, "a single world only");
   if (!w || !ms_out) return fail(SIM_E_INVALID, "NULL argument");
   if (n_steps < 1) return fail(SIM_E_INVALID, "n_steps must be >= 1");
   Engine& e = w->eng;
@@ -1087,6 +1162,7 @@ sim_status sim_profile_steps(sim_world* w, int64_t t0, int32_t n_steps, float* m
 }
 
 sim_status sim_debug_adjoint(sim_world* w, int32_t which, const void* in, void* out, void* scratch) {
+  if (w && w->eng.slots.size() != 1) return fail(SIM_E_INVALID, "a single world only");
   if (!w || !in || !out) return fail(SIM_E_INVALID, "NULL argument");
   Engine& e = w->eng;
   const Slot& s = e.slots[0];
@@ -1111,6 +1187,7 @@ sim_status sim_debug_adjoint(sim_world* w, int32_t which, const void* in, void* 
 }
 
 sim_status sim_debug_buffer(sim_world* w, int32_t which, void** ptr) {
+  if (w && w->eng.slots.size() != 1) return fail(SIM_E_INVALID, "a single world only");
   if (!w || !ptr) return fail(SIM_E_INVALID, "NULL argument");
   const Slot& s = w->eng.slots[0];
   switch (which) {
@@ -1478,7 +1555,6 @@ struct AdjLayout {
   std::vector<int4*> brec;     // m slots of [N]
   int* bin_cnt = nullptr;
   int* bin_fill = nullptr;
-  mc::WorldDev* desc = nullptr;      // m descriptors
   float* xbar[2] = {};
   float* gbar[2] = {};
   float2* ubar = nullptr;
@@ -1528,7 +1604,6 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
   L.bstart[m] = c.take<int>(L.nt + 1);
   L.bin_cnt = c.take<int>(L.nt);
   L.bin_fill = c.take<int>(L.nt);
-  L.desc = c.take<mc::WorldDev>(m);
   for (int k = 0; k < 2; ++k) {
     L.xbar[k] = c.take<float>(2 * L.N);
     L.gbar[k] = c.take<float>(9 * L.ncell);
@@ -1556,14 +1631,30 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
 
 extern "C" {
 
+// The adjoint workspace of a handle: each world's tape and buffers, then the
+// per-step descriptors [m][worlds] and adjoint buffer sets [m][2][worlds]
+// (by the parity of the adjoint state).
+struct AdjShared {
+  mc::WorldDev* desc = nullptr;
+  mc::AdjDev* adj = nullptr;
+};
+
+static size_t carve_backward(Carver& c, const Engine& e, int m, std::vector<AdjLayout>& Ls, AdjShared& S) {
+  const size_t nw = e.slots.size();
+  Ls.assign(nw, AdjLayout());
+  for (size_t w = 0; w < nw; ++w) carve_adj(c, e.slots[w].p, e.slots[w].n_part, m, Ls[w]);
+  S.desc = c.take<mc::WorldDev>((size_t)m * nw);
+  S.adj = c.take<mc::AdjDev>((size_t)2 * m * nw);
+  return c.off;
+}
+
 sim_status sim_backward_workspace_size(const sim_world* w, int32_t ckpt_every, size_t* bytes) {
   if (!w || !bytes) return fail(SIM_E_INVALID, "NULL argument");
   if (ckpt_every < 1) return fail(SIM_E_INVALID, "ckpt_every must be >= 1");
-  const Slot& s = w->eng.slots[0];
   Carver c{nullptr};
-  AdjLayout L;
-  carve_adj(c, s.p, s.n_part, ckpt_every, L);
-  *bytes = L.bytes;
+  std::vector<AdjLayout> Ls;
+  AdjShared S;
+  *bytes = carve_backward(c, w->eng, ckpt_every, Ls, S);
   return SIM_OK;
 }
 
@@ -1574,124 +1665,151 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
   if (!ckpt || !g_pos || !g_rest_angle || !adj_ws) return fail(SIM_E_INVALID, "NULL buffer");
   if ((uintptr_t)adj_ws % kAlign) return fail(SIM_E_WORKSPACE, "adjoint workspace must be 256-byte aligned");
   Engine& e = w->eng;
-  Slot& s = e.slots[0];
-  if (mode_of(s.p) != mc::kBinned)
-    return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
-                mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
-  if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
-  if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
-  if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
+  const int nw = (int)e.slots.size();
+  for (const Slot& s : e.slots) {
+    if (mode_of(s.p) != mc::kBinned)
+      return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
+                  mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
+    if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
+    if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
+    if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
+  }
   size_t need = 0;
   sim_backward_workspace_size(w, ckpt_every, &need);
   if (adj_ws_bytes < need) return fail(SIM_E_WORKSPACE, "adjoint workspace has %zu bytes, needs %zu", adj_ws_bytes, need);
   Carver c{(char*)adj_ws};
-  AdjLayout L;
-  carve_adj(c, s.p, s.n_part, ckpt_every, L);
-  const size_t N = s.n_part, ncell = L.ncell;
-  const size_t per_ck = align_up(4 * N * 4) + align_up(9 * ncell * 4);
+  std::vector<AdjLayout> Ls;
+  AdjShared S;
+  carve_backward(c, e, ckpt_every, Ls, S);
+  const int m_max = ckpt_every;
   const int nseg = (n_steps + ckpt_every - 1) / ckpt_every;
+  const int K = std::max(e.slots[0].p.mdf_iters, 1);
   hipStream_t st = e.stream;
   mc::Grid g = e.grid;
   g.any_binned = 1;
   g.any_sorted = 0;
   g.any_node = 0;
   g.any_energy = 0;                      // the energy field does not act on the motion
-
-  // per-step descriptors (identical for every segment; uploaded once)
-  std::vector<mc::WorldDev> hd(L.m);
-  for (int j = 0; j < L.m; ++j) {
-    mc::WorldDev d = e.make_desc(0, 0);
-    d.mode = mc::kBinned;
-    d.cell_in = L.x_cell[j];
-    d.frac_in = L.x_frac[j];
-    d.cell_out = L.x_cell[j + 1];
-    d.frac_out = L.x_frac[j + 1];
-    d.f_src = L.g[j];
-    d.f_dst = L.g[j + 1];
-    d.grad = L.grad[j];
-    d.Fg = L.Fg[j];
-    d.u = L.u[j];
-    d.fel = L.F[j];
-    d.bin_cnt = L.bin_cnt;
-    d.bin_fill = L.bin_fill;
-    d.bin_start = L.bstart[j];
-    d.bin_start_next = L.bstart[j + 1];
-    d.bin_rec = L.brec[j];
-    d.ctl_src = L.ctl + j;                   // the fluid kernel of step j advances it into j + 1
-    d.ctl_dst = L.ctl + j + 1;
-    d.s = nullptr;
-    d.energy = nullptr;                    // the recompute leaves the world's energy field alone
-    d.e_sensed = nullptr;
-    d.e_collected = nullptr;
-    hd[j] = d;
+  // the worlds' offsets in the caller's node arrays and checkpoint blocks
+  std::vector<size_t> noff(nw, 0), coff(nw, 0);
+  for (int k = 1; k < nw; ++k) {
+    noff[k] = noff[k - 1] + e.slots[k - 1].n_part;
+    coff[k] = coff[k - 1] + (size_t)nseg * ckpt_per_world(e.slots[k - 1]);
   }
+
+  // per-step descriptors and adjoint buffer sets (identical for every segment; uploaded once)
+  std::vector<mc::WorldDev> hd((size_t)m_max * nw);
+  std::vector<mc::AdjDev> ha((size_t)2 * m_max * nw);
+  for (int j = 0; j < m_max; ++j)
+    for (int k = 0; k < nw; ++k) {
+      const AdjLayout& L = Ls[k];
+      mc::WorldDev d = e.make_desc(k, 0);
+      d.mode = mc::kBinned;
+      d.cell_in = L.x_cell[j];
+      d.frac_in = L.x_frac[j];
+      d.cell_out = L.x_cell[j + 1];
+      d.frac_out = L.x_frac[j + 1];
+      d.f_src = L.g[j];
+      d.f_dst = L.g[j + 1];
+      d.grad = L.grad[j];
+      d.Fg = L.Fg[j];
+      d.u = L.u[j];
+      d.fel = L.F[j];
+      d.bin_cnt = L.bin_cnt;
+      d.bin_fill = L.bin_fill;
+      d.bin_start = L.bstart[j];
+      d.bin_start_next = L.bstart[j + 1];
+      d.bin_rec = L.brec[j];
+      d.ctl_src = L.ctl + j;                   // the fluid kernel of step j advances it into j + 1
+      d.ctl_dst = L.ctl + j + 1;
+      d.s = nullptr;
+      d.energy = nullptr;                    // the recompute leaves the world's energy field alone
+      d.e_sensed = nullptr;
+      d.e_collected = nullptr;
+      hd[(size_t)j * nw + k] = d;
+      for (int cur = 0; cur < 2; ++cur) {
+        mc::AdjDev A{};
+        A.xbar_in = L.xbar[cur];
+        A.xbar = L.xbar[1 - cur];
+        A.gbar_in = L.gbar[cur];
+        A.gbar = L.gbar[1 - cur];
+        A.ubar = L.ubar;
+        A.Fgbar = L.Fgbar;
+        A.Gbar = L.Gbar;
+        A.sbar = L.sbar;
+        A.Fbar = L.Fbar;
+        A.g_rest = g_rest_angle + noff[k];
+        A.mdf = K;
+        A.F = L.F[j];
+        A.Fgk = L.Fgk;
+        A.Ud = L.Ud;
+        A.mc = L.mc;
+        A.Ukbar = L.Ukbar;
+        A.Udbar = L.Udbar;
+        A.xbar_m = L.xbar_m;
+        A.jbar = L.jbar;
+        A.rhobar = L.rhobar;
+        ha[((size_t)j * 2 + cur) * nw + k] = A;
+      }
+    }
   HIPCHK(hipEventSynchronize(e.upload_done));
-  const size_t dbytes = hd.size() * sizeof(mc::WorldDev);
-  if (dbytes > e.pinned_bytes) {
+  const size_t dbytes = hd.size() * sizeof(mc::WorldDev), abytes = ha.size() * sizeof(mc::AdjDev);
+  if (dbytes + abytes > e.pinned_bytes) {
     HIPCHK(hipHostFree(e.pinned));
-    e.pinned_bytes = dbytes * 2;
+    e.pinned_bytes = (dbytes + abytes) * 2;
     HIPCHK(hipHostMalloc((void**)&e.pinned, e.pinned_bytes, hipHostMallocDefault));
   }
   std::memcpy(e.pinned, hd.data(), dbytes);
-  HIPCHK(hipMemcpyAsync(L.desc, e.pinned, dbytes, hipMemcpyHostToDevice, st));
+  std::memcpy(e.pinned + dbytes, ha.data(), abytes);
+  HIPCHK(hipMemcpyAsync(S.desc, e.pinned, dbytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(S.adj, e.pinned + dbytes, abytes, hipMemcpyHostToDevice, st));
   HIPCHK(hipEventRecord(e.upload_done, st));
-  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, st, L.bin_cnt, L.nt);
-  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, st, L.bin_fill, L.nt);
-  // dL/dx_T and dL/dg_T = 0
-  int cur = 0;
-  if (N) HIPCHK(hipMemcpyAsync(L.xbar[0], g_pos, 2 * N * 4, hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, st, (int*)L.gbar[0], 9 * ncell);
+  // dL/dx_T from the caller, dL/dg_T = 0, empty bins
+  for (int k = 0; k < nw; ++k) {
+    const AdjLayout& L = Ls[k];
+    const size_t N = e.slots[k].n_part;
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, st, L.bin_cnt, L.nt);
+    hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, st, L.bin_fill, L.nt);
+    if (N) HIPCHK(hipMemcpyAsync(L.xbar[0], g_pos + 2 * noff[k], 2 * N * 4, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, st, (int*)L.gbar[0], 9 * L.ncell);
+  }
   HIPCHK(hipGetLastError());
 
+  int cur = 0;
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int k0 = seg * ckpt_every;
     const int m = std::min(ckpt_every, n_steps - k0);
-    const char* ck = (const char*)ckpt + seg * per_ck;
-    if (N) {
-      HIPCHK(hipMemcpyAsync(L.x_cell[0], ck, 2 * N * 4, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(L.x_frac[0], ck + 2 * N * 4, 2 * N * 4, hipMemcpyDeviceToDevice, st));
+    for (int k = 0; k < nw; ++k) {
+      const AdjLayout& L = Ls[k];
+      const size_t N = e.slots[k].n_part;
+      const char* ck = (const char*)ckpt + coff[k] + seg * ckpt_per_world(e.slots[k]);
+      if (N) {
+        HIPCHK(hipMemcpyAsync(L.x_cell[0], ck, 2 * N * 4, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(L.x_frac[0], ck + 2 * N * 4, 2 * N * 4, hipMemcpyDeviceToDevice, st));
+      }
+      HIPCHK(hipMemcpyAsync(L.g[0], ck + align_up(4 * N * 4), 9 * L.ncell * 4, hipMemcpyDeviceToDevice, st));
+      // one control word write per segment and world: each recomputed step's
+      // fluid kernel sets the next step's time index
+      mc::launch_set_ctl(L.ctl, t0 + k0, m, st);
     }
-    HIPCHK(hipMemcpyAsync(L.g[0], ck + align_up(4 * N * 4), 9 * ncell * 4, hipMemcpyDeviceToDevice, st));
-    // recompute the segment forward, writing every step's fields to the tape
-    // (one control word write per segment: each step's fluid kernel sets the
-    // next step's time index)
-    mc::launch_set_ctl(L.ctl, t0 + k0, m, st);
-    mc::launch_bin_prepass(L.desc, e.tab, g, st);
-    for (int j = 0; j < m; ++j) e.enqueue_step_with(L.desc + j, g, st);
+    // recompute the segment forward for every world, writing each step's fields to the tapes
+    mc::launch_bin_prepass(S.desc, e.tab, g, st);
+    for (int j = 0; j < m; ++j) e.enqueue_step_with(S.desc + (size_t)j * nw, g, st);
     HIPCHK(hipGetLastError());
-    // reverse the segment step by step
+    // reverse the segment step by step, every world in the same launches
     for (int j = m - 1; j >= 0; --j) {
-      mc::AdjDev A{};
-      A.t = t0 + k0 + j;
-      A.xbar_in = L.xbar[cur];
-      A.xbar = L.xbar[1 - cur];
-      A.gbar_in = L.gbar[cur];
-      A.gbar = L.gbar[1 - cur];
-      A.ubar = L.ubar;
-      A.Fgbar = L.Fgbar;
-      A.Gbar = L.Gbar;
-      A.sbar = L.sbar;
-      A.Fbar = L.Fbar;
-      A.g_rest = g_rest_angle;
-      A.mdf = std::max(s.p.mdf_iters, 1);
-      A.F = L.F[j];
-      A.Fgk = L.Fgk;
-      A.Ud = L.Ud;
-      A.mc = L.mc;
-      A.Ukbar = L.Ukbar;
-      A.Udbar = L.Udbar;
-      A.xbar_m = L.xbar_m;
-      A.jbar = L.jbar;
-      A.rhobar = L.rhobar;
       mc::AdjArg a{};
-      a.arr = nullptr;
-      a.one = A;
-      mc::launch_adjoint_step(L.desc + j, e.tab, g, a, A.mdf, st);
+      a.arr = S.adj + ((size_t)j * 2 + cur) * nw;
+      mc::launch_adjoint_step(S.desc + (size_t)j * nw, e.tab, g, a, K, st);
       cur = 1 - cur;
     }
     HIPCHK(hipGetLastError());
   }
-  if (g_pos0 && N) HIPCHK(hipMemcpyAsync(g_pos0, L.xbar[cur], 2 * N * 4, hipMemcpyDeviceToDevice, st));
+  if (g_pos0)
+    for (int k = 0; k < nw; ++k) {
+      const size_t N = e.slots[k].n_part;
+      if (N) HIPCHK(hipMemcpyAsync(g_pos0 + 2 * noff[k], Ls[k].xbar[cur], 2 * N * 4, hipMemcpyDeviceToDevice, st));
+    }
   return SIM_OK;
 }
 

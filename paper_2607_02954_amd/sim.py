@@ -26,7 +26,8 @@ SIM_SPLAT_DIRECT = 2
 LATTICE_WEIGHTS = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 EXPORTS = [
-    "sim_params_default", "sim_workspace_size", "sim_create", "sim_step", "sim_rollout",
+    "sim_params_default", "sim_workspace_size", "sim_create", "sim_set_workspace_size", "sim_create_set",
+    "sim_step", "sim_rollout",
     "sim_checkpoint_size", "sim_backward_workspace_size", "sim_backward", "sim_sync",
     "sim_clear_flags", "sim_destroy", "sim_last_error", "sim_debug_substep", "sim_debug_buffer",
     "sim_profile_steps", "sim_measure_atomics", "sim_step_noalloc", "sim_debug_adjoint",
@@ -92,6 +93,8 @@ def lib():
         "sim_params_default": (None, [P(SimParams), i32, i32]),
         "sim_workspace_size": (i32, [P(SimParams), i32, i32, P(sz)]),
         "sim_create": (i32, [P(SimParams), P(SimArrays), vp, sz, vp, P(vp)]),
+        "sim_set_workspace_size": (i32, [P(SimParams), i32, P(SimArrays), P(sz)]),
+        "sim_create_set": (i32, [P(SimParams), i32, P(SimArrays), vp, sz, vp, P(vp)]),
         "sim_step": (i32, [vp, i64]),
         "sim_rollout": (i32, [vp, i64, i32, i32, vp, sz]),
         "sim_checkpoint_size": (i32, [vp, i32, i32, P(sz)]),
@@ -349,6 +352,103 @@ def _positions(self) -> torch.Tensor:
 
 World.backward = _world_backward
 World.positions = _positions
+
+
+class WorldSet:
+    """Worlds with the same parameters stepped together in the same kernel
+    launches (sim_create_set), each with its own device state.  Node vectors
+    (positions, gradients) are the worlds' blocks one after another: world
+    w's [2][N_w] block (or [N_w] for per-node scalars) follows world w-1's."""
+
+    def __init__(self, worlds, params: Optional[Params] = None, device="cuda", stream=None):
+        L = lib()
+        self.params = params or Params(nx=worlds[0].nx, ny=worlds[0].ny)
+        self.states = [DeviceState(w, device) for w in worlds]
+        self.stream = stream
+        self.n_parts = [st.n_part for st in self.states]
+        cp = self.params.c()
+        n = len(self.states)
+        self._arrays = (SimArrays * n)(*[st.arrays() for st in self.states])
+        nbytes = ctypes.c_size_t()
+        check(L.sim_set_workspace_size(ctypes.byref(cp), n, self._arrays, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.sim_create_set(ctypes.byref(cp), n, self._arrays, _ptr(self.workspace), self.workspace.numel(),
+                               _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+
+    step = World.step
+    rollout = World.rollout
+    checkpoint_bytes = World.checkpoint_bytes
+    sync = World.sync
+    close = World.close
+    __del__ = World.__del__
+
+    def positions(self) -> torch.Tensor:
+        """Node positions of every world as float64, the worlds' [2][N_w] blocks in order."""
+        return torch.cat([(st.cell.double() + st.frac.double()).reshape(-1) for st in self.states])
+
+    def set_rest_angles(self, rest: torch.Tensor):
+        """Write the worlds' rest angles from one array of their [N_w] blocks."""
+        off = 0
+        for st, n in zip(self.states, self.n_parts):
+            st.rest_angle.copy_(rest[off:off + n])
+            off += n
+
+    def rest_angles(self) -> torch.Tensor:
+        return torch.cat([st.rest_angle for st in self.states])
+
+    def backward(self, t0: int, n: int, ckpt_every: int, ckpt: torch.Tensor, g_pos: torch.Tensor,
+                 g_rest: torch.Tensor, g_pos0: Optional[torch.Tensor] = None):
+        """sim_backward over every world of the set (blocks as in positions)."""
+        L = lib()
+        nb = ctypes.c_size_t()
+        check(L.sim_backward_workspace_size(self.handle, int(ckpt_every), ctypes.byref(nb)))
+        ws = getattr(self, "_adj_ws", None)
+        if ws is None or ws.numel() < nb.value:
+            ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.workspace.device)
+            self._adj_ws = ws
+        total = sum(self.n_parts)
+        assert g_pos.dtype == torch.float32 and g_pos.is_contiguous() and g_pos.numel() == 2 * total
+        assert g_rest.dtype == torch.float32 and g_rest.is_contiguous() and g_rest.numel() == total
+        check(L.sim_backward(self.handle, int(t0), int(n), int(ckpt_every), _ptr(ckpt), _ptr(g_pos), _ptr(g_rest),
+                             _ptr(g_pos0), _ptr(ws), ws.numel()))
+
+
+class SetRollout(torch.autograd.Function):
+    """The final positions of every world of a WorldSet after n_steps, as a
+    function of all their rest angles (both as the worlds' blocks in order),
+    differentiable through one sim_backward over the whole set."""
+
+    @staticmethod
+    def forward(ctx, rest_angles, wset, t0, n_steps, ckpt_every):
+        if wset.params.transfer != "binned":
+            raise SimError(SIM_E_INVALID, "differentiation needs the tile-binned transfer "
+                                          f"(set uses '{wset.params.transfer}')")
+        ra32 = rest_angles.detach().to(torch.float32).contiguous()
+        with torch.no_grad():
+            wset.set_rest_angles(ra32)
+        ckpt = torch.empty(wset.checkpoint_bytes(n_steps, ckpt_every), dtype=torch.uint8,
+                           device=wset.workspace.device)
+        wset.rollout(t0, n_steps, ckpt_every, ckpt)
+        ctx.wset, ctx.ckpt, ctx.args = wset, ckpt, (t0, n_steps, ckpt_every)
+        ctx.rest = ra32.clone()
+        ctx.dtype = rest_angles.dtype
+        return wset.positions()
+
+    @staticmethod
+    def backward(ctx, g_x):
+        t0, n, k = ctx.args
+        S = ctx.wset
+        g_pos = g_x.detach().to(torch.float32).contiguous()
+        g_rest = torch.zeros(sum(S.n_parts), dtype=torch.float32, device=g_pos.device)
+        current = S.rest_angles().clone()
+        S.set_rest_angles(ctx.rest)
+        try:
+            S.backward(t0, n, k, ctx.ckpt, g_pos, g_rest)
+        finally:
+            S.set_rest_angles(current)
+        return g_rest.to(ctx.dtype), None, None, None, None
 
 
 class Rollout(torch.autograd.Function):
