@@ -504,7 +504,7 @@ def coupling_force(x, f, force, topo: Topology, p: Params, trace=None):
     mismatch = []
     for _ in range(p.mdf_iters - 1):
         U = interpolate2(x, (j + 0.5 * Fg) / rho, topo, p)
-        mismatch.append(float((U_d - U).abs().max()))
+        mismatch.append(float((U_d - U).detach().abs().max()))
         Fg = Fg + spread2(x, 2.0 * (U_d - U), topo, p)
     if trace is not None:
         trace["mdf_mismatch"] = mismatch
