@@ -398,10 +398,10 @@ def bench_widened(world, seed, tile, steps, warmup):
 
     * MDF and two-layer markers: a quarter of the million-node workload's
       nodes (262,144: lengths U{16..256}) on the same 2048^2 grid, with
-      explicit coupling and with 4 MDF iterations on the binned and on the
-      direct transfer, and with 4 iterations on two markers offset 0.5 cells
-      along the normal (direct); 100 steps each (at the full workload's
-      density the MDF iteration diverges where markers crowd, a limit of the
+      explicit coupling and with 4 MDF iterations, each on one layer and on
+      two markers offset 0.5 cells along the normal, on the binned and on
+      the direct transfer; 100 steps each (at the full workload's density
+      the MDF iteration diverges where markers crowd, a limit of the
       method);
     * energy field (binned transfer): the same workload with a field of 4096
       Gaussian packets (amplitudes U(0.5, 2), widths U(3, 12) cells) that the
@@ -432,13 +432,17 @@ def bench_widened(world, seed, tile, steps, warmup):
     direct = dc_replace(base, transfer="direct")
     rows = {"binned_explicit": timed(wq, base, 100, "quarter binned explicit"),
             "binned_mdf4": timed(wq, dc_replace(base, mdf_iters=4), 100, "quarter binned mdf4"),
+            "binned_two_layer": timed(wq, dc_replace(base, marker_offset=0.5), 100, "quarter binned two layers"),
+            "binned_mdf4_two_layer": timed(wq, dc_replace(base, mdf_iters=4, marker_offset=0.5), 100,
+                                           "quarter binned mdf4 two layers"),
             "explicit": timed(wq, direct, 100, "quarter direct explicit"),
             "mdf4": timed(wq, dc_replace(direct, mdf_iters=4), 100, "quarter direct mdf4"),
             "mdf4_two_layer": timed(wq, dc_replace(direct, mdf_iters=4, marker_offset=0.5), 100,
                                     "quarter direct mdf4 two layers")}
     for k in ("mdf4", "mdf4_two_layer"):
         rows[k]["over_explicit"] = rows[k]["ms_per_step"] / rows["explicit"]["ms_per_step"]
-    rows["binned_mdf4"]["over_explicit"] = rows["binned_mdf4"]["ms_per_step"] / rows["binned_explicit"]["ms_per_step"]
+    for k in ("binned_mdf4", "binned_two_layer", "binned_mdf4_two_layer"):
+        rows[k]["over_explicit"] = rows[k]["ms_per_step"] / rows["binned_explicit"]["ms_per_step"]
     out["coupling"] = dict(workload=f"{wq.n_particles} nodes (lengths U{{16..256}}) on {wq.nx}x{wq.ny}, "
                                     "100 steps", **rows)
 

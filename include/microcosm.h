@@ -99,12 +99,17 @@ typedef struct sim_params {
                               The tile-binned and the direct transfer; not with
                               SIM_SPLAT_SORTED; sim_backward differentiates it
                               (binned transfer).                               */
-  float marker_offset;     /* two-layer broadcast (SIM_SPLAT_DIRECT only): each
-                              node acts through two markers at +-marker_offset
-                              (cells, <= 1) along its normal (tangent
-                              x_next - x_prev; the edge at a chain end), half
-                              of its force at each, and moves with the mean of
-                              their velocities; 0: one layer                   */
+  float marker_offset;     /* two-layer broadcast (Methods, Fluid-filament
+                              Interaction): each node acts through two markers
+                              at +-marker_offset (cells, <= 1) along its
+                              normal (tangent x_next - x_prev; the edge at a
+                              chain end), half of its force (and of each MDF
+                              correction) at each, and moves with (and MDF
+                              samples) the mean of their velocities; density
+                              deposit, repulsion and energy stay at the node.
+                              The tile-binned and the direct transfer; not
+                              with SIM_SPLAT_SORTED; sim_backward refuses it.
+                              0: one layer                                     */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).
@@ -232,8 +237,8 @@ sim_status sim_checkpoint_size(const sim_world *w, int32_t n_steps, int32_t ckpt
  * checkpoints written by sim_rollout(t0, n_steps, ckpt_every) and g_pos =
  * dL/dx at the final step ([2][N] device floats), ACCUMULATES dL/d(rest_angle)
  * into g_rest_angle ([N], caller zeroes) and, if g_pos0 is not NULL, WRITES
- * dL/dx at t0 into g_pos0 ([2][N]).  Worlds with closed loops are not
- * differentiated (SIM_E_INVALID).  Each segment is recomputed forward from
+ * dL/dx at t0 into g_pos0 ([2][N]).  Worlds with closed loops, branches or
+ * two-layer markers are not differentiated (SIM_E_INVALID).  Each segment is recomputed forward from
  * its checkpoint into adj_ws, then hand-written adjoint kernels run step by
  * step in reverse.  adj_ws must hold sim_backward_workspace_size bytes.
  * The world's own state arrays are not modified.  Only worlds that use the

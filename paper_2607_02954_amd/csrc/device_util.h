@@ -156,19 +156,38 @@ static __device__ __forceinline__ void edge_direction(float t, float t0, float c
   }
 }
 
-// A marker displaced by (dx, dy) (|d| < 1 cell) from a node at cell (cx, cy)
-// + fraction (fx, fy): its wrapped home cell and fraction on an nx x ny grid.
-static __device__ __forceinline__ void marker_home(int c, float f, float d, int n, int* home, float* fr) {
+// A marker displaced by d (|d| <= 1 cell) along one axis from a node with
+// fraction f: the shift of its home cell from the node's (-1, 0 or 1) and
+// its own fraction.  The shift stays in [-1, 1] also where |d| exceeds one
+// cell by a rounding step: f + d rounded up to 2 is the same point as shift
+// 1 with fraction 1 (the 4-point weights of fraction 1 put nothing on the
+// first cell); f + d below -1 (by rounding only) moves to shift -1,
+// fraction 0, at most one rounding step away.
+static __device__ __forceinline__ void marker_shift(float f, float d, int* shift, float* fr) {
   const float m = f + d;
   const float fl = floorf(m);
-  int h = c + (int)fl;
+  int h = (int)fl;
   float r = m - fl;
   if (r >= 1.0f) {
     r = 0.0f;
     h += 1;
   }
-  *home = wrap_index(h, n);
+  if (h > 1) {
+    h = 1;
+    r = 1.0f;
+  } else if (h < -1) {
+    h = -1;
+    r = 0.0f;
+  }
+  *shift = h;
   *fr = r;
+}
+
+// The same marker's wrapped home cell on an axis of n cells, for a node at cell c.
+static __device__ __forceinline__ void marker_home(int c, float f, float d, int n, int* home, float* fr) {
+  int sh;
+  marker_shift(f, d, &sh, fr);
+  *home = wrap_index(c + sh, n);
 }
 
 // Global float atomics of s * W(c - X) * (vx, vy) into an interleaved
@@ -565,28 +584,67 @@ static __device__ __forceinline__ int first_image(int i, int n) {
 // truncating 32-bit conversion; larger ones by the exact 64-bit split.
 
 // Whether a node with home cell (hx, hy) reaches the spread window of the
-// tile at (x0, y0) of size tw x th (the keep rule of tile_spread_vec).
+// tile at (x0, y0) of size tw x th (the keep rule of tile_spread_vec).  With
+// two-layer markers (a world with marker displacements) a node counts if one
+// of its markers can: the markers' homes lie within one cell of the node's,
+// so the kept homes reach one cell further on every side.
 struct SpreadKeep {
   int ox, oy, kx, ky, nx, ny;
   __device__ __forceinline__ SpreadKeep(const WorldDev& w, int x0, int y0, int tw, int th) {
+    const int m = w.d_marker ? 1 : 0;
     nx = w.nx;
     ny = w.ny;
-    ox = wrap_index(x0 - 3, nx);
-    oy = wrap_index(y0 - 3, ny);
-    kx = tw + 3 <= nx ? tw + 2 : nx;
-    ky = th + 3 <= ny ? th + 2 : ny;
+    ox = wrap_index(x0 - 3 - m, nx);
+    oy = wrap_index(y0 - 3 - m, ny);
+    kx = tw + 3 + 2 * m <= nx ? tw + 2 + 2 * m : nx;
+    ky = th + 3 + 2 * m <= ny ? th + 2 + 2 * m : ny;
   }
   __device__ __forceinline__ bool operator()(const vi4& r) const {
     return wrap_near((r.x & 0xffff) - 1 - ox, nx) <= kx && wrap_near((r.x >> 16) - 1 - oy, ny) <= ky;
   }
 };
 
-// The bin set a tile spread reads: homes in [x0 - 2, x0 + tw] x [y0 - 2, y0 + th]
-// (run table kind 1).
+// The bin set a tile spread reads: homes in [x0 - 3, x0 + tw + 1] x
+// [y0 - 3, y0 + th + 1] (run table kind 1: the homes whose support, or one of
+// whose two-layer markers' supports, meets the tile; one-layer readers keep
+// the narrower range [x0 - 2, x0 + tw] of it by their keep test).
 template <int TILE>
 static __device__ __forceinline__ BinFetch spread_fetch(const WorldDev& w, int x0, int y0) {
   constexpr int sh = TileCfg<TILE>::kShift;
   return binset_fetch<TileCfg<TILE>::kRanges>(w, (y0 >> sh) * w.ntx + (x0 >> sh), 1);
+}
+
+// One point's 4x4 contribution W * (Vx, Vy) to two 64-bit fixed-point LDS
+// windows of row length SIDE at the point's support origin (px, py).
+template <int SIDE, bool SCALAR = false>
+static __device__ __forceinline__ void spread_point(long long* sx, long long* sy, const float* wx,
+                                                    const float* wy, float Vx, float Vy) {
+  unsigned long long* px = (unsigned long long*)sx;
+  unsigned long long* py = (unsigned long long*)sy;
+  if (fmaxf(fabsf(Vx), fabsf(Vy)) < 0.125f) {
+    float ax[4], ay[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ax[a] = (Vx * kFixScale) * wx[a];
+      ay[a] = (Vy * kFixScale) * wx[a];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        atomicAdd(px + b * SIDE + a, (unsigned long long)(long long)(int)(ax[a] * wy[b]));
+        if constexpr (!SCALAR) atomicAdd(py + b * SIDE + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
+      }
+  } else {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const float ww = wx[a] * wy[b];
+        atomicAdd(px + b * SIDE + a, (unsigned long long)f32_to_fix(ww * Vx * kFixScale));
+        if constexpr (!SCALAR) atomicAdd(py + b * SIDE + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
+      }
+  }
 }
 
 // With s_g (REP), the spread value of a node is its total force: v (the
@@ -650,33 +708,92 @@ static __device__ void tile_spread_vec(const WorldDev& w, int x0, int y0, int tw
       Vx = scale * v[r.w];
       Vy = SCALAR ? 0.f : scale * v[N + r.w];
     }
-    unsigned long long* px = (unsigned long long*)(s_x + dy * kSpreadSide + dx);
-    unsigned long long* py = (unsigned long long*)(s_y + dy * kSpreadSide + dx);
-    if (fmaxf(fabsf(Vx), fabsf(Vy)) < 0.125f) {
-      float ax[4], ay[4];
+    spread_point<kSpreadSide, SCALAR>(s_x + dy * kSpreadSide + dx, s_y + dy * kSpreadSide + dx, wx, wy, Vx, Vy);
+  };
+  if constexpr (LIST) for_list_records<C::kThreads>(recs, bs, body);
+  else for_bin_records<4, C::kThreads>(recs, bs, s_list, keep, body);
+}
+
+// The tile spread of a two-layer world: each node acts through its markers
+// X = x +- d (d from w.d_marker), each taking half of the node's value.  The
+// node's value is formed as in tile_spread_vec, with the gradient s_g staged
+// over a window one cell wider on every side (side kSpreadSide + 2, origin
+// (x0 - 4, y0 - 4)), since a node whose marker reaches the tile can lie one
+// cell further out.  The accumulators keep side kSpreadSide and origin
+// (x0 - 3, y0 - 3): a marker goes in by the one-layer keep rule applied to
+// its own home cell, and the others cannot touch the tile.
+template <int TILE, bool REP, bool LIST = false>
+static __device__ void tile_spread_markers(const WorldDev& w, int x0, int y0, int tw, int th,
+                                           const MC_GLOBAL float* v, float scale, long long* s_x,
+                                           long long* s_y, vi4* s_list, const MC_GLOBAL vi4* recs,
+                                           const BinFetch& bins, const vf2* s_g) {
+  using C = TileCfg<TILE>;
+  constexpr int kSpreadSide = C::kSpreadSide, kGSide = C::kSpreadSide + 2;
+  const int nx = w.nx, ny = w.ny, N = w.n_part;
+  const auto bs = binset_commit<C::kRanges>(bins);
+  const int ox = wrap_index(x0 - 3, nx), oy = wrap_index(y0 - 3, ny);
+  const int gox = wrap_index(x0 - 4, nx), goy = wrap_index(y0 - 4, ny);
+  const int keep_x = tw + 3 <= nx ? tw + 2 : nx;     // markers: largest kept home offset
+  const int keep_y = th + 3 <= ny ? th + 2 : ny;
+  const int nkeep_x = tw + 5 <= nx ? tw + 4 : nx;    // nodes: one cell more on each side
+  const int nkeep_y = th + 5 <= ny ? th + 4 : ny;
+  const float kr = w.k_rep;
+  MC_GLOBAL float* ftot = glb(w.fel);
+  const MC_GLOBAL float* dm = glb(w.d_marker);
+  const auto keep = [&](const vi4& r) {
+    const int dx = wrap_near((r.x & 0xffff) - 1 - gox, nx);
+    const int dy = wrap_near((r.x >> 16) - 1 - goy, ny);
+    return dx <= nkeep_x && dy <= nkeep_y;
+  };
+  const auto body = [&](const vi4& r) {
+    const int hx = r.x & 0xffff, hy = r.x >> 16;
+    const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);
+    float Vx, Vy;
+    if constexpr (REP) {
+      const int dx = wrap_near(hx - 1 - gox, nx), dy = wrap_near(hy - 1 - goy, ny);
+      float wx[4], wy[4];
+      peskin4(fx, wx);
+      peskin4(fy, wy);
+      float gx = 0.f, gy = 0.f;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        ax[a] = (Vx * kFixScale) * wx[a];
-        ay[a] = (Vy * kFixScale) * wx[a];
+      for (int b = 0; b < 4; ++b) {
+        const vf2* row = s_g + (dy + b) * kGSide + dx;
+        float ax = 0.f, ay = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const vf2 t = row[a];
+          ax += wx[a] * t.x;
+          ay += wx[a] * t.y;
+        }
+        gx += wy[b] * ax;
+        gy += wy[b] * ay;
       }
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          atomicAdd(px + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ax[a] * wy[b]));
-          if constexpr (!SCALAR)
-            atomicAdd(py + b * kSpreadSide + a, (unsigned long long)(long long)(int)(ay[a] * wy[b]));
-        }
+      Vx = v[r.w] - kr * gx;
+      Vy = v[N + r.w] - kr * gy;
+      if (hx >= x0 && hx < x0 + tw && hy >= y0 && hy < y0 + th) {
+        ftot[r.w] = Vx;
+        ftot[N + r.w] = Vy;
+      }
     } else {
+      Vx = scale * v[r.w];
+      Vy = scale * v[N + r.w];
+    }
+    const float ddx = dm[r.w], ddy = dm[N + r.w];
+    const float hVx = 0.5f * Vx, hVy = 0.5f * Vy;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const float ww = wx[a] * wy[b];
-          atomicAdd(px + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vx * kFixScale));
-          if constexpr (!SCALAR)
-            atomicAdd(py + b * kSpreadSide + a, (unsigned long long)f32_to_fix(ww * Vy * kFixScale));
-        }
+    for (int l = 0; l < 2; ++l) {
+      const float sg = l == 0 ? 1.f : -1.f;
+      int sx, sy;
+      float mx, my;
+      marker_shift(fx, sg * ddx, &sx, &mx);
+      marker_shift(fy, sg * ddy, &sy, &my);
+      const int mdx = wrap_index(hx + sx - 1 - ox, nx), mdy = wrap_index(hy + sy - 1 - oy, ny);
+      if (mdx <= keep_x && mdy <= keep_y) {
+        float wx[4], wy[4];
+        peskin4(mx, wx);
+        peskin4(my, wy);
+        spread_point<kSpreadSide>(s_x + mdy * kSpreadSide + mdx, s_y + mdy * kSpreadSide + mdx, wx, wy, hVx, hVy);
+      }
     }
   };
   if constexpr (LIST) for_list_records<C::kThreads>(recs, bs, body);

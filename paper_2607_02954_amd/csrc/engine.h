@@ -157,6 +157,8 @@ struct Grid {
   int max_radius;                            // largest Gaussian radius of any world (LDS sizing)
   int any_energy;                            // a world has an energy field
   int any_markers;                           // a world broadcasts two-layer markers
+  int mk_only;                               // every world of the tile kernels has markers (the
+                                             // one-layer tile variants are not launched)
   int mdf_max;                               // most MDF iterations of any world (1: none)
   int general;                               // a world passes loop flags or per-edge stiffnesses
   int branches;                              // a world has branches (filaments hanging from nodes)

@@ -36,6 +36,8 @@
 // physics needs (edge vectors, kernel offsets) are formed from small numbers.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "device_util.h"
 
 namespace mc {
@@ -631,7 +633,7 @@ __global__ void k_tile_ranges(int nx, int ny, int R, int2* out) {
     const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
     const int reg = TILE + 2 + 2 * R, xo = x0 - R - 1, yo = y0 - R - 1;
     tile_runs<TILE>(xo - 2, xo + reg, yo - 2, yo + reg, nx, ny, ntx, out + (size_t)(2 * t) * kRunStride);
-    tile_runs<TILE>(x0 - 2, x0 + tw, y0 - 2, y0 + th, nx, ny, ntx, out + (size_t)(2 * t + 1) * kRunStride);
+    tile_runs<TILE>(x0 - 3, x0 + tw + 1, y0 - 3, y0 + th + 1, nx, ny, ntx, out + (size_t)(2 * t + 1) * kRunStride);
   }
 }
 
@@ -896,15 +898,19 @@ __global__ __launch_bounds__(PACK) void k_repulse(const WorldDev* __restrict__ W
 // or by fixed-order gathers over sorted segments (sorted); every cell of the
 // tile is written once.  Direct mode accumulates in k_repulse instead.
 // ---------------------------------------------------------------------------
-template <int TILE>
+// MK: the two-layer variant (binned worlds with markers, which the plain
+// variant skips): the gradient is staged one cell wider on every side and
+// the nodes spread through their markers.
+template <int TILE, bool MK>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_spread(const WorldDev* __restrict__ W, Tables T) {
   using C = TileCfg<TILE>;
-  constexpr int kThreads = C::kThreads, kSpreadSide = C::kSpreadSide, kSpreadCells = C::kSpreadCells;
+  constexpr int kThreads = C::kThreads, kSpreadCells = C::kSpreadCells;
+  constexpr int kGSide = C::kSpreadSide + (MK ? 2 : 0), kGCells = kGSide * kGSide;
   constexpr int kSpreadCap = C::kSpreadCap;
   __shared__ __align__(16) long long s_fx[kSpreadCells];   // 64-bit fixed point, padded window
   __shared__ __align__(16) long long s_fy[kSpreadCells];
   __shared__ vi4 s_list[(kThreads / 64) * kWaveList];
-  __shared__ vf2 s_g[kSpreadCells];             // gradient over the window (binned)
+  __shared__ vf2 s_g[kGCells];                  // gradient over the window (binned)
   const int nt = n_tiles<TILE>(T);
   const int tid = threadIdx.x;
   const XcdLoop tiles(nt);
@@ -912,6 +918,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_spread(const WorldD
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode == kDirect || w.ctl_src->remaining <= 0) continue;
+    if (MK != (w.mode == kBinned && w.d_marker != nullptr)) continue;
     const int mode = w.mode;
     const int nx = w.nx, ny = w.ny;
     const int x0 = tile_x(tl.y) * TILE;
@@ -922,20 +929,20 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_spread(const WorldD
       // the window (grid cells (x0 - 3 + i, y0 - 3 + j), periodic); all loads
       // first, then the stores (the barrier in the bin set commit follows)
       {
-        constexpr int kIt = (kSpreadCells + kThreads - 1) / kThreads;
+        constexpr int kIt = (kGCells + kThreads - 1) / kThreads;
         const MC_GLOBAL vf2* grad = glbv<const vf2>(w.grad);
-        const int gx0 = wrap_index(x0 - 3, nx), gy0 = wrap_index(y0 - 3, ny);
+        const int gx0 = wrap_index(x0 - (MK ? 4 : 3), nx), gy0 = wrap_index(y0 - (MK ? 4 : 3), ny);
         vf2 gv[kIt];
 #pragma unroll
         for (int i = 0; i < kIt; ++i) {
-          const int k = min(tid + kThreads * i, kSpreadCells - 1);
-          const int j = k / kSpreadSide, c = k - (k / kSpreadSide) * kSpreadSide;
+          const int k = min(tid + kThreads * i, kGCells - 1);
+          const int j = k / kGSide, c = k - (k / kGSide) * kGSide;
           gv[i] = grad[(size_t)wrap_index(gy0 + j, ny) * nx + wrap_index(gx0 + c, nx)];
         }
 #pragma unroll
         for (int i = 0; i < kIt; ++i) {
           const int k = tid + kThreads * i;
-          if (k < kSpreadCells) s_g[k] = gv[i];
+          if (k < kGCells) s_g[k] = gv[i];
         }
       }
       zero_lds_u64(s_fx, kSpreadCells);
@@ -949,11 +956,19 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_spread(const WorldD
         f.n = 1;
         f.b0 = tix * kSpreadCap;
         f.len = __lane_id() == 0 ? cnt : 0;
-        tile_spread_vec<TILE, true, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
-                                          glbv<const vi4>(w.sp_rec), f, s_g);
+        if constexpr (MK)
+          tile_spread_markers<TILE, true, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                                glbv<const vi4>(w.sp_rec), f, s_g);
+        else
+          tile_spread_vec<TILE, true, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                            glbv<const vi4>(w.sp_rec), f, s_g);
       } else {
-        tile_spread_vec<TILE, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
-                                    glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), s_g);
+        if constexpr (MK)
+          tile_spread_markers<TILE, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                          glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), s_g);
+        else
+          tile_spread_vec<TILE, true>(w, x0, y0, tw, th, glb(w.fel_el), 1.0f, s_fx, s_fy, s_list,
+                                      glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), s_g);
       }
       __syncthreads();
     }
@@ -1170,16 +1185,20 @@ __global__ __launch_bounds__(PACK) void k_integrate(const WorldDev* __restrict__
 // gathers its 4x4 window from LDS.  (The S4 gather of binned worlds happens
 // inside k_spread.)
 // ---------------------------------------------------------------------------
-template <int TILE>
+// Stage a vector field over the cells (x0 - 1 - E .. x0 + TILE + 1 + E) of
+// each axis (side TILE + 3 + 2E): every support of a node whose home lies in
+// the tile (E = 0), or of its two-layer markers (E = 1: a marker's home lies
+// within one cell of its node's).
+template <int TILE, int E = 0>
 __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int ny, int x0, int y0, vf2* st) {
-  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kStage = TILE + 3 + 2 * E, kThreads = TileCfg<TILE>::kThreads;
   constexpr int kIt = (kStage * kStage + kThreads - 1) / kThreads;
   vf2 v[kIt];
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
     const int k = min((int)threadIdx.x + kThreads * i, kStage * kStage - 1);
     const int r = k / kStage, c = k - (k / kStage) * kStage;
-    v[i] = f[(size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx)];
+    v[i] = f[(size_t)wrap_index(y0 - 1 - E + r, ny) * nx + wrap_index(x0 - 1 - E + c, nx)];
   }
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
@@ -1188,11 +1207,12 @@ __device__ __forceinline__ void stage_field(const MC_GLOBAL vf2* f, int nx, int 
   }
 }
 
-// 4x4 kernel-weighted sum of a staged vector field at a node whose home
-// cell sits at (lx, ly) of the tile (weights wx, wy along x and y).
-template <int TILE>
+// 4x4 kernel-weighted sum of a staged vector field (stage_field<TILE, E>)
+// at a point whose support starts at staged cell (lx, ly) (a node with home
+// cell (lx, ly) of the tile when E = 0; weights wx, wy along x and y).
+template <int TILE, int E = 0>
 __device__ __forceinline__ vf2 gather_staged(const vf2* st, int lx, int ly, const float* wx, const float* wy) {
-  constexpr int kStage = TILE + 3;
+  constexpr int kStage = TILE + 3 + 2 * E;
   float gx = 0.f, gy = 0.f;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -1211,9 +1231,12 @@ __device__ __forceinline__ vf2 gather_staged(const vf2* st, int lx, int ly, cons
   return out;
 }
 
-template <int TILE>
+// MK: the two-layer variant (worlds with markers, which the plain variant
+// skips): a node moves with the mean of its two markers' velocities.
+template <int TILE, bool MK>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_integrate_tile(const WorldDev* __restrict__ W, Tables T) {
-  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kE = MK ? 1 : 0;
+  constexpr int kStage = TILE + 3 + 2 * kE, kThreads = TileCfg<TILE>::kThreads;
   __shared__ vf2 s_u[kStage * kStage];        // staged velocity, x and y interleaved
   const int nt = n_tiles<TILE>(T);
   const XcdLoop tiles(nt);
@@ -1221,6 +1244,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_integrate_tile(cons
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.ctl_src->remaining <= 0) continue;
+    if (MK != (w.d_marker != nullptr)) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * TILE;
     const int y0 = tile_y(tl.y) * TILE;
@@ -1237,7 +1261,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_integrate_tile(cons
     const bool has0 = ea < e1, has1 = eb < e1;
     const vi4 r0 = recs[has0 ? ea : 0];
     const vi4 r1 = recs[has1 ? eb : 0];
-    stage_field<TILE>(glbv<const vf2>(w.u), nx, ny, x0, y0, s_u);
+    stage_field<TILE, kE>(glbv<const vf2>(w.u), nx, ny, x0, y0, s_u);
     int c0x = 0, c0y = 0, c1x = 0, c1y = 0;    // in flight across the barrier
     if (N > 0) {
       const int g0 = has0 ? r0.w : 0, g1 = has1 ? r1.w : 0;
@@ -1250,12 +1274,35 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_integrate_tile(cons
     auto node = [&](const vi4& r, int cxo, int cyo) {
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
       const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);
-      float wx[4], wy[4];
-      peskin4(fx, wx);
-      peskin4(fy, wy);
-      const vf2 du = gather_staged<TILE>(s_u, lx, ly, wx, wy);
-      const float dux = du.x, duy = du.y;
       const int gi = r.w;
+      float dux, duy;
+      if constexpr (MK) {
+        dux = duy = 0.f;
+        const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const float sg = l == 0 ? 1.f : -1.f;
+          int sx, sy;
+          float mx, my;
+          marker_shift(fx, sg * ddx, &sx, &mx);
+          marker_shift(fy, sg * ddy, &sy, &my);
+          float wx[4], wy[4];
+          peskin4(mx, wx);
+          peskin4(my, wy);
+          const vf2 g = gather_staged<TILE, 1>(s_u, lx + sx + 1, ly + sy + 1, wx, wy);
+          dux += g.x;
+          duy += g.y;
+        }
+        dux *= 0.5f;
+        duy *= 0.5f;
+      } else {
+        float wx[4], wy[4];
+        peskin4(fx, wx);
+        peskin4(fy, wy);
+        const vf2 du = gather_staged<TILE>(s_u, lx, ly, wx, wy);
+        dux = du.x;
+        duy = du.y;
+      }
       float nfx = fx + dux, nfy = fy + duy;
       const float flx = floorf(nfx), fly = floorf(nfy);
       int ncx = cxo + (int)flx, ncy = cyo + (int)fly;
@@ -1355,14 +1402,20 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_energy_deplete(cons
     const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
     const int cnt = glb(w.sp_cnt)[tix];
     // the tile's spread list of this step (the records of the step's
-    // starting positions), or the bins if it overflowed
+    // starting positions), or the bins if it overflowed; a two-layer world's
+    // list also holds nodes one cell further out (for their markers), which
+    // the keep test drops here
     if (cnt >= 0 && cnt <= kSpreadCap) {
       BinFetch f;
       f.n = 1;
       f.b0 = tix * kSpreadCap;
       f.len = __lane_id() == 0 ? cnt : 0;
-      tile_spread_vec<TILE, false, true, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, nullptr,
-                                               s_list, glbv<const vi4>(w.sp_rec), f, nullptr);
+      if (w.d_marker)
+        tile_spread_vec<TILE, false, false, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, nullptr,
+                                                  s_list, glbv<const vi4>(w.sp_rec), f, nullptr);
+      else
+        tile_spread_vec<TILE, false, true, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, nullptr,
+                                                 s_list, glbv<const vi4>(w.sp_rec), f, nullptr);
     } else {
       tile_spread_vec<TILE, false, false, true>(w, x0, y0, tw, th, glb(w.e_node), -w.energy_rate, s_x, nullptr,
                                                 s_list, glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0),
@@ -1608,18 +1661,21 @@ __global__ __launch_bounds__(PACK) void k_mdf_correct(const WorldDev* __restrict
   }
 }
 
-// Binned transfer (one layer): the node passes of MDF as tile passes over
-// the home-tile bins, and the correction spread through the tiles' spread
-// lists, summed in LDS as 64-bit fixed point like the force spread:
-// deterministic and without HBM atomics.
+// Binned transfer: the node passes of MDF as tile passes over the home-tile
+// bins, and the correction spread through the tiles' spread lists, summed in
+// LDS as 64-bit fixed point like the force spread: deterministic and without
+// HBM atomics.
 //   k_mdf_gather_tile<TILE, true>   U_d = I[j / rho] + F / 2 at the tile's nodes
 //   k_mdf_gather_tile<TILE, false>  c = 2 (U_d - I[(j + F_grid / 2) / rho])
 //   k_mdf_spread_tile<TILE>         F_grid += S[c] over the tile
 // The velocity is formed per staged cell from the moments and the grid force.
-template <int TILE, bool DESIRED>
+// MK: the two-layer variants (I: the mean over the node's two markers; S:
+// half of the value from each marker).
+template <int TILE, bool DESIRED, bool MK>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_gather_tile(const WorldDev* __restrict__ W, Tables T,
                                                                              int iter) {
-  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kE = MK ? 1 : 0;
+  constexpr int kStage = TILE + 3 + 2 * kE, kThreads = TileCfg<TILE>::kThreads;
   constexpr int kIt = (kStage * kStage + kThreads - 1) / kThreads;
   __shared__ vf2 s_u[kStage * kStage];
   const int nt = n_tiles<TILE>(T);
@@ -1629,6 +1685,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_gather_tile(con
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || w.mdf_iters <= 1 || (!DESIRED && iter >= w.mdf_iters) || w.ctl_src->remaining <= 0)
       continue;
+    if (MK != (w.d_marker != nullptr)) continue;
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
@@ -1639,7 +1696,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_gather_tile(con
     for (int i = 0; i < kIt; ++i) {              // all loads in flight before the stores
       const int k = min((int)threadIdx.x + kThreads * i, kStage * kStage - 1);
       const int r = k / kStage, c = k - (k / kStage) * kStage;
-      const size_t idx = (size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx);
+      const size_t idx = (size_t)wrap_index(y0 - 1 - kE + r, ny) * nx + wrap_index(x0 - 1 - kE + c, nx);
       mv[i] = m[idx];
       if (!DESIRED) fv[i] = Fg[idx];
     }
@@ -1667,11 +1724,34 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_gather_tile(con
     for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
-      float wx[4], wy[4];
-      peskin4(__int_as_float(r.y), wx);
-      peskin4(__int_as_float(r.z), wy);
-      const vf2 g = gather_staged<TILE>(s_u, lx, ly, wx, wy);
+      const float fx = __int_as_float(r.y), fy = __int_as_float(r.z);
       const int gi = r.w;
+      vf2 g;
+      if constexpr (MK) {
+        g.x = g.y = 0.f;
+        const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+          const float sg = l == 0 ? 1.f : -1.f;
+          int sx, sy;
+          float mx, my;
+          marker_shift(fx, sg * ddx, &sx, &mx);
+          marker_shift(fy, sg * ddy, &sy, &my);
+          float wx[4], wy[4];
+          peskin4(mx, wx);
+          peskin4(my, wy);
+          const vf2 gl = gather_staged<TILE, 1>(s_u, lx + sx + 1, ly + sy + 1, wx, wy);
+          g.x += gl.x;
+          g.y += gl.y;
+        }
+        g.x *= 0.5f;
+        g.y *= 0.5f;
+      } else {
+        float wx[4], wy[4];
+        peskin4(fx, wx);
+        peskin4(fy, wy);
+        g = gather_staged<TILE>(s_u, lx, ly, wx, wy);
+      }
       if (DESIRED) {
         Ud[gi] = g.x + 0.5f * glb(w.fel)[gi];
         Ud[N + gi] = g.y + 0.5f * glb(w.fel)[N + gi];
@@ -1684,7 +1764,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_gather_tile(con
   }
 }
 
-template <int TILE>
+template <int TILE, bool MK>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_spread_tile(const WorldDev* __restrict__ W, Tables T,
                                                                              int iter) {
   using C = TileCfg<TILE>;
@@ -1698,6 +1778,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_spread_tile(con
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
     if (w.mode != kBinned || iter >= w.mdf_iters || w.ctl_src->remaining <= 0) continue;
+    if (MK != (w.d_marker != nullptr)) continue;
     const int nx = w.nx, ny = w.ny;
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const int tw = min(TILE, nx - x0), th = min(TILE, ny - y0);
@@ -1711,11 +1792,19 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_mdf_spread_tile(con
       f.n = 1;
       f.b0 = tix * kSpreadCap;
       f.len = __lane_id() == 0 ? cnt : 0;
-      tile_spread_vec<TILE, false, true>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
-                                         glbv<const vi4>(w.sp_rec), f, nullptr);
+      if constexpr (MK)
+        tile_spread_markers<TILE, false, true>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
+                                               glbv<const vi4>(w.sp_rec), f, nullptr);
+      else
+        tile_spread_vec<TILE, false, true>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
+                                           glbv<const vi4>(w.sp_rec), f, nullptr);
     } else {
-      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
-                                   glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+      if constexpr (MK)
+        tile_spread_markers<TILE, false>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
+                                         glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+      else
+        tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(w.mdf_c), 1.0f, s_fx, s_fy, s_list,
+                                     glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
     }
     __syncthreads();
     MC_GLOBAL vf2* Fg = glbv<vf2>(w.Fg);
@@ -1817,10 +1906,39 @@ void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream
   // binned worlds form the repulsion inside k_spread
 }
 
+// Tile kernels with a one-layer and a two-layer variant (template argument
+// MK last): each variant skips the other's worlds; the two-layer one runs
+// only where a binned world has markers, the one-layer one unless every
+// world has them.
+template <int TILE>
+static bool tile_family_present(const Grid& G) {
+  return G.tile_blocks[TileCfg<TILE>::kFamily] > 0;
+}
+
+// Launch a tile kernel template K<TILE, ..., MK> for every family present
+// and the variants the grid needs (launch(Int<TILE>, Bool<MK>) launches one).
+template <class L>
+static void for_tile_variants(const Grid& G, L launch) {
+  const bool mk = G.any_markers && G.any_binned, plain = !G.mk_only;
+  if (tile_family_present<16>(G)) {
+    if (plain) launch(std::integral_constant<int, 16>(), std::false_type());
+    if (mk) launch(std::integral_constant<int, 16>(), std::true_type());
+  }
+  if (tile_family_present<32>(G)) {
+    if (plain) launch(std::integral_constant<int, 32>(), std::false_type());
+    if (mk) launch(std::integral_constant<int, 32>(), std::true_type());
+  }
+  if (tile_family_present<64>(G)) {
+    if (plain) launch(std::integral_constant<int, 64>(), std::false_type());
+    if (mk) launch(std::integral_constant<int, 64>(), std::true_type());
+  }
+}
+
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
-  if (G.tile_blocks[0] > 0) k_spread<16><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T);
-  if (G.tile_blocks[1] > 0) k_spread<32><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T);
-  if (G.tile_blocks[2] > 0) k_spread<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
+  for_tile_variants(G, [&](auto tile, auto mk) {
+    constexpr int TL = decltype(tile)::value;
+    k_spread<TL, decltype(mk)::value><<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T);
+  });
 }
 
 void launch_lbm(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
@@ -1835,9 +1953,11 @@ void launch_lbm_timed(const WorldDev* W, const Tables& T, const Grid& G, hipStre
 void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_node) MC_PACK_DISPATCH(k_integrate, G, W, T);
   if (G.any_binned) {
-    if (G.tile_blocks[0] > 0) k_integrate_tile<16><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T);
-    if (G.tile_blocks[1] > 0) k_integrate_tile<32><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T);
-    if (G.tile_blocks[2] > 0) k_integrate_tile<64><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T);
+    for_tile_variants(G, [&](auto tile, auto mk) {
+      constexpr int TL = decltype(tile)::value;
+      k_integrate_tile<TL, decltype(mk)::value>
+          <<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T);
+    });
     k_bin_scan<<<G.world_blocks, 1024, 0, s>>>(W, T, 1);  // bins of the new positions
   }
 }
@@ -1845,14 +1965,6 @@ void launch_integrate(const WorldDev* W, const Tables& T, const Grid& G, hipStre
 void launch_markers(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   if (G.any_markers) MC_PACK_DISPATCH(k_markers, G, W, T);
 }
-
-// Binned MDF tile passes, once per tile family present.
-#define MC_TILE_DISPATCH(KERNEL, G, ...)                                                             \
-  do {                                                                                               \
-    if ((G).tile_blocks[0] > 0) KERNEL<16><<<(G).tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(__VA_ARGS__); \
-    if ((G).tile_blocks[1] > 0) KERNEL<32><<<(G).tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(__VA_ARGS__); \
-    if ((G).tile_blocks[2] > 0) KERNEL<64><<<(G).tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(__VA_ARGS__); \
-  } while (0)
 
 void launch_mdf_moments(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   k_mdf_moments<<<G.item_blocks, 256, 0, s>>>(W, T);
@@ -1863,9 +1975,11 @@ void launch_mdf(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
   k_mdf_moments<<<G.item_blocks, 256, 0, s>>>(W, T);
   if (G.any_node) MC_PACK_DISPATCH(k_mdf_desired, G, W, T);
   if (G.any_binned) {
-    if (G.tile_blocks[0] > 0) k_mdf_gather_tile<16, true><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T, 0);
-    if (G.tile_blocks[1] > 0) k_mdf_gather_tile<32, true><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T, 0);
-    if (G.tile_blocks[2] > 0) k_mdf_gather_tile<64, true><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T, 0);
+    for_tile_variants(G, [&](auto tile, auto mk) {
+      constexpr int TL = decltype(tile)::value;
+      k_mdf_gather_tile<TL, true, decltype(mk)::value>
+          <<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T, 0);
+    });
   }
   for (int iter = 1; iter < G.mdf_max; ++iter) {
     if (G.any_node) {
@@ -1873,13 +1987,16 @@ void launch_mdf(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s
       MC_PACK_DISPATCH(k_mdf_correct, G, W, T, iter);
     }
     if (G.any_binned) {
-      if (G.tile_blocks[0] > 0)
-        k_mdf_gather_tile<16, false><<<G.tile_blocks[0], TileCfg<16>::kThreads, 0, s>>>(W, T, iter);
-      if (G.tile_blocks[1] > 0)
-        k_mdf_gather_tile<32, false><<<G.tile_blocks[1], TileCfg<32>::kThreads, 0, s>>>(W, T, iter);
-      if (G.tile_blocks[2] > 0)
-        k_mdf_gather_tile<64, false><<<G.tile_blocks[2], TileCfg<64>::kThreads, 0, s>>>(W, T, iter);
-      MC_TILE_DISPATCH(k_mdf_spread_tile, G, W, T, iter);
+      for_tile_variants(G, [&](auto tile, auto mk) {
+        constexpr int TL = decltype(tile)::value;
+        k_mdf_gather_tile<TL, false, decltype(mk)::value>
+            <<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T, iter);
+      });
+      for_tile_variants(G, [&](auto tile, auto mk) {
+        constexpr int TL = decltype(tile)::value;
+        k_mdf_spread_tile<TL, decltype(mk)::value>
+            <<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T, iter);
+      });
     }
   }
 }

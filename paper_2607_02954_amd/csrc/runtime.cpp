@@ -79,8 +79,8 @@ sim_status check_params(const sim_params* p) {
   if (!(p->energy_rate >= 0.f && p->energy_rate <= 1.f)) return fail(SIM_E_INVALID, "energy_rate must be in [0, 1]");
   if (p->mdf_iters < 0 || p->mdf_iters > 64) return fail(SIM_E_INVALID, "mdf_iters must be in 1..64 (0 means 1)");
   if (!(p->marker_offset >= 0.f && p->marker_offset <= 1.f)) return fail(SIM_E_INVALID, "marker_offset must be in [0, 1]");
-  if (p->marker_offset > 0.f && !(p->flags & SIM_SPLAT_DIRECT))
-    return fail(SIM_E_INVALID, "two-layer markers need SIM_SPLAT_DIRECT");
+  if (p->marker_offset > 0.f && (p->flags & SIM_SPLAT_SORTED))
+    return fail(SIM_E_INVALID, "two-layer markers need the binned or the direct transfer");
   if (p->mdf_iters > 1 && (p->flags & SIM_SPLAT_SORTED))
     return fail(SIM_E_INVALID, "multi-direct forcing needs the binned or the direct transfer");
   if (p->flags & ~(uint32_t)(SIM_SPLAT_SORTED | SIM_SPLAT_DIRECT)) return fail(SIM_E_INVALID, "unknown flag bits");
@@ -98,7 +98,7 @@ struct WorldBufs {
   float* fel = nullptr;
   float* fel_el = nullptr;
   float* e_node = nullptr;      // [N] sensed energy; worlds with an energy rate
-  float* d_marker = nullptr;    // [2][N] two-layer marker displacement (direct transfer)
+  float* d_marker = nullptr;    // [2][N] two-layer marker displacement (binned and direct transfers)
   float* U_d = nullptr;         // [2][N] MDF desired velocity
   float* mdf_c = nullptr;       // [2][N] MDF correction per node (binned transfer)
   float4* rho_j = nullptr;      // [ncell] MDF moments
@@ -164,6 +164,7 @@ void carve_world_bufs(Carver& c, const sim_params& p, int n_part, WorldBufs& b) 
     b.tile_rng = c.take<int2>((size_t)tiles_x(p) * tiles_y(p) * 2 * mc::kRunStride);
     b.sp_rec = c.take<int4>((size_t)tiles_x(p) * tiles_y(p) * mc::spread_cap_of_side(tile_side(p)));
     b.sp_cnt = c.take<int>((size_t)tiles_x(p) * tiles_y(p));
+    if (p.marker_offset > 0.f) b.d_marker = c.take<float>(2 * N);
     if (p.mdf_iters > 1) {
       b.U_d = c.take<float>(2 * N);
       b.mdf_c = c.take<float>(2 * N);
@@ -492,6 +493,18 @@ struct Engine {
     }
     if (any_markers && !grid.any_markers) {
       grid.any_markers = 1;
+      more = true;
+    }
+    // the one-layer tile variants are left out while every tile world has markers
+    bool tile_plain = false, tile_mk = false;
+    for (const auto& sl : slots) {
+      if (!sl.used || mode_of(sl.p) == mc::kDirect) continue;
+      if (mode_of(sl.p) == mc::kBinned && sl.b.d_marker) tile_mk = true;
+      else tile_plain = true;
+    }
+    const int mk_only = tile_mk && !tile_plain ? 1 : 0;
+    if (mk_only != grid.mk_only) {
+      grid.mk_only = mk_only;
       more = true;
     }
     if (mdf_max > grid.mdf_max) {
@@ -1420,6 +1433,7 @@ sim_status sim_step_noalloc(const sim_params* p, const sim_arrays* a, int64_t t,
   g.max_radius = p->repulse_radius;
   g.any_energy = p->energy_rate > 0.f && a->energy ? 1 : 0;
   g.any_markers = L.b.d_marker ? 1 : 0;
+  g.mk_only = mode == mc::kBinned && L.b.d_marker ? 1 : 0;
   g.mdf_max = L.b.U_d ? std::max(p->mdf_iters, 1) : 1;
   g.general = slot_general(sl) ? 1 : 0;
 
@@ -1672,6 +1686,7 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
                   mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
     if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
     if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
+    if (s.b.d_marker) return fail(SIM_E_INVALID, "sim_backward does not differentiate two-layer markers");
     if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   }
   size_t need = 0;

@@ -158,7 +158,7 @@ class Params:
     tile: int = 32                    # grid tile side of the tile kernels: 16, 32 or 64
     energy_rate: float = 0.0          # energy field collection rate (0: no field)
     mdf_iters: int = 1                # multi-direct forcing iterations (binned or direct transfer)
-    marker_offset: float = 0.0        # two-layer marker offset in cells (direct transfer)
+    marker_offset: float = 0.0        # two-layer marker offset in cells (binned or direct transfer)
 
     def flags(self) -> int:
         return {"binned": 0, "sorted": SIM_SPLAT_SORTED, "direct": SIM_SPLAT_DIRECT}[self.transfer]

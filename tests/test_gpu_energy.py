@@ -51,17 +51,20 @@ def test_packets_match_oracle():
     assert e <= TOL_E
 
 
-@pytest.mark.parametrize("mode", MODES)
-def test_energy_steps_match_oracle(mode):
+@pytest.mark.parametrize("mode,offset", [(m, 0.0) for m in MODES] + [("binned", 0.5), ("direct", 0.5)])
+def test_energy_steps_match_oracle(mode, offset):
+    # with two-layer markers the nodes still sense and deplete the field at
+    # their own positions (the binned transfer then reads a wider spread list)
     sim = _sim()
     rate = 0.3
     w = wl.energy_world(1, nx=96, ny=80, n_fil=10, length=24)
     E, _ = _field(sim, w)
     w.energy = E.cpu().numpy()
-    p = sim.Params(nx=w.nx, ny=w.ny, transfer=mode, energy_rate=rate)
+    p = sim.Params(nx=w.nx, ny=w.ny, transfer=mode, energy_rate=rate, marker_offset=offset)
     W = sim.World(w, p)
     plain = sim.World(wl.energy_world(1, nx=96, ny=80, n_fil=10, length=24), sim.Params(nx=w.nx, ny=w.ny,
-                                                                                        transfer=mode))
+                                                                                        transfer=mode,
+                                                                                        marker_offset=offset))
     op = oracle_params(p)
     topo = O.Topology(w.fil_offset)
     worst = [0.0, 0.0, 0.0]
@@ -85,7 +88,7 @@ def test_energy_steps_match_oracle(mode):
                 assert torch.equal(getattr(W.state, k), getattr(plain.state, k)), (t, k)
     lost = E0 - float(W.state.energy.double().sum())
     got = float(W.state.energy_collected.double().sum())
-    print(f"energy [{mode}], 20 steps: field {worst[0]:.2e} sensed {worst[1]:.2e} collected {worst[2]:.2e}; "
+    print(f"energy [{mode}, offset {offset}], 20 steps: field {worst[0]:.2e} sensed {worst[1]:.2e} collected {worst[2]:.2e}; "
           f"field lost {lost:.6e}, collected {got:.6e}")
     assert abs(lost - got) <= 1e-4 * got
 

@@ -23,6 +23,19 @@ spread (needed: the tile's own cells):
   * a tile reads at most four bin columns in at most two runs, so a tile's
     bin set has at most eight runs (for every tile side: the margins, at most
     R + 3 = 11 cells, are shorter than a tile).
+
+Two-layer markers (a marker's home cell is its node's shifted by -1, 0 or 1
+cell, as the marker offset is at most one cell): the spread keeps nodes one
+cell further out on each side (origin four cells before the tile) and
+stages their gradient over a window two cells wider; a marker goes into the
+one-layer window by the one-layer rule applied to its own home; the
+spread's bins are those of the widened node range, and the integrate and
+MDF gathers stage the velocity one cell wider on each side.  Checked: every
+marker touching a tile cell is spread, its node kept and in the bins, its
+contribution lands where the tile's cell is read, every kept node's
+gradient support and every spread marker stay inside their windows, the
+kept nodes lie in the filter's keep set and bins (the filter writes the
+spread lists), and the gather supports stay inside the staged field.
 """
 import numpy as np
 import pytest
@@ -89,6 +102,42 @@ def check_reader(n, first, need, cols, bound_shift=0, side_shift=0, TILE=32):
     return kept
 
 
+def check_marker_reader(n, x0, tw, cols, TILE=32, node_bound_shift=0, g_side_shift=0):
+    """Two-layer spread of the tile [x0, x0 + tw) on one axis: returns the
+    node keep mask over home cells 0..n-1.  The shifts plant mistakes."""
+    h = np.arange(n)
+    dn = (h - 1 - (x0 - 4)) % n                # node support origin in the gradient window
+    nbound = (tw + 4 if tw + 5 <= n else n) + node_bound_shift
+    nkept = dn <= nbound
+    g_side = TILE + 8 + g_side_shift
+    assert np.all(dn[nkept] + 3 <= g_side - 1), (n, x0, tw)
+    in_bins = np.isin(h // TILE, cols)
+    single = tw + 3 <= n
+    mbound = tw + 2 if single else n
+    for s in (-1, 0, 1):
+        mh = h + s                             # marker home, unwrapped
+        dm = (mh - 1 - (x0 - 3)) % n           # marker support origin in the force window
+        spread = dm <= mbound
+        assert np.all(dm[spread] + 3 <= TILE + 5), (n, x0, tw, s)
+        for k in range(4):
+            c = (mh - 1 + k) % n
+            p = dm + k
+            rel = (c - x0) % n
+            needed = rel < tw if tw < n else np.ones(n, bool)
+            assert np.all(spread[needed]), (n, x0, tw, s, k)
+            assert np.all(nkept[needed]), (n, x0, tw, s, k)
+            assert np.all(in_bins[needed]), (n, x0, tw, s, k, cols)
+            if single:
+                assert np.all(p[needed] == 3 + rel[needed]), (n, x0, tw, s, k)
+            else:
+                assert np.all((p[needed] - 3 - rel[needed]) % n == 0), (n, x0, tw, s, k)
+        # gathers of the tile's own nodes: staged cells x0 - 2 .. x0 + TILE + 2
+        own = (h >= x0) & (h < x0 + tw)
+        lo = mh[own] - 1 - (x0 - 2)
+        assert np.all(lo >= 0) and np.all(lo + 3 <= TILE + 4), (n, x0, tw, s)
+    return nkept
+
+
 @pytest.mark.parametrize("TILE", TILES)
 def test_binned_transfer_windows_and_bins(TILE):
     cases = 0
@@ -96,9 +145,10 @@ def test_binned_transfer_windows_and_bins(TILE):
     for n in range(1, top):
         for x0 in range(0, n, TILE):
             tw = min(TILE, n - x0)
-            sp_cols = covering_columns(x0 - 2, x0 + tw, n, TILE)
+            sp_cols = covering_columns(x0 - 3, x0 + tw + 1, n, TILE)   # widened for the markers
             assert len(sp_cols) <= MAX_COLS[TILE] and runs(sp_cols) <= 2
             sp_kept = check_reader(n, x0, tw, sp_cols, TILE=TILE)
+            mk_kept = check_marker_reader(n, x0, tw, sp_cols, TILE=TILE)
             for R in range(1, 9):
                 reg = TILE + 2 + 2 * R
                 xo = x0 - R - 1
@@ -108,6 +158,8 @@ def test_binned_transfer_windows_and_bins(TILE):
                 h = np.arange(n)
                 assert np.all(f_kept[sp_kept]), (n, x0, R)
                 assert np.all(np.isin(h[sp_kept] // TILE, f_cols)), (n, x0, R)
+                assert np.all(f_kept[mk_kept]), (n, x0, R)
+                assert np.all(np.isin(h[mk_kept] // TILE, f_cols)), (n, x0, R)
                 cases += 1
     assert cases > 2000
 
@@ -143,3 +195,25 @@ def test_planted_mistakes_are_caught(mistake):
         kw = {"side_shift": -1}
     with pytest.raises(AssertionError):
         check_reader(n, x0 - R - 1, reg, cols, **kw)
+
+
+@pytest.mark.parametrize("mistake", ["node keep one short", "gradient window one short", "one-layer bins"])
+def test_planted_marker_mistakes_are_caught(mistake):
+    # the marker check is sharp too: a node keep bound one cell short, a
+    # gradient window one cell short, or the one-layer spread bins on an
+    # axis whose last tile is narrower than the extra cell fail it
+    TILE = 32
+    if mistake == "one-layer bins":
+        n, x0 = 98, 0                          # last tile 2 cells wide: home 95 lies in tile 2
+        tw = min(TILE, n - x0)
+        check_marker_reader(n, x0, tw, covering_columns(x0 - 3, x0 + tw + 1, n, TILE))
+        with pytest.raises(AssertionError):
+            check_marker_reader(n, x0, tw, covering_columns(x0 - 2, x0 + tw, n, TILE))
+        return
+    n, x0 = 160, 64
+    tw = TILE
+    cols = covering_columns(x0 - 3, x0 + tw + 1, n)
+    check_marker_reader(n, x0, tw, cols)
+    kw = {"node_bound_shift": -1} if mistake == "node keep one short" else {"g_side_shift": -1}
+    with pytest.raises(AssertionError):
+        check_marker_reader(n, x0, tw, cols, **kw)
