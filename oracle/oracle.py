@@ -468,9 +468,11 @@ def marker_normals(x, topo: Topology):
     a = torch.where(has_prev, prv, i)
     b = torch.where(has_next, nxt, i)
     t = x[:, b.clamp(0, max(N - 1, 0))] - x[:, a.clamp(0, max(N - 1, 0))]
-    norm = torch.sqrt(t[0] ** 2 + t[1] ** 2)
-    safe = torch.where(norm > 0, norm, torch.ones_like(norm))
-    t = torch.where(norm > 0, t / safe, torch.zeros_like(t))
+    n2 = t[0] ** 2 + t[1] ** 2
+    # the square root of a masked length, so that a node without a tangent
+    # (its normal is zero) also has a zero derivative rather than 0 * inf
+    safe = torch.sqrt(torch.where(n2 > 0, n2, torch.ones_like(n2)))
+    t = torch.where(n2 > 0, t / safe, torch.zeros_like(t))
     return torch.stack([-t[1], t[0]])
 
 

@@ -78,8 +78,14 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const Wo
     zero_lds_u64(s_x, kSpreadCells);
     zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
-    tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
-                                 spread_fetch<TILE>(w, x0, y0), nullptr);
+    // the transfers of the node<->grid coupling act through two-layer
+    // markers where a world has them; the repulsion (G~) stays at the node
+    if (w.d_marker && which != 1 && which != 4)
+      tile_spread_markers<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list,
+                                       glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+    else
+      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
+                                   spread_fetch<TILE>(w, x0, y0), nullptr);
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
@@ -191,7 +197,12 @@ __global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W,
 
 // ---------------------------------------------------------------------------
 // S5/S4/S7 node terms: dL/dF_i = sum_c W(c - x_i) dL/dF_grid(c), and the
-// derivative of the three node<->grid transfers with respect to x_t.
+// derivative of the three node<->grid transfers with respect to x_t.  In a
+// two-layer world the force spread and the velocity gather act through the
+// markers X = x +- d (half weight each): dL/dF_i and both transfers' position
+// terms are formed per marker; their sum goes to dL/dx_i and their
+// difference (dL/dd) to A.dbar, which k_adj_markers carries through the
+// normal d(x_prev, x_next).  The repulsion gather stays at the node.
 // ---------------------------------------------------------------------------
 template <int PACK>
 __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
@@ -242,6 +253,47 @@ __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__
         sfy += Wy * pf;
       }
     }
+    if (w.d_marker) {                   // two layers: the transfer terms again, at the markers
+      fbx = fby = 0.f;
+      sux = suy = sfx = sfy = 0.f;
+      const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
+      float dbx = 0.f, dby = 0.f;
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        const float sg = l == 0 ? 1.f : -1.f;
+        int shx, shy;
+        float mfx, mfy;
+        marker_shift(frac[gi], sg * ddx, &shx, &mfx);
+        marker_shift(frac[N + gi], sg * ddy, &shy, &mfy);
+        const int mbx = wrap_index(cell[gi] + shx, nx), mby = wrap_index(cell[N + gi] + shy, ny);
+        float mwx[4], mdwx[4], mwy[4], mdwy[4];
+        peskin4_d(mfx, mwx, mdwx);
+        peskin4_d(mfy, mwy, mdwy);
+        float px = 0.f, py = 0.f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const size_t row = (size_t)wrap_near(mby - 1 + b, ny) * nx;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const size_t c = row + wrap_near(mbx - 1 + a, nx);
+            const vf2 uc = u[c];
+            const vf2 fc = Fgb[c];
+            const float W0 = 0.5f * mwx[a] * mwy[b], Wx = 0.5f * mdwx[a] * mwy[b], Wy = 0.5f * mwx[a] * mdwy[b];
+            fbx += W0 * fc.x;
+            fby += W0 * fc.y;
+            const float pp = (uc.x * xbx + uc.y * xby) + (Fx * fc.x + Fy * fc.y);
+            px += Wx * pp;
+            py += Wy * pp;
+          }
+        }
+        sux += px;                      // dL/dX of each marker moves the node ...
+        suy += py;
+        dbx += sg * px;                 // ... and, with its sign, the displacement
+        dby += sg * py;
+      }
+      A.dbar[gi] = dbx;
+      A.dbar[N + gi] = dby;
+    }
     float mx = 0.f, my = 0.f;
     if (A.mdf > 1) {                    // U_d = I[j / rho] + F / 2, and the MDF transfers' position terms
       fbx += 0.5f * A.Udbar[gi];
@@ -264,6 +316,102 @@ __global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__
     A.Fbar[N + gi] = fby;
     A.xbar[gi] = xbx + sux + sfx - kr * srx + mx;
     A.xbar[N + gi] = xby + suy + sfy - kr * sry + my;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-layer markers reversed: d_i = delta n_i with n_i the unit normal
+// (-t_y, t_x) / |t| of the tangent t = x_b - x_a (a, b: the node's
+// neighbours, or the node itself at a chain end; as in k_markers).  From
+// dL/dd (A.dbar, plus the MDF transfers' A.dbar_m): dL/dt = (delta / |t|)
+// (I - t^ t^T) (dd~_y, -dd~_x), added to dL/dx_b and subtracted from
+// dL/dx_a.  Each node gathers the terms of the nodes whose tangent it ends
+// or starts, in a fixed order.
+// ---------------------------------------------------------------------------
+template <int PACK>
+__global__ __launch_bounds__(PACK) void k_adj_markers(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
+  __shared__ int s_off[PACK + 1];
+  __shared__ vf2 s_tb[PACK];
+  const int npk = *T.n_packs;
+  const int li = threadIdx.x;
+  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
+    const Pack pk = T.packs[it];
+    const WorldDev& w = W[pk.world];
+    if (!w.d_marker) continue;                                  // block-uniform
+    const AdjDev& A = adj_of(AA, pk.world);
+    const int nf = pk.fil_end - pk.fil_begin;
+    for (int k = li; k <= nf; k += PACK) s_off[k] = glb(w.fil_offset)[pk.fil_begin + k] - pk.node_begin;
+    __syncthreads();
+    const int gi = pk.node_begin + li;
+    const bool live = gi < pk.node_end;
+    int o = 0, n = 1, k = 0;
+    bool ring = false;
+    if (live) {
+      int lo = 0, hi = nf - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= li) lo = mid; else hi = mid - 1;
+      }
+      o = s_off[lo];
+      n = s_off[lo + 1] - o;
+      k = li - o;
+      ring = w.fil_flags && (glb(w.fil_flags)[pk.fil_begin + lo] & 1) && n >= 3;
+      const int first = pk.node_begin + o;
+      int a = gi, b = gi;
+      if (k > 0) a = gi - 1; else if (ring) a = first + n - 1;
+      if (k < n - 1) b = gi + 1; else if (ring) b = first;
+      const int N = w.n_part;
+      const MC_GLOBAL int* cell = glb(w.cell_in);
+      const MC_GLOBAL float* frac = glb(w.frac_in);
+      const float tx = (float)(cell[b] - cell[a]) + (frac[b] - frac[a]);
+      const float ty = (float)(cell[N + b] - cell[N + a]) + (frac[N + b] - frac[N + a]);
+      const float len = sqrtf(tx * tx + ty * ty);
+      float dbx = A.dbar[gi], dby = A.dbar[N + gi];
+      if (A.mdf > 1) {
+        dbx += A.dbar_m[gi];
+        dby += A.dbar_m[N + gi];
+      }
+      vf2 tb = {0.f, 0.f};
+      if (len > 0.f) {
+        const float inv = 1.0f / len, hx = tx * inv, hy = ty * inv;
+        const float vx = dby, vy = -dbx;
+        const float dot = hx * vx + hy * vy;
+        const float sc = w.marker_offset * inv;
+        tb.x = sc * (vx - hx * dot);
+        tb.y = sc * (vy - hy * dot);
+      }
+      s_tb[li] = tb;
+    }
+    __syncthreads();
+    if (live) {
+      // + the tangent ending here (the previous node's, or this chain end's
+      // own), - the tangent starting here (the next node's, or this chain
+      // start's own)
+      const int last = o + n - 1;
+      float ax = 0.f, ay = 0.f;
+      if (k > 0 || ring) {
+        const int p = k > 0 ? li - 1 : last;
+        ax += s_tb[p].x;
+        ay += s_tb[p].y;
+      }
+      if (k == n - 1 && !ring) {
+        ax += s_tb[li].x;
+        ay += s_tb[li].y;
+      }
+      if (k < n - 1 || ring) {
+        const int q = k < n - 1 ? li + 1 : o;
+        ax -= s_tb[q].x;
+        ay -= s_tb[q].y;
+      }
+      if (k == 0 && !ring) {
+        ax -= s_tb[li].x;
+        ay -= s_tb[li].y;
+      }
+      const int N = w.n_part;
+      A.xbar[gi] += ax;
+      A.xbar[N + gi] += ay;
+    }
+    __syncthreads();
   }
 }
 
@@ -882,6 +1030,7 @@ void launch_adjoint_debug(const WorldDev* W, const Tables& T, const Grid& G, int
 }
 
 void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, const AdjArg& A, int mdf, hipStream_t s) {
+  if (G.any_markers) launch_markers(W, T, G, s);    // the step's marker displacements, from x_t
   MC_ADJ_TILES(k_adj_spread, G, W, T, A, 0, 0);
   k_adj_lbm<<<G.item_blocks, 256, 0, s>>>(W, T, A);
   if (mdf > 1) {
@@ -904,6 +1053,7 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
     MC_ADJ_TILES2(k_adj_mdf_cell, 1, G, W, T, A, 0);
   }
   MC_ADJ_PACK(k_adj_force, G, W, T, A);
+  if (G.any_markers) MC_ADJ_PACK(k_adj_markers, G, W, T, A);
   MC_ADJ_TILES(k_adj_spread, G, W, T, A, 1, 0);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
   MC_ADJ_PACK(k_adj_pbd, G, W, T, A);

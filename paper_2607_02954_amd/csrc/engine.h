@@ -189,6 +189,9 @@ struct AdjDev {
   float* xbar_m;          // [2][N] the MDF transfers' terms of dL/dx_t
   float2* jbar;           // [ny][nx] dL/dj through MDF
   float* rhobar;          // [ny][nx] dL/drho through MDF
+  // two-layer markers (worlds with marker displacements d; X = x +- d)
+  float* dbar;            // [2][N] dL/dd of the step, from the node kernels
+  float* dbar_m;          // [2][N] dL/dd through the MDF transfers (MDF worlds)
   const float* dbg_v;     // test hook: the node vector a single spread reads
   float2* dbg_out;        // and the grid it writes
 };

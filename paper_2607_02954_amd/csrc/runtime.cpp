@@ -1586,6 +1586,9 @@ struct AdjLayout {
   float* xbar_m = nullptr;           // [2][N]
   float2* jbar = nullptr;            // [ncell]
   float* rhobar = nullptr;           // [ncell]
+  // two-layer markers
+  float* dbar = nullptr;             // [2][N]
+  float* dbar_m = nullptr;           // [2][N] (with MDF)
 };
 
 void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) {
@@ -1638,6 +1641,10 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
     L.jbar = c.take<float2>(L.ncell);
     L.rhobar = c.take<float>(L.ncell);
   }
+  if (p.marker_offset > 0.f) {
+    L.dbar = c.take<float>(2 * L.N);
+    if (p.mdf_iters > 1) L.dbar_m = c.take<float>(2 * L.N);
+  }
   L.bytes = c.off;
 }
 
@@ -1686,7 +1693,8 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
                   mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
     if (s.any_loop) return fail(SIM_E_INVALID, "sim_backward does not differentiate worlds with closed loops");
     if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
-    if (s.b.d_marker) return fail(SIM_E_INVALID, "sim_backward does not differentiate two-layer markers");
+    if (s.b.d_marker && s.p.mdf_iters > 1)
+      return fail(SIM_E_INVALID, "sim_backward does not differentiate two-layer markers with multi-direct forcing");
     if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   }
   size_t need = 0;
@@ -1764,6 +1772,8 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
         A.xbar_m = L.xbar_m;
         A.jbar = L.jbar;
         A.rhobar = L.rhobar;
+        A.dbar = L.dbar;
+        A.dbar_m = L.dbar_m;
         ha[((size_t)j * 2 + cur) * nw + k] = A;
       }
     }

@@ -32,7 +32,8 @@ def _oparams(p):
     return O.Params(nx=p.nx, ny=p.ny, tau=p.tau, trt_magic=p.trt_magic, k_bend=p.k_bend,
                     k_stretch=p.k_stretch, k_shear=p.k_shear, pbd_iters=p.pbd_iters,
                     k_elastic=p.k_elastic, k_repulse=p.k_repulse, sigma=p.sigma_repulse,
-                    radius=p.repulse_radius, u_max=p.u_max, mdf_iters=p.mdf_iters)
+                    radius=p.repulse_radius, u_max=p.u_max, mdf_iters=p.mdf_iters,
+                    marker_offset=p.marker_offset)
 
 
 def _gpu_grad(sim, w, target, n, k, **kw):
@@ -271,5 +272,25 @@ def test_adjoint_through_mdf_matches_oracle(mdf, tile):
     print(f"adjoint through MDF K={mdf} (tile {tile}): rel err {err:.2e} cos {cos:.6f}")
     assert err <= 1e-3 and cos >= 0.9999
     # without MDF the gradient differs: the test sees the MDF terms
+    g1, _, _, _ = _gpu_grad(sim, w, target, 12, 5, tile=tile)
+    assert np.linalg.norm(g1 - g) > 10 * err * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("offset,tile", [(0.5, 32), (1.0, 16), (0.7, 64)])
+def test_adjoint_through_two_layers_matches_oracle(offset, tile):
+    """The gradient through two-layer markers (binned transfer): the force
+    spread and the velocity gather at both markers, and the markers' normals
+    as functions of the neighbouring nodes, against the oracle's reverse mode
+    of the same forward, on chains with one- and two-node filaments."""
+    sim = _sim()
+    w = wl.random_world(17, 72, 56, [14, 9, 22, 3, 1, 2], amp=0.5)
+    x0 = w.positions64()
+    target = x0 + np.random.default_rng(2).normal(0, 0.5, size=x0.shape)
+    g, loss, W, p = _gpu_grad(sim, w, target, 12, 5, marker_offset=offset, tile=tile)
+    ref, _ = _oracle_grad(w, p, target, 12, 5)
+    err, cos = _compare(g, ref, _joints(w))
+    print(f"adjoint through two layers, offset {offset} (tile {tile}): rel err {err:.2e} cos {cos:.6f}")
+    assert err <= 1e-3 and cos >= 0.9999
+    # one layer gives a different gradient: the test sees the marker terms
     g1, _, _, _ = _gpu_grad(sim, w, target, 12, 5, tile=tile)
     assert np.linalg.norm(g1 - g) > 10 * err * np.linalg.norm(g)

@@ -15,6 +15,10 @@ itself).
     iteration; on unit-spaced
     chains (a strongly coupled, ill-conditioned system) the mismatch still
     falls monotonically.
+  * the reverse mode through the two-layer transfers (the markers' normals
+    as functions of the neighbouring nodes included) agrees with central
+    differences, and stays finite where a single-node filament has no
+    normal (its markers sit on the node; the derivative there is zero).
 Planted mistakes (markers both on one side, the correction without its
 factor 2) are rejected.
 """
@@ -138,3 +142,35 @@ def test_mdf_approaches_no_slip():
     mm = tr["mdf_mismatch"]
     assert all(b <= a * (1 + 1e-9) for a, b in zip(mm, mm[1:])), mm
     assert mm[-1] < 0.5 * mm[0], (mm[0], mm[-1])
+
+
+def test_two_layer_reverse_mode_matches_central_differences():
+    # L(x) = sum_c R_c . S2[v](c) + sum_i q_i . I2[u](x_i) for fixed random
+    # R, v, u, q: its gradient in x only flows through the marker positions
+    topo = O.Topology(np.array([0, 5, 6, 9]))      # a chain, a single node, a short chain
+    p = O.Params(nx=16, ny=12, marker_offset=0.6)
+    g = np.random.default_rng(3)
+    x0 = torch.tensor(np.stack([g.uniform(2, 14, 9), g.uniform(2, 10, 9)]), dtype=DT)
+    v = torch.tensor(g.normal(size=(2, 9)), dtype=DT)
+    q = torch.tensor(g.normal(size=(2, 9)), dtype=DT)
+    R = torch.tensor(g.normal(size=(2, 12, 16)), dtype=DT)
+    u = torch.tensor(g.normal(size=(2, 12, 16)), dtype=DT)
+
+    def L(x):
+        return (O.spread2(x, v, topo, p) * R).sum() + (O.interpolate2(x, u, topo, p) * q).sum()
+
+    x = x0.clone().requires_grad_(True)
+    L(x).backward()
+    grad = x.grad
+    assert torch.isfinite(grad).all()
+    h = 1e-6
+    fd = torch.zeros_like(x0)
+    for k in range(2):
+        for i in range(9):
+            e = torch.zeros_like(x0)
+            e[k, i] = h
+            fd[k, i] = (L(x0 + e) - L(x0 - e)) / (2 * h)
+    assert torch.allclose(grad, fd, rtol=1e-6, atol=1e-7), float((grad - fd).abs().max())
+    # the single node's own markers coincide with it: its gradient is the
+    # one-layer transfers' gradient there
+    assert float(grad[:, 5].abs().max()) > 0
