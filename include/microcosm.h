@@ -108,8 +108,9 @@ typedef struct sim_params {
                               samples) the mean of their velocities; density
                               deposit, repulsion and energy stay at the node.
                               The tile-binned and the direct transfer; not
-                              with SIM_SPLAT_SORTED; sim_backward refuses it.
-                              0: one layer                                     */
+                              with SIM_SPLAT_SORTED; sim_backward
+                              differentiates it (binned transfer, with or
+                              without MDF).  0: one layer                      */
 } sim_params;
 
 /* State and per-node arrays of one world (DEVICE pointers, caller-owned).
@@ -237,8 +238,8 @@ sim_status sim_checkpoint_size(const sim_world *w, int32_t n_steps, int32_t ckpt
  * checkpoints written by sim_rollout(t0, n_steps, ckpt_every) and g_pos =
  * dL/dx at the final step ([2][N] device floats), ACCUMULATES dL/d(rest_angle)
  * into g_rest_angle ([N], caller zeroes) and, if g_pos0 is not NULL, WRITES
- * dL/dx at t0 into g_pos0 ([2][N]).  Worlds with closed loops, branches or
- * two-layer markers are not differentiated (SIM_E_INVALID).  Each segment is recomputed forward from
+ * dL/dx at t0 into g_pos0 ([2][N]).  Worlds with closed loops or branches
+ * are not differentiated (SIM_E_INVALID).  Each segment is recomputed forward from
  * its checkpoint into adj_ws, then hand-written adjoint kernels run step by
  * step in reverse.  adj_ws must hold sim_backward_workspace_size bytes.
  * The world's own state arrays are not modified.  Only worlds that use the

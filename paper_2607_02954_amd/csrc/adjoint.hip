@@ -735,21 +735,24 @@ __global__ void k_adj_mdf_zero(const WorldDev* __restrict__ W, Tables T, AdjArg 
     else if (i < 2 * n2) A.xbar_m[i - n2] = 0.f;
     else if (i < 2 * n2 + 2 * nc) ((float*)A.jbar)[i - 2 * n2] = 0.f;
     else A.rhobar[i - 2 * n2 - 2 * nc] = 0.f;
+    if (A.dbar_m && i < n2) A.dbar_m[i] = 0.f;
   }
 }
 
-// Cells (x0 - 1 + c, y0 - 1 + r), c, r in [0, TILE + 3), of a tile: value(idx)
-// of each (periodic grid index) into st; all loads before the stores.
-template <int TILE, class V>
+// Cells (x0 - 1 - E + c, y0 - 1 - E + r), c, r in [0, TILE + 3 + 2E), of a
+// tile: value(idx) of each (periodic grid index) into st; all loads before
+// the stores.  E = 1 reaches the supports of the tile's nodes' two-layer
+// markers.
+template <int TILE, int E, class V>
 static __device__ __forceinline__ void adj_stage(int nx, int ny, int x0, int y0, vf2* st, V value) {
-  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kStage = TILE + 3 + 2 * E, kThreads = TileCfg<TILE>::kThreads;
   constexpr int kIt = (kStage * kStage + kThreads - 1) / kThreads;
   vf2 v[kIt];
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
     const int k = min((int)threadIdx.x + kThreads * i, kStage * kStage - 1);
     const int r = k / kStage, c = k - (k / kStage) * kStage;
-    v[i] = value((size_t)wrap_index(y0 - 1 + r, ny) * nx + wrap_index(x0 - 1 + c, nx));
+    v[i] = value((size_t)wrap_index(y0 - 1 - E + r, ny) * nx + wrap_index(x0 - 1 - E + c, nx));
   }
 #pragma unroll
   for (int i = 0; i < kIt; ++i) {
@@ -758,24 +761,51 @@ static __device__ __forceinline__ void adj_stage(int nx, int ny, int x0, int y0,
   }
 }
 
-// U_d (DESIRED) or the correction c_k of the iterate Fgk at the tile's own nodes.
-template <int TILE, bool DESIRED>
+// The points a tile node acts through, relative to the staged window of
+// adj_stage<TILE, MK ? 1 : 0>: the node itself (weight 1), or its two
+// markers (weight 1/2 each); f(l, lx, ly, fx, fy, h) is called for each with
+// the support origin in the window, the point's fractions and its weight.
+template <bool MK, class Fn>
+static __device__ __forceinline__ void for_points(const WorldDev& w, int gi, int lx, int ly, float fx, float fy,
+                                                  Fn f) {
+  if constexpr (MK) {
+    const int N = w.n_part;
+    const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+      const float sg = l == 0 ? 1.f : -1.f;
+      int sx, sy;
+      float mx, my;
+      marker_shift(fx, sg * ddx, &sx, &mx);
+      marker_shift(fy, sg * ddy, &sy, &my);
+      f(l, lx + sx + 1, ly + sy + 1, mx, my, 0.5f);
+    }
+  } else {
+    f(0, lx, ly, fx, fy, 1.0f);
+  }
+}
+
+// U_d (DESIRED) or the correction c_k of the iterate Fgk at the tile's own
+// nodes (MK: through their two-layer markers).
+template <int TILE, bool DESIRED, bool MK>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(const WorldDev* __restrict__ W,
                                                                                  Tables T, AdjArg AA, int k) {
-  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kE = MK ? 1 : 0;
+  constexpr int kStage = TILE + 3 + 2 * kE, kThreads = TileCfg<TILE>::kThreads;
   __shared__ vf2 s_u[kStage * kStage];
   const int nt = n_tiles<TILE>(T);
   const XcdLoop tiles(nt);
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    if (MK != (w.d_marker != nullptr)) continue;
     const AdjDev& A = adj_of(AA, tl.x);
     const float2* Fgk = A.Fgk + (size_t)(k > 0 ? k - 1 : 0) * ((size_t)w.nx * w.ny);   // iterate k (k >= 1)
     const int nx = w.nx, ny = w.ny, N = w.n_part;
     const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
     const MC_GLOBAL vf2* Fg = glbv<const vf2>(Fgk);
-    adj_stage<TILE>(nx, ny, x0, y0, s_u, [&](size_t c) {
+    adj_stage<TILE, kE>(nx, ny, x0, y0, s_u, [&](size_t c) {
       const vf4 mv = m[c];
       vf2 u;
       if (DESIRED) {
@@ -796,24 +826,38 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(
     for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
-      float wx[4], wy[4];
-      peskin4(__int_as_float(r.y), wx);
-      peskin4(__int_as_float(r.z), wy);
-      float gx = 0.f, gy = 0.f;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const vf2* row = s_u + (ly + b) * kStage + lx;
-        float ax = 0.f, ay = 0.f;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const vf2 t = row[a];
-          ax += wx[a] * t.x;
-          ay += wx[a] * t.y;
-        }
-        gx += wy[b] * ax;
-        gy += wy[b] * ay;
-      }
       const int gi = r.w;
+      float gx = 0.f, gy = 0.f;
+      float sx = 0.f, sy = 0.f;
+      for_points<MK>(w, gi, lx, ly, __int_as_float(r.y), __int_as_float(r.z),
+                     [&](int, int px, int py, float fx, float fy, float) {
+        float wx[4], wy[4];
+        peskin4(fx, wx);
+        peskin4(fy, wy);
+        float qx = 0.f, qy = 0.f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const vf2* row = s_u + (py + b) * kStage + px;
+          float ax = 0.f, ay = 0.f;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const vf2 t = row[a];
+            ax += wx[a] * t.x;
+            ay += wx[a] * t.y;
+          }
+          qx += wy[b] * ax;
+          qy += wy[b] * ay;
+        }
+        sx += qx;
+        sy += qy;
+      });
+      if (MK) {                         // the forward's order: both markers summed, then halved
+        gx = 0.5f * sx;
+        gy = 0.5f * sy;
+      } else {
+        gx = sx;
+        gy = sy;
+      }
       if (DESIRED) {
         A.Ud[gi] = gx + 0.5f * glb(w.fel)[gi];
         A.Ud[N + gi] = gy + 0.5f * glb(w.fel)[N + gi];
@@ -828,11 +872,14 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_fwd_gather(
 
 // Reverse node pass.  MODE 0 (iteration k, iterate Fgk): c~ = I[G~],
 // U_k~ = -2 c~ (stored), U_d~ += 2 c~, x~ += dI/dx terms of S[c_k] and I[u_k].
-// MODE 1 (U_d): x~ += U_d~ . dI[j / rho]/dx.
-template <int TILE, int MODE>
+// MODE 1 (U_d): x~ += U_d~ . dI[j / rho]/dx.  MK: I and S act through the
+// two markers (half weight each); each marker's position term goes to x~
+// and, with its sign, to dL/dd (A.dbar_m).
+template <int TILE, int MODE, bool MK>
 __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const WorldDev* __restrict__ W, Tables T,
                                                                            AdjArg AA, int k) {
-  constexpr int kStage = TILE + 3, kThreads = TileCfg<TILE>::kThreads;
+  constexpr int kE = MK ? 1 : 0;
+  constexpr int kStage = TILE + 3 + 2 * kE, kThreads = TileCfg<TILE>::kThreads;
   __shared__ vf2 s_g[MODE == 0 ? kStage * kStage : 1];
   __shared__ vf2 s_u[kStage * kStage];
   const int nt = n_tiles<TILE>(T);
@@ -840,6 +887,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const 
   for (int it = tiles.first; it < tiles.end; it += tiles.step) {
     const int2 tl = tile_entry<TILE>(T, it);
     const WorldDev& w = W[tl.x];
+    if (MK != (w.d_marker != nullptr)) continue;
     const AdjDev& A = adj_of(AA, tl.x);
     const float2* Fgk = A.Fgk + (size_t)(k > 0 ? k - 1 : 0) * ((size_t)w.nx * w.ny);   // iterate k (k >= 1)
     const int nx = w.nx, ny = w.ny, N = w.n_part;
@@ -847,8 +895,8 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const 
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
     const MC_GLOBAL vf2* Fg = glbv<const vf2>(Fgk);
     const MC_GLOBAL vf2* Gb = glbv<const vf2>(A.Fgbar);
-    if constexpr (MODE == 0) adj_stage<TILE>(nx, ny, x0, y0, s_g, [&](size_t c) { return Gb[c]; });
-    adj_stage<TILE>(nx, ny, x0, y0, s_u, [&](size_t c) {
+    if constexpr (MODE == 0) adj_stage<TILE, kE>(nx, ny, x0, y0, s_g, [&](size_t c) { return Gb[c]; });
+    adj_stage<TILE, kE>(nx, ny, x0, y0, s_u, [&](size_t c) {
       const vf4 mv = m[c];
       const float inv = 1.0f / mv.x;
       vf2 u;
@@ -869,24 +917,34 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const 
     for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
       const vi4 r = recs[e];
       const int lx = (r.x & 0xffff) - x0, ly = (r.x >> 16) - y0;
-      float wx[4], dwx[4], wy[4], dwy[4];
-      peskin4_d(__int_as_float(r.y), wx, dwx);
-      peskin4_d(__int_as_float(r.z), wy, dwy);
+      const float nfx = __int_as_float(r.y), nfy = __int_as_float(r.z);
       const int gi = r.w;
-      float cbx = 0.f, cby = 0.f, Ux = 0.f, Uy = 0.f;          // I[G~], I[u]
+      // I[G~] and I[u] (the forward's order: the points summed, then halved)
+      float cbx = 0.f, cby = 0.f, Ux = 0.f, Uy = 0.f;
+      for_points<MK>(w, gi, lx, ly, nfx, nfy, [&](int, int px, int py, float fx, float fy, float) {
+        float wx[4], wy[4];
+        peskin4(fx, wx);
+        peskin4(fy, wy);
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int k = (ly + b) * kStage + lx + a;
-          const float W0 = wx[a] * wy[b];
-          if (MODE == 0) {
-            cbx += W0 * s_g[k].x;
-            cby += W0 * s_g[k].y;
+          for (int a = 0; a < 4; ++a) {
+            const int q = (py + b) * kStage + px + a;
+            const float W0 = wx[a] * wy[b];
+            if (MODE == 0) {
+              cbx += W0 * s_g[q].x;
+              cby += W0 * s_g[q].y;
+            }
+            Ux += W0 * s_u[q].x;
+            Uy += W0 * s_u[q].y;
           }
-          Ux += W0 * s_u[k].x;
-          Uy += W0 * s_u[k].y;
-        }
+      });
+      if (MK) {
+        cbx *= 0.5f;
+        cby *= 0.5f;
+        Ux *= 0.5f;
+        Uy *= 0.5f;
+      }
       float Ubx, Uby;                                            // dL/d(the sampled velocity)
       float cx = 0.f, cy = 0.f;
       if (MODE == 0) {
@@ -902,19 +960,35 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_node(const 
         Ubx = A.Udbar[gi];
         Uby = A.Udbar[N + gi];
       }
-      float sx = 0.f, sy = 0.f;
+      float sx = 0.f, sy = 0.f, dx = 0.f, dy = 0.f;
+      for_points<MK>(w, gi, lx, ly, nfx, nfy, [&](int l, int px, int py, float fx, float fy, float h) {
+        float wx[4], dwx[4], wy[4], dwy[4];
+        peskin4_d(fx, wx, dwx);
+        peskin4_d(fy, wy, dwy);
+        float qx = 0.f, qy = 0.f;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int k = (ly + b) * kStage + lx + a;
-          float p = Ubx * s_u[k].x + Uby * s_u[k].y;
-          if (MODE == 0) p += cx * s_g[k].x + cy * s_g[k].y;
-          sx += dwx[a] * wy[b] * p;
-          sy += wx[a] * dwy[b] * p;
+          for (int a = 0; a < 4; ++a) {
+            const int q = (py + b) * kStage + px + a;
+            float p = Ubx * s_u[q].x + Uby * s_u[q].y;
+            if (MODE == 0) p += cx * s_g[q].x + cy * s_g[q].y;
+            qx += dwx[a] * wy[b] * p;
+            qy += wx[a] * dwy[b] * p;
+          }
+        sx += h * qx;
+        sy += h * qy;
+        if (MK) {
+          dx += (l == 0 ? h : -h) * qx;
+          dy += (l == 0 ? h : -h) * qy;
         }
+      });
       A.xbar_m[gi] += sx;
       A.xbar_m[N + gi] += sy;
+      if (MK) {
+        A.dbar_m[gi] += dx;
+        A.dbar_m[N + gi] += dy;
+      }
     }
     __syncthreads();
   }
@@ -946,8 +1020,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_mdf_cell(const 
     zero_lds_u64(s_x, kSpreadCells);
     zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
-    tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(nodevec), 1.0f, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
-                                 spread_fetch<TILE>(w, x0, y0), nullptr);
+    if (w.d_marker)                     // two layers: the nodes' vectors spread from their markers
+      tile_spread_markers<TILE, false>(w, x0, y0, tw, th, glb(nodevec), 1.0f, s_x, s_y, s_list,
+                                       glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
+    else
+      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(nodevec), 1.0f, s_x, s_y, s_list,
+                                   glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
     __syncthreads();
     const MC_GLOBAL vf4* m = glbv<const vf4>(w.rho_j);
     for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {
@@ -1038,18 +1116,32 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
     // F_grid_{k+1} = F_grid_k + S[c_k] up to K - 1
     launch_mdf_moments(W, T, G, s);
     k_adj_mdf_zero<<<dim3(32, G.world_blocks), 256, 0, s>>>(W, T, A);
-    MC_ADJ_TILES2(k_adj_mdf_fwd_gather, true, G, W, T, A, 0);
+    const auto fwd_gather = [&](auto desired, int k) {
+      for_tile_variants(G, [&](auto tile, auto mk) {
+        constexpr int TL = decltype(tile)::value;
+        k_adj_mdf_fwd_gather<TL, decltype(desired)::value, decltype(mk)::value>
+            <<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T, A, k);
+      });
+    };
+    const auto node_pass = [&](auto mode, int k) {
+      for_tile_variants(G, [&](auto tile, auto mk) {
+        constexpr int TL = decltype(tile)::value;
+        k_adj_mdf_node<TL, decltype(mode)::value, decltype(mk)::value>
+            <<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T, A, k);
+      });
+    };
+    fwd_gather(std::true_type(), 0);
     MC_ADJ_TILES(k_adj_spread, G, W, T, A, 2, 0);
     for (int k = 1; k <= mdf - 2; ++k) {
-      MC_ADJ_TILES2(k_adj_mdf_fwd_gather, false, G, W, T, A, k);
+      fwd_gather(std::false_type(), k);
       MC_ADJ_TILES(k_adj_spread, G, W, T, A, 3, k);
     }
     // reverse: iterations K - 1 .. 1 (the grid-force adjoint becomes dL/dF_grid_k), then U_d
     for (int k = mdf - 1; k >= 1; --k) {
-      MC_ADJ_TILES2(k_adj_mdf_node, 0, G, W, T, A, k);
+      node_pass(std::integral_constant<int, 0>(), k);
       MC_ADJ_TILES2(k_adj_mdf_cell, 0, G, W, T, A, k);
     }
-    MC_ADJ_TILES2(k_adj_mdf_node, 1, G, W, T, A, 0);
+    node_pass(std::integral_constant<int, 1>(), 0);
     MC_ADJ_TILES2(k_adj_mdf_cell, 1, G, W, T, A, 0);
   }
   MC_ADJ_PACK(k_adj_force, G, W, T, A);

@@ -3,6 +3,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "engine.h"
 
 namespace mc {
@@ -810,6 +812,33 @@ static __device__ __forceinline__ long long spread_cell(const long long* s, int 
   for (int cy = cy0; cy < kSpreadSide; cy += ny)
     for (int cx = cx0; cx < kSpreadSide; cx += nx) acc += s[cy * kSpreadSide + cx];
   return acc;
+}
+
+template <int TILE>
+static inline bool tile_family_present(const Grid& G) {
+  return G.tile_blocks[TileCfg<TILE>::kFamily] > 0;
+}
+
+// Host side: launch a tile kernel with a one-layer and a two-layer variant
+// (template argument MK last) for every tile family present, in the
+// variants the grid needs: launch(Int<TILE>, Bool<MK>) launches one.  Each
+// variant skips the other's worlds; the two-layer one runs only where a
+// binned world has markers, the one-layer one unless every world has them.
+template <class L>
+static inline void for_tile_variants(const Grid& G, L launch) {
+  const bool mk = G.any_markers && G.any_binned, plain = !G.mk_only;
+  if (tile_family_present<16>(G)) {
+    if (plain) launch(std::integral_constant<int, 16>(), std::false_type());
+    if (mk) launch(std::integral_constant<int, 16>(), std::true_type());
+  }
+  if (tile_family_present<32>(G)) {
+    if (plain) launch(std::integral_constant<int, 32>(), std::false_type());
+    if (mk) launch(std::integral_constant<int, 32>(), std::true_type());
+  }
+  if (tile_family_present<64>(G)) {
+    if (plain) launch(std::integral_constant<int, 64>(), std::false_type());
+    if (mk) launch(std::integral_constant<int, 64>(), std::true_type());
+  }
 }
 
 }  // namespace mc

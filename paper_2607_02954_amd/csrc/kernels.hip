@@ -36,8 +36,6 @@
 // physics needs (edge vectors, kernel offsets) are formed from small numbers.
 #include <hip/hip_ext.h>
 
-#include <type_traits>
-
 #include "device_util.h"
 
 namespace mc {
@@ -1906,34 +1904,7 @@ void launch_repulse(const WorldDev* W, const Tables& T, const Grid& G, hipStream
   // binned worlds form the repulsion inside k_spread
 }
 
-// Tile kernels with a one-layer and a two-layer variant (template argument
-// MK last): each variant skips the other's worlds; the two-layer one runs
-// only where a binned world has markers, the one-layer one unless every
-// world has them.
-template <int TILE>
-static bool tile_family_present(const Grid& G) {
-  return G.tile_blocks[TileCfg<TILE>::kFamily] > 0;
-}
-
-// Launch a tile kernel template K<TILE, ..., MK> for every family present
-// and the variants the grid needs (launch(Int<TILE>, Bool<MK>) launches one).
-template <class L>
-static void for_tile_variants(const Grid& G, L launch) {
-  const bool mk = G.any_markers && G.any_binned, plain = !G.mk_only;
-  if (tile_family_present<16>(G)) {
-    if (plain) launch(std::integral_constant<int, 16>(), std::false_type());
-    if (mk) launch(std::integral_constant<int, 16>(), std::true_type());
-  }
-  if (tile_family_present<32>(G)) {
-    if (plain) launch(std::integral_constant<int, 32>(), std::false_type());
-    if (mk) launch(std::integral_constant<int, 32>(), std::true_type());
-  }
-  if (tile_family_present<64>(G)) {
-    if (plain) launch(std::integral_constant<int, 64>(), std::false_type());
-    if (mk) launch(std::integral_constant<int, 64>(), std::true_type());
-  }
-}
-
+// (tile kernels with a one-layer and a two-layer variant: for_tile_variants)
 void launch_spread(const WorldDev* W, const Tables& T, const Grid& G, hipStream_t s) {
   for_tile_variants(G, [&](auto tile, auto mk) {
     constexpr int TL = decltype(tile)::value;

@@ -276,21 +276,24 @@ def test_adjoint_through_mdf_matches_oracle(mdf, tile):
     assert np.linalg.norm(g1 - g) > 10 * err * np.linalg.norm(g)
 
 
-@pytest.mark.parametrize("offset,tile", [(0.5, 32), (1.0, 16), (0.7, 64)])
-def test_adjoint_through_two_layers_matches_oracle(offset, tile):
+@pytest.mark.parametrize("offset,tile,mdf", [(0.5, 32, 1), (1.0, 16, 1), (0.7, 64, 1), (0.5, 32, 3), (1.0, 16, 4),
+                                             (0.7, 64, 2)])
+def test_adjoint_through_two_layers_matches_oracle(offset, tile, mdf):
     """The gradient through two-layer markers (binned transfer): the force
-    spread and the velocity gather at both markers, and the markers' normals
-    as functions of the neighbouring nodes, against the oracle's reverse mode
-    of the same forward, on chains with one- and two-node filaments."""
+    spread and the velocity gather at both markers, with or without MDF (its
+    iterates' spreads and gathers at the markers too), and the markers'
+    normals as functions of the neighbouring nodes, against the oracle's
+    reverse mode of the same forward, on chains with one- and two-node
+    filaments."""
     sim = _sim()
     w = wl.random_world(17, 72, 56, [14, 9, 22, 3, 1, 2], amp=0.5)
     x0 = w.positions64()
     target = x0 + np.random.default_rng(2).normal(0, 0.5, size=x0.shape)
-    g, loss, W, p = _gpu_grad(sim, w, target, 12, 5, marker_offset=offset, tile=tile)
+    g, loss, W, p = _gpu_grad(sim, w, target, 12, 5, marker_offset=offset, tile=tile, mdf_iters=mdf)
     ref, _ = _oracle_grad(w, p, target, 12, 5)
     err, cos = _compare(g, ref, _joints(w))
-    print(f"adjoint through two layers, offset {offset} (tile {tile}): rel err {err:.2e} cos {cos:.6f}")
+    print(f"adjoint through two layers, offset {offset}, MDF {mdf} (tile {tile}): rel err {err:.2e} cos {cos:.6f}")
     assert err <= 1e-3 and cos >= 0.9999
     # one layer gives a different gradient: the test sees the marker terms
-    g1, _, _, _ = _gpu_grad(sim, w, target, 12, 5, tile=tile)
+    g1, _, _, _ = _gpu_grad(sim, w, target, 12, 5, tile=tile, mdf_iters=mdf)
     assert np.linalg.norm(g1 - g) > 10 * err * np.linalg.norm(g)

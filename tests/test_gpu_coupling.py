@@ -8,7 +8,7 @@ from the GPU's state, for one and two layers, one to eight MDF iterations,
 every tile side, chains and loops, and grids smaller than a tile's windows
 (which wrap onto themselves); the combinations that are not built are
 refused (MDF or two layers on the sorted transfer, the adjoint off the
-binned transfer or through MDF and two layers together); the allocation-free step and batches
+binned transfer); the allocation-free step and batches
 mixing direct, binned, one- and two-layer MDF worlds give the single
 world's results (to the parity bar: the direct transfer sums with float
 atomics).
@@ -57,10 +57,8 @@ def test_unbuilt_combinations_are_refused():
         with pytest.raises(sim.SimError) as ei:
             sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw))
         assert ei.value.status == sim.SIM_E_INVALID
-    # the adjoint takes MDF on the binned transfer only, and MDF or two
-    # layers but not both
-    for mode, kw in (("direct", {"mdf_iters": 3}), ("direct", {"marker_offset": 0.5}),
-                     ("binned", {"mdf_iters": 3, "marker_offset": 0.5})):
+    # the adjoint takes MDF and two layers on the binned transfer only
+    for mode, kw in (("direct", {"mdf_iters": 3}), ("direct", {"marker_offset": 0.5})):
         W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny, transfer=mode, **kw))
         ra = torch.tensor(w.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
         with pytest.raises(sim.SimError) as ei:
