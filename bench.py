@@ -201,13 +201,9 @@ def bench_served(seed, pool_gib, tune_steps):
     }
 
 
-def bench_adjoint(seed, reps=5):
-    """Differentiation workload: 64 chains x 48 nodes on 256^2, 200 steps,
-    checkpoints every 20; loss = mean squared distance to the seeded target
-    fold; gradient in the rest angles through the autograd Function."""
-    w = wl.folding_population(seed)
-    p = sim.Params(nx=w.nx, ny=w.ny)
-    n, k = 200, 20
+def _differentiation_times(w, p, n, k, reps):
+    """Median plain rollout, checkpointed forward and backward times (ms) of
+    one world over n steps (checkpoints every k), and the last loss."""
     W = sim.World(w, p)
     tgt = torch.tensor(w.target, dtype=torch.float64, device="cuda")
     cell0, frac0 = W.state.cell.clone(), W.state.frac.clone()
@@ -245,7 +241,20 @@ def bench_adjoint(seed, reps=5):
             fwd.append(ev[2].elapsed_time(ev[3]))
             bwd.append(b0.elapsed_time(b1))
     W.close()
-    pm, fm, bm = float(np.median(plain)), float(np.median(fwd)), float(np.median(bwd))
+    return float(np.median(plain)), float(np.median(fwd)), float(np.median(bwd)), float(loss.detach())
+
+
+def bench_adjoint(seed, reps=5):
+    """Differentiation workload: 64 chains x 48 nodes on 256^2, 200 steps,
+    checkpoints every 20; loss = mean squared distance to the seeded target
+    fold; gradient in the rest angles through the autograd Function.  Also
+    the same with the coupling's leakage fixes (3 MDF iterations, two marker
+    layers 0.5 cells apart, both), and 16 such worlds as one set."""
+    from dataclasses import replace as dc_replace
+    w = wl.folding_population(seed)
+    p = sim.Params(nx=w.nx, ny=w.ny)
+    n, k = 200, 20
+    pm, fm, bm, loss = _differentiation_times(w, p, n, k, reps)
     out = {
         "workload": "folding: 64 chains x 48 nodes on 256x256, 200 steps, checkpoints every 20, "
                     "gradient of the target-fold loss in the rest angles",
@@ -254,8 +263,15 @@ def bench_adjoint(seed, reps=5):
         "backward_ms": bm,
         "bwd_over_fwd": bm / fm,
         "bwd_over_plain_fwd": bm / pm,
-        "loss": float(loss.detach()),
+        "loss": loss,
     }
+    variants = {}
+    for name, kw in (("mdf3", dict(mdf_iters=3)), ("two_layer", dict(marker_offset=0.5)),
+                     ("mdf3_two_layer", dict(mdf_iters=3, marker_offset=0.5))):
+        vp, vf, vb, vl = _differentiation_times(w, dc_replace(p, **kw), n, k, max(2, reps // 2))
+        variants[name] = {"checkpointed_forward_ms": vf, "backward_ms": vb, "bwd_over_fwd": vb / vf, "loss": vl}
+        log(f"differentiation {name}: forward {vf:.2f} ms, backward {vb:.2f} ms")
+    out["coupling_variants"] = variants
     out["set_of_worlds"] = bench_adjoint_set(seed, n, k, fm + bm, reps=max(2, reps // 2))
     return out
 
