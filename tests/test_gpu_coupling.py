@@ -49,6 +49,17 @@ def test_mdf_and_two_layers_match_oracle(mode, mdf, offset, tile):
         print(f"MDF {mdf}, offset {offset} [{mode}, tile {tile}], {w.nx}x{w.ny} N={w.n_particles}: {E}")
 
 
+@pytest.mark.parametrize("mode,mdf", [("binned", 1), ("binned", 3), ("direct", 1)])
+def test_two_layers_on_branched_creatures(mode, mdf):
+    # the markers' normals come from each filament's own neighbours (an
+    # attachment edge is not a tangent); children and parents, chains and
+    # loops, on both transfers and with MDF
+    sim = _sim()
+    w = wl.branched_world(5, 72, 64, 3)
+    E = _rollout_compare(sim, w, 10, mode, mdf_iters=mdf, marker_offset=0.5)
+    print(f"branched creatures, two layers, MDF {mdf} [{mode}], N={w.n_particles}: {E}")
+
+
 def test_unbuilt_combinations_are_refused():
     sim = _sim()
     w = ragged_world(1)
