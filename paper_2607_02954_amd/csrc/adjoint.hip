@@ -482,9 +482,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const Wo
 }
 
 // ---------------------------------------------------------------------------
-// S2 + S1 + S0 reversed, one block per node pack.
+// S2 + S1 + S0 reversed, one block per node pack.  GEN: the general variant
+// of the forward's PBD (closed loops: the joint before node 0 and the
+// closing edge, a third colour on loops of odd length; per-edge
+// stiffnesses), reversed pass by pass in the same way.
 // ---------------------------------------------------------------------------
-template <int PACK>
+template <int PACK, bool GEN>
 __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
   __shared__ float s_th[PACK];
   __shared__ float s_dx[PACK];
@@ -515,9 +518,20 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     const int o = s_off[lo];
     const int n = s_off[lo + 1] - o;
     const int k = li - o;
-    const bool has_edge = active && k < n - 1;
-    const bool is_joint = active && k >= 1 && k <= n - 2;
-    const int j = k - 1;
+    const int fil = pk.fil_begin + lo;
+    // as in the forward: a closed loop (three nodes or more) closes with the
+    // edge from its last node to its first, and every node is a joint
+    const bool ring = GEN && active && w.fil_flags && (glb(w.fil_flags)[fil] & 1) && n >= 3;
+    const bool has_edge = active && (k < n - 1 || ring);
+    const bool is_joint = active && (ring || (k >= 1 && k <= n - 2));
+    const int j = ring ? k : k - 1;
+    const int m = ring ? n : n - 2;
+    const int li_prev = (ring && k == 0) ? o + n - 1 : li - 1;    // edge before the joint
+    const int li_next = (ring && k == n - 1) ? o : li + 1;        // far node of the edge
+    const int jcol = (ring && (n & 1) && j == n - 1) ? 2 : (j & 1);
+    const int ecol = (ring && (n & 1) && k == n - 1) ? 2 : (k & 1);
+    int ncol = 2;                                // block-uniform
+    if constexpr (GEN) ncol = __syncthreads_or(ring && (n & 1)) ? 3 : 2;
 
     int cx = 0, cy = 0;
     float fx = 0.f, fy = 0.f;
@@ -528,8 +542,9 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     float v0x = 0.f, v0y = 0.f, L = 0.f, th = 0.f;
     float u0x = 1.f, u0y = 0.f;
     if (has_edge) {
-      v0x = (float)(cell[gi + 1] - cx) + (frac[gi + 1] - fx);
-      v0y = (float)(cell[N + gi + 1] - cy) + (frac[N + gi + 1] - fy);
+      const int gn = pk.node_begin + li_next;
+      v0x = (float)(cell[gn] - cx) + (frac[gn] - fx);
+      v0y = (float)(cell[N + gn] - cy) + (frac[N + gn] - fy);
       L = glb(w.rest_length)[gi];
       th = atan2f(v0y, v0x);
       const float l0 = hw_sqrt(v0x * v0x + v0y * v0y);
@@ -540,11 +555,9 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
       }
     }
     float th_hat = 0.f;
-    if (is_joint) {
-      const int f = pk.fil_begin + lo;
-      th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[f], glb(w.act_period)[f],
-                              glb(w.act_phase)[f], w.ctl_src->t, j, n - 2);
-    }
+    if (is_joint)
+      th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[fil], glb(w.act_period)[fil],
+                              glb(w.act_phase)[fil], w.ctl_src->t, j, m);
     // dL/dx_t so far (written by k_adj_force) plus the deposit derivative
     float xbx = 0.f, xby = 0.f;
     if (active) {
@@ -569,13 +582,13 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 
     // forward PBD again, keeping the state each position pass starts from
     const int K = w.pbd_iters;
-    // per-edge stiffnesses of the joint and the edge at this node (chains only:
-    // worlds with loops are not differentiated)
+    // per-edge stiffnesses of the joint and the edge at this node
     const int gs = active ? gi : pk.node_begin;
     const float hb = 0.5f * (w.kb_arr ? glb(w.kb_arr)[gs] : w.k_bend);
     const float hs = 0.5f * (w.ks_arr ? glb(w.ks_arr)[gs] : w.k_stretch);
     const float ksh = w.ksh_arr ? glb(w.ksh_arr)[gs] : w.k_shear;
-    float d_pe_x[kMaxAdjIters], d_pe_y[kMaxAdjIters], d_po_x[kMaxAdjIters], d_po_y[kMaxAdjIters];
+    constexpr int kCol = GEN ? 3 : 2;
+    float d_p_x[kCol][kMaxAdjIters], d_p_y[kCol][kMaxAdjIters];   // d before each position colour
     float th_p[kMaxAdjIters];
     s_th[li] = th;
     s_dx[li] = 0.f;
@@ -584,30 +597,29 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 #pragma unroll
     for (int iter = 0; iter < kMaxAdjIters; ++iter) {
       if (iter < K) {
-        for (int par = 0; par < 2; ++par) {
-          if (is_joint && (j & 1) == par) {
-            const float t1 = s_th[li - 1];
-            const float t2 = s_th[li];
-            const float c = wrap_angle(t2 - t1) - th_hat;
-            s_th[li - 1] = t1 + hb * c;
-            s_th[li] = t2 - hb * c;
+#pragma unroll
+        for (int par = 0; par < kCol; ++par) {
+          if (par < ncol) {
+            if (is_joint && jcol == par) {
+              const float t1 = s_th[li_prev];
+              const float t2 = s_th[li];
+              const float c = wrap_angle(t2 - t1) - th_hat;
+              s_th[li_prev] = t1 + hb * c;
+              s_th[li] = t2 - hb * c;
+            }
+            __syncthreads();
           }
-          __syncthreads();
         }
         th_p[iter] = s_th[li];
-        for (int par = 0; par < 2; ++par) {
-          const float mdx = s_dx[li], mdy = s_dy[li];
-          if (par == 0) {
-            d_pe_x[iter] = mdx;
-            d_pe_y[iter] = mdy;
-          } else {
-            d_po_x[iter] = mdx;
-            d_po_y[iter] = mdy;
-          }
+#pragma unroll
+        for (int par = 0; par < kCol; ++par) {
+          if (par >= ncol) continue;
+          d_p_x[par][iter] = s_dx[li];
+          d_p_y[par][iter] = s_dy[li];
           __syncthreads();
-          if (has_edge && (k & 1) == par) {
+          if (has_edge && ecol == par) {
             const float d0x = s_dx[li], d0y = s_dy[li];
-            const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
+            const float d1x = s_dx[li_next], d1y = s_dy[li_next];
             const float vx = v0x + (d1x - d0x);
             const float vy = v0y + (d1y - d0y);
             const float ell = hw_sqrt(vx * vx + vy * vy);
@@ -619,8 +631,8 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
             const float dy = hs * (csy + ksh * (vy - L * sn - csy));
             s_dx[li] = d0x + dx;
             s_dy[li] = d0y + dy;
-            s_dx[li + 1] = d1x - dx;
-            s_dy[li + 1] = d1y - dy;
+            s_dx[li_next] = d1x - dx;
+            s_dy[li_next] = d1y - dy;
           }
           __syncthreads();
         }
@@ -637,19 +649,21 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 #pragma unroll
     for (int iter = kMaxAdjIters - 1; iter >= 0; --iter) {
       if (iter < K) {
-        for (int par = 1; par >= 0; --par) {
-          s_dx[li] = par == 0 ? d_pe_x[iter] : d_po_x[iter];
-          s_dy[li] = par == 0 ? d_pe_y[iter] : d_po_y[iter];
+#pragma unroll
+        for (int par = kCol - 1; par >= 0; --par) {
+          if (par >= ncol) continue;
+          s_dx[li] = d_p_x[par][iter];
+          s_dy[li] = d_p_y[par][iter];
           __syncthreads();
-          if (has_edge && (k & 1) == par) {
+          if (has_edge && ecol == par) {
             const float d0x = s_dx[li], d0y = s_dy[li];
-            const float d1x = s_dx[li + 1], d1y = s_dy[li + 1];
+            const float d1x = s_dx[li_next], d1y = s_dy[li_next];
             const float vx = v0x + (d1x - d0x);
             const float vy = v0y + (d1y - d0y);
             const float ell = sqrtf(vx * vx + vy * vy);
             const float hx = vx / ell, hy = vy / ell;
-            const float Dbx = s_gx[li] - s_gx[li + 1];
-            const float Dby = s_gy[li] - s_gy[li + 1];
+            const float Dbx = s_gx[li] - s_gx[li_next];
+            const float Dby = s_gy[li] - s_gy[li_next];
             // M = hs [(1 - ksh) (I - (L/ell)(I - h h^T)) + ksh I]
             const float a = 1.0f - ksh;
             const float lr = L / ell;
@@ -658,8 +672,8 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
             const float mby = hs * (Dby - a * lr * (Dby - hy * hd));
             s_gx[li] -= mbx;
             s_gy[li] -= mby;
-            s_gx[li + 1] += mbx;
-            s_gy[li + 1] += mby;
+            s_gx[li_next] += mbx;
+            s_gy[li_next] += mby;
             v0bx += mbx;
             v0by += mby;
             float sn, cs;
@@ -668,10 +682,12 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
           }
           __syncthreads();
         }
-        for (int par = 1; par >= 0; --par) {
-          if (is_joint && (j & 1) == par) {
-            const float cb = hb * (s_gth[li - 1] - s_gth[li]);
-            s_gth[li - 1] -= cb;
+#pragma unroll
+        for (int par = kCol - 1; par >= 0; --par) {
+          if (par >= ncol) continue;
+          if (is_joint && jcol == par) {
+            const float cb = hb * (s_gth[li_prev] - s_gth[li]);
+            s_gth[li_prev] -= cb;
             s_gth[li] += cb;
             thhb -= cb;
           }
@@ -687,16 +703,16 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
       v0by += tb * (v0x / r2);
     }
     __syncthreads();
-    // v0_e = x_{e+1} - x_e
+    // v0_e = x_next(e) - x_e
     s_dx[li] = has_edge ? v0bx : 0.f;
     s_dy[li] = has_edge ? v0by : 0.f;
     __syncthreads();
     if (active) {
       xbx -= s_dx[li];
       xby -= s_dy[li];
-      if (k >= 1) {
-        xbx += s_dx[li - 1];
-        xby += s_dy[li - 1];
+      if (k >= 1 || ring) {                     // the edge ending here (a loop's closing edge at node 0)
+        xbx += s_dx[li_prev];
+        xby += s_dy[li_prev];
       }
       A.xbar[gi] = xbx;
       A.xbar[N + gi] = xby;
@@ -1148,7 +1164,17 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
   if (G.any_markers) MC_ADJ_PACK(k_adj_markers, G, W, T, A);
   MC_ADJ_TILES(k_adj_spread, G, W, T, A, 1, 0);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
-  MC_ADJ_PACK(k_adj_pbd, G, W, T, A);
+  if (G.general) {
+    if (G.pack == 256)
+      k_adj_pbd<256, true><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+    else
+      k_adj_pbd<1024, true><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
+  } else {
+    if (G.pack == 256)
+      k_adj_pbd<256, false><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+    else
+      k_adj_pbd<1024, false><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
+  }
 }
 
 }  // namespace mc

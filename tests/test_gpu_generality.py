@@ -112,7 +112,18 @@ def test_batch_and_noalloc_with_loops():
     assert all(torch.equal(getattr(st, k), getattr(ref.state, k)) for k in ("cell", "frac", "f", "u"))
 
 
-def test_adjoint_with_per_edge_stiffness_and_loop_refusal():
+def _all_joints(w):
+    """Joint nodes: interior nodes of chains, every node of a closed loop."""
+    off, closed_f = w.fil_offset, w.closed
+    idx = []
+    for f in range(len(off) - 1):
+        a, e = int(off[f]), int(off[f + 1])
+        closed = closed_f is not None and bool(closed_f[f]) and e - a >= 3
+        idx.append(np.arange(a, e) if closed else np.arange(a + 1, e - 1))
+    return np.concatenate(idx)
+
+
+def test_adjoint_with_per_edge_stiffness():
     sim = _sim()
     w = wl.generality_world(5, 64, 56, [12, 7, 20, 2, 30], [])
     x0 = w.positions64()
@@ -122,15 +133,30 @@ def test_adjoint_with_per_edge_stiffness_and_loop_refusal():
     err, cos = _compare(g, ref, _joints(w))
     print(f"adjoint with per-edge stiffness: rel err {err:.2e} cos {cos:.6f}")
     assert err <= 1e-3 and cos >= 0.9999
-    wl_ = _world(6)
-    Wl = sim.World(wl_, sim.Params(nx=wl_.nx, ny=wl_.ny))
-    ck = torch.empty(Wl.checkpoint_bytes(4, 2), dtype=torch.uint8, device="cuda")
-    Wl.rollout(0, 4, 2, ck)
-    g_pos = torch.zeros(2, wl_.n_particles, dtype=torch.float32, device="cuda")
-    g_rest = torch.zeros(wl_.n_particles, dtype=torch.float32, device="cuda")
-    with pytest.raises(sim.SimError) as ei:
-        Wl.backward(0, 4, 2, ck, g_pos, g_rest)
-    assert ei.value.status == sim.SIM_E_INVALID
+
+
+@pytest.mark.parametrize("tile", [32, 16])
+def test_adjoint_through_loops_matches_oracle(tile):
+    """Reverse mode through closed loops (Methods, Filaments: loops): the
+    joint before node 0 and the closing edge, the third colour of loops of
+    odd length (3 and 9 nodes) beside an even one, per-edge stiffnesses and
+    chains, against the oracle's reverse mode; every joint of a loop has a
+    rest angle and so a gradient."""
+    sim = _sim()
+    w = wl.generality_world(7, 72, 64, [14, 9, 2], [9, 12, 3])
+    x0 = w.positions64()
+    target = x0 + np.random.default_rng(4).normal(0, 0.5, size=x0.shape)
+    g, _, W, p = _gpu_grad(sim, w, target, 12, 5, tile=tile)
+    ref, _ = _oracle_grad(w, p, target, 12, 5)
+    joints = _all_joints(w)
+    err, cos = _compare(g, ref, joints)
+    off = w.fil_offset
+    loops = np.concatenate([np.arange(off[f], off[f + 1]) for f in range(len(off) - 1) if w.closed[f]])
+    e_loop, c_loop = _compare(g, ref, loops)
+    print(f"adjoint through loops (tile {tile}): rel err {err:.2e} cos {cos:.6f}; loop joints alone "
+          f"{e_loop:.2e} / {c_loop:.6f}")
+    assert err <= 1e-3 and cos >= 0.9999
+    assert e_loop <= 1e-3 and c_loop >= 0.9999 and float(np.abs(ref[loops]).max()) > 0
 
 
 def test_rest_effort_matches_oracle():
