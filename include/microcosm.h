@@ -172,7 +172,7 @@ typedef struct sim_arrays {
    * an entering edge (a node of a loop, or not the first node of a chain);
    * f is not a closed loop; a node carries at most one filament; a
    * creature holds at most 1024 nodes (sim_batch_admit: the batch's pack
-   * capacity).  sim_backward and sim_step_noalloc refuse branched worlds. */
+   * capacity).  sim_step_noalloc refuses branched worlds. */
   const int32_t *fil_parent;  /* [F] node filament f hangs from, or -1             */
   const float *fil_attach;    /* [3][F] per filament: attachment rest length, rest
                                  angle at p, rest angle at c0 (ignored for
@@ -238,9 +238,9 @@ sim_status sim_checkpoint_size(const sim_world *w, int32_t n_steps, int32_t ckpt
  * checkpoints written by sim_rollout(t0, n_steps, ckpt_every) and g_pos =
  * dL/dx at the final step ([2][N] device floats), ACCUMULATES dL/d(rest_angle)
  * into g_rest_angle ([N], caller zeroes) and, if g_pos0 is not NULL, WRITES
- * dL/dx at t0 into g_pos0 ([2][N]).  Chains and closed loops are
- * differentiated, branched worlds are not (SIM_E_INVALID).  Each segment is
- * recomputed forward from its checkpoint into adj_ws, then hand-written adjoint kernels run step by
+ * dL/dx at t0 into g_pos0 ([2][N]): chains, closed loops and branched
+ * creatures (whose attachment rest lengths and angles are constants).  Each
+ * segment is recomputed forward from its checkpoint into adj_ws, then hand-written adjoint kernels run step by
  * step in reverse.  adj_ws must hold sim_backward_workspace_size bytes.
  * The world's own state arrays are not modified.  Only worlds that use the
  * tile-binned transfer (flags without SIM_SPLAT_SORTED / SIM_SPLAT_DIRECT)

@@ -485,16 +485,22 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const Wo
 // S2 + S1 + S0 reversed, one block per node pack.  GEN: the general variant
 // of the forward's PBD (closed loops: the joint before node 0 and the
 // closing edge, a third colour on loops of odd length; per-edge
-// stiffnesses), reversed pass by pass in the same way.
+// stiffnesses), reversed pass by pass in the same way.  BR: branches too
+// (each attached filament's first node c0 owns its attachment: the joints
+// at the parent p and at c0, then the edge p -> c0, after the regular
+// passes of each kind, with the world's stiffnesses and fixed rest angles).
 // ---------------------------------------------------------------------------
-template <int PACK, bool GEN>
+template <int PACK, bool GEN, bool BR>
 __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
+  static_assert(GEN || !BR, "branches take the general variant");
   __shared__ float s_th[PACK];
   __shared__ float s_dx[PACK];
   __shared__ float s_dy[PACK];
   __shared__ float s_gx[PACK];     // dL/dd per node
   __shared__ float s_gy[PACK];
   __shared__ float s_gth[PACK];    // dL/dtheta per edge
+  __shared__ float s_ta[BR ? PACK : 1];    // attachment edge angle (owned by c0)
+  __shared__ float s_gta[BR ? PACK : 1];   // and its adjoint
   __shared__ int s_off[PACK + 1];
   const int npk = *T.n_packs;
   const int li = threadIdx.x;
@@ -558,6 +564,40 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     if (is_joint)
       th_hat = actuated_angle(glb(w.rest_angle)[gi], glb(w.act_amp)[fil], glb(w.act_period)[fil],
                               glb(w.act_phase)[fil], w.ctl_src->t, j, m);
+    // the attachment this node owns (as in the forward)
+    bool att = false, att_cj = false, any_att = false;
+    int p_l = 0, in_l = 0;
+    float a_vx = 0.f, a_vy = 0.f, a_th = 0.f, a_ux = 1.f, a_uy = 0.f, a_L = 0.f, a_al = 0.f, a_be = 0.f;
+    if (BR && w.fil_parent) {                  // block-uniform: the pack's world
+      const int par = (active && k == 0) ? glb(w.fil_parent)[fil] : -1;
+      att = par >= 0;
+      if (att) {
+        p_l = par - pk.node_begin;
+        int lp = 0, hp = nf - 1;
+        while (lp < hp) {
+          const int mid = (lp + hp + 1) >> 1;
+          if (s_off[mid] <= p_l) lp = mid; else hp = mid - 1;
+        }
+        in_l = p_l == s_off[lp] ? s_off[lp + 1] - 1 : p_l - 1;   // p's entering edge
+        const int F = w.n_fil;
+        a_L = glb(w.fil_attach)[fil];
+        a_al = glb(w.fil_attach)[F + fil];
+        a_be = glb(w.fil_attach)[2 * F + fil];
+        a_vx = (float)(cx - cell[par]) + (fx - frac[par]);
+        a_vy = (float)(cy - cell[N + par]) + (fy - frac[N + par]);
+        a_th = atan2f(a_vy, a_vx);
+        const float l0 = hw_sqrt(a_vx * a_vx + a_vy * a_vy);
+        if (l0 > 0.f) {
+          const float il = hw_rcp(l0);
+          a_ux = a_vx * il;
+          a_uy = a_vy * il;
+        }
+        att_cj = n >= 2;
+      }
+      s_ta[li] = a_th;
+      any_att = __syncthreads_or(att);
+    }
+    const float hb_w = 0.5f * w.k_bend, hs_w = 0.5f * w.k_stretch, ksh_w = w.k_shear;
     // dL/dx_t so far (written by k_adj_force) plus the deposit derivative
     float xbx = 0.f, xby = 0.f;
     if (active) {
@@ -590,6 +630,8 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     constexpr int kCol = GEN ? 3 : 2;
     float d_p_x[kCol][kMaxAdjIters], d_p_y[kCol][kMaxAdjIters];   // d before each position colour
     float th_p[kMaxAdjIters];
+    constexpr int kAtt = BR ? kMaxAdjIters : 1;
+    float ta_p[kAtt], da_x[kAtt], da_y[kAtt];   // attachment angle after the joints; d before its edge pass
     s_th[li] = th;
     s_dx[li] = 0.f;
     s_dy[li] = 0.f;
@@ -610,7 +652,24 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
             __syncthreads();
           }
         }
+        if (BR && any_att) {                   // attachment joints: at p, then at c0
+          if (att) {
+            const float t1 = s_th[in_l], t2 = s_ta[li];
+            const float c = wrap_angle(t2 - t1) - a_al;
+            s_th[in_l] = t1 + hb_w * c;
+            s_ta[li] = t2 - hb_w * c;
+          }
+          __syncthreads();
+          if (att_cj) {
+            const float t1 = s_ta[li], t2 = s_th[li];
+            const float c = wrap_angle(t2 - t1) - a_be;
+            s_ta[li] = t1 + hb_w * c;
+            s_th[li] = t2 - hb_w * c;
+          }
+          __syncthreads();
+        }
         th_p[iter] = s_th[li];
+        if constexpr (BR) ta_p[iter] = s_ta[li];
 #pragma unroll
         for (int par = 0; par < kCol; ++par) {
           if (par >= ncol) continue;
@@ -636,6 +695,31 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
           }
           __syncthreads();
         }
+        if (BR && any_att) {                   // attachment edges p -> c0
+          if constexpr (BR) {
+            da_x[iter] = s_dx[li];
+            da_y[iter] = s_dy[li];
+          }
+          __syncthreads();
+          if (att) {
+            const float d0x = s_dx[p_l], d0y = s_dy[p_l];
+            const float d1x = s_dx[li], d1y = s_dy[li];
+            const float vx = a_vx + (d1x - d0x);
+            const float vy = a_vy + (d1y - d0y);
+            const float ell = hw_sqrt(vx * vx + vy * vy);
+            const float sc = (ell - a_L) * hw_rcp(ell);
+            const float csx = sc * vx, csy = sc * vy;
+            float sn, cs;
+            edge_direction(ta_p[BR ? iter : 0], a_th, a_ux, a_uy, &cs, &sn);
+            const float dx = hs_w * (csx + ksh_w * (vx - a_L * cs - csx));
+            const float dy = hs_w * (csy + ksh_w * (vy - a_L * sn - csy));
+            s_dx[p_l] = d0x + dx;
+            s_dy[p_l] = d0y + dy;
+            s_dx[li] = d1x - dx;
+            s_dy[li] = d1y - dy;
+          }
+          __syncthreads();
+        }
       }
     }
 
@@ -644,11 +728,45 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     s_gx[li] = active ? kel * A.Fbar[gi] : 0.f;
     s_gy[li] = active ? kel * A.Fbar[N + gi] : 0.f;
     s_gth[li] = 0.f;
+    if constexpr (BR) s_gta[li] = 0.f;
     float v0bx = 0.f, v0by = 0.f, thhb = 0.f;
+    float a_v0bx = 0.f, a_v0by = 0.f;          // dL/d(attachment vector), c0 lanes
     __syncthreads();
 #pragma unroll
     for (int iter = kMaxAdjIters - 1; iter >= 0; --iter) {
       if (iter < K) {
+        if (BR && any_att) {                   // attachment edges reversed
+          if constexpr (BR) {
+            s_dx[li] = da_x[iter];
+            s_dy[li] = da_y[iter];
+          }
+          __syncthreads();
+          if (att) {
+            const float d0x = s_dx[p_l], d0y = s_dy[p_l];
+            const float d1x = s_dx[li], d1y = s_dy[li];
+            const float vx = a_vx + (d1x - d0x);
+            const float vy = a_vy + (d1y - d0y);
+            const float ell = sqrtf(vx * vx + vy * vy);
+            const float hx = vx / ell, hy = vy / ell;
+            const float Dbx = s_gx[p_l] - s_gx[li];
+            const float Dby = s_gy[p_l] - s_gy[li];
+            const float a = 1.0f - ksh_w;
+            const float lr = a_L / ell;
+            const float hd = hx * Dbx + hy * Dby;
+            const float mbx = hs_w * (Dbx - a * lr * (Dbx - hx * hd));
+            const float mby = hs_w * (Dby - a * lr * (Dby - hy * hd));
+            s_gx[p_l] -= mbx;
+            s_gy[p_l] -= mby;
+            s_gx[li] += mbx;
+            s_gy[li] += mby;
+            a_v0bx += mbx;
+            a_v0by += mby;
+            float sn, cs;
+            edge_direction(ta_p[BR ? iter : 0], a_th, a_ux, a_uy, &cs, &sn);
+            s_gta[li] += -hs_w * ksh_w * a_L * (-sn * Dbx + cs * Dby);
+          }
+          __syncthreads();
+        }
 #pragma unroll
         for (int par = kCol - 1; par >= 0; --par) {
           if (par >= ncol) continue;
@@ -682,6 +800,20 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
           }
           __syncthreads();
         }
+        if (BR && any_att) {                   // attachment joints reversed: at c0, then at p
+          if (att_cj) {
+            const float cb = hb_w * (s_gta[li] - s_gth[li]);
+            s_gta[li] -= cb;
+            s_gth[li] += cb;
+          }
+          __syncthreads();
+          if (att) {
+            const float cb = hb_w * (s_gth[in_l] - s_gta[li]);
+            s_gth[in_l] -= cb;
+            s_gta[li] += cb;
+          }
+          __syncthreads();
+        }
 #pragma unroll
         for (int par = kCol - 1; par >= 0; --par) {
           if (par >= ncol) continue;
@@ -703,16 +835,36 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
       v0by += tb * (v0x / r2);
     }
     __syncthreads();
+    // the attachment angle atan2(a_v), a_v = x_c0 - x_p
+    if (BR && att) {
+      const float r2 = a_vx * a_vx + a_vy * a_vy;
+      const float tb = s_gta[li];
+      a_v0bx += tb * (-a_vy / r2);
+      a_v0by += tb * (a_vx / r2);
+    }
     // v0_e = x_next(e) - x_e
     s_dx[li] = has_edge ? v0bx : 0.f;
     s_dy[li] = has_edge ? v0by : 0.f;
+    if constexpr (BR) {                        // (dL/dd is no longer needed: it holds -dL/da_v at p)
+      s_gx[li] = 0.f;
+      s_gy[li] = 0.f;
+    }
     __syncthreads();
+    if (BR && att) {                           // one child per parent node: a single writer
+      s_gx[p_l] = -a_v0bx;
+      s_gy[p_l] = -a_v0by;
+    }
+    if constexpr (BR) __syncthreads();
     if (active) {
       xbx -= s_dx[li];
       xby -= s_dy[li];
       if (k >= 1 || ring) {                     // the edge ending here (a loop's closing edge at node 0)
         xbx += s_dx[li_prev];
         xby += s_dy[li_prev];
+      }
+      if constexpr (BR) {
+        xbx += s_gx[li] + a_v0bx;
+        xby += s_gy[li] + a_v0by;
       }
       A.xbar[gi] = xbx;
       A.xbar[N + gi] = xby;
@@ -1164,16 +1316,21 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
   if (G.any_markers) MC_ADJ_PACK(k_adj_markers, G, W, T, A);
   MC_ADJ_TILES(k_adj_spread, G, W, T, A, 1, 0);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
-  if (G.general) {
+  if (G.branches) {
     if (G.pack == 256)
-      k_adj_pbd<256, true><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+      k_adj_pbd<256, true, true><<<G.node_blocks, 256, 0, s>>>(W, T, A);
     else
-      k_adj_pbd<1024, true><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
+      k_adj_pbd<1024, true, true><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
+  } else if (G.general) {
+    if (G.pack == 256)
+      k_adj_pbd<256, true, false><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+    else
+      k_adj_pbd<1024, true, false><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
   } else {
     if (G.pack == 256)
-      k_adj_pbd<256, false><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+      k_adj_pbd<256, false, false><<<G.node_blocks, 256, 0, s>>>(W, T, A);
     else
-      k_adj_pbd<1024, false><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
+      k_adj_pbd<1024, false, false><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
   }
 }
 

@@ -1691,7 +1691,6 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
     if (mode_of(s.p) != mc::kBinned)
       return fail(SIM_E_INVALID, "sim_backward needs the tile-binned transfer (world created with SIM_SPLAT_%s)",
                   mode_of(s.p) == mc::kSorted ? "SORTED" : "DIRECT");
-    if (s.any_branch) return fail(SIM_E_INVALID, "sim_backward does not differentiate branched worlds");
     if (s.p.pbd_iters > 8) return fail(SIM_E_INVALID, "the adjoint supports at most 8 PBD iterations");
   }
   size_t need = 0;

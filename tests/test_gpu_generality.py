@@ -8,10 +8,11 @@ Per step: e_x <= 1e-5, e_u <= 1e-4 and each step's displacement e_d <= 1e-4,
 in every transfer; a polygon loop and a T-junction at their rest shapes feel
 no elastic force; stiffness arrays equal to the scalars change no bit; a
 batch of such worlds equals its worlds run alone; the allocation-free step
-equals sim_step; the adjoint with per-edge stiffness matches the oracle's,
-and worlds with loops or branches are refused by sim_backward (branched ones
-by the allocation-free step too); topologies that break the branch rules are
-refused at creation; sim_rest_effort matches the oracle's efforts.
+equals sim_step; the adjoint matches the oracle's reverse mode with
+per-edge stiffnesses, through closed loops and through branched creatures;
+the allocation-free step refuses branched worlds; topologies that break the
+branch rules are refused at creation; sim_rest_effort matches the oracle's
+efforts.
 """
 import math
 
@@ -239,7 +240,7 @@ def test_branch_batch_alone_and_refusals():
         with pytest.raises(sim.SimError) as ei:
             sim.World(w, sim.Params(nx=64, ny=64))
         assert ei.value.status == sim.SIM_E_INVALID, par
-    # the allocation-free step and the adjoint refuse branched worlds
+    # the allocation-free step refuses branched worlds
     w = _branched(6)
     p = sim.Params(nx=w.nx, ny=w.ny)
     st = sim.DeviceState(w, "cuda")
@@ -247,11 +248,28 @@ def test_branch_batch_alone_and_refusals():
     with pytest.raises(sim.SimError) as ei:
         sim.step_noalloc(st, p, 0, status)
     assert ei.value.status == sim.SIM_E_INVALID
-    Wb = sim.World(w, p)
-    ck = torch.empty(Wb.checkpoint_bytes(4, 2), dtype=torch.uint8, device="cuda")
-    Wb.rollout(0, 4, 2, ck)
-    g_pos = torch.zeros(2, w.n_particles, dtype=torch.float32, device="cuda")
-    g_rest = torch.zeros(w.n_particles, dtype=torch.float32, device="cuda")
-    with pytest.raises(sim.SimError) as ei:
-        Wb.backward(0, 4, 2, ck, g_pos, g_rest)
-    assert ei.value.status == sim.SIM_E_INVALID
+
+
+@pytest.mark.parametrize("which", ["six creatures 96x80", "four creatures 72x64"])
+def test_adjoint_through_branches_matches_oracle(which):
+    """Reverse mode through branched creatures (Methods, Filaments: loops and
+    branches): the attachment joints at the parent and the child's first
+    node and the attachment edge, after the regular passes of each kind,
+    with children on chains and on loops, against the oracle's reverse mode;
+    the attachment rest values are constants."""
+    sim = _sim()
+    w = _branched(8) if which.startswith("six") else wl.branched_world(9, 72, 64, 4)
+    x0 = w.positions64()
+    target = x0 + np.random.default_rng(5).normal(0, 0.5, size=x0.shape)
+    g, _, W, p = _gpu_grad(sim, w, target, 12, 5)
+    ref, _ = _oracle_grad(w, p, target, 12, 5)
+    joints = _all_joints(w)
+    err, cos = _compare(g, ref, joints)
+    child = np.concatenate([np.arange(w.fil_offset[f], w.fil_offset[f + 1])
+                            for f in range(len(w.fil_offset) - 1) if w.parent[f] >= 0])
+    child = np.intersect1d(child, joints)
+    e_c, c_c = _compare(g, ref, child) if child.size else (0.0, 1.0)
+    print(f"adjoint through branches [{which}], {len(w.fil_offset) - 1} filaments: rel err {err:.2e} "
+          f"cos {cos:.6f}; joints of attached filaments {e_c:.2e} / {c_c:.6f}")
+    assert err <= 1e-3 and cos >= 0.9999
+    assert e_c <= 1e-3 and c_c >= 0.9999
