@@ -40,7 +40,7 @@ def _check(sim, x64, nx, ny, T, sigma, amp, label):
     (g_ref,) = torch.autograd.grad(L_ref, x) if x64.shape[1] else (torch.zeros(2, 0, dtype=DT),)
     im, gg = image.cpu().double().numpy(), g.cpu().double().numpy()
     e_im = np.max(np.abs(im - im_ref.detach().numpy())) / max(float(im_ref.detach().abs().max()), 1e-30)
-    e_L = abs(float(loss) - float(L_ref)) / float(L_ref)
+    e_L = abs(float(loss) - float(L_ref.detach())) / float(L_ref.detach())
     e_g = (np.max(np.abs(gg - g_ref.numpy())) / float(g_ref.abs().max())) if x64.shape[1] else 0.0
     print(f"{label}: image {e_im:.2e} loss {e_L:.2e} grad {e_g:.2e}")
     assert e_im <= 1e-5 and e_L <= 1e-5 and e_g <= 1e-4, (e_im, e_L, e_g)
