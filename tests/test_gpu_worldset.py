@@ -3,7 +3,8 @@
 run alone (bit for bit: the binned transfer's sums are fixed point and every
 kernel reads its world's own buffers), and one world's gradient matches the
 FP64 oracle's reverse mode (normwise relative <= 1e-3, cosine >= 0.9999);
-with multi-direct forcing as well; the single-world test hooks refuse sets.
+with multi-direct forcing and with two-layer markers as well; the
+single-world test hooks refuse sets.
 """
 import numpy as np
 import pytest
@@ -41,11 +42,11 @@ def _loss(x, tgts, n_parts):
     return loss
 
 
-@pytest.mark.parametrize("mdf", [1, 3])
-def test_set_equals_worlds_alone_and_the_oracle(mdf):
+@pytest.mark.parametrize("mdf,offset", [(1, 0.0), (3, 0.0), (3, 0.5)])
+def test_set_equals_worlds_alone_and_the_oracle(mdf, offset):
     sim = _sim()
     worlds = _worlds()
-    p = sim.Params(nx=80, ny=64, mdf_iters=mdf)
+    p = sim.Params(nx=80, ny=64, mdf_iters=mdf, marker_offset=offset)
     n, k = 14, 5
     S = sim.WorldSet(worlds, p)
     tg = [torch.tensor(t, dtype=torch.float64, device="cuda") for t in _targets(worlds)]
@@ -66,7 +67,7 @@ def test_set_equals_worlds_alone_and_the_oracle(mdf):
             assert torch.equal(getattr(S.states[i], key), getattr(W.state, key)), (i, key)
         g_one = raw.grad.cpu().numpy()
         d = float(np.abs(g_set[off:off + w.n_particles] - g_one).max())
-        print(f"MDF {mdf}, world {i} (N={w.n_particles}): set vs alone max |dg| = {d:.1e}")
+        print(f"MDF {mdf}, offset {offset}, world {i} (N={w.n_particles}): set vs alone max |dg| = {d:.1e}")
         assert np.array_equal(g_set[off:off + w.n_particles], g_one)
         if i == 1:
             ref, _ = _oracle_grad(w, p, _targets(worlds)[i], n, k)
