@@ -4,20 +4,24 @@
 // (Methods; Experiments, Filament Folding).  Given dL/dx_{t+1} and
 // dL/dg_{t+1}, one reversed step produces dL/dx_t, dL/dg_t and accumulates
 // dL/d(rest angle), visiting the forward sub-steps backwards:
-//   k_adj_u       S7: u~ = spread(dL/dx_{t+1})                 (tile, LDS)
+//   k_adj_spread  S7 (operand 0): u~ = spread(dL/dx_{t+1})     (tile, LDS)
 //   k_adj_lbm     S6: streaming^T (pull) and the collision Jacobian^T per
 //                     cell -> dL/dg_t, dL/dF_grid
 //   (MDF)         S5 with multi-direct forcing: the iterates recomputed,
 //                     then reversed iteration by iteration (k_adj_mdf_*)
 //   k_adj_force   S5, S4, S7: dL/dF_i = gather(dL/dF_grid); the derivative
 //                     terms of the three node gathers/spreads w.r.t. x_t
-//   k_adj_grad    S4: dL/dG = -k_rep spread(dL/dF)              (tile, LDS)
+//                     (at the two-layer markers where a world has them)
+//   k_adj_markers two layers: dL/dd through each node's normal to the
+//                     neighbours that define it
+//   k_adj_spread  S4 (operand 1): dL/dG = -k_rep spread(dL/dF) (tile, LDS)
 //   k_adj_filter  S3: dL/ds = G (D^T dL/dG): the central difference and the
 //                     symmetric Gaussian transposed                (tile, LDS)
 //   k_adj_pbd     S2, S1, S0: the deposit derivative, then the PBD iterations
 //                     reversed pass by pass (forward states recomputed and
-//                     kept in registers), atan2 of the initial edge angles and
-//                     the actuation -> dL/dx_t and dL/d(rest angle)
+//                     kept in registers; chains, closed loops, branches),
+//                     atan2 of the initial edge angles and the actuation ->
+//                     dL/dx_t and dL/d(rest angle)
 // Every forward field the adjoint needs (x_t, g_t, G_t, F_t, F_grid, u_t and
 // the tile bins of x_t) is taken from the tape written by the recomputed
 // forward step; the descriptor passed in points at that tape slot.
