@@ -879,8 +879,9 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 }
 
 // ---------------------------------------------------------------------------
-// S5 with multi-direct forcing (binned, one layer), forward recomputed and
-// reversed.  Forward: F_grid_1 = S[F], U_d = I[j / rho] + F / 2, and for
+// S5 with multi-direct forcing (binned transfer), forward recomputed and
+// reversed; with two layers, I and S act through the markers (the MK
+// variants), and the position terms also go to dL/dd.  Forward: F_grid_1 = S[F], U_d = I[j / rho] + F / 2, and for
 // k = 1 .. K-1: u_k = (j + F_grid_k / 2) / rho, c_k = 2 (U_d - I[u_k]),
 // F_grid_{k+1} = F_grid_k + S[c_k].  Given G~ = dL/dF_grid_{k+1}, iteration k
 // reversed: c~ = I[G~]; U_d~ += 2 c~; U_k~ = -2 c~; x~ gets the derivatives
@@ -889,7 +890,8 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
 // F~ += U_d~ / 2 (in k_adj_force), x~ from I[j / rho], v~ = S[U_d~] gives
 // j~ += v~ / rho, rho~ -= v~ . (j / rho) / rho, and finally g~_q += rho~ + c_q . j~.
 // Node passes gather over each tile's own-bin nodes from fields staged over
-// the tile and a 3-cell halo; the spreads are the tile spread in 64-bit
+// the tile with one cell before it and two after on each axis (one more on
+// each side with markers); the spreads are the tile spread in 64-bit
 // fixed point.  The recomputed iterates use the forward's arithmetic and sums,
 // so they equal the forward's bit for bit.
 // ---------------------------------------------------------------------------
