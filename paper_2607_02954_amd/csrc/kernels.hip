@@ -227,6 +227,12 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
         }
         __syncthreads();
       }
+      // the edge directions of this iteration (the angles change only in the
+      // bending passes), for every lane at once rather than per colour
+      float cs = 1.f, sn = 0.f;
+      if (has_edge) edge_direction(s_th[li], th, u0x, u0y, &cs, &sn);
+      float a_cs = 1.f, a_sn = 0.f;
+      if (BR && att) edge_direction(s_ta[li], a_th, a_ux, a_uy, &a_cs, &a_sn);
       // position pass (Eqs. 2-4): even edges, then odd edges (then the third colour)
       for (int par = 0; par < ncol; ++par) {
         if (has_edge && ecol == par) {
@@ -237,8 +243,6 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           const float ell = hw_sqrt(vx * vx + vy * vy);
           const float sc = (ell - L) * hw_rcp(ell);
           const float csx = sc * vx, csy = sc * vy;
-          float sn, cs;
-          edge_direction(s_th[li], th, u0x, u0y, &cs, &sn);
           const float dx = hs * (csx + ksh * (vx - L * cs - csx));
           const float dy = hs * (csy + ksh * (vy - L * sn - csy));
           s_dx[li] = d0x + dx;
@@ -257,10 +261,8 @@ __global__ __launch_bounds__(PACK) void k_elastic(const WorldDev* __restrict__ W
           const float ell = hw_sqrt(vx * vx + vy * vy);
           const float sc = (ell - a_L) * hw_rcp(ell);
           const float csx = sc * vx, csy = sc * vy;
-          float sn, cs;
-          edge_direction(s_ta[li], a_th, a_ux, a_uy, &cs, &sn);
-          const float dx = hs_w * (csx + ksh_w * (vx - a_L * cs - csx));
-          const float dy = hs_w * (csy + ksh_w * (vy - a_L * sn - csy));
+          const float dx = hs_w * (csx + ksh_w * (vx - a_L * a_cs - csx));
+          const float dy = hs_w * (csy + ksh_w * (vy - a_L * a_sn - csy));
           s_dx[p_l] = d0x + dx;
           s_dy[p_l] = d0y + dy;
           s_dx[li] = d1x - dx;
