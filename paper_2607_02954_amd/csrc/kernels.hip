@@ -1373,8 +1373,19 @@ __global__ __launch_bounds__(PACK) void k_energy_gather(const WorldDev* __restri
     s_c[li] = c;
     __syncthreads();
     if (w.e_collected && li < nf) {
+      // in node order; the loads eight at a time, so that one lane's chain
+      // of adds does not wait for each load in turn
       float sum = 0.f;
-      for (int k = s_off[li]; k < s_off[li + 1]; ++k) sum += s_c[k];
+      int k = s_off[li];
+      const int k1 = s_off[li + 1];
+      for (; k + 8 <= k1; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = s_c[k + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum += v[q];
+      }
+      for (; k < k1; ++k) sum += s_c[k];
       glb(w.e_collected)[pk.fil_begin + li] += sum;
     }
     __syncthreads();
