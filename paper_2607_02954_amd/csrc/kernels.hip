@@ -1469,20 +1469,85 @@ __global__ __launch_bounds__(PACK) void k_energy_deplete_atomic(const WorldDev* 
 }
 
 // Gaussian packets added to a field, every cell (minimum image).
-__global__ void k_energy_packets(int nx, int ny, int n_packets, const float* centres, const float* amps,
-                                 const float* widths, float* field) {
-  const int n = nx * ny;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-    const int y = c / nx, x = c - y * nx;
-    float acc = 0.f;
-    for (int p = 0; p < n_packets; ++p) {
-      float dx = (float)x - centres[p], dy = (float)y - centres[n_packets + p];
-      dx -= (float)nx * floorf(dx / (float)nx + 0.5f);
-      dy -= (float)ny * floorf(dy / (float)ny + 0.5f);
-      const float s = widths[p];
-      acc += amps[p] * expf(-(dx * dx + dy * dy) / (2.0f * s * s));
+// One block per 32x32 tile: the packets that can reach the tile are listed
+// (in index order) and each cell sums only those, in that order.  A packet
+// whose nearest distance to the tile (minimum image, less one cell for
+// rounding) exceeds sqrt(220) widths has exp(-r^2 / (2 s^2)) below e^-110,
+// which is exactly 0 in FP32 (below half the smallest denormal), at every
+// cell of the tile, so the sum is the full sum bit for bit.
+constexpr int kPacketTile = 32;
+constexpr int kPacketChunk = 1024;               // packets listed per pass
+__global__ __launch_bounds__(256) void k_energy_packets(int nx, int ny, int n_packets, const float* centres,
+                                                        const float* amps, const float* widths, float* field) {
+  __shared__ int s_list[kPacketChunk];
+  __shared__ int s_wave[4];
+  const int ntx = (nx + kPacketTile - 1) / kPacketTile, nty = (ny + kPacketTile - 1) / kPacketTile;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
+    const int x0 = (t % ntx) * kPacketTile, y0 = (t / ntx) * kPacketTile;
+    const int x1 = min(x0 + kPacketTile, nx) - 1, y1 = min(y0 + kPacketTile, ny) - 1;
+    const float hx = 0.5f * (float)(x1 - x0), hy = 0.5f * (float)(y1 - y0);
+    const float mx = 0.5f * (float)(x0 + x1), my = 0.5f * (float)(y0 + y1);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};             // cells tid + 256 k of the tile
+    for (int p0 = 0; p0 < n_packets; p0 += kPacketChunk) {
+      // list this chunk's packets that can reach the tile, in index order:
+      // thread tid tests packets p0 + 4 tid .. + 3
+      int keep[4];
+      int n_keep = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pi = p0 + 4 * tid + q;
+        keep[q] = 0;
+        if (pi < n_packets) {
+          float dx = centres[pi] - mx, dy = centres[n_packets + pi] - my;
+          dx -= (float)nx * floorf(dx / (float)nx + 0.5f);
+          dy -= (float)ny * floorf(dy / (float)ny + 0.5f);
+          const float ex = fmaxf(fabsf(dx) - hx - 1.0f, 0.f), ey = fmaxf(fabsf(dy) - hy - 1.0f, 0.f);
+          const float s = widths[pi];
+          keep[q] = ex * ex + ey * ey <= 220.0f * s * s ? 1 : 0;
+          n_keep += keep[q];
+        }
+      }
+      // exclusive prefix of n_keep over the block (thread order = packet order)
+      int x = n_keep;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+      }
+      if (lane == 63) s_wave[wv] = x;
+      __syncthreads();
+      int base = x - n_keep;
+      for (int j = 0; j < wv; ++j) base += s_wave[j];
+      const int total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (keep[q]) s_list[base++] = p0 + 4 * tid + q;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = tid + 256 * k;
+        const int x = x0 + (c & (kPacketTile - 1)), y = y0 + (c >> 5);
+        if (x > x1 || y > y1) continue;
+        float a = acc[k];
+        for (int i = 0; i < total; ++i) {
+          const int p = s_list[i];
+          float dx = (float)x - centres[p], dy = (float)y - centres[n_packets + p];
+          dx -= (float)nx * floorf(dx / (float)nx + 0.5f);
+          dy -= (float)ny * floorf(dy / (float)ny + 0.5f);
+          const float s = widths[p];
+          a += amps[p] * expf(-(dx * dx + dy * dy) / (2.0f * s * s));
+        }
+        acc[k] = a;
+      }
+      __syncthreads();
     }
-    field[c] += acc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = tid + 256 * k;
+      const int x = x0 + (c & (kPacketTile - 1)), y = y0 + (c >> 5);
+      if (x <= x1 && y <= y1) field[(size_t)y * nx + x] += acc[k];
+    }
   }
 }
 
@@ -1998,9 +2063,8 @@ void launch_energy(const WorldDev* W, const Tables& T, const Grid& G, hipStream_
 
 void launch_energy_packets(int nx, int ny, int n_packets, const float* centres, const float* amps,
                            const float* widths, float* field, hipStream_t s) {
-  const int n = nx * ny;
-  k_energy_packets<<<n / 256 + 1 < 4096 ? n / 256 + 1 : 4096, 256, 0, s>>>(nx, ny, n_packets, centres, amps, widths,
-                                                                         field);
+  const int nt = ((nx + kPacketTile - 1) / kPacketTile) * ((ny + kPacketTile - 1) / kPacketTile);
+  k_energy_packets<<<nt < 8192 ? nt : 8192, 256, 0, s>>>(nx, ny, n_packets, centres, amps, widths, field);
 }
 
 void launch_tile_ranges(int nx, int ny, int R, int tile, int2* out, hipStream_t s) {
