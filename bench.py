@@ -276,6 +276,41 @@ def bench_adjoint(seed, reps=5):
     return out
 
 
+def bench_adjoint_scale(world, tile, n=20, k=10, reps=3):
+    """Reverse mode at the full workload (1,048,576 nodes on 2048^2): one
+    checkpointed rollout of n steps (checkpoints every k) and its backward,
+    loss = mean squared distance of the final positions to a seeded target."""
+    W = sim.World(world, sim.Params(nx=world.nx, ny=world.ny, tile=tile))
+    x0 = world.positions64()
+    tgt = torch.tensor(x0 + np.random.default_rng(7).normal(0, 0.5, size=x0.shape), dtype=torch.float64,
+                       device="cuda")
+    cell0, frac0 = W.state.cell.clone(), W.state.frac.clone()
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        W.state.cell.copy_(cell0)
+        W.state.frac.copy_(frac0)
+        W.state.f.zero_()
+        ra = torch.tensor(world.rest_angle, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        xT = sim.Rollout.apply(ra, W, 0, n, k)
+        loss = ((xT - tgt) ** 2).sum() / xT.shape[1]
+        e[1].record()
+        loss.backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        if r:
+            fwd.append(e[0].elapsed_time(e[1]))
+            bwd.append(e[1].elapsed_time(e[2]))
+    W.close()
+    fm, bm = float(np.median(fwd)), float(np.median(bwd))
+    return {"workload": f"scaling: {world.n_particles} nodes on {world.nx}x{world.ny}, {n} steps, checkpoints every "
+                        f"{k}, gradient of a target-position loss in the rest angles",
+            "checkpointed_forward_ms": fm, "backward_ms": bm, "bwd_over_fwd": bm / fm,
+            "backward_ms_per_step": bm / n}
+
+
 def bench_adjoint_set(seed, n, k, alone_ms, n_worlds=16, reps=2):
     """The same differentiation for 16 folding worlds (seeds seed..seed+15)
     stepped and reversed together as one set of worlds (sim_create_set): one
@@ -706,6 +741,7 @@ def main():
     out["atomic_throughput"] = at
     if not args.no_adjoint:
         out["differentiation"] = bench_adjoint(args.seed)
+        out["differentiation"]["at_scale"] = bench_adjoint_scale(world, tile)
         log("differentiation done")
         out["density_folding"] = bench_density_folding(args.seed)
         log("density folding done")
