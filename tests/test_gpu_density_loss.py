@@ -74,7 +74,7 @@ def _pipeline(sim, w, T, sigma, amp, n, k):
     L = sim.DensityLoss.apply(xT, w.nx, w.ny, Tg, sigma, amp)
     L.backward()
     torch.cuda.synchronize()
-    return ra.grad.cpu().numpy(), float(L), W
+    return ra.grad.cpu().numpy(), float(L.detach()), W
 
 
 def _oracle_pipeline(w, T, sigma, amp, n, k):
