@@ -88,7 +88,7 @@ def _oracle_pipeline(w, T, sigma, amp, n, k):
     L = O.density_loss(O.density_image(xr, w.nx, w.ny, Wd, H, sigma, amp), torch.tensor(T, dtype=DT))
     (gx,) = torch.autograd.grad(L, xr)
     g_ra, _ = O.rollout_gradient(x0, f0, 0, n, inp, op, gx, segment=k)
-    return g_ra.numpy(), float(L)
+    return g_ra.numpy(), float(L.detach())
 
 
 def _joints(w):
