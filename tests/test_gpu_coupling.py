@@ -60,6 +60,23 @@ def test_two_layers_on_branched_creatures(mode, mdf):
     print(f"branched creatures, two layers, MDF {mdf} [{mode}], N={w.n_particles}: {E}")
 
 
+@pytest.mark.parametrize("mode", ["binned", "direct"])
+def test_edge_cases_with_mdf_and_two_layers(mode):
+    sim = _sim()
+    # an empty world stays at rest; a world of single nodes and two-node
+    # filaments (no tangent beyond their one edge) and a filament longer than
+    # 256 nodes (the 1024-node pack) match the oracle
+    empty = wl._assemble(32, 24, [], [], [], [], [], [])
+    W = sim.World(empty, sim.Params(nx=32, ny=24, transfer=mode, mdf_iters=3, marker_offset=0.5))
+    W.rollout(0, 5)
+    W.sync()
+    assert float(W.state.f.abs().max()) < 1e-7
+    W.close()
+    for w in (wl.random_world(6, 48, 40, [1, 2, 1, 2, 1], amp=0.5), wl.random_world(7, 96, 96, [600, 3], amp=0.5)):
+        E = _rollout_compare(sim, w, 8, mode, mdf_iters=3, marker_offset=0.5)
+        print(f"MDF 3, two layers [{mode}], {w.nx}x{w.ny} N={w.n_particles}: {E}")
+
+
 def test_unbuilt_combinations_are_refused():
     sim = _sim()
     w = ragged_world(1)
