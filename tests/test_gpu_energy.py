@@ -58,8 +58,8 @@ def test_energy_steps_match_oracle(mode, offset):
     sim = _sim()
     rate = 0.3
     w = wl.energy_world(1, nx=96, ny=80, n_fil=10, length=24)
-    E, _ = _field(sim, w)
-    w.energy = E.cpu().numpy()
+    _, ref = _field(sim, w)             # the initial field from the oracle's packets (FP32 copy)
+    w.energy = ref.numpy().astype(np.float32)
     p = sim.Params(nx=w.nx, ny=w.ny, transfer=mode, energy_rate=rate, marker_offset=offset)
     W = sim.World(w, p)
     plain = sim.World(wl.energy_world(1, nx=96, ny=80, n_fil=10, length=24), sim.Params(nx=w.nx, ny=w.ny,
