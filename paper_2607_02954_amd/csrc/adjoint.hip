@@ -208,118 +208,151 @@ __global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W,
 // difference (dL/dd) to A.dbar, which k_adj_markers carries through the
 // normal d(x_prev, x_next).  The repulsion gather stays at the node.
 // ---------------------------------------------------------------------------
-template <int PACK>
-__global__ __launch_bounds__(PACK) void k_adj_force(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
-  const int npk = *T.n_packs;
-  for (int it = blockIdx.x; it < npk; it += gridDim.x) {
-    const Pack pk = T.packs[it];
-    const WorldDev& w = W[pk.world];
-    const AdjDev& A = adj_of(AA, pk.world);
-    const int gi = pk.node_begin + threadIdx.x;
-    if (gi >= pk.node_end) continue;
+template <int TILE, bool MK>
+__global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_force(const WorldDev* __restrict__ W, Tables T,
+                                                                        AdjArg AA) {
+  // per tile: u, dL/dF_grid and the density gradient staged over the cells
+  // the supports of the tile's own nodes (and of their markers: MK) reach,
+  // then one thread per node of the tile's bin
+  constexpr int kE = MK ? 1 : 0;
+  constexpr int kStage = TILE + 3 + 2 * kE, kThreads = TileCfg<TILE>::kThreads, kCells = kStage * kStage;
+  __shared__ vf2 s_u[kCells];
+  __shared__ vf2 s_fb[kCells];
+  __shared__ vf2 s_g[kCells];
+  const int nt = n_tiles<TILE>(T);
+  const XcdLoop tiles(nt);
+  for (int it = tiles.first; it < tiles.end; it += tiles.step) {
+    const int2 tl = tile_entry<TILE>(T, it);
+    const WorldDev& w = W[tl.x];
+    if (MK != (w.d_marker != nullptr)) continue;
+    const AdjDev& A = adj_of(AA, tl.x);
     const int N = w.n_part, nx = w.nx, ny = w.ny;
-    const MC_GLOBAL int* cell = glb(w.cell_in);
-    const MC_GLOBAL float* frac = glb(w.frac_in);
-    const int bx = wrap_index(cell[gi], nx), by = wrap_index(cell[N + gi], ny);
-    float wx[4], dwx[4], wy[4], dwy[4];
-    peskin4_d(frac[gi], wx, dwx);
-    peskin4_d(frac[N + gi], wy, dwy);
-    const float xbx = A.xbar_in[gi], xby = A.xbar_in[N + gi];
-    const float Fx = w.fel[gi], Fy = w.fel[N + gi];
+    const int x0 = tile_x(tl.y) * TILE, y0 = tile_y(tl.y) * TILE;
     const MC_GLOBAL vf2* u = glbv<const vf2>(w.u);
     const MC_GLOBAL vf2* Fgb = glbv<const vf2>(A.Fgbar);
     const MC_GLOBAL vf2* Gr = glbv<const vf2>(w.grad);
-    int ix[4];
+    {
+      constexpr int kIt = (kCells + kThreads - 1) / kThreads;
+      vf2 vu[kIt], vf[kIt], vg[kIt];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) ix[a] = wrap_near(bx - 1 + a, nx);
-    float fbx = 0.f, fby = 0.f;       // dL/dF_i
-    float sux = 0.f, suy = 0.f;       // d/dx of  sum_c W (u_c . xbar')
-    float sfx = 0.f, sfy = 0.f;       // d/dx of  sum_c W (F_i . Fgbar_c)
-    float grx[4][4], gry[4][4];
+      for (int i = 0; i < kIt; ++i) {          // every load in flight before the stores
+        const int k = min((int)threadIdx.x + kThreads * i, kCells - 1);
+        const int r = k / kStage, c = k - (k / kStage) * kStage;
+        const size_t idx = (size_t)wrap_index(y0 - 1 - kE + r, ny) * nx + wrap_index(x0 - 1 - kE + c, nx);
+        vu[i] = u[idx];
+        vf[i] = Fgb[idx];
+        vg[i] = Gr[idx];
+      }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const size_t row = (size_t)wrap_near(by - 1 + b, ny) * nx;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const vf2 uc = u[row + ix[a]];
-        const vf2 fc = Fgb[row + ix[a]];
-        const vf2 gc = Gr[row + ix[a]];
-        grx[b][a] = gc.x;
-        gry[b][a] = gc.y;
-        const float W0 = wx[a] * wy[b], Wx = dwx[a] * wy[b], Wy = wx[a] * dwy[b];
-        fbx += W0 * fc.x;
-        fby += W0 * fc.y;
-        const float pu = uc.x * xbx + uc.y * xby;
-        sux += Wx * pu;
-        suy += Wy * pu;
-        const float pf = Fx * fc.x + Fy * fc.y;
-        sfx += Wx * pf;
-        sfy += Wy * pf;
+      for (int i = 0; i < kIt; ++i) {
+        const int k = (int)threadIdx.x + kThreads * i;
+        if (k < kCells) {
+          s_u[k] = vu[i];
+          s_fb[k] = vf[i];
+          s_g[k] = vg[i];
+        }
       }
     }
-    if (w.d_marker) {                   // two layers: the transfer terms again, at the markers
-      fbx = fby = 0.f;
-      sux = suy = sfx = sfy = 0.f;
-      const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
-      float dbx = 0.f, dby = 0.f;
+    __syncthreads();
+    const int tile = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int e0 = glb(w.bin_start)[tile], e1 = glb(w.bin_start)[tile + 1];
+    const MC_GLOBAL vi4* recs = glbv<const vi4>(w.bin_rec);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
+      const vi4 rec = recs[e];
+      const int lx = (rec.x & 0xffff) - x0, ly = (rec.x >> 16) - y0;   // home cell in the tile
+      const int gi = rec.w;
+      const float nfx = __int_as_float(rec.y), nfy = __int_as_float(rec.z);
+      float wx[4], dwx[4], wy[4], dwy[4];
+      peskin4_d(nfx, wx, dwx);
+      peskin4_d(nfy, wy, dwy);
+      const float xbx = A.xbar_in[gi], xby = A.xbar_in[N + gi];
+      const float Fx = w.fel[gi], Fy = w.fel[N + gi];
+      float fbx = 0.f, fby = 0.f;       // dL/dF_i
+      float sux = 0.f, suy = 0.f;       // d/dx of  sum_c W (u_c . xbar')
+      float sfx = 0.f, sfy = 0.f;       // d/dx of  sum_c W (F_i . Fgbar_c)
+      float grx[4][4], gry[4][4];
 #pragma unroll
-      for (int l = 0; l < 2; ++l) {
-        const float sg = l == 0 ? 1.f : -1.f;
-        int shx, shy;
-        float mfx, mfy;
-        marker_shift(frac[gi], sg * ddx, &shx, &mfx);
-        marker_shift(frac[N + gi], sg * ddy, &shy, &mfy);
-        const int mbx = wrap_index(cell[gi] + shx, nx), mby = wrap_index(cell[N + gi] + shy, ny);
-        float mwx[4], mdwx[4], mwy[4], mdwy[4];
-        peskin4_d(mfx, mwx, mdwx);
-        peskin4_d(mfy, mwy, mdwy);
-        float px = 0.f, py = 0.f;
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const size_t row = (size_t)wrap_near(mby - 1 + b, ny) * nx;
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            const size_t c = row + wrap_near(mbx - 1 + a, nx);
-            const vf2 uc = u[c];
-            const vf2 fc = Fgb[c];
-            const float W0 = 0.5f * mwx[a] * mwy[b], Wx = 0.5f * mdwx[a] * mwy[b], Wy = 0.5f * mwx[a] * mdwy[b];
+        for (int a = 0; a < 4; ++a) {
+          const int q = (ly + kE + b) * kStage + lx + kE + a;
+          const vf2 gc = s_g[q];
+          grx[b][a] = gc.x;
+          gry[b][a] = gc.y;
+          if constexpr (!MK) {
+            const vf2 uc = s_u[q];
+            const vf2 fc = s_fb[q];
+            const float W0 = wx[a] * wy[b], Wx = dwx[a] * wy[b], Wy = wx[a] * dwy[b];
             fbx += W0 * fc.x;
             fby += W0 * fc.y;
-            const float pp = (uc.x * xbx + uc.y * xby) + (Fx * fc.x + Fy * fc.y);
-            px += Wx * pp;
-            py += Wy * pp;
+            const float pu = uc.x * xbx + uc.y * xby;
+            sux += Wx * pu;
+            suy += Wy * pu;
+            const float pf = Fx * fc.x + Fy * fc.y;
+            sfx += Wx * pf;
+            sfy += Wy * pf;
           }
         }
-        sux += px;                      // dL/dX of each marker moves the node ...
-        suy += py;
-        dbx += sg * px;                 // ... and, with its sign, the displacement
-        dby += sg * py;
-      }
-      A.dbar[gi] = dbx;
-      A.dbar[N + gi] = dby;
-    }
-    float mx = 0.f, my = 0.f;
-    if (A.mdf > 1) {                    // U_d = I[j / rho] + F / 2, and the MDF transfers' position terms
-      fbx += 0.5f * A.Udbar[gi];
-      fby += 0.5f * A.Udbar[N + gi];
-      mx = A.xbar_m[gi];
-      my = A.xbar_m[N + gi];
-    }
-    // repulsion F_rep = -k sum_c W G_c : d/dx of (-k sum_c W (G_c . Fbar))
-    float srx = 0.f, sry = 0.f;
+      if constexpr (MK) {               // two layers: the transfer terms at the markers
+        const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
+        float dbx = 0.f, dby = 0.f;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+        for (int l = 0; l < 2; ++l) {
+          const float sg = l == 0 ? 1.f : -1.f;
+          int shx, shy;
+          float mfx, mfy;
+          marker_shift(nfx, sg * ddx, &shx, &mfx);
+          marker_shift(nfy, sg * ddy, &shy, &mfy);
+          float mwx[4], mdwx[4], mwy[4], mdwy[4];
+          peskin4_d(mfx, mwx, mdwx);
+          peskin4_d(mfy, mwy, mdwy);
+          float px = 0.f, py = 0.f;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const float pg = grx[b][a] * fbx + gry[b][a] * fby;
-        srx += dwx[a] * wy[b] * pg;
-        sry += wx[a] * dwy[b] * pg;
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int q = (ly + shy + 1 + b) * kStage + lx + shx + 1 + a;
+              const vf2 uc = s_u[q];
+              const vf2 fc = s_fb[q];
+              const float W0 = 0.5f * mwx[a] * mwy[b], Wx = 0.5f * mdwx[a] * mwy[b], Wy = 0.5f * mwx[a] * mdwy[b];
+              fbx += W0 * fc.x;
+              fby += W0 * fc.y;
+              const float pp = (uc.x * xbx + uc.y * xby) + (Fx * fc.x + Fy * fc.y);
+              px += Wx * pp;
+              py += Wy * pp;
+            }
+          sux += px;                    // dL/dX of each marker moves the node ...
+          suy += py;
+          dbx += sg * px;               // ... and, with its sign, the displacement
+          dby += sg * py;
+        }
+        A.dbar[gi] = dbx;
+        A.dbar[N + gi] = dby;
       }
-    const float kr = w.k_rep;
-    A.Fbar[gi] = fbx;
-    A.Fbar[N + gi] = fby;
-    A.xbar[gi] = xbx + sux + sfx - kr * srx + mx;
-    A.xbar[N + gi] = xby + suy + sfy - kr * sry + my;
+      float mx = 0.f, my = 0.f;
+      if (A.mdf > 1) {                  // U_d = I[j / rho] + F / 2, and the MDF transfers' position terms
+        fbx += 0.5f * A.Udbar[gi];
+        fby += 0.5f * A.Udbar[N + gi];
+        mx = A.xbar_m[gi];
+        my = A.xbar_m[N + gi];
+      }
+      // repulsion F_rep = -k sum_c W G_c : d/dx of (-k sum_c W (G_c . Fbar))
+      float srx = 0.f, sry = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float pg = grx[b][a] * fbx + gry[b][a] * fby;
+          srx += dwx[a] * wy[b] * pg;
+          sry += wx[a] * dwy[b] * pg;
+        }
+      const float kr = w.k_rep;
+      A.Fbar[gi] = fbx;
+      A.Fbar[N + gi] = fby;
+      A.xbar[gi] = xbx + sux + sfx - kr * srx + mx;
+      A.xbar[N + gi] = xby + suy + sfy - kr * sry + my;
+    }
+    __syncthreads();
   }
 }
 
@@ -1318,7 +1351,10 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
     node_pass(std::integral_constant<int, 1>(), 0);
     MC_ADJ_TILES2(k_adj_mdf_cell, 1, G, W, T, A, 0);
   }
-  MC_ADJ_PACK(k_adj_force, G, W, T, A);
+  for_tile_variants(G, [&](auto tile, auto mk) {
+    constexpr int TL = decltype(tile)::value;
+    k_adj_force<TL, decltype(mk)::value><<<G.tile_blocks[TileCfg<TL>::kFamily], TileCfg<TL>::kThreads, 0, s>>>(W, T, A);
+  });
   if (G.any_markers) MC_ADJ_PACK(k_adj_markers, G, W, T, A);
   MC_ADJ_TILES(k_adj_spread, G, W, T, A, 1, 0);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
