@@ -111,8 +111,11 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const Wo
 // transposed, per cell.  Reads g_t, F_grid_t (tape) and u~ (from k_adj_u).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
-  const int nit = *T.n_items;
-  for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+  // (items in XCD-contiguous order, as in the forward fluid kernel; the
+  // populations and their adjoint are touched once per reversed step, so
+  // their loads and stores bypass the caches' allocation)
+  const XcdLoop items(*T.n_items);
+  for (int it = items.first; it < items.end; it += items.step) {
     const int2 item = T.items[it];
     const WorldDev& w = W[item.x];
     const AdjDev& A = adj_of(AA, item.x);
@@ -127,10 +130,10 @@ __global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W,
     float g[9], gs[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      g[q] = src[(size_t)q * ncell + c];
+      g[q] = __builtin_nontemporal_load((const float*)(src + (size_t)q * ncell + c));
       const int xn = wrap_near(x + kCX[q], nx);
       const int yn = wrap_near(y + kCY[q], ny);
-      gs[q] = gin[(size_t)q * ncell + (size_t)yn * nx + xn];     // dL/dg*_q(c)
+      gs[q] = __builtin_nontemporal_load((const float*)(gin + (size_t)q * ncell + (size_t)yn * nx + xn));   // dL/dg*_q(c)
     }
     const vf2 F = glbv<const vf2>(w.Fg)[c];
     const vf2 ubv = glbv<const vf2>(A.ubar)[c];
@@ -193,7 +196,8 @@ __global__ __launch_bounds__(256) void k_adj_lbm(const WorldDev* __restrict__ W,
     MC_GLOBAL float* gout = glb(A.gbar);
 #pragma unroll
     for (int q = 0; q < 9; ++q)
-      gout[(size_t)q * ncell + c] = gdir[q] + drb + (float)kCX[q] * jbx + (float)kCY[q] * jby;
+      __builtin_nontemporal_store(gdir[q] + drb + (float)kCX[q] * jbx + (float)kCY[q] * jby,
+                                  (float*)(gout + (size_t)q * ncell + c));
     const vf2 fb = {Fbx, Fby};
     glbv<vf2>(A.Fgbar)[c] = fb;
   }
