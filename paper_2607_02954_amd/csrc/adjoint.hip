@@ -22,9 +22,10 @@
 //                     kept in registers; chains, closed loops, branches),
 //                     atan2 of the initial edge angles and the actuation ->
 //                     dL/dx_t and dL/d(rest angle)
-// Every forward field the adjoint needs (x_t, g_t, G_t, F_t, F_grid, u_t and
-// the tile bins of x_t) is taken from the tape written by the recomputed
-// forward step; the descriptor passed in points at that tape slot.
+// Every forward field the adjoint needs (x_t, g_t, G_t, F_t, F_grid, u_t, the
+// tile bins of x_t and the filter's spread lists) is taken from the tape
+// written by the recomputed forward step; the descriptor passed in points at
+// that tape slot.
 #include "device_util.h"
 
 namespace mc {
@@ -82,14 +83,34 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_spread(const Wo
     zero_lds_u64(s_x, kSpreadCells);
     zero_lds_u64(s_y, kSpreadCells);
     __syncthreads();
+    // the step's spread list (written by the recomputed filter into the
+    // tape), or the bins if it overflowed (and for the test hook, which runs
+    // on a world's own buffers)
+    const int tix = tile_y(tl.y) * w.ntx + tile_x(tl.y);
+    const int cnt = which != 4 ? glb(w.sp_cnt)[tix] : -1;
+    BinFetch lf;
+    lf.n = 1;
+    lf.b0 = tix * C::kSpreadCap;
+    lf.len = __lane_id() == 0 ? cnt : 0;
+    const bool list = cnt >= 0 && cnt <= C::kSpreadCap;
+    const MC_GLOBAL vi4* lrec = glbv<const vi4>(w.sp_rec);
+    const MC_GLOBAL vi4* brec = glbv<const vi4>(w.bin_rec);
     // the transfers of the node<->grid coupling act through two-layer
     // markers where a world has them; the repulsion (G~) stays at the node
-    if (w.d_marker && which != 1 && which != 4)
-      tile_spread_markers<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list,
-                                       glbv<const vi4>(w.bin_rec), spread_fetch<TILE>(w, x0, y0), nullptr);
-    else
-      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, glbv<const vi4>(w.bin_rec),
+    if (w.d_marker && which != 1 && which != 4) {
+      if (list)
+        tile_spread_markers<TILE, false, true>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, lrec, lf, nullptr);
+      else
+        tile_spread_markers<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, brec,
+                                         spread_fetch<TILE>(w, x0, y0), nullptr);
+    } else if (list && !w.d_marker) {
+      tile_spread_vec<TILE, false, true>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, lrec, lf, nullptr);
+    } else if (list) {                 // a two-layer world's list also holds nodes one cell further out
+      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, lrec, lf, nullptr);
+    } else {
+      tile_spread_vec<TILE, false>(w, x0, y0, tw, th, glb(v), scale, s_x, s_y, s_list, brec,
                                    spread_fetch<TILE>(w, x0, y0), nullptr);
+    }
     __syncthreads();
     MC_GLOBAL vf2* o = glbv<vf2>(out);
     for (int k = threadIdx.x; k < TILE * TILE; k += kThreads) {

@@ -1567,6 +1567,8 @@ struct AdjLayout {
   std::vector<float*> F;       // m slots of [2][N]
   std::vector<int*> bstart;    // m + 1 slots of [nt+1] (step j's bins; slot m is scratch)
   std::vector<int4*> brec;     // m slots of [N]
+  std::vector<int4*> sprec;    // m slots of the spread lists the recomputed filter writes
+  std::vector<int*> spcnt;     // m slots of their lengths
   int* bin_cnt = nullptr;
   int* bin_fill = nullptr;
   float* xbar[2] = {};
@@ -1610,6 +1612,9 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
   L.F.resize(m);
   L.bstart.resize(m + 1);
   L.brec.resize(m);
+  L.sprec.resize(m);
+  L.spcnt.resize(m);
+  const size_t ntiles = (size_t)tiles_x(p) * tiles_y(p);
   for (int j = 0; j < m; ++j) {
     L.grad[j] = c.take<float2>(L.ncell);
     L.Fg[j] = c.take<float2>(L.ncell);
@@ -1617,6 +1622,8 @@ void carve_adj(Carver& c, const sim_params& p, int n_part, int m, AdjLayout& L) 
     L.F[j] = c.take<float>(2 * L.N);
     L.bstart[j] = c.take<int>(L.nt + 1);
     L.brec[j] = c.take<int4>(L.N);
+    L.sprec[j] = c.take<int4>(ntiles * mc::spread_cap_of_side(tile_side(p)));
+    L.spcnt[j] = c.take<int>(ntiles);
   }
   L.bstart[m] = c.take<int>(L.nt + 1);
   L.bin_cnt = c.take<int>(L.nt);
@@ -1739,6 +1746,8 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
       d.bin_start = L.bstart[j];
       d.bin_start_next = L.bstart[j + 1];
       d.bin_rec = L.brec[j];
+      d.sp_rec = L.sprec[j];                   // step j's spread lists, for the adjoint spreads
+      d.sp_cnt = L.spcnt[j];
       d.ctl_src = L.ctl + j;                   // the fluid kernel of step j advances it into j + 1
       d.ctl_dst = L.ctl + j + 1;
       d.s = nullptr;
