@@ -30,7 +30,7 @@
 
 namespace mc {
 
-constexpr int kMaxAdjIters = 8;   // PBD iterations the adjoint keeps in registers
+constexpr int kMaxAdjIters = 8;   // most PBD iterations the adjoint keeps in registers
 
 static __device__ __forceinline__ const AdjDev& adj_of(const AdjArg& a, int world) {
   return a.arr ? a.arr[world] : a.one;
@@ -551,8 +551,11 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_filter(const Wo
 // (each attached filament's first node c0 owns its attachment: the joints
 // at the parent p and at c0, then the edge p -> c0, after the regular
 // passes of each kind, with the world's stiffnesses and fixed rest angles).
+// IT: the iterations whose states the registers hold (at least every
+// world's pbd_iters; 4 for the usual count, kMaxAdjIters otherwise: fewer
+// registers, more blocks per CU).
 // ---------------------------------------------------------------------------
-template <int PACK, bool GEN, bool BR>
+template <int PACK, bool GEN, bool BR, int IT>
 __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W, Tables T, AdjArg AA) {
   static_assert(GEN || !BR, "branches take the general variant");
   __shared__ float s_th[PACK];
@@ -690,16 +693,16 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     const float hs = 0.5f * (w.ks_arr ? glb(w.ks_arr)[gs] : w.k_stretch);
     const float ksh = w.ksh_arr ? glb(w.ksh_arr)[gs] : w.k_shear;
     constexpr int kCol = GEN ? 3 : 2;
-    float d_p_x[kCol][kMaxAdjIters], d_p_y[kCol][kMaxAdjIters];   // d before each position colour
-    float th_p[kMaxAdjIters];
-    constexpr int kAtt = BR ? kMaxAdjIters : 1;
+    float d_p_x[kCol][IT], d_p_y[kCol][IT];   // d before each position colour
+    float th_p[IT];
+    constexpr int kAtt = BR ? IT : 1;
     float ta_p[kAtt], da_x[kAtt], da_y[kAtt];   // attachment angle after the joints; d before its edge pass
     s_th[li] = th;
     s_dx[li] = 0.f;
     s_dy[li] = 0.f;
     __syncthreads();
 #pragma unroll
-    for (int iter = 0; iter < kMaxAdjIters; ++iter) {
+    for (int iter = 0; iter < IT; ++iter) {
       if (iter < K) {
 #pragma unroll
         for (int par = 0; par < kCol; ++par) {
@@ -795,7 +798,7 @@ __global__ __launch_bounds__(PACK) void k_adj_pbd(const WorldDev* __restrict__ W
     float a_v0bx = 0.f, a_v0by = 0.f;          // dL/d(attachment vector), c0 lanes
     __syncthreads();
 #pragma unroll
-    for (int iter = kMaxAdjIters - 1; iter >= 0; --iter) {
+    for (int iter = IT - 1; iter >= 0; --iter) {
       if (iter < K) {
         if (BR && any_att) {                   // attachment edges reversed
           if constexpr (BR) {
@@ -1383,22 +1386,28 @@ void launch_adjoint_step(const WorldDev* W, const Tables& T, const Grid& G, cons
   if (G.any_markers) MC_ADJ_PACK(k_adj_markers, G, W, T, A);
   MC_ADJ_TILES(k_adj_spread, G, W, T, A, 1, 0);
   MC_ADJ_TILES(k_adj_filter, G, W, T, A);
-  if (G.branches) {
+  const auto pbd = [&](auto gen, auto br, auto it) {
+    constexpr bool GN = decltype(gen)::value, B = decltype(br)::value;
+    constexpr int I = decltype(it)::value;
     if (G.pack == 256)
-      k_adj_pbd<256, true, true><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+      k_adj_pbd<256, GN, B, I><<<G.node_blocks, 256, 0, s>>>(W, T, A);
     else
-      k_adj_pbd<1024, true, true><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
-  } else if (G.general) {
-    if (G.pack == 256)
-      k_adj_pbd<256, true, false><<<G.node_blocks, 256, 0, s>>>(W, T, A);
+      k_adj_pbd<1024, GN, B, I><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
+  };
+  const auto pbd_iters = [&](auto gen, auto br) {
+    if (G.pbd_max <= 4)
+      pbd(gen, br, std::integral_constant<int, 4>());
     else
-      k_adj_pbd<1024, true, false><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
-  } else {
-    if (G.pack == 256)
-      k_adj_pbd<256, false, false><<<G.node_blocks, 256, 0, s>>>(W, T, A);
-    else
-      k_adj_pbd<1024, false, false><<<G.node_blocks, 1024, 0, s>>>(W, T, A);
-  }
+      pbd(gen, br, std::integral_constant<int, kMaxAdjIters>());
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  if (G.branches)
+    pbd_iters(T_(), T_());
+  else if (G.general)
+    pbd_iters(T_(), F_());
+  else
+    pbd_iters(F_(), F_());
 }
 
 }  // namespace mc

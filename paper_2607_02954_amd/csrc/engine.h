@@ -162,6 +162,8 @@ struct Grid {
   int mdf_max;                               // most MDF iterations of any world (1: none)
   int general;                               // a world passes loop flags or per-edge stiffnesses
   int branches;                              // a world has branches (filaments hanging from nodes)
+  int pbd_max;                               // most PBD iterations of any world (set by the
+                                             // reverse mode: sizes its register states)
 };
 
 // Reverse-mode buffers of one step (adjoint.hip).  "_in" holds dL/d(state at

@@ -1713,6 +1713,8 @@ sim_status sim_backward(sim_world* w, int64_t t0, int32_t n_steps, int32_t ckpt_
   hipStream_t st = e.stream;
   mc::Grid g = e.grid;
   g.any_binned = 1;
+  g.pbd_max = 0;
+  for (const Slot& s : e.slots) g.pbd_max = std::max(g.pbd_max, s.p.pbd_iters);
   g.any_sorted = 0;
   g.any_node = 0;
   g.any_energy = 0;                      // the energy field does not act on the motion

@@ -187,11 +187,16 @@ def test_backward_is_independent_of_checkpoint_interval_and_repeatable():
     print(f"backward, intervals 10 and 5, repeated: max |g| {float(ga.abs().max()):.3e}, bitwise equal")
 
 
-@pytest.mark.parametrize("case", ["radius1", "radius8", "long_filament", "narrow_grid"])
+@pytest.mark.parametrize("case", ["radius1", "radius8", "long_filament", "narrow_grid", "pbd1", "pbd6", "pbd8"])
 def test_adjoint_configurations_match_oracle(case):
+    # pbd1 .. pbd8: PBD iteration counts below, between and at the two
+    # register-state sizes of the reversed PBD kernel (4 and 8 iterations)
     sim = _sim()
     kw = {}
-    if case == "radius1":
+    if case.startswith("pbd"):
+        w = wl.random_world(25, 64, 56, [18, 9, 30], amp=0.5)
+        kw = dict(pbd_iters=int(case[3:]))
+    elif case == "radius1":
         w = wl.random_world(21, 64, 56, [20, 9, 33], amp=0.5)
         kw = dict(repulse_radius=1, sigma_repulse=0.5)
     elif case == "radius8":
@@ -209,6 +214,21 @@ def test_adjoint_configurations_match_oracle(case):
     err, cos = _compare(g, ref, _joints(w))
     print(f"adjoint [{case}]: rel err {err:.2e} cos {cos:.6f}")
     assert err <= 1e-3 and cos >= 0.9999
+
+
+def test_backward_refuses_more_than_eight_pbd_iterations():
+    sim = _sim()
+    w = wl.random_world(3, 48, 40, [12, 7], amp=0.5)
+    W = sim.World(w, sim.Params(nx=w.nx, ny=w.ny, pbd_iters=9))
+    ck = torch.empty(W.checkpoint_bytes(4, 2), dtype=torch.uint8, device="cuda")
+    W.rollout(0, 4, 2, ck)
+    N = w.n_particles
+    g_pos = torch.zeros(2 * N, dtype=torch.float32, device="cuda")
+    g_rest = torch.zeros(N, dtype=torch.float32, device="cuda")
+    with pytest.raises(sim.SimError) as ei:
+        W.backward(0, 4, 2, ck, g_pos, g_rest)
+    assert ei.value.status == sim.SIM_E_INVALID
+    W.sync()
 
 
 @pytest.mark.parametrize("mode", ["sorted", "direct"])

@@ -136,8 +136,8 @@ def test_adjoint_with_per_edge_stiffness():
     assert err <= 1e-3 and cos >= 0.9999
 
 
-@pytest.mark.parametrize("tile", [32, 16])
-def test_adjoint_through_loops_matches_oracle(tile):
+@pytest.mark.parametrize("tile,iters", [(32, 4), (16, 4), (32, 7)])
+def test_adjoint_through_loops_matches_oracle(tile, iters):
     """Reverse mode through closed loops (Methods, Filaments: loops): the
     joint before node 0 and the closing edge, the third colour of loops of
     odd length (3 and 9 nodes) beside an even one, per-edge stiffnesses and
@@ -147,14 +147,14 @@ def test_adjoint_through_loops_matches_oracle(tile):
     w = wl.generality_world(7, 72, 64, [14, 9, 2], [9, 12, 3])
     x0 = w.positions64()
     target = x0 + np.random.default_rng(4).normal(0, 0.5, size=x0.shape)
-    g, _, W, p = _gpu_grad(sim, w, target, 12, 5, tile=tile)
+    g, _, W, p = _gpu_grad(sim, w, target, 12, 5, tile=tile, pbd_iters=iters)
     ref, _ = _oracle_grad(w, p, target, 12, 5)
     joints = _all_joints(w)
     err, cos = _compare(g, ref, joints)
     off = w.fil_offset
     loops = np.concatenate([np.arange(off[f], off[f + 1]) for f in range(len(off) - 1) if w.closed[f]])
     e_loop, c_loop = _compare(g, ref, loops)
-    print(f"adjoint through loops (tile {tile}): rel err {err:.2e} cos {cos:.6f}; loop joints alone "
+    print(f"adjoint through loops (tile {tile}, {iters} PBD iterations): rel err {err:.2e} cos {cos:.6f}; loop joints alone "
           f"{e_loop:.2e} / {c_loop:.6f}")
     assert err <= 1e-3 and cos >= 0.9999
     assert e_loop <= 1e-3 and c_loop >= 0.9999 and float(np.abs(ref[loops]).max()) > 0
@@ -250,8 +250,9 @@ def test_branch_batch_alone_and_refusals():
     assert ei.value.status == sim.SIM_E_INVALID
 
 
-@pytest.mark.parametrize("which", ["six creatures 96x80", "four creatures 72x64"])
-def test_adjoint_through_branches_matches_oracle(which):
+@pytest.mark.parametrize("which,iters", [("six creatures 96x80", 4), ("four creatures 72x64", 4),
+                                         ("four creatures 72x64", 8)])
+def test_adjoint_through_branches_matches_oracle(which, iters):
     """Reverse mode through branched creatures (Methods, Filaments: loops and
     branches): the attachment joints at the parent and the child's first
     node and the attachment edge, after the regular passes of each kind,
@@ -261,7 +262,7 @@ def test_adjoint_through_branches_matches_oracle(which):
     w = _branched(8) if which.startswith("six") else wl.branched_world(9, 72, 64, 4)
     x0 = w.positions64()
     target = x0 + np.random.default_rng(5).normal(0, 0.5, size=x0.shape)
-    g, _, W, p = _gpu_grad(sim, w, target, 12, 5)
+    g, _, W, p = _gpu_grad(sim, w, target, 12, 5, pbd_iters=iters)
     ref, _ = _oracle_grad(w, p, target, 12, 5)
     joints = _all_joints(w)
     err, cos = _compare(g, ref, joints)
@@ -269,7 +270,7 @@ def test_adjoint_through_branches_matches_oracle(which):
                             for f in range(len(w.fil_offset) - 1) if w.parent[f] >= 0])
     child = np.intersect1d(child, joints)
     e_c, c_c = _compare(g, ref, child) if child.size else (0.0, 1.0)
-    print(f"adjoint through branches [{which}], {len(w.fil_offset) - 1} filaments: rel err {err:.2e} "
+    print(f"adjoint through branches [{which}, {iters} PBD iterations], {len(w.fil_offset) - 1} filaments: rel err {err:.2e} "
           f"cos {cos:.6f}; joints of attached filaments {e_c:.2e} / {c_c:.6f}")
     assert err <= 1e-3 and cos >= 0.9999
     assert e_c <= 1e-3 and c_c >= 0.9999
