@@ -295,16 +295,12 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_force(const Wor
       float fbx = 0.f, fby = 0.f;       // dL/dF_i
       float sux = 0.f, suy = 0.f;       // d/dx of  sum_c W (u_c . xbar')
       float sfx = 0.f, sfy = 0.f;       // d/dx of  sum_c W (F_i . Fgbar_c)
-      float grx[4][4], gry[4][4];
+      if constexpr (!MK) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int q = (ly + kE + b) * kStage + lx + kE + a;
-          const vf2 gc = s_g[q];
-          grx[b][a] = gc.x;
-          gry[b][a] = gc.y;
-          if constexpr (!MK) {
+          for (int a = 0; a < 4; ++a) {
+            const int q = (ly + b) * kStage + lx + a;
             const vf2 uc = s_u[q];
             const vf2 fc = s_fb[q];
             const float W0 = wx[a] * wy[b], Wx = dwx[a] * wy[b], Wy = wx[a] * dwy[b];
@@ -317,8 +313,7 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_force(const Wor
             sfx += Wx * pf;
             sfy += Wy * pf;
           }
-        }
-      if constexpr (MK) {               // two layers: the transfer terms at the markers
+      } else {                          // two layers: the transfer terms at the markers
         const float ddx = glb(w.d_marker)[gi], ddy = glb(w.d_marker)[N + gi];
         float dbx = 0.f, dby = 0.f;
 #pragma unroll
@@ -362,12 +357,14 @@ __global__ __launch_bounds__(TileCfg<TILE>::kThreads) void k_adj_force(const Wor
         my = A.xbar_m[N + gi];
       }
       // repulsion F_rep = -k sum_c W G_c : d/dx of (-k sum_c W (G_c . Fbar))
+      // (the gradient read from the staged window again: fewer registers)
       float srx = 0.f, sry = 0.f;
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const float pg = grx[b][a] * fbx + gry[b][a] * fby;
+          const vf2 gc = s_g[(ly + kE + b) * kStage + lx + kE + a];
+          const float pg = gc.x * fbx + gc.y * fby;
           srx += dwx[a] * wy[b] * pg;
           sry += wx[a] * dwy[b] * pg;
         }
