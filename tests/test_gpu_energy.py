@@ -8,8 +8,9 @@ the step, each node's sensed value and each filament's collected energy
 against the oracle's energy update (relative max-norm error <= 1e-5; the
 field is FP32), in every transfer; the motion itself is unchanged by the
 field (positions and u equal to a run without it, bitwise for the binned
-transfer); the field loses what the nodes collect; a batch of energy worlds
-equals its worlds run alone.
+transfer); the field loses what the nodes collect; a batch of energy worlds,
+and energy-field jobs through the continuous-batching server, equal their
+worlds run alone.
 """
 import numpy as np
 import pytest
@@ -115,3 +116,36 @@ def test_batch_of_energy_worlds_equals_alone():
         for k in ("cell", "frac", "f", "u", "energy", "energy_collected"):
             assert torch.equal(getattr(got, k), getattr(W.state, k)), k
     print("batched energy worlds bitwise equal to their runs alone")
+
+
+def test_served_energy_jobs_equal_alone():
+    """Energy-field rollouts through the continuous-batching server (the
+    candidates an evolutionary search submits, scored by what they collect):
+    five jobs queued at once for four slots and a pool of 2.2 times the
+    largest job, so that some wait for others to retire; every result
+    (motion, field and per-filament collected energy) equals the same world
+    run alone, bitwise."""
+    sim = _sim()
+    from paper_2607_02954_amd import batch, serve
+    jobs = []
+    for i, (nx, ny, steps) in enumerate([(64, 64, 30), (96, 64, 20), (64, 96, 40), (80, 80, 10), (128, 96, 25)]):
+        w = wl.energy_world(30 + i, nx=nx, ny=ny, n_fil=5, length=18)
+        E, _ = _field(sim, w)
+        w.energy = E.cpu().numpy()
+        jobs.append(wl.Job(job_id=i, arrival=0.0, steps=steps, world=w))   # all queued at once
+    pf = lambda job: sim.Params(nx=job.world.nx, ny=job.world.ny, energy_rate=0.2)
+    need = max(batch.BatchEngine.world_bytes(pf(j), j.world.n_filaments, j.world.n_particles) for j in jobs)
+    eng = batch.BatchEngine(max_worlds=4, pool_bytes=int(2.2 * need) + (8 << 20))
+    srv = serve.Server(serve.GpuExecutor(eng, pf), chunk_steps=10)
+    stats = srv.run(jobs)
+    assert all(r.ok for r in stats.results), [r.error for r in stats.results]
+    assert stats.peak_resident >= 2
+    for job, r in zip(jobs, stats.results):
+        W = sim.World(job.world, pf(job))
+        W.rollout(0, job.steps)
+        W.sync()
+        for k in ("cell", "frac", "f", "u", "energy", "energy_collected"):
+            assert torch.equal(getattr(r.state, k), getattr(W.state, k)), (job.job_id, k)
+        assert float(r.state.energy_collected.double().sum()) > 0
+        W.close()
+    print("served energy jobs bitwise equal to their runs alone:", stats.summary())
